@@ -1,0 +1,263 @@
+/*
+ * tem.h -- C ABI of libtem: pole-shifted sparse solves for transient EM
+ * (rational approximation of the matrix exponential), gfx950 / MI355X.
+ *
+ * The calls follow the statement of the problem in Boerner, Guettel &
+ * Guenther, "Scalable Parallel 3-D TEM Inversion via Rational Approximation
+ * of the Matrix Exponential":
+ *   - semi-discrete system K u + M du/dt = 0, M u(0) = f  (section "Spatial
+ *     discretization");
+ *   - u(t_j) ~ 2 Re sum_i alpha_i^[j] (K - xi_i M)^{-1} f  (section "Rational
+ *     approximation using RKFIT");
+ *   - Algorithm 1 (form A_i = K - xi_i M, factor once, cache, solve g_i);
+ *   - d_j = Q u(t_j), data stacked over times (section "The Inverse Problem");
+ *   - J v and J^T w through the same cached factors (section "Jacobian
+ *     computation");
+ *   - the Gauss-Newton step by LSQR on the augmented system (section
+ *     "Optimization").
+ *
+ * Discretisation: uniform hexahedral mesh, lowest-order edge elements, DOF =
+ * line integral of E along an edge, tangential E = 0 on the outer boundary.
+ * Canonical edge numbering (used by every edge-indexed array of this ABI):
+ *   x-edges (i,j,k), i<nx, j<=ny, k<=nz:  i + nx*(j + (ny+1)*k)
+ *   y-edges (i,j,k), i<=nx, j<ny, k<=nz:  Ex + i + (nx+1)*(j + ny*k)
+ *   z-edges (i,j,k), i<=nx, j<=ny, k<nz:  Ex + Ey + i + (nx+1)*(j + (ny+1)*k)
+ * with Ex = nx(ny+1)(nz+1), Ey = (nx+1)ny(nz+1); cells (i,j,k) are numbered
+ * i + nx*(j + ny*k).  Boundary (PEC) edges are not unknowns: inputs on them
+ * are ignored and outputs on them are zero.
+ *
+ * Conventions
+ *   Ownership: caller buffers are borrowed for the duration of a call; the
+ *     library owns K, M, the symbolic structure, the factors, the cached
+ *     solutions g_i and all work space, and frees them in tem_destroy.
+ *   Memory spaces: every argument says "device" or "host".  Device
+ *     pointers must be allocated on the context's device.
+ *   Streams: device work is ordered on the context's stream; calls return
+ *     once their results are in the caller's buffers (the library
+ *     synchronises its stream before returning).
+ *   Errors: a negative tem_status; tem_last_error() describes it.  After an
+ *     error the context keeps the last stage that completed.
+ *   State machine: create -> assemble -> analyse -> factor_poles ->
+ *     {solve_poles | forward} -> {jvp, vjp, gn_step}*.  A new tem_assemble
+ *     on the same mesh keeps the symbolic structure and drops factors and
+ *     cached solutions; a different mesh also drops the symbolic structure.
+ *     Calls out of order return TEM_ESTATE.
+ *   Determinism: identical inputs give bitwise identical outputs on the
+ *     same device (no floating-point atomics).
+ *   Threading: one context per host thread.
+ *   Pole convention: A_i = K - xi_i M with Im(xi_i) > 0; the conjugate poles
+ *     are implicit through 2 Re (section "Comparison to other numerical
+ *     approaches": 42 poles give 21 complex systems).  Complex numbers are
+ *     (re, im) pairs of doubles.
+ */
+#ifndef TEM_H
+#define TEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tem_ctx tem_ctx;
+
+typedef enum {
+  TEM_OK = 0,
+  TEM_EINVAL = -1,   /* bad argument (NULL, size, range, non-finite input) */
+  TEM_ENOMEM = -2,   /* device or host allocation failed / budget exceeded */
+  TEM_EDEVICE = -3,  /* HIP runtime error */
+  TEM_ESTATE = -4,   /* call out of order */
+  TEM_EPIVOT = -5,   /* zero or non-finite pivot in the LDL^T factorisation */
+  TEM_ENOCONV = -6   /* refinement did not reach the requested tolerance */
+} tem_status;
+
+typedef enum {
+  TEM_FP64 = 0,     /* complex FP64 factors, FP64 solves, FP64 refinement */
+  TEM_FP32_IR = 1   /* complex FP32 factors; FP64 residuals and GMRES-based
+                       iterative refinement (preconditioned by the FP32
+                       factors) */
+} tem_precision;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `hip_device`.  `hip_stream` (host value of a
+ * hipStream_t, may be NULL) is the stream all device work is ordered on;
+ * NULL makes the library create its own.  *out receives the context. */
+tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream);
+
+/* Free every library allocation of ctx.  NULL-safe. */
+void tem_destroy(tem_ctx *ctx);
+
+/* Text of the last error on ctx (or of the last failed tem_create when ctx
+ * is NULL).  Valid until the next call on ctx. */
+const char *tem_last_error(const tem_ctx *ctx);
+
+/* ------------------------------------------------------------- assembly */
+
+typedef struct {
+  int32_t nx, ny, nz;  /* cells per axis, each >= 2 */
+  double h;            /* cell size (m), > 0 */
+  double mu;           /* magnetic permeability (H/m), > 0 */
+} tem_mesh;
+
+/* Assemble K (curl-curl stiffness, 1/mu int curl N_a . curl N_b) and
+ * M (int sigma N_a . N_b) over the interior edges on the device, FP64
+ * (section "Spatial discretization").
+ *   sigma_cells  device, nx*ny*nz doubles (S/m), all > 0 and finite.
+ *   n_params     number of model parameters P (m = ln sigma on these cells,
+ *                section "The Inverse Problem"); 0 disables jvp/vjp.
+ *   param_cells  host, P distinct cell ids (any order; parameter p is cell
+ *                param_cells[p]).  Copied. */
+tem_status tem_assemble(tem_ctx *ctx, const tem_mesh *mesh, const double *sigma_cells,
+                        int32_t n_params, const int32_t *param_cells);
+
+/* Set sigma = exp(m) on the parameter cells (m = ln sigma, section "The
+ * Inverse Problem"; other cells keep their conductivity) and re-assemble M.
+ * Drops factors and cached solutions.
+ *   m  device, P doubles (parameter order of tem_assemble), finite. */
+tem_status tem_set_model(tem_ctx *ctx, const double *m);
+
+/* Inspection: copy the assembled operators to host memory in the current
+ * unknown ordering (after tem_analyse: the nested-dissection ordering).
+ * Each output may be NULL.
+ *   perm    [N]     perm[q] = unknown index of row q (unknowns numbered in
+ *                   increasing canonical edge order)
+ *   rowptr  [N+1], col [nnz] (row-sorted), kval [nnz], mval [nnz]
+ * nnz is tem_symbolic_info.nnz_a (or call with NULL arrays and read *nnz). */
+tem_status tem_export_operators(const tem_ctx *ctx, int64_t *n_unknowns, int64_t *nnz,
+                                int32_t *perm, int64_t *rowptr, int32_t *col, double *kval,
+                                double *mval);
+
+/* --------------------------------------------------------- symbolic phase */
+
+typedef struct {
+  int32_t leaf_max_cells;   /* nested-dissection leaf size (<= 0: 4) */
+} tem_analyse_opts;
+
+typedef struct {
+  int64_t n_unknowns;       /* N */
+  int64_t nnz_a;            /* entries of the CSR pattern of A_i (both triangles) */
+  int64_t nnz_l;            /* entries of L incl. diagonal (supernodal) */
+  int64_t n_rows_total;     /* sum over supernodes of |U_s| */
+  int32_t n_supernodes;
+  int32_t n_levels;
+  int32_t max_front;        /* max over supernodes of k_s + |U_s| */
+  int32_t reserved;
+  double flops_per_pole;    /* real flops of one complex partial LDL^T sweep */
+} tem_symbolic_info;
+
+/* Nested-dissection ordering and supernodal symbolic factorisation of the
+ * common pattern of all A_i (one structure serves every pole: section
+ * "Computational performance").  Host work; uploads maps to the device and
+ * re-lays K and M out in the new ordering.  info may be NULL. */
+tem_status tem_analyse(tem_ctx *ctx, const tem_analyse_opts *opts, tem_symbolic_info *info);
+
+/* Host-only symbolic analysis of an nx*ny*nz mesh without a context or a
+ * GPU (same algorithm as tem_analyse).  Outputs, all host and optional
+ * (NULL skips):
+ *   perm       [N]      perm[new] = unknown index (unknowns numbered in
+ *                       increasing canonical edge order)
+ *   sn_ptr     [ns+1]   columns of supernode s are new indices
+ *                       sn_ptr[s] .. sn_ptr[s+1]-1 (post-order)
+ *   sn_parent  [ns]     parent supernode, -1 at the root
+ *   rows_ptr   [ns+1]   update rows U_s are rows[rows_ptr[s] .. rows_ptr[s+1]-1]
+ *   rows       [n_rows_total]  new indices, increasing within a supernode
+ * Call once with NULL arrays to learn the sizes from info. */
+tem_status tem_symbolic_host(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max_cells,
+                             tem_symbolic_info *info, int32_t *perm, int32_t *sn_ptr,
+                             int32_t *sn_parent, int64_t *rows_ptr, int32_t *rows);
+
+/* ---------------------------------------------------------- factorisation */
+
+typedef struct {
+  int64_t mem_budget_bytes; /* <= 0: 92% of free device memory */
+  int32_t max_group;        /* poles factored together (<= 0: as many as fit) */
+  int32_t reserved;
+} tem_factor_opts;
+
+/* Form A_i = K - xi_i M and compute A_i = P^T L D L^T P (complex
+ * symmetric, no pivoting, no conjugation) for all m poles with a batched
+ * multifrontal method; the factors stay cached on the device (Algorithm 1).
+ *   xi    host, 2*m doubles (re, im); Im > 0 required.
+ *   opts  may be NULL.
+ * Poles are factored in groups when the contribution blocks of all poles do
+ * not fit beside the factors; the grouping is reported by tem_get_stats. */
+tem_status tem_factor_poles(tem_ctx *ctx, int32_t m, const double *xi, tem_precision prec,
+                            const tem_factor_opts *opts);
+
+/* -------------------------------------------------------------- solves */
+
+typedef struct {
+  double rtol;          /* target ||f - A x||_2 / ||f||_2 per system (<= 0: 1e-10) */
+  int32_t max_iter;     /* max refinement solves per system (<= 0: 200) */
+  int32_t restart;      /* GMRES restart length in FP32 mode (<= 0: 30, max 60);
+                           1 gives classical iterative refinement */
+} tem_ir_opts;
+
+typedef struct {
+  int32_t *iters;        /* host, m*nrhs or NULL: solves spent per system */
+  double *final_rel_res; /* host, m*nrhs or NULL: last residual ratio */
+  int32_t n_unconverged; /* systems above rtol after max_iter */
+  int32_t reserved;
+} tem_ir_stats;
+
+/* g_is = A_i^{-1} f_s for every pole i and right-hand side s, refined in
+ * FP64 to ir->rtol (Algorithm 1, "compute A_i^{-1} f"); caches g for
+ * tem_jvp / tem_vjp.
+ *   F    device, n_edges x nrhs doubles, column-major (column s = f_s).
+ *   G    device or NULL: m x nrhs x n_edges complex doubles (interleaved
+ *        re, im; pole slowest, edge fastest); boundary edges get 0.
+ *   ir, stats may be NULL.
+ * Returns TEM_ENOCONV (after filling G and stats) if some system missed
+ * the tolerance. */
+tem_status tem_solve_poles(tem_ctx *ctx, int32_t nrhs, const double *F, double *G,
+                           const tem_ir_opts *ir, tem_ir_stats *stats);
+
+/* Forward map: tem_solve_poles for the S sources, then
+ * d[s][j][r] = 2 Re sum_i alpha[j][i] (Q g_is)_r  (Algorithm 1's final
+ * linear combination followed by the observation operator).
+ *   F      device, n_edges x S (as in tem_solve_poles).
+ *   Q      host CSR with R rows over canonical edge columns: q_ptr[R+1]
+ *          (int64), q_col[nnz] (int32), q_val[nnz] (double).  Copied.
+ *   alpha  host, K x m complex (re, im interleaved; time slowest).  Copied.
+ *   d      device, S*K*R doubles, layout [s][j][r].
+ * Also fixes S, Q and alpha for later tem_jvp / tem_vjp calls. */
+tem_status tem_forward(tem_ctx *ctx, int32_t S, const double *F, int32_t R,
+                       const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
+                       int32_t K, const double *alpha, const tem_ir_opts *ir, double *d,
+                       tem_ir_stats *stats);
+
+/* J v with J = d d / d m, m = ln sigma on the parameter cells (section
+ * "Jacobian computation"): J v = 2 Re sum_i alpha_i^[j] xi_i Q A_i^{-1}
+ * [dM/dm g_i v], through the cached factors.
+ *   v   device, P doubles.   jv  device, S*K*R doubles ([s][j][r]). */
+tem_status tem_jvp(tem_ctx *ctx, const double *v, double *jv, const tem_ir_opts *ir,
+                   tem_ir_stats *stats);
+
+/* J^T w = 2 Re sum_i xi_i [dM/dm g_i]^T A_i^{-1} Q^T (sum_j alpha_i^[j] w_j)
+ * (plain transpose: A_i is complex symmetric).
+ *   w   device, S*K*R doubles ([s][j][r]).   jtw  device, P doubles. */
+tem_status tem_vjp(tem_ctx *ctx, const double *w, double *jtw, const tem_ir_opts *ir,
+                   tem_ir_stats *stats);
+
+/* ------------------------------------------------------------ statistics */
+
+typedef struct {
+  int32_t n_poles;
+  int32_t n_groups;            /* pole groups used by the last factorisation */
+  int32_t group_size;
+  int32_t precision;           /* tem_precision of the cached factors */
+  int64_t factor_bytes;        /* device bytes held by the factors */
+  int64_t workspace_bytes;     /* contribution-block arenas etc. */
+  int32_t n_tiny_pivots;       /* pivots with |d| below 1e-300 (FP64) / 1e-30 (FP32) */
+  int32_t last_solves;         /* refinement solves of the last solve call (max) */
+  double factor_ms;            /* device time of the last factorisation */
+  double solve_ms;             /* device time of the last solve call */
+} tem_stats;
+
+tem_status tem_get_stats(const tem_ctx *ctx, tem_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TEM_H */

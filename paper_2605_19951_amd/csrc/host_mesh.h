@@ -1,0 +1,75 @@
+// Host-side mesh topology, element matrices and the supernodal symbolic
+// structure of the shifted matrices A_i = K - xi_i M (one structure for all
+// poles).  Pure C++; no HIP types, so it also builds into the host-only
+// symbolic entry point.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace tem {
+
+struct MeshTopo {
+  int nx = 0, ny = 0, nz = 0;
+  int64_t ex = 0, ey = 0, ez = 0, n_edges = 0, n_cells = 0;
+  std::vector<int32_t> unk_of_edge;   // canonical edge -> unknown index or -1
+  std::vector<int32_t> edge_of_unk;   // unknown index -> canonical edge
+  int64_t n_unknowns = 0;
+
+  void init(int nx_, int ny_, int nz_);
+  int64_t xedge(int i, int j, int k) const { return i + (int64_t)nx * (j + (int64_t)(ny + 1) * k); }
+  int64_t yedge(int i, int j, int k) const { return ex + i + (int64_t)(nx + 1) * (j + (int64_t)ny * k); }
+  int64_t zedge(int i, int j, int k) const {
+    return ex + ey + i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k);
+  }
+  // direction and lower node of a canonical edge
+  void geometry(int64_t e, int &dir, int &i, int &j, int &k) const;
+  // the 12 edges of cell (i,j,k) in local order: x-edges (dy,dz), y-edges
+  // (dx,dz), z-edges (dx,dy), each over (0,0),(1,0),(0,1),(1,1)
+  void cell_edges(int i, int j, int k, int64_t out[12]) const;
+};
+
+// 12x12 element matrices (row-major): unit-conductivity mass and stiffness.
+void element_mass_unit(double h, double out[144]);
+void element_stiffness(double h, double mu, double out[144]);
+
+struct SymNode {
+  int box[3][2];
+  int64_t first = 0, last = 0;   // column range (new indices)
+  int64_t sub_first = 0;         // first new index of the subtree
+  int parent = -1;
+  int child[2] = {-1, -1};
+  int level = 0;                 // depth, root = 0
+  int64_t rows_off = 0;          // U_s = rows[rows_off .. rows_off + nrows)
+  int64_t nrows = 0;
+};
+
+struct Symbolic {
+  int leaf_max = 4;
+  std::vector<SymNode> nodes;          // post-order
+  std::vector<int32_t> perm;           // new -> unknown
+  std::vector<int32_t> iperm;          // unknown -> new
+  std::vector<int32_t> rows;           // concatenated U_s (new indices)
+  int n_levels = 0;
+  int max_front = 0;
+  double flops_per_pole = 0.0;
+  int64_t nnz_l = 0;
+};
+
+// Nested dissection + supernodal symbolic factorisation (exact spec of the
+// ordering: longest side split at lo + (hi-lo)/2, ties x < y < z, leaves of
+// side <= leaf_max, post-order numbering, columns by canonical id).
+void analyse_symbolic(const MeshTopo &mt, int leaf_max, Symbolic &sym);
+
+// CSR pattern of "shares a cell" between unknowns, in the ordering given by
+// perm (perm[new] = unknown); columns sorted.  row_edge[new] = canonical edge.
+struct Pattern {
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<int32_t> row_edge;
+  std::vector<int32_t> edge_new;   // canonical edge -> new index or -1
+};
+void build_pattern(const MeshTopo &mt, const std::vector<int32_t> &perm, Pattern &pat);
+
+}  // namespace tem

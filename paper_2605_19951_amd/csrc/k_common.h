@@ -1,0 +1,46 @@
+// Device helpers shared by the HIP kernel files.
+#pragma once
+
+#include "tem_internal.h"
+
+namespace tem {
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+// acc + a*b
+template <typename T>
+__device__ __forceinline__ cpx<T> cfma(cpx<T> a, cpx<T> b, cpx<T> acc) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cinv(cpx<T> a) {
+  T den = a.re * a.re + a.im * a.im;
+  return {a.re / den, -a.im / den};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> czero() {
+  return {T(0), T(0)};
+}
+
+inline unsigned grid_1d(int64_t n, int block, int64_t cap = 65535 * 16) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace tem

@@ -1,0 +1,361 @@
+// Batched supernodal triangular solves with the cached factors, all poles
+// and all right-hand sides of one tree level per launch.
+//   forward:  per front, top rows  y_s = L11^{-1} (b_s + child updates)
+//             update rows          W_s = (child updates) - L21 y_s
+//   backward: per front            t_s = L21^T x(U_s)
+//                                  x_s = L11^{-T} (D^{-1} y_s - t_s)
+// Vectors are [pole][N][S] complex, S <= 16, in the nested-dissection
+// ordering; W arenas hold each front's update rows [row][S].
+#include "k_common.h"
+
+namespace tem {
+
+constexpr int RT = 64;   // rows per LDS tile (rectangle kernels)
+constexpr int RTT = 32;  // rows per LDS tile (triangle kernels, keeps LDS under 64 KiB)
+
+// Pointer to column c's data such that element (r, c) is colptr[r].
+template <typename T>
+__device__ __forceinline__ const cpx<T> *col_ptr(const cpx<T> *P, int64_t n, int64_t c,
+                                                 int64_t &ld) {
+  const int64_t b = c / NB, r0 = NB * b;
+  ld = n - r0;
+  return P + panel_block_off(n, b) + (c - r0) * ld - r0;
+}
+
+// ------------------------------------------------------------ forward tri
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl_nodes, int S,
+                                                 int64_t N, const cpx<T> *factor,
+                                                 int64_t f_stride, cpx<T> *x,
+                                                 const cpx<T> *w_child, int64_t w_stride) {
+  const int s = lvl_nodes[blockIdx.x];
+  const int p = blockIdx.y;
+  const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
+  if (k == 0) return;
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;     // rows of this front's columns
+  const int tid = threadIdx.x;
+  // child contributions into the top rows
+  const int32_t *gm0 = ft.gmap0 + ft.gmap_off[s];
+  const int32_t *gm1 = ft.gmap1 + ft.gmap_off[s];
+  const int c0 = ft.child0[s], c1 = ft.child1[s];
+  const cpx<T> *W0 = c0 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c0] * S : nullptr;
+  const cpx<T> *W1 = c1 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c1] * S : nullptr;
+  if (c0 >= 0) {
+    for (int64_t idx = tid; idx < k * S; idx += blockDim.x) {
+      const int64_t q = idx / S, c = idx % S;
+      cpx<T> v = X[idx];
+      if (gm0[q] >= 0) v = cadd(v, W0[(int64_t)gm0[q] * S + c]);
+      if (gm1[q] >= 0) v = cadd(v, W1[(int64_t)gm1[q] * S + c]);
+      X[idx] = v;
+    }
+  }
+  __shared__ cpx<T> Li[NB][NB + 1];   // Li[j][l]: inverse of the unit-lower diagonal block
+  __shared__ cpx<T> V[NB][16];
+  __shared__ cpx<T> Y[NB][16];
+  __shared__ cpx<T> Lt[NB][RTT + 1];   // Lt[l][i] = L(r0 + i, jb + l)
+  for (int64_t jb = 0; jb < k; jb += NB) {
+    const int w = (int)min((int64_t)NB, k - jb);
+    int64_t ld;
+    const cpx<T> *Lc = col_ptr(P, n, jb, ld);   // column jb; column jb+l at Lc + l*ld
+    __syncthreads();
+    for (int idx = tid; idx < w * w; idx += blockDim.x) {
+      const int j = idx % w, l = idx / w;
+      // stored transposed in the upper part: Linv[j][l] at (row jb+l, col jb+j)
+      if (l < j) Li[j][l] = Lc[(int64_t)j * ld + jb + l];
+    }
+    for (int idx = tid; idx < w * S; idx += blockDim.x) V[idx / S][idx % S] = X[(jb) * S + idx];
+    __syncthreads();
+    for (int idx = tid; idx < w * S; idx += blockDim.x) {
+      const int j = idx / S, c = idx % S;
+      cpx<T> acc = V[j][c];
+      for (int l = 0; l < j; ++l) acc = cfma(Li[j][l], V[l][c], acc);
+      Y[j][c] = acc;
+      X[jb * S + idx] = acc;
+    }
+    __syncthreads();
+    // rows below inside L11: X[r] -= sum_l L(r, jb+l) Y[l]
+    for (int64_t rc = jb + w; rc < k; rc += RTT) {
+      const int nr = (int)min((int64_t)RTT, k - rc);
+      for (int idx = tid; idx < RTT * w; idx += blockDim.x) {
+        const int i = idx % RTT, l = idx / RTT;
+        Lt[l][i] = (i < nr) ? Lc[(int64_t)l * ld + rc + i] : czero<T>();
+      }
+      __syncthreads();
+      for (int idx = tid; idx < nr * S; idx += blockDim.x) {
+        const int i = idx / S, c = idx % S;
+        cpx<T> acc = czero<T>();
+        for (int l = 0; l < w; ++l) acc = cfma(Lt[l][i], Y[l][c], acc);
+        cpx<T> *q = X + (rc + i) * S + c;
+        *q = csub(*q, acc);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                          int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
+                          cpx<T> *x, const cpx<T> *w_child, int64_t w_stride) {
+  if (n_nodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
+                     factor, f_stride, x, w_child, w_stride);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ forward rect
+// W_s[a] = child updates at front row k+a  -  sum_j L(k+a, j) y_j
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_rect(FrontTab ft, const int32_t *lvl_nodes, int S,
+                                                  int64_t N, const cpx<T> *factor,
+                                                  int64_t f_stride, const cpx<T> *x,
+                                                  const cpx<T> *w_child, cpx<T> *w_out,
+                                                  int64_t w_stride) {
+  const int s = lvl_nodes[blockIdx.y];
+  const int p = blockIdx.z;
+  const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
+  const int64_t a0 = (int64_t)blockIdx.x * RT;
+  if (a0 >= u) return;
+  const int na = (int)min((int64_t)RT, u - a0);
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  const cpx<T> *X = x + ((int64_t)p * N + first) * S;
+  const int tid = threadIdx.x;
+  const int32_t *gm0 = ft.gmap0 + ft.gmap_off[s] + k;
+  const int32_t *gm1 = ft.gmap1 + ft.gmap_off[s] + k;
+  const int c0 = ft.child0[s], c1 = ft.child1[s];
+  const cpx<T> *W0 = c0 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c0] * S : nullptr;
+  const cpx<T> *W1 = c1 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c1] * S : nullptr;
+  // each thread owns up to 4 (row, rhs) pairs: idx = tid + 256 q
+  cpx<T> acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    acc[q] = czero<T>();
+    const int idx = tid + 256 * q;
+    if (idx < na * S) {
+      const int i = idx / S, c = idx % S;
+      const int64_t a = a0 + i;
+      if (c0 >= 0 && gm0[a] >= 0) acc[q] = cadd(acc[q], W0[(int64_t)gm0[a] * S + c]);
+      if (c1 >= 0 && gm1[a] >= 0) acc[q] = cadd(acc[q], W1[(int64_t)gm1[a] * S + c]);
+    }
+  }
+  __shared__ cpx<T> Lt[NB][RT + 1];
+  __shared__ cpx<T> Y[NB][16];
+  for (int64_t jb = 0; jb < k; jb += NB) {
+    const int w = (int)min((int64_t)NB, k - jb);
+    int64_t ld;
+    const cpx<T> *Lc = col_ptr(P, n, jb, ld);
+    __syncthreads();
+    for (int idx = tid; idx < RT * w; idx += blockDim.x) {
+      const int i = idx % RT, l = idx / RT;
+      Lt[l][i] = (i < na) ? Lc[(int64_t)l * ld + k + a0 + i] : czero<T>();
+    }
+    for (int idx = tid; idx < w * S; idx += blockDim.x) Y[idx / S][idx % S] = X[jb * S + idx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < na * S) {
+        const int i = idx / S, c = idx % S;
+        cpx<T> sacc = acc[q];
+        for (int l = 0; l < w; ++l) {
+          const cpx<T> pr = cmul(Lt[l][i], Y[l][c]);
+          sacc = csub(sacc, pr);
+        }
+        acc[q] = sacc;
+      }
+    }
+  }
+  cpx<T> *Wo = w_out + (int64_t)p * w_stride + ft.w_off[s] * S;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q;
+    if (idx < na * S) Wo[a0 * S + idx] = acc[q];
+  }
+}
+
+template <typename T>
+hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_u, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, const cpx<T> *x, const cpx<T> *w_child,
+                           cpx<T> *w_out, int64_t w_stride) {
+  if (n_nodes <= 0 || max_u <= 0) return hipSuccess;
+  dim3 grid((max_u + RT - 1) / RT, n_nodes, npole);
+  hipLaunchKernelGGL(k_fwd_rect<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
+                     x, w_child, w_out, w_stride);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- backward rect
+// t[first + jb + l] = sum_a L(k + a, jb + l) x[U_s[a]] for one column block
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lvl_nodes, int S,
+                                                  int64_t N, const cpx<T> *factor,
+                                                  int64_t f_stride, const cpx<T> *x, cpx<T> *t,
+                                                  int64_t t_stride) {
+  const int s = lvl_nodes[blockIdx.y];
+  const int p = blockIdx.z;
+  const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
+  const int64_t jb = (int64_t)blockIdx.x * NB;
+  if (jb >= k) return;
+  const int w = (int)min((int64_t)NB, k - jb);
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  const cpx<T> *Xp = x + (int64_t)p * N * S;
+  const int32_t *rows = ft.rows + ft.rows_off[s];
+  const int tid = threadIdx.x;
+  int64_t ld;
+  const cpx<T> *Lc = col_ptr(P, n, jb, ld);
+  __shared__ cpx<T> Lt[NB][RT + 1];
+  __shared__ cpx<T> Xt[RT][16];
+  cpx<T> acc[2];
+  acc[0] = czero<T>();
+  acc[1] = czero<T>();
+  for (int64_t ac = 0; ac < u; ac += RT) {
+    const int na = (int)min((int64_t)RT, u - ac);
+    __syncthreads();
+    for (int idx = tid; idx < RT * w; idx += blockDim.x) {
+      const int i = idx % RT, l = idx / RT;
+      Lt[l][i] = (i < na) ? Lc[(int64_t)l * ld + k + ac + i] : czero<T>();
+    }
+    for (int idx = tid; idx < na * S; idx += blockDim.x) {
+      const int i = idx / S, c = idx % S;
+      Xt[i][c] = Xp[(int64_t)rows[ac + i] * S + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < w * S) {
+        const int l = idx / S, c = idx % S;
+        cpx<T> sacc = acc[q];
+        for (int i = 0; i < na; ++i) sacc = cfma(Lt[l][i], Xt[i][c], sacc);
+        acc[q] = sacc;
+      }
+    }
+  }
+  cpx<T> *To = t + (int64_t)p * t_stride + (first + jb) * S;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int idx = tid + 256 * q;
+    if (idx < w * S) To[idx] = acc[q];
+  }
+}
+
+template <typename T>
+hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_k, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, const cpx<T> *x, cpx<T> *t, int64_t t_stride) {
+  if (n_nodes <= 0 || max_k <= 0) return hipSuccess;
+  dim3 grid((max_k + NB - 1) / NB, n_nodes, npole);
+  hipLaunchKernelGGL(k_bwd_rect<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
+                     x, t, t_stride);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ backward tri
+// x_s = L11^{-T} (D^{-1} y_s - t_s), blocks from the last to the first
+// (left-looking: each block first gathers the contributions of the rows
+// below it inside L11).  With u == 0 the t term is absent.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl_nodes, int S,
+                                                 int64_t N, const cpx<T> *factor,
+                                                 int64_t f_stride, cpx<T> *x, const cpx<T> *t,
+                                                 int64_t t_stride) {
+  const int s = lvl_nodes[blockIdx.x];
+  const int p = blockIdx.y;
+  const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
+  if (k == 0) return;
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;
+  const cpx<T> *Tv = t + (int64_t)p * t_stride + first * S;
+  const int tid = threadIdx.x;
+  __shared__ cpx<T> Li[NB][NB + 1];
+  __shared__ cpx<T> V[NB][16];
+  __shared__ cpx<T> Lt[NB][RTT + 1];
+  __shared__ cpx<T> Xt[RTT][16];
+  const int64_t nblk = (k + NB - 1) / NB;
+  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+    const int64_t jb = bi * NB;
+    const int w = (int)min((int64_t)NB, k - jb);
+    int64_t ld;
+    const cpx<T> *Lc = col_ptr(P, n, jb, ld);
+    cpx<T> acc[2];
+    acc[0] = czero<T>();
+    acc[1] = czero<T>();
+    // contributions of the already solved rows jb+w .. k-1
+    for (int64_t rc = jb + w; rc < k; rc += RTT) {
+      const int nr = (int)min((int64_t)RTT, k - rc);
+      __syncthreads();
+      for (int idx = tid; idx < RTT * w; idx += blockDim.x) {
+        const int i = idx % RTT, l = idx / RTT;
+        Lt[l][i] = (i < nr) ? Lc[(int64_t)l * ld + rc + i] : czero<T>();
+      }
+      for (int idx = tid; idx < nr * S; idx += blockDim.x) Xt[idx / S][idx % S] = X[rc * S + idx];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int idx = tid + 256 * q;
+        if (idx < w * S) {
+          const int l = idx / S, c = idx % S;
+          cpx<T> sacc = acc[q];
+          for (int i = 0; i < nr; ++i) sacc = cfma(Lt[l][i], Xt[i][c], sacc);
+          acc[q] = sacc;
+        }
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < w * w; idx += blockDim.x) {
+      const int j = idx % w, l = idx / w;
+      if (l < j) Li[j][l] = Lc[(int64_t)j * ld + jb + l];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < w * S) {
+        const int l = idx / S, c = idx % S;
+        const cpx<T> d = Lc[(int64_t)l * ld + jb + l];
+        cpx<T> v = cmul(X[jb * S + idx], cinv(d));
+        if (u > 0) v = csub(v, Tv[jb * S + idx]);
+        V[l][c] = csub(v, acc[q]);
+      }
+    }
+    __syncthreads();
+    // x_b = Linv^T v_b : x[l] = v[l] + sum_{j > l} Linv[j][l] v[j]
+    for (int idx = tid; idx < w * S; idx += blockDim.x) {
+      const int l = idx / S, c = idx % S;
+      cpx<T> r = V[l][c];
+      for (int j = l + 1; j < w; ++j) r = cfma(Li[j][l], V[j][c], r);
+      X[jb * S + idx] = r;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                          int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
+                          cpx<T> *x, const cpx<T> *t, int64_t t_stride) {
+  if (n_nodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
+                     factor, f_stride, x, t, t_stride);
+  return hipGetLastError();
+}
+
+#define TEM_INST(T)                                                                              \
+  template hipError_t launch_fwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
+                                        int64_t, const cpx<T> *, int64_t, cpx<T> *,              \
+                                        const cpx<T> *, int64_t);                                \
+  template hipError_t launch_fwd_rect<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
+                                         int, int64_t, const cpx<T> *, int64_t, const cpx<T> *,  \
+                                         const cpx<T> *, cpx<T> *, int64_t);                     \
+  template hipError_t launch_bwd_rect<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
+                                         int, int64_t, const cpx<T> *, int64_t, const cpx<T> *,  \
+                                         cpx<T> *, int64_t);                                     \
+  template hipError_t launch_bwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
+                                        int64_t, const cpx<T> *, int64_t, cpx<T> *,              \
+                                        const cpx<T> *, int64_t);
+TEM_INST(float)
+TEM_INST(double)
+#undef TEM_INST
+
+}  // namespace tem

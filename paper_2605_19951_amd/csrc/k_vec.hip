@@ -1,0 +1,588 @@
+// Assembly of K and M, FP64 residuals and shifted products, batched
+// reductions for the refinement, precision conversions, observation and
+// residue time assembly, and the Jacobian right-hand sides / reductions.
+#include "k_common.h"
+
+namespace tem {
+
+// ---------------------------------------------------------------- assembly
+// Row-owner gather: each thread owns one row (unknown edge) and sums the
+// element contributions of the <= 4 cells that contain it, in a fixed order.
+__global__ void k_assemble_KM(int64_t N, const int64_t *rowptr, const int32_t *col,
+                              const int32_t *row_edge, const int32_t *edge_new, int nx, int ny,
+                              int nz, const double *Ke, const double *Me, const double *sigma,
+                              double *Kv, double *Mv) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N) return;
+  const int64_t ex = (int64_t)nx * (ny + 1) * (nz + 1);
+  const int64_t ey = (int64_t)(nx + 1) * ny * (nz + 1);
+  int64_t e = row_edge[q];
+  int d, i, j, k;
+  if (e < ex) {
+    d = 0; i = (int)(e % nx); int64_t r = e / nx; j = (int)(r % (ny + 1)); k = (int)(r / (ny + 1));
+  } else if (e < ex + ey) {
+    e -= ex; d = 1; i = (int)(e % (nx + 1)); int64_t r = e / (nx + 1); j = (int)(r % ny); k = (int)(r / ny);
+  } else {
+    e -= ex + ey; d = 2; i = (int)(e % (nx + 1)); int64_t r = e / (nx + 1); j = (int)(r % (ny + 1)); k = (int)(r / (ny + 1));
+  }
+  const int64_t rb = rowptr[q], re = rowptr[q + 1];
+  for (int64_t p = rb; p < re; ++p) {
+    Kv[p] = 0.0;
+    Mv[p] = 0.0;
+  }
+  const int AB[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+  for (int p = 0; p < 4; ++p) {
+    const int a = AB[p][0], b = AB[p][1];
+    int ci, cj, ck;
+    if (d == 0) { ci = i; cj = j - a; ck = k - b; }
+    else if (d == 1) { ci = i - a; cj = j; ck = k - b; }
+    else { ci = i - a; cj = j - b; ck = k; }
+    if (ci < 0 || cj < 0 || ck < 0 || ci >= nx || cj >= ny || ck >= nz) continue;
+    const int la = 4 * d + p;
+    const int64_t cell = ci + (int64_t)nx * (cj + (int64_t)ny * ck);
+    const double sg = sigma[cell];
+    int64_t ce[12];
+    for (int t = 0; t < 4; ++t) {
+      const int aa = AB[t][0], bb = AB[t][1];
+      ce[t] = ci + (int64_t)nx * ((cj + aa) + (int64_t)(ny + 1) * (ck + bb));
+      ce[4 + t] = ex + (ci + aa) + (int64_t)(nx + 1) * (cj + (int64_t)ny * (ck + bb));
+      ce[8 + t] = ex + ey + (ci + aa) + (int64_t)(nx + 1) * ((cj + bb) + (int64_t)(ny + 1) * ck);
+    }
+    for (int t = 0; t < 12; ++t) {
+      const int32_t c = edge_new[ce[t]];
+      if (c < 0) continue;
+      // binary search of c in the sorted row
+      int64_t lo = rb, hi = re - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < c) lo = mid + 1; else hi = mid;
+      }
+      Kv[lo] += Ke[la * 12 + t];
+      Mv[lo] += sg * Me[la * 12 + t];
+    }
+  }
+}
+
+hipError_t launch_assemble_KM(hipStream_t st, int64_t N, const int64_t *rowptr, const int32_t *col,
+                              const int32_t *row_edge, const int32_t *edge_new, int nx, int ny,
+                              int nz, const double *Ke, const double *Me, const double *sigma,
+                              double *Kv, double *Mv) {
+  hipLaunchKernelGGL(k_assemble_KM, dim3(grid_1d(N, 128, 1 << 30)), dim3(128), 0, st, N, rowptr,
+                     col, row_edge, edge_new, nx, ny, nz, Ke, Me, sigma, Kv, Mv);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ shifted products
+// one thread per (row, pole, rhs); x, y, r: [pole][N][S]
+__global__ void k_residual(int64_t N, int npole, int S, const int64_t *rowptr,
+                           const int32_t *col, const double *Kv, const double *Mv,
+                           const double *xi, const double *f_real, const cpx<double> *f_cplx,
+                           const cpx<double> *x, cpx<double> *r, int mode) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mS = (int64_t)npole * S;
+  if (idx >= N * mS) return;
+  const int64_t q = idx / mS;
+  const int ps = (int)(idx % mS);
+  const int p = ps / S, c = ps % S;
+  const double xr = xi[2 * p], xim = xi[2 * p + 1];
+  const cpx<double> *X = x + (int64_t)p * N * S + c;
+  double ar = 0.0, ai = 0.0;
+  for (int64_t t = rowptr[q]; t < rowptr[q + 1]; ++t) {
+    const double kv = Kv[t], mv = Mv[t];
+    const cpx<double> v = X[(int64_t)col[t] * S];
+    // (K - xi M) v, xi M v = (xr + i xim) mv v
+    const double sr = kv - xr * mv, si = -xim * mv;
+    ar += sr * v.re - si * v.im;
+    ai += sr * v.im + si * v.re;
+  }
+  cpx<double> out;
+  if (mode == 0) {
+    out.re = ar;
+    out.im = ai;
+  } else {
+    double fr = 0.0, fi = 0.0;
+    if (f_cplx) {
+      const cpx<double> f = f_cplx[((int64_t)p * N + q) * S + c];
+      fr = f.re;
+      fi = f.im;
+    } else if (f_real) {
+      fr = f_real[q * S + c];
+    }
+    out.re = fr - ar;
+    out.im = fi - ai;
+  }
+  r[((int64_t)p * N + q) * S + c] = out;
+}
+
+hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
+                           const int32_t *col, const double *Kv, const double *Mv,
+                           const double *xi, const double *f_real, const cpx<double> *f_cplx,
+                           const cpx<double> *x, cpx<double> *r) {
+  const int64_t tot = N * npole * S;
+  hipLaunchKernelGGL(k_residual, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
+                     rowptr, col, Kv, Mv, xi, f_real, f_cplx, x, r, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
+                               const int32_t *col, const double *Kv, const double *Mv,
+                               const double *xi, const cpx<double> *x, cpx<double> *y) {
+  const int64_t tot = N * npole * S;
+  hipLaunchKernelGGL(k_residual, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
+                     rowptr, col, Kv, Mv, xi, nullptr, nullptr, x, y, 0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- batched dots
+// Stage 1: block (chunk, pole) reduces rows of its chunk for every rhs.
+// Stage 2: one thread per system sums the chunk partials in order.
+constexpr int DOT_BLOCK = 256;
+
+__global__ __launch_bounds__(DOT_BLOCK) void k_dot_stage1(int64_t N, int S, const cpx<double> *a,
+                                                          const cpx<double> *b, int conj_a,
+                                                          int n_chunks, cpx<double> *partial) {
+  const int chunk = blockIdx.x, p = blockIdx.y;
+  const int tid = threadIdx.x;
+  int lanes = 1;                       // rows per sweep: largest power of two <= 256 / S
+  while (lanes * 2 * S <= DOT_BLOCK) lanes *= 2;
+  const int c = tid % S, rl = tid / S;
+  const int64_t per = (N + n_chunks - 1) / n_chunks;
+  const int64_t r0 = (int64_t)chunk * per, r1 = min(N, r0 + per);
+  double sr = 0.0, si = 0.0;
+  if (rl < lanes) {
+    const cpx<double> *A = a + (int64_t)p * N * S;
+    const cpx<double> *B = b + (int64_t)p * N * S;
+    for (int64_t q = r0 + rl; q < r1; q += lanes) {
+      const cpx<double> x = A[q * S + c], y = B[q * S + c];
+      const double xi = conj_a ? -x.im : x.im;
+      sr += x.re * y.re - xi * y.im;
+      si += x.re * y.im + xi * y.re;
+    }
+  }
+  __shared__ double shr[DOT_BLOCK], shi[DOT_BLOCK];
+  shr[tid] = sr;
+  shi[tid] = si;
+  __syncthreads();
+  // tree over the row lanes of each rhs c
+  for (int off = lanes / 2; off > 0; off >>= 1) {
+    if (rl < off) {
+      shr[tid] += shr[tid + off * S];
+      shi[tid] += shi[tid + off * S];
+    }
+    __syncthreads();
+  }
+  if (rl == 0) partial[((int64_t)p * n_chunks + chunk) * S + c] = {shr[c], shi[c]};
+}
+
+__global__ void k_dot_stage2(int npole, int S, int n_chunks, const cpx<double> *partial,
+                             cpx<double> *out) {
+  const int ps = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ps >= npole * S) return;
+  const int p = ps / S, c = ps % S;
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < n_chunks; ++k) {
+    const cpx<double> v = partial[((int64_t)p * n_chunks + k) * S + c];
+    sr += v.re;
+    si += v.im;
+  }
+  out[ps] = {sr, si};
+}
+
+hipError_t launch_batched_dot(hipStream_t st, int64_t N, int npole, int S, const cpx<double> *a,
+                              const cpx<double> *b, bool conj_a, cpx<double> *partial,
+                              int n_partial_blocks, cpx<double> *out) {
+  hipLaunchKernelGGL(k_dot_stage1, dim3(n_partial_blocks, npole), dim3(DOT_BLOCK), 0, st, N, S, a,
+                     b, conj_a ? 1 : 0, n_partial_blocks, partial);
+  hipLaunchKernelGGL(k_dot_stage2, dim3((npole * S + 127) / 128), dim3(128), 0, st, npole, S,
+                     n_partial_blocks, partial, out);
+  return hipGetLastError();
+}
+
+__global__ void k_axpy(int64_t N, int npole, int S, const cpx<double> *alpha, double sign,
+                       const cpx<double> *x, cpx<double> *y, const int *mask) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = N * npole * S;
+  if (idx >= tot) return;
+  const int c = (int)(idx % S);
+  const int p = (int)(idx / ((int64_t)N * S));
+  const int ps = p * S + c;
+  if (mask && mask[ps] == 0) return;
+  cpx<double> a = alpha[ps];
+  a.re *= sign;
+  a.im *= sign;
+  const cpx<double> v = x[idx];
+  cpx<double> w = y[idx];
+  w.re += a.re * v.re - a.im * v.im;
+  w.im += a.re * v.im + a.im * v.re;
+  y[idx] = w;
+}
+
+hipError_t launch_batched_axpy(hipStream_t st, int64_t N, int npole, int S,
+                               const cpx<double> *alpha, double sign, const cpx<double> *x,
+                               cpx<double> *y, const int *mask) {
+  const int64_t tot = N * npole * S;
+  hipLaunchKernelGGL(k_axpy, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
+                     alpha, sign, x, y, mask);
+  return hipGetLastError();
+}
+
+__global__ void k_scale(int64_t N, int npole, int S, const double *scale, cpx<double> *x) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = N * npole * S;
+  if (idx >= tot) return;
+  const int c = (int)(idx % S);
+  const int p = (int)(idx / ((int64_t)N * S));
+  const double s = scale[p * S + c];
+  cpx<double> v = x[idx];
+  v.re *= s;
+  v.im *= s;
+  x[idx] = v;
+}
+
+hipError_t launch_batched_scale(hipStream_t st, int64_t N, int npole, int S, const double *scale,
+                                cpx<double> *x) {
+  const int64_t tot = N * npole * S;
+  hipLaunchKernelGGL(k_scale, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
+                     scale, x);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------- conversions
+template <typename T>
+__global__ void k_convert_in(int64_t n_per_pole, int npole, int S, const cpx<double> *in,
+                             const double *scale, cpx<T> *out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = n_per_pole * npole;
+  if (idx >= tot) return;
+  const int c = (int)(idx % S);
+  const int p = (int)(idx / n_per_pole);
+  const double s = scale ? scale[p * S + c] : 1.0;
+  const cpx<double> v = in[idx];
+  out[idx] = {(T)(v.re * s), (T)(v.im * s)};
+}
+
+template <typename T>
+__global__ void k_convert_out(int64_t n_per_pole, int npole, int S, const cpx<T> *in,
+                              const double *scale, cpx<double> *out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = n_per_pole * npole;
+  if (idx >= tot) return;
+  const int c = (int)(idx % S);
+  const int p = (int)(idx / n_per_pole);
+  const double s = scale ? scale[p * S + c] : 1.0;
+  const cpx<T> v = in[idx];
+  out[idx] = {(double)v.re * s, (double)v.im * s};
+}
+
+template <typename T>
+hipError_t launch_convert_in(hipStream_t st, int64_t n_per_pole, int npole, int S,
+                             const cpx<double> *in, const double *scale, cpx<T> *out) {
+  const int64_t tot = n_per_pole * npole;
+  hipLaunchKernelGGL(k_convert_in<T>, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st,
+                     n_per_pole, npole, S, in, scale, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_convert_out(hipStream_t st, int64_t n_per_pole, int npole, int S,
+                              const cpx<T> *in, const double *scale, cpx<double> *out) {
+  const int64_t tot = n_per_pole * npole;
+  hipLaunchKernelGGL(k_convert_out<T>, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st,
+                     n_per_pole, npole, S, in, scale, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_convert_in<float>(hipStream_t, int64_t, int, int, const cpx<double> *,
+                                             const double *, cpx<float> *);
+template hipError_t launch_convert_in<double>(hipStream_t, int64_t, int, int, const cpx<double> *,
+                                              const double *, cpx<double> *);
+template hipError_t launch_convert_out<float>(hipStream_t, int64_t, int, int, const cpx<float> *,
+                                              const double *, cpx<double> *);
+template hipError_t launch_convert_out<double>(hipStream_t, int64_t, int, int,
+                                               const cpx<double> *, const double *,
+                                               cpx<double> *);
+
+// --------------------------------------------------------- edge layouts
+__global__ void k_gather_rhs(int64_t N, int S, int64_t n_edges, const int32_t *row_edge,
+                             const double *F, double *f_new) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * S) return;
+  const int64_t q = idx / S;
+  const int c = (int)(idx % S);
+  f_new[idx] = F[(int64_t)c * n_edges + row_edge[q]];
+}
+
+hipError_t launch_gather_rhs(hipStream_t st, int64_t N, int S, int64_t n_edges,
+                             const int32_t *row_edge, const double *F, double *f_new) {
+  hipLaunchKernelGGL(k_gather_rhs, dim3(grid_1d(N * S, 256, 1 << 30)), dim3(256), 0, st, N, S,
+                     n_edges, row_edge, F, f_new);
+  return hipGetLastError();
+}
+
+__global__ void k_scatter_solution(int64_t N, int npole, int S, int64_t n_edges,
+                                   const int32_t *edge_new, const cpx<double> *g,
+                                   cpx<double> *G) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = n_edges * npole * S;
+  if (idx >= tot) return;
+  const int64_t e = idx % n_edges;
+  const int64_t ps = idx / n_edges;
+  const int p = (int)(ps / S), c = (int)(ps % S);
+  const int32_t q = edge_new[e];
+  G[idx] = q >= 0 ? g[((int64_t)p * N + q) * S + c] : cpx<double>{0.0, 0.0};
+}
+
+hipError_t launch_scatter_solution(hipStream_t st, int64_t N, int npole, int S, int64_t n_edges,
+                                   const int32_t *edge_new, const cpx<double> *g,
+                                   cpx<double> *G) {
+  const int64_t tot = n_edges * npole * S;
+  hipLaunchKernelGGL(k_scatter_solution, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N,
+                     npole, S, n_edges, edge_new, g, G);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- time assembly
+// d[s][j][r] = 2 Re sum_i alpha[j][i] (Q g_is)_r, Neumaier-compensated over i
+__global__ void k_time_assembly(int S, int K, int R, int npole, int64_t N, const int64_t *q_ptr,
+                                const int32_t *q_col, const double *q_val,
+                                const cpx<double> *alpha, const cpx<double> *g, double *d) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)S * K * R) return;
+  const int r = (int)(idx % R);
+  const int j = (int)((idx / R) % K);
+  const int s = (int)(idx / ((int64_t)R * K));
+  double sum = 0.0, comp = 0.0;
+  for (int i = 0; i < npole; ++i) {
+    double yr = 0.0, yi = 0.0;
+    for (int64_t t = q_ptr[r]; t < q_ptr[r + 1]; ++t) {
+      const cpx<double> v = g[((int64_t)i * N + q_col[t]) * S + s];
+      yr += q_val[t] * v.re;
+      yi += q_val[t] * v.im;
+    }
+    const cpx<double> a = alpha[(int64_t)j * npole + i];
+    const double term = 2.0 * (a.re * yr - a.im * yi);
+    const double tsum = sum + term;
+    if (fabs(sum) >= fabs(term)) comp += (sum - tsum) + term;
+    else comp += (term - tsum) + sum;
+    sum = tsum;
+  }
+  d[idx] = sum + comp;
+}
+
+hipError_t launch_time_assembly(hipStream_t st, int S, int K, int R, int npole, int64_t N,
+                                const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
+                                const cpx<double> *alpha, const cpx<double> *g, double *d) {
+  const int64_t tot = (int64_t)S * K * R;
+  hipLaunchKernelGGL(k_time_assembly, dim3(grid_1d(tot, 128, 1 << 30)), dim3(128), 0, st, S, K, R,
+                     npole, N, q_ptr, q_col, q_val, alpha, g, d);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------- Jacobian pieces
+__global__ void k_set_sigma_exp(int P, const int32_t *params, const double *m, double *sigma) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  sigma[params[p]] = exp(m[p]);
+}
+
+hipError_t launch_set_sigma_exp(hipStream_t st, int P, const int32_t *params, const double *m,
+                                double *sigma) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_sigma_exp, dim3((P + 255) / 256), dim3(256), 0, st, P, params, m, sigma);
+  return hipGetLastError();
+}
+
+__global__ void k_param_scatter(int P, const int32_t *params, const double *v,
+                                const double *sigma, double *vs) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int32_t c = params[p];
+  vs[c] = v[p] * sigma[c];
+}
+
+hipError_t launch_param_scatter(hipStream_t st, int P, const int32_t *params, const double *v,
+                                const double *sigma, int64_t n_cells, double *vs) {
+  hipError_t e = launch_fill_f64(st, vs, n_cells, 0.0);
+  if (e != hipSuccess) return e;
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_param_scatter, dim3((P + 255) / 256), dim3(256), 0, st, P, params, v, sigma,
+                     vs);
+  return hipGetLastError();
+}
+
+// rhs[p][q][s] = xi_p sum_{cells c of edge q} vs[c] sum_b Me[la][b] g[p][cell_new[c][b]][s]
+__global__ void k_jv_rhs(int64_t N, int npole, int S, int nx, int ny, int nz,
+                         const int32_t *row_edge, const int32_t *cell_new, const double *vs,
+                         const double *Me, const double *xi, const cpx<double> *g,
+                         cpx<double> *rhs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mS = (int64_t)npole * S;
+  if (idx >= N * mS) return;
+  const int64_t q = idx / mS;
+  const int ps = (int)(idx % mS);
+  const int p = ps / S, c = ps % S;
+  const int64_t ex = (int64_t)nx * (ny + 1) * (nz + 1);
+  const int64_t ey = (int64_t)(nx + 1) * ny * (nz + 1);
+  int64_t e = row_edge[q];
+  int d, i, j, k;
+  if (e < ex) {
+    d = 0; i = (int)(e % nx); int64_t r = e / nx; j = (int)(r % (ny + 1)); k = (int)(r / (ny + 1));
+  } else if (e < ex + ey) {
+    e -= ex; d = 1; i = (int)(e % (nx + 1)); int64_t r = e / (nx + 1); j = (int)(r % ny); k = (int)(r / ny);
+  } else {
+    e -= ex + ey; d = 2; i = (int)(e % (nx + 1)); int64_t r = e / (nx + 1); j = (int)(r % (ny + 1)); k = (int)(r / (ny + 1));
+  }
+  const int AB[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+  const cpx<double> *G = g + (int64_t)p * N * S + c;
+  double ar = 0.0, ai = 0.0;
+  for (int pp = 0; pp < 4; ++pp) {
+    const int a = AB[pp][0], b = AB[pp][1];
+    int ci, cj, ck;
+    if (d == 0) { ci = i; cj = j - a; ck = k - b; }
+    else if (d == 1) { ci = i - a; cj = j; ck = k - b; }
+    else { ci = i - a; cj = j - b; ck = k; }
+    if (ci < 0 || cj < 0 || ck < 0 || ci >= nx || cj >= ny || ck >= nz) continue;
+    const int64_t cell = ci + (int64_t)nx * (cj + (int64_t)ny * ck);
+    const double w = vs[cell];
+    if (w == 0.0) continue;
+    const int la = 4 * d + pp;
+    double sr = 0.0, si = 0.0;
+    for (int t = 0; t < 4; ++t) {
+      const int lb = 4 * d + t;
+      const int32_t qb = cell_new[cell * 12 + lb];
+      if (qb < 0) continue;
+      const cpx<double> v = G[(int64_t)qb * S];
+      sr += Me[la * 12 + lb] * v.re;
+      si += Me[la * 12 + lb] * v.im;
+    }
+    ar += w * sr;
+    ai += w * si;
+  }
+  const double xr = xi[2 * p], xim = xi[2 * p + 1];
+  rhs[((int64_t)p * N + q) * S + c] = {xr * ar - xim * ai, xr * ai + xim * ar};
+}
+
+hipError_t launch_jv_rhs(hipStream_t st, int64_t N, int npole, int S, int nx, int ny, int nz,
+                         const int32_t *row_edge, const int32_t *cell_new, const double *vs,
+                         const double *Me, const double *xi, const cpx<double> *g,
+                         cpx<double> *rhs) {
+  const int64_t tot = N * npole * S;
+  hipLaunchKernelGGL(k_jv_rhs, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
+                     nx, ny, nz, row_edge, cell_new, vs, Me, xi, g, rhs);
+  return hipGetLastError();
+}
+
+// rhs = Q^T (sum_j alpha[j][p] w[s][j][:]); one thread per (pole, rhs) walks
+// the receivers in order (rhs must be zeroed first).
+__global__ void k_jtw_rhs(int S, int K, int R, int npole, int64_t N, const int64_t *q_ptr,
+                          const int32_t *q_col, const double *q_val, const cpx<double> *alpha,
+                          const double *w, cpx<double> *rhs) {
+  const int ps = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ps >= npole * S) return;
+  const int p = ps / S, s = ps % S;
+  cpx<double> *Rv = rhs + (int64_t)p * N * S + s;
+  for (int r = 0; r < R; ++r) {
+    double wr = 0.0, wi = 0.0;
+    for (int j = 0; j < K; ++j) {
+      const double x = w[((int64_t)s * K + j) * R + r];
+      const cpx<double> a = alpha[(int64_t)j * npole + p];
+      wr += a.re * x;
+      wi += a.im * x;
+    }
+    for (int64_t t = q_ptr[r]; t < q_ptr[r + 1]; ++t) {
+      cpx<double> v = Rv[(int64_t)q_col[t] * S];
+      v.re += q_val[t] * wr;
+      v.im += q_val[t] * wi;
+      Rv[(int64_t)q_col[t] * S] = v;
+    }
+  }
+}
+
+hipError_t launch_jtw_rhs(hipStream_t st, int S, int K, int R, int npole, int64_t N,
+                          const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
+                          const cpx<double> *alpha, const double *w, cpx<double> *rhs) {
+  hipError_t e = launch_fill_f64(st, (double *)rhs, 2 * N * npole * S, 0.0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_jtw_rhs, dim3((npole * S + 63) / 64), dim3(64), 0, st, S, K, R, npole, N,
+                     q_ptr, q_col, q_val, alpha, w, rhs);
+  return hipGetLastError();
+}
+
+// (J^T w)_p = 2 Re sum_{i,s} xi_i sigma_c g|_c^T Me lam|_c, one thread per parameter
+__global__ void k_jtw_reduce(int P, int npole, int S, int64_t N, const int32_t *params,
+                             const int32_t *cell_new, const double *sigma, const double *Me,
+                             const double *xi, const cpx<double> *g, const cpx<double> *lam,
+                             double *out) {
+  const int pp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pp >= P) return;
+  const int64_t cell = params[pp];
+  int32_t qe[12];
+  for (int t = 0; t < 12; ++t) qe[t] = cell_new[cell * 12 + t];
+  double tot = 0.0;
+  for (int i = 0; i < npole; ++i) {
+    double br = 0.0, bi = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const cpx<double> *G = g + (int64_t)i * N * S + s;
+      const cpx<double> *L = lam + (int64_t)i * N * S + s;
+      for (int dd = 0; dd < 3; ++dd) {
+        cpx<double> gv[4], lv[4];
+        for (int t = 0; t < 4; ++t) {
+          const int32_t q = qe[4 * dd + t];
+          gv[t] = q >= 0 ? G[(int64_t)q * S] : cpx<double>{0.0, 0.0};
+          lv[t] = q >= 0 ? L[(int64_t)q * S] : cpx<double>{0.0, 0.0};
+        }
+        for (int a = 0; a < 4; ++a) {
+          double mr = 0.0, mi = 0.0;
+          for (int b = 0; b < 4; ++b) {
+            const double m = Me[(4 * dd + a) * 12 + 4 * dd + b];
+            mr += m * lv[b].re;
+            mi += m * lv[b].im;
+          }
+          br += gv[a].re * mr - gv[a].im * mi;
+          bi += gv[a].re * mi + gv[a].im * mr;
+        }
+      }
+    }
+    tot += 2.0 * (xi[2 * i] * br - xi[2 * i + 1] * bi);
+  }
+  out[pp] = tot * sigma[cell];
+}
+
+hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int64_t N,
+                             const int32_t *params, const int32_t *cell_new, const double *sigma,
+                             const double *Me, const double *xi, const cpx<double> *g,
+                             const cpx<double> *lam, double *out) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_jtw_reduce, dim3((P + 127) / 128), dim3(128), 0, st, P, npole, S, N, params,
+                     cell_new, sigma, Me, xi, g, lam, out);
+  return hipGetLastError();
+}
+
+// inv[ps] = 1/sqrt(re(dot)) (1 for zero), nrm[ps] = sqrt(re(dot))
+__global__ void k_norm_scales(int n, const cpx<double> *dots, double *inv, double *nrm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = sqrt(fmax(dots[i].re, 0.0));
+  nrm[i] = v;
+  inv[i] = v > 0.0 ? 1.0 / v : 1.0;
+}
+
+hipError_t launch_norm_scales(hipStream_t st, int n, const cpx<double> *dots, double *inv,
+                              double *nrm) {
+  hipLaunchKernelGGL(k_norm_scales, dim3((n + 127) / 128), dim3(128), 0, st, n, dots, inv, nrm);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_f64(hipStream_t st, double *p, int64_t n, double v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_1d(n, 256, 8192)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace tem

@@ -1,0 +1,1297 @@
+// C ABI of libtem: context, state machine, symbolic maps, and the host
+// orchestration of the batched factorisation, the solves with FP64
+// refinement, the time assembly and the Jacobian products.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tem.h"
+#include "host_mesh.h"
+#include "tem_internal.h"
+
+using namespace tem;
+
+namespace {
+
+std::string g_create_error;
+
+// ------------------------------------------------------------ device buffer
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t b) {
+    if (b == bytes && p) return hipSuccess;
+    release();
+    if (b == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = b;
+    return hipSuccess;
+  }
+  template <typename T>
+  T *as() const {
+    return (T *)p;
+  }
+};
+
+template <typename T>
+hipError_t upload(DBuf &b, const std::vector<T> &v, hipStream_t st) {
+  hipError_t e = b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
+  if (e != hipSuccess) return e;
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+}
+
+struct LevelInfo {
+  std::vector<int32_t> nodes;
+  int64_t lvl_begin = 0;           // offset in the device level-node list
+  int n = 0;
+  int max_k = 0, max_u = 0, max_n = 0;
+  int max_u_child[2] = {0, 0};
+  int64_t panel_begin = 0, panel_end = 0;   // per-pole element range
+  int64_t amap_begin = 0, amap_end = 0;
+  int64_t cb_size = 0;             // elements per pole
+  int64_t w_rows = 0;              // update rows per pole
+};
+
+struct Tiles {
+  // tiles of the lower trapezoid with columns [cbeg, cend) of an n-row front
+  static int64_t count(int64_t n, int64_t cbeg, int64_t cend) {
+    if (cbeg >= cend) return 0;
+    int64_t nct = (cend - cbeg + 63) / 64, tot = 0;
+    for (int64_t ct = 0; ct < nct; ++ct) tot += (n - (cbeg + 64 * ct) + 63) / 64;
+    return tot;
+  }
+};
+
+}  // namespace
+
+struct tem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // stages
+  bool assembled = false, analysed = false, factored = false, solved = false, surveyed = false;
+  // mesh
+  tem_mesh mesh{};
+  MeshTopo mt;
+  double Ke[144], Me[144];
+  std::vector<int32_t> params;
+  // ordering currently used by the device pattern
+  std::vector<int32_t> perm;
+  Pattern pat;
+  Symbolic sym;
+  int leaf = 4;
+  // device: mesh and operators
+  DBuf d_rowptr, d_col, d_K, d_M, d_row_edge, d_edge_new, d_cell_new, d_sigma, d_params, d_Ke,
+      d_Me;
+  // device: symbolic
+  DBuf d_first, d_k, d_u, d_rows_off, d_rows, d_rel, d_panel_off, d_cb_off, d_w_off, d_gmap_off,
+      d_gmap0, d_gmap1, d_child0, d_child1, d_lvl_nodes, d_amap_csr, d_amap_pos;
+  std::vector<LevelInfo> levels;   // by depth (0 = root)
+  int64_t pole_stride = 0;         // panel elements per pole
+  int64_t cb_stride = 0;           // max level CB elements per pole
+  int64_t w_rows_max = 0;
+  // factors
+  int npole = 0;
+  tem_precision prec = TEM_FP64;
+  std::vector<double> xi;
+  DBuf d_xi, d_factor, d_cb0, d_cb1, d_flags;
+  int n_groups = 0, group_size = 0;
+  int n_tiny = 0;
+  double factor_ms = 0.0, solve_ms = 0.0;
+  int last_solves = 0;
+  // solve state
+  int S = 0;
+  DBuf d_g;                        // cached g [pole][N][S] complex double
+  DBuf d_fnew;                     // sources [N][S] real (new ordering)
+  // survey
+  int R = 0, K = 0;
+  DBuf d_qptr, d_qcol, d_qval, d_alpha;
+  // work space
+  DBuf w_x, w_t, w_w0, w_w1;       // factor-precision sweep buffers
+  DBuf v_r, v_z, v_x, v_w, v_rhs, v_lam, v_vs, v_dots, v_partial, v_inv, v_nrm, v_coef, v_mask;
+  DBuf v_basis;
+  int basis_len = 0;
+
+  hipError_t check_last() { return hipGetLastError(); }
+};
+
+namespace {
+
+tem_status fail(tem_ctx *c, tem_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+tem_status hip_fail(tem_ctx *c, hipError_t e, const char *where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? TEM_ENOMEM : TEM_EDEVICE, m);
+}
+
+#define HIPCHK(expr, where)                     \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(c, e_, where); \
+  } while (0)
+
+int64_t N_of(const tem_ctx *c) { return c->mt.n_unknowns; }
+
+// --------------------------------------------------- assembly on the device
+tem_status upload_pattern_and_assemble(tem_ctx *c) {
+  hipStream_t st = c->stream;
+  build_pattern(c->mt, c->perm, c->pat);
+  HIPCHK(upload(c->d_rowptr, c->pat.rowptr, st), "upload rowptr");
+  HIPCHK(upload(c->d_col, c->pat.col, st), "upload col");
+  HIPCHK(upload(c->d_row_edge, c->pat.row_edge, st), "upload row_edge");
+  HIPCHK(upload(c->d_edge_new, c->pat.edge_new, st), "upload edge_new");
+  // cell -> 12 new indices
+  std::vector<int32_t> cn((size_t)c->mt.n_cells * 12);
+  int64_t ce[12];
+  for (int k = 0; k < c->mt.nz; ++k)
+    for (int j = 0; j < c->mt.ny; ++j)
+      for (int i = 0; i < c->mt.nx; ++i) {
+        int64_t cell = i + (int64_t)c->mt.nx * (j + (int64_t)c->mt.ny * k);
+        c->mt.cell_edges(i, j, k, ce);
+        for (int t = 0; t < 12; ++t) cn[cell * 12 + t] = c->pat.edge_new[ce[t]];
+      }
+  HIPCHK(upload(c->d_cell_new, cn, st), "upload cell_new");
+  const size_t nnz = c->pat.col.size();
+  HIPCHK(c->d_K.alloc(sizeof(double) * nnz), "alloc K");
+  HIPCHK(c->d_M.alloc(sizeof(double) * nnz), "alloc M");
+  HIPCHK(launch_assemble_KM(st, N_of(c), c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+                            c->d_row_edge.as<int32_t>(), c->d_edge_new.as<int32_t>(), c->mt.nx,
+                            c->mt.ny, c->mt.nz, c->d_Ke.as<double>(), c->d_Me.as<double>(),
+                            c->d_sigma.as<double>(), c->d_K.as<double>(), c->d_M.as<double>()),
+         "assemble kernel");
+  return TEM_OK;
+}
+
+void drop_factors(tem_ctx *c) {
+  c->d_factor.release();
+  c->d_cb0.release();
+  c->d_cb1.release();
+  c->factored = false;
+  c->solved = false;
+  c->d_g.release();
+}
+
+// ------------------------------------------------ symbolic maps (host)
+tem_status build_front_maps(tem_ctx *c) {
+  const Symbolic &sym = c->sym;
+  const int ns = (int)sym.nodes.size();
+  std::vector<int64_t> first(ns), rows_off(ns), panel_off(ns), cb_off(ns), w_off(ns), gmap_off(ns);
+  std::vector<int32_t> kk(ns), uu(ns), child0(ns), child1(ns);
+  std::vector<int32_t> rel(sym.rows.size(), -1);
+  for (int s = 0; s < ns; ++s) {
+    const SymNode &nd = sym.nodes[s];
+    first[s] = nd.first;
+    kk[s] = (int32_t)(nd.last - nd.first);
+    uu[s] = (int32_t)nd.nrows;
+    rows_off[s] = nd.rows_off;
+    child0[s] = nd.child[0];
+    child1[s] = nd.child[1];
+  }
+  // relative maps: each U_s row's position in the parent's front
+  for (int s = 0; s < ns; ++s) {
+    const SymNode &nd = sym.nodes[s];
+    if (nd.parent < 0) {
+      if (nd.nrows) return fail(c, TEM_EINVAL, "root supernode has update rows");
+      continue;
+    }
+    const SymNode &pa = sym.nodes[nd.parent];
+    const int32_t *prow = sym.rows.data() + pa.rows_off;
+    for (int64_t a = 0; a < nd.nrows; ++a) {
+      int32_t q = sym.rows[nd.rows_off + a];
+      int64_t pos;
+      if (q >= pa.first && q < pa.last) {
+        pos = q - pa.first;
+      } else {
+        const int32_t *it = std::lower_bound(prow, prow + pa.nrows, q);
+        if (it == prow + pa.nrows || *it != q)
+          return fail(c, TEM_EINVAL, "update row missing from the parent front");
+        pos = (pa.last - pa.first) + (it - prow);
+      }
+      rel[nd.rows_off + a] = (int32_t)pos;
+    }
+  }
+  // levels (depth); factor/solve order is deepest first
+  int nl = sym.n_levels;
+  c->levels.assign(nl, LevelInfo());
+  for (int s = 0; s < ns; ++s) c->levels[sym.nodes[s].level].nodes.push_back(s);
+  std::vector<int32_t> lvl_nodes;
+  int64_t poff = 0;
+  c->cb_stride = 0;
+  c->w_rows_max = 0;
+  for (int L = nl - 1; L >= 0; --L) {
+    LevelInfo &li = c->levels[L];
+    li.n = (int)li.nodes.size();
+    li.lvl_begin = (int64_t)lvl_nodes.size();
+    lvl_nodes.insert(lvl_nodes.end(), li.nodes.begin(), li.nodes.end());
+    li.panel_begin = poff;
+    int64_t cbo = 0, wo = 0;
+    for (int s : li.nodes) {
+      int64_t n = (int64_t)kk[s] + uu[s];
+      panel_off[s] = poff;
+      poff += panel_size(n, kk[s]);
+      cb_off[s] = cbo;
+      cbo += (int64_t)uu[s] * uu[s];
+      w_off[s] = wo;
+      wo += uu[s];
+      li.max_k = std::max(li.max_k, kk[s]);
+      li.max_u = std::max(li.max_u, uu[s]);
+      li.max_n = std::max(li.max_n, (int)n);
+      for (int sl = 0; sl < 2; ++sl) {
+        int ch = sym.nodes[s].child[sl];
+        if (ch >= 0) li.max_u_child[sl] = std::max(li.max_u_child[sl], uu[ch]);
+      }
+    }
+    li.panel_end = poff;
+    li.cb_size = cbo;
+    li.w_rows = wo;
+    c->cb_stride = std::max(c->cb_stride, cbo);
+    c->w_rows_max = std::max(c->w_rows_max, wo);
+  }
+  c->pole_stride = poff;
+  // original-entry map, level by level (deepest first)
+  std::vector<int32_t> amap_csr;
+  std::vector<int64_t> amap_pos;
+  const Pattern &pat = c->pat;
+  for (int L = nl - 1; L >= 0; --L) {
+    LevelInfo &li = c->levels[L];
+    li.amap_begin = (int64_t)amap_csr.size();
+    for (int s : li.nodes) {
+      const SymNode &nd = sym.nodes[s];
+      const int64_t k = nd.last - nd.first, n = k + nd.nrows;
+      const int32_t *rw = sym.rows.data() + nd.rows_off;
+      for (int64_t j = nd.first; j < nd.last; ++j) {
+        for (int64_t t = pat.rowptr[j]; t < pat.rowptr[j + 1]; ++t) {
+          int32_t r = pat.col[t];
+          if (r < j) continue;
+          int64_t lr;
+          if (r < nd.last) {
+            lr = r - nd.first;
+          } else {
+            const int32_t *it = std::lower_bound(rw, rw + nd.nrows, r);
+            if (it == rw + nd.nrows || *it != r)
+              return fail(c, TEM_EINVAL, "matrix entry outside its front");
+            lr = k + (it - rw);
+          }
+          amap_csr.push_back((int32_t)t);
+          amap_pos.push_back(panel_off[s] + panel_elem(n, lr, j - nd.first));
+        }
+      }
+    }
+    li.amap_end = (int64_t)amap_csr.size();
+  }
+  // child gather maps for the solves
+  std::vector<int32_t> gmap0, gmap1;
+  int64_t goff = 0;
+  for (int s = 0; s < ns; ++s) {
+    const SymNode &nd = sym.nodes[s];
+    const int64_t n = (nd.last - nd.first) + nd.nrows;
+    gmap_off[s] = goff;
+    gmap0.resize(goff + n, -1);
+    gmap1.resize(goff + n, -1);
+    for (int sl = 0; sl < 2; ++sl) {
+      int ch = nd.child[sl];
+      if (ch < 0) continue;
+      const SymNode &cn = sym.nodes[ch];
+      for (int64_t a = 0; a < cn.nrows; ++a) {
+        int32_t pos = rel[cn.rows_off + a];
+        (sl == 0 ? gmap0 : gmap1)[goff + pos] = (int32_t)a;
+      }
+    }
+    goff += n;
+  }
+  hipStream_t st = c->stream;
+  HIPCHK(upload(c->d_first, first, st), "upload first");
+  HIPCHK(upload(c->d_k, kk, st), "upload k");
+  HIPCHK(upload(c->d_u, uu, st), "upload u");
+  HIPCHK(upload(c->d_rows_off, rows_off, st), "upload rows_off");
+  HIPCHK(upload(c->d_rows, sym.rows, st), "upload rows");
+  HIPCHK(upload(c->d_rel, rel, st), "upload rel");
+  HIPCHK(upload(c->d_panel_off, panel_off, st), "upload panel_off");
+  HIPCHK(upload(c->d_cb_off, cb_off, st), "upload cb_off");
+  HIPCHK(upload(c->d_w_off, w_off, st), "upload w_off");
+  HIPCHK(upload(c->d_gmap_off, gmap_off, st), "upload gmap_off");
+  HIPCHK(upload(c->d_gmap0, gmap0, st), "upload gmap0");
+  HIPCHK(upload(c->d_gmap1, gmap1, st), "upload gmap1");
+  HIPCHK(upload(c->d_child0, child0, st), "upload child0");
+  HIPCHK(upload(c->d_child1, child1, st), "upload child1");
+  HIPCHK(upload(c->d_lvl_nodes, lvl_nodes, st), "upload levels");
+  HIPCHK(upload(c->d_amap_csr, amap_csr, st), "upload amap_csr");
+  HIPCHK(upload(c->d_amap_pos, amap_pos, st), "upload amap_pos");
+  HIPCHK(hipStreamSynchronize(st), "sync maps");
+  return TEM_OK;
+}
+
+FrontTab front_tab(const tem_ctx *c) {
+  FrontTab ft;
+  ft.first = c->d_first.as<int64_t>();
+  ft.k = c->d_k.as<int32_t>();
+  ft.u = c->d_u.as<int32_t>();
+  ft.rows_off = c->d_rows_off.as<int64_t>();
+  ft.rows = c->d_rows.as<int32_t>();
+  ft.rel = c->d_rel.as<int32_t>();
+  ft.panel_off = c->d_panel_off.as<int64_t>();
+  ft.cb_off = c->d_cb_off.as<int64_t>();
+  ft.w_off = c->d_w_off.as<int64_t>();
+  ft.gmap_off = c->d_gmap_off.as<int64_t>();
+  ft.gmap0 = c->d_gmap0.as<int32_t>();
+  ft.gmap1 = c->d_gmap1.as<int32_t>();
+  ft.child0 = c->d_child0.as<int32_t>();
+  ft.child1 = c->d_child1.as<int32_t>();
+  return ft;
+}
+
+const int32_t *lvl_ptr(const tem_ctx *c, const LevelInfo &li) {
+  return c->d_lvl_nodes.as<int32_t>() + li.lvl_begin;
+}
+
+// ------------------------------------------------------- factorisation
+template <typename T>
+tem_status factor_group(tem_ctx *c, int p0, int g) {
+  hipStream_t st = c->stream;
+  FrontTab ft = front_tab(c);
+  cpx<T> *F = c->d_factor.as<cpx<T>>() + (int64_t)p0 * c->pole_stride;
+  cpx<T> *arena[2] = {c->d_cb0.as<cpx<T>>(), c->d_cb1.as<cpx<T>>()};
+  const double *xi = c->d_xi.as<double>() + 2 * p0;
+  const int nl = (int)c->levels.size();
+  const Symbolic &sym = c->sym;
+  for (int L = nl - 1; L >= 0; --L) {
+    const LevelInfo &li = c->levels[L];
+    const int32_t *ln = lvl_ptr(c, li);
+    cpx<T> *cbL = arena[L & 1];
+    cpx<T> *cbC = arena[(L + 1) & 1];
+    HIPCHK(launch_fill_zero<T>(st, F + li.panel_begin, li.panel_end - li.panel_begin, g,
+                               c->pole_stride),
+           "zero panels");
+    HIPCHK(launch_fill_zero<T>(st, cbL, li.cb_size, g, c->cb_stride), "zero cb");
+    HIPCHK(launch_front_assemble<T>(st, li.amap_end - li.amap_begin,
+                                    c->d_amap_csr.as<int32_t>() + li.amap_begin,
+                                    c->d_amap_pos.as<int64_t>() + li.amap_begin,
+                                    c->d_K.as<double>(), c->d_M.as<double>(), xi, g, F,
+                                    c->pole_stride),
+           "front assemble");
+    for (int sl = 0; sl < 2; ++sl)
+      HIPCHK(launch_extend_add<T>(st, ft, ln, li.n, sl, li.max_u_child[sl], g, F, c->pole_stride,
+                                  cbL, cbC, c->cb_stride),
+             "extend-add");
+    for (int j0 = 0; j0 < li.max_k; j0 += NB) {
+      int max_rows = 0;
+      int64_t max_tiles = 0;
+      for (int s : li.nodes) {
+        const SymNode &nd = sym.nodes[s];
+        const int64_t k = nd.last - nd.first, n = k + nd.nrows;
+        if (j0 >= k) continue;
+        const int64_t w = std::min<int64_t>(NB, k - j0);
+        max_rows = std::max<int>(max_rows, (int)(n - j0 - w));
+        max_tiles = std::max(max_tiles, Tiles::count(n, j0 + NB, k));
+      }
+      HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, g, F, c->pole_stride,
+                                  c->d_flags.as<int>()),
+             "panel diag");
+      HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, max_rows, g, F, c->pole_stride),
+             "panel trsm");
+      HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 0, j0, max_tiles, g, F, c->pole_stride,
+                                    cbL, c->cb_stride),
+             "trailing update");
+    }
+    int64_t cb_tiles = 0;
+    for (int s : li.nodes) {
+      const SymNode &nd = sym.nodes[s];
+      const int64_t k = nd.last - nd.first, n = k + nd.nrows;
+      if (k > 0) cb_tiles = std::max(cb_tiles, Tiles::count(n, k, n));
+    }
+    HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, cb_tiles, g, F, c->pole_stride, cbL,
+                                  c->cb_stride),
+           "contribution update");
+  }
+  return TEM_OK;
+}
+
+// ---------------------------------------------------------------- sweeps
+template <typename T>
+tem_status ensure_sweep_ws(tem_ctx *c, int S) {
+  const int64_t N = N_of(c);
+  const size_t vec = sizeof(cpx<T>) * (size_t)c->npole * N * S;
+  const size_t wb = sizeof(cpx<T>) * (size_t)c->npole * std::max<int64_t>(c->w_rows_max, 1) * S;
+  if (c->w_x.bytes != vec) HIPCHK(c->w_x.alloc(vec), "alloc sweep x");
+  if (c->w_t.bytes != vec) HIPCHK(c->w_t.alloc(vec), "alloc sweep t");
+  if (c->w_w0.bytes != wb) HIPCHK(c->w_w0.alloc(wb), "alloc sweep w0");
+  if (c->w_w1.bytes != wb) HIPCHK(c->w_w1.alloc(wb), "alloc sweep w1");
+  return TEM_OK;
+}
+
+// in place: x (factor precision, [pole][N][S]) <- A^{-1} x for every pole
+template <typename T>
+tem_status sweep(tem_ctx *c, cpx<T> *x, int S) {
+  hipStream_t st = c->stream;
+  FrontTab ft = front_tab(c);
+  const int64_t N = N_of(c);
+  const cpx<T> *F = c->d_factor.as<cpx<T>>();
+  const int m = c->npole;
+  cpx<T> *W[2] = {c->w_w0.as<cpx<T>>(), c->w_w1.as<cpx<T>>()};
+  const int64_t ws = std::max<int64_t>(c->w_rows_max, 1) * S;
+  cpx<T> *t = c->w_t.as<cpx<T>>();
+  const int nl = (int)c->levels.size();
+  for (int L = nl - 1; L >= 0; --L) {
+    const LevelInfo &li = c->levels[L];
+    const int32_t *ln = lvl_ptr(c, li);
+    HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, m, S, N, F, c->pole_stride, x, W[(L + 1) & 1], ws),
+           "fwd tri");
+    HIPCHK(launch_fwd_rect<T>(st, ft, ln, li.n, li.max_u, m, S, N, F, c->pole_stride, x,
+                              W[(L + 1) & 1], W[L & 1], ws),
+           "fwd rect");
+  }
+  for (int L = 0; L < nl; ++L) {
+    const LevelInfo &li = c->levels[L];
+    const int32_t *ln = lvl_ptr(c, li);
+    HIPCHK(launch_bwd_rect<T>(st, ft, ln, li.n, li.max_k, m, S, N, F, c->pole_stride, x, t, N * S),
+           "bwd rect");
+    HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, m, S, N, F, c->pole_stride, x, t, N * S),
+           "bwd tri");
+  }
+  return TEM_OK;
+}
+
+tem_status ensure_vec(tem_ctx *c, DBuf &b, size_t bytes, const char *what) {
+  if (b.bytes != bytes) HIPCHK(b.alloc(bytes), what);
+  return TEM_OK;
+}
+
+#define TRY(expr)                  \
+  do {                             \
+    tem_status s_ = (expr);        \
+    if (s_ != TEM_OK) return s_;   \
+  } while (0)
+
+int dot_blocks(int64_t N) {
+  int64_t b = (N + 8191) / 8192;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256));
+}
+
+// norms^2 of all systems of v -> host
+tem_status sysnorms(tem_ctx *c, const cpx<double> *v, int S, std::vector<double> &out) {
+  const int64_t N = N_of(c);
+  const int mS = c->npole * S;
+  const int nb = dot_blocks(N);
+  TRY(ensure_vec(c, c->v_partial, sizeof(cpx<double>) * (size_t)nb * mS * 2, "alloc partial"));
+  TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)mS * 64, "alloc dots"));
+  HIPCHK(launch_batched_dot(c->stream, N, c->npole, S, v, v, true, c->v_partial.as<cpx<double>>(),
+                            nb, c->v_dots.as<cpx<double>>()),
+         "norm");
+  std::vector<cpx<double>> h(mS);
+  HIPCHK(hipMemcpyAsync(h.data(), c->v_dots.p, sizeof(cpx<double>) * mS, hipMemcpyDeviceToHost,
+                        c->stream),
+         "norm d2h");
+  HIPCHK(hipStreamSynchronize(c->stream), "norm sync");
+  out.resize(mS);
+  for (int i = 0; i < mS; ++i) out[i] = std::sqrt(std::max(h[i].re, 0.0));
+  return TEM_OK;
+}
+
+// out = A^{-1} in (approximately, in the factor precision), FP64 in/out
+tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c);
+  const int m = c->npole;
+  const int mS = m * S;
+  if (c->prec == TEM_FP64) {
+    TRY(ensure_sweep_ws<double>(c, S));
+    cpx<double> *x = c->w_x.as<cpx<double>>();
+    HIPCHK(hipMemcpyAsync(x, in, sizeof(cpx<double>) * (size_t)mS * N, hipMemcpyDeviceToDevice, st),
+           "copy rhs");
+    TRY(sweep<double>(c, x, S));
+    HIPCHK(hipMemcpyAsync(out, x, sizeof(cpx<double>) * (size_t)mS * N, hipMemcpyDeviceToDevice, st),
+           "copy sol");
+    return TEM_OK;
+  }
+  TRY(ensure_sweep_ws<float>(c, S));
+  const int nb = dot_blocks(N);
+  TRY(ensure_vec(c, c->v_partial, sizeof(cpx<double>) * (size_t)nb * mS * 2, "alloc partial"));
+  TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)mS * 64, "alloc dots"));
+  TRY(ensure_vec(c, c->v_inv, sizeof(double) * mS, "alloc inv"));
+  TRY(ensure_vec(c, c->v_nrm, sizeof(double) * mS, "alloc nrm"));
+  HIPCHK(launch_batched_dot(st, N, m, S, in, in, true, c->v_partial.as<cpx<double>>(), nb,
+                            c->v_dots.as<cpx<double>>()),
+         "precond norm");
+  HIPCHK(launch_norm_scales(st, mS, c->v_dots.as<cpx<double>>(), c->v_inv.as<double>(),
+                            c->v_nrm.as<double>()),
+         "precond scales");
+  cpx<float> *x = c->w_x.as<cpx<float>>();
+  HIPCHK(launch_convert_in<float>(st, N * S, m, S, in, c->v_inv.as<double>(), x), "to fp32");
+  TRY(sweep<float>(c, x, S));
+  HIPCHK(launch_convert_out<float>(st, N * S, m, S, x, c->v_nrm.as<double>(), out), "to fp64");
+  return TEM_OK;
+}
+
+struct IrResult {
+  std::vector<int> iters;
+  std::vector<double> rel;
+  int unconverged = 0;
+  int solves = 0;
+};
+
+// Solve A_p x_ps = f_ps for all systems.  f either real [N][S] (same for
+// all poles) or complex [pole][N][S].  x: [pole][N][S] complex double.
+// FP64 factors: classical refinement.  FP32 factors: restarted GMRES in
+// FP64 right-preconditioned by the FP32 factors (GMRES-based iterative
+// refinement), restart = 1 being classical refinement.
+tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_cplx, int S,
+                        cpx<double> *x, const tem_ir_opts *ir, IrResult &res) {
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c);
+  const int m = c->npole;
+  const int mS = m * S;
+  const double rtol = (ir && ir->rtol > 0) ? ir->rtol : 1e-10;
+  const int max_iter = (ir && ir->max_iter > 0) ? ir->max_iter : 200;
+  int restart = (ir && ir->restart > 0) ? ir->restart : 30;
+  restart = std::min(restart, 60);
+  if (c->prec == TEM_FP64) restart = 1;
+  const size_t vbytes = sizeof(cpx<double>) * (size_t)mS * N;
+  TRY(ensure_vec(c, c->v_r, vbytes, "alloc r"));
+  TRY(ensure_vec(c, c->v_z, vbytes, "alloc z"));
+  TRY(ensure_vec(c, c->v_w, vbytes, "alloc w"));
+  TRY(ensure_vec(c, c->v_coef, sizeof(cpx<double>) * (size_t)mS * 2, "alloc coef"));
+  TRY(ensure_vec(c, c->v_mask, sizeof(int) * (size_t)mS, "alloc mask"));
+  cpx<double> *r = c->v_r.as<cpx<double>>();
+  cpx<double> *z = c->v_z.as<cpx<double>>();
+  cpx<double> *w = c->v_w.as<cpx<double>>();
+  const double *xi = c->d_xi.as<double>();
+  // x = 0, so that r = f and ||r|| = ||f||
+  std::vector<double> fn;
+  HIPCHK(launch_fill_f64(st, (double *)x, 2 * (int64_t)mS * N, 0.0), "zero x");
+  HIPCHK(launch_residual(st, N, m, S, c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+                         c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
+         "residual");
+  TRY(sysnorms(c, r, S, fn));
+  res.iters.assign(mS, 0);
+  res.rel.assign(mS, 0.0);
+  std::vector<int> active(mS, 1);
+  for (int i = 0; i < mS; ++i)
+    if (fn[i] == 0.0) active[i] = 0;
+  int solves = 0;
+  if (restart <= 1) {
+    // classical refinement
+    for (int it = 0; it <= max_iter; ++it) {
+      std::vector<double> rn;
+      TRY(sysnorms(c, r, S, rn));
+      bool any = false;
+      for (int i = 0; i < mS; ++i) {
+        res.rel[i] = fn[i] > 0 ? rn[i] / fn[i] : 0.0;
+        if (active[i] && res.rel[i] <= rtol) active[i] = 0;
+        any = any || active[i];
+      }
+      if (!any || it == max_iter) break;
+      HIPCHK(hipMemcpyAsync(c->v_mask.p, active.data(), sizeof(int) * mS, hipMemcpyHostToDevice,
+                            st),
+             "mask");
+      TRY(precond(c, r, z, S));
+      ++solves;
+      for (int i = 0; i < mS; ++i)
+        if (active[i]) res.iters[i]++;
+      std::vector<cpx<double>> one(mS, {1.0, 0.0});
+      HIPCHK(hipMemcpyAsync(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS,
+                            hipMemcpyHostToDevice, st),
+             "coef");
+      HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
+                                 c->v_mask.as<int>()),
+             "x += z");
+      HIPCHK(launch_residual(st, N, m, S, c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+                             c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
+             "residual");
+    }
+  } else {
+    // GMRES(restart) with right preconditioning, all systems in lock step
+    const int kmax = restart;
+    TRY(ensure_vec(c, c->v_basis, vbytes * (size_t)(kmax + 1), "alloc krylov basis"));
+    cpx<double> *V = c->v_basis.as<cpx<double>>();
+    const int64_t vs = (int64_t)mS * N;
+    const int nb = dot_blocks(N);
+    TRY(ensure_vec(c, c->v_partial, sizeof(cpx<double>) * (size_t)nb * mS * 2, "alloc partial"));
+    TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)mS * 64, "alloc dots"));
+    TRY(ensure_vec(c, c->v_inv, sizeof(double) * mS, "alloc inv"));
+    TRY(ensure_vec(c, c->v_nrm, sizeof(double) * mS, "alloc nrm"));
+    cpx<double> *dots = c->v_dots.as<cpx<double>>();
+    typedef std::complex<double> cd;
+    int total = 0;
+    while (true) {
+      std::vector<double> rn;
+      TRY(sysnorms(c, r, S, rn));
+      bool any = false;
+      for (int i = 0; i < mS; ++i) {
+        res.rel[i] = fn[i] > 0 ? rn[i] / fn[i] : 0.0;
+        if (active[i] && res.rel[i] <= rtol) active[i] = 0;
+        any = any || active[i];
+      }
+      if (!any || total >= max_iter) break;
+      // V0 = r / ||r||
+      std::vector<double> inv(mS);
+      for (int i = 0; i < mS; ++i) inv[i] = rn[i] > 0 ? 1.0 / rn[i] : 0.0;
+      HIPCHK(hipMemcpyAsync(V, r, vbytes, hipMemcpyDeviceToDevice, st), "V0");
+      HIPCHK(hipMemcpyAsync(c->v_inv.p, inv.data(), sizeof(double) * mS, hipMemcpyHostToDevice, st),
+             "inv");
+      HIPCHK(launch_batched_scale(st, N, m, S, c->v_inv.as<double>(), V), "V0 scale");
+      // Hessenberg per system (column-major (kmax+1) x kmax), Givens
+      std::vector<cd> H((size_t)mS * (kmax + 1) * kmax, cd(0, 0));
+      std::vector<cd> cs((size_t)mS * kmax), sn((size_t)mS * kmax);
+      std::vector<cd> gvec((size_t)mS * (kmax + 1), cd(0, 0));
+      for (int i = 0; i < mS; ++i) gvec[(size_t)i * (kmax + 1)] = cd(rn[i], 0);
+      int kdone = 0;
+      std::vector<cpx<double>> hcol((size_t)mS * (kmax + 1));
+      for (int k = 0; k < kmax && total < max_iter; ++k) {
+        TRY(precond(c, V + k * vs, z, S));
+        ++solves;
+        ++total;
+        HIPCHK(launch_spmv_shifted(st, N, m, S, c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+                                   c->d_K.as<double>(), c->d_M.as<double>(), xi, z, w),
+               "A z");
+        // modified Gram-Schmidt, twice (reorthogonalisation)
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int j = 0; j <= k; ++j) {
+            HIPCHK(launch_batched_dot(st, N, m, S, V + j * vs, w, true,
+                                      c->v_partial.as<cpx<double>>(), nb, dots + j * mS),
+                   "mgs dot");
+            HIPCHK(launch_batched_axpy(st, N, m, S, dots + j * mS, -1.0, V + j * vs, w, nullptr),
+                   "mgs axpy");
+          }
+          HIPCHK(hipMemcpyAsync(hcol.data(), dots,
+                                sizeof(cpx<double>) * (size_t)mS * (k + 1), hipMemcpyDeviceToHost,
+                                st),
+                 "h d2h");
+          HIPCHK(hipStreamSynchronize(st), "h sync");
+          for (int j = 0; j <= k; ++j)
+            for (int i = 0; i < mS; ++i) {
+              const cpx<double> hv = hcol[(size_t)j * mS + i];
+              H[((size_t)i * kmax + k) * (kmax + 1) + j] += cd(hv.re, hv.im);
+            }
+        }
+        std::vector<double> wn;
+        TRY(sysnorms(c, w, S, wn));
+        std::vector<double> winv(mS);
+        for (int i = 0; i < mS; ++i) {
+          H[((size_t)i * kmax + k) * (kmax + 1) + k + 1] = cd(wn[i], 0);
+          winv[i] = wn[i] > 0 ? 1.0 / wn[i] : 0.0;
+        }
+        HIPCHK(hipMemcpyAsync(V + (k + 1) * vs, w, vbytes, hipMemcpyDeviceToDevice, st), "V k+1");
+        HIPCHK(hipMemcpyAsync(c->v_inv.p, winv.data(), sizeof(double) * mS, hipMemcpyHostToDevice,
+                              st),
+               "winv");
+        HIPCHK(launch_batched_scale(st, N, m, S, c->v_inv.as<double>(), V + (k + 1) * vs),
+               "V scale");
+        // Givens per system
+        bool all_small = true;
+        for (int i = 0; i < mS; ++i) {
+          cd *h = &H[((size_t)i * kmax + k) * (kmax + 1)];
+          for (int j = 0; j < k; ++j) {
+            cd a = h[j], b = h[j + 1];
+            h[j] = std::conj(cs[(size_t)i * kmax + j]) * a + std::conj(sn[(size_t)i * kmax + j]) * b;
+            h[j + 1] = -sn[(size_t)i * kmax + j] * a + cs[(size_t)i * kmax + j] * b;
+          }
+          cd a = h[k], b = h[k + 1];
+          double den = std::sqrt(std::norm(a) + std::norm(b));
+          cd cc = den > 0 ? a / den : cd(1, 0), ss = den > 0 ? b / den : cd(0, 0);
+          cs[(size_t)i * kmax + k] = cc;
+          sn[(size_t)i * kmax + k] = ss;
+          h[k] = std::conj(cc) * a + std::conj(ss) * b;
+          h[k + 1] = 0;
+          cd g0 = gvec[(size_t)i * (kmax + 1) + k];
+          gvec[(size_t)i * (kmax + 1) + k] = std::conj(cc) * g0;
+          gvec[(size_t)i * (kmax + 1) + k + 1] = -ss * g0;
+          if (active[i] && std::abs(gvec[(size_t)i * (kmax + 1) + k + 1]) > 0.5 * rtol * fn[i])
+            all_small = false;
+        }
+        for (int i = 0; i < mS; ++i)
+          if (active[i]) res.iters[i]++;
+        kdone = k + 1;
+        if (all_small) break;
+      }
+      // y = R^{-1} g per system; update u = V y; x += M^{-1} u
+      std::vector<cd> Y((size_t)mS * kdone, cd(0, 0));
+      for (int i = 0; i < mS; ++i) {
+        if (!active[i]) continue;
+        for (int j = kdone - 1; j >= 0; --j) {
+          cd acc = gvec[(size_t)i * (kmax + 1) + j];
+          for (int l = j + 1; l < kdone; ++l)
+            acc -= H[((size_t)i * kmax + l) * (kmax + 1) + j] * Y[(size_t)i * kdone + l];
+          cd hjj = H[((size_t)i * kmax + j) * (kmax + 1) + j];
+          Y[(size_t)i * kdone + j] = std::abs(hjj) > 0 ? acc / hjj : cd(0, 0);
+        }
+      }
+      HIPCHK(launch_fill_f64(st, (double *)w, 2 * vs, 0.0), "zero u");
+      std::vector<cpx<double>> yc(mS);
+      for (int j = 0; j < kdone; ++j) {
+        for (int i = 0; i < mS; ++i) {
+          cd v = Y[(size_t)i * kdone + j];
+          yc[i] = {v.real(), v.imag()};
+        }
+        HIPCHK(hipMemcpyAsync(c->v_coef.p, yc.data(), sizeof(cpx<double>) * mS,
+                              hipMemcpyHostToDevice, st),
+               "y");
+        HIPCHK(hipStreamSynchronize(st), "y sync");
+        HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, V + j * vs, w,
+                                   nullptr),
+               "u += V y");
+      }
+      TRY(precond(c, w, z, S));
+      ++solves;
+      std::vector<cpx<double>> one(mS, {1.0, 0.0});
+      HIPCHK(hipMemcpyAsync(c->v_mask.p, active.data(), sizeof(int) * mS, hipMemcpyHostToDevice, st),
+             "mask");
+      HIPCHK(hipMemcpyAsync(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS,
+                            hipMemcpyHostToDevice, st),
+             "coef");
+      HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
+                                 c->v_mask.as<int>()),
+             "x += z");
+      HIPCHK(hipStreamSynchronize(st), "x sync");
+      HIPCHK(launch_residual(st, N, m, S, c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+                             c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
+             "residual");
+    }
+  }
+  res.unconverged = 0;
+  for (int i = 0; i < mS; ++i)
+    if (res.rel[i] > rtol) res.unconverged++;
+  res.solves = solves;
+  return TEM_OK;
+}
+
+void fill_stats(const IrResult &res, tem_ir_stats *stats) {
+  if (!stats) return;
+  for (size_t i = 0; i < res.iters.size(); ++i) {
+    if (stats->iters) stats->iters[i] = res.iters[i];
+    if (stats->final_rel_res) stats->final_rel_res[i] = res.rel[i];
+  }
+  stats->n_unconverged = res.unconverged;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
+  if (!out) {
+    g_create_error = "tem_create: out is NULL";
+    return TEM_EINVAL;
+  }
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    g_create_error = std::string("tem_create: no HIP device: ") + hipGetErrorString(e);
+    return TEM_EDEVICE;
+  }
+  if (hip_device < 0 || hip_device >= ndev) {
+    g_create_error = "tem_create: device index out of range";
+    return TEM_EINVAL;
+  }
+  e = hipSetDevice(hip_device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("tem_create: hipSetDevice: ") + hipGetErrorString(e);
+    return TEM_EDEVICE;
+  }
+  std::unique_ptr<tem_ctx> c(new tem_ctx());
+  c->device = hip_device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    e = hipStreamCreate(&c->stream);
+    if (e != hipSuccess) {
+      g_create_error = std::string("tem_create: hipStreamCreate: ") + hipGetErrorString(e);
+      return TEM_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  e = c->d_flags.alloc(sizeof(int) * 4);
+  if (e != hipSuccess) {
+    g_create_error = "tem_create: flags allocation failed";
+    return TEM_ENOMEM;
+  }
+  *out = c.release();
+  return TEM_OK;
+}
+
+void tem_destroy(tem_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  hipStream_t st = c->stream;
+  bool own = c->own_stream;
+  delete c;
+  if (own) hipStreamDestroy(st);
+}
+
+const char *tem_last_error(const tem_ctx *c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+tem_status tem_assemble(tem_ctx *c, const tem_mesh *mesh, const double *sigma_cells,
+                        int32_t n_params, const int32_t *param_cells) {
+  if (!c) return TEM_EINVAL;
+  if (!mesh || !sigma_cells) return fail(c, TEM_EINVAL, "tem_assemble: NULL mesh or sigma");
+  if (mesh->nx < 2 || mesh->ny < 2 || mesh->nz < 2)
+    return fail(c, TEM_EINVAL, "tem_assemble: each axis needs at least 2 cells");
+  if (!(mesh->h > 0) || !(mesh->mu > 0) || !std::isfinite(mesh->h) || !std::isfinite(mesh->mu))
+    return fail(c, TEM_EINVAL, "tem_assemble: h and mu must be positive and finite");
+  const int64_t n_cells = (int64_t)mesh->nx * mesh->ny * mesh->nz;
+  if ((int64_t)3 * (mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1) > ((int64_t)1 << 31) - 1)
+    return fail(c, TEM_EINVAL, "tem_assemble: mesh too large for 32-bit edge ids");
+  if (n_params < 0 || (n_params > 0 && !param_cells))
+    return fail(c, TEM_EINVAL, "tem_assemble: bad parameter list");
+  std::vector<int32_t> prm(param_cells, param_cells + n_params);
+  {
+    std::vector<char> seen(n_cells, 0);
+    for (int32_t p : prm) {
+      if (p < 0 || p >= n_cells) return fail(c, TEM_EINVAL, "tem_assemble: parameter cell out of range");
+      if (seen[p]) return fail(c, TEM_EINVAL, "tem_assemble: duplicate parameter cell");
+      seen[p] = 1;
+    }
+  }
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  // validate sigma on the host copy
+  std::vector<double> sg(n_cells);
+  HIPCHK(hipMemcpy(sg.data(), sigma_cells, sizeof(double) * n_cells, hipMemcpyDeviceToHost),
+         "tem_assemble: sigma d2h");
+  for (double v : sg)
+    if (!(v > 0) || !std::isfinite(v))
+      return fail(c, TEM_EINVAL, "tem_assemble: sigma must be positive and finite");
+  const bool same_mesh = c->assembled && c->mesh.nx == mesh->nx && c->mesh.ny == mesh->ny &&
+                         c->mesh.nz == mesh->nz && c->mesh.h == mesh->h && c->mesh.mu == mesh->mu;
+  drop_factors(c);
+  if (!same_mesh) {
+    c->analysed = false;
+    c->assembled = false;
+    c->mesh = *mesh;
+    c->mt.init(mesh->nx, mesh->ny, mesh->nz);
+    element_mass_unit(mesh->h, c->Me);
+    element_stiffness(mesh->h, mesh->mu, c->Ke);
+    std::vector<double> ke(c->Ke, c->Ke + 144), me(c->Me, c->Me + 144);
+    HIPCHK(upload(c->d_Ke, ke, c->stream), "upload Ke");
+    HIPCHK(upload(c->d_Me, me, c->stream), "upload Me");
+    c->perm.resize(c->mt.n_unknowns);
+    for (int64_t q = 0; q < c->mt.n_unknowns; ++q) c->perm[q] = (int32_t)q;
+  }
+  HIPCHK(c->d_sigma.alloc(sizeof(double) * n_cells), "alloc sigma");
+  HIPCHK(hipMemcpyAsync(c->d_sigma.p, sigma_cells, sizeof(double) * n_cells,
+                        hipMemcpyDeviceToDevice, c->stream),
+         "copy sigma");
+  c->params = prm;
+  HIPCHK(upload(c->d_params, c->params, c->stream), "upload params");
+  if (!same_mesh) {
+    TRY(upload_pattern_and_assemble(c));
+  } else {
+    HIPCHK(launch_assemble_KM(c->stream, N_of(c), c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+                              c->d_row_edge.as<int32_t>(), c->d_edge_new.as<int32_t>(), c->mt.nx,
+                              c->mt.ny, c->mt.nz, c->d_Ke.as<double>(), c->d_Me.as<double>(),
+                              c->d_sigma.as<double>(), c->d_K.as<double>(), c->d_M.as<double>()),
+           "assemble kernel");
+  }
+  HIPCHK(hipStreamSynchronize(c->stream), "tem_assemble sync");
+  c->assembled = true;
+  return TEM_OK;
+}
+
+tem_status tem_set_model(tem_ctx *c, const double *m) {
+  if (!c) return TEM_EINVAL;
+  if (!c->assembled) return fail(c, TEM_ESTATE, "tem_set_model: call tem_assemble first");
+  if (!m) return fail(c, TEM_EINVAL, "tem_set_model: m is NULL");
+  if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_set_model: no model parameters");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  const int P = (int)c->params.size();
+  std::vector<double> mh(P);
+  HIPCHK(hipMemcpy(mh.data(), m, sizeof(double) * P, hipMemcpyDeviceToHost), "m d2h");
+  for (double v : mh)
+    if (!std::isfinite(v) || std::fabs(v) > 700.0)
+      return fail(c, TEM_EINVAL, "tem_set_model: m must be finite with |m| <= 700");
+  drop_factors(c);
+  HIPCHK(launch_set_sigma_exp(c->stream, P, c->d_params.as<int32_t>(), m, c->d_sigma.as<double>()),
+         "set sigma");
+  HIPCHK(launch_assemble_KM(c->stream, N_of(c), c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+                            c->d_row_edge.as<int32_t>(), c->d_edge_new.as<int32_t>(), c->mt.nx,
+                            c->mt.ny, c->mt.nz, c->d_Ke.as<double>(), c->d_Me.as<double>(),
+                            c->d_sigma.as<double>(), c->d_K.as<double>(), c->d_M.as<double>()),
+         "assemble kernel");
+  HIPCHK(hipStreamSynchronize(c->stream), "set_model sync");
+  return TEM_OK;
+}
+
+tem_status tem_export_operators(const tem_ctx *cc, int64_t *n_unknowns, int64_t *nnz,
+                                int32_t *perm, int64_t *rowptr, int32_t *col, double *kval,
+                                double *mval) {
+  tem_ctx *c = const_cast<tem_ctx *>(cc);
+  if (!c) return TEM_EINVAL;
+  if (!c->assembled) return fail(c, TEM_ESTATE, "tem_export_operators: nothing assembled");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  const int64_t N = N_of(c), nz = (int64_t)c->pat.col.size();
+  if (n_unknowns) *n_unknowns = N;
+  if (nnz) *nnz = nz;
+  if (perm) std::memcpy(perm, c->perm.data(), sizeof(int32_t) * N);
+  if (rowptr) std::memcpy(rowptr, c->pat.rowptr.data(), sizeof(int64_t) * (N + 1));
+  if (col) std::memcpy(col, c->pat.col.data(), sizeof(int32_t) * nz);
+  HIPCHK(hipStreamSynchronize(c->stream), "export sync");
+  if (kval) HIPCHK(hipMemcpy(kval, c->d_K.p, sizeof(double) * nz, hipMemcpyDeviceToHost), "K d2h");
+  if (mval) HIPCHK(hipMemcpy(mval, c->d_M.p, sizeof(double) * nz, hipMemcpyDeviceToHost), "M d2h");
+  return TEM_OK;
+}
+
+tem_status tem_analyse(tem_ctx *c, const tem_analyse_opts *opts, tem_symbolic_info *info) {
+  if (!c) return TEM_EINVAL;
+  if (!c->assembled) return fail(c, TEM_ESTATE, "tem_analyse: call tem_assemble first");
+  int leaf = (opts && opts->leaf_max_cells > 0) ? opts->leaf_max_cells : 4;
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  if (!c->analysed || leaf != c->leaf) {
+    drop_factors(c);
+    try {
+      analyse_symbolic(c->mt, leaf, c->sym);
+    } catch (const std::exception &ex) {
+      return fail(c, TEM_EINVAL, std::string("tem_analyse: ") + ex.what());
+    }
+    c->leaf = leaf;
+    c->perm = c->sym.perm;
+    TRY(upload_pattern_and_assemble(c));
+    TRY(build_front_maps(c));
+    c->analysed = true;
+  }
+  if (info) {
+    info->n_unknowns = c->mt.n_unknowns;
+    info->nnz_a = (int64_t)c->pat.col.size();
+    info->nnz_l = c->sym.nnz_l;
+    info->n_rows_total = (int64_t)c->sym.rows.size();
+    info->n_supernodes = (int32_t)c->sym.nodes.size();
+    info->n_levels = c->sym.n_levels;
+    info->max_front = c->sym.max_front;
+    info->reserved = 0;
+    info->flops_per_pole = c->sym.flops_per_pole;
+  }
+  return TEM_OK;
+}
+
+tem_status tem_symbolic_host(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_max_cells,
+                             tem_symbolic_info *info, int32_t *perm, int32_t *sn_ptr,
+                             int32_t *sn_parent, int64_t *rows_ptr, int32_t *rows) {
+  if (nx < 2 || ny < 2 || nz < 2) return TEM_EINVAL;
+  if ((int64_t)3 * (nx + 1) * (ny + 1) * (nz + 1) > ((int64_t)1 << 31) - 1) return TEM_EINVAL;
+  MeshTopo mt;
+  Symbolic sym;
+  try {
+    mt.init(nx, ny, nz);
+    analyse_symbolic(mt, leaf_max_cells > 0 ? leaf_max_cells : 4, sym);
+  } catch (...) {
+    return TEM_EINVAL;
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->n_unknowns = mt.n_unknowns;
+    info->nnz_l = sym.nnz_l;
+    info->n_rows_total = (int64_t)sym.rows.size();
+    info->n_supernodes = (int32_t)sym.nodes.size();
+    info->n_levels = sym.n_levels;
+    info->max_front = sym.max_front;
+    info->flops_per_pole = sym.flops_per_pole;
+    Pattern pat;
+    build_pattern(mt, sym.perm, pat);
+    info->nnz_a = (int64_t)pat.col.size();
+  }
+  const int ns = (int)sym.nodes.size();
+  if (perm) std::memcpy(perm, sym.perm.data(), sizeof(int32_t) * sym.perm.size());
+  if (sn_ptr) {
+    for (int s = 0; s < ns; ++s) sn_ptr[s] = (int32_t)sym.nodes[s].first;
+    sn_ptr[ns] = (int32_t)mt.n_unknowns;
+  }
+  if (sn_parent)
+    for (int s = 0; s < ns; ++s) sn_parent[s] = sym.nodes[s].parent;
+  if (rows_ptr) {
+    for (int s = 0; s < ns; ++s) rows_ptr[s] = sym.nodes[s].rows_off;
+    rows_ptr[ns] = (int64_t)sym.rows.size();
+  }
+  if (rows) std::memcpy(rows, sym.rows.data(), sizeof(int32_t) * sym.rows.size());
+  return TEM_OK;
+}
+
+tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precision prec,
+                            const tem_factor_opts *opts) {
+  if (!c) return TEM_EINVAL;
+  if (!c->analysed) return fail(c, TEM_ESTATE, "tem_factor_poles: call tem_analyse first");
+  if (m <= 0 || !xi) return fail(c, TEM_EINVAL, "tem_factor_poles: need m > 0 poles");
+  if (m > 65535) return fail(c, TEM_EINVAL, "tem_factor_poles: too many poles");
+  if (prec != TEM_FP64 && prec != TEM_FP32_IR)
+    return fail(c, TEM_EINVAL, "tem_factor_poles: unknown precision");
+  for (int i = 0; i < m; ++i) {
+    if (!std::isfinite(xi[2 * i]) || !std::isfinite(xi[2 * i + 1]) || !(xi[2 * i + 1] > 0))
+      return fail(c, TEM_EINVAL, "tem_factor_poles: poles need finite values and Im > 0");
+  }
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  drop_factors(c);
+  if (m != c->npole) c->surveyed = false;   // residues are per pole
+  c->w_x.release();
+  c->w_t.release();
+  c->v_basis.release();
+  c->npole = m;
+  c->prec = prec;
+  c->xi.assign(xi, xi + 2 * m);
+  HIPCHK(upload(c->d_xi, c->xi, c->stream), "upload xi");
+  const size_t esz = prec == TEM_FP64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
+  const size_t fbytes = esz * (size_t)c->pole_stride * m;
+  const size_t cb_pole = esz * (size_t)std::max<int64_t>(c->cb_stride, 1);
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+  int64_t budget = (opts && opts->mem_budget_bytes > 0) ? opts->mem_budget_bytes
+                                                         : (int64_t)(0.92 * (double)free_b);
+  if ((int64_t)fbytes + 2 * (int64_t)cb_pole > budget)
+    return fail(c, TEM_ENOMEM, "tem_factor_poles: factors do not fit in the memory budget");
+  int g = (int)std::min<int64_t>(m, (budget - (int64_t)fbytes) / (2 * (int64_t)cb_pole));
+  if (opts && opts->max_group > 0) g = std::min(g, (int)opts->max_group);
+  g = std::max(g, 1);
+  const int ngroups = (m + g - 1) / g;
+  g = (m + ngroups - 1) / ngroups;    // balance the groups
+  HIPCHK(c->d_factor.alloc(fbytes), "alloc factors");
+  HIPCHK(c->d_cb0.alloc(cb_pole * g), "alloc cb arena");
+  HIPCHK(c->d_cb1.alloc(cb_pole * g), "alloc cb arena");
+  HIPCHK(hipMemsetAsync(c->d_flags.p, 0, sizeof(int) * 4, c->stream), "clear flags");
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0), "event");
+  HIPCHK(hipEventCreate(&e1), "event");
+  HIPCHK(hipEventRecord(e0, c->stream), "event");
+  for (int p0 = 0; p0 < m; p0 += g) {
+    int gg = std::min(g, m - p0);
+    tem_status s = prec == TEM_FP64 ? factor_group<double>(c, p0, gg) : factor_group<float>(c, p0, gg);
+    if (s != TEM_OK) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return s;
+    }
+  }
+  HIPCHK(hipEventRecord(e1, c->stream), "event");
+  HIPCHK(hipEventSynchronize(e1), "factor sync");
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->factor_ms = ms;
+  int flags[4];
+  HIPCHK(hipMemcpy(flags, c->d_flags.p, sizeof(flags), hipMemcpyDeviceToHost), "flags d2h");
+  c->n_tiny = flags[1];
+  c->n_groups = ngroups;
+  c->group_size = g;
+  c->d_cb0.release();
+  c->d_cb1.release();
+  if (flags[0]) {
+    c->d_factor.release();
+    return fail(c, TEM_EPIVOT, "tem_factor_poles: zero or non-finite pivot");
+  }
+  c->factored = true;
+  return TEM_OK;
+}
+
+tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
+                           const tem_ir_opts *ir, tem_ir_stats *stats) {
+  if (!c) return TEM_EINVAL;
+  if (!c->factored) return fail(c, TEM_ESTATE, "tem_solve_poles: call tem_factor_poles first");
+  if (nrhs <= 0 || nrhs > 16 || !F)
+    return fail(c, TEM_EINVAL, "tem_solve_poles: need 1 <= nrhs <= 16 and a source array");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  const int64_t N = N_of(c);
+  const int S = nrhs;
+  hipStream_t st = c->stream;
+  c->solved = false;
+  TRY(ensure_vec(c, c->d_fnew, sizeof(double) * (size_t)N * S, "alloc f"));
+  HIPCHK(launch_gather_rhs(st, N, S, c->mt.n_edges, c->d_row_edge.as<int32_t>(), F,
+                           c->d_fnew.as<double>()),
+         "gather f");
+  TRY(ensure_vec(c, c->d_g, sizeof(cpx<double>) * (size_t)c->npole * N * S, "alloc g"));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0), "event");
+  HIPCHK(hipEventCreate(&e1), "event");
+  HIPCHK(hipEventRecord(e0, st), "event");
+  IrResult res;
+  tem_status s = refine_solve(c, c->d_fnew.as<double>(), nullptr, S, c->d_g.as<cpx<double>>(), ir, res);
+  hipEventRecord(e1, st);
+  hipEventSynchronize(e1);
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (s != TEM_OK) return s;
+  c->solve_ms = ms;
+  c->last_solves = res.solves;
+  c->S = S;
+  if (G) {
+    HIPCHK(launch_scatter_solution(st, N, c->npole, S, c->mt.n_edges, c->d_edge_new.as<int32_t>(),
+                                   c->d_g.as<cpx<double>>(), (cpx<double> *)G),
+           "scatter g");
+  }
+  HIPCHK(hipStreamSynchronize(st), "solve sync");
+  fill_stats(res, stats);
+  c->solved = true;
+  if (res.unconverged) {
+    double worst = 0;
+    for (double v : res.rel) worst = std::max(worst, v);
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "tem_solve_poles: %d systems above rtol (worst %.3e) after %d solves",
+                  res.unconverged, worst, res.solves);
+    return fail(c, TEM_ENOCONV, buf);
+  }
+  return TEM_OK;
+}
+
+static tem_status set_survey(tem_ctx *c, int R, const int64_t *q_ptr, const int32_t *q_col,
+                             const double *q_val, int K, const double *alpha) {
+  if (R <= 0 || K <= 0 || !q_ptr || !q_col || !q_val || !alpha)
+    return fail(c, TEM_EINVAL, "tem_forward: bad receivers or residues");
+  if (q_ptr[0] != 0) return fail(c, TEM_EINVAL, "tem_forward: q_ptr[0] must be 0");
+  const int64_t nnz = q_ptr[R];
+  std::vector<int64_t> qp(R + 1, 0);
+  std::vector<int32_t> qc;
+  std::vector<double> qv;
+  for (int r = 0; r < R; ++r) {
+    if (q_ptr[r + 1] < q_ptr[r] || q_ptr[r + 1] > nnz)
+      return fail(c, TEM_EINVAL, "tem_forward: q_ptr not monotone");
+    for (int64_t t = q_ptr[r]; t < q_ptr[r + 1]; ++t) {
+      if (q_col[t] < 0 || q_col[t] >= c->mt.n_edges)
+        return fail(c, TEM_EINVAL, "tem_forward: receiver column out of range");
+      if (!std::isfinite(q_val[t])) return fail(c, TEM_EINVAL, "tem_forward: non-finite Q value");
+      int32_t q = c->pat.edge_new[q_col[t]];
+      if (q < 0) continue;   // boundary edge: the field is zero there
+      qc.push_back(q);
+      qv.push_back(q_val[t]);
+    }
+    qp[r + 1] = (int64_t)qc.size();
+  }
+  for (int i = 0; i < 2 * K * c->npole; ++i)
+    if (!std::isfinite(alpha[i])) return fail(c, TEM_EINVAL, "tem_forward: non-finite residue");
+  std::vector<double> al(alpha, alpha + 2 * (size_t)K * c->npole);
+  HIPCHK(upload(c->d_qptr, qp, c->stream), "upload q_ptr");
+  HIPCHK(upload(c->d_qcol, qc, c->stream), "upload q_col");
+  HIPCHK(upload(c->d_qval, qv, c->stream), "upload q_val");
+  HIPCHK(upload(c->d_alpha, al, c->stream), "upload alpha");
+  c->R = R;
+  c->K = K;
+  return TEM_OK;
+}
+
+tem_status tem_forward(tem_ctx *c, int32_t S, const double *F, int32_t R, const int64_t *q_ptr,
+                       const int32_t *q_col, const double *q_val, int32_t K, const double *alpha,
+                       const tem_ir_opts *ir, double *d, tem_ir_stats *stats) {
+  if (!c) return TEM_EINVAL;
+  if (!c->factored) return fail(c, TEM_ESTATE, "tem_forward: call tem_factor_poles first");
+  if (!d) return fail(c, TEM_EINVAL, "tem_forward: d is NULL");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  TRY(set_survey(c, R, q_ptr, q_col, q_val, K, alpha));
+  tem_status s = tem_solve_poles(c, S, F, nullptr, ir, stats);
+  if (s != TEM_OK && s != TEM_ENOCONV) return s;
+  HIPCHK(launch_time_assembly(c->stream, S, K, R, c->npole, N_of(c), c->d_qptr.as<int64_t>(),
+                              c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
+                              c->d_alpha.as<cpx<double>>(), c->d_g.as<cpx<double>>(), d),
+         "time assembly");
+  HIPCHK(hipStreamSynchronize(c->stream), "forward sync");
+  c->surveyed = true;
+  return s;
+}
+
+tem_status tem_jvp(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *ir,
+                   tem_ir_stats *stats) {
+  if (!c) return TEM_EINVAL;
+  if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_jvp: call tem_forward first");
+  if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_jvp: no model parameters");
+  if (!v || !jv) return fail(c, TEM_EINVAL, "tem_jvp: NULL argument");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c);
+  const int S = c->S, m = c->npole;
+  TRY(ensure_vec(c, c->v_vs, sizeof(double) * (size_t)c->mt.n_cells, "alloc vs"));
+  TRY(ensure_vec(c, c->v_rhs, sizeof(cpx<double>) * (size_t)m * N * S, "alloc rhs"));
+  TRY(ensure_vec(c, c->v_lam, sizeof(cpx<double>) * (size_t)m * N * S, "alloc sol"));
+  HIPCHK(launch_param_scatter(st, (int)c->params.size(), c->d_params.as<int32_t>(), v,
+                              c->d_sigma.as<double>(), c->mt.n_cells, c->v_vs.as<double>()),
+         "param scatter");
+  HIPCHK(launch_jv_rhs(st, N, m, S, c->mt.nx, c->mt.ny, c->mt.nz, c->d_row_edge.as<int32_t>(),
+                       c->d_cell_new.as<int32_t>(), c->v_vs.as<double>(), c->d_Me.as<double>(),
+                       c->d_xi.as<double>(), c->d_g.as<cpx<double>>(), c->v_rhs.as<cpx<double>>()),
+         "jv rhs");
+  IrResult res;
+  TRY(refine_solve(c, nullptr, c->v_rhs.as<cpx<double>>(), S, c->v_lam.as<cpx<double>>(), ir, res));
+  HIPCHK(launch_time_assembly(st, S, c->K, c->R, m, N, c->d_qptr.as<int64_t>(),
+                              c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
+                              c->d_alpha.as<cpx<double>>(), c->v_lam.as<cpx<double>>(), jv),
+         "jv time assembly");
+  HIPCHK(hipStreamSynchronize(st), "jvp sync");
+  fill_stats(res, stats);
+  c->last_solves = res.solves;
+  if (res.unconverged) return fail(c, TEM_ENOCONV, "tem_jvp: refinement did not converge");
+  return TEM_OK;
+}
+
+tem_status tem_vjp(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *ir,
+                   tem_ir_stats *stats) {
+  if (!c) return TEM_EINVAL;
+  if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_vjp: call tem_forward first");
+  if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_vjp: no model parameters");
+  if (!w || !jtw) return fail(c, TEM_EINVAL, "tem_vjp: NULL argument");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c);
+  const int S = c->S, m = c->npole;
+  TRY(ensure_vec(c, c->v_rhs, sizeof(cpx<double>) * (size_t)m * N * S, "alloc rhs"));
+  TRY(ensure_vec(c, c->v_lam, sizeof(cpx<double>) * (size_t)m * N * S, "alloc sol"));
+  HIPCHK(launch_jtw_rhs(st, S, c->K, c->R, m, N, c->d_qptr.as<int64_t>(), c->d_qcol.as<int32_t>(),
+                        c->d_qval.as<double>(), c->d_alpha.as<cpx<double>>(), w,
+                        c->v_rhs.as<cpx<double>>()),
+         "jtw rhs");
+  IrResult res;
+  TRY(refine_solve(c, nullptr, c->v_rhs.as<cpx<double>>(), S, c->v_lam.as<cpx<double>>(), ir, res));
+  HIPCHK(launch_jtw_reduce(st, (int)c->params.size(), m, S, N, c->d_params.as<int32_t>(),
+                           c->d_cell_new.as<int32_t>(), c->d_sigma.as<double>(),
+                           c->d_Me.as<double>(), c->d_xi.as<double>(), c->d_g.as<cpx<double>>(),
+                           c->v_lam.as<cpx<double>>(), jtw),
+         "jtw reduce");
+  HIPCHK(hipStreamSynchronize(st), "vjp sync");
+  fill_stats(res, stats);
+  c->last_solves = res.solves;
+  if (res.unconverged) return fail(c, TEM_ENOCONV, "tem_vjp: refinement did not converge");
+  return TEM_OK;
+}
+
+tem_status tem_get_stats(const tem_ctx *c, tem_stats *out) {
+  if (!c || !out) return TEM_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->n_poles = c->npole;
+  out->n_groups = c->n_groups;
+  out->group_size = c->group_size;
+  out->precision = (int32_t)c->prec;
+  out->factor_bytes = (int64_t)c->d_factor.bytes;
+  out->workspace_bytes = (int64_t)(c->w_x.bytes + c->w_t.bytes + c->w_w0.bytes + c->w_w1.bytes +
+                                   c->v_r.bytes + c->v_z.bytes + c->v_w.bytes + c->v_basis.bytes +
+                                   c->v_rhs.bytes + c->v_lam.bytes);
+  out->n_tiny_pivots = c->n_tiny;
+  out->last_solves = c->last_solves;
+  out->factor_ms = c->factor_ms;
+  out->solve_ms = c->solve_ms;
+  return TEM_OK;
+}
+
+}  // extern "C"

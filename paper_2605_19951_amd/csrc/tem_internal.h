@@ -1,0 +1,208 @@
+// Internal declarations shared by the HIP kernels and the host orchestration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tem {
+
+constexpr int NB = 32;          // panel (column block) width of the factors
+
+// Complex value stored as interleaved (re, im).
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T re, im;
+};
+
+// -------------------------------------------------------------------------
+// Front panel layout ("column-block trapezoid").  A front of n = k + u rows
+// keeps its k eliminated columns in blocks of NB columns; block b holds
+// columns [NB b, NB b + w_b) for rows [NB b, n) column-major with leading
+// dimension n - NB b.  Element (r, c), r >= NB*(c/NB), lives at
+// panel_elem(n, r, c).  Within each NB x NB diagonal block the strictly
+// lower part holds L, the diagonal holds D, and the strictly upper part
+// holds the transpose of the inverse of the unit-lower diagonal block.
+// -------------------------------------------------------------------------
+__host__ __device__ inline int64_t panel_block_off(int64_t n, int64_t b) {
+  // sum over b' < b of NB * (n - NB b')
+  return (int64_t)NB * (b * n - (int64_t)NB * (b * (b - 1) / 2));
+}
+__host__ __device__ inline int64_t panel_elem(int64_t n, int64_t r, int64_t c) {
+  int64_t b = c / NB;
+  int64_t r0 = NB * b;
+  return panel_block_off(n, b) + (c - r0) * (n - r0) + (r - r0);
+}
+__host__ __device__ inline int64_t panel_size(int64_t n, int64_t k) {
+  int64_t nb = (k + NB - 1) / NB;
+  if (nb == 0) return 0;
+  int64_t last_w = k - NB * (nb - 1);
+  return panel_block_off(n, nb - 1) + last_w * (n - NB * (nb - 1));
+}
+
+// Device view of the supernodal structure (pole independent).
+struct FrontTab {
+  const int64_t *first;     // first column (new index)
+  const int32_t *k;         // number of columns
+  const int32_t *u;         // |U_s|
+  const int64_t *rows_off;  // offset of U_s in rows / rel
+  const int32_t *rows;      // U_s as new indices
+  const int32_t *rel;       // position of each U_s row in the parent's front
+  const int64_t *panel_off; // element offset of the panel in one pole's factor
+  const int64_t *cb_off;    // element offset of the CB in one pole's level arena
+  const int64_t *w_off;     // row offset of the solve update vector in one pole's level arena
+  const int64_t *gmap_off;  // offset of the front's child gather maps
+  const int32_t *gmap0;     // front position -> row of child 0's update (or -1)
+  const int32_t *gmap1;     // front position -> row of child 1's update (or -1)
+  const int32_t *child0;
+  const int32_t *child1;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return hipGetLastError().
+// T is float (FP32 factors) or double (FP64 factors).
+
+hipError_t launch_assemble_KM(hipStream_t st, int64_t N, const int64_t *rowptr, const int32_t *col,
+                              const int32_t *row_edge, const int32_t *edge_new, int nx, int ny,
+                              int nz, const double *Ke, const double *Me, const double *sigma,
+                              double *Kv, double *Mv);
+
+template <typename T>
+hipError_t launch_fill_zero(hipStream_t st, cpx<T> *base, int64_t count, int npole,
+                            int64_t pole_stride);
+
+template <typename T>
+hipError_t launch_front_assemble(hipStream_t st, int64_t n_entries, const int32_t *csr,
+                                 const int64_t *pos, const double *Kv, const double *Mv,
+                                 const double *xi, int npole, cpx<T> *factor,
+                                 int64_t pole_stride);
+
+template <typename T>
+hipError_t launch_extend_add(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                             int slot, int max_u_child, int npole, cpx<T> *factor,
+                             int64_t f_stride, cpx<T> *cb_parent, cpx<T> *cb_child,
+                             int64_t cb_stride);
+
+template <typename T>
+hipError_t launch_panel_diag(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                             int j0, int npole, cpx<T> *factor, int64_t f_stride, int *flags);
+
+template <typename T>
+hipError_t launch_panel_trsm(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                             int j0, int max_rows, int npole, cpx<T> *factor, int64_t f_stride);
+
+// mode 0: trailing update of panel columns after column block j0/NB;
+// mode 1: contribution block C -= L21 D L21^T.
+template <typename T>
+hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                               int mode, int j0, int64_t max_tiles, int npole, cpx<T> *factor,
+                               int64_t f_stride, cpx<T> *cb, int64_t cb_stride);
+
+// ------------------------------------------------------------------ solves
+// Vectors are [pole][N][S] complex T (S fastest), S <= 16.
+template <typename T>
+hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                          int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
+                          cpx<T> *x, const cpx<T> *w_child, int64_t w_stride);
+
+template <typename T>
+hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_u, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, const cpx<T> *x, const cpx<T> *w_child,
+                           cpx<T> *w_out, int64_t w_stride);
+
+template <typename T>
+hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_k, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, const cpx<T> *x, cpx<T> *t, int64_t t_stride);
+
+template <typename T>
+hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                          int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
+                          cpx<T> *x, const cpx<T> *t, int64_t t_stride);
+
+// ------------------------------------------------------- vector kernels
+// Residual r = f - (K - xi_p M) x for all poles p and rhs s (FP64);
+// x, r: [pole][N][S] complex double; f: [N][S] real (new ordering) or, with
+// f_cplx, [pole][N][S] complex.
+hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
+                           const int32_t *col, const double *Kv, const double *Mv,
+                           const double *xi, const double *f_real, const cpx<double> *f_cplx,
+                           const cpx<double> *x, cpx<double> *r);
+
+// y = (K - xi_p M) x  (FP64), same layout as residual.
+hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
+                               const int32_t *col, const double *Kv, const double *Mv,
+                               const double *xi, const cpx<double> *x, cpx<double> *y);
+
+// Batched complex dot products over the N dimension for all (pole, s):
+// out[p*S+s] = sum_row conj(a) * b (conj_a) or sum a*b.  Deterministic.
+hipError_t launch_batched_dot(hipStream_t st, int64_t N, int npole, int S, const cpx<double> *a,
+                              const cpx<double> *b, bool conj_a, cpx<double> *partial,
+                              int n_partial_blocks, cpx<double> *out);
+
+// y[p][i][s] += alpha[p*S+s] * x[p][i][s]  (complex alpha per system); mask
+// (int per system, may be null) skips systems with mask == 0.
+// sign multiplies alpha (use -1 for y -= alpha x)
+hipError_t launch_batched_axpy(hipStream_t st, int64_t N, int npole, int S,
+                               const cpx<double> *alpha, double sign, const cpx<double> *x,
+                               cpx<double> *y, const int *mask);
+// inv[i] = 1/sqrt(Re dots[i]) (1 when zero), nrm[i] = sqrt(Re dots[i])
+hipError_t launch_norm_scales(hipStream_t st, int n, const cpx<double> *dots, double *inv,
+                              double *nrm);
+hipError_t launch_fill_f64(hipStream_t st, double *p, int64_t n, double v);
+// x[p][i][s] *= scale[p*S+s] (real)
+hipError_t launch_batched_scale(hipStream_t st, int64_t N, int npole, int S, const double *scale,
+                                cpx<double> *x);
+
+// conversions between the FP64 refinement vectors and the factor precision,
+// with a per-system scale: out = in * scale[p*S+s].
+template <typename T>
+hipError_t launch_convert_in(hipStream_t st, int64_t n_per_pole, int npole, int S,
+                             const cpx<double> *in, const double *scale, cpx<T> *out);
+template <typename T>
+hipError_t launch_convert_out(hipStream_t st, int64_t n_per_pole, int npole, int S,
+                              const cpx<T> *in, const double *scale, cpx<double> *out);
+
+// canonical edge-major real array [n_edges][*] column-major (n_edges x S)
+// -> new-ordering [pole][N][S] complex (imag 0), replicated over poles.
+hipError_t launch_gather_rhs(hipStream_t st, int64_t N, int S, int64_t n_edges,
+                             const int32_t *row_edge, const double *F, double *f_new);
+
+// g [pole][N][S] complex (new order) -> G [pole][S][n_edges] complex (canonical).
+hipError_t launch_scatter_solution(hipStream_t st, int64_t N, int npole, int S, int64_t n_edges,
+                                   const int32_t *edge_new, const cpx<double> *g,
+                                   cpx<double> *G);
+
+// Observation + residue time assembly:
+// d[s][j][r] = 2 Re sum_i alpha[j][i] sum_q Qval * g[i][Qcol][s]
+hipError_t launch_time_assembly(hipStream_t st, int S, int K, int R, int npole, int64_t N,
+                                const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
+                                const cpx<double> *alpha, const cpx<double> *g, double *d);
+
+// Jv right-hand sides: rhs[p][e][s] = xi_p sum_{cells c of e} vs[c] (Me1 g_p|_c)[local]
+// with vs[c] = v_param * sigma_c (0 for non-parameter cells).
+hipError_t launch_jv_rhs(hipStream_t st, int64_t N, int npole, int S, int nx, int ny, int nz,
+                         const int32_t *row_edge, const int32_t *cell_new, const double *vs,
+                         const double *Me, const double *xi, const cpx<double> *g,
+                         cpx<double> *rhs);
+
+// sigma[params[p]] = exp(m[p])
+hipError_t launch_set_sigma_exp(hipStream_t st, int P, const int32_t *params, const double *m,
+                                double *sigma);
+
+hipError_t launch_param_scatter(hipStream_t st, int P, const int32_t *params, const double *v,
+                                const double *sigma, int64_t n_cells, double *vs);
+
+// J^T w right-hand sides: rhs[p][e][s] = sum_r Q[r][e] sum_j alpha[j][p] w[s][j][r]
+hipError_t launch_jtw_rhs(hipStream_t st, int S, int K, int R, int npole, int64_t N,
+                          const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
+                          const cpx<double> *alpha, const double *w, cpx<double> *rhs);
+
+// (J^T w)_p = 2 Re sum_{i,s} xi_i sigma_c g_is|_c^T Me1 lam_is|_c, c = params[p]
+hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int64_t N,
+                             const int32_t *params, const int32_t *cell_new, const double *sigma,
+                             const double *Me, const double *xi, const cpx<double> *g,
+                             const cpx<double> *lam, double *out);
+
+}  // namespace tem
