@@ -253,9 +253,25 @@ typedef struct {
   int32_t last_solves;         /* refinement solves of the last solve call (max) */
   double factor_ms;            /* device time of the last factorisation */
   double solve_ms;             /* device time of the last solve call */
+  /* filled while profiling is enabled (tem_set_profiling), accumulated
+     since it was enabled: HIP-event time and algorithmic work of the MFMA
+     front-update launches (flops of C -= L D L^T on the lower triangle) and
+     of the triangular sweeps (bytes: factors read twice, vectors read and
+     written in both passes) */
+  double update_ms;
+  double update_flops;
+  int64_t update_launches;
+  double sweep_ms;
+  double sweep_bytes;
+  int64_t sweeps;
 } tem_stats;
 
 tem_status tem_get_stats(const tem_ctx *ctx, tem_stats *out);
+
+/* Enable (1) or disable (0) per-launch HIP-event timing of the front
+ * updates and the sweeps, and reset the accumulated figures of tem_stats.
+ * For measurement only; adds two events per timed launch. */
+tem_status tem_set_profiling(tem_ctx *ctx, int32_t enable);
 
 #ifdef __cplusplus
 }

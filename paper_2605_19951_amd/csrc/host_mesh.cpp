@@ -39,6 +39,18 @@ void MeshTopo::init(int nx_, int ny_, int nz_) {
     }
   }
   n_unknowns = u;
+  n_nodes = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  unk_of_node.assign(n_nodes, -1);
+  node_of_unk.clear();
+  int32_t v = 0;
+  for (int k = 0; k <= nz; ++k)
+    for (int j = 0; j <= ny; ++j)
+      for (int i = 0; i <= nx; ++i)
+        if (i > 0 && i < nx && j > 0 && j < ny && k > 0 && k < nz) {
+          unk_of_node[node(i, j, k)] = v++;
+          node_of_unk.push_back((int32_t)node(i, j, k));
+        }
+  n_inodes = v;
 }
 
 void MeshTopo::geometry(int64_t e, int &dir, int &i, int &j, int &k) const {
@@ -129,6 +141,37 @@ void element_stiffness(double h, double mu, double out[144]) {
     }
 }
 
+void element_gradient(int out[96]) {
+  // edge (start node -> end node along +axis); local nodes (dx,dy,dz) -> dx + 2 dy + 4 dz
+  std::memset(out, 0, sizeof(int) * 96);
+  for (int p = 0; p < 4; ++p) {
+    int a = kAB[p][0], b = kAB[p][1];
+    // x-edge (dy=a, dz=b): (0,a,b) -> (1,a,b)
+    out[p * 8 + (0 + 2 * a + 4 * b)] = -1;
+    out[p * 8 + (1 + 2 * a + 4 * b)] = +1;
+    // y-edge (dx=a, dz=b): (a,0,b) -> (a,1,b)
+    out[(4 + p) * 8 + (a + 0 + 4 * b)] = -1;
+    out[(4 + p) * 8 + (a + 2 + 4 * b)] = +1;
+    // z-edge (dx=a, dy=b): (a,b,0) -> (a,b,1)
+    out[(8 + p) * 8 + (a + 2 * b + 0)] = -1;
+    out[(8 + p) * 8 + (a + 2 * b + 4)] = +1;
+  }
+}
+
+void element_grad_mass(double h, double out[64]) {
+  double M1[144];
+  int G[96];
+  element_mass_unit(h, M1);
+  element_gradient(G);
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) {
+      double s = 0.0;
+      for (int e = 0; e < 12; ++e)
+        for (int f = 0; f < 12; ++f) s += G[e * 8 + a] * M1[e * 12 + f] * G[f * 8 + b];
+      out[a * 8 + b] = s;
+    }
+}
+
 // ------------------------------------------------------ nested dissection
 namespace {
 
@@ -136,13 +179,20 @@ struct NDBuilder {
   const MeshTopo &mt;
   int leaf_max;
   Symbolic &sym;
+  bool nodes;
   std::vector<int64_t> scratch;
 
-  NDBuilder(const MeshTopo &m, int lm, Symbolic &s) : mt(m), leaf_max(lm), sym(s) {}
+  NDBuilder(const MeshTopo &m, int lm, Symbolic &s, bool nd) : mt(m), leaf_max(lm), sym(s), nodes(nd) {}
 
-  // edges in the closed box, not on its surface
+  // edges (nodes) in the closed box, not on its surface
   void interior(const int b[3][2], std::vector<int64_t> &out) {
     int x0 = b[0][0], x1 = b[0][1], y0 = b[1][0], y1 = b[1][1], z0 = b[2][0], z1 = b[2][1];
+    if (nodes) {
+      for (int k = z0 + 1; k < z1; ++k)
+        for (int j = y0 + 1; j < y1; ++j)
+          for (int i = x0 + 1; i < x1; ++i) out.push_back(mt.node(i, j, k));
+      return;
+    }
     for (int k = z0 + 1; k < z1; ++k)
       for (int j = y0 + 1; j < y1; ++j)
         for (int i = x0; i < x1; ++i) out.push_back(mt.xedge(i, j, k));
@@ -154,9 +204,22 @@ struct NDBuilder {
         for (int i = x0 + 1; i < x1; ++i) out.push_back(mt.zedge(i, j, k));
   }
 
-  // edges in the plane {axis = p} inside the closed box, not on its surface
+  // edges (nodes) in the plane {axis = p} inside the closed box, not on its surface
   void plane(const int b[3][2], int axis, int p, std::vector<int64_t> &out) {
     int x0 = b[0][0], x1 = b[0][1], y0 = b[1][0], y1 = b[1][1], z0 = b[2][0], z1 = b[2][1];
+    if (nodes) {
+      if (axis == 0) {
+        for (int k = z0 + 1; k < z1; ++k)
+          for (int j = y0 + 1; j < y1; ++j) out.push_back(mt.node(p, j, k));
+      } else if (axis == 1) {
+        for (int k = z0 + 1; k < z1; ++k)
+          for (int i = x0 + 1; i < x1; ++i) out.push_back(mt.node(i, p, k));
+      } else {
+        for (int j = y0 + 1; j < y1; ++j)
+          for (int i = x0 + 1; i < x1; ++i) out.push_back(mt.node(i, j, p));
+      }
+      return;
+    }
     if (axis == 0) {
       for (int k = z0 + 1; k < z1; ++k)
         for (int j = y0; j < y1; ++j) out.push_back(mt.yedge(p, j, k));
@@ -179,8 +242,8 @@ struct NDBuilder {
     std::sort(edges.begin(), edges.end());
     nd.first = (int64_t)sym.perm.size();
     for (int64_t e : edges) {
-      int32_t u = mt.unk_of_edge[e];
-      if (u < 0) throw std::runtime_error("nested dissection produced a boundary edge");
+      int32_t u = nodes ? mt.unk_of_node[e] : mt.unk_of_edge[e];
+      if (u < 0) throw std::runtime_error("nested dissection produced a boundary entity");
       sym.perm.push_back(u);
     }
     nd.last = (int64_t)sym.perm.size();
@@ -251,39 +314,77 @@ int edge_cells(const MeshTopo &mt, int64_t e, int cells[4][3], int local[4]) {
   return n;
 }
 
+// cells that contain canonical node v
+int node_cells(const MeshTopo &mt, int64_t v, int cells[8][3]) {
+  int i = (int)(v % (mt.nx + 1));
+  int64_t r = v / (mt.nx + 1);
+  int j = (int)(r % (mt.ny + 1)), k = (int)(r / (mt.ny + 1));
+  int n = 0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        int ci = i - dx, cj = j - dy, ck = k - dz;
+        if (ci < 0 || cj < 0 || ck < 0 || ci >= mt.nx || cj >= mt.ny || ck >= mt.nz) continue;
+        cells[n][0] = ci;
+        cells[n][1] = cj;
+        cells[n][2] = ck;
+        ++n;
+      }
+  return n;
+}
+
+// unknown indices of the entities sharing a cell with canonical entity x
+void neighbours(const MeshTopo &mt, bool nodes, int64_t x, std::vector<int32_t> &out) {
+  out.clear();
+  if (nodes) {
+    int cells[8][3];
+    int nc = node_cells(mt, x, cells);
+    for (int c = 0; c < nc; ++c)
+      for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            int32_t u = mt.unk_of_node[mt.node(cells[c][0] + dx, cells[c][1] + dy, cells[c][2] + dz)];
+            if (u >= 0) out.push_back(u);
+          }
+    return;
+  }
+  int cells[4][3], local[4];
+  int64_t ce[12];
+  int nc = edge_cells(mt, x, cells, local);
+  for (int c = 0; c < nc; ++c) {
+    mt.cell_edges(cells[c][0], cells[c][1], cells[c][2], ce);
+    for (int b = 0; b < 12; ++b) {
+      int32_t u = mt.unk_of_edge[ce[b]];
+      if (u >= 0) out.push_back(u);
+    }
+  }
+}
+
 }  // namespace
 
-void analyse_symbolic(const MeshTopo &mt, int leaf_max, Symbolic &sym) {
+void analyse_symbolic(const MeshTopo &mt, int leaf_max, Symbolic &sym, bool nodes) {
   sym = Symbolic();
   sym.leaf_max = leaf_max;
-  sym.perm.reserve(mt.n_unknowns);
-  NDBuilder nb(mt, leaf_max, sym);
+  const int64_t N = nodes ? mt.n_inodes : mt.n_unknowns;
+  sym.perm.reserve(N);
+  NDBuilder nb(mt, leaf_max, sym, nodes);
   int root[3][2] = {{0, mt.nx}, {0, mt.ny}, {0, mt.nz}};
   nb.rec(root, 0);
-  const int64_t N = mt.n_unknowns;
   if ((int64_t)sym.perm.size() != N) throw std::runtime_error("ordering does not cover all unknowns");
   sym.iperm.assign(N, -1);
   for (int64_t q = 0; q < N; ++q) sym.iperm[sym.perm[q]] = (int32_t)q;
   // U_s = (adj(cols(s)) U children's U) \ [sub_first, last)
-  std::vector<int32_t> cand;
-  std::vector<int64_t> starts;
+  std::vector<int32_t> cand, nb_;
   sym.rows.clear();
-  int cells[4][3], local[4];
-  int64_t ce[12];
   for (size_t s = 0; s < sym.nodes.size(); ++s) {
     SymNode &nd = sym.nodes[s];
     cand.clear();
     for (int64_t q = nd.first; q < nd.last; ++q) {
-      int64_t e = mt.edge_of_unk[sym.perm[q]];
-      int nc = edge_cells(mt, e, cells, local);
-      for (int c = 0; c < nc; ++c) {
-        mt.cell_edges(cells[c][0], cells[c][1], cells[c][2], ce);
-        for (int b = 0; b < 12; ++b) {
-          int32_t u = mt.unk_of_edge[ce[b]];
-          if (u < 0) continue;
-          int32_t r = sym.iperm[u];
-          if (r < nd.sub_first || r >= nd.last) cand.push_back(r);
-        }
+      int64_t x = nodes ? mt.node_of_unk[sym.perm[q]] : mt.edge_of_unk[sym.perm[q]];
+      neighbours(mt, nodes, x, nb_);
+      for (int32_t u : nb_) {
+        int32_t r = sym.iperm[u];
+        if (r < nd.sub_first || r >= nd.last) cand.push_back(r);
       }
     }
     for (int c = 0; c < 2; ++c) {
@@ -313,33 +414,26 @@ void analyse_symbolic(const MeshTopo &mt, int leaf_max, Symbolic &sym) {
   }
 }
 
-void build_pattern(const MeshTopo &mt, const std::vector<int32_t> &perm, Pattern &pat) {
-  const int64_t N = mt.n_unknowns;
+void build_pattern(const MeshTopo &mt, const std::vector<int32_t> &perm, Pattern &pat,
+                   bool nodes) {
+  const int64_t N = nodes ? mt.n_inodes : mt.n_unknowns;
   std::vector<int32_t> iperm(N);
   for (int64_t q = 0; q < N; ++q) iperm[perm[q]] = (int32_t)q;
   pat.row_edge.resize(N);
-  pat.edge_new.assign(mt.n_edges, -1);
+  pat.edge_new.assign(nodes ? mt.n_nodes : mt.n_edges, -1);
   for (int64_t q = 0; q < N; ++q) {
-    int32_t e = mt.edge_of_unk[perm[q]];
+    int32_t e = nodes ? mt.node_of_unk[perm[q]] : mt.edge_of_unk[perm[q]];
     pat.row_edge[q] = e;
     pat.edge_new[e] = (int32_t)q;
   }
   pat.rowptr.assign(N + 1, 0);
   pat.col.clear();
-  pat.col.reserve(N * 33);
-  std::vector<int32_t> buf;
-  int cells[4][3], local[4];
-  int64_t ce[12];
+  pat.col.reserve(N * (nodes ? 27 : 33));
+  std::vector<int32_t> buf, nb_;
   for (int64_t q = 0; q < N; ++q) {
     buf.clear();
-    int nc = edge_cells(mt, pat.row_edge[q], cells, local);
-    for (int c = 0; c < nc; ++c) {
-      mt.cell_edges(cells[c][0], cells[c][1], cells[c][2], ce);
-      for (int b = 0; b < 12; ++b) {
-        int32_t r = pat.edge_new[ce[b]];
-        if (r >= 0) buf.push_back(r);
-      }
-    }
+    neighbours(mt, nodes, pat.row_edge[q], nb_);
+    for (int32_t u : nb_) buf.push_back(iperm[u]);
     std::sort(buf.begin(), buf.end());
     buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
     pat.col.insert(pat.col.end(), buf.begin(), buf.end());

@@ -16,6 +16,13 @@ struct MeshTopo {
   std::vector<int32_t> unk_of_edge;   // canonical edge -> unknown index or -1
   std::vector<int32_t> edge_of_unk;   // unknown index -> canonical edge
   int64_t n_unknowns = 0;
+  // interior nodes (the nodal functions whose gradients span the null space
+  // of the curl-curl operator with tangential-E boundary condition)
+  int64_t n_nodes = 0;
+  std::vector<int32_t> unk_of_node;   // canonical node -> interior index or -1
+  std::vector<int32_t> node_of_unk;
+  int64_t n_inodes = 0;
+  int64_t node(int i, int j, int k) const { return i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k); }
 
   void init(int nx_, int ny_, int nz_);
   int64_t xedge(int i, int j, int k) const { return i + (int64_t)nx * (j + (int64_t)(ny + 1) * k); }
@@ -33,6 +40,11 @@ struct MeshTopo {
 // 12x12 element matrices (row-major): unit-conductivity mass and stiffness.
 void element_mass_unit(double h, double out[144]);
 void element_stiffness(double h, double mu, double out[144]);
+// 8x8 nodal matrix G_c^T M1_c G_c of one cell (unit conductivity); local
+// node order (dx,dy,dz) = (0,0,0),(1,0,0),(0,1,0),(1,1,0),(0,0,1),...
+void element_grad_mass(double h, double out[64]);
+// local gradient of one cell: 12 edges x 8 nodes, entries -1/0/+1
+void element_gradient(int out[96]);
 
 struct SymNode {
   int box[3][2];
@@ -60,16 +72,19 @@ struct Symbolic {
 // Nested dissection + supernodal symbolic factorisation (exact spec of the
 // ordering: longest side split at lo + (hi-lo)/2, ties x < y < z, leaves of
 // side <= leaf_max, post-order numbering, columns by canonical id).
-void analyse_symbolic(const MeshTopo &mt, int leaf_max, Symbolic &sym);
+// Unknowns are the interior edges; with `nodes` the interior nodes (same
+// boxes, separators = nodes of the split plane inside the box).
+void analyse_symbolic(const MeshTopo &mt, int leaf_max, Symbolic &sym, bool nodes = false);
 
 // CSR pattern of "shares a cell" between unknowns, in the ordering given by
 // perm (perm[new] = unknown); columns sorted.  row_edge[new] = canonical edge.
 struct Pattern {
   std::vector<int64_t> rowptr;
   std::vector<int32_t> col;
-  std::vector<int32_t> row_edge;
-  std::vector<int32_t> edge_new;   // canonical edge -> new index or -1
+  std::vector<int32_t> row_edge;   // canonical edge (or node) of each row
+  std::vector<int32_t> edge_new;   // canonical edge (or node) -> new index or -1
 };
-void build_pattern(const MeshTopo &mt, const std::vector<int32_t> &perm, Pattern &pat);
+void build_pattern(const MeshTopo &mt, const std::vector<int32_t> &perm, Pattern &pat,
+                   bool nodes = false);
 
 }  // namespace tem

@@ -558,6 +558,119 @@ hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int64_t N,
   return hipGetLastError();
 }
 
+// ------------------------------------------------ nodal gradient space
+// Row-owner assembly of G^T M G over interior nodes: each thread sums the
+// sigma-weighted 8x8 element blocks of the <= 8 cells around its node.
+__global__ void k_assemble_nodal(int64_t Nn, const int64_t *rowptr, const int32_t *col,
+                                 const int32_t *row_node, const int32_t *node_new, int nx, int ny,
+                                 int nz, const double *Le, const double *sigma, double *Lv) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Nn) return;
+  const int64_t v = row_node[q];
+  const int i = (int)(v % (nx + 1));
+  const int64_t rr = v / (nx + 1);
+  const int j = (int)(rr % (ny + 1)), k = (int)(rr / (ny + 1));
+  const int64_t rb = rowptr[q], re = rowptr[q + 1];
+  for (int64_t t = rb; t < re; ++t) Lv[t] = 0.0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int ci = i - dx, cj = j - dy, ck = k - dz;
+        if (ci < 0 || cj < 0 || ck < 0 || ci >= nx || cj >= ny || ck >= nz) continue;
+        const double sg = sigma[ci + (int64_t)nx * (cj + (int64_t)ny * ck)];
+        const int la = dx + 2 * dy + 4 * dz;
+        for (int lb = 0; lb < 8; ++lb) {
+          const int bx = lb & 1, by = (lb >> 1) & 1, bz = lb >> 2;
+          const int32_t cidx =
+              node_new[(ci + bx) + (int64_t)(nx + 1) * ((cj + by) + (int64_t)(ny + 1) * (ck + bz))];
+          if (cidx < 0) continue;
+          int64_t lo = rb, hi = re - 1;
+          while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (col[mid] < cidx) lo = mid + 1; else hi = mid;
+          }
+          Lv[lo] += sg * Le[la * 8 + lb];
+        }
+      }
+}
+
+hipError_t launch_assemble_nodal(hipStream_t st, int64_t Nn, const int64_t *rowptr,
+                                 const int32_t *col, const int32_t *row_node,
+                                 const int32_t *node_new, int nx, int ny, int nz, const double *Le,
+                                 const double *sigma, double *Lv) {
+  if (Nn <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble_nodal, dim3(grid_1d(Nn, 128, 1 << 30)), dim3(128), 0, st, Nn,
+                     rowptr, col, row_node, node_new, nx, ny, nz, Le, sigma, Lv);
+  return hipGetLastError();
+}
+
+// out[p][n][s] = (G^T r)_n = sum over the 6 incident edges, + for the edge
+// ending at n and - for the edge starting at n
+__global__ void k_grad_T(int64_t Nn, int npole, int S, int64_t N, const int32_t *node_edges,
+                         const cpx<double> *r, cpx<double> *out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mS = (int64_t)npole * S;
+  if (idx >= Nn * mS) return;
+  const int64_t n = idx / mS;
+  const int ps = (int)(idx % mS);
+  const int p = ps / S, c = ps % S;
+  const cpx<double> *R = r + (int64_t)p * N * S + c;
+  double ar = 0.0, ai = 0.0;
+  for (int t = 0; t < 6; ++t) {
+    const cpx<double> v = R[(int64_t)node_edges[n * 6 + t] * S];
+    const double sg = (t & 1) ? -1.0 : 1.0;
+    ar += sg * v.re;
+    ai += sg * v.im;
+  }
+  out[((int64_t)p * Nn + n) * S + c] = {ar, ai};
+}
+
+hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int64_t N,
+                         const int32_t *node_edges, const cpx<double> *r, cpx<double> *out) {
+  const int64_t tot = Nn * npole * S;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_T, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, Nn, npole, S, N,
+                     node_edges, r, out);
+  return hipGetLastError();
+}
+
+// z[p][q][s] += coef[p] * (y[p][end(q)][s] - y[p][start(q)][s])
+__global__ void k_grad_add(int64_t N, int npole, int S, int64_t Nn, const int32_t *edge_nodes,
+                           const cpx<double> *coef, const cpx<double> *y, cpx<double> *z) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mS = (int64_t)npole * S;
+  if (idx >= N * mS) return;
+  const int64_t q = idx / mS;
+  const int ps = (int)(idx % mS);
+  const int p = ps / S, c = ps % S;
+  const cpx<double> *Y = y + (int64_t)p * Nn * S + c;
+  const int32_t a = edge_nodes[q * 2], b = edge_nodes[q * 2 + 1];
+  double gr = 0.0, gi = 0.0;
+  if (b >= 0) {
+    gr += Y[(int64_t)b * S].re;
+    gi += Y[(int64_t)b * S].im;
+  }
+  if (a >= 0) {
+    gr -= Y[(int64_t)a * S].re;
+    gi -= Y[(int64_t)a * S].im;
+  }
+  const cpx<double> k = coef[p];
+  cpx<double> *Z = z + ((int64_t)p * N + q) * S + c;
+  cpx<double> v = *Z;
+  v.re += k.re * gr - k.im * gi;
+  v.im += k.re * gi + k.im * gr;
+  *Z = v;
+}
+
+hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int64_t Nn,
+                           const int32_t *edge_nodes, const cpx<double> *coef,
+                           const cpx<double> *y, cpx<double> *z) {
+  const int64_t tot = N * npole * S;
+  hipLaunchKernelGGL(k_grad_add, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
+                     Nn, edge_nodes, coef, y, z);
+  return hipGetLastError();
+}
+
 // inv[ps] = 1/sqrt(re(dot)) (1 for zero), nrm[ps] = sqrt(re(dot))
 __global__ void k_norm_scales(int n, const cpx<double> *dots, double *inv, double *nrm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

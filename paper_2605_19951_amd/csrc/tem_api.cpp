@@ -83,6 +83,25 @@ struct Tiles {
   }
 };
 
+// One multifrontal system: symbolic structure, pattern and device maps.
+// The edge system holds the shifted matrices of all poles; the nodal system
+// holds the gradient-space matrix G^T M G used by the refinement.
+struct MF {
+  bool nodes = false;
+  Symbolic sym;
+  Pattern pat;
+  std::vector<int32_t> perm;
+  int64_t N = 0;
+  DBuf d_rowptr, d_col, d_row_ent, d_ent_new;
+  DBuf d_first, d_k, d_u, d_rows_off, d_rows, d_rel, d_panel_off, d_cb_off, d_w_off, d_gmap_off,
+      d_gmap0, d_gmap1, d_child0, d_child1, d_lvl_nodes, d_amap_csr, d_amap_pos;
+  std::vector<LevelInfo> levels;   // by depth (0 = root)
+  int64_t pole_stride = 0;         // panel elements per pole
+  int64_t cb_stride = 0;           // max level CB elements per pole
+  int64_t w_rows_max = 0;
+  DBuf w_t, w_w0, w_w1;            // sweep work space
+};
+
 }  // namespace
 
 struct tem_ctx {
@@ -97,21 +116,15 @@ struct tem_ctx {
   MeshTopo mt;
   double Ke[144], Me[144];
   std::vector<int32_t> params;
-  // ordering currently used by the device pattern
-  std::vector<int32_t> perm;
-  Pattern pat;
-  Symbolic sym;
   int leaf = 4;
+  MF ed;                           // edge system (ordering used by the device pattern)
+  MF nd;                           // nodal gradient-space system
   // device: mesh and operators
-  DBuf d_rowptr, d_col, d_K, d_M, d_row_edge, d_edge_new, d_cell_new, d_sigma, d_params, d_Ke,
-      d_Me;
-  // device: symbolic
-  DBuf d_first, d_k, d_u, d_rows_off, d_rows, d_rel, d_panel_off, d_cb_off, d_w_off, d_gmap_off,
-      d_gmap0, d_gmap1, d_child0, d_child1, d_lvl_nodes, d_amap_csr, d_amap_pos;
-  std::vector<LevelInfo> levels;   // by depth (0 = root)
-  int64_t pole_stride = 0;         // panel elements per pole
-  int64_t cb_stride = 0;           // max level CB elements per pole
-  int64_t w_rows_max = 0;
+  DBuf d_K, d_M, d_cell_new, d_sigma, d_params, d_Ke, d_Me, d_Le;
+  // nodal matrix G^T M G (values on nd's pattern), zeros, its factor
+  DBuf d_Ln, d_Lzero, d_nfactor, d_nxi, d_edge_nodes, d_node_edges, d_nvec, d_ncoef;
+  bool nodal_ready = false;
+  bool aux = true;                 // gradient-space correction in FP32 refinement
   // factors
   int npole = 0;
   tem_precision prec = TEM_FP64;
@@ -129,10 +142,22 @@ struct tem_ctx {
   int R = 0, K = 0;
   DBuf d_qptr, d_qcol, d_qval, d_alpha;
   // work space
-  DBuf w_x, w_t, w_w0, w_w1;       // factor-precision sweep buffers
+  DBuf w_x;                        // factor-precision sweep vector
   DBuf v_r, v_z, v_x, v_w, v_rhs, v_lam, v_vs, v_dots, v_partial, v_inv, v_nrm, v_coef, v_mask;
-  DBuf v_basis;
+  DBuf v_basis, v_aux;
   int basis_len = 0;
+  // profiling (HIP events around the update launches and the sweeps)
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Span {
+    hipEvent_t a, b;
+    double work;   // flops (updates) or bytes (sweeps)
+    int kind;      // 0 update, 1 sweep
+  };
+  std::vector<Span> spans;
+  double upd_ms = 0, upd_flops = 0, sweep_ms = 0, sweep_bytes = 0;
+  int64_t upd_launches = 0, sweeps = 0;
 
   hipError_t check_last() { return hipGetLastError(); }
 };
@@ -155,16 +180,39 @@ tem_status hip_fail(tem_ctx *c, hipError_t e, const char *where) {
     if (e_ != hipSuccess) return hip_fail(c, e_, where); \
   } while (0)
 
+#define TRY(expr)                  \
+  do {                             \
+    tem_status s_ = (expr);        \
+    if (s_ != TEM_OK) return s_;   \
+  } while (0)
+
 int64_t N_of(const tem_ctx *c) { return c->mt.n_unknowns; }
 
 // --------------------------------------------------- assembly on the device
+tem_status run_assemble_edges(tem_ctx *c) {
+  MF &e = c->ed;
+  HIPCHK(launch_assemble_KM(c->stream, e.N, e.d_rowptr.as<int64_t>(), e.d_col.as<int32_t>(),
+                            e.d_row_ent.as<int32_t>(), e.d_ent_new.as<int32_t>(), c->mt.nx,
+                            c->mt.ny, c->mt.nz, c->d_Ke.as<double>(), c->d_Me.as<double>(),
+                            c->d_sigma.as<double>(), c->d_K.as<double>(), c->d_M.as<double>()),
+         "assemble kernel");
+  return TEM_OK;
+}
+
+tem_status upload_pattern(tem_ctx *c, MF &mf) {
+  hipStream_t st = c->stream;
+  build_pattern(c->mt, mf.perm, mf.pat, mf.nodes);
+  mf.N = (int64_t)mf.perm.size();
+  HIPCHK(upload(mf.d_rowptr, mf.pat.rowptr, st), "upload rowptr");
+  HIPCHK(upload(mf.d_col, mf.pat.col, st), "upload col");
+  HIPCHK(upload(mf.d_row_ent, mf.pat.row_edge, st), "upload row map");
+  HIPCHK(upload(mf.d_ent_new, mf.pat.edge_new, st), "upload entity map");
+  return TEM_OK;
+}
+
 tem_status upload_pattern_and_assemble(tem_ctx *c) {
   hipStream_t st = c->stream;
-  build_pattern(c->mt, c->perm, c->pat);
-  HIPCHK(upload(c->d_rowptr, c->pat.rowptr, st), "upload rowptr");
-  HIPCHK(upload(c->d_col, c->pat.col, st), "upload col");
-  HIPCHK(upload(c->d_row_edge, c->pat.row_edge, st), "upload row_edge");
-  HIPCHK(upload(c->d_edge_new, c->pat.edge_new, st), "upload edge_new");
+  TRY(upload_pattern(c, c->ed));
   // cell -> 12 new indices
   std::vector<int32_t> cn((size_t)c->mt.n_cells * 12);
   int64_t ce[12];
@@ -173,21 +221,17 @@ tem_status upload_pattern_and_assemble(tem_ctx *c) {
       for (int i = 0; i < c->mt.nx; ++i) {
         int64_t cell = i + (int64_t)c->mt.nx * (j + (int64_t)c->mt.ny * k);
         c->mt.cell_edges(i, j, k, ce);
-        for (int t = 0; t < 12; ++t) cn[cell * 12 + t] = c->pat.edge_new[ce[t]];
+        for (int t = 0; t < 12; ++t) cn[cell * 12 + t] = c->ed.pat.edge_new[ce[t]];
       }
   HIPCHK(upload(c->d_cell_new, cn, st), "upload cell_new");
-  const size_t nnz = c->pat.col.size();
+  const size_t nnz = c->ed.pat.col.size();
   HIPCHK(c->d_K.alloc(sizeof(double) * nnz), "alloc K");
   HIPCHK(c->d_M.alloc(sizeof(double) * nnz), "alloc M");
-  HIPCHK(launch_assemble_KM(st, N_of(c), c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
-                            c->d_row_edge.as<int32_t>(), c->d_edge_new.as<int32_t>(), c->mt.nx,
-                            c->mt.ny, c->mt.nz, c->d_Ke.as<double>(), c->d_Me.as<double>(),
-                            c->d_sigma.as<double>(), c->d_K.as<double>(), c->d_M.as<double>()),
-         "assemble kernel");
-  return TEM_OK;
+  return run_assemble_edges(c);
 }
 
 void drop_factors(tem_ctx *c) {
+  c->nodal_ready = false;
   c->d_factor.release();
   c->d_cb0.release();
   c->d_cb1.release();
@@ -197,8 +241,8 @@ void drop_factors(tem_ctx *c) {
 }
 
 // ------------------------------------------------ symbolic maps (host)
-tem_status build_front_maps(tem_ctx *c) {
-  const Symbolic &sym = c->sym;
+tem_status build_front_maps(tem_ctx *c, MF &mf) {
+  const Symbolic &sym = mf.sym;
   const int ns = (int)sym.nodes.size();
   std::vector<int64_t> first(ns), rows_off(ns), panel_off(ns), cb_off(ns), w_off(ns), gmap_off(ns);
   std::vector<int32_t> kk(ns), uu(ns), child0(ns), child1(ns);
@@ -237,14 +281,14 @@ tem_status build_front_maps(tem_ctx *c) {
   }
   // levels (depth); factor/solve order is deepest first
   int nl = sym.n_levels;
-  c->levels.assign(nl, LevelInfo());
-  for (int s = 0; s < ns; ++s) c->levels[sym.nodes[s].level].nodes.push_back(s);
+  mf.levels.assign(nl, LevelInfo());
+  for (int s = 0; s < ns; ++s) mf.levels[sym.nodes[s].level].nodes.push_back(s);
   std::vector<int32_t> lvl_nodes;
   int64_t poff = 0;
-  c->cb_stride = 0;
-  c->w_rows_max = 0;
+  mf.cb_stride = 0;
+  mf.w_rows_max = 0;
   for (int L = nl - 1; L >= 0; --L) {
-    LevelInfo &li = c->levels[L];
+    LevelInfo &li = mf.levels[L];
     li.n = (int)li.nodes.size();
     li.lvl_begin = (int64_t)lvl_nodes.size();
     lvl_nodes.insert(lvl_nodes.end(), li.nodes.begin(), li.nodes.end());
@@ -269,16 +313,16 @@ tem_status build_front_maps(tem_ctx *c) {
     li.panel_end = poff;
     li.cb_size = cbo;
     li.w_rows = wo;
-    c->cb_stride = std::max(c->cb_stride, cbo);
-    c->w_rows_max = std::max(c->w_rows_max, wo);
+    mf.cb_stride = std::max(mf.cb_stride, cbo);
+    mf.w_rows_max = std::max(mf.w_rows_max, wo);
   }
-  c->pole_stride = poff;
+  mf.pole_stride = poff;
   // original-entry map, level by level (deepest first)
   std::vector<int32_t> amap_csr;
   std::vector<int64_t> amap_pos;
-  const Pattern &pat = c->pat;
+  const Pattern &pat = mf.pat;
   for (int L = nl - 1; L >= 0; --L) {
-    LevelInfo &li = c->levels[L];
+    LevelInfo &li = mf.levels[L];
     li.amap_begin = (int64_t)amap_csr.size();
     for (int s : li.nodes) {
       const SymNode &nd = sym.nodes[s];
@@ -325,82 +369,125 @@ tem_status build_front_maps(tem_ctx *c) {
     goff += n;
   }
   hipStream_t st = c->stream;
-  HIPCHK(upload(c->d_first, first, st), "upload first");
-  HIPCHK(upload(c->d_k, kk, st), "upload k");
-  HIPCHK(upload(c->d_u, uu, st), "upload u");
-  HIPCHK(upload(c->d_rows_off, rows_off, st), "upload rows_off");
-  HIPCHK(upload(c->d_rows, sym.rows, st), "upload rows");
-  HIPCHK(upload(c->d_rel, rel, st), "upload rel");
-  HIPCHK(upload(c->d_panel_off, panel_off, st), "upload panel_off");
-  HIPCHK(upload(c->d_cb_off, cb_off, st), "upload cb_off");
-  HIPCHK(upload(c->d_w_off, w_off, st), "upload w_off");
-  HIPCHK(upload(c->d_gmap_off, gmap_off, st), "upload gmap_off");
-  HIPCHK(upload(c->d_gmap0, gmap0, st), "upload gmap0");
-  HIPCHK(upload(c->d_gmap1, gmap1, st), "upload gmap1");
-  HIPCHK(upload(c->d_child0, child0, st), "upload child0");
-  HIPCHK(upload(c->d_child1, child1, st), "upload child1");
-  HIPCHK(upload(c->d_lvl_nodes, lvl_nodes, st), "upload levels");
-  HIPCHK(upload(c->d_amap_csr, amap_csr, st), "upload amap_csr");
-  HIPCHK(upload(c->d_amap_pos, amap_pos, st), "upload amap_pos");
+  HIPCHK(upload(mf.d_first, first, st), "upload first");
+  HIPCHK(upload(mf.d_k, kk, st), "upload k");
+  HIPCHK(upload(mf.d_u, uu, st), "upload u");
+  HIPCHK(upload(mf.d_rows_off, rows_off, st), "upload rows_off");
+  HIPCHK(upload(mf.d_rows, sym.rows, st), "upload rows");
+  HIPCHK(upload(mf.d_rel, rel, st), "upload rel");
+  HIPCHK(upload(mf.d_panel_off, panel_off, st), "upload panel_off");
+  HIPCHK(upload(mf.d_cb_off, cb_off, st), "upload cb_off");
+  HIPCHK(upload(mf.d_w_off, w_off, st), "upload w_off");
+  HIPCHK(upload(mf.d_gmap_off, gmap_off, st), "upload gmap_off");
+  HIPCHK(upload(mf.d_gmap0, gmap0, st), "upload gmap0");
+  HIPCHK(upload(mf.d_gmap1, gmap1, st), "upload gmap1");
+  HIPCHK(upload(mf.d_child0, child0, st), "upload child0");
+  HIPCHK(upload(mf.d_child1, child1, st), "upload child1");
+  HIPCHK(upload(mf.d_lvl_nodes, lvl_nodes, st), "upload levels");
+  HIPCHK(upload(mf.d_amap_csr, amap_csr, st), "upload amap_csr");
+  HIPCHK(upload(mf.d_amap_pos, amap_pos, st), "upload amap_pos");
   HIPCHK(hipStreamSynchronize(st), "sync maps");
   return TEM_OK;
 }
 
-FrontTab front_tab(const tem_ctx *c) {
+hipEvent_t ev_get(tem_ctx *c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+// time a launch sequence: call before (returns start event or null)
+hipEvent_t span_begin(tem_ctx *c) {
+  if (!c->profile) return nullptr;
+  hipEvent_t a = ev_get(c);
+  if (a) hipEventRecord(a, c->stream);
+  return a;
+}
+void span_end(tem_ctx *c, hipEvent_t a, double work, int kind) {
+  if (!c->profile || !a) return;
+  hipEvent_t b = ev_get(c);
+  if (!b) return;
+  hipEventRecord(b, c->stream);
+  c->spans.push_back({a, b, work, kind});
+}
+// fold recorded spans into the totals (after a stream synchronisation)
+void spans_collect(tem_ctx *c) {
+  for (auto &sp : c->spans) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) continue;
+    if (sp.kind == 0) {
+      c->upd_ms += ms;
+      c->upd_flops += sp.work;
+      c->upd_launches++;
+    } else {
+      c->sweep_ms += ms;
+      c->sweep_bytes += sp.work;
+      c->sweeps++;
+    }
+  }
+  c->spans.clear();
+  c->ev_used = 0;
+}
+
+FrontTab front_tab(const MF &mf) {
   FrontTab ft;
-  ft.first = c->d_first.as<int64_t>();
-  ft.k = c->d_k.as<int32_t>();
-  ft.u = c->d_u.as<int32_t>();
-  ft.rows_off = c->d_rows_off.as<int64_t>();
-  ft.rows = c->d_rows.as<int32_t>();
-  ft.rel = c->d_rel.as<int32_t>();
-  ft.panel_off = c->d_panel_off.as<int64_t>();
-  ft.cb_off = c->d_cb_off.as<int64_t>();
-  ft.w_off = c->d_w_off.as<int64_t>();
-  ft.gmap_off = c->d_gmap_off.as<int64_t>();
-  ft.gmap0 = c->d_gmap0.as<int32_t>();
-  ft.gmap1 = c->d_gmap1.as<int32_t>();
-  ft.child0 = c->d_child0.as<int32_t>();
-  ft.child1 = c->d_child1.as<int32_t>();
+  ft.first = mf.d_first.as<int64_t>();
+  ft.k = mf.d_k.as<int32_t>();
+  ft.u = mf.d_u.as<int32_t>();
+  ft.rows_off = mf.d_rows_off.as<int64_t>();
+  ft.rows = mf.d_rows.as<int32_t>();
+  ft.rel = mf.d_rel.as<int32_t>();
+  ft.panel_off = mf.d_panel_off.as<int64_t>();
+  ft.cb_off = mf.d_cb_off.as<int64_t>();
+  ft.w_off = mf.d_w_off.as<int64_t>();
+  ft.gmap_off = mf.d_gmap_off.as<int64_t>();
+  ft.gmap0 = mf.d_gmap0.as<int32_t>();
+  ft.gmap1 = mf.d_gmap1.as<int32_t>();
+  ft.child0 = mf.d_child0.as<int32_t>();
+  ft.child1 = mf.d_child1.as<int32_t>();
   return ft;
 }
 
-const int32_t *lvl_ptr(const tem_ctx *c, const LevelInfo &li) {
-  return c->d_lvl_nodes.as<int32_t>() + li.lvl_begin;
+const int32_t *lvl_ptr(const MF &mf, const LevelInfo &li) {
+  return mf.d_lvl_nodes.as<int32_t>() + li.lvl_begin;
 }
 
 // ------------------------------------------------------- factorisation
+// Factor g matrices Kv - xi_p Mv (p < g) of system mf into F (pole stride
+// mf.pole_stride), using the two contribution-block arenas.
 template <typename T>
-tem_status factor_group(tem_ctx *c, int p0, int g) {
+tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, const double *Kv,
+                        const double *Mv, int g, cpx<T> *arena0, cpx<T> *arena1) {
   hipStream_t st = c->stream;
-  FrontTab ft = front_tab(c);
-  cpx<T> *F = c->d_factor.as<cpx<T>>() + (int64_t)p0 * c->pole_stride;
-  cpx<T> *arena[2] = {c->d_cb0.as<cpx<T>>(), c->d_cb1.as<cpx<T>>()};
-  const double *xi = c->d_xi.as<double>() + 2 * p0;
-  const int nl = (int)c->levels.size();
-  const Symbolic &sym = c->sym;
+  FrontTab ft = front_tab(mf);
+  cpx<T> *arena[2] = {arena0, arena1};
+  const int nl = (int)mf.levels.size();
+  const Symbolic &sym = mf.sym;
   for (int L = nl - 1; L >= 0; --L) {
-    const LevelInfo &li = c->levels[L];
-    const int32_t *ln = lvl_ptr(c, li);
+    const LevelInfo &li = mf.levels[L];
+    const int32_t *ln = lvl_ptr(mf, li);
     cpx<T> *cbL = arena[L & 1];
     cpx<T> *cbC = arena[(L + 1) & 1];
     HIPCHK(launch_fill_zero<T>(st, F + li.panel_begin, li.panel_end - li.panel_begin, g,
-                               c->pole_stride),
+                               mf.pole_stride),
            "zero panels");
-    HIPCHK(launch_fill_zero<T>(st, cbL, li.cb_size, g, c->cb_stride), "zero cb");
+    HIPCHK(launch_fill_zero<T>(st, cbL, li.cb_size, g, mf.cb_stride), "zero cb");
     HIPCHK(launch_front_assemble<T>(st, li.amap_end - li.amap_begin,
-                                    c->d_amap_csr.as<int32_t>() + li.amap_begin,
-                                    c->d_amap_pos.as<int64_t>() + li.amap_begin,
-                                    c->d_K.as<double>(), c->d_M.as<double>(), xi, g, F,
-                                    c->pole_stride),
+                                    mf.d_amap_csr.as<int32_t>() + li.amap_begin,
+                                    mf.d_amap_pos.as<int64_t>() + li.amap_begin, Kv, Mv, xi, g, F,
+                                    mf.pole_stride),
            "front assemble");
     for (int sl = 0; sl < 2; ++sl)
-      HIPCHK(launch_extend_add<T>(st, ft, ln, li.n, sl, li.max_u_child[sl], g, F, c->pole_stride,
-                                  cbL, cbC, c->cb_stride),
+      HIPCHK(launch_extend_add<T>(st, ft, ln, li.n, sl, li.max_u_child[sl], g, F, mf.pole_stride,
+                                  cbL, cbC, mf.cb_stride),
              "extend-add");
     for (int j0 = 0; j0 < li.max_k; j0 += NB) {
       int max_rows = 0;
       int64_t max_tiles = 0;
+      double fl = 0;
       for (int s : li.nodes) {
         const SymNode &nd = sym.nodes[s];
         const int64_t k = nd.last - nd.first, n = k + nd.nrows;
@@ -408,84 +495,102 @@ tem_status factor_group(tem_ctx *c, int p0, int g) {
         const int64_t w = std::min<int64_t>(NB, k - j0);
         max_rows = std::max<int>(max_rows, (int)(n - j0 - w));
         max_tiles = std::max(max_tiles, Tiles::count(n, j0 + NB, k));
+        if (c->profile && j0 + NB < k) {
+          // lower-trapezoid entries of columns [j0+NB, k): sum (n - col)
+          const double c0 = j0 + NB, c1 = (double)k;
+          fl += 8.0 * (double)w * ((c1 - c0) * n - (c1 * (c1 - 1) - c0 * (c0 - 1)) / 2.0) * g;
+        }
       }
-      HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, g, F, c->pole_stride,
+      HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, g, F, mf.pole_stride,
                                   c->d_flags.as<int>()),
              "panel diag");
-      HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, max_rows, g, F, c->pole_stride),
+      HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, max_rows, g, F, mf.pole_stride),
              "panel trsm");
-      HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 0, j0, max_tiles, g, F, c->pole_stride,
-                                    cbL, c->cb_stride),
+      hipEvent_t ea = span_begin(c);
+      HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 0, j0, max_tiles, g, F, mf.pole_stride,
+                                    cbL, mf.cb_stride),
              "trailing update");
+      span_end(c, ea, fl, 0);
     }
     int64_t cb_tiles = 0;
+    double fl = 0;
     for (int s : li.nodes) {
       const SymNode &nd = sym.nodes[s];
       const int64_t k = nd.last - nd.first, n = k + nd.nrows;
       if (k > 0) cb_tiles = std::max(cb_tiles, Tiles::count(n, k, n));
+      fl += 8.0 * (double)k * (double)nd.nrows * (double)(nd.nrows + 1) / 2.0 * g;
     }
-    HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, cb_tiles, g, F, c->pole_stride, cbL,
-                                  c->cb_stride),
+    hipEvent_t ea = span_begin(c);
+    HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, cb_tiles, g, F, mf.pole_stride, cbL,
+                                  mf.cb_stride),
            "contribution update");
+    span_end(c, ea, fl, 0);
   }
   return TEM_OK;
 }
 
 // ---------------------------------------------------------------- sweeps
 template <typename T>
-tem_status ensure_sweep_ws(tem_ctx *c, int S) {
-  const int64_t N = N_of(c);
-  const size_t vec = sizeof(cpx<T>) * (size_t)c->npole * N * S;
-  const size_t wb = sizeof(cpx<T>) * (size_t)c->npole * std::max<int64_t>(c->w_rows_max, 1) * S;
-  if (c->w_x.bytes != vec) HIPCHK(c->w_x.alloc(vec), "alloc sweep x");
-  if (c->w_t.bytes != vec) HIPCHK(c->w_t.alloc(vec), "alloc sweep t");
-  if (c->w_w0.bytes != wb) HIPCHK(c->w_w0.alloc(wb), "alloc sweep w0");
-  if (c->w_w1.bytes != wb) HIPCHK(c->w_w1.alloc(wb), "alloc sweep w1");
+tem_status ensure_sweep_ws(tem_ctx *c, MF &mf, int npole, int S) {
+  const size_t vec = sizeof(cpx<T>) * (size_t)npole * mf.N * S;
+  const size_t wb = sizeof(cpx<T>) * (size_t)npole * std::max<int64_t>(mf.w_rows_max, 1) * S;
+  if (mf.w_t.bytes < vec) HIPCHK(mf.w_t.alloc(vec), "alloc sweep t");
+  if (mf.w_w0.bytes < wb) HIPCHK(mf.w_w0.alloc(wb), "alloc sweep w0");
+  if (mf.w_w1.bytes < wb) HIPCHK(mf.w_w1.alloc(wb), "alloc sweep w1");
   return TEM_OK;
 }
 
-// in place: x (factor precision, [pole][N][S]) <- A^{-1} x for every pole
+// in place: x ([pole][N][S], factor precision) <- A_p^{-1} x for npole
+// systems whose factors start at F with stride f_stride (0: one shared factor)
 template <typename T>
-tem_status sweep(tem_ctx *c, cpx<T> *x, int S) {
+tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, int npole,
+                        cpx<T> *x, int S) {
+  TRY(ensure_sweep_ws<T>(c, mf, npole, S));
   hipStream_t st = c->stream;
-  FrontTab ft = front_tab(c);
-  const int64_t N = N_of(c);
-  const cpx<T> *F = c->d_factor.as<cpx<T>>();
-  const int m = c->npole;
-  cpx<T> *W[2] = {c->w_w0.as<cpx<T>>(), c->w_w1.as<cpx<T>>()};
-  const int64_t ws = std::max<int64_t>(c->w_rows_max, 1) * S;
-  cpx<T> *t = c->w_t.as<cpx<T>>();
-  const int nl = (int)c->levels.size();
+  FrontTab ft = front_tab(mf);
+  const int64_t N = mf.N;
+  cpx<T> *W[2] = {mf.w_w0.as<cpx<T>>(), mf.w_w1.as<cpx<T>>()};
+  const int64_t ws = std::max<int64_t>(mf.w_rows_max, 1) * S;
+  cpx<T> *t = mf.w_t.as<cpx<T>>();
+  const int nl = (int)mf.levels.size();
   for (int L = nl - 1; L >= 0; --L) {
-    const LevelInfo &li = c->levels[L];
-    const int32_t *ln = lvl_ptr(c, li);
-    HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, m, S, N, F, c->pole_stride, x, W[(L + 1) & 1], ws),
+    const LevelInfo &li = mf.levels[L];
+    const int32_t *ln = lvl_ptr(mf, li);
+    HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, W[(L + 1) & 1], ws),
            "fwd tri");
-    HIPCHK(launch_fwd_rect<T>(st, ft, ln, li.n, li.max_u, m, S, N, F, c->pole_stride, x,
+    HIPCHK(launch_fwd_rect<T>(st, ft, ln, li.n, li.max_u, npole, S, N, F, f_stride, x,
                               W[(L + 1) & 1], W[L & 1], ws),
            "fwd rect");
   }
   for (int L = 0; L < nl; ++L) {
-    const LevelInfo &li = c->levels[L];
-    const int32_t *ln = lvl_ptr(c, li);
-    HIPCHK(launch_bwd_rect<T>(st, ft, ln, li.n, li.max_k, m, S, N, F, c->pole_stride, x, t, N * S),
+    const LevelInfo &li = mf.levels[L];
+    const int32_t *ln = lvl_ptr(mf, li);
+    HIPCHK(launch_bwd_rect<T>(st, ft, ln, li.n, li.max_k, npole, S, N, F, f_stride, x, t, N * S),
            "bwd rect");
-    HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, m, S, N, F, c->pole_stride, x, t, N * S),
+    HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S),
            "bwd tri");
   }
   return TEM_OK;
+}
+
+// edge sweep with the cached pole factors (timed when profiling)
+template <typename T>
+tem_status sweep(tem_ctx *c, cpx<T> *x, int S) {
+  hipEvent_t ea = span_begin(c);
+  tem_status s0 = sweep_levels<T>(c, c->ed, c->d_factor.as<cpx<T>>(), c->ed.pole_stride,
+                                  c->npole, x, S);
+  // each factor entry is read once forward and once backward; the
+  // solution vector is read and written in both passes
+  const double bytes = 2.0 * (double)sizeof(cpx<T>) * (double)c->ed.pole_stride * c->npole +
+                       4.0 * (double)sizeof(cpx<T>) * (double)c->npole * N_of(c) * S;
+  span_end(c, ea, bytes, 1);
+  return s0;
 }
 
 tem_status ensure_vec(tem_ctx *c, DBuf &b, size_t bytes, const char *what) {
   if (b.bytes != bytes) HIPCHK(b.alloc(bytes), what);
   return TEM_OK;
 }
-
-#define TRY(expr)                  \
-  do {                             \
-    tem_status s_ = (expr);        \
-    if (s_ != TEM_OK) return s_;   \
-  } while (0)
 
 int dot_blocks(int64_t N) {
   int64_t b = (N + 8191) / 8192;
@@ -512,6 +617,32 @@ tem_status sysnorms(tem_ctx *c, const cpx<double> *v, int S, std::vector<double>
   return TEM_OK;
 }
 
+// Gradient-space (Galerkin) correction of a preconditioned solve:
+// z += G (G^T A_p G)^{-1} G^T (r - A_p z), with G^T A_p G = -xi_p G^T M G
+// because K G = 0; one FP64 factor of the nodal matrix G^T M G serves every
+// pole.  This removes the error the FP32 factors leave on the
+// (nearly singular) gradient modes of the low-conductivity region.
+tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S) {
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c), Nn = c->nd.N;
+  const int m = c->npole;
+  TRY(ensure_vec(c, c->v_aux, sizeof(cpx<double>) * (size_t)m * S * N, "alloc aux residual"));
+  TRY(ensure_vec(c, c->d_nvec, sizeof(cpx<double>) * (size_t)m * S * std::max<int64_t>(Nn, 1),
+                 "alloc nodal vector"));
+  cpx<double> *w = c->v_aux.as<cpx<double>>();
+  cpx<double> *y = c->d_nvec.as<cpx<double>>();
+  HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
+                         c->d_K.as<double>(), c->d_M.as<double>(), c->d_xi.as<double>(), nullptr,
+                         r, z, w),
+         "aux residual");
+  HIPCHK(launch_grad_T(st, Nn, m, S, N, c->d_node_edges.as<int32_t>(), w, y), "G^T");
+  TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, m, y, S));
+  HIPCHK(launch_grad_add(st, N, m, S, Nn, c->d_edge_nodes.as<int32_t>(),
+                         c->d_ncoef.as<cpx<double>>(), y, z),
+         "z += G y");
+  return TEM_OK;
+}
+
 // out = A^{-1} in (approximately, in the factor precision), FP64 in/out
 tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
   hipStream_t st = c->stream;
@@ -519,7 +650,7 @@ tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
   const int m = c->npole;
   const int mS = m * S;
   if (c->prec == TEM_FP64) {
-    TRY(ensure_sweep_ws<double>(c, S));
+    TRY(ensure_vec(c, c->w_x, sizeof(cpx<double>) * (size_t)mS * N, "alloc sweep x"));
     cpx<double> *x = c->w_x.as<cpx<double>>();
     HIPCHK(hipMemcpyAsync(x, in, sizeof(cpx<double>) * (size_t)mS * N, hipMemcpyDeviceToDevice, st),
            "copy rhs");
@@ -528,7 +659,7 @@ tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
            "copy sol");
     return TEM_OK;
   }
-  TRY(ensure_sweep_ws<float>(c, S));
+  TRY(ensure_vec(c, c->w_x, sizeof(cpx<float>) * (size_t)mS * N, "alloc sweep x"));
   const int nb = dot_blocks(N);
   TRY(ensure_vec(c, c->v_partial, sizeof(cpx<double>) * (size_t)nb * mS * 2, "alloc partial"));
   TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)mS * 64, "alloc dots"));
@@ -544,6 +675,7 @@ tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
   HIPCHK(launch_convert_in<float>(st, N * S, m, S, in, c->v_inv.as<double>(), x), "to fp32");
   TRY(sweep<float>(c, x, S));
   HIPCHK(launch_convert_out<float>(st, N * S, m, S, x, c->v_nrm.as<double>(), out), "to fp64");
+  if (c->aux && c->nodal_ready) TRY(aux_correct(c, in, out, S));
   return TEM_OK;
 }
 
@@ -569,7 +701,10 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
   const int max_iter = (ir && ir->max_iter > 0) ? ir->max_iter : 200;
   int restart = (ir && ir->restart > 0) ? ir->restart : 30;
   restart = std::min(restart, 60);
+  // FP64 factors: classical refinement.  FP32 factors with the gradient-space
+  // correction: classical refinement unless GMRES is asked for explicitly.
   if (c->prec == TEM_FP64) restart = 1;
+  if (c->prec == TEM_FP32_IR && c->aux && c->nodal_ready && !(ir && ir->restart > 1)) restart = 1;
   const size_t vbytes = sizeof(cpx<double>) * (size_t)mS * N;
   TRY(ensure_vec(c, c->v_r, vbytes, "alloc r"));
   TRY(ensure_vec(c, c->v_z, vbytes, "alloc z"));
@@ -583,7 +718,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
   // x = 0, so that r = f and ||r|| = ||f||
   std::vector<double> fn;
   HIPCHK(launch_fill_f64(st, (double *)x, 2 * (int64_t)mS * N, 0.0), "zero x");
-  HIPCHK(launch_residual(st, N, m, S, c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+  HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
                          c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
          "residual");
   TRY(sysnorms(c, r, S, fn));
@@ -619,7 +754,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
                                  c->v_mask.as<int>()),
              "x += z");
-      HIPCHK(launch_residual(st, N, m, S, c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+      HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
                              c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
              "residual");
     }
@@ -665,7 +800,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
         TRY(precond(c, V + k * vs, z, S));
         ++solves;
         ++total;
-        HIPCHK(launch_spmv_shifted(st, N, m, S, c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+        HIPCHK(launch_spmv_shifted(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
                                    c->d_K.as<double>(), c->d_M.as<double>(), xi, z, w),
                "A z");
         // modified Gram-Schmidt, twice (reorthogonalisation)
@@ -767,7 +902,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
                                  c->v_mask.as<int>()),
              "x += z");
       HIPCHK(hipStreamSynchronize(st), "x sync");
-      HIPCHK(launch_residual(st, N, m, S, c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
+      HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
                              c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
              "residual");
     }
@@ -789,6 +924,94 @@ void fill_stats(const IrResult &res, tem_ir_stats *stats) {
 }
 
 }  // namespace
+
+// ------------------------------------------------ nodal gradient system
+tem_status setup_nodal(tem_ctx *c, int leaf) {
+  MF &nd = c->nd;
+  nd.nodes = true;
+  c->nodal_ready = false;
+  if (c->mt.n_inodes == 0) return TEM_OK;
+  try {
+    analyse_symbolic(c->mt, leaf, nd.sym, true);
+  } catch (const std::exception &ex) {
+    return fail(c, TEM_EINVAL, std::string("nodal analysis: ") + ex.what());
+  }
+  nd.perm = nd.sym.perm;
+  TRY(upload_pattern(c, nd));
+  TRY(build_front_maps(c, nd));
+  // node -> 6 incident edges (new edge indices), edge -> (start, end) nodes
+  const MeshTopo &mt = c->mt;
+  const Pattern &ep = c->ed.pat;
+  std::vector<int32_t> ne((size_t)nd.N * 6);
+  for (int64_t q = 0; q < nd.N; ++q) {
+    int64_t v = nd.pat.row_edge[q];
+    int i = (int)(v % (mt.nx + 1));
+    int64_t rr = v / (mt.nx + 1);
+    int j = (int)(rr % (mt.ny + 1)), k = (int)(rr / (mt.ny + 1));
+    int64_t es[6] = {mt.xedge(i - 1, j, k), mt.xedge(i, j, k), mt.yedge(i, j - 1, k),
+                     mt.yedge(i, j, k),     mt.zedge(i, j, k - 1), mt.zedge(i, j, k)};
+    for (int t = 0; t < 6; ++t) {
+      int32_t qe = ep.edge_new[es[t]];
+      if (qe < 0) return fail(c, TEM_EINVAL, "interior node touches a boundary edge");
+      ne[q * 6 + t] = qe;
+    }
+  }
+  std::vector<int32_t> en((size_t)c->ed.N * 2);
+  for (int64_t q = 0; q < c->ed.N; ++q) {
+    int d, i, j, k;
+    mt.geometry(ep.row_edge[q], d, i, j, k);
+    int64_t a = mt.node(i, j, k), b = mt.node(i + (d == 0), j + (d == 1), k + (d == 2));
+    en[q * 2] = nd.pat.edge_new[a];
+    en[q * 2 + 1] = nd.pat.edge_new[b];
+  }
+  HIPCHK(upload(c->d_node_edges, ne, c->stream), "upload node edges");
+  HIPCHK(upload(c->d_edge_nodes, en, c->stream), "upload edge nodes");
+  double le[64];
+  element_grad_mass(c->mesh.h, le);
+  std::vector<double> lev(le, le + 64);
+  HIPCHK(upload(c->d_Le, lev, c->stream), "upload Le");
+  const size_t nnz = nd.pat.col.size();
+  HIPCHK(c->d_Ln.alloc(sizeof(double) * nnz), "alloc nodal values");
+  HIPCHK(c->d_Lzero.alloc(sizeof(double) * nnz), "alloc zeros");
+  HIPCHK(launch_fill_f64(c->stream, c->d_Lzero.as<double>(), (int64_t)nnz, 0.0), "zeros");
+  std::vector<double> zxi = {0.0, 0.0};
+  HIPCHK(upload(c->d_nxi, zxi, c->stream), "upload zero shift");
+  HIPCHK(hipStreamSynchronize(c->stream), "nodal setup sync");
+  return TEM_OK;
+}
+
+// assemble G^T M G for the current sigma and factor it (FP64)
+tem_status factor_nodal(tem_ctx *c) {
+  MF &nd = c->nd;
+  c->nodal_ready = false;
+  if (nd.N == 0) return TEM_OK;
+  hipStream_t st = c->stream;
+  HIPCHK(launch_assemble_nodal(st, nd.N, nd.d_rowptr.as<int64_t>(), nd.d_col.as<int32_t>(),
+                               nd.d_row_ent.as<int32_t>(), nd.d_ent_new.as<int32_t>(), c->mt.nx,
+                               c->mt.ny, c->mt.nz, c->d_Le.as<double>(), c->d_sigma.as<double>(),
+                               c->d_Ln.as<double>()),
+         "nodal assembly");
+  HIPCHK(c->d_nfactor.alloc(sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.pole_stride, 1)),
+         "alloc nodal factor");
+  DBuf a0, a1;
+  const size_t cbb = sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.cb_stride, 1);
+  HIPCHK(a0.alloc(cbb), "alloc nodal cb");
+  HIPCHK(a1.alloc(cbb), "alloc nodal cb");
+  TRY(factor_group<double>(c, nd, c->d_nfactor.as<cpx<double>>(), c->d_nxi.as<double>(),
+                           c->d_Ln.as<double>(), c->d_Lzero.as<double>(), 1, a0.as<cpx<double>>(),
+                           a1.as<cpx<double>>()));
+  // coefficients -1/xi_p of the correction
+  std::vector<double> coef(2 * c->npole);
+  for (int p = 0; p < c->npole; ++p) {
+    std::complex<double> v = -1.0 / std::complex<double>(c->xi[2 * p], c->xi[2 * p + 1]);
+    coef[2 * p] = v.real();
+    coef[2 * p + 1] = v.imag();
+  }
+  HIPCHK(upload(c->d_ncoef, coef, st), "upload coefficients");
+  HIPCHK(hipStreamSynchronize(st), "nodal factor sync");
+  c->nodal_ready = true;
+  return TEM_OK;
+}
 
 // =================================================================== ABI
 extern "C" {
@@ -841,6 +1064,7 @@ void tem_destroy(tem_ctx *c) {
   hipStreamSynchronize(c->stream);
   hipStream_t st = c->stream;
   bool own = c->own_stream;
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   delete c;
   if (own) hipStreamDestroy(st);
 }
@@ -893,8 +1117,8 @@ tem_status tem_assemble(tem_ctx *c, const tem_mesh *mesh, const double *sigma_ce
     std::vector<double> ke(c->Ke, c->Ke + 144), me(c->Me, c->Me + 144);
     HIPCHK(upload(c->d_Ke, ke, c->stream), "upload Ke");
     HIPCHK(upload(c->d_Me, me, c->stream), "upload Me");
-    c->perm.resize(c->mt.n_unknowns);
-    for (int64_t q = 0; q < c->mt.n_unknowns; ++q) c->perm[q] = (int32_t)q;
+    c->ed.perm.resize(c->mt.n_unknowns);
+    for (int64_t q = 0; q < c->mt.n_unknowns; ++q) c->ed.perm[q] = (int32_t)q;
   }
   HIPCHK(c->d_sigma.alloc(sizeof(double) * n_cells), "alloc sigma");
   HIPCHK(hipMemcpyAsync(c->d_sigma.p, sigma_cells, sizeof(double) * n_cells,
@@ -905,11 +1129,7 @@ tem_status tem_assemble(tem_ctx *c, const tem_mesh *mesh, const double *sigma_ce
   if (!same_mesh) {
     TRY(upload_pattern_and_assemble(c));
   } else {
-    HIPCHK(launch_assemble_KM(c->stream, N_of(c), c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
-                              c->d_row_edge.as<int32_t>(), c->d_edge_new.as<int32_t>(), c->mt.nx,
-                              c->mt.ny, c->mt.nz, c->d_Ke.as<double>(), c->d_Me.as<double>(),
-                              c->d_sigma.as<double>(), c->d_K.as<double>(), c->d_M.as<double>()),
-           "assemble kernel");
+    TRY(run_assemble_edges(c));
   }
   HIPCHK(hipStreamSynchronize(c->stream), "tem_assemble sync");
   c->assembled = true;
@@ -931,11 +1151,7 @@ tem_status tem_set_model(tem_ctx *c, const double *m) {
   drop_factors(c);
   HIPCHK(launch_set_sigma_exp(c->stream, P, c->d_params.as<int32_t>(), m, c->d_sigma.as<double>()),
          "set sigma");
-  HIPCHK(launch_assemble_KM(c->stream, N_of(c), c->d_rowptr.as<int64_t>(), c->d_col.as<int32_t>(),
-                            c->d_row_edge.as<int32_t>(), c->d_edge_new.as<int32_t>(), c->mt.nx,
-                            c->mt.ny, c->mt.nz, c->d_Ke.as<double>(), c->d_Me.as<double>(),
-                            c->d_sigma.as<double>(), c->d_K.as<double>(), c->d_M.as<double>()),
-         "assemble kernel");
+  TRY(run_assemble_edges(c));
   HIPCHK(hipStreamSynchronize(c->stream), "set_model sync");
   return TEM_OK;
 }
@@ -947,12 +1163,12 @@ tem_status tem_export_operators(const tem_ctx *cc, int64_t *n_unknowns, int64_t 
   if (!c) return TEM_EINVAL;
   if (!c->assembled) return fail(c, TEM_ESTATE, "tem_export_operators: nothing assembled");
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
-  const int64_t N = N_of(c), nz = (int64_t)c->pat.col.size();
+  const int64_t N = N_of(c), nz = (int64_t)c->ed.pat.col.size();
   if (n_unknowns) *n_unknowns = N;
   if (nnz) *nnz = nz;
-  if (perm) std::memcpy(perm, c->perm.data(), sizeof(int32_t) * N);
-  if (rowptr) std::memcpy(rowptr, c->pat.rowptr.data(), sizeof(int64_t) * (N + 1));
-  if (col) std::memcpy(col, c->pat.col.data(), sizeof(int32_t) * nz);
+  if (perm) std::memcpy(perm, c->ed.perm.data(), sizeof(int32_t) * N);
+  if (rowptr) std::memcpy(rowptr, c->ed.pat.rowptr.data(), sizeof(int64_t) * (N + 1));
+  if (col) std::memcpy(col, c->ed.pat.col.data(), sizeof(int32_t) * nz);
   HIPCHK(hipStreamSynchronize(c->stream), "export sync");
   if (kval) HIPCHK(hipMemcpy(kval, c->d_K.p, sizeof(double) * nz, hipMemcpyDeviceToHost), "K d2h");
   if (mval) HIPCHK(hipMemcpy(mval, c->d_M.p, sizeof(double) * nz, hipMemcpyDeviceToHost), "M d2h");
@@ -967,26 +1183,27 @@ tem_status tem_analyse(tem_ctx *c, const tem_analyse_opts *opts, tem_symbolic_in
   if (!c->analysed || leaf != c->leaf) {
     drop_factors(c);
     try {
-      analyse_symbolic(c->mt, leaf, c->sym);
+      analyse_symbolic(c->mt, leaf, c->ed.sym, false);
     } catch (const std::exception &ex) {
       return fail(c, TEM_EINVAL, std::string("tem_analyse: ") + ex.what());
     }
     c->leaf = leaf;
-    c->perm = c->sym.perm;
+    c->ed.perm = c->ed.sym.perm;
     TRY(upload_pattern_and_assemble(c));
-    TRY(build_front_maps(c));
+    TRY(build_front_maps(c, c->ed));
+    TRY(setup_nodal(c, leaf));
     c->analysed = true;
   }
   if (info) {
     info->n_unknowns = c->mt.n_unknowns;
-    info->nnz_a = (int64_t)c->pat.col.size();
-    info->nnz_l = c->sym.nnz_l;
-    info->n_rows_total = (int64_t)c->sym.rows.size();
-    info->n_supernodes = (int32_t)c->sym.nodes.size();
-    info->n_levels = c->sym.n_levels;
-    info->max_front = c->sym.max_front;
+    info->nnz_a = (int64_t)c->ed.pat.col.size();
+    info->nnz_l = c->ed.sym.nnz_l;
+    info->n_rows_total = (int64_t)c->ed.sym.rows.size();
+    info->n_supernodes = (int32_t)c->ed.sym.nodes.size();
+    info->n_levels = c->ed.sym.n_levels;
+    info->max_front = c->ed.sym.max_front;
     info->reserved = 0;
-    info->flops_per_pole = c->sym.flops_per_pole;
+    info->flops_per_pole = c->ed.sym.flops_per_pole;
   }
   return TEM_OK;
 }
@@ -1049,15 +1266,14 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
   drop_factors(c);
   if (m != c->npole) c->surveyed = false;   // residues are per pole
   c->w_x.release();
-  c->w_t.release();
   c->v_basis.release();
   c->npole = m;
   c->prec = prec;
   c->xi.assign(xi, xi + 2 * m);
   HIPCHK(upload(c->d_xi, c->xi, c->stream), "upload xi");
   const size_t esz = prec == TEM_FP64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
-  const size_t fbytes = esz * (size_t)c->pole_stride * m;
-  const size_t cb_pole = esz * (size_t)std::max<int64_t>(c->cb_stride, 1);
+  const size_t fbytes = esz * (size_t)c->ed.pole_stride * m;
+  const size_t cb_pole = esz * (size_t)std::max<int64_t>(c->ed.cb_stride, 1);
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
   int64_t budget = (opts && opts->mem_budget_bytes > 0) ? opts->mem_budget_bytes
@@ -1079,7 +1295,26 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
   HIPCHK(hipEventRecord(e0, c->stream), "event");
   for (int p0 = 0; p0 < m; p0 += g) {
     int gg = std::min(g, m - p0);
-    tem_status s = prec == TEM_FP64 ? factor_group<double>(c, p0, gg) : factor_group<float>(c, p0, gg);
+    tem_status s =
+        prec == TEM_FP64
+            ? factor_group<double>(c, c->ed, c->d_factor.as<cpx<double>>() + (int64_t)p0 * c->ed.pole_stride,
+                                   c->d_xi.as<double>() + 2 * p0, c->d_K.as<double>(),
+                                   c->d_M.as<double>(), gg, c->d_cb0.as<cpx<double>>(),
+                                   c->d_cb1.as<cpx<double>>())
+            : factor_group<float>(c, c->ed, c->d_factor.as<cpx<float>>() + (int64_t)p0 * c->ed.pole_stride,
+                                  c->d_xi.as<double>() + 2 * p0, c->d_K.as<double>(),
+                                  c->d_M.as<double>(), gg, c->d_cb0.as<cpx<float>>(),
+                                  c->d_cb1.as<cpx<float>>());
+    if (s != TEM_OK) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return s;
+    }
+  }
+  c->d_cb0.release();
+  c->d_cb1.release();
+  if (prec == TEM_FP32_IR && c->aux) {
+    tem_status s = factor_nodal(c);
     if (s != TEM_OK) {
       hipEventDestroy(e0);
       hipEventDestroy(e1);
@@ -1093,6 +1328,7 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->factor_ms = ms;
+  spans_collect(c);
   int flags[4];
   HIPCHK(hipMemcpy(flags, c->d_flags.p, sizeof(flags), hipMemcpyDeviceToHost), "flags d2h");
   c->n_tiny = flags[1];
@@ -1120,7 +1356,7 @@ tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
   hipStream_t st = c->stream;
   c->solved = false;
   TRY(ensure_vec(c, c->d_fnew, sizeof(double) * (size_t)N * S, "alloc f"));
-  HIPCHK(launch_gather_rhs(st, N, S, c->mt.n_edges, c->d_row_edge.as<int32_t>(), F,
+  HIPCHK(launch_gather_rhs(st, N, S, c->mt.n_edges, c->ed.d_row_ent.as<int32_t>(), F,
                            c->d_fnew.as<double>()),
          "gather f");
   TRY(ensure_vec(c, c->d_g, sizeof(cpx<double>) * (size_t)c->npole * N * S, "alloc g"));
@@ -1138,10 +1374,11 @@ tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
   hipEventDestroy(e1);
   if (s != TEM_OK) return s;
   c->solve_ms = ms;
+  spans_collect(c);
   c->last_solves = res.solves;
   c->S = S;
   if (G) {
-    HIPCHK(launch_scatter_solution(st, N, c->npole, S, c->mt.n_edges, c->d_edge_new.as<int32_t>(),
+    HIPCHK(launch_scatter_solution(st, N, c->npole, S, c->mt.n_edges, c->ed.d_ent_new.as<int32_t>(),
                                    c->d_g.as<cpx<double>>(), (cpx<double> *)G),
            "scatter g");
   }
@@ -1175,7 +1412,7 @@ static tem_status set_survey(tem_ctx *c, int R, const int64_t *q_ptr, const int3
       if (q_col[t] < 0 || q_col[t] >= c->mt.n_edges)
         return fail(c, TEM_EINVAL, "tem_forward: receiver column out of range");
       if (!std::isfinite(q_val[t])) return fail(c, TEM_EINVAL, "tem_forward: non-finite Q value");
-      int32_t q = c->pat.edge_new[q_col[t]];
+      int32_t q = c->ed.pat.edge_new[q_col[t]];
       if (q < 0) continue;   // boundary edge: the field is zero there
       qc.push_back(q);
       qv.push_back(q_val[t]);
@@ -1229,7 +1466,7 @@ tem_status tem_jvp(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *i
   HIPCHK(launch_param_scatter(st, (int)c->params.size(), c->d_params.as<int32_t>(), v,
                               c->d_sigma.as<double>(), c->mt.n_cells, c->v_vs.as<double>()),
          "param scatter");
-  HIPCHK(launch_jv_rhs(st, N, m, S, c->mt.nx, c->mt.ny, c->mt.nz, c->d_row_edge.as<int32_t>(),
+  HIPCHK(launch_jv_rhs(st, N, m, S, c->mt.nx, c->mt.ny, c->mt.nz, c->ed.d_row_ent.as<int32_t>(),
                        c->d_cell_new.as<int32_t>(), c->v_vs.as<double>(), c->d_Me.as<double>(),
                        c->d_xi.as<double>(), c->d_g.as<cpx<double>>(), c->v_rhs.as<cpx<double>>()),
          "jv rhs");
@@ -1240,6 +1477,7 @@ tem_status tem_jvp(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *i
                               c->d_alpha.as<cpx<double>>(), c->v_lam.as<cpx<double>>(), jv),
          "jv time assembly");
   HIPCHK(hipStreamSynchronize(st), "jvp sync");
+  spans_collect(c);
   fill_stats(res, stats);
   c->last_solves = res.solves;
   if (res.unconverged) return fail(c, TEM_ENOCONV, "tem_jvp: refinement did not converge");
@@ -1270,9 +1508,18 @@ tem_status tem_vjp(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *
                            c->v_lam.as<cpx<double>>(), jtw),
          "jtw reduce");
   HIPCHK(hipStreamSynchronize(st), "vjp sync");
+  spans_collect(c);
   fill_stats(res, stats);
   c->last_solves = res.solves;
   if (res.unconverged) return fail(c, TEM_ENOCONV, "tem_vjp: refinement did not converge");
+  return TEM_OK;
+}
+
+tem_status tem_set_profiling(tem_ctx *c, int32_t enable) {
+  if (!c) return TEM_EINVAL;
+  c->profile = enable != 0;
+  c->upd_ms = c->upd_flops = c->sweep_ms = c->sweep_bytes = 0;
+  c->upd_launches = c->sweeps = 0;
   return TEM_OK;
 }
 
@@ -1284,13 +1531,19 @@ tem_status tem_get_stats(const tem_ctx *c, tem_stats *out) {
   out->group_size = c->group_size;
   out->precision = (int32_t)c->prec;
   out->factor_bytes = (int64_t)c->d_factor.bytes;
-  out->workspace_bytes = (int64_t)(c->w_x.bytes + c->w_t.bytes + c->w_w0.bytes + c->w_w1.bytes +
+  out->workspace_bytes = (int64_t)(c->w_x.bytes + c->ed.w_t.bytes + c->ed.w_w0.bytes + c->ed.w_w1.bytes +
                                    c->v_r.bytes + c->v_z.bytes + c->v_w.bytes + c->v_basis.bytes +
                                    c->v_rhs.bytes + c->v_lam.bytes);
   out->n_tiny_pivots = c->n_tiny;
   out->last_solves = c->last_solves;
   out->factor_ms = c->factor_ms;
   out->solve_ms = c->solve_ms;
+  out->update_ms = c->upd_ms;
+  out->update_flops = c->upd_flops;
+  out->update_launches = c->upd_launches;
+  out->sweep_ms = c->sweep_ms;
+  out->sweep_bytes = c->sweep_bytes;
+  out->sweeps = c->sweeps;
   return TEM_OK;
 }
 

@@ -205,4 +205,18 @@ hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int64_t N,
                              const double *Me, const double *xi, const cpx<double> *g,
                              const cpx<double> *lam, double *out);
 
+// ------------------------------------------------ nodal gradient space
+// G^T M G on interior nodes (row-owner gather over the <= 8 cells of a node)
+hipError_t launch_assemble_nodal(hipStream_t st, int64_t Nn, const int64_t *rowptr,
+                                 const int32_t *col, const int32_t *row_node,
+                                 const int32_t *node_new, int nx, int ny, int nz, const double *Le,
+                                 const double *sigma, double *Lv);
+// out = G^T r  (edge vectors [pole][N][S] -> nodal vectors [pole][Nn][S])
+hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int64_t N,
+                         const int32_t *node_edges, const cpx<double> *r, cpx<double> *out);
+// z += coef[pole] * G y
+hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int64_t Nn,
+                           const int32_t *edge_nodes, const cpx<double> *coef,
+                           const cpx<double> *y, cpx<double> *z);
+
 }  // namespace tem

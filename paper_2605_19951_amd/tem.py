@@ -23,7 +23,8 @@ _STATUS = {0: "TEM_OK", -1: "TEM_EINVAL", -2: "TEM_ENOMEM", -3: "TEM_EDEVICE", -
 # every entry point declared in include/tem.h
 EXPORTS = ["tem_create", "tem_destroy", "tem_last_error", "tem_assemble", "tem_set_model",
            "tem_export_operators", "tem_analyse", "tem_symbolic_host", "tem_factor_poles",
-           "tem_solve_poles", "tem_forward", "tem_jvp", "tem_vjp", "tem_get_stats"]
+           "tem_solve_poles", "tem_forward", "tem_jvp", "tem_vjp", "tem_get_stats",
+           "tem_set_profiling"]
 
 
 class TemError(RuntimeError):
@@ -69,7 +70,10 @@ class Stats(C.Structure):
     _fields_ = [("n_poles", C.c_int32), ("n_groups", C.c_int32), ("group_size", C.c_int32),
                 ("precision", C.c_int32), ("factor_bytes", C.c_int64),
                 ("workspace_bytes", C.c_int64), ("n_tiny_pivots", C.c_int32),
-                ("last_solves", C.c_int32), ("factor_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("last_solves", C.c_int32), ("factor_ms", C.c_double), ("solve_ms", C.c_double),
+                ("update_ms", C.c_double), ("update_flops", C.c_double),
+                ("update_launches", C.c_int64), ("sweep_ms", C.c_double),
+                ("sweep_bytes", C.c_double), ("sweeps", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -104,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "tem_jvp": ([vp, dp, dp, C.POINTER(IrOpts), C.POINTER(IrStats)], C.c_int),
         "tem_vjp": ([vp, dp, dp, C.POINTER(IrOpts), C.POINTER(IrStats)], C.c_int),
         "tem_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
+        "tem_set_profiling": ([vp, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -289,6 +294,9 @@ class Tem:
         self._chk(self.L.tem_vjp(self.h, _dev(w, "float64", self._dshape()),
                                  _dev(jtw, "float64", (self.n_params,)), self._ir(ir), C.byref(s)))
         return dict(iters=it.reshape(self.npole, self.S), rel=rr.reshape(self.npole, self.S))
+
+    def set_profiling(self, enable=True):
+        self._chk(self.L.tem_set_profiling(self.h, 1 if enable else 0))
 
     def stats(self):
         s = Stats()
