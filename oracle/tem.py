@@ -5,7 +5,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 * ``solve_poles``: g_is = (K - xi_i M)^{-1} f_s, the solution of each shifted
   system (Algorithm 1; "derivative of the inverse" subsection defines g_i the
   same way).  The plain definition is the solution of a linear system, so a
-  library sparse LU (SuperLU, complex128) is the step that computes it.
+  library sparse LU (SuperLU, complex128) is the step that computes it, on
+  the matrix permuted by the oracle's own nested-dissection ordering:
+  g = P^T (P A P^T)^{-1} P f.
 * ``fields`` / ``data``: u(t_j) = 2 Re sum_i alpha_i^[j] g_i (the partial
   fraction form of the rational approximation) and d_j = Q u(t_j) (section
   "The Inverse Problem"), data stacked as d[s, j, r].
@@ -39,6 +41,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .fem import HexMesh, assemble, element_mass_unit
+from .ordering import nested_dissection
 
 MU0 = 4.0e-7 * math.pi
 
@@ -87,13 +90,26 @@ class OracleTEM:
     def A(self, i):
         return (self.K - self.xi[i] * self.M).astype(complex).tocsc()
 
+    def ordering(self):
+        if getattr(self, "_perm", None) is None:
+            self._perm = nested_dissection(self.mesh)[1]
+        return self._perm
+
     def lu(self, i):
         if i not in self._lu:
-            self._lu[i] = spla.splu(self.A(i))
+            p = self.ordering()
+            Ap = self.A(i)[p][:, p].tocsc()
+            self._lu[i] = spla.splu(Ap, permc_spec="NATURAL", diag_pivot_thresh=0.0,
+                                    options=dict(SymmetricMode=True))
         return self._lu[i]
 
     def solve(self, i, B):
-        return self.lu(i).solve(np.asarray(B, complex))
+        p = self.ordering()
+        B = np.asarray(B, complex)
+        x = self.lu(i).solve(B[p])
+        out = np.empty_like(x)
+        out[p] = x
+        return out
 
     # ---------------------------------------------------------------
     def solve_poles(self):
