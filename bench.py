@@ -1,0 +1,178 @@
+"""Benchmark of the pole-shifted TEM hot path on one MI355X.
+
+One step = one pass of the whole hot path over the 64^3 precision workload
+(762,048 unknowns, 16 poles, 8 loop sources, 60 times, 16 receivers):
+assemble M(sigma) on the device, factor all 16 shifted matrices, solve all
+poles x sources with FP64 refinement to 1e-10, assemble the data at all
+times, then one J v and one J^T w through the cached factors.
+
+Reported (BASELINE metric "all-pole factor+solve s & J^T v/s at 64^3, FP32+IR
+vs FP64, same GPU"): value = factor+solve seconds of the FP32+IR path
+(median over the timed steps); J^T v per second and the FP64 figures are in
+``phases``.  The roofline object covers the dominant kernel (the MFMA front
+update, FP32) from HIP events inside the library; the CPU baseline is the
+FP64 oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps 1] [--warmup 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "all-pole factor+solve s & Jᵀv/s at 64³ edge mesh, FP32+IR vs FP64, same GPU"
+PEAK_FP32 = 157.3e12      # dense FP32 MFMA, MI355X
+PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12
+
+
+def run_precision(t, wl, prec, steps, warmup, torch, dev, F, v, w):
+    import numpy as np
+    K, R = len(wl.poles.t), wl.rx.n
+    d = torch.zeros((wl.S, K, R), dtype=torch.float64, device=dev)
+    jv = torch.zeros_like(d)
+    jtw = torch.zeros(len(wl.params), dtype=torch.float64, device=dev)
+    sigma = torch.tensor(wl.sigma, device=dev)
+    me = wl.mesh
+    rec = []
+    for it in range(warmup + steps):
+        timed = it >= warmup
+        t.set_profiling(timed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.assemble(me.nx, me.ny, me.nz, me.h, 4e-7 * math.pi, sigma, wl.params)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        t.factor_poles(wl.poles.xi, prec)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ir = t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        t.jvp(v, jv)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        t.vjp(w, jtw)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        st = t.stats()
+        if timed:
+            rec.append(dict(assemble=t1 - t0, factor=t2 - t1, forward=t3 - t2, jvp=t4 - t3,
+                            vjp=t5 - t4, step=t5 - t0, solves=int(ir["iters"].max()), stats=st))
+        print("# prec=%d step %d: assemble %.3f factor %.3f forward %.3f jvp %.3f vjp %.3f s"
+              % (prec, it, t1 - t0, t2 - t1, t3 - t2, t4 - t3, t5 - t4), file=sys.stderr, flush=True)
+    med = lambda k: sorted(r[k] for r in rec)[len(rec) // 2]  # noqa: E731
+    out = dict(assemble_s=med("assemble"), factor_s=med("factor"), forward_s=med("forward"),
+               jvp_s=med("jvp"), vjp_s=med("vjp"), step_s=med("step"),
+               factor_solve_s=med("factor") + med("forward"), jtv_per_s=1.0 / med("vjp"),
+               ir_solves=rec[-1]["solves"], groups=rec[-1]["stats"]["n_groups"],
+               group_size=rec[-1]["stats"]["group_size"],
+               factor_gb=rec[-1]["stats"]["factor_bytes"] / 1e9)
+    st = rec[-1]["stats"]
+    out["update_ms"] = st["update_ms"]
+    out["update_flops"] = st["update_flops"]
+    out["update_launches"] = st["update_launches"]
+    out["sweep_ms"] = st["sweep_ms"]
+    out["sweep_bytes"] = st["sweep_bytes"]
+    out["sweeps"] = st["sweeps"]
+    return out, d.cpu().numpy(), jtw.cpu().numpy()
+
+
+def cpu_baseline(flops64):
+    """The FP64 oracle on the host: factor + solve of one pole of the same
+    generator on a 32^3 mesh (8 sources), scaled to all 16 poles at 64^3 by
+    the ratio of multifrontal factor flops."""
+    import numpy as np
+    import tem_inputs as ti
+    from oracle.ordering import analyse, factor_flops
+    from oracle.tem import OracleTEM
+    wl = ti.smooth_workload(32, 4, S=8, m=16, K=60, g=4, seed=3, name="hex32_sample")
+    me = wl.mesh
+    o = OracleTEM(me.nx, me.ny, me.nz, me.h, wl.sigma, wl.F, wl.rx.ptr, wl.rx.col, wl.rx.val,
+                  wl.poles.xi, wl.poles.alpha, wl.params)
+    o.ordering()
+    t0 = time.perf_counter()
+    o.solve(0, o.F)
+    dt = time.perf_counter() - t0
+    nodes, _, _ = analyse(o.mesh)
+    f32 = factor_flops(nodes)
+    scale = 16.0 * flops64 / f32
+    return dict(value=dt * scale, unit="s", cores=1, kind="oracle",
+                sample="factor+solve of 1 pole x 8 sources on a 32^3 mesh of the same generator "
+                       "(%.1f s measured), scaled x%.0f (16 poles x factor-flop ratio 64^3/32^3)"
+                       % (dt, scale))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the pole-sharded multi-GPU path is not part of this "
+              "build (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import tem_inputs as ti
+    from paper_2605_19951_amd import FP32_IR, FP64, Tem
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wl = ti.workload(2)
+    me = wl.mesh
+    t = Tem(0)
+    t.assemble(me.nx, me.ny, me.nz, me.h, 4e-7 * math.pi, torch.tensor(wl.sigma, device=dev),
+               wl.params)
+    ta = time.perf_counter()
+    info = t.analyse()
+    analyse_s = time.perf_counter() - ta
+    F = torch.tensor(wl.F.T.copy(), device=dev)
+    rng = np.random.default_rng(7)
+    v = torch.tensor(rng.standard_normal(len(wl.params)), device=dev)
+    w = torch.tensor(rng.standard_normal((wl.S, len(wl.poles.t), wl.rx.n)), device=dev)
+    phases = {}
+    res32, d32, g32 = run_precision(t, wl, FP32_IR, args.steps, args.warmup, torch, dev, F, v, w)
+    phases["fp32_ir"] = res32
+    acc = None
+    if not args.fp32_only:
+        res64, d64, g64 = run_precision(t, wl, FP64, args.steps, args.warmup, torch, dev, F, v, w)
+        phases["fp64"] = res64
+        acc = dict(data_rel_fp32_vs_fp64=float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
+                   jtw_rel_fp32_vs_fp64=float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)))
+    t.close()
+    ach = res32["update_flops"] / (res32["update_ms"] * 1e-3) if res32["update_ms"] > 0 else 0.0
+    roof = dict(bound="mfma", kernel="k_front_update<float>", achieved=ach / 1e12,
+                peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=ach / PEAK_FP32, traffic=None,
+                launches=res32["update_launches"])
+    sweep_bw = res32["sweep_bytes"] / (res32["sweep_ms"] * 1e-3) if res32["sweep_ms"] > 0 else 0.0
+    line = dict(metric=METRIC, value=res32["factor_solve_s"], unit="s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=res32["step_s"] * 1e3,
+                higher_is_better=False, scaling="weak", vs_baseline=None,
+                dtype="c64 factors + f64 refinement", data="synthetic",
+                config=dict(workload=wl.name, mesh="64x64x64", h_m=25.0, n_unknowns=info["n_unknowns"],
+                            poles=len(wl.poles.xi), sources=wl.S, times=len(wl.poles.t),
+                            receivers=wl.rx.n, params=len(wl.params), ir_rtol=1e-10,
+                            flops_per_pole=info["flops_per_pole"], analyse_s=analyse_s),
+                phases=phases, accuracy=acc, roofline=roof,
+                sweep=dict(bound="hbm", achieved=sweep_bw / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                           frac=sweep_bw / PEAK_HBM))
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(info["flops_per_pole"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

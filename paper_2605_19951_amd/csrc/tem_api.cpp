@@ -997,9 +997,14 @@ tem_status factor_nodal(tem_ctx *c) {
   const size_t cbb = sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.cb_stride, 1);
   HIPCHK(a0.alloc(cbb), "alloc nodal cb");
   HIPCHK(a1.alloc(cbb), "alloc nodal cb");
-  TRY(factor_group<double>(c, nd, c->d_nfactor.as<cpx<double>>(), c->d_nxi.as<double>(),
-                           c->d_Ln.as<double>(), c->d_Lzero.as<double>(), 1, a0.as<cpx<double>>(),
-                           a1.as<cpx<double>>()));
+  // the nodal factor is not part of the timed front-update figures
+  const bool prof = c->profile;
+  c->profile = false;
+  tem_status fs = factor_group<double>(c, nd, c->d_nfactor.as<cpx<double>>(), c->d_nxi.as<double>(),
+                                       c->d_Ln.as<double>(), c->d_Lzero.as<double>(), 1,
+                                       a0.as<cpx<double>>(), a1.as<cpx<double>>());
+  c->profile = prof;
+  TRY(fs);
   // coefficients -1/xi_p of the correction
   std::vector<double> coef(2 * c->npole);
   for (int p = 0; p < c->npole; ++p) {
