@@ -23,15 +23,20 @@ __device__ __forceinline__ const cpx<T> *col_ptr(const cpx<T> *P, int64_t n, int
 }
 
 // ------------------------------------------------------------ forward tri
+// Solves the diagonal blocks of columns [cb, ce), ce = min(cb + BB, k), and
+// updates only the rows inside that range; cb == 0 first adds the children's
+// update rows to all top rows.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl_nodes, int S,
                                                  int64_t N, const cpx<T> *factor,
                                                  int64_t f_stride, cpx<T> *x,
-                                                 const cpx<T> *w_child, int64_t w_stride) {
+                                                 const cpx<T> *w_child, int64_t w_stride,
+                                                 int64_t cb, int64_t BB) {
   const int s = lvl_nodes[blockIdx.x];
   const int p = blockIdx.y;
   const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
-  if (k == 0) return;
+  if (k == 0 || cb >= k) return;
+  const int64_t ce = min(k, cb + BB);
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
   cpx<T> *X = x + ((int64_t)p * N + first) * S;     // rows of this front's columns
   const int tid = threadIdx.x;
@@ -41,7 +46,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
   const int c0 = ft.child0[s], c1 = ft.child1[s];
   const cpx<T> *W0 = c0 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c0] * S : nullptr;
   const cpx<T> *W1 = c1 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c1] * S : nullptr;
-  if (c0 >= 0) {
+  if (c0 >= 0 && cb == 0) {
     for (int64_t idx = tid; idx < k * S; idx += blockDim.x) {
       const int64_t q = idx / S, c = idx % S;
       cpx<T> v = X[idx];
@@ -54,7 +59,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
   __shared__ cpx<T> V[NB][16];
   __shared__ cpx<T> Y[NB][16];
   __shared__ cpx<T> Lt[NB][RTT + 1];   // Lt[l][i] = L(r0 + i, jb + l)
-  for (int64_t jb = 0; jb < k; jb += NB) {
+  for (int64_t jb = cb; jb < ce; jb += NB) {
     const int w = (int)min((int64_t)NB, k - jb);
     int64_t ld;
     const cpx<T> *Lc = col_ptr(P, n, jb, ld);   // column jb; column jb+l at Lc + l*ld
@@ -74,9 +79,9 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
       X[jb * S + idx] = acc;
     }
     __syncthreads();
-    // rows below inside L11: X[r] -= sum_l L(r, jb+l) Y[l]
-    for (int64_t rc = jb + w; rc < k; rc += RTT) {
-      const int nr = (int)min((int64_t)RTT, k - rc);
+    // rows below inside the range: X[r] -= sum_l L(r, jb+l) Y[l]
+    for (int64_t rc = jb + w; rc < ce; rc += RTT) {
+      const int nr = (int)min((int64_t)RTT, ce - rc);
       for (int idx = tid; idx < RTT * w; idx += blockDim.x) {
         const int i = idx % RTT, l = idx / RTT;
         Lt[l][i] = (i < nr) ? Lc[(int64_t)l * ld + rc + i] : czero<T>();
@@ -97,10 +102,76 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
 template <typename T>
 hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
-                          cpx<T> *x, const cpx<T> *w_child, int64_t w_stride) {
+                          cpx<T> *x, const cpx<T> *w_child, int64_t w_stride, int64_t cb,
+                          int64_t BB) {
   if (n_nodes <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
-                     factor, f_stride, x, w_child, w_stride);
+                     factor, f_stride, x, w_child, w_stride, cb, BB);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- forward rows
+// X[r] -= sum_{j in [cb, ce)} L(r, j) y_j for L11 rows r in [ce, k)
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_rows(FrontTab ft, const int32_t *lvl_nodes, int S,
+                                                  int64_t N, const cpx<T> *factor,
+                                                  int64_t f_stride, cpx<T> *x, int64_t cb,
+                                                  int64_t BB) {
+  const int s = lvl_nodes[blockIdx.y];
+  const int p = blockIdx.z;
+  const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
+  const int64_t ce = min(k, cb + BB);
+  const int64_t a0 = ce + (int64_t)blockIdx.x * RT;
+  if (cb >= k || a0 >= k) return;
+  const int na = (int)min((int64_t)RT, k - a0);
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;
+  const int tid = threadIdx.x;
+  cpx<T> acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = czero<T>();
+  __shared__ cpx<T> Lt[NB][RT + 1];
+  __shared__ cpx<T> Y[NB][16];
+  for (int64_t jb = cb; jb < ce; jb += NB) {
+    const int w = (int)min((int64_t)NB, k - jb);
+    int64_t ld;
+    const cpx<T> *Lc = col_ptr(P, n, jb, ld);
+    __syncthreads();
+    for (int idx = tid; idx < RT * w; idx += blockDim.x) {
+      const int i = idx % RT, l = idx / RT;
+      Lt[l][i] = (i < na) ? Lc[(int64_t)l * ld + a0 + i] : czero<T>();
+    }
+    for (int idx = tid; idx < w * S; idx += blockDim.x) Y[idx / S][idx % S] = X[jb * S + idx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < na * S) {
+        const int i = idx / S, c = idx % S;
+        cpx<T> sacc = acc[q];
+        for (int l = 0; l < w; ++l) sacc = cfma(Lt[l][i], Y[l][c], sacc);
+        acc[q] = sacc;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q;
+    if (idx < na * S) {
+      cpx<T> *o = X + a0 * S + idx;
+      *o = csub(*o, acc[q]);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_rows, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB) {
+  if (n_nodes <= 0 || max_rows <= 0) return hipSuccess;
+  dim3 grid((max_rows + RT - 1) / RT, n_nodes, npole);
+  hipLaunchKernelGGL(k_fwd_rows<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
+                     x, cb, BB);
   return hipGetLastError();
 }
 
@@ -141,17 +212,30 @@ __global__ __launch_bounds__(256) void k_fwd_rect(FrontTab ft, const int32_t *lv
   }
   __shared__ cpx<T> Lt[NB][RT + 1];
   __shared__ cpx<T> Y[NB][16];
-  for (int64_t jb = 0; jb < k; jb += NB) {
+  // register prefetch of the next 64 x 32 panel tile (8 elements per thread)
+  cpx<T> pre[8];
+  auto fetch = [&](int64_t jb) {
     const int w = (int)min((int64_t)NB, k - jb);
     int64_t ld;
     const cpx<T> *Lc = col_ptr(P, n, jb, ld);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q, i = idx % RT, l = idx / RT;
+      pre[q] = (i < na && l < w) ? Lc[(int64_t)l * ld + k + a0 + i] : czero<T>();
+    }
+  };
+  if (k > 0) fetch(0);
+  for (int64_t jb = 0; jb < k; jb += NB) {
+    const int w = (int)min((int64_t)NB, k - jb);
     __syncthreads();
-    for (int idx = tid; idx < RT * w; idx += blockDim.x) {
-      const int i = idx % RT, l = idx / RT;
-      Lt[l][i] = (i < na) ? Lc[(int64_t)l * ld + k + a0 + i] : czero<T>();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q;
+      Lt[idx / RT][idx % RT] = pre[q];
     }
     for (int idx = tid; idx < w * S; idx += blockDim.x) Y[idx / S][idx % S] = X[jb * S + idx];
     __syncthreads();
+    if (jb + NB < k) fetch(jb + NB);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
@@ -210,18 +294,39 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
   cpx<T> acc[2];
   acc[0] = czero<T>();
   acc[1] = czero<T>();
+  // register prefetch of the next 64-row tile: 8 panel elements and up to
+  // 4 x-values per thread
+  cpx<T> pre[8], prx[4];
+  auto fetch = [&](int64_t ac) {
+    const int na = (int)min((int64_t)RT, u - ac);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q, i = idx % RT, l = idx / RT;
+      pre[q] = (i < na && l < w) ? Lc[(int64_t)l * ld + k + ac + i] : czero<T>();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int i = idx / S, c = idx % S;
+      prx[q] = (idx < na * S) ? Xp[(int64_t)rows[ac + i] * S + c] : czero<T>();
+    }
+  };
+  if (u > 0) fetch(0);
   for (int64_t ac = 0; ac < u; ac += RT) {
     const int na = (int)min((int64_t)RT, u - ac);
     __syncthreads();
-    for (int idx = tid; idx < RT * w; idx += blockDim.x) {
-      const int i = idx % RT, l = idx / RT;
-      Lt[l][i] = (i < na) ? Lc[(int64_t)l * ld + k + ac + i] : czero<T>();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q;
+      Lt[idx / RT][idx % RT] = pre[q];
     }
-    for (int idx = tid; idx < na * S; idx += blockDim.x) {
-      const int i = idx / S, c = idx % S;
-      Xt[i][c] = Xp[(int64_t)rows[ac + i] * S + c];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < na * S) Xt[idx / S][idx % S] = prx[q];
     }
     __syncthreads();
+    if (ac + RT < u) fetch(ac + RT);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int idx = tid + 256 * q;
@@ -256,15 +361,21 @@ hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 // x_s = L11^{-T} (D^{-1} y_s - t_s), blocks from the last to the first
 // (left-looking: each block first gathers the contributions of the rows
 // below it inside L11).  With u == 0 the t term is absent.
+// Blocks of columns [cb, ce) from the last to the first.  With init the
+// right-hand side of each block is D^{-1} y - t (the whole triangle in one
+// launch when cb = 0 and BB >= k); without, X already holds that value
+// minus the contributions of the rows below ce (k_bwd_init + k_bwd_cols).
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl_nodes, int S,
                                                  int64_t N, const cpx<T> *factor,
                                                  int64_t f_stride, cpx<T> *x, const cpx<T> *t,
-                                                 int64_t t_stride) {
+                                                 int64_t t_stride, int64_t cb, int64_t BB,
+                                                 int init) {
   const int s = lvl_nodes[blockIdx.x];
   const int p = blockIdx.y;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
-  if (k == 0) return;
+  if (k == 0 || cb >= k) return;
+  const int64_t ce = min(k, cb + BB);
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
   cpx<T> *X = x + ((int64_t)p * N + first) * S;
   const cpx<T> *Tv = t + (int64_t)p * t_stride + first * S;
@@ -273,8 +384,8 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
   __shared__ cpx<T> V[NB][16];
   __shared__ cpx<T> Lt[NB][RTT + 1];
   __shared__ cpx<T> Xt[RTT][16];
-  const int64_t nblk = (k + NB - 1) / NB;
-  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+  const int64_t b_first = cb / NB, b_last = (ce + NB - 1) / NB - 1;
+  for (int64_t bi = b_last; bi >= b_first; --bi) {
     const int64_t jb = bi * NB;
     const int w = (int)min((int64_t)NB, k - jb);
     int64_t ld;
@@ -282,9 +393,9 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
     cpx<T> acc[2];
     acc[0] = czero<T>();
     acc[1] = czero<T>();
-    // contributions of the already solved rows jb+w .. k-1
-    for (int64_t rc = jb + w; rc < k; rc += RTT) {
-      const int nr = (int)min((int64_t)RTT, k - rc);
+    // contributions of the already solved rows jb+w .. ce-1
+    for (int64_t rc = jb + w; rc < ce; rc += RTT) {
+      const int nr = (int)min((int64_t)RTT, ce - rc);
       __syncthreads();
       for (int idx = tid; idx < RTT * w; idx += blockDim.x) {
         const int i = idx % RTT, l = idx / RTT;
@@ -313,9 +424,12 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
       const int idx = tid + 256 * q;
       if (idx < w * S) {
         const int l = idx / S, c = idx % S;
-        const cpx<T> d = Lc[(int64_t)l * ld + jb + l];
-        cpx<T> v = cmul(X[jb * S + idx], cinv(d));
-        if (u > 0) v = csub(v, Tv[jb * S + idx]);
+        cpx<T> v = X[jb * S + idx];
+        if (init) {
+          const cpx<T> d = Lc[(int64_t)l * ld + jb + l];
+          v = cmul(v, cinv(d));
+          if (u > 0) v = csub(v, Tv[jb * S + idx]);
+        }
         V[l][c] = csub(v, acc[q]);
       }
     }
@@ -334,17 +448,124 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
 template <typename T>
 hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
-                          cpx<T> *x, const cpx<T> *t, int64_t t_stride) {
+                          cpx<T> *x, const cpx<T> *t, int64_t t_stride, int64_t cb, int64_t BB,
+                          int init) {
   if (n_nodes <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
-                     factor, f_stride, x, t, t_stride);
+                     factor, f_stride, x, t, t_stride, cb, BB, init);
   return hipGetLastError();
 }
+
+// ------------------------------------------------------ backward init
+// X[j] = y_j / d_j - t_j for all columns of the front
+template <typename T>
+__global__ void k_bwd_init(FrontTab ft, const int32_t *lvl_nodes, int S, int64_t N,
+                           const cpx<T> *factor, int64_t f_stride, cpx<T> *x, const cpx<T> *t,
+                           int64_t t_stride) {
+  const int s = lvl_nodes[blockIdx.y];
+  const int p = blockIdx.z;
+  const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= k * S) return;
+  const int64_t j = idx / S;
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  const cpx<T> d = P[panel_elem(n, j, j)];
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;
+  cpx<T> v = cmul(X[idx], cinv(d));
+  if (u > 0) v = csub(v, t[(int64_t)p * t_stride + first * S + idx]);
+  X[idx] = v;
+}
+
+template <typename T>
+hipError_t launch_bwd_init(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_k, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, cpx<T> *x, const cpx<T> *t, int64_t t_stride) {
+  if (n_nodes <= 0 || max_k <= 0) return hipSuccess;
+  dim3 grid(((int64_t)max_k * S + 255) / 256, n_nodes, npole);
+  hipLaunchKernelGGL(k_bwd_init<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
+                     x, t, t_stride);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ backward cols
+// X[j] -= sum_{r in [cb, ce)} L(r, j) x_r for the column block of j < cb
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_cols(FrontTab ft, const int32_t *lvl_nodes, int S,
+                                                  int64_t N, const cpx<T> *factor,
+                                                  int64_t f_stride, cpx<T> *x, int64_t cb,
+                                                  int64_t BB) {
+  const int s = lvl_nodes[blockIdx.y];
+  const int p = blockIdx.z;
+  const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
+  const int64_t jb = (int64_t)blockIdx.x * NB;
+  if (cb >= k || jb >= cb) return;
+  const int64_t ce = min(k, cb + BB);
+  const int w = (int)min((int64_t)NB, cb - jb);
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;
+  const int tid = threadIdx.x;
+  int64_t ld;
+  const cpx<T> *Lc = col_ptr(P, n, jb, ld);
+  __shared__ cpx<T> Lt[NB][RT + 1];
+  __shared__ cpx<T> Xt[RT][16];
+  cpx<T> acc[2];
+  acc[0] = czero<T>();
+  acc[1] = czero<T>();
+  for (int64_t rc = cb; rc < ce; rc += RT) {
+    const int nr = (int)min((int64_t)RT, ce - rc);
+    __syncthreads();
+    for (int idx = tid; idx < RT * w; idx += blockDim.x) {
+      const int i = idx % RT, l = idx / RT;
+      Lt[l][i] = (i < nr) ? Lc[(int64_t)l * ld + rc + i] : czero<T>();
+    }
+    for (int idx = tid; idx < nr * S; idx += blockDim.x) Xt[idx / S][idx % S] = X[rc * S + idx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < w * S) {
+        const int l = idx / S, c = idx % S;
+        cpx<T> sacc = acc[q];
+        for (int i = 0; i < nr; ++i) sacc = cfma(Lt[l][i], Xt[i][c], sacc);
+        acc[q] = sacc;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int idx = tid + 256 * q;
+    if (idx < w * S) {
+      cpx<T> *o = X + jb * S + idx;
+      *o = csub(*o, acc[q]);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int64_t cb, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, cpx<T> *x, int64_t BB) {
+  if (n_nodes <= 0 || cb <= 0) return hipSuccess;
+  dim3 grid((unsigned)((cb + NB - 1) / NB), n_nodes, npole);
+  hipLaunchKernelGGL(k_bwd_cols<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
+                     x, cb, BB);
+  return hipGetLastError();
+}
+
 
 #define TEM_INST(T)                                                                              \
   template hipError_t launch_fwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
                                         int64_t, const cpx<T> *, int64_t, cpx<T> *,              \
-                                        const cpx<T> *, int64_t);                                \
+                                        const cpx<T> *, int64_t, int64_t, int64_t);              \
+  template hipError_t launch_fwd_rows<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
+                                         int, int64_t, const cpx<T> *, int64_t, cpx<T> *,        \
+                                         int64_t, int64_t);                                      \
+  template hipError_t launch_bwd_init<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
+                                         int, int64_t, const cpx<T> *, int64_t, cpx<T> *,        \
+                                         const cpx<T> *, int64_t);                               \
+  template hipError_t launch_bwd_cols<T>(hipStream_t, FrontTab, const int32_t *, int, int64_t,    \
+                                         int, int, int64_t, const cpx<T> *, int64_t, cpx<T> *,   \
+                                         int64_t);                                               \
   template hipError_t launch_fwd_rect<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, const cpx<T> *,  \
                                          const cpx<T> *, cpx<T> *, int64_t);                     \
@@ -353,7 +574,7 @@ hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
                                          cpx<T> *, int64_t);                                     \
   template hipError_t launch_bwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
                                         int64_t, const cpx<T> *, int64_t, cpx<T> *,              \
-                                        const cpx<T> *, int64_t);
+                                        const cpx<T> *, int64_t, int64_t, int64_t, int);
 TEM_INST(float)
 TEM_INST(double)
 #undef TEM_INST

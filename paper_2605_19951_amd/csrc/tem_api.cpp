@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -125,6 +126,8 @@ struct tem_ctx {
   DBuf d_Ln, d_Lzero, d_nfactor, d_nxi, d_edge_nodes, d_node_edges, d_nvec, d_ncoef;
   bool nodal_ready = false;
   bool aux = true;                 // gradient-space correction in FP32 refinement
+  int64_t sweep_bb = 256;          // big column block of the wide-front sweeps
+  int64_t sweep_big_limit = 1024;  // fronts x poles below which a level is "wide"
   // factors
   int npole = 0;
   tem_precision prec = TEM_FP64;
@@ -553,11 +556,30 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
   const int64_t ws = std::max<int64_t>(mf.w_rows_max, 1) * S;
   cpx<T> *t = mf.w_t.as<cpx<T>>();
   const int nl = (int)mf.levels.size();
+  // Levels whose fronts are few and wide are walked in big column blocks:
+  // one workgroup per front solves a BB-wide diagonal block, then many
+  // workgroups apply it to the remaining rows (forward) or columns (backward).
+  const int64_t BB = c->sweep_bb;
+  auto big = [&](const LevelInfo &li) {
+    return li.max_k > BB && (int64_t)li.n * npole < c->sweep_big_limit;
+  };
   for (int L = nl - 1; L >= 0; --L) {
     const LevelInfo &li = mf.levels[L];
     const int32_t *ln = lvl_ptr(mf, li);
-    HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, W[(L + 1) & 1], ws),
-           "fwd tri");
+    if (!big(li)) {
+      HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, W[(L + 1) & 1], ws,
+                               0, (int64_t)1 << 40),
+             "fwd tri");
+    } else {
+      for (int64_t cb = 0; cb < li.max_k; cb += BB) {
+        HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, W[(L + 1) & 1],
+                                 ws, cb, BB),
+               "fwd tri");
+        HIPCHK(launch_fwd_rows<T>(st, ft, ln, li.n, (int)std::max<int64_t>(0, li.max_k - cb - BB),
+                                  npole, S, N, F, f_stride, x, cb, BB),
+               "fwd rows");
+      }
+    }
     HIPCHK(launch_fwd_rect<T>(st, ft, ln, li.n, li.max_u, npole, S, N, F, f_stride, x,
                               W[(L + 1) & 1], W[L & 1], ws),
            "fwd rect");
@@ -567,8 +589,23 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
     const int32_t *ln = lvl_ptr(mf, li);
     HIPCHK(launch_bwd_rect<T>(st, ft, ln, li.n, li.max_k, npole, S, N, F, f_stride, x, t, N * S),
            "bwd rect");
-    HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S),
-           "bwd tri");
+    if (!big(li)) {
+      HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, 0,
+                               (int64_t)1 << 40, 1),
+             "bwd tri");
+    } else {
+      HIPCHK(launch_bwd_init<T>(st, ft, ln, li.n, li.max_k, npole, S, N, F, f_stride, x, t, N * S),
+             "bwd init");
+      const int64_t nbb = (li.max_k + BB - 1) / BB;
+      for (int64_t bb = nbb - 1; bb >= 0; --bb) {
+        const int64_t cb = bb * BB;
+        HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, cb, BB,
+                                 0),
+               "bwd tri");
+        HIPCHK(launch_bwd_cols<T>(st, ft, ln, li.n, cb, npole, S, N, F, f_stride, x, BB),
+               "bwd cols");
+      }
+    }
   }
   return TEM_OK;
 }
@@ -1053,6 +1090,15 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
       return TEM_EDEVICE;
     }
     c->own_stream = true;
+  }
+  // tuning overrides (used by the tests to exercise both sweep schedules)
+  if (const char *v = std::getenv("TEM_SWEEP_BLOCK")) {
+    long b = std::strtol(v, nullptr, 10);
+    if (b >= NB && b % NB == 0) c->sweep_bb = b;
+  }
+  if (const char *v = std::getenv("TEM_SWEEP_BIG_LIMIT")) {
+    long b = std::strtol(v, nullptr, 10);
+    if (b >= 0) c->sweep_big_limit = b;
   }
   e = c->d_flags.alloc(sizeof(int) * 4);
   if (e != hipSuccess) {

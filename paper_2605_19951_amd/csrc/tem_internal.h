@@ -100,10 +100,28 @@ hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_n
 
 // ------------------------------------------------------------------ solves
 // Vectors are [pole][N][S] complex T (S fastest), S <= 16.
+// Triangle kernels work on the column range [cb, min(cb + BB, k)); BB >= k
+// covers the whole front in one launch (one workgroup per front and pole).
 template <typename T>
 hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
-                          cpx<T> *x, const cpx<T> *w_child, int64_t w_stride);
+                          cpx<T> *x, const cpx<T> *w_child, int64_t w_stride, int64_t cb,
+                          int64_t BB);
+// rows [cb+BB, k) -= L(rows, [cb, cb+BB)) y   (many workgroups per front)
+template <typename T>
+hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_rows, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB);
+// x_j = y_j / d_j - t_j
+template <typename T>
+hipError_t launch_bwd_init(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_k, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, cpx<T> *x, const cpx<T> *t, int64_t t_stride);
+// columns [0, cb) -= L([cb, cb+BB), cols)^T x  (many workgroups per front)
+template <typename T>
+hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int64_t cb, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, cpx<T> *x, int64_t BB);
 
 template <typename T>
 hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
@@ -119,7 +137,8 @@ hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 template <typename T>
 hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
-                          cpx<T> *x, const cpx<T> *t, int64_t t_stride);
+                          cpx<T> *x, const cpx<T> *t, int64_t t_stride, int64_t cb, int64_t BB,
+                          int init);
 
 // ------------------------------------------------------- vector kernels
 // Residual r = f - (K - xi_p M) x for all poles p and rhs s (FP64);

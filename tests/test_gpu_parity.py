@@ -55,6 +55,22 @@ class Run:
         self.o = _oracle(wl)
 
 
+def _wide(wl, prec):
+    """Run with the big-block sweep schedule forced on every level."""
+    import os
+    old = {k: os.environ.get(k) for k in ("TEM_SWEEP_BLOCK", "TEM_SWEEP_BIG_LIMIT")}
+    os.environ["TEM_SWEEP_BLOCK"] = "64"
+    os.environ["TEM_SWEEP_BIG_LIMIT"] = "1000000"
+    try:
+        return Run(wl, prec)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
 CASES = {
     "tiny64": lambda: Run(ti.tiny_workload(), 0),
     "tiny32": lambda: Run(ti.tiny_workload(), 1),
@@ -62,6 +78,8 @@ CASES = {
     "r13_32": lambda: Run(ti.smooth_workload(13, 2, S=3, m=5, K=7, g=2, seed=21), 1),
     "c16_64": lambda: Run(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 0),
     "c16_32": lambda: Run(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 1),
+    "w16_64": lambda: _wide(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 0),
+    "w16_32": lambda: _wide(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 1),
 }
 _cache = {}
 
@@ -133,7 +151,7 @@ def test_data_all_times(name):
         assert np.linalg.norm(d[:, j] - dref[:, j]) <= tol * max(nrm, np.linalg.norm(cond[:, j]))
 
 
-@pytest.mark.parametrize("name", ["r13_64", "r13_32", "c16_64", "c16_32"])
+@pytest.mark.parametrize("name", ["r13_64", "r13_32", "c16_64", "c16_32", "w16_64", "w16_32"])
 def test_jvp_vjp(name):
     r = get(name)
     torch = r.torch
