@@ -240,6 +240,25 @@ tem_status tem_jvp(tem_ctx *ctx, const double *v, double *jv, const tem_ir_opts 
 tem_status tem_vjp(tem_ctx *ctx, const double *w, double *jtw, const tem_ir_opts *ir,
                    tem_ir_stats *stats);
 
+/* One Gauss-Newton update (section "Optimization"): runs `iters`
+ * iterations of LSQR (Paige & Saunders 1982, x0 = 0, no damping) on
+ *   min || [W_d J; sqrt(lambda) R] dm + [W_d (d(m) - d_obs); sqrt(lambda) R (m - m_ref)] ||
+ * with J v and J^T w through the cached factors (tem_jvp / tem_vjp) and R
+ * the first differences m_b - m_a over faces shared by two parameter cells
+ * a < b (x-faces, then y-faces, then z-faces, each in increasing cell
+ * index of the lower cell): on a uniform hex mesh the section
+ * "Regularization"'s RT0 smoothness operator with a lumped mass reduces to
+ * these differences up to scale and boundary treatment.  d(m) is the data
+ * of the last tem_forward, which must have been run at m.
+ *   d_obs, wd   device, S*K*R doubles ([s][j][r]); wd = W_d diagonal
+ *   m, m_ref    device, P doubles
+ *   dm          device, P doubles (output; the step, m is not updated)
+ *   hist        host, iters doubles or NULL: LSQR residual estimate per iteration
+ *   ir          refinement options of the inner solves (may be NULL) */
+tem_status tem_gn_step(tem_ctx *ctx, const double *d_obs, const double *wd, const double *m,
+                       const double *m_ref, double lambda, int32_t iters, double *dm,
+                       double *hist, const tem_ir_opts *ir);
+
 /* ------------------------------------------------------------ statistics */
 
 typedef struct {

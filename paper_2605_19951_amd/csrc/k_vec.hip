@@ -671,6 +671,102 @@ hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int64_t 
   return hipGetLastError();
 }
 
+// ----------------------------------------------------- LSQR helpers (FP64)
+// deterministic dot product: fixed per-block partial sums, then one block
+__global__ __launch_bounds__(256) void k_rdot1(int64_t n, const double *a, const double *b,
+                                               double *partial) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += a[i] * b[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_rdot2(int nb, const double *partial, double *out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+hipError_t launch_rdot(hipStream_t st, int64_t n, const double *a, const double *b,
+                       double *partial, double *out) {
+  const int nb = 256;
+  hipLaunchKernelGGL(k_rdot1, dim3(nb), dim3(256), 0, st, n, a, b, partial);
+  hipLaunchKernelGGL(k_rdot2, dim3(1), dim3(256), 0, st, nb, partial, out);
+  return hipGetLastError();
+}
+
+// y = a * x + b * y   (x may be null: y = b * y); with w: x is weighted by w
+__global__ void k_raxpby(int64_t n, double a, const double *x, const double *w, double b,
+                         double *y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double xv = x ? x[i] : 0.0;
+  if (w) xv *= w[i];
+  // b == 0 overwrites y without reading it (y may hold stale, non-finite data)
+  y[i] = b == 0.0 ? a * xv : a * xv + b * y[i];
+}
+
+hipError_t launch_raxpby(hipStream_t st, int64_t n, double a, const double *x, const double *w,
+                         double b, double *y) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_raxpby, dim3(grid_1d(n, 256, 1 << 30)), dim3(256), 0, st, n, a, x, w, b, y);
+  return hipGetLastError();
+}
+
+// first-difference rows: out[r] = a * out[r] + sc * (m[hi[r]] - m[lo[r]])
+__global__ void k_reg(int64_t nr, const int32_t *lo, const int32_t *hi, double sc,
+                      const double *m, double a, double *out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nr) return;
+  const double v = sc * (m[hi[r]] - m[lo[r]]);
+  out[r] = a == 0.0 ? v : a * out[r] + v;
+}
+
+hipError_t launch_reg(hipStream_t st, int64_t nr, const int32_t *lo, const int32_t *hi, double sc,
+                      const double *m, double a, double *out) {
+  if (nr <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reg, dim3(grid_1d(nr, 256, 1 << 30)), dim3(256), 0, st, nr, lo, hi, sc, m,
+                     a, out);
+  return hipGetLastError();
+}
+
+// transpose, gathered per parameter: out[p] = a * out[p] + sc * sum_t sgn_t u[row_t]
+// (incidence CSR inc_ptr/inc_row; sign encoded as the sign of row+1)
+__global__ void k_regT(int P, const int64_t *inc_ptr, const int32_t *inc_row, double sc,
+                       const double *u, double a, double *out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double s = 0.0;
+  for (int64_t t = inc_ptr[p]; t < inc_ptr[p + 1]; ++t) {
+    const int32_t e = inc_row[t];
+    if (e > 0) s += u[e - 1];
+    else s -= u[-e - 1];
+  }
+  out[p] = a == 0.0 ? sc * s : a * out[p] + sc * s;
+}
+
+hipError_t launch_regT(hipStream_t st, int P, const int64_t *inc_ptr, const int32_t *inc_row,
+                       double sc, const double *u, double a, double *out) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_regT, dim3((P + 255) / 256), dim3(256), 0, st, P, inc_ptr, inc_row, sc, u,
+                     a, out);
+  return hipGetLastError();
+}
+
 // inv[ps] = 1/sqrt(re(dot)) (1 for zero), nrm[ps] = sqrt(re(dot))
 __global__ void k_norm_scales(int n, const cpx<double> *dots, double *inv, double *nrm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

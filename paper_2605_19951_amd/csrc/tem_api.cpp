@@ -54,12 +54,22 @@ struct DBuf {
   }
 };
 
+// Host-to-device copies from pageable host memory complete before these
+// helpers return, so the host buffer may be reused or freed right away.
 template <typename T>
 hipError_t upload(DBuf &b, const std::vector<T> &v, hipStream_t st) {
   hipError_t e = b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
   if (e != hipSuccess) return e;
   if (v.empty()) return hipSuccess;
-  return hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+  e = hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
 }
 
 struct LevelInfo {
@@ -144,6 +154,11 @@ struct tem_ctx {
   // survey
   int R = 0, K = 0;
   DBuf d_qptr, d_qcol, d_qval, d_alpha;
+  // first-difference regularisation over faces shared by two parameter cells
+  int64_t n_reg = 0;
+  DBuf d_reg_lo, d_reg_hi, d_reg_incp, d_reg_inc;
+  // LSQR work space
+  DBuf l_u, l_v, l_w, l_x, l_tmpd, l_tmpm, l_part, l_scal;
   // work space
   DBuf w_x;                        // factor-precision sweep vector
   DBuf v_r, v_z, v_x, v_w, v_rhs, v_lam, v_vs, v_dots, v_partial, v_inv, v_nrm, v_coef, v_mask;
@@ -244,6 +259,47 @@ void drop_factors(tem_ctx *c) {
 }
 
 // ------------------------------------------------ symbolic maps (host)
+// Rows (m_b - m_a) for every face shared by two parameter cells a < b:
+// x-faces, then y-faces, then z-faces, each in increasing cell index of the
+// lower cell; parameter incidence lists (signed row+1) for the transpose.
+tem_status build_regulariser(tem_ctx *c) {
+  const MeshTopo &mt = c->mt;
+  std::vector<int32_t> pid(mt.n_cells, -1);
+  for (size_t p = 0; p < c->params.size(); ++p) pid[c->params[p]] = (int32_t)p;
+  std::vector<int32_t> cells(c->params.begin(), c->params.end());
+  std::sort(cells.begin(), cells.end());
+  std::vector<int32_t> lo, hi;
+  for (int d = 0; d < 3; ++d)
+    for (int32_t cell : cells) {
+      int i = cell % mt.nx, j = (cell / mt.nx) % mt.ny, k = cell / (mt.nx * mt.ny);
+      int i2 = i + (d == 0), j2 = j + (d == 1), k2 = k + (d == 2);
+      if (i2 >= mt.nx || j2 >= mt.ny || k2 >= mt.nz) continue;
+      int32_t nb = pid[i2 + mt.nx * (j2 + mt.ny * k2)];
+      if (nb < 0) continue;
+      lo.push_back(pid[cell]);
+      hi.push_back(nb);
+    }
+  const int P = (int)c->params.size();
+  std::vector<int64_t> incp(P + 1, 0);
+  for (size_t r = 0; r < lo.size(); ++r) {
+    incp[lo[r] + 1]++;
+    incp[hi[r] + 1]++;
+  }
+  for (int p = 0; p < P; ++p) incp[p + 1] += incp[p];
+  std::vector<int32_t> inc(incp[P]);
+  std::vector<int64_t> fill(incp.begin(), incp.end() - 1);
+  for (size_t r = 0; r < lo.size(); ++r) {
+    inc[fill[lo[r]]++] = -(int32_t)(r + 1);
+    inc[fill[hi[r]]++] = (int32_t)(r + 1);
+  }
+  c->n_reg = (int64_t)lo.size();
+  HIPCHK(upload(c->d_reg_lo, lo, c->stream), "upload reg");
+  HIPCHK(upload(c->d_reg_hi, hi, c->stream), "upload reg");
+  HIPCHK(upload(c->d_reg_incp, incp, c->stream), "upload reg");
+  HIPCHK(upload(c->d_reg_inc, inc, c->stream), "upload reg");
+  return TEM_OK;
+}
+
 tem_status build_front_maps(tem_ctx *c, MF &mf) {
   const Symbolic &sym = mf.sym;
   const int ns = (int)sym.nodes.size();
@@ -777,16 +833,14 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
         any = any || active[i];
       }
       if (!any || it == max_iter) break;
-      HIPCHK(hipMemcpyAsync(c->v_mask.p, active.data(), sizeof(int) * mS, hipMemcpyHostToDevice,
-                            st),
+      HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * mS, st),
              "mask");
       TRY(precond(c, r, z, S));
       ++solves;
       for (int i = 0; i < mS; ++i)
         if (active[i]) res.iters[i]++;
       std::vector<cpx<double>> one(mS, {1.0, 0.0});
-      HIPCHK(hipMemcpyAsync(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS,
-                            hipMemcpyHostToDevice, st),
+      HIPCHK(h2d(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS, st),
              "coef");
       HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
                                  c->v_mask.as<int>()),
@@ -823,7 +877,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       std::vector<double> inv(mS);
       for (int i = 0; i < mS; ++i) inv[i] = rn[i] > 0 ? 1.0 / rn[i] : 0.0;
       HIPCHK(hipMemcpyAsync(V, r, vbytes, hipMemcpyDeviceToDevice, st), "V0");
-      HIPCHK(hipMemcpyAsync(c->v_inv.p, inv.data(), sizeof(double) * mS, hipMemcpyHostToDevice, st),
+      HIPCHK(h2d(c->v_inv.p, inv.data(), sizeof(double) * mS, st),
              "inv");
       HIPCHK(launch_batched_scale(st, N, m, S, c->v_inv.as<double>(), V), "V0 scale");
       // Hessenberg per system (column-major (kmax+1) x kmax), Givens
@@ -868,8 +922,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
           winv[i] = wn[i] > 0 ? 1.0 / wn[i] : 0.0;
         }
         HIPCHK(hipMemcpyAsync(V + (k + 1) * vs, w, vbytes, hipMemcpyDeviceToDevice, st), "V k+1");
-        HIPCHK(hipMemcpyAsync(c->v_inv.p, winv.data(), sizeof(double) * mS, hipMemcpyHostToDevice,
-                              st),
+        HIPCHK(h2d(c->v_inv.p, winv.data(), sizeof(double) * mS, st),
                "winv");
         HIPCHK(launch_batched_scale(st, N, m, S, c->v_inv.as<double>(), V + (k + 1) * vs),
                "V scale");
@@ -919,8 +972,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
           cd v = Y[(size_t)i * kdone + j];
           yc[i] = {v.real(), v.imag()};
         }
-        HIPCHK(hipMemcpyAsync(c->v_coef.p, yc.data(), sizeof(cpx<double>) * mS,
-                              hipMemcpyHostToDevice, st),
+        HIPCHK(h2d(c->v_coef.p, yc.data(), sizeof(cpx<double>) * mS, st),
                "y");
         HIPCHK(hipStreamSynchronize(st), "y sync");
         HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, V + j * vs, w,
@@ -930,10 +982,9 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       TRY(precond(c, w, z, S));
       ++solves;
       std::vector<cpx<double>> one(mS, {1.0, 0.0});
-      HIPCHK(hipMemcpyAsync(c->v_mask.p, active.data(), sizeof(int) * mS, hipMemcpyHostToDevice, st),
+      HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * mS, st),
              "mask");
-      HIPCHK(hipMemcpyAsync(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS,
-                            hipMemcpyHostToDevice, st),
+      HIPCHK(h2d(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS, st),
              "coef");
       HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
                                  c->v_mask.as<int>()),
@@ -946,7 +997,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
   }
   res.unconverged = 0;
   for (int i = 0; i < mS; ++i)
-    if (res.rel[i] > rtol) res.unconverged++;
+    if (!(res.rel[i] <= rtol)) res.unconverged++;   // NaN counts as unconverged
   res.solves = solves;
   return TEM_OK;
 }
@@ -1177,6 +1228,7 @@ tem_status tem_assemble(tem_ctx *c, const tem_mesh *mesh, const double *sigma_ce
          "copy sigma");
   c->params = prm;
   HIPCHK(upload(c->d_params, c->params, c->stream), "upload params");
+  TRY(build_regulariser(c));
   if (!same_mesh) {
     TRY(upload_pattern_and_assemble(c));
   } else {
@@ -1563,6 +1615,98 @@ tem_status tem_vjp(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *
   fill_stats(res, stats);
   c->last_solves = res.solves;
   if (res.unconverged) return fail(c, TEM_ENOCONV, "tem_vjp: refinement did not converge");
+  return TEM_OK;
+}
+
+static tem_status lsqr_norm(tem_ctx *c, int64_t n, const double *a, double &out) {
+  HIPCHK(launch_rdot(c->stream, n, a, a, c->l_part.as<double>(), c->l_scal.as<double>()), "dot");
+  double v = 0;
+  HIPCHK(hipMemcpyAsync(&v, c->l_scal.p, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+  HIPCHK(hipStreamSynchronize(c->stream), "sync");
+  out = std::sqrt(std::max(v, 0.0));
+  return TEM_OK;
+}
+
+tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const double *m,
+                       const double *m_ref, double lambda, int32_t iters, double *dm,
+                       double *hist, const tem_ir_opts *ir) {
+  if (!c) return TEM_EINVAL;
+  if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_gn_step: call tem_forward first");
+  if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_gn_step: no model parameters");
+  if (!d_obs || !wd || !m || !m_ref || !dm || iters <= 0 || !(lambda >= 0) || !std::isfinite(lambda))
+    return fail(c, TEM_EINVAL, "tem_gn_step: bad argument");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = c->stream;
+  const int64_t nd = (int64_t)c->S * c->K * c->R, nr = c->n_reg, nu = nd + nr;
+  const int P = (int)c->params.size();
+  const double sl = std::sqrt(lambda);
+  TRY(ensure_vec(c, c->l_u, sizeof(double) * nu, "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_v, sizeof(double) * P, "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_w, sizeof(double) * P, "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_x, sizeof(double) * P, "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_tmpd, sizeof(double) * nd, "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_tmpm, sizeof(double) * P, "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_part, sizeof(double) * 256, "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_scal, sizeof(double) * 4, "alloc lsqr"));
+  double *u = c->l_u.as<double>(), *v = c->l_v.as<double>(), *w = c->l_w.as<double>();
+  double *x = c->l_x.as<double>(), *td = c->l_tmpd.as<double>(), *tm = c->l_tmpm.as<double>();
+  const int32_t *rlo = c->d_reg_lo.as<int32_t>(), *rhi = c->d_reg_hi.as<int32_t>();
+  // A v = [W_d J v ; sqrt(lam) R v] -> u (times a, plus b u)
+  auto matvec = [&](const double *vin, double a, double b) -> tem_status {
+    TRY(tem_jvp(c, vin, td, ir, nullptr));
+    HIPCHK(launch_raxpby(st, nd, a, td, wd, b, u), "u data");
+    HIPCHK(launch_reg(st, nr, rlo, rhi, a * sl, vin, b, u + nd), "u reg");
+    return TEM_OK;
+  };
+  // A^T u = J^T (W_d u_d) + sqrt(lam) R^T u_r -> v (times a, plus b v)
+  auto rmatvec = [&](double a, double b) -> tem_status {
+    HIPCHK(launch_raxpby(st, nd, 1.0, u, wd, 0.0, td), "W u");
+    TRY(tem_vjp(c, td, tm, ir, nullptr));
+    HIPCHK(launch_raxpby(st, P, a, tm, nullptr, b, v), "v data");
+    HIPCHK(launch_regT(st, P, c->d_reg_incp.as<int64_t>(), c->d_reg_inc.as<int32_t>(), a * sl,
+                       u + nd, 1.0, v),
+           "v reg");
+    return TEM_OK;
+  };
+  // b = -[W_d (d(m) - d_obs); sqrt(lam) R (m - m_ref)]
+  HIPCHK(launch_time_assembly(st, c->S, c->K, c->R, c->npole, N_of(c), c->d_qptr.as<int64_t>(),
+                              c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
+                              c->d_alpha.as<cpx<double>>(), c->d_g.as<cpx<double>>(), td),
+         "d(m)");
+  HIPCHK(launch_raxpby(st, nd, -1.0, d_obs, nullptr, 1.0, td), "d - d_obs");
+  HIPCHK(launch_raxpby(st, nd, -1.0, td, wd, 0.0, u), "b data");
+  HIPCHK(launch_raxpby(st, P, 1.0, m, nullptr, 0.0, tm), "m");
+  HIPCHK(launch_raxpby(st, P, -1.0, m_ref, nullptr, 1.0, tm), "m - m_ref");
+  HIPCHK(launch_reg(st, nr, rlo, rhi, -sl, tm, 0.0, u + nd), "b reg");
+  double beta, alpha;
+  TRY(lsqr_norm(c, nu, u, beta));
+  if (beta > 0) HIPCHK(launch_raxpby(st, nu, 0.0, nullptr, nullptr, 1.0 / beta, u), "u /= beta");
+  HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 0.0, v), "v = 0");
+  TRY(rmatvec(1.0, 0.0));
+  TRY(lsqr_norm(c, P, v, alpha));
+  if (alpha > 0) HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 1.0 / alpha, v), "v /= alpha");
+  HIPCHK(launch_raxpby(st, P, 1.0, v, nullptr, 0.0, w), "w = v");
+  HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 0.0, x), "x = 0");
+  double phibar = beta, rhobar = alpha;
+  for (int it = 0; it < iters; ++it) {
+    TRY(matvec(v, 1.0, -alpha));                  // u = A v - alpha u
+    TRY(lsqr_norm(c, nu, u, beta));
+    if (beta > 0) HIPCHK(launch_raxpby(st, nu, 0.0, nullptr, nullptr, 1.0 / beta, u), "u scale");
+    TRY(rmatvec(1.0, -beta));                     // v = A^T u - beta v
+    TRY(lsqr_norm(c, P, v, alpha));
+    if (alpha > 0) HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 1.0 / alpha, v), "v scale");
+    const double rho = std::hypot(rhobar, beta);
+    const double cs = rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    rhobar = -cs * alpha;
+    const double phi = cs * phibar;
+    phibar = sn * phibar;
+    HIPCHK(launch_raxpby(st, P, phi / rho, w, nullptr, 1.0, x), "x update");
+    HIPCHK(launch_raxpby(st, P, 1.0, v, nullptr, -theta / rho, w), "w update");
+    if (hist) hist[it] = phibar;
+  }
+  HIPCHK(hipMemcpyAsync(dm, x, sizeof(double) * P, hipMemcpyDeviceToDevice, st), "dm");
+  HIPCHK(hipStreamSynchronize(st), "gn sync");
   return TEM_OK;
 }
 

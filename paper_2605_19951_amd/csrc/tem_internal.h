@@ -224,6 +224,16 @@ hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int64_t N,
                              const double *Me, const double *xi, const cpx<double> *g,
                              const cpx<double> *lam, double *out);
 
+// ----------------------------------------------------- LSQR helpers (FP64)
+hipError_t launch_rdot(hipStream_t st, int64_t n, const double *a, const double *b,
+                       double *partial /* 256 */, double *out);
+hipError_t launch_raxpby(hipStream_t st, int64_t n, double a, const double *x, const double *w,
+                         double b, double *y);
+hipError_t launch_reg(hipStream_t st, int64_t nr, const int32_t *lo, const int32_t *hi, double sc,
+                      const double *m, double a, double *out);
+hipError_t launch_regT(hipStream_t st, int P, const int64_t *inc_ptr, const int32_t *inc_row,
+                       double sc, const double *u, double a, double *out);
+
 // ------------------------------------------------ nodal gradient space
 // G^T M G on interior nodes (row-owner gather over the <= 8 cells of a node)
 hipError_t launch_assemble_nodal(hipStream_t st, int64_t Nn, const int64_t *rowptr,

@@ -24,7 +24,7 @@ _STATUS = {0: "TEM_OK", -1: "TEM_EINVAL", -2: "TEM_ENOMEM", -3: "TEM_EDEVICE", -
 EXPORTS = ["tem_create", "tem_destroy", "tem_last_error", "tem_assemble", "tem_set_model",
            "tem_export_operators", "tem_analyse", "tem_symbolic_host", "tem_factor_poles",
            "tem_solve_poles", "tem_forward", "tem_jvp", "tem_vjp", "tem_get_stats",
-           "tem_set_profiling"]
+           "tem_set_profiling", "tem_gn_step"]
 
 
 class TemError(RuntimeError):
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH):
         "tem_vjp": ([vp, dp, dp, C.POINTER(IrOpts), C.POINTER(IrStats)], C.c_int),
         "tem_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
         "tem_set_profiling": ([vp, i32], C.c_int),
+        "tem_gn_step": ([vp, dp, dp, dp, dp, C.c_double, i32, dp, vp, C.POINTER(IrOpts)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -294,6 +295,17 @@ class Tem:
         self._chk(self.L.tem_vjp(self.h, _dev(w, "float64", self._dshape()),
                                  _dev(jtw, "float64", (self.n_params,)), self._ir(ir), C.byref(s)))
         return dict(iters=it.reshape(self.npole, self.S), rel=rr.reshape(self.npole, self.S))
+
+    def gn_step(self, d_obs, wd, m, m_ref, lam, iters, dm, ir=None):
+        """One Gauss-Newton step by LSQR; returns the residual estimates."""
+        hist = np.zeros(iters)
+        shp = self._dshape()
+        self._chk(self.L.tem_gn_step(self.h, _dev(d_obs, "float64", shp), _dev(wd, "float64", shp),
+                                     _dev(m, "float64", (self.n_params,)),
+                                     _dev(m_ref, "float64", (self.n_params,)), float(lam), int(iters),
+                                     _dev(dm, "float64", (self.n_params,)),
+                                     hist.ctypes.data_as(C.c_void_p), self._ir(ir)))
+        return hist
 
     def set_profiling(self, enable=True):
         self._chk(self.L.tem_set_profiling(self.h, 1 if enable else 0))
