@@ -181,7 +181,12 @@ typedef struct {
  *   xi    host, 2*m doubles (re, im); Im > 0 required.
  *   opts  may be NULL.
  * Poles are factored in groups when the contribution blocks of all poles do
- * not fit beside the factors; the grouping is reported by tem_get_stats. */
+ * not fit beside the factors; the grouping is reported by tem_get_stats.
+ * Memory: the factor storage (and, while at least 32 GiB stay free, the
+ * contribution-block arenas) remains allocated in the context and is reused
+ * by the next call of the same size (a new model in a Gauss-Newton loop);
+ * the budget counts it as available.  A different mesh, leaf size or
+ * tem_destroy gives it back. */
 tem_status tem_factor_poles(tem_ctx *ctx, int32_t m, const double *xi, tem_precision prec,
                             const tem_factor_opts *opts);
 

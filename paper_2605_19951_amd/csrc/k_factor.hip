@@ -233,79 +233,103 @@ hipError_t launch_panel_trsm(hipStream_t st, FrontTab ft, const int32_t *lvl_nod
 }
 
 // ------------------------------------------------------ MFMA tile update
-// C -= L D L^T on the lower triangle, 64 x 64 output tiles, 4 waves of
-// 32 x 32, complex arithmetic as four real MFMAs per depth step on split
-// real/imaginary planes staged through LDS.
-constexpr int TT = 64;   // output tile
+// C -= L D L^T on the lower triangle.  TTS x TTS output tiles, 4 waves of
+// (TTS/2) x (TTS/2); complex arithmetic as four real MFMAs per depth step on
+// split real/imaginary planes staged through LDS; the next depth chunk is
+// prefetched into registers while the current one is multiplied.
 constexpr int KB = 16;   // depth chunk (divides NB)
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <typename T>
+template <typename T, int TTS>
 struct WaveAcc;
 
-template <>
-struct WaveAcc<float> {
-  floatx16 re, im;
+// FP32: blocks of 32 x 32 (v_mfma_f32_32x32x2f32), NBK x NBK blocks per wave
+template <int TTS>
+struct WaveAcc<float, TTS> {
+  static constexpr int NBK = TTS / 64;
+  floatx16 re[NBK][NBK], im[NBK][NBK];
   __device__ void zero() {
-    for (int i = 0; i < 16; ++i) {
-      re[i] = 0.f;
-      im[i] = 0.f;
-    }
+#pragma unroll
+    for (int a = 0; a < NBK; ++a)
+#pragma unroll
+      for (int b = 0; b < NBK; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          re[a][b][i] = 0.f;
+          im[a][b][i] = 0.f;
+        }
   }
-  // acc -= A B^T over one KB chunk; As/Bs planes [KB][TT]
-  __device__ void step(const float (*Ar)[TT], const float (*Ai)[TT], const float (*Br)[TT],
-                       const float (*Bi)[TT], int wr, int wc, int lane) {
+  __device__ void step(const float (*Ar)[TTS], const float (*Ai)[TTS], const float (*Br)[TTS],
+                       const float (*Bi)[TTS], int wr, int wc, int lane) {
     const int rr = lane & 31, kh = lane >> 5;
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 2) {
-      const float ar = Ar[kk + kh][wr * 32 + rr], ai = Ai[kk + kh][wr * 32 + rr];
-      const float br = Br[kk + kh][wc * 32 + rr], bi = Bi[kk + kh][wc * 32 + rr];
-      re = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar, br, re, 0, 0, 0);
-      re = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, re, 0, 0, 0);
-      im = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar, bi, im, 0, 0, 0);
-      im = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, br, im, 0, 0, 0);
+      float ar[NBK], ai[NBK], br[NBK], bi[NBK];
+#pragma unroll
+      for (int a = 0; a < NBK; ++a) {
+        ar[a] = Ar[kk + kh][wr * (TTS / 2) + a * 32 + rr];
+        ai[a] = Ai[kk + kh][wr * (TTS / 2) + a * 32 + rr];
+        br[a] = Br[kk + kh][wc * (TTS / 2) + a * 32 + rr];
+        bi[a] = Bi[kk + kh][wc * (TTS / 2) + a * 32 + rr];
+      }
+#pragma unroll
+      for (int a = 0; a < NBK; ++a)
+#pragma unroll
+        for (int b = 0; b < NBK; ++b) {
+          re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar[a], br[b], re[a][b], 0, 0, 0);
+          re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[a], bi[b], re[a][b], 0, 0, 0);
+          im[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar[a], bi[b], im[a][b], 0, 0, 0);
+          im[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[a], br[b], im[a][b], 0, 0, 0);
+        }
     }
   }
-  // element i of this lane -> (row, col) inside the wave's 32 x 32 tile
-  __device__ static int nelem() { return 16; }
-  __device__ static void coord(int lane, int i, int &row, int &col) {
-    row = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-    col = lane & 31;
+  static constexpr int nelem() { return NBK * NBK * 16; }
+  // element e of this lane -> (row, col) inside the wave's tile
+  __device__ static void coord(int lane, int e, int &row, int &col) {
+    const int blk = e >> 4, i = e & 15;
+    const int a = blk / NBK, b = blk % NBK;
+    row = a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+    col = b * 32 + (lane & 31);
   }
-  __device__ float get_re(int i) const { return re[i]; }
-  __device__ float get_im(int i) const { return im[i]; }
+  __device__ float get_re(int e) const { return re[(e >> 4) / NBK][(e >> 4) % NBK][e & 15]; }
+  __device__ float get_im(int e) const { return im[(e >> 4) / NBK][(e >> 4) % NBK][e & 15]; }
 };
 
-template <>
-struct WaveAcc<double> {
-  doublex4 re[2][2], im[2][2];
+// FP64: blocks of 16 x 16 (v_mfma_f64_16x16x4f64), NBK x NBK blocks per wave
+template <int TTS>
+struct WaveAcc<double, TTS> {
+  static constexpr int NBK = TTS / 32;
+  doublex4 re[NBK][NBK], im[NBK][NBK];
   __device__ void zero() {
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < NBK; ++a)
+#pragma unroll
+      for (int b = 0; b < NBK; ++b)
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
           re[a][b][i] = 0.0;
           im[a][b][i] = 0.0;
         }
   }
-  __device__ void step(const double (*Ar)[TT], const double (*Ai)[TT], const double (*Br)[TT],
-                       const double (*Bi)[TT], int wr, int wc, int lane) {
+  __device__ void step(const double (*Ar)[TTS], const double (*Ai)[TTS], const double (*Br)[TTS],
+                       const double (*Bi)[TTS], int wr, int wc, int lane) {
     const int rr = lane & 15, kq = lane >> 4;
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 4) {
-      double ar[2], ai[2], br[2], bi[2];
+      double ar[NBK], ai[NBK], br[NBK], bi[NBK];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        ar[a] = Ar[kk + kq][wr * 32 + a * 16 + rr];
-        ai[a] = Ai[kk + kq][wr * 32 + a * 16 + rr];
-        br[a] = Br[kk + kq][wc * 32 + a * 16 + rr];
-        bi[a] = Bi[kk + kq][wc * 32 + a * 16 + rr];
+      for (int a = 0; a < NBK; ++a) {
+        ar[a] = Ar[kk + kq][wr * (TTS / 2) + a * 16 + rr];
+        ai[a] = Ai[kk + kq][wr * (TTS / 2) + a * 16 + rr];
+        br[a] = Br[kk + kq][wc * (TTS / 2) + a * 16 + rr];
+        bi[a] = Bi[kk + kq][wc * (TTS / 2) + a * 16 + rr];
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < NBK; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < NBK; ++b) {
           re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[a], br[b], re[a][b], 0, 0, 0);
           re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], re[a][b], 0, 0, 0);
           im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[a], bi[b], im[a][b], 0, 0, 0);
@@ -313,31 +337,33 @@ struct WaveAcc<double> {
         }
     }
   }
-  __device__ static int nelem() { return 16; }
-  __device__ static void coord(int lane, int i, int &row, int &col) {
-    const int blk = i >> 2, e = i & 3;
-    const int a = blk >> 1, b = blk & 1;
-    row = a * 16 + (lane >> 4) + 4 * e;   // f64 16x16x4 result: row l/16 + 4v
+  static constexpr int nelem() { return NBK * NBK * 4; }
+  __device__ static void coord(int lane, int e, int &row, int &col) {
+    const int blk = e >> 2, i = e & 3;
+    const int a = blk / NBK, b = blk % NBK;
+    row = a * 16 + (lane >> 4) + 4 * i;   // f64 16x16x4 result: row lane/16 + 4i
     col = b * 16 + (lane & 15);
   }
-  __device__ double get_re(int i) const { return re[(i >> 2) >> 1][(i >> 2) & 1][i & 3]; }
-  __device__ double get_im(int i) const { return im[(i >> 2) >> 1][(i >> 2) & 1][i & 3]; }
+  __device__ double get_re(int e) const { return re[(e >> 2) / NBK][(e >> 2) % NBK][e & 3]; }
+  __device__ double get_im(int e) const { return im[(e >> 2) / NBK][(e >> 2) % NBK][e & 3]; }
 };
 
-template <typename T>
+// mode 0: depth (eliminated columns) [j0, j0 + dw), updated columns
+// [j0 + dw, min(k, ccap)); mode 1: depth [0, k), contribution block.
+template <typename T, int TTS>
 __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t *lvl_nodes,
-                                                      int mode, int j0, cpx<T> *factor,
-                                                      int64_t f_stride, cpx<T> *cb,
-                                                      int64_t cb_stride) {
+                                                      int mode, int j0, int dw, int ccap,
+                                                      cpx<T> *factor, int64_t f_stride,
+                                                      cpx<T> *cb, int64_t cb_stride) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u;
   int64_t cbeg, cend, l0, l1;
   if (mode == 0) {
-    cbeg = j0 + NB;
-    cend = k;
+    cbeg = (int64_t)j0 + dw;
+    cend = min(k, (int64_t)ccap);
     l0 = j0;
-    l1 = min((int64_t)j0 + NB, k);
+    l1 = min((int64_t)j0 + dw, k);
   } else {
     cbeg = k;
     cend = n;
@@ -347,74 +373,89 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
   if (cbeg >= cend || l0 >= l1) return;
   // linear tile id -> (column tile, row tile) over the lower trapezoid
   int64_t t = blockIdx.x;
-  const int64_t nct = (cend - cbeg + TT - 1) / TT;
+  const int64_t nct = (cend - cbeg + TTS - 1) / TTS;
   int64_t ct = 0;
   for (; ct < nct; ++ct) {
-    const int64_t cnt = (n - (cbeg + TT * ct) + TT - 1) / TT;
+    const int64_t cnt = (n - (cbeg + TTS * ct) + TTS - 1) / TTS;
     if (t < cnt) break;
     t -= cnt;
   }
   if (ct >= nct) return;
-  const int64_t col0 = cbeg + TT * ct;
-  const int64_t row0 = col0 + TT * t;
+  const int64_t col0 = cbeg + TTS * ct;
+  const int64_t row0 = col0 + TTS * t;
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
 
-  __shared__ T Ar[KB][TT], Ai[KB][TT], Br[KB][TT], Bi[KB][TT];
+  __shared__ T Ar[KB][TTS], Ai[KB][TTS], Br[KB][TTS], Bi[KB][TTS];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
-  WaveAcc<T> acc;
-  acc.zero();
-  const int lr = tid & 63;         // row inside the tile this thread loads
-  const int lk = (tid >> 6) * 4;   // first of the 4 depth columns it loads
-  for (int64_t l = l0; l < l1; l += KB) {
-    const int64_t b = l / NB;
-    const int64_t r0 = NB * b;
-    const int64_t ldb = n - r0;
+  constexpr int PER = TTS * KB / 256;   // elements of A (and of B) per thread and chunk
+  const int lr = tid % TTS;             // tile row this thread loads
+  const int lk = (tid / TTS) * PER;     // first depth column it loads
+  cpx<T> pa[PER], pb[PER];
+  auto fetch = [&](int64_t l) {
+    const int64_t b = l / NB, r0 = NB * b, ldb = n - r0;
     const cpx<T> *base = P + panel_block_off(n, b);
-    __syncthreads();
+    const int64_t ra = row0 + lr, rb = col0 + lr;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < PER; ++q) {
       const int64_t lc = l + lk + q;
       cpx<T> a = czero<T>(), bb = czero<T>();
       if (lc < l1) {
         const cpx<T> *colp = base + (lc - r0) * ldb - r0;
-        const int64_t ra = row0 + lr, rb = col0 + lr;
         if (ra < n) a = colp[ra];
         if (rb < n) bb = cmul(colp[rb], colp[lc]);
       }
-      Ar[lk + q][lr] = a.re;
-      Ai[lk + q][lr] = a.im;
-      Br[lk + q][lr] = bb.re;
-      Bi[lk + q][lr] = bb.im;
+      pa[q] = a;
+      pb[q] = bb;
+    }
+  };
+  WaveAcc<T, TTS> acc;
+  acc.zero();
+  fetch(l0);
+  for (int64_t l = l0; l < l1; l += KB) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      Ar[lk + q][lr] = pa[q].re;
+      Ai[lk + q][lr] = pa[q].im;
+      Br[lk + q][lr] = pb[q].re;
+      Bi[lk + q][lr] = pb[q].im;
     }
     __syncthreads();
+    if (l + KB < l1) fetch(l + KB);
     acc.step(Ar, Ai, Br, Bi, wr, wc, lane);
   }
   // epilogue: C += acc on the lower triangle
   cpx<T> *Cb = (mode == 1) ? cb + (int64_t)p * cb_stride + ft.cb_off[s] : nullptr;
   cpx<T> *Pw = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  for (int i = 0; i < WaveAcc<T>::nelem(); ++i) {
+#pragma unroll
+  for (int e = 0; e < WaveAcc<T, TTS>::nelem(); ++e) {
     int rr, cc;
-    WaveAcc<T>::coord(lane, i, rr, cc);
-    const int64_t row = row0 + wr * 32 + rr, col = col0 + wc * 32 + cc;
+    WaveAcc<T, TTS>::coord(lane, e, rr, cc);
+    const int64_t row = row0 + wr * (TTS / 2) + rr, col = col0 + wc * (TTS / 2) + cc;
     if (row >= n || col >= cend || row < col) continue;
     cpx<T> *q = (mode == 1) ? Cb + (col - k) * u + (row - k) : Pw + panel_elem(n, row, col);
     cpx<T> v = *q;
-    v.re += acc.get_re(i);
-    v.im += acc.get_im(i);
+    v.re += acc.get_re(e);
+    v.im += acc.get_im(e);
     *q = v;
   }
 }
 
 template <typename T>
 hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                               int mode, int j0, int64_t max_tiles, int npole, cpx<T> *factor,
-                               int64_t f_stride, cpx<T> *cb, int64_t cb_stride) {
+                               int mode, int j0, int dw, int ccap, int64_t max_tiles, int npole,
+                               cpx<T> *factor, int64_t f_stride, cpx<T> *cb, int64_t cb_stride,
+                               int tile) {
   if (n_nodes <= 0 || max_tiles <= 0) return hipSuccess;
   dim3 grid((unsigned)max_tiles, n_nodes, npole);
-  hipLaunchKernelGGL(k_front_update<T>, grid, dim3(256), 0, st, ft, lvl_nodes, mode, j0, factor,
-                     f_stride, cb, cb_stride);
+  if (tile == 128)
+    hipLaunchKernelGGL((k_front_update<T, 128>), grid, dim3(256), 0, st, ft, lvl_nodes, mode, j0,
+                       dw, ccap, factor, f_stride, cb, cb_stride);
+  else
+    hipLaunchKernelGGL((k_front_update<T, 64>), grid, dim3(256), 0, st, ft, lvl_nodes, mode, j0,
+                       dw, ccap, factor, f_stride, cb, cb_stride);
   return hipGetLastError();
 }
 
@@ -431,8 +472,8 @@ hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_n
   template hipError_t launch_panel_trsm<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \
                                            int, cpx<T> *, int64_t);                              \
   template hipError_t launch_front_update<T>(hipStream_t, FrontTab, const int32_t *, int, int,    \
-                                             int, int64_t, int, cpx<T> *, int64_t, cpx<T> *,     \
-                                             int64_t);
+                                             int, int, int, int64_t, int, cpx<T> *, int64_t,      \
+                                             cpx<T> *, int64_t, int);
 TEM_INST(float)
 TEM_INST(double)
 #undef TEM_INST

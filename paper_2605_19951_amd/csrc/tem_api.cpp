@@ -36,6 +36,8 @@ struct DBuf {
     p = nullptr;
     bytes = 0;
   }
+  // Freeing and mapping tens of GB takes seconds, so buffers that are
+  // rebuilt with the same size (factors, arenas) keep their allocation.
   hipError_t alloc(size_t b) {
     if (b == bytes && p) return hipSuccess;
     release();
@@ -85,11 +87,12 @@ struct LevelInfo {
 };
 
 struct Tiles {
-  // tiles of the lower trapezoid with columns [cbeg, cend) of an n-row front
-  static int64_t count(int64_t n, int64_t cbeg, int64_t cend) {
+  // tiles of edge tt covering the lower trapezoid with columns [cbeg, cend)
+  // of an n-row front
+  static int64_t count(int64_t n, int64_t cbeg, int64_t cend, int64_t tt) {
     if (cbeg >= cend) return 0;
-    int64_t nct = (cend - cbeg + 63) / 64, tot = 0;
-    for (int64_t ct = 0; ct < nct; ++ct) tot += (n - (cbeg + 64 * ct) + 63) / 64;
+    int64_t nct = (cend - cbeg + tt - 1) / tt, tot = 0;
+    for (int64_t ct = 0; ct < nct; ++ct) tot += (n - (cbeg + tt * ct) + tt - 1) / tt;
     return tot;
   }
 };
@@ -138,6 +141,7 @@ struct tem_ctx {
   bool aux = true;                 // gradient-space correction in FP32 refinement
   int64_t sweep_bb = 256;          // big column block of the wide-front sweeps
   int64_t sweep_big_limit = 1024;  // fronts x poles below which a level is "wide"
+  bool upd_tile128 = false;        // 128 x 128 MFMA update tiles (FP32)
   // factors
   int npole = 0;
   tem_precision prec = TEM_FP64;
@@ -248,13 +252,18 @@ tem_status upload_pattern_and_assemble(tem_ctx *c) {
   return run_assemble_edges(c);
 }
 
+// Invalidates the factors and pole solutions; their memory stays allocated
+// for a refactorisation of the same size (free_factors releases it).
 void drop_factors(tem_ctx *c) {
   c->nodal_ready = false;
+  c->factored = false;
+  c->solved = false;
+}
+void free_factors(tem_ctx *c) {
+  drop_factors(c);
   c->d_factor.release();
   c->d_cb0.release();
   c->d_cb1.release();
-  c->factored = false;
-  c->solved = false;
   c->d_g.release();
 }
 
@@ -543,45 +552,66 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, const d
       HIPCHK(launch_extend_add<T>(st, ft, ln, li.n, sl, li.max_u_child[sl], g, F, mf.pole_stride,
                                   cbL, cbC, mf.cb_stride),
              "extend-add");
-    for (int j0 = 0; j0 < li.max_k; j0 += NB) {
-      int max_rows = 0;
+    // 128-column panels: inside a panel every 32-column block is factored and
+    // applied (rank 32) to the rest of the panel only; the panel then
+    // updates all later columns at once (rank 128).
+    const int PW = 4 * NB;
+    auto trailing = [&](int j0, int dw, int ccap) -> tem_status {
       int64_t max_tiles = 0;
       double fl = 0;
+      const int tt = (sizeof(T) == 4 && c->upd_tile128 && li.max_n - j0 - dw >= 256) ? 128 : 64;
       for (int s : li.nodes) {
         const SymNode &nd = sym.nodes[s];
         const int64_t k = nd.last - nd.first, n = k + nd.nrows;
-        if (j0 >= k) continue;
-        const int64_t w = std::min<int64_t>(NB, k - j0);
-        max_rows = std::max<int>(max_rows, (int)(n - j0 - w));
-        max_tiles = std::max(max_tiles, Tiles::count(n, j0 + NB, k));
-        if (c->profile && j0 + NB < k) {
-          // lower-trapezoid entries of columns [j0+NB, k): sum (n - col)
-          const double c0 = j0 + NB, c1 = (double)k;
-          fl += 8.0 * (double)w * ((c1 - c0) * n - (c1 * (c1 - 1) - c0 * (c0 - 1)) / 2.0) * g;
+        const int64_t c0 = j0 + dw, c1 = std::min<int64_t>(k, ccap);
+        if (c0 >= c1) continue;
+        max_tiles = std::max(max_tiles, Tiles::count(n, c0, c1, tt));
+        if (c->profile) {
+          const double w = (double)std::min<int64_t>(dw, k - j0);
+          const double a0 = (double)c0, a1 = (double)c1;
+          // lower-trapezoid entries of columns [c0, c1): sum (n - col)
+          fl += 8.0 * w * ((a1 - a0) * n - (a1 * (a1 - 1) - a0 * (a0 - 1)) / 2.0) * g;
         }
       }
-      HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, g, F, mf.pole_stride,
-                                  c->d_flags.as<int>()),
-             "panel diag");
-      HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, max_rows, g, F, mf.pole_stride),
-             "panel trsm");
+      if (max_tiles == 0) return TEM_OK;
       hipEvent_t ea = span_begin(c);
-      HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 0, j0, max_tiles, g, F, mf.pole_stride,
-                                    cbL, mf.cb_stride),
+      HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 0, j0, dw, ccap, max_tiles, g, F,
+                                    mf.pole_stride, cbL, mf.cb_stride, tt),
              "trailing update");
       span_end(c, ea, fl, 0);
+      return TEM_OK;
+    };
+    for (int P0 = 0; P0 < li.max_k; P0 += PW) {
+      for (int j0 = P0; j0 < std::min(P0 + PW, li.max_k); j0 += NB) {
+        int max_rows = 0;
+        for (int s : li.nodes) {
+          const SymNode &nd = sym.nodes[s];
+          const int64_t k = nd.last - nd.first, n = k + nd.nrows;
+          if (j0 >= k) continue;
+          const int64_t w = std::min<int64_t>(NB, k - j0);
+          max_rows = std::max<int>(max_rows, (int)(n - j0 - w));
+        }
+        HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, g, F, mf.pole_stride,
+                                    c->d_flags.as<int>()),
+               "panel diag");
+        HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, max_rows, g, F, mf.pole_stride),
+               "panel trsm");
+        TRY(trailing(j0, NB, P0 + PW));
+      }
+      TRY(trailing(P0, PW, 1 << 30));
     }
     int64_t cb_tiles = 0;
     double fl = 0;
+    const int ttc = (sizeof(T) == 4 && c->upd_tile128 && li.max_u >= 256) ? 128 : 64;
     for (int s : li.nodes) {
       const SymNode &nd = sym.nodes[s];
       const int64_t k = nd.last - nd.first, n = k + nd.nrows;
-      if (k > 0) cb_tiles = std::max(cb_tiles, Tiles::count(n, k, n));
+      if (k > 0) cb_tiles = std::max(cb_tiles, Tiles::count(n, k, n, ttc));
       fl += 8.0 * (double)k * (double)nd.nrows * (double)(nd.nrows + 1) / 2.0 * g;
     }
     hipEvent_t ea = span_begin(c);
-    HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, cb_tiles, g, F, mf.pole_stride, cbL,
-                                  mf.cb_stride),
+    HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, 0, 0, cb_tiles, g, F, mf.pole_stride,
+                                  cbL, mf.cb_stride, ttc),
            "contribution update");
     span_end(c, ea, fl, 0);
   }
@@ -1151,6 +1181,7 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
     long b = std::strtol(v, nullptr, 10);
     if (b >= 0) c->sweep_big_limit = b;
   }
+  if (const char *v = std::getenv("TEM_UPDATE_TILE")) c->upd_tile128 = std::strtol(v, nullptr, 10) == 128;
   e = c->d_flags.alloc(sizeof(int) * 4);
   if (e != hipSuccess) {
     g_create_error = "tem_create: flags allocation failed";
@@ -1208,7 +1239,10 @@ tem_status tem_assemble(tem_ctx *c, const tem_mesh *mesh, const double *sigma_ce
       return fail(c, TEM_EINVAL, "tem_assemble: sigma must be positive and finite");
   const bool same_mesh = c->assembled && c->mesh.nx == mesh->nx && c->mesh.ny == mesh->ny &&
                          c->mesh.nz == mesh->nz && c->mesh.h == mesh->h && c->mesh.mu == mesh->mu;
-  drop_factors(c);
+  if (same_mesh)
+    drop_factors(c);
+  else
+    free_factors(c);
   if (!same_mesh) {
     c->analysed = false;
     c->assembled = false;
@@ -1284,7 +1318,7 @@ tem_status tem_analyse(tem_ctx *c, const tem_analyse_opts *opts, tem_symbolic_in
   int leaf = (opts && opts->leaf_max_cells > 0) ? opts->leaf_max_cells : 4;
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
   if (!c->analysed || leaf != c->leaf) {
-    drop_factors(c);
+    free_factors(c);
     try {
       analyse_symbolic(c->mt, leaf, c->ed.sym, false);
     } catch (const std::exception &ex) {
@@ -1377,10 +1411,15 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
   const size_t esz = prec == TEM_FP64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
   const size_t fbytes = esz * (size_t)c->ed.pole_stride * m;
   const size_t cb_pole = esz * (size_t)std::max<int64_t>(c->ed.cb_stride, 1);
+  // a factor buffer of another size and the arenas are given back first;
+  // the budget counts what is still held as available.
+  if (c->d_factor.bytes != fbytes) c->d_factor.release();
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-  int64_t budget = (opts && opts->mem_budget_bytes > 0) ? opts->mem_budget_bytes
-                                                         : (int64_t)(0.92 * (double)free_b);
+  const int64_t held = (int64_t)(c->d_factor.bytes + c->d_cb0.bytes + c->d_cb1.bytes);
+  int64_t budget = (opts && opts->mem_budget_bytes > 0)
+                       ? opts->mem_budget_bytes
+                       : (int64_t)(0.92 * (double)free_b) + held;
   if ((int64_t)fbytes + 2 * (int64_t)cb_pole > budget)
     return fail(c, TEM_ENOMEM, "tem_factor_poles: factors do not fit in the memory budget");
   int g = (int)std::min<int64_t>(m, (budget - (int64_t)fbytes) / (2 * (int64_t)cb_pole));
@@ -1388,6 +1427,10 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
   g = std::max(g, 1);
   const int ngroups = (m + g - 1) / g;
   g = (m + ngroups - 1) / ngroups;    // balance the groups
+  if (c->d_cb0.bytes != cb_pole * g) {
+    c->d_cb0.release();
+    c->d_cb1.release();
+  }
   HIPCHK(c->d_factor.alloc(fbytes), "alloc factors");
   HIPCHK(c->d_cb0.alloc(cb_pole * g), "alloc cb arena");
   HIPCHK(c->d_cb1.alloc(cb_pole * g), "alloc cb arena");
@@ -1414,8 +1457,14 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
       return s;
     }
   }
-  c->d_cb0.release();
-  c->d_cb1.release();
+  {
+    // keep the arenas for the next factorisation unless the solves need the room
+    size_t fr = 0, tt = 0;
+    if (hipMemGetInfo(&fr, &tt) != hipSuccess || fr < (size_t)32 << 30) {
+      c->d_cb0.release();
+      c->d_cb1.release();
+    }
+  }
   if (prec == TEM_FP32_IR && c->aux) {
     tem_status s = factor_nodal(c);
     if (s != TEM_OK) {
@@ -1437,10 +1486,7 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
   c->n_tiny = flags[1];
   c->n_groups = ngroups;
   c->group_size = g;
-  c->d_cb0.release();
-  c->d_cb1.release();
   if (flags[0]) {
-    c->d_factor.release();
     return fail(c, TEM_EPIVOT, "tem_factor_poles: zero or non-finite pivot");
   }
   c->factored = true;

@@ -91,12 +91,15 @@ template <typename T>
 hipError_t launch_panel_trsm(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                              int j0, int max_rows, int npole, cpx<T> *factor, int64_t f_stride);
 
-// mode 0: trailing update of panel columns after column block j0/NB;
-// mode 1: contribution block C -= L21 D L21^T.
+// mode 0: trailing update of panel columns [j0+dw, min(k, ccap)) by the
+// eliminated columns [j0, j0+dw); mode 1: contribution block
+// C -= L21 D L21^T.  tile = 64 or 128 (output tile edge; max_tiles counted
+// with the same edge).
 template <typename T>
 hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                               int mode, int j0, int64_t max_tiles, int npole, cpx<T> *factor,
-                               int64_t f_stride, cpx<T> *cb, int64_t cb_stride);
+                               int mode, int j0, int dw, int ccap, int64_t max_tiles, int npole,
+                               cpx<T> *factor, int64_t f_stride, cpx<T> *cb, int64_t cb_stride,
+                               int tile);
 
 // ------------------------------------------------------------------ solves
 // Vectors are [pole][N][S] complex T (S fastest), S <= 16.
