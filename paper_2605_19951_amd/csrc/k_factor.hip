@@ -242,115 +242,164 @@ constexpr int KB = 16;   // depth chunk (divides NB)
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <typename T, int TTS>
-struct WaveAcc;
 
-// FP32: blocks of 32 x 32 (v_mfma_f32_32x32x2f32), NBK x NBK blocks per wave
-template <int TTS>
-struct WaveAcc<float, TTS> {
-  static constexpr int NBK = TTS / 64;
-  floatx16 re[NBK][NBK], im[NBK][NBK];
+// Complex products.  The update is C -= A B^T with A = Ar + i Ai (rows of
+// L) and B = Br + i Bi (rows of L D).  With M3 = false four real products
+// accumulate Re = Ar Br^T - Ai Bi^T and Im = Ar Bi^T + Ai Br^T; with
+// M3 = true three (the 3M method): P1 = Ar Br^T, P2 = Ai Bi^T,
+// P3 = (Ar + Ai)(Br + Bi)^T, Re = P1 - P2, Im = P3 - P1 - P2.  The 3M form
+// does a quarter fewer matrix-core products and its error stays normwise
+// of the order of the unit roundoff (Higham, SIAM J. Matrix Anal. Appl. 13,
+// 1992).  Accumulator q of a wave holds NBK x NBK MFMA blocks.
+template <typename T>
+struct Mfma;
+// FP32: blocks of 32 x 32, v_mfma_f32_32x32x2f32 (depth 2 per product;
+// operand lane l carries row l % 32, depth l / 32; result element i of lane
+// l is row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32)
+template <>
+struct Mfma<float> {
+  static constexpr int BS = 32, DK = 2, NV = 16;
+  using acc_t = floatx16;
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static void operand(int lane, int &r, int &k) {
+    r = lane & 31;
+    k = lane >> 5;
+  }
+  __device__ static void coord(int lane, int i, int &row, int &col) {
+    row = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+    col = lane & 31;
+  }
+};
+// FP64: blocks of 16 x 16, v_mfma_f64_16x16x4f64 (depth 4; operand lane l
+// carries row l % 16, depth l / 16; result element i of lane l is row
+// l / 16 + 4 i, column l % 16)
+template <>
+struct Mfma<double> {
+  static constexpr int BS = 16, DK = 4, NV = 4;
+  using acc_t = doublex4;
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static void operand(int lane, int &r, int &k) {
+    r = lane & 15;
+    k = lane >> 4;
+  }
+  __device__ static void coord(int lane, int i, int &row, int &col) {
+    row = (lane >> 4) + 4 * i;
+    col = lane & 15;
+  }
+};
+
+template <typename T, int TTS, bool M3>
+struct WaveAcc {
+  using F = Mfma<T>;
+  static constexpr int NBK = TTS / 2 / F::BS;   // a wave owns a TTS/2 x TTS/2 quarter
+  static constexpr int NQ = M3 ? 3 : 2;
+  typename F::acc_t q[NQ][NBK][NBK];
   __device__ void zero() {
 #pragma unroll
-    for (int a = 0; a < NBK; ++a)
+    for (int z = 0; z < NQ; ++z)
 #pragma unroll
-      for (int b = 0; b < NBK; ++b)
+      for (int a = 0; a < NBK; ++a)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          re[a][b][i] = 0.f;
-          im[a][b][i] = 0.f;
-        }
+        for (int b = 0; b < NBK; ++b)
+#pragma unroll
+          for (int i = 0; i < F::NV; ++i) q[z][a][b][i] = T(0);
   }
-  __device__ void step(const float (*Ar)[TTS], const float (*Ai)[TTS], const float (*Br)[TTS],
-                       const float (*Bi)[TTS], int wr, int wc, int lane) {
-    const int rr = lane & 31, kh = lane >> 5;
+  // Ar, Ai: rows of L (the wave's rows); Br, Bi: rows of L (its columns);
+  // Dr, Di: the pivots of the chunk's depth columns, applied here
+  __device__ void step(const T (*Ar)[TTS], const T (*Ai)[TTS], const T (*Br)[TTS],
+                       const T (*Bi)[TTS], const T *Dr, const T *Di, int wr, int wc,
+                       int lane) {
+    int rr, kh;
+    F::operand(lane, rr, kh);
 #pragma unroll
-    for (int kk = 0; kk < KB; kk += 2) {
-      float ar[NBK], ai[NBK], br[NBK], bi[NBK];
+    for (int kk = 0; kk < KB; kk += F::DK) {
+      T ar[NBK], ai[NBK], br[NBK], bi[NBK];
+      const T dr = Dr[kk + kh], di = Di[kk + kh];
 #pragma unroll
       for (int a = 0; a < NBK; ++a) {
-        ar[a] = Ar[kk + kh][wr * (TTS / 2) + a * 32 + rr];
-        ai[a] = Ai[kk + kh][wr * (TTS / 2) + a * 32 + rr];
-        br[a] = Br[kk + kh][wc * (TTS / 2) + a * 32 + rr];
-        bi[a] = Bi[kk + kh][wc * (TTS / 2) + a * 32 + rr];
+        ar[a] = Ar[kk + kh][wr * (TTS / 2) + a * F::BS + rr];
+        ai[a] = Ai[kk + kh][wr * (TTS / 2) + a * F::BS + rr];
+        const T lr = Br[kk + kh][wc * (TTS / 2) + a * F::BS + rr];
+        const T li = Bi[kk + kh][wc * (TTS / 2) + a * F::BS + rr];
+        br[a] = lr * dr - li * di;
+        bi[a] = lr * di + li * dr;
       }
 #pragma unroll
       for (int a = 0; a < NBK; ++a)
 #pragma unroll
         for (int b = 0; b < NBK; ++b) {
-          re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar[a], br[b], re[a][b], 0, 0, 0);
-          re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[a], bi[b], re[a][b], 0, 0, 0);
-          im[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar[a], bi[b], im[a][b], 0, 0, 0);
-          im[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[a], br[b], im[a][b], 0, 0, 0);
+          if constexpr (M3) {
+            q[0][a][b] = F::mma(ar[a], br[b], q[0][a][b]);
+            q[1][a][b] = F::mma(ai[a], bi[b], q[1][a][b]);
+            q[2][a][b] = F::mma(ar[a] + ai[a], br[b] + bi[b], q[2][a][b]);
+          } else {
+            q[0][a][b] = F::mma(-ar[a], br[b], q[0][a][b]);
+            q[0][a][b] = F::mma(ai[a], bi[b], q[0][a][b]);
+            q[1][a][b] = F::mma(-ar[a], bi[b], q[1][a][b]);
+            q[1][a][b] = F::mma(-ai[a], br[b], q[1][a][b]);
+          }
         }
     }
   }
-  static constexpr int nelem() { return NBK * NBK * 16; }
-  // element e of this lane -> (row, col) inside the wave's tile
+  static constexpr int nelem() { return NBK * NBK * F::NV; }
+  // element e of this lane -> (row, col) inside the wave's quarter
   __device__ static void coord(int lane, int e, int &row, int &col) {
-    const int blk = e >> 4, i = e & 15;
-    const int a = blk / NBK, b = blk % NBK;
-    row = a * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-    col = b * 32 + (lane & 31);
+    const int blk = e / F::NV, i = e % F::NV;
+    F::coord(lane, i, row, col);
+    row += (blk / NBK) * F::BS;
+    col += (blk % NBK) * F::BS;
   }
-  __device__ float get_re(int e) const { return re[(e >> 4) / NBK][(e >> 4) % NBK][e & 15]; }
-  __device__ float get_im(int e) const { return im[(e >> 4) / NBK][(e >> 4) % NBK][e & 15]; }
+  // the update's increment -A B^T at element e
+  __device__ T get_re(int e) const {
+    const int a = (e / F::NV) / NBK, b = (e / F::NV) % NBK, i = e % F::NV;
+    if constexpr (M3)
+      return q[1][a][b][i] - q[0][a][b][i];
+    else
+      return q[0][a][b][i];
+  }
+  __device__ T get_im(int e) const {
+    const int a = (e / F::NV) / NBK, b = (e / F::NV) % NBK, i = e % F::NV;
+    if constexpr (M3)
+      return (q[0][a][b][i] + q[1][a][b][i]) - q[2][a][b][i];
+    else
+      return q[1][a][b][i];
+  }
 };
 
-// FP64: blocks of 16 x 16 (v_mfma_f64_16x16x4f64), NBK x NBK blocks per wave
-template <int TTS>
-struct WaveAcc<double, TTS> {
-  static constexpr int NBK = TTS / 32;
-  doublex4 re[NBK][NBK], im[NBK][NBK];
-  __device__ void zero() {
-#pragma unroll
-    for (int a = 0; a < NBK; ++a)
-#pragma unroll
-      for (int b = 0; b < NBK; ++b)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          re[a][b][i] = 0.0;
-          im[a][b][i] = 0.0;
-        }
-  }
-  __device__ void step(const double (*Ar)[TTS], const double (*Ai)[TTS], const double (*Br)[TTS],
-                       const double (*Bi)[TTS], int wr, int wc, int lane) {
-    const int rr = lane & 15, kq = lane >> 4;
-#pragma unroll
-    for (int kk = 0; kk < KB; kk += 4) {
-      double ar[NBK], ai[NBK], br[NBK], bi[NBK];
-#pragma unroll
-      for (int a = 0; a < NBK; ++a) {
-        ar[a] = Ar[kk + kq][wr * (TTS / 2) + a * 16 + rr];
-        ai[a] = Ai[kk + kq][wr * (TTS / 2) + a * 16 + rr];
-        br[a] = Br[kk + kq][wc * (TTS / 2) + a * 16 + rr];
-        bi[a] = Bi[kk + kq][wc * (TTS / 2) + a * 16 + rr];
+// Tile number id of a lower trapezoid of nct column tiles and nrt >= nct
+// row tiles (tile (ct, rt) exists for rt >= ct) in super-column order:
+// column tiles are grouped by SUPER_W; inside a group the tiles run by row
+// tile, then column tile.  id must be below the tile count.
+constexpr int SUPER_W = 8;
+__device__ inline void trap_tile(int64_t id, int64_t nct, int64_t nrt, int64_t &ct, int64_t &rt) {
+  for (int64_t c0 = 0;; c0 += SUPER_W) {
+    const int64_t w = min((int64_t)SUPER_W, nct - c0);
+    const int64_t tri = w * (w + 1) / 2;
+    const int64_t here = tri + w * (nrt - c0 - w);
+    if (id < here) {
+      if (id < tri) {
+        int64_t r = 0;
+        while ((r + 1) * (r + 2) / 2 <= id) ++r;
+        rt = c0 + r;
+        ct = c0 + id - r * (r + 1) / 2;
+      } else {
+        const int64_t q = id - tri;
+        rt = c0 + w + q / w;
+        ct = c0 + q % w;
       }
-#pragma unroll
-      for (int a = 0; a < NBK; ++a)
-#pragma unroll
-        for (int b = 0; b < NBK; ++b) {
-          re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[a], br[b], re[a][b], 0, 0, 0);
-          re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], re[a][b], 0, 0, 0);
-          im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[a], bi[b], im[a][b], 0, 0, 0);
-          im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], br[b], im[a][b], 0, 0, 0);
-        }
+      return;
     }
+    id -= here;
   }
-  static constexpr int nelem() { return NBK * NBK * 4; }
-  __device__ static void coord(int lane, int e, int &row, int &col) {
-    const int blk = e >> 2, i = e & 3;
-    const int a = blk / NBK, b = blk % NBK;
-    row = a * 16 + (lane >> 4) + 4 * i;   // f64 16x16x4 result: row lane/16 + 4i
-    col = b * 16 + (lane & 15);
-  }
-  __device__ double get_re(int e) const { return re[(e >> 2) / NBK][(e >> 2) % NBK][e & 3]; }
-  __device__ double get_im(int e) const { return im[(e >> 2) / NBK][(e >> 2) % NBK][e & 3]; }
-};
+}
 
 // mode 0: depth (eliminated columns) [j0, j0 + dw), updated columns
 // [j0 + dw, min(k, ccap)); mode 1: depth [0, k), contribution block.
-template <typename T, int TTS>
+template <typename T, int TTS, bool M3>
 __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t *lvl_nodes,
                                                       int mode, int j0, int dw, int ccap,
                                                       cpx<T> *factor, int64_t f_stride,
@@ -371,75 +420,118 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
     l1 = k;
   }
   if (cbeg >= cend || l0 >= l1) return;
-  // linear tile id -> (column tile, row tile) over the lower trapezoid
-  int64_t t = blockIdx.x;
-  const int64_t nct = (cend - cbeg + TTS - 1) / TTS;
-  int64_t ct = 0;
-  for (; ct < nct; ++ct) {
-    const int64_t cnt = (n - (cbeg + TTS * ct) + TTS - 1) / TTS;
-    if (t < cnt) break;
-    t -= cnt;
-  }
-  if (ct >= nct) return;
+  // Work split across the eight XCDs: the grid's x extent is a multiple of
+  // 8, workgroups are handed to XCDs round robin, so x % 8 names the XCD and
+  // each XCD takes one contiguous eighth of the tile sequence, walked in
+  // super-column order so that the tiles in flight on an XCD share row and
+  // column panels in its L2.
+  const int64_t nct = (cend - cbeg + TTS - 1) / TTS, nrt = (n - cbeg + TTS - 1) / TTS;
+  const int64_t cnt = nct * nrt - nct * (nct - 1) / 2;
+  const int64_t chunk = (cnt + 7) / 8;
+  const int64_t loc = blockIdx.x >> 3;
+  if (loc >= chunk) return;
+  const int64_t id = (int64_t)(blockIdx.x & 7) * chunk + loc;
+  if (id >= cnt) return;
+  int64_t ct, rt;
+  trap_tile(id, nct, nrt, ct, rt);
   const int64_t col0 = cbeg + TTS * ct;
-  const int64_t row0 = col0 + TTS * t;
+  const int64_t row0 = cbeg + TTS * rt;
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
 
-  __shared__ T Ar[KB][TTS], Ai[KB][TTS], Br[KB][TTS], Bi[KB][TTS];
+  __shared__ T Ar[2][KB][TTS], Ai[2][KB][TTS], Br[2][KB][TTS], Bi[2][KB][TTS];
+  __shared__ T Dr[2][KB], Di[2][KB];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
   constexpr int PER = TTS * KB / 256;   // elements of A (and of B) per thread and chunk
   const int lr = tid % TTS;             // tile row this thread loads
   const int lk = (tid / TTS) * PER;     // first depth column it loads
-  cpx<T> pa[PER], pb[PER];
+  // Prefetch of the next depth chunk: unconditional loads from clamped
+  // (in-bounds) addresses, so nothing waits on them until the chunk is
+  // written to LDS, where the masking happens.  Clamped rows stay in the
+  // panel block: every row index is >= cbeg >= l1.  Threads tid < KB also
+  // fetch the pivot D of depth column l + tid.
+  cpx<T> pa[PER], pb[PER], pd;
+  int64_t pl = l0;
+  const int64_t ra = row0 + lr, rb = col0 + lr;
+  const int64_t rac = min(ra, n - 1), rbc = min(rb, n - 1);
   auto fetch = [&](int64_t l) {
     const int64_t b = l / NB, r0 = NB * b, ldb = n - r0;
-    const cpx<T> *base = P + panel_block_off(n, b);
-    const int64_t ra = row0 + lr, rb = col0 + lr;
+    const cpx<T> *base = P + panel_block_off(n, b) - r0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int64_t lc = l + lk + q;
-      cpx<T> a = czero<T>(), bb = czero<T>();
-      if (lc < l1) {
-        const cpx<T> *colp = base + (lc - r0) * ldb - r0;
-        if (ra < n) a = colp[ra];
-        if (rb < n) bb = cmul(colp[rb], colp[lc]);
-      }
-      pa[q] = a;
-      pb[q] = bb;
+      const int64_t lc = min(l + lk + q, l1 - 1);
+      const cpx<T> *colp = base + (lc - r0) * ldb;
+      pa[q] = colp[rac];
+      pb[q] = colp[rbc];
+    }
+    const int64_t ld = min(l + (tid % KB), l1 - 1);
+    pd = base[(ld - r0) * ldb + ld];
+    pl = l;
+  };
+  // registers -> LDS buffer bf, masked (columns past l1 get D = 0)
+  auto stage = [&](int bf) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const bool okc = pl + lk + q < l1;
+      const cpx<T> a = (okc && ra < n) ? pa[q] : czero<T>();
+      const cpx<T> bb = (okc && rb < n) ? pb[q] : czero<T>();
+      Ar[bf][lk + q][lr] = a.re;
+      Ai[bf][lk + q][lr] = a.im;
+      Br[bf][lk + q][lr] = bb.re;
+      Bi[bf][lk + q][lr] = bb.im;
+    }
+    if (tid < KB) {
+      const bool okd = pl + tid < l1;
+      Dr[bf][tid] = okd ? pd.re : T(0);
+      Di[bf][tid] = okd ? pd.im : T(0);
     }
   };
-  WaveAcc<T, TTS> acc;
+  // two LDS buffers: chunk i+1 is loaded while chunk i is multiplied, one
+  // barrier per chunk
+  WaveAcc<T, TTS, M3> acc;
   acc.zero();
   fetch(l0);
+  stage(0);
+  __syncthreads();
+  int bf = 0;
   for (int64_t l = l0; l < l1; l += KB) {
+    const bool more = l + KB < l1;
+    if (more) fetch(l + KB);
+    acc.step(Ar[bf], Ai[bf], Br[bf], Bi[bf], Dr[bf], Di[bf], wr, wc, lane);
+    if (more) stage(bf ^ 1);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      Ar[lk + q][lr] = pa[q].re;
-      Ai[lk + q][lr] = pa[q].im;
-      Br[lk + q][lr] = pb[q].re;
-      Bi[lk + q][lr] = pb[q].im;
-    }
-    __syncthreads();
-    if (l + KB < l1) fetch(l + KB);
-    acc.step(Ar, Ai, Br, Bi, wr, wc, lane);
+    bf ^= 1;
   }
-  // epilogue: C += acc on the lower triangle
+  // epilogue: C += acc on the lower triangle, four entries at a time: their
+  // loads are issued together (entries outside the triangle read the tile's
+  // corner (row0, col0), which always exists), then the valid ones stored.
   cpx<T> *Cb = (mode == 1) ? cb + (int64_t)p * cb_stride + ft.cb_off[s] : nullptr;
   cpx<T> *Pw = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  constexpr int NE = WaveAcc<T, TTS, M3>::nelem(), GE = 4;
 #pragma unroll
-  for (int e = 0; e < WaveAcc<T, TTS>::nelem(); ++e) {
-    int rr, cc;
-    WaveAcc<T, TTS>::coord(lane, e, rr, cc);
-    const int64_t row = row0 + wr * (TTS / 2) + rr, col = col0 + wc * (TTS / 2) + cc;
-    if (row >= n || col >= cend || row < col) continue;
-    cpx<T> *q = (mode == 1) ? Cb + (col - k) * u + (row - k) : Pw + panel_elem(n, row, col);
-    cpx<T> v = *q;
-    v.re += acc.get_re(e);
-    v.im += acc.get_im(e);
-    *q = v;
+  for (int e0 = 0; e0 < NE; e0 += GE) {
+    cpx<T> *qp[GE];
+    bool ok[GE];
+    cpx<T> cv[GE];
+#pragma unroll
+    for (int j = 0; j < GE; ++j) {
+      int rr, cc;
+      WaveAcc<T, TTS, M3>::coord(lane, e0 + j, rr, cc);
+      const int64_t row = row0 + wr * (TTS / 2) + rr, col = col0 + wc * (TTS / 2) + cc;
+      ok[j] = !(row >= n || col >= cend || row < col);
+      const int64_t r = ok[j] ? row : row0, c = ok[j] ? col : col0;
+      qp[j] = (mode == 1) ? Cb + (c - k) * u + (r - k) : Pw + panel_elem(n, r, c);
+      cv[j] = *qp[j];
+    }
+#pragma unroll
+    for (int j = 0; j < GE; ++j) {
+      if (!ok[j]) continue;
+      cpx<T> v = cv[j];
+      v.re += acc.get_re(e0 + j);
+      v.im += acc.get_im(e0 + j);
+      *qp[j] = v;
+    }
   }
 }
 
@@ -447,15 +539,24 @@ template <typename T>
 hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                                int mode, int j0, int dw, int ccap, int64_t max_tiles, int npole,
                                cpx<T> *factor, int64_t f_stride, cpx<T> *cb, int64_t cb_stride,
-                               int tile) {
+                               int tile, bool m3) {
   if (n_nodes <= 0 || max_tiles <= 0) return hipSuccess;
-  dim3 grid((unsigned)max_tiles, n_nodes, npole);
-  if (tile == 128)
-    hipLaunchKernelGGL((k_front_update<T, 128>), grid, dim3(256), 0, st, ft, lvl_nodes, mode, j0,
-                       dw, ccap, factor, f_stride, cb, cb_stride);
+  dim3 grid((unsigned)(8 * ((max_tiles + 7) / 8)), n_nodes, npole);
+#define TEM_UPD(TT, M)                                                                            \
+  hipLaunchKernelGGL((k_front_update<T, TT, M>), grid, dim3(256), 0, st, ft, lvl_nodes, mode, j0, \
+                     dw, ccap, factor, f_stride, cb, cb_stride)
+  if constexpr (sizeof(T) == 4) {
+    if (tile == 128) {   // 4M only: the 3M accumulators do not fit beside it
+      TEM_UPD(128, false);
+      return hipGetLastError();
+    }
+  }
+  if (tile != 64) return hipErrorInvalidValue;   // FP64 runs 64-tiles only
+  if (m3)
+    TEM_UPD(64, true);
   else
-    hipLaunchKernelGGL((k_front_update<T, 64>), grid, dim3(256), 0, st, ft, lvl_nodes, mode, j0,
-                       dw, ccap, factor, f_stride, cb, cb_stride);
+    TEM_UPD(64, false);
+#undef TEM_UPD
   return hipGetLastError();
 }
 
@@ -473,7 +574,7 @@ hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_n
                                            int, cpx<T> *, int64_t);                              \
   template hipError_t launch_front_update<T>(hipStream_t, FrontTab, const int32_t *, int, int,    \
                                              int, int, int, int64_t, int, cpx<T> *, int64_t,      \
-                                             cpx<T> *, int64_t, int);
+                                             cpx<T> *, int64_t, int, bool);
 TEM_INST(float)
 TEM_INST(double)
 #undef TEM_INST

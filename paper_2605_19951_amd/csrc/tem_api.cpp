@@ -142,6 +142,8 @@ struct tem_ctx {
   int64_t sweep_bb = 256;          // big column block of the wide-front sweeps
   int64_t sweep_big_limit = 1024;  // fronts x poles below which a level is "wide"
   bool upd_tile128 = false;        // 128 x 128 MFMA update tiles (FP32)
+  bool upd_m3_f32 = true;          // 3M complex products in the FP32 update
+  bool upd_m3_f64 = false;         // 3M complex products in the FP64 update
   // factors
   int npole = 0;
   tem_precision prec = TEM_FP64;
@@ -500,6 +502,11 @@ void spans_collect(tem_ctx *c) {
   c->ev_used = 0;
 }
 
+template <typename T>
+bool upd_m3(const tem_ctx *c) {
+  return sizeof(T) == 4 ? c->upd_m3_f32 : c->upd_m3_f64;
+}
+
 FrontTab front_tab(const MF &mf) {
   FrontTab ft;
   ft.first = mf.d_first.as<int64_t>();
@@ -576,7 +583,7 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, const d
       if (max_tiles == 0) return TEM_OK;
       hipEvent_t ea = span_begin(c);
       HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 0, j0, dw, ccap, max_tiles, g, F,
-                                    mf.pole_stride, cbL, mf.cb_stride, tt),
+                                    mf.pole_stride, cbL, mf.cb_stride, tt, upd_m3<T>(c)),
              "trailing update");
       span_end(c, ea, fl, 0);
       return TEM_OK;
@@ -611,7 +618,7 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, const d
     }
     hipEvent_t ea = span_begin(c);
     HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, 0, 0, cb_tiles, g, F, mf.pole_stride,
-                                  cbL, mf.cb_stride, ttc),
+                                  cbL, mf.cb_stride, ttc, upd_m3<T>(c)),
            "contribution update");
     span_end(c, ea, fl, 0);
   }
@@ -1182,6 +1189,11 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
     if (b >= 0) c->sweep_big_limit = b;
   }
   if (const char *v = std::getenv("TEM_UPDATE_TILE")) c->upd_tile128 = std::strtol(v, nullptr, 10) == 128;
+  if (const char *v = std::getenv("TEM_UPDATE_3M")) {   // "f32", "f64", "both" or "none"
+    const std::string m(v);
+    c->upd_m3_f32 = m == "f32" || m == "both";
+    c->upd_m3_f64 = m == "f64" || m == "both";
+  }
   e = c->d_flags.alloc(sizeof(int) * 4);
   if (e != hipSuccess) {
     g_create_error = "tem_create: flags allocation failed";

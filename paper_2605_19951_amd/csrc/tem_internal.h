@@ -93,13 +93,14 @@ hipError_t launch_panel_trsm(hipStream_t st, FrontTab ft, const int32_t *lvl_nod
 
 // mode 0: trailing update of panel columns [j0+dw, min(k, ccap)) by the
 // eliminated columns [j0, j0+dw); mode 1: contribution block
-// C -= L21 D L21^T.  tile = 64 or 128 (output tile edge; max_tiles counted
-// with the same edge).
+// C -= L21 D L21^T.  tile = 64 or 128 (output tile edge, 128 for FP32
+// only; max_tiles counted with the same edge); m3: complex products with
+// three real matrix-core products instead of four.
 template <typename T>
 hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                                int mode, int j0, int dw, int ccap, int64_t max_tiles, int npole,
                                cpx<T> *factor, int64_t f_stride, cpx<T> *cb, int64_t cb_stride,
-                               int tile);
+                               int tile, bool m3);
 
 // ------------------------------------------------------------------ solves
 // Vectors are [pole][N][S] complex T (S fastest), S <= 16.
