@@ -264,6 +264,62 @@ tem_status tem_gn_step(tem_ctx *ctx, const double *d_obs, const double *wd, cons
                        const double *m_ref, double lambda, int32_t iters, double *dm,
                        double *hist, const tem_ir_opts *ir);
 
+/* ------------------------------------------------------ ragged batches
+ * Several independent meshes solved together: the per-pole shifted systems
+ * of every mesh (the paper's Algorithm 1, repeated per mesh) are merged
+ * into one block-diagonal system, so that each level of the multifrontal
+ * factorisation and of the sweeps is one launch over the fronts of all
+ * meshes and all poles.  Meshes may differ in size, pole count and source
+ * count; missing poles of a mesh are not computed.  After
+ * tem_assemble_batch the context is in batch mode: tem_analyse (with its
+ * usual options) analyses every mesh, then tem_factor_poles_batch and
+ * tem_forward_batch apply.  tem_set_model, tem_factor_poles,
+ * tem_solve_poles, tem_forward, tem_jvp, tem_vjp, tem_gn_step and
+ * tem_export_operators return TEM_ESTATE in batch mode; tem_assemble
+ * returns the context to single-mesh mode. */
+
+/* Assemble K and M(sigma) of n_mesh meshes (1..4096).
+ *   meshes       host, n_mesh descriptions (as in tem_assemble).
+ *   sigma_cells  device, concatenated cell conductivities: mesh b's
+ *                nx*ny*nz cells follow those of meshes 0..b-1, each block
+ *                in tem_assemble's cell order.
+ * The same meshes again (same sizes, h and mu) keep the analysis and only
+ * refresh the values (a new model); other meshes reset the batch. */
+tem_status tem_assemble_batch(tem_ctx *ctx, int32_t n_mesh, const tem_mesh *meshes,
+                              const double *sigma_cells);
+
+/* Factor A_bi = K_b - xi_bi M_b for every mesh b and each of its m[b]
+ * poles (as tem_factor_poles).
+ *   m    host, n_mesh pole counts (1..4096 each).
+ *   xi   host, sum(m) complex poles (re, im interleaved), mesh-major:
+ *        mesh b's poles follow those of meshes 0..b-1; Im > 0. */
+tem_status tem_factor_poles_batch(tem_ctx *ctx, const int32_t *m, const double *xi,
+                                  tem_precision prec, const tem_factor_opts *opts);
+
+/* Forward map of every mesh (as tem_forward), with refinement to ir->rtol
+ * judged per mesh, pole and source.  Blocks are concatenated mesh-major:
+ *   S      host, n_mesh source counts (1..16 each).
+ *   F      device, mesh b's n_edges_b x S[b] column-major block follows
+ *          those of meshes 0..b-1.
+ *   R      host, n_mesh receiver counts (>= 1 each).
+ *   q_ptr  host, mesh b's R[b]+1 row pointers (each block starts at 0)
+ *          follow those of the previous meshes; q_col / q_val: mesh b's
+ *          entries (canonical edge ids of mesh b) follow likewise.
+ *   K      number of times (shared by all meshes).
+ *   alpha  host, mesh b's K x m[b] complex residues (time slowest) follow
+ *          those of the previous meshes.
+ *   d      device, mesh b's S[b]*K*R[b] doubles ([s][j][r]) follow those of
+ *          the previous meshes.
+ *   stats  iters / final_rel_res (if not NULL) hold n_mesh*MP*Smax entries
+ *          [mesh][pole][source] with MP = max m, Smax = max S; slots past a
+ *          mesh's own poles or sources read 0.
+ * Returns TEM_ENOCONV (after filling d and stats) if some system missed
+ * the tolerance. */
+tem_status tem_forward_batch(tem_ctx *ctx, const int32_t *S, const double *F, const int32_t *R,
+                             const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
+                             int32_t K, const double *alpha, const tem_ir_opts *ir, double *d,
+                             tem_ir_stats *stats);
+
 /* ------------------------------------------------------------ statistics */
 
 typedef struct {

@@ -36,6 +36,24 @@ __device__ __forceinline__ cpx<T> czero() {
   return {T(0), T(0)};
 }
 
+// segment of index i (0 for a single mesh)
+__device__ __forceinline__ int seg_find(const Seg &sg, int64_t i) {
+  if (sg.n <= 1) return 0;
+  int lo = 0, hi = sg.n - 1;   // largest b with off[b] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sg.off[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+// pole slot p of front s is padding (nothing to compute)
+__device__ __forceinline__ bool pole_absent(const FrontTab &ft, int s, int p) {
+  return ft.np && ft.p0 + p >= ft.np[s];
+}
+
 inline unsigned grid_1d(int64_t n, int block, int64_t cap = 65535 * 16) {
   int64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;

@@ -26,17 +26,19 @@ hipError_t launch_fill_zero(hipStream_t st, cpx<T> *base, int64_t count, int npo
 }
 
 // ------------------------------------------------------ original entries
-// factor[pole][pos[i]] = K[csr[i]] - xi_pole * M[csr[i]]
+// factor[pole][pos[i]] = K[csr[i]] - xi * M[csr[i]], xi the pole's shift for
+// the mesh that owns matrix entry csr[i] (sg: entry segments)
 template <typename T>
 __global__ void k_front_assemble(int64_t n, const int32_t *csr, const int64_t *pos,
-                                 const double *Kv, const double *Mv, const double *xi,
+                                 const double *Kv, const double *Mv, const double *xi, Seg sg,
                                  cpx<T> *factor, int64_t pole_stride) {
   const int p = blockIdx.y;
-  const double xr = xi[2 * p], xim = xi[2 * p + 1];
   cpx<T> *F = factor + (int64_t)p * pole_stride;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t e = csr[i];
+    const int64_t xo = 2 * ((int64_t)seg_find(sg, e) * sg.stride + p);
+    const double xr = xi[xo], xim = xi[xo + 1];
     const double kv = Kv[e], mv = Mv[e];
     cpx<T> v;
     v.re = (T)(kv - xr * mv);
@@ -48,12 +50,12 @@ __global__ void k_front_assemble(int64_t n, const int32_t *csr, const int64_t *p
 template <typename T>
 hipError_t launch_front_assemble(hipStream_t st, int64_t n_entries, const int32_t *csr,
                                  const int64_t *pos, const double *Kv, const double *Mv,
-                                 const double *xi, int npole, cpx<T> *factor,
+                                 const double *xi, Seg sg, int npole, cpx<T> *factor,
                                  int64_t pole_stride) {
   if (n_entries <= 0) return hipSuccess;
   dim3 grid(grid_1d(n_entries, 256, 8192), npole);
   hipLaunchKernelGGL(k_front_assemble<T>, grid, dim3(256), 0, st, n_entries, csr, pos, Kv, Mv,
-                     xi, factor, pole_stride);
+                     xi, sg, factor, pole_stride);
   return hipGetLastError();
 }
 
@@ -67,6 +69,7 @@ __global__ void k_extend_add(FrontTab ft, const int32_t *lvl_nodes, int slot, cp
                              int64_t cb_stride) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
   const int ch = slot == 0 ? ft.child0[s] : ft.child1[s];
   if (ch < 0) return;
   const int64_t uc = ft.u[ch];
@@ -116,6 +119,7 @@ __global__ __launch_bounds__(256) void k_panel_diag(FrontTab ft, const int32_t *
                                                     int *flags) {
   const int s = lvl_nodes[blockIdx.x];
   const int p = blockIdx.y;
+  if (pole_absent(ft, s, p)) return;
   const int k = ft.k[s];
   if (j0 >= k) return;
   const int w = min(NB, k - j0);
@@ -184,6 +188,7 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FrontTab ft, const int32_t *
                                                     cpx<T> *factor, int64_t f_stride) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
   const int k = ft.k[s];
   if (j0 >= k) return;
   const int w = min(NB, k - j0);
@@ -406,6 +411,7 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
                                                       cpx<T> *cb, int64_t cb_stride) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u;
   int64_t cbeg, cend, l0, l1;
   if (mode == 0) {
@@ -565,7 +571,7 @@ hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_n
   template hipError_t launch_fill_zero<T>(hipStream_t, cpx<T> *, int64_t, int, int64_t);         \
   template hipError_t launch_front_assemble<T>(hipStream_t, int64_t, const int32_t *,            \
                                                const int64_t *, const double *, const double *,  \
-                                               const double *, int, cpx<T> *, int64_t);          \
+                                               const double *, Seg, int, cpx<T> *, int64_t);     \
   template hipError_t launch_extend_add<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \
                                            int, cpx<T> *, int64_t, cpx<T> *, cpx<T> *, int64_t);  \
   template hipError_t launch_panel_diag<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \

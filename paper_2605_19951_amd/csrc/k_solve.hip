@@ -34,6 +34,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
                                                  int64_t cb, int64_t BB) {
   const int s = lvl_nodes[blockIdx.x];
   const int p = blockIdx.y;
+  if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
   if (k == 0 || cb >= k) return;
   const int64_t ce = min(k, cb + BB);
@@ -119,6 +120,7 @@ __global__ __launch_bounds__(256) void k_fwd_rows(FrontTab ft, const int32_t *lv
                                                   int64_t BB) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
   const int64_t ce = min(k, cb + BB);
   const int64_t a0 = ce + (int64_t)blockIdx.x * RT;
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(256) void k_fwd_rect(FrontTab ft, const int32_t *lv
                                                   int64_t w_stride) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
   const int64_t a0 = (int64_t)blockIdx.x * RT;
   if (a0 >= u) return;
@@ -279,6 +282,7 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
                                                   int64_t t_stride) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
   const int64_t jb = (int64_t)blockIdx.x * NB;
   if (jb >= k) return;
@@ -373,6 +377,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
                                                  int init) {
   const int s = lvl_nodes[blockIdx.x];
   const int p = blockIdx.y;
+  if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
   if (k == 0 || cb >= k) return;
   const int64_t ce = min(k, cb + BB);
@@ -464,6 +469,7 @@ __global__ void k_bwd_init(FrontTab ft, const int32_t *lvl_nodes, int S, int64_t
                            int64_t t_stride) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= k * S) return;
@@ -496,6 +502,7 @@ __global__ __launch_bounds__(256) void k_bwd_cols(FrontTab ft, const int32_t *lv
                                                   int64_t BB) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
   const int64_t jb = (int64_t)blockIdx.x * NB;
   if (cb >= k || jb >= cb) return;

@@ -76,15 +76,17 @@ hipError_t launch_assemble_KM(hipStream_t st, int64_t N, const int64_t *rowptr, 
 // one thread per (row, pole, rhs); x, y, r: [pole][N][S]
 __global__ void k_residual(int64_t N, int npole, int S, const int64_t *rowptr,
                            const int32_t *col, const double *Kv, const double *Mv,
-                           const double *xi, const double *f_real, const cpx<double> *f_cplx,
-                           const cpx<double> *x, cpx<double> *r, int mode) {
+                           const double *xi, Seg sg, const double *f_real,
+                           const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r,
+                           int mode) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t mS = (int64_t)npole * S;
   if (idx >= N * mS) return;
   const int64_t q = idx / mS;
   const int ps = (int)(idx % mS);
   const int p = ps / S, c = ps % S;
-  const double xr = xi[2 * p], xim = xi[2 * p + 1];
+  const int64_t xo = 2 * ((int64_t)seg_find(sg, q) * sg.stride + p);
+  const double xr = xi[xo], xim = xi[xo + 1];
   const cpx<double> *X = x + (int64_t)p * N * S + c;
   double ar = 0.0, ai = 0.0;
   for (int64_t t = rowptr[q]; t < rowptr[q + 1]; ++t) {
@@ -116,20 +118,20 @@ __global__ void k_residual(int64_t N, int npole, int S, const int64_t *rowptr,
 
 hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                            const int32_t *col, const double *Kv, const double *Mv,
-                           const double *xi, const double *f_real, const cpx<double> *f_cplx,
-                           const cpx<double> *x, cpx<double> *r) {
+                           const double *xi, Seg sg, const double *f_real,
+                           const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r) {
   const int64_t tot = N * npole * S;
   hipLaunchKernelGGL(k_residual, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     rowptr, col, Kv, Mv, xi, f_real, f_cplx, x, r, 1);
+                     rowptr, col, Kv, Mv, xi, sg, f_real, f_cplx, x, r, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                                const int32_t *col, const double *Kv, const double *Mv,
-                               const double *xi, const cpx<double> *x, cpx<double> *y) {
+                               const double *xi, Seg sg, const cpx<double> *x, cpx<double> *y) {
   const int64_t tot = N * npole * S;
   hipLaunchKernelGGL(k_residual, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     rowptr, col, Kv, Mv, xi, nullptr, nullptr, x, y, 0);
+                     rowptr, col, Kv, Mv, xi, sg, nullptr, nullptr, x, y, 0);
   return hipGetLastError();
 }
 
@@ -138,7 +140,8 @@ hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, cons
 // Stage 2: one thread per system sums the chunk partials in order.
 constexpr int DOT_BLOCK = 256;
 
-__global__ __launch_bounds__(DOT_BLOCK) void k_dot_stage1(int64_t N, int S, const cpx<double> *a,
+__global__ __launch_bounds__(DOT_BLOCK) void k_dot_stage1(int64_t N, int S, int64_t pstride,
+                                                          const cpx<double> *a,
                                                           const cpx<double> *b, int conj_a,
                                                           int n_chunks, cpx<double> *partial) {
   const int chunk = blockIdx.x, p = blockIdx.y;
@@ -150,8 +153,8 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_dot_stage1(int64_t N, int S, cons
   const int64_t r0 = (int64_t)chunk * per, r1 = min(N, r0 + per);
   double sr = 0.0, si = 0.0;
   if (rl < lanes) {
-    const cpx<double> *A = a + (int64_t)p * N * S;
-    const cpx<double> *B = b + (int64_t)p * N * S;
+    const cpx<double> *A = a + (int64_t)p * pstride;
+    const cpx<double> *B = b + (int64_t)p * pstride;
     for (int64_t q = r0 + rl; q < r1; q += lanes) {
       const cpx<double> x = A[q * S + c], y = B[q * S + c];
       const double xi = conj_a ? -x.im : x.im;
@@ -188,25 +191,28 @@ __global__ void k_dot_stage2(int npole, int S, int n_chunks, const cpx<double> *
   out[ps] = {sr, si};
 }
 
-hipError_t launch_batched_dot(hipStream_t st, int64_t N, int npole, int S, const cpx<double> *a,
-                              const cpx<double> *b, bool conj_a, cpx<double> *partial,
-                              int n_partial_blocks, cpx<double> *out) {
-  hipLaunchKernelGGL(k_dot_stage1, dim3(n_partial_blocks, npole), dim3(DOT_BLOCK), 0, st, N, S, a,
-                     b, conj_a ? 1 : 0, n_partial_blocks, partial);
+hipError_t launch_batched_dot(hipStream_t st, int64_t N, int npole, int S, int64_t pstride,
+                              const cpx<double> *a, const cpx<double> *b, bool conj_a,
+                              cpx<double> *partial, int n_partial_blocks, cpx<double> *out) {
+  hipLaunchKernelGGL(k_dot_stage1, dim3(n_partial_blocks, npole), dim3(DOT_BLOCK), 0, st, N, S,
+                     pstride, a, b, conj_a ? 1 : 0, n_partial_blocks, partial);
   hipLaunchKernelGGL(k_dot_stage2, dim3((npole * S + 127) / 128), dim3(128), 0, st, npole, S,
                      n_partial_blocks, partial, out);
   return hipGetLastError();
 }
 
 __global__ void k_axpy(int64_t N, int npole, int S, const cpx<double> *alpha, double sign,
-                       const cpx<double> *x, cpx<double> *y, const int *mask) {
+                       const cpx<double> *x, cpx<double> *y, const int *mask, Seg sg) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tot = N * npole * S;
   if (idx >= tot) return;
   const int c = (int)(idx % S);
   const int p = (int)(idx / ((int64_t)N * S));
   const int ps = p * S + c;
-  if (mask && mask[ps] == 0) return;
+  if (mask) {
+    const int64_t q = (idx / S) % N;
+    if (mask[(int64_t)seg_find(sg, q) * npole * S + ps] == 0) return;
+  }
   cpx<double> a = alpha[ps];
   a.re *= sign;
   a.im *= sign;
@@ -219,10 +225,10 @@ __global__ void k_axpy(int64_t N, int npole, int S, const cpx<double> *alpha, do
 
 hipError_t launch_batched_axpy(hipStream_t st, int64_t N, int npole, int S,
                                const cpx<double> *alpha, double sign, const cpx<double> *x,
-                               cpx<double> *y, const int *mask) {
+                               cpx<double> *y, const int *mask, Seg sg) {
   const int64_t tot = N * npole * S;
   hipLaunchKernelGGL(k_axpy, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     alpha, sign, x, y, mask);
+                     alpha, sign, x, y, mask, sg);
   return hipGetLastError();
 }
 
@@ -303,19 +309,20 @@ template hipError_t launch_convert_out<double>(hipStream_t, int64_t, int, int,
                                                cpx<double> *);
 
 // --------------------------------------------------------- edge layouts
-__global__ void k_gather_rhs(int64_t N, int S, int64_t n_edges, const int32_t *row_edge,
+__global__ void k_gather_rhs(int64_t N, int S, int ldS, int64_t n_edges, const int32_t *row_edge,
                              const double *F, double *f_new) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= N * S) return;
   const int64_t q = idx / S;
   const int c = (int)(idx % S);
-  f_new[idx] = F[(int64_t)c * n_edges + row_edge[q]];
+  f_new[q * ldS + c] = F[(int64_t)c * n_edges + row_edge[q]];
 }
 
-hipError_t launch_gather_rhs(hipStream_t st, int64_t N, int S, int64_t n_edges,
+hipError_t launch_gather_rhs(hipStream_t st, int64_t N, int S, int ldS, int64_t n_edges,
                              const int32_t *row_edge, const double *F, double *f_new) {
+  if (N * S <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_rhs, dim3(grid_1d(N * S, 256, 1 << 30)), dim3(256), 0, st, N, S,
-                     n_edges, row_edge, F, f_new);
+                     ldS, n_edges, row_edge, F, f_new);
   return hipGetLastError();
 }
 
@@ -343,8 +350,8 @@ hipError_t launch_scatter_solution(hipStream_t st, int64_t N, int npole, int S, 
 
 // ------------------------------------------------------- time assembly
 // d[s][j][r] = 2 Re sum_i alpha[j][i] (Q g_is)_r, Neumaier-compensated over i
-__global__ void k_time_assembly(int S, int K, int R, int npole, int64_t N, const int64_t *q_ptr,
-                                const int32_t *q_col, const double *q_val,
+__global__ void k_time_assembly(int S, int K, int R, int npole, int64_t N, int ldS,
+                                const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
                                 const cpx<double> *alpha, const cpx<double> *g, double *d) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)S * K * R) return;
@@ -355,7 +362,7 @@ __global__ void k_time_assembly(int S, int K, int R, int npole, int64_t N, const
   for (int i = 0; i < npole; ++i) {
     double yr = 0.0, yi = 0.0;
     for (int64_t t = q_ptr[r]; t < q_ptr[r + 1]; ++t) {
-      const cpx<double> v = g[((int64_t)i * N + q_col[t]) * S + s];
+      const cpx<double> v = g[((int64_t)i * N + q_col[t]) * ldS + s];
       yr += q_val[t] * v.re;
       yi += q_val[t] * v.im;
     }
@@ -369,12 +376,12 @@ __global__ void k_time_assembly(int S, int K, int R, int npole, int64_t N, const
   d[idx] = sum + comp;
 }
 
-hipError_t launch_time_assembly(hipStream_t st, int S, int K, int R, int npole, int64_t N,
+hipError_t launch_time_assembly(hipStream_t st, int S, int K, int R, int npole, int64_t N, int ldS,
                                 const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
                                 const cpx<double> *alpha, const cpx<double> *g, double *d) {
   const int64_t tot = (int64_t)S * K * R;
   hipLaunchKernelGGL(k_time_assembly, dim3(grid_1d(tot, 128, 1 << 30)), dim3(128), 0, st, S, K, R,
-                     npole, N, q_ptr, q_col, q_val, alpha, g, d);
+                     npole, N, ldS, q_ptr, q_col, q_val, alpha, g, d);
   return hipGetLastError();
 }
 
@@ -636,7 +643,8 @@ hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int64_t N
 
 // z[p][q][s] += coef[p] * (y[p][end(q)][s] - y[p][start(q)][s])
 __global__ void k_grad_add(int64_t N, int npole, int S, int64_t Nn, const int32_t *edge_nodes,
-                           const cpx<double> *coef, const cpx<double> *y, cpx<double> *z) {
+                           const cpx<double> *coef, Seg sg, const cpx<double> *y,
+                           cpx<double> *z) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t mS = (int64_t)npole * S;
   if (idx >= N * mS) return;
@@ -654,7 +662,7 @@ __global__ void k_grad_add(int64_t N, int npole, int S, int64_t Nn, const int32_
     gr -= Y[(int64_t)a * S].re;
     gi -= Y[(int64_t)a * S].im;
   }
-  const cpx<double> k = coef[p];
+  const cpx<double> k = coef[(int64_t)seg_find(sg, q) * sg.stride + p];
   cpx<double> *Z = z + ((int64_t)p * N + q) * S + c;
   cpx<double> v = *Z;
   v.re += k.re * gr - k.im * gi;
@@ -663,11 +671,11 @@ __global__ void k_grad_add(int64_t N, int npole, int S, int64_t Nn, const int32_
 }
 
 hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int64_t Nn,
-                           const int32_t *edge_nodes, const cpx<double> *coef,
+                           const int32_t *edge_nodes, const cpx<double> *coef, Seg sg,
                            const cpx<double> *y, cpx<double> *z) {
   const int64_t tot = N * npole * S;
   hipLaunchKernelGGL(k_grad_add, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     Nn, edge_nodes, coef, y, z);
+                     Nn, edge_nodes, coef, sg, y, z);
   return hipGetLastError();
 }
 

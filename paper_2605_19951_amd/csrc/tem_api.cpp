@@ -114,6 +114,13 @@ struct MF {
   int64_t cb_stride = 0;           // max level CB elements per pole
   int64_t w_rows_max = 0;
   DBuf w_t, w_w0, w_w1;            // sweep work space
+  DBuf d_np;                       // batch: poles of each front's mesh (else empty)
+  std::vector<int32_t> h_np;
+  // poles of front s among the g slots starting at p0
+  int present(int s, int p0, int g) const {
+    if (h_np.empty()) return g;
+    return std::max(0, std::min(g, h_np[s] - p0));
+  }
 };
 
 }  // namespace
@@ -144,8 +151,24 @@ struct tem_ctx {
   bool upd_tile128 = false;        // 128 x 128 MFMA update tiles (FP32)
   bool upd_m3_f32 = true;          // 3M complex products in the FP32 update
   bool upd_m3_f64 = false;         // 3M complex products in the FP64 update
+  // Batch of meshes (B > 0): the per-mesh contexts in `sub` assemble and
+  // analyse each mesh; this context holds the merged block-diagonal edge and
+  // nodal systems (mesh b owns edge rows [row_off[b], row_off[b+1]), matrix
+  // entries [nnz_off[b], nnz_off[b+1]), nodal rows [node_off[b], ...)).
+  // Pole tables are [mesh][MP], MP the largest pole count; absent poles of a
+  // mesh are padding that no kernel computes.
+  int B = 0;
+  std::vector<tem_ctx *> sub;
+  std::vector<int64_t> row_off, nnz_off, node_off, nnz_node_off, cell_off;
+  std::vector<int> np_mesh;
+  int MP = 0;
+  DBuf d_row_seg, d_nnz_seg;
+  std::vector<int32_t> h_node_edges, h_edge_nodes;   // nodal incidence (host copies)
+  std::vector<int> S_mesh, R_mesh;
+  int S_max = 0;
   // factors
-  int npole = 0;
+  int npole = 0;                   // pole slots (a batch: the largest pole count)
+  int64_t fac_elems = 0;           // factor elements of the poles present
   tem_precision prec = TEM_FP64;
   std::vector<double> xi;
   DBuf d_xi, d_factor, d_cb0, d_cb1, d_flags;
@@ -210,7 +233,26 @@ tem_status hip_fail(tem_ctx *c, hipError_t e, const char *where) {
     if (s_ != TEM_OK) return s_;   \
   } while (0)
 
-int64_t N_of(const tem_ctx *c) { return c->mt.n_unknowns; }
+int64_t N_of(const tem_ctx *c) { return c->ed.N; }
+
+// systems per (pole, source) slot: one per mesh of a batch
+int n_seg(const tem_ctx *c) { return c->B > 0 ? c->B : 1; }
+Seg row_seg(const tem_ctx *c) {
+  Seg sg;
+  if (c->B > 0) {
+    sg.n = c->B;
+    sg.off = c->d_row_seg.as<int64_t>();
+    sg.stride = c->MP;
+  } else {
+    sg.stride = c->npole;
+  }
+  return sg;
+}
+Seg nnz_seg(const tem_ctx *c) {
+  Seg sg = row_seg(c);
+  if (c->B > 0) sg.off = c->d_nnz_seg.as<int64_t>();
+  return sg;
+}
 
 // --------------------------------------------------- assembly on the device
 tem_status run_assemble_edges(tem_ctx *c) {
@@ -507,8 +549,10 @@ bool upd_m3(const tem_ctx *c) {
   return sizeof(T) == 4 ? c->upd_m3_f32 : c->upd_m3_f64;
 }
 
-FrontTab front_tab(const MF &mf) {
+FrontTab front_tab(const MF &mf, int p0 = 0) {
   FrontTab ft;
+  ft.np = mf.d_np.p ? mf.d_np.as<int32_t>() : nullptr;
+  ft.p0 = p0;
   ft.first = mf.d_first.as<int64_t>();
   ft.k = mf.d_k.as<int32_t>();
   ft.u = mf.d_u.as<int32_t>();
@@ -534,10 +578,11 @@ const int32_t *lvl_ptr(const MF &mf, const LevelInfo &li) {
 // Factor g matrices Kv - xi_p Mv (p < g) of system mf into F (pole stride
 // mf.pole_stride), using the two contribution-block arenas.
 template <typename T>
-tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, const double *Kv,
-                        const double *Mv, int g, cpx<T> *arena0, cpx<T> *arena1) {
+tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xseg,
+                        const double *Kv, const double *Mv, int p0, int g, cpx<T> *arena0,
+                        cpx<T> *arena1) {
   hipStream_t st = c->stream;
-  FrontTab ft = front_tab(mf);
+  FrontTab ft = front_tab(mf, p0);
   cpx<T> *arena[2] = {arena0, arena1};
   const int nl = (int)mf.levels.size();
   const Symbolic &sym = mf.sym;
@@ -552,8 +597,8 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, const d
     HIPCHK(launch_fill_zero<T>(st, cbL, li.cb_size, g, mf.cb_stride), "zero cb");
     HIPCHK(launch_front_assemble<T>(st, li.amap_end - li.amap_begin,
                                     mf.d_amap_csr.as<int32_t>() + li.amap_begin,
-                                    mf.d_amap_pos.as<int64_t>() + li.amap_begin, Kv, Mv, xi, g, F,
-                                    mf.pole_stride),
+                                    mf.d_amap_pos.as<int64_t>() + li.amap_begin, Kv, Mv, xi, xseg,
+                                    g, F, mf.pole_stride),
            "front assemble");
     for (int sl = 0; sl < 2; ++sl)
       HIPCHK(launch_extend_add<T>(st, ft, ln, li.n, sl, li.max_u_child[sl], g, F, mf.pole_stride,
@@ -577,7 +622,8 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, const d
           const double w = (double)std::min<int64_t>(dw, k - j0);
           const double a0 = (double)c0, a1 = (double)c1;
           // lower-trapezoid entries of columns [c0, c1): sum (n - col)
-          fl += 8.0 * w * ((a1 - a0) * n - (a1 * (a1 - 1) - a0 * (a0 - 1)) / 2.0) * g;
+          fl += 8.0 * w * ((a1 - a0) * n - (a1 * (a1 - 1) - a0 * (a0 - 1)) / 2.0) *
+                mf.present(s, p0, g);
         }
       }
       if (max_tiles == 0) return TEM_OK;
@@ -614,7 +660,8 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, const d
       const SymNode &nd = sym.nodes[s];
       const int64_t k = nd.last - nd.first, n = k + nd.nrows;
       if (k > 0) cb_tiles = std::max(cb_tiles, Tiles::count(n, k, n, ttc));
-      fl += 8.0 * (double)k * (double)nd.nrows * (double)(nd.nrows + 1) / 2.0 * g;
+      fl += 8.0 * (double)k * (double)nd.nrows * (double)(nd.nrows + 1) / 2.0 *
+            mf.present(s, p0, g);
     }
     hipEvent_t ea = span_begin(c);
     HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, 0, 0, cb_tiles, g, F, mf.pole_stride,
@@ -643,7 +690,7 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
                         cpx<T> *x, int S) {
   TRY(ensure_sweep_ws<T>(c, mf, npole, S));
   hipStream_t st = c->stream;
-  FrontTab ft = front_tab(mf);
+  FrontTab ft = front_tab(mf, 0);
   const int64_t N = mf.N;
   cpx<T> *W[2] = {mf.w_w0.as<cpx<T>>(), mf.w_w1.as<cpx<T>>()};
   const int64_t ws = std::max<int64_t>(mf.w_rows_max, 1) * S;
@@ -711,7 +758,7 @@ tem_status sweep(tem_ctx *c, cpx<T> *x, int S) {
                                   c->npole, x, S);
   // each factor entry is read once forward and once backward; the
   // solution vector is read and written in both passes
-  const double bytes = 2.0 * (double)sizeof(cpx<T>) * (double)c->ed.pole_stride * c->npole +
+  const double bytes = 2.0 * (double)sizeof(cpx<T>) * (double)c->fac_elems +
                        4.0 * (double)sizeof(cpx<T>) * (double)c->npole * N_of(c) * S;
   span_end(c, ea, bytes, 1);
   return s0;
@@ -727,23 +774,29 @@ int dot_blocks(int64_t N) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256));
 }
 
-// norms^2 of all systems of v -> host
+// norms of all systems of v -> host, [segment][pole][s] (one segment per
+// mesh of a batch, so that each mesh's systems are judged on their own rows)
 tem_status sysnorms(tem_ctx *c, const cpx<double> *v, int S, std::vector<double> &out) {
   const int64_t N = N_of(c);
   const int mS = c->npole * S;
+  const int B = n_seg(c);
   const int nb = dot_blocks(N);
   TRY(ensure_vec(c, c->v_partial, sizeof(cpx<double>) * (size_t)nb * mS * 2, "alloc partial"));
-  TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)mS * 64, "alloc dots"));
-  HIPCHK(launch_batched_dot(c->stream, N, c->npole, S, v, v, true, c->v_partial.as<cpx<double>>(),
-                            nb, c->v_dots.as<cpx<double>>()),
-         "norm");
-  std::vector<cpx<double>> h(mS);
-  HIPCHK(hipMemcpyAsync(h.data(), c->v_dots.p, sizeof(cpx<double>) * mS, hipMemcpyDeviceToHost,
-                        c->stream),
+  TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)B * mS * 64, "alloc dots"));
+  for (int b = 0; b < B; ++b) {
+    const int64_t r0 = c->B > 0 ? c->row_off[b] : 0, r1 = c->B > 0 ? c->row_off[b + 1] : N;
+    HIPCHK(launch_batched_dot(c->stream, r1 - r0, c->npole, S, N * S, v + r0 * S, v + r0 * S, true,
+                              c->v_partial.as<cpx<double>>(), dot_blocks(r1 - r0),
+                              c->v_dots.as<cpx<double>>() + (size_t)b * mS),
+           "norm");
+  }
+  std::vector<cpx<double>> h((size_t)B * mS);
+  HIPCHK(hipMemcpyAsync(h.data(), c->v_dots.p, sizeof(cpx<double>) * B * mS,
+                        hipMemcpyDeviceToHost, c->stream),
          "norm d2h");
   HIPCHK(hipStreamSynchronize(c->stream), "norm sync");
-  out.resize(mS);
-  for (int i = 0; i < mS; ++i) out[i] = std::sqrt(std::max(h[i].re, 0.0));
+  out.resize((size_t)B * mS);
+  for (size_t i = 0; i < out.size(); ++i) out[i] = std::sqrt(std::max(h[i].re, 0.0));
   return TEM_OK;
 }
 
@@ -762,13 +815,13 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S) 
   cpx<double> *w = c->v_aux.as<cpx<double>>();
   cpx<double> *y = c->d_nvec.as<cpx<double>>();
   HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                         c->d_K.as<double>(), c->d_M.as<double>(), c->d_xi.as<double>(), nullptr,
-                         r, z, w),
+                         c->d_K.as<double>(), c->d_M.as<double>(), c->d_xi.as<double>(),
+                         row_seg(c), nullptr, r, z, w),
          "aux residual");
   HIPCHK(launch_grad_T(st, Nn, m, S, N, c->d_node_edges.as<int32_t>(), w, y), "G^T");
   TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, m, y, S));
   HIPCHK(launch_grad_add(st, N, m, S, Nn, c->d_edge_nodes.as<int32_t>(),
-                         c->d_ncoef.as<cpx<double>>(), y, z),
+                         c->d_ncoef.as<cpx<double>>(), row_seg(c), y, z),
          "z += G y");
   return TEM_OK;
 }
@@ -795,7 +848,7 @@ tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
   TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)mS * 64, "alloc dots"));
   TRY(ensure_vec(c, c->v_inv, sizeof(double) * mS, "alloc inv"));
   TRY(ensure_vec(c, c->v_nrm, sizeof(double) * mS, "alloc nrm"));
-  HIPCHK(launch_batched_dot(st, N, m, S, in, in, true, c->v_partial.as<cpx<double>>(), nb,
+  HIPCHK(launch_batched_dot(st, N, m, S, N * S, in, in, true, c->v_partial.as<cpx<double>>(), nb,
                             c->v_dots.as<cpx<double>>()),
          "precond norm");
   HIPCHK(launch_norm_scales(st, mS, c->v_dots.as<cpx<double>>(), c->v_inv.as<double>(),
@@ -835,12 +888,21 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
   // correction: classical refinement unless GMRES is asked for explicitly.
   if (c->prec == TEM_FP64) restart = 1;
   if (c->prec == TEM_FP32_IR && c->aux && c->nodal_ready && !(ir && ir->restart > 1)) restart = 1;
+  if (c->B > 0) restart = 1;   // batches: classical refinement only
   const size_t vbytes = sizeof(cpx<double>) * (size_t)mS * N;
   TRY(ensure_vec(c, c->v_r, vbytes, "alloc r"));
   TRY(ensure_vec(c, c->v_z, vbytes, "alloc z"));
   TRY(ensure_vec(c, c->v_w, vbytes, "alloc w"));
+  // systems: [mesh][pole][s] (one mesh unless a batch); absent poles of a
+  // mesh in a batch are padding and never active
+  const int nsys = n_seg(c) * mS;
+  std::vector<char> pad(nsys, 0);
+  if (c->B > 0)
+    for (int b = 0; b < c->B; ++b)
+      for (int p = c->np_mesh[b]; p < m; ++p)
+        for (int q = 0; q < S; ++q) pad[(size_t)b * mS + p * S + q] = 1;
   TRY(ensure_vec(c, c->v_coef, sizeof(cpx<double>) * (size_t)mS * 2, "alloc coef"));
-  TRY(ensure_vec(c, c->v_mask, sizeof(int) * (size_t)mS, "alloc mask"));
+  TRY(ensure_vec(c, c->v_mask, sizeof(int) * (size_t)nsys, "alloc mask"));
   cpx<double> *r = c->v_r.as<cpx<double>>();
   cpx<double> *z = c->v_z.as<cpx<double>>();
   cpx<double> *w = c->v_w.as<cpx<double>>();
@@ -848,15 +910,16 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
   // x = 0, so that r = f and ||r|| = ||f||
   std::vector<double> fn;
   HIPCHK(launch_fill_f64(st, (double *)x, 2 * (int64_t)mS * N, 0.0), "zero x");
+  const Seg rs = row_seg(c);
   HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                         c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
+                         c->d_K.as<double>(), c->d_M.as<double>(), xi, rs, f_real, f_cplx, x, r),
          "residual");
   TRY(sysnorms(c, r, S, fn));
-  res.iters.assign(mS, 0);
-  res.rel.assign(mS, 0.0);
-  std::vector<int> active(mS, 1);
-  for (int i = 0; i < mS; ++i)
-    if (fn[i] == 0.0) active[i] = 0;
+  res.iters.assign(nsys, 0);
+  res.rel.assign(nsys, 0.0);
+  std::vector<int> active(nsys, 1);
+  for (int i = 0; i < nsys; ++i)
+    if (fn[i] == 0.0 || pad[i]) active[i] = 0;
   int solves = 0;
   if (restart <= 1) {
     // classical refinement
@@ -864,26 +927,27 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       std::vector<double> rn;
       TRY(sysnorms(c, r, S, rn));
       bool any = false;
-      for (int i = 0; i < mS; ++i) {
-        res.rel[i] = fn[i] > 0 ? rn[i] / fn[i] : 0.0;
+      for (int i = 0; i < nsys; ++i) {
+        res.rel[i] = (fn[i] > 0 && !pad[i]) ? rn[i] / fn[i] : 0.0;
         if (active[i] && res.rel[i] <= rtol) active[i] = 0;
         any = any || active[i];
       }
       if (!any || it == max_iter) break;
-      HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * mS, st),
+      HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * nsys, st),
              "mask");
       TRY(precond(c, r, z, S));
       ++solves;
-      for (int i = 0; i < mS; ++i)
+      for (int i = 0; i < nsys; ++i)
         if (active[i]) res.iters[i]++;
       std::vector<cpx<double>> one(mS, {1.0, 0.0});
       HIPCHK(h2d(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS, st),
              "coef");
       HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
-                                 c->v_mask.as<int>()),
+                                 c->v_mask.as<int>(), rs),
              "x += z");
       HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                             c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
+                             c->d_K.as<double>(), c->d_M.as<double>(), xi, rs, f_real, f_cplx, x,
+                             r),
              "residual");
     }
   } else {
@@ -929,12 +993,12 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
         ++solves;
         ++total;
         HIPCHK(launch_spmv_shifted(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                                   c->d_K.as<double>(), c->d_M.as<double>(), xi, z, w),
+                                   c->d_K.as<double>(), c->d_M.as<double>(), xi, rs, z, w),
                "A z");
         // modified Gram-Schmidt, twice (reorthogonalisation)
         for (int pass = 0; pass < 2; ++pass) {
           for (int j = 0; j <= k; ++j) {
-            HIPCHK(launch_batched_dot(st, N, m, S, V + j * vs, w, true,
+            HIPCHK(launch_batched_dot(st, N, m, S, N * S, V + j * vs, w, true,
                                       c->v_partial.as<cpx<double>>(), nb, dots + j * mS),
                    "mgs dot");
             HIPCHK(launch_batched_axpy(st, N, m, S, dots + j * mS, -1.0, V + j * vs, w, nullptr),
@@ -1028,12 +1092,13 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
              "x += z");
       HIPCHK(hipStreamSynchronize(st), "x sync");
       HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                             c->d_K.as<double>(), c->d_M.as<double>(), xi, f_real, f_cplx, x, r),
+                             c->d_K.as<double>(), c->d_M.as<double>(), xi, rs, f_real, f_cplx, x,
+                             r),
              "residual");
     }
   }
   res.unconverged = 0;
-  for (int i = 0; i < mS; ++i)
+  for (int i = 0; i < nsys; ++i)
     if (!(res.rel[i] <= rtol)) res.unconverged++;   // NaN counts as unconverged
   res.solves = solves;
   return TEM_OK;
@@ -1091,6 +1156,8 @@ tem_status setup_nodal(tem_ctx *c, int leaf) {
   }
   HIPCHK(upload(c->d_node_edges, ne, c->stream), "upload node edges");
   HIPCHK(upload(c->d_edge_nodes, en, c->stream), "upload edge nodes");
+  c->h_node_edges = std::move(ne);
+  c->h_edge_nodes = std::move(en);
   double le[64];
   element_grad_mass(c->mesh.h, le);
   std::vector<double> lev(le, le + 64);
@@ -1111,11 +1178,26 @@ tem_status factor_nodal(tem_ctx *c) {
   c->nodal_ready = false;
   if (nd.N == 0) return TEM_OK;
   hipStream_t st = c->stream;
-  HIPCHK(launch_assemble_nodal(st, nd.N, nd.d_rowptr.as<int64_t>(), nd.d_col.as<int32_t>(),
-                               nd.d_row_ent.as<int32_t>(), nd.d_ent_new.as<int32_t>(), c->mt.nx,
-                               c->mt.ny, c->mt.nz, c->d_Le.as<double>(), c->d_sigma.as<double>(),
-                               c->d_Ln.as<double>()),
-         "nodal assembly");
+  if (c->B > 0) {
+    // each mesh assembles its block of the merged nodal matrix
+    for (int b = 0; b < c->B; ++b) {
+      tem_ctx *sb = c->sub[b];
+      const MF &snd = sb->nd;
+      if (snd.N == 0) continue;
+      HIPCHK(launch_assemble_nodal(st, snd.N, snd.d_rowptr.as<int64_t>(), snd.d_col.as<int32_t>(),
+                                   snd.d_row_ent.as<int32_t>(), snd.d_ent_new.as<int32_t>(),
+                                   sb->mt.nx, sb->mt.ny, sb->mt.nz, sb->d_Le.as<double>(),
+                                   sb->d_sigma.as<double>(),
+                                   c->d_Ln.as<double>() + c->nnz_node_off[b]),
+             "nodal assembly");
+    }
+  } else {
+    HIPCHK(launch_assemble_nodal(st, nd.N, nd.d_rowptr.as<int64_t>(), nd.d_col.as<int32_t>(),
+                                 nd.d_row_ent.as<int32_t>(), nd.d_ent_new.as<int32_t>(), c->mt.nx,
+                                 c->mt.ny, c->mt.nz, c->d_Le.as<double>(),
+                                 c->d_sigma.as<double>(), c->d_Ln.as<double>()),
+           "nodal assembly");
+  }
   HIPCHK(c->d_nfactor.alloc(sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.pole_stride, 1)),
          "alloc nodal factor");
   DBuf a0, a1;
@@ -1126,13 +1208,14 @@ tem_status factor_nodal(tem_ctx *c) {
   const bool prof = c->profile;
   c->profile = false;
   tem_status fs = factor_group<double>(c, nd, c->d_nfactor.as<cpx<double>>(), c->d_nxi.as<double>(),
-                                       c->d_Ln.as<double>(), c->d_Lzero.as<double>(), 1,
+                                       Seg(), c->d_Ln.as<double>(), c->d_Lzero.as<double>(), 0, 1,
                                        a0.as<cpx<double>>(), a1.as<cpx<double>>());
   c->profile = prof;
   TRY(fs);
-  // coefficients -1/xi_p of the correction
-  std::vector<double> coef(2 * c->npole);
-  for (int p = 0; p < c->npole; ++p) {
+  // coefficients -1/xi of the correction, one per pole slot of each mesh
+  const size_t nco = (size_t)n_seg(c) * c->npole;
+  std::vector<double> coef(2 * nco);
+  for (size_t p = 0; p < nco; ++p) {
     std::complex<double> v = -1.0 / std::complex<double>(c->xi[2 * p], c->xi[2 * p + 1]);
     coef[2 * p] = v.real();
     coef[2 * p + 1] = v.imag();
@@ -1141,6 +1224,234 @@ tem_status factor_nodal(tem_ctx *c) {
   HIPCHK(hipStreamSynchronize(st), "nodal factor sync");
   c->nodal_ready = true;
   return TEM_OK;
+}
+
+// Factor every pole slot of c->xi (a table [mesh][npole] for a batch) in
+// precision prec; pole groups when the arenas do not fit beside the factors.
+tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *opts) {
+  const int m = c->npole;
+  HIPCHK(upload(c->d_xi, c->xi, c->stream), "upload xi");
+  const size_t esz = prec == TEM_FP64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
+  const size_t fbytes = esz * (size_t)c->ed.pole_stride * m;
+  const size_t cb_pole = esz * (size_t)std::max<int64_t>(c->ed.cb_stride, 1);
+  // a factor buffer of another size and the arenas are given back first;
+  // the budget counts what is still held as available.
+  if (c->d_factor.bytes != fbytes) c->d_factor.release();
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+  const int64_t held = (int64_t)(c->d_factor.bytes + c->d_cb0.bytes + c->d_cb1.bytes);
+  int64_t budget = (opts && opts->mem_budget_bytes > 0)
+                       ? opts->mem_budget_bytes
+                       : (int64_t)(0.92 * (double)free_b) + held;
+  if ((int64_t)fbytes + 2 * (int64_t)cb_pole > budget)
+    return fail(c, TEM_ENOMEM, "tem_factor_poles: factors do not fit in the memory budget");
+  int g = (int)std::min<int64_t>(m, (budget - (int64_t)fbytes) / (2 * (int64_t)cb_pole));
+  if (opts && opts->max_group > 0) g = std::min(g, (int)opts->max_group);
+  g = std::max(g, 1);
+  const int ngroups = (m + g - 1) / g;
+  g = (m + ngroups - 1) / ngroups;    // balance the groups
+  if (c->d_cb0.bytes != cb_pole * g) {
+    c->d_cb0.release();
+    c->d_cb1.release();
+  }
+  HIPCHK(c->d_factor.alloc(fbytes), "alloc factors");
+  HIPCHK(c->d_cb0.alloc(cb_pole * g), "alloc cb arena");
+  HIPCHK(c->d_cb1.alloc(cb_pole * g), "alloc cb arena");
+  HIPCHK(hipMemsetAsync(c->d_flags.p, 0, sizeof(int) * 4, c->stream), "clear flags");
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0), "event");
+  HIPCHK(hipEventCreate(&e1), "event");
+  HIPCHK(hipEventRecord(e0, c->stream), "event");
+  for (int p0 = 0; p0 < m; p0 += g) {
+    int gg = std::min(g, m - p0);
+    tem_status s =
+        prec == TEM_FP64
+            ? factor_group<double>(c, c->ed,
+                                   c->d_factor.as<cpx<double>>() + (int64_t)p0 * c->ed.pole_stride,
+                                   c->d_xi.as<double>() + 2 * p0, nnz_seg(c), c->d_K.as<double>(),
+                                   c->d_M.as<double>(), p0, gg, c->d_cb0.as<cpx<double>>(),
+                                   c->d_cb1.as<cpx<double>>())
+            : factor_group<float>(c, c->ed,
+                                  c->d_factor.as<cpx<float>>() + (int64_t)p0 * c->ed.pole_stride,
+                                  c->d_xi.as<double>() + 2 * p0, nnz_seg(c), c->d_K.as<double>(),
+                                  c->d_M.as<double>(), p0, gg, c->d_cb0.as<cpx<float>>(),
+                                  c->d_cb1.as<cpx<float>>());
+    if (s != TEM_OK) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return s;
+    }
+  }
+  {
+    // keep the arenas for the next factorisation unless the solves need the room
+    size_t fr = 0, tt = 0;
+    if (hipMemGetInfo(&fr, &tt) != hipSuccess || fr < (size_t)32 << 30) {
+      c->d_cb0.release();
+      c->d_cb1.release();
+    }
+  }
+  if (prec == TEM_FP32_IR && c->aux) {
+    tem_status s = factor_nodal(c);
+    if (s != TEM_OK) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return s;
+    }
+  }
+  HIPCHK(hipEventRecord(e1, c->stream), "event");
+  HIPCHK(hipEventSynchronize(e1), "factor sync");
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->factor_ms = ms;
+  spans_collect(c);
+  int flags[4];
+  HIPCHK(hipMemcpy(flags, c->d_flags.p, sizeof(flags), hipMemcpyDeviceToHost), "flags d2h");
+  c->n_tiny = flags[1];
+  c->n_groups = ngroups;
+  c->group_size = g;
+  if (flags[0]) {
+    return fail(c, TEM_EPIVOT, "tem_factor_poles: zero or non-finite pivot");
+  }
+  c->factored = true;
+  return TEM_OK;
+}
+
+// ------------------------------------------------------------- batches
+// Concatenate the meshes' edge (or nodal) systems into one block-diagonal
+// system: mesh b's unknowns follow those of meshes 0..b-1, its supernodes
+// keep their depths, so one level of the merged forest holds that level of
+// every mesh and each launch covers all of them.
+tem_status merge_systems(tem_ctx *c, bool nodes) {
+  MF &M = nodes ? c->nd : c->ed;
+  Symbolic &S = M.sym;
+  Pattern &P = M.pat;
+  S.nodes.clear();
+  S.perm.clear();
+  S.iperm.clear();
+  S.rows.clear();
+  S.n_levels = 0;
+  S.max_front = 0;
+  S.flops_per_pole = 0.0;
+  S.nnz_l = 0;
+  P.rowptr.assign(1, 0);
+  P.col.clear();
+  P.row_edge.clear();
+  P.edge_new.clear();
+  M.h_np.clear();
+  M.d_np.release();
+  std::vector<int64_t> &roff = nodes ? c->node_off : c->row_off;
+  std::vector<int64_t> &zoff = nodes ? c->nnz_node_off : c->nnz_off;
+  roff.assign(c->B + 1, 0);
+  zoff.assign(c->B + 1, 0);
+  int64_t r0 = 0, e0 = 0, z0 = 0;
+  int node0 = 0;
+  int64_t rows0 = 0;
+  for (int b = 0; b < c->B; ++b) {
+    const tem_ctx *sb = c->sub[b];
+    const MF &m = nodes ? sb->nd : sb->ed;
+    const int64_t ents = nodes ? sb->mt.n_nodes : sb->mt.n_edges;
+    roff[b] = r0;
+    zoff[b] = z0;
+    for (SymNode nd : m.sym.nodes) {
+      nd.first += r0;
+      nd.last += r0;
+      nd.sub_first += r0;
+      if (nd.parent >= 0) nd.parent += node0;
+      for (int t = 0; t < 2; ++t)
+        if (nd.child[t] >= 0) nd.child[t] += node0;
+      nd.rows_off += rows0;
+      S.nodes.push_back(nd);
+    }
+    for (int32_t q : m.sym.rows) S.rows.push_back((int32_t)(q + r0));
+    for (int32_t q : m.perm) S.perm.push_back((int32_t)(q + r0));
+    for (int32_t q : m.sym.iperm) S.iperm.push_back((int32_t)(q + r0));
+    S.n_levels = std::max(S.n_levels, m.sym.n_levels);
+    S.max_front = std::max(S.max_front, m.sym.max_front);
+    S.flops_per_pole += m.sym.flops_per_pole;
+    S.nnz_l += m.sym.nnz_l;
+    for (size_t i = 0; i + 1 < m.pat.rowptr.size(); ++i) P.rowptr.push_back(m.pat.rowptr[i + 1] + z0);
+    for (int32_t q : m.pat.col) P.col.push_back((int32_t)(q + r0));
+    for (int32_t e : m.pat.row_edge) P.row_edge.push_back((int32_t)(e + e0));
+    for (int32_t q : m.pat.edge_new) P.edge_new.push_back(q >= 0 ? (int32_t)(q + r0) : -1);
+    r0 += m.N;
+    e0 += ents;
+    z0 += (int64_t)m.pat.col.size();
+    node0 += (int)m.sym.nodes.size();
+    rows0 += (int64_t)m.sym.rows.size();
+  }
+  roff[c->B] = r0;
+  zoff[c->B] = z0;
+  if (r0 > ((int64_t)1 << 31) - 1 || e0 > ((int64_t)1 << 31) - 1)
+    return fail(c, TEM_EINVAL, "tem_analyse: batch too large for 32-bit indices");
+  M.nodes = nodes;
+  M.perm = S.perm;
+  M.N = r0;
+  hipStream_t st = c->stream;
+  HIPCHK(upload(M.d_rowptr, P.rowptr, st), "upload rowptr");
+  HIPCHK(upload(M.d_col, P.col, st), "upload col");
+  HIPCHK(upload(M.d_row_ent, P.row_edge, st), "upload row map");
+  HIPCHK(upload(M.d_ent_new, P.edge_new, st), "upload entity map");
+  return build_front_maps(c, M);
+}
+
+// merged K, M values from the meshes' own (analysed) assemblies
+tem_status batch_values(tem_ctx *c) {
+  for (int b = 0; b < c->B; ++b) {
+    const tem_ctx *sb = c->sub[b];
+    const size_t n = sizeof(double) * (size_t)(c->nnz_off[b + 1] - c->nnz_off[b]);
+    HIPCHK(hipMemcpyAsync(c->d_K.as<double>() + c->nnz_off[b], sb->d_K.p, n,
+                          hipMemcpyDeviceToDevice, c->stream),
+           "copy K block");
+    HIPCHK(hipMemcpyAsync(c->d_M.as<double>() + c->nnz_off[b], sb->d_M.p, n,
+                          hipMemcpyDeviceToDevice, c->stream),
+           "copy M block");
+  }
+  return TEM_OK;
+}
+
+// merged systems, segment tables and the nodal incidence of a batch
+tem_status batch_analyse(tem_ctx *c) {
+  TRY(merge_systems(c, false));
+  TRY(merge_systems(c, true));
+  hipStream_t st = c->stream;
+  HIPCHK(upload(c->d_row_seg, c->row_off, st), "upload row segments");
+  HIPCHK(upload(c->d_nnz_seg, c->nnz_off, st), "upload entry segments");
+  const size_t nnz = c->ed.pat.col.size();
+  HIPCHK(c->d_K.alloc(sizeof(double) * std::max<size_t>(nnz, 1)), "alloc K");
+  HIPCHK(c->d_M.alloc(sizeof(double) * std::max<size_t>(nnz, 1)), "alloc M");
+  TRY(batch_values(c));
+  // nodal incidence in merged numbering
+  std::vector<int32_t> ne, en;
+  for (int b = 0; b < c->B; ++b) {
+    const tem_ctx *sb = c->sub[b];
+    for (int32_t q : sb->h_node_edges) ne.push_back((int32_t)(q + c->row_off[b]));
+    for (int32_t a : sb->h_edge_nodes) en.push_back(a >= 0 ? (int32_t)(a + c->node_off[b]) : -1);
+  }
+  if ((int64_t)en.size() != 2 * c->ed.N || (int64_t)ne.size() != 6 * c->nd.N)
+    return fail(c, TEM_EINVAL, "tem_analyse: nodal incidence does not match the merged systems");
+  HIPCHK(upload(c->d_node_edges, ne, st), "upload node edges");
+  HIPCHK(upload(c->d_edge_nodes, en, st), "upload edge nodes");
+  const size_t nnn = c->nd.pat.col.size();
+  HIPCHK(c->d_Ln.alloc(sizeof(double) * std::max<size_t>(nnn, 1)), "alloc nodal values");
+  HIPCHK(c->d_Lzero.alloc(sizeof(double) * std::max<size_t>(nnn, 1)), "alloc zeros");
+  HIPCHK(launch_fill_f64(st, c->d_Lzero.as<double>(), (int64_t)std::max<size_t>(nnn, 1), 0.0),
+         "zeros");
+  std::vector<double> zxi = {0.0, 0.0};
+  HIPCHK(upload(c->d_nxi, zxi, st), "upload zero shift");
+  HIPCHK(hipStreamSynchronize(st), "batch analyse sync");
+  return TEM_OK;
+}
+
+void batch_release(tem_ctx *c) {
+  for (tem_ctx *sb : c->sub) tem_destroy(sb);
+  c->sub.clear();
+  c->B = 0;
+  c->MP = 0;
+  c->np_mesh.clear();
+  c->ed.h_np.clear();
+  c->ed.d_np.release();
 }
 
 // =================================================================== ABI
@@ -1207,6 +1518,7 @@ void tem_destroy(tem_ctx *c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
+  batch_release(c);
   hipStream_t st = c->stream;
   bool own = c->own_stream;
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
@@ -1249,6 +1561,12 @@ tem_status tem_assemble(tem_ctx *c, const tem_mesh *mesh, const double *sigma_ce
   for (double v : sg)
     if (!(v > 0) || !std::isfinite(v))
       return fail(c, TEM_EINVAL, "tem_assemble: sigma must be positive and finite");
+  if (c->B > 0) {   // leaving batch mode
+    batch_release(c);
+    free_factors(c);
+    c->assembled = false;
+    c->analysed = false;
+  }
   const bool same_mesh = c->assembled && c->mesh.nx == mesh->nx && c->mesh.ny == mesh->ny &&
                          c->mesh.nz == mesh->nz && c->mesh.h == mesh->h && c->mesh.mu == mesh->mu;
   if (same_mesh)
@@ -1287,6 +1605,7 @@ tem_status tem_assemble(tem_ctx *c, const tem_mesh *mesh, const double *sigma_ce
 
 tem_status tem_set_model(tem_ctx *c, const double *m) {
   if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_set_model: not available on a batch of meshes");
   if (!c->assembled) return fail(c, TEM_ESTATE, "tem_set_model: call tem_assemble first");
   if (!m) return fail(c, TEM_EINVAL, "tem_set_model: m is NULL");
   if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_set_model: no model parameters");
@@ -1310,6 +1629,7 @@ tem_status tem_export_operators(const tem_ctx *cc, int64_t *n_unknowns, int64_t 
                                 double *mval) {
   tem_ctx *c = const_cast<tem_ctx *>(cc);
   if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_export_operators: not available on a batch of meshes");
   if (!c->assembled) return fail(c, TEM_ESTATE, "tem_export_operators: nothing assembled");
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
   const int64_t N = N_of(c), nz = (int64_t)c->ed.pat.col.size();
@@ -1329,7 +1649,20 @@ tem_status tem_analyse(tem_ctx *c, const tem_analyse_opts *opts, tem_symbolic_in
   if (!c->assembled) return fail(c, TEM_ESTATE, "tem_analyse: call tem_assemble first");
   int leaf = (opts && opts->leaf_max_cells > 0) ? opts->leaf_max_cells : 4;
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
-  if (!c->analysed || leaf != c->leaf) {
+  if (c->B > 0 && (!c->analysed || leaf != c->leaf)) {
+    free_factors(c);
+    tem_analyse_opts so{};
+    so.leaf_max_cells = leaf;
+    for (int b = 0; b < c->B; ++b) {
+      tem_status sb = tem_analyse(c->sub[b], &so, nullptr);
+      if (sb != TEM_OK) return fail(c, sb, std::string("mesh ") + std::to_string(b) + ": " +
+                                               tem_last_error(c->sub[b]));
+    }
+    c->leaf = leaf;
+    TRY(batch_analyse(c));
+    c->analysed = true;
+  }
+  if (c->B == 0 && (!c->analysed || leaf != c->leaf)) {
     free_factors(c);
     try {
       analyse_symbolic(c->mt, leaf, c->ed.sym, false);
@@ -1344,7 +1677,7 @@ tem_status tem_analyse(tem_ctx *c, const tem_analyse_opts *opts, tem_symbolic_in
     c->analysed = true;
   }
   if (info) {
-    info->n_unknowns = c->mt.n_unknowns;
+    info->n_unknowns = c->ed.N;
     info->nnz_a = (int64_t)c->ed.pat.col.size();
     info->nnz_l = c->ed.sym.nnz_l;
     info->n_rows_total = (int64_t)c->ed.sym.rows.size();
@@ -1402,6 +1735,7 @@ tem_status tem_symbolic_host(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_ma
 tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precision prec,
                             const tem_factor_opts *opts) {
   if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_factor_poles: not available on a batch of meshes");
   if (!c->analysed) return fail(c, TEM_ESTATE, "tem_factor_poles: call tem_analyse first");
   if (m <= 0 || !xi) return fail(c, TEM_EINVAL, "tem_factor_poles: need m > 0 poles");
   if (m > 65535) return fail(c, TEM_EINVAL, "tem_factor_poles: too many poles");
@@ -1419,95 +1753,14 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
   c->npole = m;
   c->prec = prec;
   c->xi.assign(xi, xi + 2 * m);
-  HIPCHK(upload(c->d_xi, c->xi, c->stream), "upload xi");
-  const size_t esz = prec == TEM_FP64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
-  const size_t fbytes = esz * (size_t)c->ed.pole_stride * m;
-  const size_t cb_pole = esz * (size_t)std::max<int64_t>(c->ed.cb_stride, 1);
-  // a factor buffer of another size and the arenas are given back first;
-  // the budget counts what is still held as available.
-  if (c->d_factor.bytes != fbytes) c->d_factor.release();
-  size_t free_b = 0, total_b = 0;
-  HIPCHK(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-  const int64_t held = (int64_t)(c->d_factor.bytes + c->d_cb0.bytes + c->d_cb1.bytes);
-  int64_t budget = (opts && opts->mem_budget_bytes > 0)
-                       ? opts->mem_budget_bytes
-                       : (int64_t)(0.92 * (double)free_b) + held;
-  if ((int64_t)fbytes + 2 * (int64_t)cb_pole > budget)
-    return fail(c, TEM_ENOMEM, "tem_factor_poles: factors do not fit in the memory budget");
-  int g = (int)std::min<int64_t>(m, (budget - (int64_t)fbytes) / (2 * (int64_t)cb_pole));
-  if (opts && opts->max_group > 0) g = std::min(g, (int)opts->max_group);
-  g = std::max(g, 1);
-  const int ngroups = (m + g - 1) / g;
-  g = (m + ngroups - 1) / ngroups;    // balance the groups
-  if (c->d_cb0.bytes != cb_pole * g) {
-    c->d_cb0.release();
-    c->d_cb1.release();
-  }
-  HIPCHK(c->d_factor.alloc(fbytes), "alloc factors");
-  HIPCHK(c->d_cb0.alloc(cb_pole * g), "alloc cb arena");
-  HIPCHK(c->d_cb1.alloc(cb_pole * g), "alloc cb arena");
-  HIPCHK(hipMemsetAsync(c->d_flags.p, 0, sizeof(int) * 4, c->stream), "clear flags");
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0), "event");
-  HIPCHK(hipEventCreate(&e1), "event");
-  HIPCHK(hipEventRecord(e0, c->stream), "event");
-  for (int p0 = 0; p0 < m; p0 += g) {
-    int gg = std::min(g, m - p0);
-    tem_status s =
-        prec == TEM_FP64
-            ? factor_group<double>(c, c->ed, c->d_factor.as<cpx<double>>() + (int64_t)p0 * c->ed.pole_stride,
-                                   c->d_xi.as<double>() + 2 * p0, c->d_K.as<double>(),
-                                   c->d_M.as<double>(), gg, c->d_cb0.as<cpx<double>>(),
-                                   c->d_cb1.as<cpx<double>>())
-            : factor_group<float>(c, c->ed, c->d_factor.as<cpx<float>>() + (int64_t)p0 * c->ed.pole_stride,
-                                  c->d_xi.as<double>() + 2 * p0, c->d_K.as<double>(),
-                                  c->d_M.as<double>(), gg, c->d_cb0.as<cpx<float>>(),
-                                  c->d_cb1.as<cpx<float>>());
-    if (s != TEM_OK) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      return s;
-    }
-  }
-  {
-    // keep the arenas for the next factorisation unless the solves need the room
-    size_t fr = 0, tt = 0;
-    if (hipMemGetInfo(&fr, &tt) != hipSuccess || fr < (size_t)32 << 30) {
-      c->d_cb0.release();
-      c->d_cb1.release();
-    }
-  }
-  if (prec == TEM_FP32_IR && c->aux) {
-    tem_status s = factor_nodal(c);
-    if (s != TEM_OK) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      return s;
-    }
-  }
-  HIPCHK(hipEventRecord(e1, c->stream), "event");
-  HIPCHK(hipEventSynchronize(e1), "factor sync");
-  float ms = 0;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  c->factor_ms = ms;
-  spans_collect(c);
-  int flags[4];
-  HIPCHK(hipMemcpy(flags, c->d_flags.p, sizeof(flags), hipMemcpyDeviceToHost), "flags d2h");
-  c->n_tiny = flags[1];
-  c->n_groups = ngroups;
-  c->group_size = g;
-  if (flags[0]) {
-    return fail(c, TEM_EPIVOT, "tem_factor_poles: zero or non-finite pivot");
-  }
-  c->factored = true;
-  return TEM_OK;
+  c->fac_elems = c->ed.pole_stride * (int64_t)m;
+  return factor_core(c, prec, opts);
 }
 
 tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
                            const tem_ir_opts *ir, tem_ir_stats *stats) {
   if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_solve_poles: not available on a batch of meshes");
   if (!c->factored) return fail(c, TEM_ESTATE, "tem_solve_poles: call tem_factor_poles first");
   if (nrhs <= 0 || nrhs > 16 || !F)
     return fail(c, TEM_EINVAL, "tem_solve_poles: need 1 <= nrhs <= 16 and a source array");
@@ -1517,7 +1770,7 @@ tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
   hipStream_t st = c->stream;
   c->solved = false;
   TRY(ensure_vec(c, c->d_fnew, sizeof(double) * (size_t)N * S, "alloc f"));
-  HIPCHK(launch_gather_rhs(st, N, S, c->mt.n_edges, c->ed.d_row_ent.as<int32_t>(), F,
+  HIPCHK(launch_gather_rhs(st, N, S, S, c->mt.n_edges, c->ed.d_row_ent.as<int32_t>(), F,
                            c->d_fnew.as<double>()),
          "gather f");
   TRY(ensure_vec(c, c->d_g, sizeof(cpx<double>) * (size_t)c->npole * N * S, "alloc g"));
@@ -1596,13 +1849,14 @@ tem_status tem_forward(tem_ctx *c, int32_t S, const double *F, int32_t R, const 
                        const int32_t *q_col, const double *q_val, int32_t K, const double *alpha,
                        const tem_ir_opts *ir, double *d, tem_ir_stats *stats) {
   if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_forward: not available on a batch of meshes");
   if (!c->factored) return fail(c, TEM_ESTATE, "tem_forward: call tem_factor_poles first");
   if (!d) return fail(c, TEM_EINVAL, "tem_forward: d is NULL");
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
   TRY(set_survey(c, R, q_ptr, q_col, q_val, K, alpha));
   tem_status s = tem_solve_poles(c, S, F, nullptr, ir, stats);
   if (s != TEM_OK && s != TEM_ENOCONV) return s;
-  HIPCHK(launch_time_assembly(c->stream, S, K, R, c->npole, N_of(c), c->d_qptr.as<int64_t>(),
+  HIPCHK(launch_time_assembly(c->stream, S, K, R, c->npole, N_of(c), S, c->d_qptr.as<int64_t>(),
                               c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
                               c->d_alpha.as<cpx<double>>(), c->d_g.as<cpx<double>>(), d),
          "time assembly");
@@ -1614,6 +1868,7 @@ tem_status tem_forward(tem_ctx *c, int32_t S, const double *F, int32_t R, const 
 tem_status tem_jvp(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *ir,
                    tem_ir_stats *stats) {
   if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_jvp: not available on a batch of meshes");
   if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_jvp: call tem_forward first");
   if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_jvp: no model parameters");
   if (!v || !jv) return fail(c, TEM_EINVAL, "tem_jvp: NULL argument");
@@ -1633,7 +1888,7 @@ tem_status tem_jvp(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *i
          "jv rhs");
   IrResult res;
   TRY(refine_solve(c, nullptr, c->v_rhs.as<cpx<double>>(), S, c->v_lam.as<cpx<double>>(), ir, res));
-  HIPCHK(launch_time_assembly(st, S, c->K, c->R, m, N, c->d_qptr.as<int64_t>(),
+  HIPCHK(launch_time_assembly(st, S, c->K, c->R, m, N, S, c->d_qptr.as<int64_t>(),
                               c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
                               c->d_alpha.as<cpx<double>>(), c->v_lam.as<cpx<double>>(), jv),
          "jv time assembly");
@@ -1648,6 +1903,7 @@ tem_status tem_jvp(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *i
 tem_status tem_vjp(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *ir,
                    tem_ir_stats *stats) {
   if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_vjp: not available on a batch of meshes");
   if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_vjp: call tem_forward first");
   if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_vjp: no model parameters");
   if (!w || !jtw) return fail(c, TEM_EINVAL, "tem_vjp: NULL argument");
@@ -1689,6 +1945,7 @@ tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const 
                        const double *m_ref, double lambda, int32_t iters, double *dm,
                        double *hist, const tem_ir_opts *ir) {
   if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_gn_step: not available on a batch of meshes");
   if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_gn_step: call tem_forward first");
   if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_gn_step: no model parameters");
   if (!d_obs || !wd || !m || !m_ref || !dm || iters <= 0 || !(lambda >= 0) || !std::isfinite(lambda))
@@ -1727,7 +1984,8 @@ tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const 
     return TEM_OK;
   };
   // b = -[W_d (d(m) - d_obs); sqrt(lam) R (m - m_ref)]
-  HIPCHK(launch_time_assembly(st, c->S, c->K, c->R, c->npole, N_of(c), c->d_qptr.as<int64_t>(),
+  HIPCHK(launch_time_assembly(st, c->S, c->K, c->R, c->npole, N_of(c), c->S,
+                              c->d_qptr.as<int64_t>(),
                               c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
                               c->d_alpha.as<cpx<double>>(), c->d_g.as<cpx<double>>(), td),
          "d(m)");
@@ -1773,6 +2031,236 @@ tem_status tem_set_profiling(tem_ctx *c, int32_t enable) {
   c->profile = enable != 0;
   c->upd_ms = c->upd_flops = c->sweep_ms = c->sweep_bytes = 0;
   c->upd_launches = c->sweeps = 0;
+  return TEM_OK;
+}
+
+// --------------------------------------------------------- batches
+tem_status tem_assemble_batch(tem_ctx *c, int32_t n_mesh, const tem_mesh *meshes,
+                              const double *sigma_cells) {
+  if (!c) return TEM_EINVAL;
+  if (n_mesh <= 0 || n_mesh > 4096 || !meshes || !sigma_cells)
+    return fail(c, TEM_EINVAL, "tem_assemble_batch: need 1..4096 meshes and sigma");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  bool same = c->B == n_mesh && c->assembled;
+  for (int b = 0; same && b < n_mesh; ++b) {
+    const tem_mesh &a = c->sub[b]->mesh, &m = meshes[b];
+    same = a.nx == m.nx && a.ny == m.ny && a.nz == m.nz && a.h == m.h && a.mu == m.mu;
+  }
+  if (!same) {
+    free_factors(c);
+    batch_release(c);
+    c->assembled = false;
+    c->analysed = false;
+    c->mesh = tem_mesh{};
+    c->mt = MeshTopo();
+    c->params.clear();
+    for (int b = 0; b < n_mesh; ++b) {
+      tem_ctx *sb = nullptr;
+      tem_status st = tem_create(&sb, c->device, (void *)c->stream);
+      if (st != TEM_OK) {
+        batch_release(c);
+        return fail(c, st, "tem_assemble_batch: cannot create a mesh context");
+      }
+      c->sub.push_back(sb);
+    }
+    c->B = n_mesh;
+  } else {
+    drop_factors(c);
+  }
+  c->cell_off.assign(n_mesh + 1, 0);
+  for (int b = 0; b < n_mesh; ++b)
+    c->cell_off[b + 1] =
+        c->cell_off[b] + (int64_t)meshes[b].nx * meshes[b].ny * meshes[b].nz;
+  for (int b = 0; b < n_mesh; ++b) {
+    tem_status st = tem_assemble(c->sub[b], &meshes[b], sigma_cells + c->cell_off[b], 0, nullptr);
+    if (st != TEM_OK) {
+      std::string msg = std::string("tem_assemble_batch: mesh ") + std::to_string(b) + ": " +
+                        tem_last_error(c->sub[b]);
+      batch_release(c);
+      c->assembled = false;
+      c->analysed = false;
+      return fail(c, st, msg);
+    }
+  }
+  if (c->analysed) {
+    // same meshes, new conductivities: refresh the merged values
+    TRY(batch_values(c));
+    HIPCHK(hipStreamSynchronize(c->stream), "tem_assemble_batch sync");
+  }
+  c->assembled = true;
+  return TEM_OK;
+}
+
+tem_status tem_factor_poles_batch(tem_ctx *c, const int32_t *m, const double *xi,
+                                  tem_precision prec, const tem_factor_opts *opts) {
+  if (!c) return TEM_EINVAL;
+  if (c->B == 0) return fail(c, TEM_ESTATE, "tem_factor_poles_batch: no batch assembled");
+  if (!c->analysed) return fail(c, TEM_ESTATE, "tem_factor_poles_batch: call tem_analyse first");
+  if (!m || !xi) return fail(c, TEM_EINVAL, "tem_factor_poles_batch: NULL pole counts or poles");
+  if (prec != TEM_FP64 && prec != TEM_FP32_IR)
+    return fail(c, TEM_EINVAL, "tem_factor_poles_batch: unknown precision");
+  int MP = 0;
+  int64_t tot = 0;
+  for (int b = 0; b < c->B; ++b) {
+    if (m[b] <= 0 || m[b] > 4096)
+      return fail(c, TEM_EINVAL, "tem_factor_poles_batch: every mesh needs 1..4096 poles");
+    MP = std::max(MP, (int)m[b]);
+    tot += m[b];
+  }
+  for (int64_t i = 0; i < tot; ++i)
+    if (!std::isfinite(xi[2 * i]) || !std::isfinite(xi[2 * i + 1]) || !(xi[2 * i + 1] > 0))
+      return fail(c, TEM_EINVAL, "tem_factor_poles_batch: poles need finite values and Im > 0");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  drop_factors(c);
+  c->surveyed = false;
+  c->w_x.release();
+  c->v_basis.release();
+  // pole table [mesh][MP]; absent slots repeat the mesh's last pole (never
+  // computed: the kernels skip them, the table only stays well defined)
+  c->np_mesh.assign(m, m + c->B);
+  c->MP = MP;
+  c->npole = MP;
+  c->prec = prec;
+  c->xi.assign(2 * (size_t)c->B * MP, 0.0);
+  c->fac_elems = 0;
+  int64_t o = 0;
+  for (int b = 0; b < c->B; ++b) {
+    for (int p = 0; p < MP; ++p) {
+      const int64_t src = o + std::min(p, m[b] - 1);
+      c->xi[2 * ((size_t)b * MP + p)] = xi[2 * src];
+      c->xi[2 * ((size_t)b * MP + p) + 1] = xi[2 * src + 1];
+    }
+    o += m[b];
+    c->fac_elems += (int64_t)m[b] * c->sub[b]->ed.pole_stride;
+  }
+  // pole count of every merged front
+  MF &e = c->ed;
+  e.h_np.assign(e.sym.nodes.size(), 0);
+  int node0 = 0;
+  for (int b = 0; b < c->B; ++b) {
+    const int nn = (int)c->sub[b]->ed.sym.nodes.size();
+    for (int q = 0; q < nn; ++q) e.h_np[node0 + q] = m[b];
+    node0 += nn;
+  }
+  HIPCHK(upload(e.d_np, e.h_np, c->stream), "upload pole counts");
+  return factor_core(c, prec, opts);
+}
+
+tem_status tem_forward_batch(tem_ctx *c, const int32_t *S, const double *F, const int32_t *R,
+                             const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
+                             int32_t K, const double *alpha, const tem_ir_opts *ir, double *d,
+                             tem_ir_stats *stats) {
+  if (!c) return TEM_EINVAL;
+  if (c->B == 0) return fail(c, TEM_ESTATE, "tem_forward_batch: no batch assembled");
+  if (!c->factored) return fail(c, TEM_ESTATE, "tem_forward_batch: call tem_factor_poles_batch first");
+  if (!S || !F || !R || !q_ptr || !q_col || !q_val || !alpha || !d || K <= 0)
+    return fail(c, TEM_EINVAL, "tem_forward_batch: NULL argument or K <= 0");
+  const int B = c->B, MP = c->MP;
+  int Smax = 0;
+  for (int b = 0; b < B; ++b) {
+    if (S[b] <= 0 || S[b] > 16) return fail(c, TEM_EINVAL, "tem_forward_batch: need 1 <= S <= 16");
+    if (R[b] <= 0) return fail(c, TEM_EINVAL, "tem_forward_batch: need R > 0 receivers");
+    Smax = std::max(Smax, (int)S[b]);
+  }
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c);
+  // receivers in merged numbering, residues [mesh][K][MP] (0 for absent poles)
+  std::vector<int64_t> qp(1, 0), qrow(B + 1, 0);
+  std::vector<int32_t> qc;
+  std::vector<double> qv;
+  std::vector<double> al(2 * (size_t)B * K * MP, 0.0);
+  int64_t po = 0, zo = 0, ao = 0;
+  for (int b = 0; b < B; ++b) {
+    const tem_ctx *sb = c->sub[b];
+    const int64_t *pp = q_ptr + po;
+    if (pp[0] != 0) return fail(c, TEM_EINVAL, "tem_forward_batch: each q_ptr block starts at 0");
+    for (int r = 0; r < R[b]; ++r) {
+      if (pp[r + 1] < pp[r]) return fail(c, TEM_EINVAL, "tem_forward_batch: q_ptr not monotone");
+      for (int64_t t = pp[r]; t < pp[r + 1]; ++t) {
+        const int32_t e = q_col[zo + t];
+        const double v = q_val[zo + t];
+        if (e < 0 || e >= sb->mt.n_edges)
+          return fail(c, TEM_EINVAL, "tem_forward_batch: receiver column out of range");
+        if (!std::isfinite(v)) return fail(c, TEM_EINVAL, "tem_forward_batch: non-finite Q value");
+        const int32_t q = sb->ed.pat.edge_new[e];
+        if (q < 0) continue;   // boundary edge: the field is zero there
+        qc.push_back((int32_t)(q + c->row_off[b]));
+        qv.push_back(v);
+      }
+      qp.push_back((int64_t)qc.size());
+    }
+    qrow[b + 1] = qrow[b] + R[b];
+    zo += pp[R[b]];
+    po += R[b] + 1;
+    for (int j = 0; j < K; ++j)
+      for (int p = 0; p < c->np_mesh[b]; ++p) {
+        const double ar = alpha[2 * (ao + (int64_t)j * c->np_mesh[b] + p)];
+        const double ai = alpha[2 * (ao + (int64_t)j * c->np_mesh[b] + p) + 1];
+        if (!std::isfinite(ar) || !std::isfinite(ai))
+          return fail(c, TEM_EINVAL, "tem_forward_batch: non-finite residue");
+        al[2 * (((size_t)b * K + j) * MP + p)] = ar;
+        al[2 * (((size_t)b * K + j) * MP + p) + 1] = ai;
+      }
+    ao += (int64_t)K * c->np_mesh[b];
+  }
+  HIPCHK(upload(c->d_qptr, qp, st), "upload q_ptr");
+  HIPCHK(upload(c->d_qcol, qc, st), "upload q_col");
+  HIPCHK(upload(c->d_qval, qv, st), "upload q_val");
+  HIPCHK(upload(c->d_alpha, al, st), "upload alpha");
+  // sources: merged rows [N][Smax], zero columns past a mesh's own count
+  c->solved = false;
+  TRY(ensure_vec(c, c->d_fnew, sizeof(double) * (size_t)N * Smax, "alloc f"));
+  HIPCHK(launch_fill_f64(st, c->d_fnew.as<double>(), N * Smax, 0.0), "zero f");
+  int64_t fo = 0;
+  for (int b = 0; b < B; ++b) {
+    const tem_ctx *sb = c->sub[b];
+    HIPCHK(launch_gather_rhs(st, sb->ed.N, S[b], Smax, sb->mt.n_edges,
+                             sb->ed.d_row_ent.as<int32_t>(), F + fo,
+                             c->d_fnew.as<double>() + c->row_off[b] * Smax),
+           "gather f");
+    fo += sb->mt.n_edges * S[b];
+  }
+  TRY(ensure_vec(c, c->d_g, sizeof(cpx<double>) * (size_t)MP * N * Smax, "alloc g"));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0), "event");
+  HIPCHK(hipEventCreate(&e1), "event");
+  HIPCHK(hipEventRecord(e0, st), "event");
+  IrResult res;
+  tem_status s = refine_solve(c, c->d_fnew.as<double>(), nullptr, Smax, c->d_g.as<cpx<double>>(),
+                              ir, res);
+  hipEventRecord(e1, st);
+  hipEventSynchronize(e1);
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (s != TEM_OK) return s;
+  c->solve_ms = ms;
+  spans_collect(c);
+  c->last_solves = res.solves;
+  c->S = Smax;
+  int64_t dof = 0;
+  for (int b = 0; b < B; ++b) {
+    HIPCHK(launch_time_assembly(st, S[b], K, R[b], MP, N, Smax, c->d_qptr.as<int64_t>() + qrow[b],
+                                c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
+                                c->d_alpha.as<cpx<double>>() + (size_t)b * K * MP,
+                                c->d_g.as<cpx<double>>(), d + dof),
+           "time assembly");
+    dof += (int64_t)S[b] * K * R[b];
+  }
+  HIPCHK(hipStreamSynchronize(st), "forward sync");
+  fill_stats(res, stats);
+  c->solved = true;
+  if (res.unconverged) {
+    double worst = 0;
+    for (double v : res.rel) worst = std::max(worst, v);
+    char buf[160];
+    std::snprintf(buf, sizeof(buf),
+                  "tem_forward_batch: %d systems above rtol (worst %.3e) after %d solves",
+                  res.unconverged, worst, res.solves);
+    return fail(c, TEM_ENOCONV, buf);
+  }
   return TEM_OK;
 }
 

@@ -56,6 +56,21 @@ struct FrontTab {
   const int32_t *gmap1;     // front position -> row of child 1's update (or -1)
   const int32_t *child0;
   const int32_t *child1;
+  // Ragged pole counts of a batch of meshes: pole slot p0 + z of a launch
+  // (z = its pole index) exists for front s only if p0 + z < np[s].  np is
+  // null when every front has every pole.
+  const int32_t *np;
+  int p0;
+};
+
+// Contiguous index segments, one per mesh of a batch (rows, matrix entries,
+// ...): index i belongs to segment b with off[b] <= i < off[b+1].  Per-mesh
+// tables (shifts, coefficients) are indexed [b * stride + pole].  A single
+// mesh is n = 1 with off = null.
+struct Seg {
+  int n = 1;
+  const int64_t *off = nullptr;
+  int stride = 0;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -74,7 +89,7 @@ hipError_t launch_fill_zero(hipStream_t st, cpx<T> *base, int64_t count, int npo
 template <typename T>
 hipError_t launch_front_assemble(hipStream_t st, int64_t n_entries, const int32_t *csr,
                                  const int64_t *pos, const double *Kv, const double *Mv,
-                                 const double *xi, int npole, cpx<T> *factor,
+                                 const double *xi, Seg entry_seg, int npole, cpx<T> *factor,
                                  int64_t pole_stride);
 
 template <typename T>
@@ -150,26 +165,31 @@ hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
 // f_cplx, [pole][N][S] complex.
 hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                            const int32_t *col, const double *Kv, const double *Mv,
-                           const double *xi, const double *f_real, const cpx<double> *f_cplx,
-                           const cpx<double> *x, cpx<double> *r);
+                           const double *xi, Seg row_seg, const double *f_real,
+                           const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r);
 
 // y = (K - xi_p M) x  (FP64), same layout as residual.
 hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                                const int32_t *col, const double *Kv, const double *Mv,
-                               const double *xi, const cpx<double> *x, cpx<double> *y);
+                               const double *xi, Seg row_seg, const cpx<double> *x,
+                               cpx<double> *y);
 
-// Batched complex dot products over the N dimension for all (pole, s):
+// Batched complex dot products over N rows for all (pole, s):
 // out[p*S+s] = sum_row conj(a) * b (conj_a) or sum a*b.  Deterministic.
-hipError_t launch_batched_dot(hipStream_t st, int64_t N, int npole, int S, const cpx<double> *a,
-                              const cpx<double> *b, bool conj_a, cpx<double> *partial,
-                              int n_partial_blocks, cpx<double> *out);
+// Pole p's rows start at a + p * pstride (pstride = N * S for whole
+// vectors; a row range of a larger vector otherwise).
+hipError_t launch_batched_dot(hipStream_t st, int64_t N, int npole, int S, int64_t pstride,
+                              const cpx<double> *a, const cpx<double> *b, bool conj_a,
+                              cpx<double> *partial, int n_partial_blocks, cpx<double> *out);
 
 // y[p][i][s] += alpha[p*S+s] * x[p][i][s]  (complex alpha per system); mask
 // (int per system, may be null) skips systems with mask == 0.
 // sign multiplies alpha (use -1 for y -= alpha x)
+// With row segments (a batch) the mask is per (segment, pole, s):
+// mask[b * npole * S + p * S + s].
 hipError_t launch_batched_axpy(hipStream_t st, int64_t N, int npole, int S,
                                const cpx<double> *alpha, double sign, const cpx<double> *x,
-                               cpx<double> *y, const int *mask);
+                               cpx<double> *y, const int *mask, Seg row_seg = Seg());
 // inv[i] = 1/sqrt(Re dots[i]) (1 when zero), nrm[i] = sqrt(Re dots[i])
 hipError_t launch_norm_scales(hipStream_t st, int n, const cpx<double> *dots, double *inv,
                               double *nrm);
@@ -187,9 +207,9 @@ template <typename T>
 hipError_t launch_convert_out(hipStream_t st, int64_t n_per_pole, int npole, int S,
                               const cpx<T> *in, const double *scale, cpx<double> *out);
 
-// canonical edge-major real array [n_edges][*] column-major (n_edges x S)
-// -> new-ordering [pole][N][S] complex (imag 0), replicated over poles.
-hipError_t launch_gather_rhs(hipStream_t st, int64_t N, int S, int64_t n_edges,
+// canonical-edge real array F (n_edges x S, column-major) -> new-ordering
+// real rows f_new[q * ldS + s] (ldS >= S), q < N.
+hipError_t launch_gather_rhs(hipStream_t st, int64_t N, int S, int ldS, int64_t n_edges,
                              const int32_t *row_edge, const double *F, double *f_new);
 
 // g [pole][N][S] complex (new order) -> G [pole][S][n_edges] complex (canonical).
@@ -199,7 +219,8 @@ hipError_t launch_scatter_solution(hipStream_t st, int64_t N, int npole, int S, 
 
 // Observation + residue time assembly:
 // d[s][j][r] = 2 Re sum_i alpha[j][i] sum_q Qval * g[i][Qcol][s]
-hipError_t launch_time_assembly(hipStream_t st, int S, int K, int R, int npole, int64_t N,
+// g is [pole][N][ldS] (ldS >= S).
+hipError_t launch_time_assembly(hipStream_t st, int S, int K, int R, int npole, int64_t N, int ldS,
                                 const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
                                 const cpx<double> *alpha, const cpx<double> *g, double *d);
 
@@ -248,8 +269,9 @@ hipError_t launch_assemble_nodal(hipStream_t st, int64_t Nn, const int64_t *rowp
 hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int64_t N,
                          const int32_t *node_edges, const cpx<double> *r, cpx<double> *out);
 // z += coef[pole] * G y
+// coef indexed [segment of the edge row * row_seg.stride + pole]
 hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int64_t Nn,
-                           const int32_t *edge_nodes, const cpx<double> *coef,
+                           const int32_t *edge_nodes, const cpx<double> *coef, Seg row_seg,
                            const cpx<double> *y, cpx<double> *z);
 
 }  // namespace tem

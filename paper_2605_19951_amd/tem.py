@@ -24,7 +24,8 @@ _STATUS = {0: "TEM_OK", -1: "TEM_EINVAL", -2: "TEM_ENOMEM", -3: "TEM_EDEVICE", -
 EXPORTS = ["tem_create", "tem_destroy", "tem_last_error", "tem_assemble", "tem_set_model",
            "tem_export_operators", "tem_analyse", "tem_symbolic_host", "tem_factor_poles",
            "tem_solve_poles", "tem_forward", "tem_jvp", "tem_vjp", "tem_get_stats",
-           "tem_set_profiling", "tem_gn_step"]
+           "tem_set_profiling", "tem_gn_step", "tem_assemble_batch", "tem_factor_poles_batch",
+           "tem_forward_batch"]
 
 
 class TemError(RuntimeError):
@@ -110,6 +111,10 @@ def load_library(path: str = LIB_PATH):
         "tem_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
         "tem_set_profiling": ([vp, i32], C.c_int),
         "tem_gn_step": ([vp, dp, dp, dp, dp, C.c_double, i32, dp, vp, C.POINTER(IrOpts)], C.c_int),
+        "tem_assemble_batch": ([vp, i32, vp, dp], C.c_int),
+        "tem_factor_poles_batch": ([vp, vp, vp, C.c_int, C.POINTER(FactorOpts)], C.c_int),
+        "tem_forward_batch": ([vp, vp, dp, vp, vp, vp, vp, i32, vp, C.POINTER(IrOpts), dp,
+                               C.POINTER(IrStats)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -306,6 +311,55 @@ class Tem:
                                      _dev(dm, "float64", (self.n_params,)),
                                      hist.ctypes.data_as(C.c_void_p), self._ir(ir)))
         return hist
+
+    # ------------------------------------------------------- ragged batches
+    def assemble_batch(self, meshes, mu, sigma):
+        """meshes: list of (nx, ny, nz, h); sigma: float64 GPU tensor of all
+        cells, mesh after mesh.  Puts the context in batch mode."""
+        arr = (Mesh * len(meshes))(*[Mesh(int(a), int(b), int(c), float(h), float(mu))
+                                     for a, b, c, h in meshes])
+        self._bmeshes = arr
+        self.batch = [tuple(m) for m in meshes]
+        self.batch_edges = [a * (b + 1) * (c + 1) + (a + 1) * b * (c + 1) + (a + 1) * (b + 1) * c
+                            for a, b, c, _ in meshes]
+        ncell = sum(a * b * c for a, b, c, _ in meshes)
+        self._chk(self.L.tem_assemble_batch(self.h, len(meshes), C.cast(arr, C.c_void_p),
+                                            _dev(sigma, "float64", (ncell,))))
+
+    def factor_poles_batch(self, xi_list, precision=FP32_IR, mem_budget_bytes=0, max_group=0):
+        """xi_list: one array of poles (Im > 0) per mesh."""
+        m, mp = _host([len(x) for x in xi_list], np.int32)
+        xi = np.concatenate([np.asarray(x, complex) for x in xi_list])
+        buf, bp = _host(np.stack([xi.real, xi.imag], axis=1).reshape(-1), np.float64)
+        self._chk(self.L.tem_factor_poles_batch(self.h, mp, bp, int(precision),
+                                                C.byref(FactorOpts(int(mem_budget_bytes),
+                                                                   int(max_group), 0))))
+        self.batch_m = [len(x) for x in xi_list]
+
+    def forward_batch(self, F, S, receivers, alpha_list, d, ir=None, allow_noconv=False):
+        """F: float64 GPU tensor, mesh b's (S[b], n_edges_b) block after the
+        previous ones; receivers: list of (q_ptr, q_col, q_val) per mesh;
+        alpha_list: (K, m_b) complex residues per mesh; d: float64 GPU tensor
+        receiving mesh b's (S[b], K, R_b) block after the previous ones."""
+        B = len(S)
+        Sa, sp = _host(S, np.int32)
+        Ra, rp = _host([len(q[0]) - 1 for q in receivers], np.int32)
+        qp, qpp = _host(np.concatenate([np.asarray(q[0], np.int64) for q in receivers]), np.int64)
+        qc, qcp = _host(np.concatenate([np.asarray(q[1], np.int32) for q in receivers]), np.int32)
+        qv, qvp = _host(np.concatenate([np.asarray(q[2], np.float64) for q in receivers]),
+                        np.float64)
+        K = np.asarray(alpha_list[0]).shape[0]
+        al = np.concatenate([np.asarray(a, complex).reshape(-1) for a in alpha_list])
+        alb, alp = _host(np.stack([al.real, al.imag], axis=1).reshape(-1), np.float64)
+        nf = sum(int(S[b]) * self.batch_edges[b] for b in range(B))
+        nd = sum(int(S[b]) * K * int(Ra[b]) for b in range(B))
+        MP, Smax = max(self.batch_m), int(max(S))
+        s, it, rr = self._stats_struct(B * MP * Smax)
+        st = self.L.tem_forward_batch(self.h, sp, _dev(F, "float64", (nf,)), rp, qpp, qcp, qvp, K,
+                                      alp, self._ir(ir), _dev(d, "float64", (nd,)), C.byref(s))
+        self._chk(st, (TEM_ENOCONV,) if allow_noconv else ())
+        return dict(iters=it.reshape(B, MP, Smax), rel=rr.reshape(B, MP, Smax),
+                    n_unconverged=s.n_unconverged, status=st)
 
     def set_profiling(self, enable=True):
         self._chk(self.L.tem_set_profiling(self.h, 1 if enable else 0))

@@ -429,3 +429,18 @@ def ragged_batch(seed=5):
         out.append(smooth_workload(n, max(1, int(round(n / 8))), S=S, m=m, K=40, g=4,
                                    seed=seed * 1000 + k, name="hex%d_b%d" % (n, k)))
     return out
+
+
+def small_ragged_batch(seed=7):
+    """A ragged batch small enough for the oracle: three meshes of 12, 13
+    and 14 cells per side (2 air layers), 1..3 loops, 4..7 poles, 9 times,
+    3 x 3 receivers; each mesh draws from its own substream."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, n in enumerate((12, 13, 14)):
+        S = int(rng.integers(1, 4))
+        m = int(rng.integers(4, 8))
+        out.append(smooth_workload(n, 2, S=S, m=m, K=9, g=3, seed=seed * 1000 + k,
+                                   name="hex%d_sb%d" % (n, k)))
+    return out
+
