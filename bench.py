@@ -86,6 +86,75 @@ def run_precision(t, wl, prec, steps, warmup, torch, dev, F, v, w):
     return out, d.cpu().numpy(), jtw.cpu().numpy()
 
 
+def ragged_phase(torch, dev, prec, reps=2):
+    """Twelve meshes (16^3 .. 40^3, 8-16 poles, 1-4 sources, 40 times):
+    factor + forward of the whole batch through the batch entry points
+    against the same meshes one at a time through the single-mesh path.
+    Assemble and analyse are outside the timed region in both cases."""
+    import numpy as np
+    import tem_inputs as ti
+    from paper_2605_19951_amd import Tem
+    wls = ti.ragged_batch()
+    K = len(wls[0].poles.t)
+    # one mesh at a time
+    singles = []
+    for wl in wls:
+        me = wl.mesh
+        t = Tem(0)
+        t.assemble(me.nx, me.ny, me.nz, me.h, 4e-7 * math.pi, torch.tensor(wl.sigma, device=dev),
+                   wl.params)
+        t.analyse()
+        F = torch.tensor(wl.F.T.copy(), device=dev)
+        d = torch.zeros((wl.S, K, wl.rx.n), dtype=torch.float64, device=dev)
+        singles.append((t, F, d))
+    one = []
+    for it in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (t, F, d), wl in zip(singles, wls):
+            t.factor_poles(wl.poles.xi, prec)
+            t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+        torch.cuda.synchronize()
+        one.append(time.perf_counter() - t0)
+    d_one = np.concatenate([d.cpu().numpy().reshape(-1) for _, _, d in singles])
+    for t, _, _ in singles:
+        t.close()
+    del singles
+    # the batch
+    t = Tem(0)
+    t.assemble_batch([(w.mesh.nx, w.mesh.ny, w.mesh.nz, w.mesh.h) for w in wls], 4e-7 * math.pi,
+                     torch.tensor(np.concatenate([w.sigma for w in wls]), device=dev))
+    info = t.analyse()
+    F = torch.tensor(np.concatenate([w.F.T.reshape(-1) for w in wls]), device=dev)
+    d = torch.zeros(sum(w.S * K * w.rx.n for w in wls), dtype=torch.float64, device=dev)
+    bat = []
+    for it in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.factor_poles_batch([w.poles.xi for w in wls], prec)
+        ir = t.forward_batch(F, [w.S for w in wls], [(w.rx.ptr, w.rx.col, w.rx.val) for w in wls],
+                             [w.poles.alpha for w in wls], d)
+        torch.cuda.synchronize()
+        bat.append(time.perf_counter() - t0)
+    d_bat = d.cpu().numpy()
+    t.close()
+    systems = sum(len(w.poles.xi) * w.S for w in wls)
+    tb, to = min(bat), min(one)
+    return dict(meshes=[w.mesh.nx for w in wls], poles=[len(w.poles.xi) for w in wls],
+                sources=[w.S for w in wls], n_unknowns_total=info["n_unknowns"],
+                flops_total=float(sum(len(w.poles.xi) * info_w for w, info_w in
+                                      zip(wls, _flops_per_mesh(wls)))),
+                batch_s=tb, one_at_a_time_s=to, speedup=to / tb,
+                systems_per_s_batch=systems / tb, systems_per_s_one_at_a_time=systems / to,
+                ir_solves=int(ir["iters"].max()),
+                rel_diff_batch_vs_single=float(np.linalg.norm(d_bat - d_one) / np.linalg.norm(d_one)))
+
+
+def _flops_per_mesh(wls):
+    from paper_2605_19951_amd import symbolic_host
+    return [symbolic_host(w.mesh.nx, w.mesh.ny, w.mesh.nz)["flops_per_pole"] for w in wls]
+
+
 def cpu_baseline(flops64):
     """The FP64 oracle on the host: factor + solve of one pole of the same
     generator on a 32^3 mesh (8 sources), scaled to all 16 poles at 64^3 by
@@ -118,6 +187,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the pole-sharded multi-GPU path is not part of this "
@@ -153,6 +223,9 @@ def main():
         acc = dict(data_rel_fp32_vs_fp64=float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
                    jtw_rel_fp32_vs_fp64=float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)))
     t.close()
+    del t
+    if not args.no_ragged:
+        phases["ragged_batch_fp32_ir"] = ragged_phase(torch, dev, FP32_IR)
     ach = res32["update_flops"] / (res32["update_ms"] * 1e-3) if res32["update_ms"] > 0 else 0.0
     roof = dict(bound="mfma", kernel="k_front_update<float>", achieved=ach / 1e12,
                 peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=ach / PEAK_FP32, traffic=None,

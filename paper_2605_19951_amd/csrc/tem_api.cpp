@@ -687,10 +687,10 @@ tem_status ensure_sweep_ws(tem_ctx *c, MF &mf, int npole, int S) {
 // systems whose factors start at F with stride f_stride (0: one shared factor)
 template <typename T>
 tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, int npole,
-                        cpx<T> *x, int S) {
+                        cpx<T> *x, int S, int p0 = 0) {
   TRY(ensure_sweep_ws<T>(c, mf, npole, S));
   hipStream_t st = c->stream;
-  FrontTab ft = front_tab(mf, 0);
+  FrontTab ft = front_tab(mf, p0);
   const int64_t N = mf.N;
   cpx<T> *W[2] = {mf.w_w0.as<cpx<T>>(), mf.w_w1.as<cpx<T>>()};
   const int64_t ws = std::max<int64_t>(mf.w_rows_max, 1) * S;
@@ -750,18 +750,45 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
   return TEM_OK;
 }
 
-// edge sweep with the cached pole factors (timed when profiling)
+// Contiguous pole slots [p0, p0 + n) that still have systems to refine.
+struct PoleRun {
+  int p0, n;
+};
+std::vector<PoleRun> all_poles(const tem_ctx *c) { return {PoleRun{0, c->npole}}; }
+// runs of pole slots with at least one active system ([mesh][pole][s])
+std::vector<PoleRun> active_runs(const tem_ctx *c, const std::vector<int> &active, int S) {
+  const int m = c->npole, mS = m * S;
+  std::vector<char> on(m, 0);
+  for (size_t i = 0; i < active.size(); ++i)
+    if (active[i]) on[(i % mS) / S] = 1;
+  std::vector<PoleRun> runs;
+  for (int p = 0; p < m; ++p) {
+    if (!on[p]) continue;
+    if (!runs.empty() && runs.back().p0 + runs.back().n == p)
+      runs.back().n++;
+    else
+      runs.push_back({p, 1});
+  }
+  return runs;
+}
+
+// edge sweep with the cached pole factors for the poles of `runs`; x is
+// the full [pole][N][S] vector (timed when profiling)
 template <typename T>
-tem_status sweep(tem_ctx *c, cpx<T> *x, int S) {
-  hipEvent_t ea = span_begin(c);
-  tem_status s0 = sweep_levels<T>(c, c->ed, c->d_factor.as<cpx<T>>(), c->ed.pole_stride,
-                                  c->npole, x, S);
-  // each factor entry is read once forward and once backward; the
-  // solution vector is read and written in both passes
-  const double bytes = 2.0 * (double)sizeof(cpx<T>) * (double)c->fac_elems +
-                       4.0 * (double)sizeof(cpx<T>) * (double)c->npole * N_of(c) * S;
-  span_end(c, ea, bytes, 1);
-  return s0;
+tem_status sweep(tem_ctx *c, cpx<T> *x, int S, const std::vector<PoleRun> &runs) {
+  const int64_t N = N_of(c);
+  for (const PoleRun &pr : runs) {
+    hipEvent_t ea = span_begin(c);
+    TRY(sweep_levels<T>(c, c->ed, c->d_factor.as<cpx<T>>() + (int64_t)pr.p0 * c->ed.pole_stride,
+                        c->ed.pole_stride, pr.n, x + (int64_t)pr.p0 * N * S, S, pr.p0));
+    // each factor entry of the run's poles is read once forward and once
+    // backward; the solution vector is read and written in both passes
+    const double bytes =
+        2.0 * (double)sizeof(cpx<T>) * (double)c->fac_elems * pr.n / std::max(c->npole, 1) +
+        4.0 * (double)sizeof(cpx<T>) * (double)pr.n * N * S;
+    span_end(c, ea, bytes, 1);
+  }
+  return TEM_OK;
 }
 
 tem_status ensure_vec(tem_ctx *c, DBuf &b, size_t bytes, const char *what) {
@@ -805,7 +832,8 @@ tem_status sysnorms(tem_ctx *c, const cpx<double> *v, int S, std::vector<double>
 // because K G = 0; one FP64 factor of the nodal matrix G^T M G serves every
 // pole.  This removes the error the FP32 factors leave on the
 // (nearly singular) gradient modes of the low-conductivity region.
-tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S) {
+tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
+                       const std::vector<PoleRun> &runs) {
   hipStream_t st = c->stream;
   const int64_t N = N_of(c), Nn = c->nd.N;
   const int m = c->npole;
@@ -814,20 +842,29 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S) 
                  "alloc nodal vector"));
   cpx<double> *w = c->v_aux.as<cpx<double>>();
   cpx<double> *y = c->d_nvec.as<cpx<double>>();
-  HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                         c->d_K.as<double>(), c->d_M.as<double>(), c->d_xi.as<double>(),
-                         row_seg(c), nullptr, r, z, w),
-         "aux residual");
-  HIPCHK(launch_grad_T(st, Nn, m, S, N, c->d_node_edges.as<int32_t>(), w, y), "G^T");
-  TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, m, y, S));
-  HIPCHK(launch_grad_add(st, N, m, S, Nn, c->d_edge_nodes.as<int32_t>(),
-                         c->d_ncoef.as<cpx<double>>(), row_seg(c), y, z),
-         "z += G y");
+  const Seg rs = row_seg(c);
+  for (const PoleRun &pr : runs) {
+    // the shift and coefficient tables are [mesh][pole]: offsetting them
+    // by p0 keeps the (mesh, p0 + p) entry under index mesh * stride + p
+    const int64_t o = (int64_t)pr.p0 * N * S, on = (int64_t)pr.p0 * Nn * S;
+    HIPCHK(launch_residual(st, N, pr.n, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
+                           c->d_K.as<double>(), c->d_M.as<double>(),
+                           c->d_xi.as<double>() + 2 * pr.p0, rs, nullptr, r + o, z + o, w + o),
+           "aux residual");
+    HIPCHK(launch_grad_T(st, Nn, pr.n, S, N, c->d_node_edges.as<int32_t>(), w + o, y + on),
+           "G^T");
+    TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, pr.n, y + on, S));
+    HIPCHK(launch_grad_add(st, N, pr.n, S, Nn, c->d_edge_nodes.as<int32_t>(),
+                           c->d_ncoef.as<cpx<double>>() + pr.p0, rs, y + on, z + o),
+           "z += G y");
+  }
   return TEM_OK;
 }
 
-// out = A^{-1} in (approximately, in the factor precision), FP64 in/out
-tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
+// out = A^{-1} in (approximately, in the factor precision) for the poles of
+// `runs`, FP64 in/out; other poles of out are left undefined
+tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S,
+                   const std::vector<PoleRun> &runs) {
   hipStream_t st = c->stream;
   const int64_t N = N_of(c);
   const int m = c->npole;
@@ -837,7 +874,7 @@ tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
     cpx<double> *x = c->w_x.as<cpx<double>>();
     HIPCHK(hipMemcpyAsync(x, in, sizeof(cpx<double>) * (size_t)mS * N, hipMemcpyDeviceToDevice, st),
            "copy rhs");
-    TRY(sweep<double>(c, x, S));
+    TRY(sweep<double>(c, x, S, runs));
     HIPCHK(hipMemcpyAsync(out, x, sizeof(cpx<double>) * (size_t)mS * N, hipMemcpyDeviceToDevice, st),
            "copy sol");
     return TEM_OK;
@@ -845,7 +882,7 @@ tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
   TRY(ensure_vec(c, c->w_x, sizeof(cpx<float>) * (size_t)mS * N, "alloc sweep x"));
   const int nb = dot_blocks(N);
   TRY(ensure_vec(c, c->v_partial, sizeof(cpx<double>) * (size_t)nb * mS * 2, "alloc partial"));
-  TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)mS * 64, "alloc dots"));
+  TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)n_seg(c) * mS * 64, "alloc dots"));
   TRY(ensure_vec(c, c->v_inv, sizeof(double) * mS, "alloc inv"));
   TRY(ensure_vec(c, c->v_nrm, sizeof(double) * mS, "alloc nrm"));
   HIPCHK(launch_batched_dot(st, N, m, S, N * S, in, in, true, c->v_partial.as<cpx<double>>(), nb,
@@ -856,9 +893,9 @@ tem_status precond(tem_ctx *c, const cpx<double> *in, cpx<double> *out, int S) {
          "precond scales");
   cpx<float> *x = c->w_x.as<cpx<float>>();
   HIPCHK(launch_convert_in<float>(st, N * S, m, S, in, c->v_inv.as<double>(), x), "to fp32");
-  TRY(sweep<float>(c, x, S));
+  TRY(sweep<float>(c, x, S, runs));
   HIPCHK(launch_convert_out<float>(st, N * S, m, S, x, c->v_nrm.as<double>(), out), "to fp64");
-  if (c->aux && c->nodal_ready) TRY(aux_correct(c, in, out, S));
+  if (c->aux && c->nodal_ready) TRY(aux_correct(c, in, out, S, runs));
   return TEM_OK;
 }
 
@@ -935,7 +972,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       if (!any || it == max_iter) break;
       HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * nsys, st),
              "mask");
-      TRY(precond(c, r, z, S));
+      TRY(precond(c, r, z, S, active_runs(c, active, S)));
       ++solves;
       for (int i = 0; i < nsys; ++i)
         if (active[i]) res.iters[i]++;
@@ -989,7 +1026,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       int kdone = 0;
       std::vector<cpx<double>> hcol((size_t)mS * (kmax + 1));
       for (int k = 0; k < kmax && total < max_iter; ++k) {
-        TRY(precond(c, V + k * vs, z, S));
+        TRY(precond(c, V + k * vs, z, S, all_poles(c)));
         ++solves;
         ++total;
         HIPCHK(launch_spmv_shifted(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
@@ -1080,7 +1117,7 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
                                    nullptr),
                "u += V y");
       }
-      TRY(precond(c, w, z, S));
+      TRY(precond(c, w, z, S, all_poles(c)));
       ++solves;
       std::vector<cpx<double>> one(mS, {1.0, 0.0});
       HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * mS, st),
