@@ -60,50 +60,52 @@ hipError_t launch_front_assemble(hipStream_t st, int64_t n_entries, const int32_
 }
 
 // ----------------------------------------------------------- extend-add
-// Adds the lower triangle of child `slot`'s contribution block into the
-// parent front through the relative row map.  One slot per launch keeps the
-// scatter free of races (two children may hit the same parent entry).
+// Adds child `slot`'s contribution block into its parent front through the
+// relative row map, one column b of the block (rows a >= b) per wave: the
+// list holds (parent front, b) pairs.  Columns whose parent position is a
+// pivot column of the parent go to the panel (before the parent is
+// factored); the others go to the parent's contribution block (after its
+// own update has written it).  One slot per launch keeps the scatter free
+// of races (two children may hit the same parent entry).
 template <typename T>
-__global__ void k_extend_add(FrontTab ft, const int32_t *lvl_nodes, int slot, cpx<T> *factor,
-                             int64_t f_stride, cpx<T> *cb_par, cpx<T> *cb_ch,
-                             int64_t cb_stride) {
-  const int s = lvl_nodes[blockIdx.y];
-  const int p = blockIdx.z;
+__global__ __launch_bounds__(256) void k_extend_add(FrontTab ft, const int2 *cols, int64_t n_cols,
+                                                    int slot, cpx<T> *factor, int64_t f_stride,
+                                                    cpx<T> *cb_par, cpx<T> *cb_ch,
+                                                    int64_t cb_stride) {
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.y;
+  if (e >= n_cols) return;
+  const int s = cols[e].x;
+  const int64_t b = cols[e].y;
   if (pole_absent(ft, s, p)) return;
   const int ch = slot == 0 ? ft.child0[s] : ft.child1[s];
-  if (ch < 0) return;
   const int64_t uc = ft.u[ch];
-  const int64_t cnt = uc * uc;
   const int64_t kp = ft.k[s], up = ft.u[s], np = kp + up;
   const int32_t *rel = ft.rel + ft.rows_off[ch];
-  const cpx<T> *src = cb_ch + (int64_t)p * cb_stride + ft.cb_off[ch];
-  cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  cpx<T> *C = cb_par + (int64_t)p * cb_stride + ft.cb_off[s];
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < cnt;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t a = idx % uc, b = idx / uc;
-    if (a < b) continue;
-    const int64_t ra = rel[a], rb = rel[b];
-    const cpx<T> v = src[idx];
-    if (rb < kp) {
-      cpx<T> *q = P + panel_elem(np, ra, rb);
-      *q = cadd(*q, v);
-    } else {
-      cpx<T> *q = C + (rb - kp) * up + (ra - kp);
-      *q = cadd(*q, v);
-    }
+  const cpx<T> *src = cb_ch + (int64_t)p * cb_stride + ft.cb_off[ch] + b * uc;
+  const int64_t rb = rel[b];
+  cpx<T> *dst;
+  if (rb < kp) {   // panel column rb: element (r, rb) at dst[r]
+    const int64_t r0 = NB * (rb / NB);
+    dst = factor + (int64_t)p * f_stride + ft.panel_off[s] + panel_block_off(np, rb / NB) +
+          (rb - r0) * (np - r0) - r0;
+  } else {         // contribution-block column rb - kp: element (r, rb) at dst[r]
+    dst = cb_par + (int64_t)p * cb_stride + ft.cb_off[s] + (rb - kp) * up - kp;
+  }
+  for (int64_t a = b + lane; a < uc; a += 64) {
+    cpx<T> *q = dst + rel[a];
+    *q = cadd(*q, src[a]);
   }
 }
 
 template <typename T>
-hipError_t launch_extend_add(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                             int slot, int max_u_child, int npole, cpx<T> *factor,
-                             int64_t f_stride, cpx<T> *cb_parent, cpx<T> *cb_child,
-                             int64_t cb_stride) {
-  if (n_nodes <= 0 || max_u_child <= 0) return hipSuccess;
-  int64_t cnt = (int64_t)max_u_child * max_u_child;
-  dim3 grid(grid_1d(cnt, 256, 2048), n_nodes, npole);
-  hipLaunchKernelGGL(k_extend_add<T>, grid, dim3(256), 0, st, ft, lvl_nodes, slot, factor,
+hipError_t launch_extend_add(hipStream_t st, FrontTab ft, const int2 *cols, int64_t n_cols,
+                             int slot, int npole, cpx<T> *factor, int64_t f_stride,
+                             cpx<T> *cb_parent, cpx<T> *cb_child, int64_t cb_stride) {
+  if (n_cols <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n_cols + 3) / 4), npole);
+  hipLaunchKernelGGL(k_extend_add<T>, grid, dim3(256), 0, st, ft, cols, n_cols, slot, factor,
                      f_stride, cb_parent, cb_child, cb_stride);
   return hipGetLastError();
 }
@@ -425,7 +427,8 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
     l0 = 0;
     l1 = k;
   }
-  if (cbeg >= cend || l0 >= l1) return;
+  if (cbeg >= cend) return;
+  if (mode == 0 && l0 >= l1) return;   // mode 1 with k = 0 writes zeros
   // Work split across the eight XCDs: the grid's x extent is a multiple of
   // 8, workgroups are handed to XCDs round robin, so x % 8 names the XCD and
   // each XCD takes one contiguous eighth of the tile sequence, walked in
@@ -497,24 +500,39 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
   // barrier per chunk
   WaveAcc<T, TTS, M3> acc;
   acc.zero();
-  fetch(l0);
-  stage(0);
-  __syncthreads();
-  int bf = 0;
-  for (int64_t l = l0; l < l1; l += KB) {
-    const bool more = l + KB < l1;
-    if (more) fetch(l + KB);
-    acc.step(Ar[bf], Ai[bf], Br[bf], Bi[bf], Dr[bf], Di[bf], wr, wc, lane);
-    if (more) stage(bf ^ 1);
+  if (l1 > l0) {
+    fetch(l0);
+    stage(0);
     __syncthreads();
-    bf ^= 1;
+    int bf = 0;
+    for (int64_t l = l0; l < l1; l += KB) {
+      const bool more = l + KB < l1;
+      if (more) fetch(l + KB);
+      acc.step(Ar[bf], Ai[bf], Br[bf], Bi[bf], Dr[bf], Di[bf], wr, wc, lane);
+      if (more) stage(bf ^ 1);
+      __syncthreads();
+      bf ^= 1;
+    }
   }
-  // epilogue: C += acc on the lower triangle, four entries at a time: their
-  // loads are issued together (entries outside the triangle read the tile's
-  // corner (row0, col0), which always exists), then the valid ones stored.
+  // epilogue on the lower triangle.  Mode 1 writes the contribution block
+  // C = -L21 D L21^T (the children's parts are added after this update).
+  // Mode 0 adds into the panel, four entries at a time: their loads are
+  // issued together (entries outside the triangle read the tile's corner
+  // (row0, col0), which always exists), then the valid ones are stored.
   cpx<T> *Cb = (mode == 1) ? cb + (int64_t)p * cb_stride + ft.cb_off[s] : nullptr;
   cpx<T> *Pw = factor + (int64_t)p * f_stride + ft.panel_off[s];
   constexpr int NE = WaveAcc<T, TTS, M3>::nelem(), GE = 4;
+  if (mode == 1) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      int rr, cc;
+      WaveAcc<T, TTS, M3>::coord(lane, e, rr, cc);
+      const int64_t row = row0 + wr * (TTS / 2) + rr, col = col0 + wc * (TTS / 2) + cc;
+      if (row >= n || col >= cend || row < col) continue;
+      Cb[(col - k) * u + (row - k)] = {acc.get_re(e), acc.get_im(e)};
+    }
+    return;
+  }
 #pragma unroll
   for (int e0 = 0; e0 < NE; e0 += GE) {
     cpx<T> *qp[GE];
@@ -527,7 +545,7 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
       const int64_t row = row0 + wr * (TTS / 2) + rr, col = col0 + wc * (TTS / 2) + cc;
       ok[j] = !(row >= n || col >= cend || row < col);
       const int64_t r = ok[j] ? row : row0, c = ok[j] ? col : col0;
-      qp[j] = (mode == 1) ? Cb + (c - k) * u + (r - k) : Pw + panel_elem(n, r, c);
+      qp[j] = Pw + panel_elem(n, r, c);
       cv[j] = *qp[j];
     }
 #pragma unroll
@@ -572,8 +590,8 @@ hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_n
   template hipError_t launch_front_assemble<T>(hipStream_t, int64_t, const int32_t *,            \
                                                const int64_t *, const double *, const double *,  \
                                                const double *, Seg, int, cpx<T> *, int64_t);     \
-  template hipError_t launch_extend_add<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \
-                                           int, cpx<T> *, int64_t, cpx<T> *, cpx<T> *, int64_t);  \
+  template hipError_t launch_extend_add<T>(hipStream_t, FrontTab, const int2 *, int64_t, int, int, \
+                                           cpx<T> *, int64_t, cpx<T> *, cpx<T> *, int64_t);      \
   template hipError_t launch_panel_diag<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \
                                            cpx<T> *, int64_t, int *);                            \
   template hipError_t launch_panel_trsm<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \

@@ -84,6 +84,9 @@ struct LevelInfo {
   int64_t amap_begin = 0, amap_end = 0;
   int64_t cb_size = 0;             // elements per pole
   int64_t w_rows = 0;              // update rows per pole
+  // extend-add column lists per child slot: [xa, xm) go to the panels,
+  // [xm, xe) to the contribution blocks (offsets into d_xcols)
+  int64_t xa[2] = {0, 0}, xm[2] = {0, 0}, xe[2] = {0, 0};
 };
 
 struct Tiles {
@@ -108,7 +111,7 @@ struct MF {
   int64_t N = 0;
   DBuf d_rowptr, d_col, d_row_ent, d_ent_new;
   DBuf d_first, d_k, d_u, d_rows_off, d_rows, d_rel, d_panel_off, d_cb_off, d_w_off, d_gmap_off,
-      d_gmap0, d_gmap1, d_child0, d_child1, d_lvl_nodes, d_amap_csr, d_amap_pos;
+      d_gmap0, d_gmap1, d_child0, d_child1, d_lvl_nodes, d_amap_csr, d_amap_pos, d_xcols;
   std::vector<LevelInfo> levels;   // by depth (0 = root)
   int64_t pole_stride = 0;         // panel elements per pole
   int64_t cb_stride = 0;           // max level CB elements per pole
@@ -460,6 +463,29 @@ tem_status build_front_maps(tem_ctx *c, MF &mf) {
     }
     li.amap_end = (int64_t)amap_csr.size();
   }
+  // extend-add column lists, level by level and child slot by slot
+  std::vector<int32_t> xcols;
+  for (int L = nl - 1; L >= 0; --L) {
+    LevelInfo &li = mf.levels[L];
+    for (int sl = 0; sl < 2; ++sl) {
+      li.xa[sl] = (int64_t)xcols.size() / 2;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) li.xm[sl] = (int64_t)xcols.size() / 2;
+        for (int s : li.nodes) {
+          const int ch = sym.nodes[s].child[sl];
+          if (ch < 0) continue;
+          const SymNode &cn = sym.nodes[ch];
+          for (int64_t bcol = 0; bcol < cn.nrows; ++bcol) {
+            const bool to_panel = rel[cn.rows_off + bcol] < kk[s];
+            if (to_panel != (pass == 0)) continue;
+            xcols.push_back(s);
+            xcols.push_back((int32_t)bcol);
+          }
+        }
+      }
+      li.xe[sl] = (int64_t)xcols.size() / 2;
+    }
+  }
   // child gather maps for the solves
   std::vector<int32_t> gmap0, gmap1;
   int64_t goff = 0;
@@ -498,6 +524,7 @@ tem_status build_front_maps(tem_ctx *c, MF &mf) {
   HIPCHK(upload(mf.d_lvl_nodes, lvl_nodes, st), "upload levels");
   HIPCHK(upload(mf.d_amap_csr, amap_csr, st), "upload amap_csr");
   HIPCHK(upload(mf.d_amap_pos, amap_pos, st), "upload amap_pos");
+  HIPCHK(upload(mf.d_xcols, xcols, st), "upload extend-add lists");
   HIPCHK(hipStreamSynchronize(st), "sync maps");
   return TEM_OK;
 }
@@ -594,16 +621,16 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
     HIPCHK(launch_fill_zero<T>(st, F + li.panel_begin, li.panel_end - li.panel_begin, g,
                                mf.pole_stride),
            "zero panels");
-    HIPCHK(launch_fill_zero<T>(st, cbL, li.cb_size, g, mf.cb_stride), "zero cb");
     HIPCHK(launch_front_assemble<T>(st, li.amap_end - li.amap_begin,
                                     mf.d_amap_csr.as<int32_t>() + li.amap_begin,
                                     mf.d_amap_pos.as<int64_t>() + li.amap_begin, Kv, Mv, xi, xseg,
                                     g, F, mf.pole_stride),
            "front assemble");
+    const int2 *xl = mf.d_xcols.as<int2>();
     for (int sl = 0; sl < 2; ++sl)
-      HIPCHK(launch_extend_add<T>(st, ft, ln, li.n, sl, li.max_u_child[sl], g, F, mf.pole_stride,
-                                  cbL, cbC, mf.cb_stride),
-             "extend-add");
+      HIPCHK(launch_extend_add<T>(st, ft, xl + li.xa[sl], li.xm[sl] - li.xa[sl], sl, g, F,
+                                  mf.pole_stride, cbL, cbC, mf.cb_stride),
+             "extend-add into panels");
     // 128-column panels: inside a panel every 32-column block is factored and
     // applied (rank 32) to the rest of the panel only; the panel then
     // updates all later columns at once (rank 128).
@@ -659,7 +686,7 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
     for (int s : li.nodes) {
       const SymNode &nd = sym.nodes[s];
       const int64_t k = nd.last - nd.first, n = k + nd.nrows;
-      if (k > 0) cb_tiles = std::max(cb_tiles, Tiles::count(n, k, n, ttc));
+      if (nd.nrows > 0) cb_tiles = std::max(cb_tiles, Tiles::count(n, k, n, ttc));
       fl += 8.0 * (double)k * (double)nd.nrows * (double)(nd.nrows + 1) / 2.0 *
             mf.present(s, p0, g);
     }
@@ -668,6 +695,10 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
                                   cbL, mf.cb_stride, ttc, upd_m3<T>(c)),
            "contribution update");
     span_end(c, ea, fl, 0);
+    for (int sl = 0; sl < 2; ++sl)
+      HIPCHK(launch_extend_add<T>(st, ft, xl + li.xm[sl], li.xe[sl] - li.xm[sl], sl, g, F,
+                                  mf.pole_stride, cbL, cbC, mf.cb_stride),
+             "extend-add into contribution blocks");
   }
   return TEM_OK;
 }

@@ -92,11 +92,11 @@ hipError_t launch_front_assemble(hipStream_t st, int64_t n_entries, const int32_
                                  const double *xi, Seg entry_seg, int npole, cpx<T> *factor,
                                  int64_t pole_stride);
 
+// cols: n_cols (parent front, child column) pairs of child `slot`
 template <typename T>
-hipError_t launch_extend_add(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                             int slot, int max_u_child, int npole, cpx<T> *factor,
-                             int64_t f_stride, cpx<T> *cb_parent, cpx<T> *cb_child,
-                             int64_t cb_stride);
+hipError_t launch_extend_add(hipStream_t st, FrontTab ft, const int2 *cols, int64_t n_cols,
+                             int slot, int npole, cpx<T> *factor, int64_t f_stride,
+                             cpx<T> *cb_parent, cpx<T> *cb_child, int64_t cb_stride);
 
 template <typename T>
 hipError_t launch_panel_diag(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
