@@ -22,6 +22,27 @@ __device__ __forceinline__ const cpx<T> *col_ptr(const cpx<T> *P, int64_t n, int
   return P + panel_block_off(n, b) + (c - r0) * ld - r0;
 }
 
+// Stages rows r0 .. r0+nr-1 of columns 0 .. w-1 of a column block (column
+// l at Lc + l * ld) into Lt[l][i], zero past nr rows and w columns.  The
+// loads go to clamped in-bounds positions and are all issued before any is
+// used (256 threads).
+template <typename T, int RTS>
+__device__ __forceinline__ void stage_tile(cpx<T> (*Lt)[RTS + 1], const cpx<T> *Lc, int64_t ld,
+                                           int64_t r0, int nr, int w, int tid) {
+  constexpr int PERT = RTS * NB / 256;
+  cpx<T> v[PERT];
+#pragma unroll
+  for (int q = 0; q < PERT; ++q) {
+    const int idx = tid + 256 * q, i = idx % RTS, l = idx / RTS;
+    v[q] = Lc[(int64_t)min(l, w - 1) * ld + r0 + min(i, nr - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < PERT; ++q) {
+    const int idx = tid + 256 * q, i = idx % RTS, l = idx / RTS;
+    Lt[l][i] = (i < nr && l < w) ? v[q] : czero<T>();
+  }
+}
+
 // ------------------------------------------------------------ forward tri
 // Solves the diagonal blocks of columns [cb, ce), ce = min(cb + BB, k), and
 // updates only the rows inside that range; cb == 0 first adds the children's
@@ -47,13 +68,35 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
   const int c0 = ft.child0[s], c1 = ft.child1[s];
   const cpx<T> *W0 = c0 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c0] * S : nullptr;
   const cpx<T> *W1 = c1 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c1] * S : nullptr;
-  if (c0 >= 0 && cb == 0) {
-    for (int64_t idx = tid; idx < k * S; idx += blockDim.x) {
-      const int64_t q = idx / S, c = idx % S;
-      cpx<T> v = X[idx];
-      if (gm0[q] >= 0) v = cadd(v, W0[(int64_t)gm0[q] * S + c]);
-      if (gm1[q] >= 0) v = cadd(v, W1[(int64_t)gm1[q] * S + c]);
-      X[idx] = v;
+  const bool h0 = c0 >= 0 && ft.u[c0] > 0, h1 = c1 >= 0 && ft.u[c1] > 0;
+  if ((h0 || h1) && cb == 0) {
+    // four elements per thread in flight: maps, then child rows, then sums
+    const int64_t tot = k * S;
+    for (int64_t base = tid; base < tot; base += 4 * 256) {
+      int g0[4], g1[4];
+      cpx<T> xv[4], v0[4], v1[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t id = min(base + 256 * j, tot - 1), q = id / S;
+        g0[j] = h0 ? gm0[q] : -1;
+        g1[j] = h1 ? gm1[q] : -1;
+        xv[j] = X[id];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t id = min(base + 256 * j, tot - 1), c = id % S;
+        v0[j] = h0 ? W0[(int64_t)max(g0[j], 0) * S + c] : czero<T>();
+        v1[j] = h1 ? W1[(int64_t)max(g1[j], 0) * S + c] : czero<T>();
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t id = base + 256 * j;
+        if (id >= tot) continue;
+        cpx<T> v = xv[j];
+        if (g0[j] >= 0) v = cadd(v, v0[j]);
+        if (g1[j] >= 0) v = cadd(v, v1[j]);
+        X[id] = v;
+      }
     }
   }
   __shared__ cpx<T> Li[NB][NB + 1];   // Li[j][l]: inverse of the unit-lower diagonal block
@@ -68,7 +111,8 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
     for (int idx = tid; idx < w * w; idx += blockDim.x) {
       const int j = idx % w, l = idx / w;
       // stored transposed in the upper part: Linv[j][l] at (row jb+l, col jb+j)
-      if (l < j) Li[j][l] = Lc[(int64_t)j * ld + jb + l];
+      // (entries l >= j are read but not used)
+      Li[j][l] = Lc[(int64_t)j * ld + jb + l];
     }
     for (int idx = tid; idx < w * S; idx += blockDim.x) V[idx / S][idx % S] = X[(jb) * S + idx];
     __syncthreads();
@@ -83,10 +127,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
     // rows below inside the range: X[r] -= sum_l L(r, jb+l) Y[l]
     for (int64_t rc = jb + w; rc < ce; rc += RTT) {
       const int nr = (int)min((int64_t)RTT, ce - rc);
-      for (int idx = tid; idx < RTT * w; idx += blockDim.x) {
-        const int i = idx % RTT, l = idx / RTT;
-        Lt[l][i] = (i < nr) ? Lc[(int64_t)l * ld + rc + i] : czero<T>();
-      }
+      stage_tile<T, RTT>(Lt, Lc, ld, rc, nr, w, tid);
       __syncthreads();
       for (int idx = tid; idx < nr * S; idx += blockDim.x) {
         const int i = idx / S, c = idx % S;
@@ -139,10 +180,7 @@ __global__ __launch_bounds__(256) void k_fwd_rows(FrontTab ft, const int32_t *lv
     int64_t ld;
     const cpx<T> *Lc = col_ptr(P, n, jb, ld);
     __syncthreads();
-    for (int idx = tid; idx < RT * w; idx += blockDim.x) {
-      const int i = idx % RT, l = idx / RT;
-      Lt[l][i] = (i < na) ? Lc[(int64_t)l * ld + a0 + i] : czero<T>();
-    }
+    stage_tile<T, RT>(Lt, Lc, ld, a0, na, w, tid);
     for (int idx = tid; idx < w * S; idx += blockDim.x) Y[idx / S][idx % S] = X[jb * S + idx];
     __syncthreads();
 #pragma unroll
@@ -179,85 +217,81 @@ hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 
 // ------------------------------------------------------------ forward rect
 // W_s[a] = child updates at front row k+a  -  sum_j L(k+a, j) y_j
+// Each thread owns one update row a of the front (256 rows per workgroup)
+// and all right-hand sides: W[a] = (children's rows) - sum_l L(k + a, l) y_l.
+// The panel row is read straight from HBM, one column block (FR columns)
+// of loads in flight per thread; y is staged in LDS and read by broadcast.
+template <typename T>
+struct FwdRectCfg {
+  static constexpr int FR = 32;   // columns loaded ahead per thread
+};
+template <>
+struct FwdRectCfg<double> {
+  static constexpr int FR = 16;
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fwd_rect(FrontTab ft, const int32_t *lvl_nodes, int S,
                                                   int64_t N, const cpx<T> *factor,
                                                   int64_t f_stride, const cpx<T> *x,
                                                   const cpx<T> *w_child, cpx<T> *w_out,
                                                   int64_t w_stride) {
+  constexpr int FR = FwdRectCfg<T>::FR;
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
   if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
-  const int64_t a0 = (int64_t)blockIdx.x * RT;
+  const int64_t a0 = (int64_t)blockIdx.x * 256;
   if (a0 >= u) return;
-  const int na = (int)min((int64_t)RT, u - a0);
+  const int tid = threadIdx.x;
+  const int64_t a = a0 + tid, ac = min(a, u - 1);
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
   const cpx<T> *X = x + ((int64_t)p * N + first) * S;
-  const int tid = threadIdx.x;
-  const int32_t *gm0 = ft.gmap0 + ft.gmap_off[s] + k;
-  const int32_t *gm1 = ft.gmap1 + ft.gmap_off[s] + k;
+  // the children's update rows for row a
   const int c0 = ft.child0[s], c1 = ft.child1[s];
-  const cpx<T> *W0 = c0 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c0] * S : nullptr;
-  const cpx<T> *W1 = c1 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c1] * S : nullptr;
-  // each thread owns up to 4 (row, rhs) pairs: idx = tid + 256 q
-  cpx<T> acc[4];
+  const bool h0 = c0 >= 0 && ft.u[c0] > 0, h1 = c1 >= 0 && ft.u[c1] > 0;
+  const int g0 = h0 ? ft.gmap0[ft.gmap_off[s] + k + ac] : -1;
+  const int g1 = h1 ? ft.gmap1[ft.gmap_off[s] + k + ac] : -1;
+  const cpx<T> *W0 = h0 ? w_child + (int64_t)p * w_stride + (ft.w_off[c0] + max(g0, 0)) * S
+                        : nullptr;
+  const cpx<T> *W1 = h1 ? w_child + (int64_t)p * w_stride + (ft.w_off[c1] + max(g1, 0)) * S
+                        : nullptr;
+  cpx<T> acc[16];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    acc[q] = czero<T>();
-    const int idx = tid + 256 * q;
-    if (idx < na * S) {
-      const int i = idx / S, c = idx % S;
-      const int64_t a = a0 + i;
-      if (c0 >= 0 && gm0[a] >= 0) acc[q] = cadd(acc[q], W0[(int64_t)gm0[a] * S + c]);
-      if (c1 >= 0 && gm1[a] >= 0) acc[q] = cadd(acc[q], W1[(int64_t)gm1[a] * S + c]);
+  for (int c = 0; c < 16; ++c) {
+    acc[c] = czero<T>();
+    if (c < S) {
+      if (g0 >= 0) acc[c] = cadd(acc[c], W0[c]);
+      if (g1 >= 0) acc[c] = cadd(acc[c], W1[c]);
     }
   }
-  __shared__ cpx<T> Lt[NB][RT + 1];
-  __shared__ cpx<T> Y[NB][16];
-  // register prefetch of the next 64 x 32 panel tile (8 elements per thread)
-  cpx<T> pre[8];
-  auto fetch = [&](int64_t jb) {
-    const int w = (int)min((int64_t)NB, k - jb);
+  __shared__ cpx<T> Y[FR][16];
+  for (int64_t jb = 0; jb < k; jb += FR) {
+    const int w = (int)min((int64_t)FR, k - jb);
+    // FR consecutive columns lie in one NB-column block of the panel;
+    // column jb + l is at Lc + l * ld
     int64_t ld;
     const cpx<T> *Lc = col_ptr(P, n, jb, ld);
+    cpx<T> lv[FR];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q, i = idx % RT, l = idx / RT;
-      pre[q] = (i < na && l < w) ? Lc[(int64_t)l * ld + k + a0 + i] : czero<T>();
-    }
-  };
-  if (k > 0) fetch(0);
-  for (int64_t jb = 0; jb < k; jb += NB) {
-    const int w = (int)min((int64_t)NB, k - jb);
+    for (int l = 0; l < FR; ++l) lv[l] = Lc[(int64_t)min(l, w - 1) * ld + k + ac];
+    __syncthreads();
+    for (int idx = tid; idx < w * S; idx += 256) Y[idx / S][idx % S] = X[jb * S + idx];
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q;
-      Lt[idx / RT][idx % RT] = pre[q];
-    }
-    for (int idx = tid; idx < w * S; idx += blockDim.x) Y[idx / S][idx % S] = X[jb * S + idx];
-    __syncthreads();
-    if (jb + NB < k) fetch(jb + NB);
+    for (int l = 0; l < FR; ++l) {
+      if (l < w) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q;
-      if (idx < na * S) {
-        const int i = idx / S, c = idx % S;
-        cpx<T> sacc = acc[q];
-        for (int l = 0; l < w; ++l) {
-          const cpx<T> pr = cmul(Lt[l][i], Y[l][c]);
-          sacc = csub(sacc, pr);
-        }
-        acc[q] = sacc;
+        for (int c = 0; c < 16; ++c)
+          if (c < S) acc[c] = csub(acc[c], cmul(lv[l], Y[l][c]));
       }
     }
   }
-  cpx<T> *Wo = w_out + (int64_t)p * w_stride + ft.w_off[s] * S;
+  if (a < u) {
+    cpx<T> *Wo = w_out + (int64_t)p * w_stride + (ft.w_off[s] + a) * S;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = tid + 256 * q;
-    if (idx < na * S) Wo[a0 * S + idx] = acc[q];
+    for (int c = 0; c < 16; ++c)
+      if (c < S) Wo[c] = acc[c];
   }
 }
 
@@ -267,7 +301,7 @@ hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
                            int64_t f_stride, const cpx<T> *x, const cpx<T> *w_child,
                            cpx<T> *w_out, int64_t w_stride) {
   if (n_nodes <= 0 || max_u <= 0) return hipSuccess;
-  dim3 grid((max_u + RT - 1) / RT, n_nodes, npole);
+  dim3 grid((max_u + 255) / 256, n_nodes, npole);
   hipLaunchKernelGGL(k_fwd_rect<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
                      x, w_child, w_out, w_stride);
   return hipGetLastError();
@@ -300,19 +334,20 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
   acc[1] = czero<T>();
   // register prefetch of the next 64-row tile: 8 panel elements and up to
   // 4 x-values per thread
+  // (loads from clamped in-bounds positions; masking happens in LDS)
   cpx<T> pre[8], prx[4];
   auto fetch = [&](int64_t ac) {
     const int na = (int)min((int64_t)RT, u - ac);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q, i = idx % RT, l = idx / RT;
-      pre[q] = (i < na && l < w) ? Lc[(int64_t)l * ld + k + ac + i] : czero<T>();
+      const int idx = tid + 256 * q, i = min(idx % RT, na - 1), l = min(idx / RT, w - 1);
+      pre[q] = Lc[(int64_t)l * ld + k + ac + i];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
-      const int i = idx / S, c = idx % S;
-      prx[q] = (idx < na * S) ? Xp[(int64_t)rows[ac + i] * S + c] : czero<T>();
+      const int i = min(idx / S, na - 1), c = idx % S;
+      prx[q] = Xp[(int64_t)rows[ac + i] * S + c];
     }
   };
   if (u > 0) fetch(0);
@@ -322,7 +357,8 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int idx = tid + 256 * q;
-      Lt[idx / RT][idx % RT] = pre[q];
+      const bool ok = idx % RT < na && idx / RT < w;
+      Lt[idx / RT][idx % RT] = ok ? pre[q] : czero<T>();
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -402,10 +438,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
     for (int64_t rc = jb + w; rc < ce; rc += RTT) {
       const int nr = (int)min((int64_t)RTT, ce - rc);
       __syncthreads();
-      for (int idx = tid; idx < RTT * w; idx += blockDim.x) {
-        const int i = idx % RTT, l = idx / RTT;
-        Lt[l][i] = (i < nr) ? Lc[(int64_t)l * ld + rc + i] : czero<T>();
-      }
+      stage_tile<T, RTT>(Lt, Lc, ld, rc, nr, w, tid);
       for (int idx = tid; idx < nr * S; idx += blockDim.x) Xt[idx / S][idx % S] = X[rc * S + idx];
       __syncthreads();
 #pragma unroll
@@ -422,7 +455,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
     __syncthreads();
     for (int idx = tid; idx < w * w; idx += blockDim.x) {
       const int j = idx % w, l = idx / w;
-      if (l < j) Li[j][l] = Lc[(int64_t)j * ld + jb + l];
+      Li[j][l] = Lc[(int64_t)j * ld + jb + l];   // entries l >= j unused
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -521,10 +554,7 @@ __global__ __launch_bounds__(256) void k_bwd_cols(FrontTab ft, const int32_t *lv
   for (int64_t rc = cb; rc < ce; rc += RT) {
     const int nr = (int)min((int64_t)RT, ce - rc);
     __syncthreads();
-    for (int idx = tid; idx < RT * w; idx += blockDim.x) {
-      const int i = idx % RT, l = idx / RT;
-      Lt[l][i] = (i < nr) ? Lc[(int64_t)l * ld + rc + i] : czero<T>();
-    }
+    stage_tile<T, RT>(Lt, Lc, ld, rc, nr, w, tid);
     for (int idx = tid; idx < nr * S; idx += blockDim.x) Xt[idx / S][idx % S] = X[rc * S + idx];
     __syncthreads();
 #pragma unroll
