@@ -329,12 +329,20 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
   const cpx<T> *Lc = col_ptr(P, n, jb, ld);
   __shared__ cpx<T> Lt[NB][RT + 1];
   __shared__ cpx<T> Xt[RT][16];
-  cpx<T> acc[2];
-  acc[0] = czero<T>();
-  acc[1] = czero<T>();
+  // register blocking: a thread owns LB columns x CBK right-hand sides of
+  // the block's outputs over the rows i = grp, grp + ngrp, ... of each tile
+  constexpr int LB = 4;
+  const int CBK = (S % 2 == 0) ? 2 : 1;
+  const int nlb = NB / LB, nblk = nlb * (S / CBK), ngrp = 256 / nblk;
+  const int blk = tid % nblk, grp = tid / nblk;
+  const bool live = grp < ngrp;
+  const int l0 = (blk % nlb) * LB, cb0 = (blk / nlb) * CBK;
+  cpx<T> acc[LB][2];
+#pragma unroll
+  for (int j = 0; j < LB; ++j) acc[j][0] = acc[j][1] = czero<T>();
   // register prefetch of the next 64-row tile: 8 panel elements and up to
-  // 4 x-values per thread
-  // (loads from clamped in-bounds positions; masking happens in LDS)
+  // 4 x-values per thread (loads from clamped in-bounds positions; masking
+  // happens in LDS)
   cpx<T> pre[8], prx[4];
   auto fetch = [&](int64_t ac) {
     const int na = (int)min((int64_t)RT, u - ac);
@@ -367,22 +375,36 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
     }
     __syncthreads();
     if (ac + RT < u) fetch(ac + RT);
+    if (live) {
+      for (int i = grp; i < na; i += ngrp) {
+        const cpx<T> x0 = Xt[i][cb0], x1 = Xt[i][cb0 + CBK - 1];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int idx = tid + 256 * q;
-      if (idx < w * S) {
-        const int l = idx / S, c = idx % S;
-        cpx<T> sacc = acc[q];
-        for (int i = 0; i < na; ++i) sacc = cfma(Lt[l][i], Xt[i][c], sacc);
-        acc[q] = sacc;
+        for (int j = 0; j < LB; ++j) {
+          const cpx<T> lv = Lt[l0 + j][i];
+          acc[j][0] = cfma(lv, x0, acc[j][0]);
+          acc[j][1] = cfma(lv, x1, acc[j][1]);
+        }
       }
     }
   }
-  cpx<T> *To = t + (int64_t)p * t_stride + (first + jb) * S;
+  // sum the row groups' partials in a fixed order (LDS reused)
+  __syncthreads();
+  cpx<T> *red = &Lt[0][0];   // [grp][blk][LB][CBK], 256 * LB * 2 <= NB * (RT + 1) entries
+  if (live) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int idx = tid + 256 * q;
-    if (idx < w * S) To[idx] = acc[q];
+    for (int j = 0; j < LB; ++j)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+        if (cc < CBK) red[((grp * nblk + blk) * LB + j) * CBK + cc] = acc[j][cc];
+  }
+  __syncthreads();
+  cpx<T> *To = t + (int64_t)p * t_stride + (first + jb) * S;
+  for (int idx = tid; idx < w * S; idx += 256) {
+    const int l = idx / S, c = idx % S;
+    const int b = (l / LB) + nlb * (c / CBK), j = l % LB, cc = c % CBK;
+    cpx<T> v = czero<T>();
+    for (int g = 0; g < ngrp; ++g) v = cadd(v, red[((g * nblk + b) * LB + j) * CBK + cc]);
+    To[idx] = v;
   }
 }
 

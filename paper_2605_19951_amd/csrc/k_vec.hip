@@ -73,54 +73,76 @@ hipError_t launch_assemble_KM(hipStream_t st, int64_t N, const int64_t *rowptr, 
 }
 
 // ------------------------------------------------------ shifted products
-// one thread per (row, pole, rhs); x, y, r: [pole][N][S]
+// One thread per (row, rhs, group of RG poles): the row's K, M entries and
+// column indices are loaded once and applied to RG poles; x, y, r are
+// [pole][N][S], threads ordered rhs fastest, then row, then pole group.
+constexpr int RG = 4;
+
 __global__ void k_residual(int64_t N, int npole, int S, const int64_t *rowptr,
                            const int32_t *col, const double *Kv, const double *Mv,
                            const double *xi, Seg sg, const double *f_real,
                            const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r,
                            int mode) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t mS = (int64_t)npole * S;
-  if (idx >= N * mS) return;
-  const int64_t q = idx / mS;
-  const int ps = (int)(idx % mS);
-  const int p = ps / S, c = ps % S;
-  const int64_t xo = 2 * ((int64_t)seg_find(sg, q) * sg.stride + p);
-  const double xr = xi[xo], xim = xi[xo + 1];
-  const cpx<double> *X = x + (int64_t)p * N * S + c;
-  double ar = 0.0, ai = 0.0;
+  const int ng = (npole + RG - 1) / RG;
+  if (idx >= N * S * ng) return;
+  const int c = (int)(idx % S);
+  const int64_t q = (idx / S) % N;
+  const int g = (int)(idx / ((int64_t)S * N));
+  const int64_t xb = 2 * (int64_t)seg_find(sg, q) * sg.stride;
+  double xr[RG], xim[RG], ar[RG], ai[RG];
+  const cpx<double> *X[RG];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    const int p = min(g * RG + j, npole - 1);
+    xr[j] = xi[xb + 2 * p];
+    xim[j] = xi[xb + 2 * p + 1];
+    X[j] = x + (int64_t)p * N * S + c;
+    ar[j] = 0.0;
+    ai[j] = 0.0;
+  }
   for (int64_t t = rowptr[q]; t < rowptr[q + 1]; ++t) {
     const double kv = Kv[t], mv = Mv[t];
-    const cpx<double> v = X[(int64_t)col[t] * S];
-    // (K - xi M) v, xi M v = (xr + i xim) mv v
-    const double sr = kv - xr * mv, si = -xim * mv;
-    ar += sr * v.re - si * v.im;
-    ai += sr * v.im + si * v.re;
-  }
-  cpx<double> out;
-  if (mode == 0) {
-    out.re = ar;
-    out.im = ai;
-  } else {
-    double fr = 0.0, fi = 0.0;
-    if (f_cplx) {
-      const cpx<double> f = f_cplx[((int64_t)p * N + q) * S + c];
-      fr = f.re;
-      fi = f.im;
-    } else if (f_real) {
-      fr = f_real[q * S + c];
+    const int64_t o = (int64_t)col[t] * S;
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      const cpx<double> v = X[j][o];
+      // (K - xi M) v, xi M v = (xr + i xim) mv v
+      const double sr = kv - xr[j] * mv, si = -xim[j] * mv;
+      ar[j] += sr * v.re - si * v.im;
+      ai[j] += sr * v.im + si * v.re;
     }
-    out.re = fr - ar;
-    out.im = fi - ai;
   }
-  r[((int64_t)p * N + q) * S + c] = out;
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    const int p = g * RG + j;
+    if (p >= npole) break;
+    cpx<double> out;
+    if (mode == 0) {
+      out.re = ar[j];
+      out.im = ai[j];
+    } else {
+      double fr = 0.0, fi = 0.0;
+      if (f_cplx) {
+        const cpx<double> f = f_cplx[((int64_t)p * N + q) * S + c];
+        fr = f.re;
+        fi = f.im;
+      } else if (f_real) {
+        fr = f_real[q * S + c];
+      }
+      out.re = fr - ar[j];
+      out.im = fi - ai[j];
+    }
+    r[((int64_t)p * N + q) * S + c] = out;
+  }
 }
 
 hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                            const int32_t *col, const double *Kv, const double *Mv,
                            const double *xi, Seg sg, const double *f_real,
                            const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r) {
-  const int64_t tot = N * npole * S;
+  const int64_t tot = N * S * ((npole + RG - 1) / RG);
+  if (tot <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_residual, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
                      rowptr, col, Kv, Mv, xi, sg, f_real, f_cplx, x, r, 1);
   return hipGetLastError();
@@ -129,7 +151,8 @@ hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const in
 hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                                const int32_t *col, const double *Kv, const double *Mv,
                                const double *xi, Seg sg, const cpx<double> *x, cpx<double> *y) {
-  const int64_t tot = N * npole * S;
+  const int64_t tot = N * S * ((npole + RG - 1) / RG);
+  if (tot <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_residual, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
                      rowptr, col, Kv, Mv, xi, sg, nullptr, nullptr, x, y, 0);
   return hipGetLastError();
@@ -611,56 +634,66 @@ hipError_t launch_assemble_nodal(hipStream_t st, int64_t Nn, const int64_t *rowp
   return hipGetLastError();
 }
 
-// out[p][n][s] = (G^T r)_n = sum over the 6 incident edges, + for the edge
-// ending at n and - for the edge starting at n
-__global__ void k_grad_T(int64_t Nn, int npole, int S, int64_t N, const int32_t *node_edges,
-                         const cpx<double> *r, cpx<double> *out) {
+// Nodal vectors are packed: system j = p * S + s of the npole x S systems
+// sits in column j % S2 of "virtual pole" j / S2, out[vp][n][S2], so that
+// one pass over the (pole-independent) nodal factor serves S2 systems;
+// slots past npole * S are zero.
+// out = G^T r: sum over the 6 incident edges, + for the edge ending at n
+// and - for the edge starting at n
+__global__ void k_grad_T(int64_t Nn, int npole, int S, int S2, int64_t N,
+                         const int32_t *node_edges, const cpx<double> *r, cpx<double> *out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t mS = (int64_t)npole * S;
-  if (idx >= Nn * mS) return;
-  const int64_t n = idx / mS;
-  const int ps = (int)(idx % mS);
-  const int p = ps / S, c = ps % S;
-  const cpx<double> *R = r + (int64_t)p * N * S + c;
+  const int nsys = npole * S, nv = (nsys + S2 - 1) / S2;
+  if (idx >= Nn * nv * S2) return;
+  const int s2 = (int)(idx % S2);
+  const int64_t n = (idx / S2) % Nn;
+  const int vp = (int)(idx / ((int64_t)S2 * Nn));
+  const int j = vp * S2 + s2;
   double ar = 0.0, ai = 0.0;
-  for (int t = 0; t < 6; ++t) {
-    const cpx<double> v = R[(int64_t)node_edges[n * 6 + t] * S];
-    const double sg = (t & 1) ? -1.0 : 1.0;
-    ar += sg * v.re;
-    ai += sg * v.im;
+  if (j < nsys) {
+    const int p = j / S, c = j % S;
+    const cpx<double> *R = r + (int64_t)p * N * S + c;
+    for (int t = 0; t < 6; ++t) {
+      const cpx<double> v = R[(int64_t)node_edges[n * 6 + t] * S];
+      const double sg = (t & 1) ? -1.0 : 1.0;
+      ar += sg * v.re;
+      ai += sg * v.im;
+    }
   }
-  out[((int64_t)p * Nn + n) * S + c] = {ar, ai};
+  out[idx] = {ar, ai};
 }
 
-hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int64_t N,
+hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int S2, int64_t N,
                          const int32_t *node_edges, const cpx<double> *r, cpx<double> *out) {
-  const int64_t tot = Nn * npole * S;
+  const int nv = (npole * S + S2 - 1) / S2;
+  const int64_t tot = Nn * nv * S2;
   if (tot <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_grad_T, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, Nn, npole, S, N,
-                     node_edges, r, out);
+  hipLaunchKernelGGL(k_grad_T, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, Nn, npole, S,
+                     S2, N, node_edges, r, out);
   return hipGetLastError();
 }
 
-// z[p][q][s] += coef[p] * (y[p][end(q)][s] - y[p][start(q)][s])
-__global__ void k_grad_add(int64_t N, int npole, int S, int64_t Nn, const int32_t *edge_nodes,
-                           const cpx<double> *coef, Seg sg, const cpx<double> *y,
-                           cpx<double> *z) {
+// z[p][q][s] += coef * (y(end(q)) - y(start(q))) of system p * S + s (y
+// packed as in k_grad_T)
+__global__ void k_grad_add(int64_t N, int npole, int S, int S2, int64_t Nn,
+                           const int32_t *edge_nodes, const cpx<double> *coef, Seg sg,
+                           const cpx<double> *y, cpx<double> *z) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t mS = (int64_t)npole * S;
   if (idx >= N * mS) return;
   const int64_t q = idx / mS;
   const int ps = (int)(idx % mS);
   const int p = ps / S, c = ps % S;
-  const cpx<double> *Y = y + (int64_t)p * Nn * S + c;
+  const cpx<double> *Y = y + (int64_t)(ps / S2) * Nn * S2 + ps % S2;
   const int32_t a = edge_nodes[q * 2], b = edge_nodes[q * 2 + 1];
   double gr = 0.0, gi = 0.0;
   if (b >= 0) {
-    gr += Y[(int64_t)b * S].re;
-    gi += Y[(int64_t)b * S].im;
+    gr += Y[(int64_t)b * S2].re;
+    gi += Y[(int64_t)b * S2].im;
   }
   if (a >= 0) {
-    gr -= Y[(int64_t)a * S].re;
-    gi -= Y[(int64_t)a * S].im;
+    gr -= Y[(int64_t)a * S2].re;
+    gi -= Y[(int64_t)a * S2].im;
   }
   const cpx<double> k = coef[(int64_t)seg_find(sg, q) * sg.stride + p];
   cpx<double> *Z = z + ((int64_t)p * N + q) * S + c;
@@ -670,12 +703,13 @@ __global__ void k_grad_add(int64_t N, int npole, int S, int64_t Nn, const int32_
   *Z = v;
 }
 
-hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int64_t Nn,
+hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int S2, int64_t Nn,
                            const int32_t *edge_nodes, const cpx<double> *coef, Seg sg,
                            const cpx<double> *y, cpx<double> *z) {
   const int64_t tot = N * npole * S;
+  if (tot <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_grad_add, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     Nn, edge_nodes, coef, sg, y, z);
+                     S2, Nn, edge_nodes, coef, sg, y, z);
   return hipGetLastError();
 }
 

@@ -869,7 +869,8 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
   const int64_t N = N_of(c), Nn = c->nd.N;
   const int m = c->npole;
   TRY(ensure_vec(c, c->v_aux, sizeof(cpx<double>) * (size_t)m * S * N, "alloc aux residual"));
-  TRY(ensure_vec(c, c->d_nvec, sizeof(cpx<double>) * (size_t)m * S * std::max<int64_t>(Nn, 1),
+  TRY(ensure_vec(c, c->d_nvec,
+                 sizeof(cpx<double>) * (size_t)(m * S + 16) * std::max<int64_t>(Nn, 1),
                  "alloc nodal vector"));
   cpx<double> *w = c->v_aux.as<cpx<double>>();
   cpx<double> *y = c->d_nvec.as<cpx<double>>();
@@ -877,16 +878,18 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
   for (const PoleRun &pr : runs) {
     // the shift and coefficient tables are [mesh][pole]: offsetting them
     // by p0 keeps the (mesh, p0 + p) entry under index mesh * stride + p
-    const int64_t o = (int64_t)pr.p0 * N * S, on = (int64_t)pr.p0 * Nn * S;
+    const int64_t o = (int64_t)pr.p0 * N * S;
     HIPCHK(launch_residual(st, N, pr.n, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
                            c->d_K.as<double>(), c->d_M.as<double>(),
                            c->d_xi.as<double>() + 2 * pr.p0, rs, nullptr, r + o, z + o, w + o),
            "aux residual");
-    HIPCHK(launch_grad_T(st, Nn, pr.n, S, N, c->d_node_edges.as<int32_t>(), w + o, y + on),
-           "G^T");
-    TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, pr.n, y + on, S));
-    HIPCHK(launch_grad_add(st, N, pr.n, S, Nn, c->d_edge_nodes.as<int32_t>(),
-                           c->d_ncoef.as<cpx<double>>() + pr.p0, rs, y + on, z + o),
+    // the nodal factor is the same for every pole: its sweep takes the
+    // run's systems packed S2 = 16 to a pass
+    const int nsys = pr.n * S, S2 = std::min(16, nsys), nv = (nsys + S2 - 1) / S2;
+    HIPCHK(launch_grad_T(st, Nn, pr.n, S, S2, N, c->d_node_edges.as<int32_t>(), w + o, y), "G^T");
+    TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, nv, y, S2));
+    HIPCHK(launch_grad_add(st, N, pr.n, S, S2, Nn, c->d_edge_nodes.as<int32_t>(),
+                           c->d_ncoef.as<cpx<double>>() + pr.p0, rs, y, z + o),
            "z += G y");
   }
   return TEM_OK;

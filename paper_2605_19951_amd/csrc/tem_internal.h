@@ -265,12 +265,15 @@ hipError_t launch_assemble_nodal(hipStream_t st, int64_t Nn, const int64_t *rowp
                                  const int32_t *col, const int32_t *row_node,
                                  const int32_t *node_new, int nx, int ny, int nz, const double *Le,
                                  const double *sigma, double *Lv);
-// out = G^T r  (edge vectors [pole][N][S] -> nodal vectors [pole][Nn][S])
-hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int64_t N,
+// out = G^T r  (edge vectors [pole][N][S] -> packed nodal vectors: system
+// j = p * S + s in column j % S2 of virtual pole j / S2, [vp][Nn][S2],
+// zero past npole * S)
+hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int S2, int64_t N,
                          const int32_t *node_edges, const cpx<double> *r, cpx<double> *out);
 // z += coef[pole] * G y
-// coef indexed [segment of the edge row * row_seg.stride + pole]
-hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int64_t Nn,
+// z += coef * G y with y packed as for launch_grad_T; coef indexed
+// [segment of the edge row * row_seg.stride + pole]
+hipError_t launch_grad_add(hipStream_t st, int64_t N, int npole, int S, int S2, int64_t Nn,
                            const int32_t *edge_nodes, const cpx<double> *coef, Seg row_seg,
                            const cpx<double> *y, cpx<double> *z);
 
