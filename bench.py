@@ -32,6 +32,38 @@ METRIC = "all-pole factor+solve s & Jᵀv/s at 64³ edge mesh, FP32+IR vs FP64, 
 PEAK_FP32 = 157.3e12      # dense FP32 MFMA, MI355X
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "front_update_hex64_fp32_traffic.json")
+UPDATE_SOURCE = os.path.join(ROOT, "paper_2605_19951_amd", "csrc", "k_factor.hip")
+
+
+def source_hash(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the FP32 front update from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record, if it was taken on the current
+    kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    with open(TRAFFIC_RECORD) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256_16") != source_hash(UPDATE_SOURCE):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def copy_probe(torch, dev, n_bytes=1 << 30, reps=5):
+    """A plain device copy of n_bytes, reps times: the calibration run for the
+    FETCH_SIZE / WRITE_SIZE counters (read n_bytes, write n_bytes each)."""
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_probe_bytes=n_bytes, reps=reps)), flush=True)
 
 
 def run_precision(t, wl, prec, steps, warmup, torch, dev, F, v, w):
@@ -188,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the counter-calibration copy (1 GiB, 5 times)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the pole-sharded multi-GPU path is not part of this "
@@ -201,6 +235,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        copy_probe(torch, dev)
+        return
     wl = ti.workload(2)
     me = wl.mesh
     t = Tem(0)
@@ -228,8 +265,10 @@ def main():
         phases["ragged_batch_fp32_ir"] = ragged_phase(torch, dev, FP32_IR)
     ach = res32["update_flops"] / (res32["update_ms"] * 1e-3) if res32["update_ms"] > 0 else 0.0
     roof = dict(bound="mfma", kernel="k_front_update<float>", achieved=ach / 1e12,
-                peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=ach / PEAK_FP32, traffic=None,
-                launches=res32["update_launches"])
+                peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=ach / PEAK_FP32,
+                traffic=recorded_traffic(), launches=res32["update_launches"],
+                flops_per_launch=res32["update_flops"] / max(res32["update_launches"], 1),
+                ms_per_launch=res32["update_ms"] / max(res32["update_launches"], 1))
     sweep_bw = res32["sweep_bytes"] / (res32["sweep_ms"] * 1e-3) if res32["sweep_ms"] > 0 else 0.0
     line = dict(metric=METRIC, value=res32["factor_solve_s"], unit="s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=res32["step_s"] * 1e3,

@@ -328,7 +328,8 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
   int64_t ld;
   const cpx<T> *Lc = col_ptr(P, n, jb, ld);
   __shared__ cpx<T> Lt[NB][RT + 1];
-  __shared__ cpx<T> Xt[RT][16];
+  __shared__ cpx<T> Xs[RT * 16 + 1];   // x rows [RT][16] and one sink slot
+  cpx<T>(*Xt)[16] = reinterpret_cast<cpx<T>(*)[16]>(Xs);
   // register blocking: a thread owns LB columns x CBK right-hand sides of
   // the block's outputs over the rows i = grp, grp + ngrp, ... of each tile
   constexpr int LB = 4;
@@ -343,7 +344,14 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
   // register prefetch of the next 64-row tile: 8 panel elements and up to
   // 4 x-values per thread (loads from clamped in-bounds positions; masking
   // happens in LDS)
-  cpx<T> pre[8], prx[4];
+  // (the four x values are separate variables: as an array the FP64
+  // instance was kept in scratch memory)
+  cpx<T> pre[8], px0, px1, px2, px3;
+  auto xval = [&](int q, int64_t ac, int na) -> cpx<T> {
+    const int idx = tid + 256 * q;
+    const int i = min(idx / S, na - 1), c = idx % S;
+    return Xp[(int64_t)rows[ac + i] * S + c];
+  };
   auto fetch = [&](int64_t ac) {
     const int na = (int)min((int64_t)RT, u - ac);
 #pragma unroll
@@ -351,12 +359,10 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
       const int idx = tid + 256 * q, i = min(idx % RT, na - 1), l = min(idx / RT, w - 1);
       pre[q] = Lc[(int64_t)l * ld + k + ac + i];
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q;
-      const int i = min(idx / S, na - 1), c = idx % S;
-      prx[q] = Xp[(int64_t)rows[ac + i] * S + c];
-    }
+    px0 = xval(0, ac, na);
+    px1 = xval(1, ac, na);
+    px2 = xval(2, ac, na);
+    px3 = xval(3, ac, na);
   };
   if (u > 0) fetch(0);
   for (int64_t ac = 0; ac < u; ac += RT) {
@@ -368,11 +374,15 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
       const bool ok = idx % RT < na && idx / RT < w;
       Lt[idx / RT][idx % RT] = ok ? pre[q] : czero<T>();
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    // unconditional stores: slots past na rows go to the sink
+    auto xput = [&](int q, cpx<T> v) {
       const int idx = tid + 256 * q;
-      if (idx < na * S) Xt[idx / S][idx % S] = prx[q];
-    }
+      Xs[idx < na * S ? (idx / S) * 16 + idx % S : RT * 16] = v;
+    };
+    xput(0, px0);
+    xput(1, px1);
+    xput(2, px2);
+    xput(3, px3);
     __syncthreads();
     if (ac + RT < u) fetch(ac + RT);
     if (live) {

@@ -75,17 +75,31 @@ hipError_t launch_assemble_KM(hipStream_t st, int64_t N, const int64_t *rowptr, 
 // ------------------------------------------------------ shifted products
 // One thread per (row, rhs, group of RG poles): the row's K, M entries and
 // column indices are loaded once and applied to RG poles; x, y, r are
-// [pole][N][S], threads ordered rhs fastest, then row, then pole group.
+// [pole][N][S], threads ordered rhs fastest, then row, then pole group, so
+// that the K, M entries are read once per RG poles.  Workgroups are handed
+// to the eight XCDs round robin; block b works on block (b % 8) * chunk +
+// b / 8, so each XCD walks a contiguous eighth of the rows and the rows of
+// x that neighbouring rows share stay in its L2.
 constexpr int RG = 4;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
+  const int64_t chunk = (nblk + 7) / 8;
+  return (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
+}
+inline unsigned xcd_grid(int64_t tot, int block) {
+  const int64_t nblk = (tot + block - 1) / block;
+  return (unsigned)(8 * ((nblk + 7) / 8));
+}
 
 __global__ void k_residual(int64_t N, int npole, int S, const int64_t *rowptr,
                            const int32_t *col, const double *Kv, const double *Mv,
                            const double *xi, Seg sg, const double *f_real,
                            const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r,
                            int mode) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int ng = (npole + RG - 1) / RG;
-  if (idx >= N * S * ng) return;
+  const int64_t tot = N * S * ng;
+  const int64_t idx = xcd_block((tot + 255) / 256) * 256 + threadIdx.x;
+  if (idx >= tot) return;
   const int c = (int)(idx % S);
   const int64_t q = (idx / S) % N;
   const int g = (int)(idx / ((int64_t)S * N));
@@ -143,8 +157,8 @@ hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const in
                            const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r) {
   const int64_t tot = N * S * ((npole + RG - 1) / RG);
   if (tot <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     rowptr, col, Kv, Mv, xi, sg, f_real, f_cplx, x, r, 1);
+  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(tot, 256)), dim3(256), 0, st, N, npole, S, rowptr,
+                     col, Kv, Mv, xi, sg, f_real, f_cplx, x, r, 1);
   return hipGetLastError();
 }
 
@@ -153,8 +167,8 @@ hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, cons
                                const double *xi, Seg sg, const cpx<double> *x, cpx<double> *y) {
   const int64_t tot = N * S * ((npole + RG - 1) / RG);
   if (tot <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     rowptr, col, Kv, Mv, xi, sg, nullptr, nullptr, x, y, 0);
+  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(tot, 256)), dim3(256), 0, st, N, npole, S, rowptr,
+                     col, Kv, Mv, xi, sg, nullptr, nullptr, x, y, 0);
   return hipGetLastError();
 }
 
