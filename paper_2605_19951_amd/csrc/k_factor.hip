@@ -299,46 +299,50 @@ struct Mfma<double> {
   }
 };
 
-template <typename T, int TTS, bool M3>
+template <typename T, int NBR, int NBC, bool M3>
 struct WaveAcc {
   using F = Mfma<T>;
-  static constexpr int NBK = TTS / 2 / F::BS;   // a wave owns a TTS/2 x TTS/2 quarter
   static constexpr int NQ = M3 ? 3 : 2;
-  typename F::acc_t q[NQ][NBK][NBK];
+  typename F::acc_t q[NQ][NBR][NBC];
   __device__ void zero() {
 #pragma unroll
     for (int z = 0; z < NQ; ++z)
 #pragma unroll
-      for (int a = 0; a < NBK; ++a)
+      for (int a = 0; a < NBR; ++a)
 #pragma unroll
-        for (int b = 0; b < NBK; ++b)
+        for (int b = 0; b < NBC; ++b)
 #pragma unroll
           for (int i = 0; i < F::NV; ++i) q[z][a][b][i] = T(0);
   }
-  // Ar, Ai: rows of L (the wave's rows); Br, Bi: rows of L (its columns);
-  // Dr, Di: the pivots of the chunk's depth columns, applied here
-  __device__ void step(const T (*Ar)[TTS], const T (*Ai)[TTS], const T (*Br)[TTS],
-                       const T (*Bi)[TTS], const T *Dr, const T *Di, int wr, int wc,
+  // Ar, Ai: rows of L for the wave's NBR row blocks (from row ar0 of the LDS
+  // planes of width TA); Br, Bi: rows of L for its NBC column blocks (from
+  // row br0, width TB); Dr, Di: the pivots of the chunk, applied here
+  template <int TA, int TB>
+  __device__ void step(const T (*Ar)[TA], const T (*Ai)[TA], const T (*Br)[TB],
+                       const T (*Bi)[TB], const T *Dr, const T *Di, int ar0, int br0,
                        int lane) {
     int rr, kh;
     F::operand(lane, rr, kh);
 #pragma unroll
     for (int kk = 0; kk < KB; kk += F::DK) {
-      T ar[NBK], ai[NBK], br[NBK], bi[NBK];
+      T ar[NBR], ai[NBR], br[NBC], bi[NBC];
       const T dr = Dr[kk + kh], di = Di[kk + kh];
 #pragma unroll
-      for (int a = 0; a < NBK; ++a) {
-        ar[a] = Ar[kk + kh][wr * (TTS / 2) + a * F::BS + rr];
-        ai[a] = Ai[kk + kh][wr * (TTS / 2) + a * F::BS + rr];
-        const T lr = Br[kk + kh][wc * (TTS / 2) + a * F::BS + rr];
-        const T li = Bi[kk + kh][wc * (TTS / 2) + a * F::BS + rr];
-        br[a] = lr * dr - li * di;
-        bi[a] = lr * di + li * dr;
+      for (int a = 0; a < NBR; ++a) {
+        ar[a] = Ar[kk + kh][ar0 + a * F::BS + rr];
+        ai[a] = Ai[kk + kh][ar0 + a * F::BS + rr];
       }
 #pragma unroll
-      for (int a = 0; a < NBK; ++a)
+      for (int b = 0; b < NBC; ++b) {
+        const T lr = Br[kk + kh][br0 + b * F::BS + rr];
+        const T li = Bi[kk + kh][br0 + b * F::BS + rr];
+        br[b] = lr * dr - li * di;
+        bi[b] = lr * di + li * dr;
+      }
 #pragma unroll
-        for (int b = 0; b < NBK; ++b) {
+      for (int a = 0; a < NBR; ++a)
+#pragma unroll
+        for (int b = 0; b < NBC; ++b) {
           if constexpr (M3) {
             q[0][a][b] = F::mma(ar[a], br[b], q[0][a][b]);
             q[1][a][b] = F::mma(ai[a], bi[b], q[1][a][b]);
@@ -352,24 +356,24 @@ struct WaveAcc {
         }
     }
   }
-  static constexpr int nelem() { return NBK * NBK * F::NV; }
-  // element e of this lane -> (row, col) inside the wave's quarter
+  static constexpr int nelem() { return NBR * NBC * F::NV; }
+  // element e of this lane -> (row, col) inside the wave's sub-tile
   __device__ static void coord(int lane, int e, int &row, int &col) {
     const int blk = e / F::NV, i = e % F::NV;
     F::coord(lane, i, row, col);
-    row += (blk / NBK) * F::BS;
-    col += (blk % NBK) * F::BS;
+    row += (blk / NBC) * F::BS;
+    col += (blk % NBC) * F::BS;
   }
   // the update's increment -A B^T at element e
   __device__ T get_re(int e) const {
-    const int a = (e / F::NV) / NBK, b = (e / F::NV) % NBK, i = e % F::NV;
+    const int a = (e / F::NV) / NBC, b = (e / F::NV) % NBC, i = e % F::NV;
     if constexpr (M3)
       return q[1][a][b][i] - q[0][a][b][i];
     else
       return q[0][a][b][i];
   }
   __device__ T get_im(int e) const {
-    const int a = (e / F::NV) / NBK, b = (e / F::NV) % NBK, i = e % F::NV;
+    const int a = (e / F::NV) / NBC, b = (e / F::NV) % NBC, i = e % F::NV;
     if constexpr (M3)
       return (q[0][a][b][i] + q[1][a][b][i]) - q[2][a][b][i];
     else
@@ -377,40 +381,61 @@ struct WaveAcc {
   }
 };
 
-// Tile number id of a lower trapezoid of nct column tiles and nrt >= nct
-// row tiles (tile (ct, rt) exists for rt >= ct) in super-column order:
-// column tiles are grouped by SUPER_W; inside a group the tiles run by row
-// tile, then column tile.  id must be below the tile count.
+// Output tiles of TR rows x TC columns (TR = R TC, R = 1 or 2) over the lower
+// trapezoid of columns [cbeg, cend) and rows [cbeg, n), on a row grid
+// aligned to TR: tile (ct, rt) covers columns cbeg + TC ct .. and rows
+// cbeg + TR rt .., and exists for floor(ct / R) <= rt < nrt, nrt =
+// ceil((n - cbeg) / TR).  Numbering in super-column order: column tiles are
+// grouped by SUPER_W; inside a group the tiles run by row tile, then column
+// tile, so that the tiles in flight share row and column panels.  Returns
+// false past the last tile.
 constexpr int SUPER_W = 8;
-__device__ inline void trap_tile(int64_t id, int64_t nct, int64_t nrt, int64_t &ct, int64_t &rt) {
-  for (int64_t c0 = 0;; c0 += SUPER_W) {
+template <int R>
+__device__ inline bool trap_tile(int64_t id, int64_t nct, int64_t nrt, int64_t &ct,
+                                 int64_t &rt) {
+  for (int64_t c0 = 0; c0 < nct; c0 += SUPER_W) {
     const int64_t w = min((int64_t)SUPER_W, nct - c0);
-    const int64_t tri = w * (w + 1) / 2;
-    const int64_t here = tri + w * (nrt - c0 - w);
-    if (id < here) {
-      if (id < tri) {
-        int64_t r = 0;
-        while ((r + 1) * (r + 2) / 2 <= id) ++r;
-        rt = c0 + r;
-        ct = c0 + id - r * (r + 1) / 2;
-      } else {
-        const int64_t q = id - tri;
-        rt = c0 + w + q / w;
-        ct = c0 + q % w;
-      }
-      return;
+    int64_t here = 0;
+    for (int64_t c = c0; c < c0 + w; ++c) here += nrt - c / R;
+    if (id >= here) {
+      id -= here;
+      continue;
     }
-    id -= here;
+    // rows where only a prefix of the group's columns has reached the diagonal
+    int64_t r = c0 / R;
+    for (; r < nrt; ++r) {
+      const int64_t act = min(w, R * (r + 1) - c0);
+      if (act >= w) break;
+      if (id < act) {
+        ct = c0 + id;
+        rt = r;
+        return true;
+      }
+      id -= act;
+    }
+    ct = c0 + id % w;
+    rt = r + id / w;
+    return true;
   }
+  return false;
+}
+template <int R>
+__device__ inline int64_t trap_count(int64_t nct, int64_t nrt) {
+  int64_t c = 0;
+  for (int64_t t = 0; t < nct; ++t) c += nrt - t / R;
+  return c;
 }
 
 // mode 0: depth (eliminated columns) [j0, j0 + dw), updated columns
 // [j0 + dw, min(k, ccap)); mode 1: depth [0, k), contribution block.
-template <typename T, int TTS, bool M3>
+// TR x TC output tile per workgroup, 4 waves of (TR/2) x (TC/2).
+template <typename T, int TR, int TC, bool M3>
 __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t *lvl_nodes,
                                                       int mode, int j0, int dw, int ccap,
                                                       cpx<T> *factor, int64_t f_stride,
                                                       cpx<T> *cb, int64_t cb_stride) {
+  constexpr int R = TR / TC;
+  using Acc = WaveAcc<T, TR / 2 / Mfma<T>::BS, TC / 2 / Mfma<T>::BS, M3>;
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
   if (pole_absent(ft, s, p)) return;
@@ -434,45 +459,48 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
   // each XCD takes one contiguous eighth of the tile sequence, walked in
   // super-column order so that the tiles in flight on an XCD share row and
   // column panels in its L2.
-  const int64_t nct = (cend - cbeg + TTS - 1) / TTS, nrt = (n - cbeg + TTS - 1) / TTS;
-  const int64_t cnt = nct * nrt - nct * (nct - 1) / 2;
+  const int64_t nct = (cend - cbeg + TC - 1) / TC, nrt = (n - cbeg + TR - 1) / TR;
+  const int64_t cnt = trap_count<R>(nct, nrt);
   const int64_t chunk = (cnt + 7) / 8;
   const int64_t loc = blockIdx.x >> 3;
   if (loc >= chunk) return;
   const int64_t id = (int64_t)(blockIdx.x & 7) * chunk + loc;
   if (id >= cnt) return;
   int64_t ct, rt;
-  trap_tile(id, nct, nrt, ct, rt);
-  const int64_t col0 = cbeg + TTS * ct;
-  const int64_t row0 = cbeg + TTS * rt;
+  if (!trap_tile<R>(id, nct, nrt, ct, rt)) return;
+  const int64_t col0 = cbeg + TC * ct;
+  const int64_t row0 = cbeg + TR * rt;
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
 
-  __shared__ T Ar[2][KB][TTS], Ai[2][KB][TTS], Br[2][KB][TTS], Bi[2][KB][TTS];
+  __shared__ T Ar[2][KB][TR], Ai[2][KB][TR], Br[2][KB][TC], Bi[2][KB][TC];
   __shared__ T Dr[2][KB], Di[2][KB];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
-  constexpr int PER = TTS * KB / 256;   // elements of A (and of B) per thread and chunk
-  const int lr = tid % TTS;             // tile row this thread loads
-  const int lk = (tid / TTS) * PER;     // first depth column it loads
+  constexpr int PA = TR * KB / 256, PB = TC * KB / 256;   // elements per thread and chunk
+  const int lra = tid % TR, lka = (tid / TR) * PA;       // A row / first depth it loads
+  const int lrb = tid % TC, lkb = (tid / TC) * PB;       // B row / first depth it loads
   // Prefetch of the next depth chunk: unconditional loads from clamped
   // (in-bounds) addresses, so nothing waits on them until the chunk is
   // written to LDS, where the masking happens.  Clamped rows stay in the
   // panel block: every row index is >= cbeg >= l1.  Threads tid < KB also
   // fetch the pivot D of depth column l + tid.
-  cpx<T> pa[PER], pb[PER], pd;
+  cpx<T> pa[PA], pb[PB], pd;
   int64_t pl = l0;
-  const int64_t ra = row0 + lr, rb = col0 + lr;
+  const int64_t ra = row0 + lra, rb = col0 + lrb;
   const int64_t rac = min(ra, n - 1), rbc = min(rb, n - 1);
   auto fetch = [&](int64_t l) {
     const int64_t b = l / NB, r0 = NB * b, ldb = n - r0;
     const cpx<T> *base = P + panel_block_off(n, b) - r0;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int64_t lc = min(l + lk + q, l1 - 1);
-      const cpx<T> *colp = base + (lc - r0) * ldb;
-      pa[q] = colp[rac];
-      pb[q] = colp[rbc];
+    for (int q = 0; q < PA; ++q) {
+      const int64_t lc = min(l + lka + q, l1 - 1);
+      pa[q] = base[(lc - r0) * ldb + rac];
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int64_t lc = min(l + lkb + q, l1 - 1);
+      pb[q] = base[(lc - r0) * ldb + rbc];
     }
     const int64_t ld = min(l + (tid % KB), l1 - 1);
     pd = base[(ld - r0) * ldb + ld];
@@ -481,14 +509,16 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
   // registers -> LDS buffer bf, masked (columns past l1 get D = 0)
   auto stage = [&](int bf) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const bool okc = pl + lk + q < l1;
-      const cpx<T> a = (okc && ra < n) ? pa[q] : czero<T>();
-      const cpx<T> bb = (okc && rb < n) ? pb[q] : czero<T>();
-      Ar[bf][lk + q][lr] = a.re;
-      Ai[bf][lk + q][lr] = a.im;
-      Br[bf][lk + q][lr] = bb.re;
-      Bi[bf][lk + q][lr] = bb.im;
+    for (int q = 0; q < PA; ++q) {
+      const cpx<T> a = (pl + lka + q < l1 && ra < n) ? pa[q] : czero<T>();
+      Ar[bf][lka + q][lra] = a.re;
+      Ai[bf][lka + q][lra] = a.im;
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const cpx<T> bb = (pl + lkb + q < l1 && rb < n) ? pb[q] : czero<T>();
+      Br[bf][lkb + q][lrb] = bb.re;
+      Bi[bf][lkb + q][lrb] = bb.im;
     }
     if (tid < KB) {
       const bool okd = pl + tid < l1;
@@ -498,7 +528,7 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
   };
   // two LDS buffers: chunk i+1 is loaded while chunk i is multiplied, one
   // barrier per chunk
-  WaveAcc<T, TTS, M3> acc;
+  Acc acc;
   acc.zero();
   if (l1 > l0) {
     fetch(l0);
@@ -508,7 +538,8 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
     for (int64_t l = l0; l < l1; l += KB) {
       const bool more = l + KB < l1;
       if (more) fetch(l + KB);
-      acc.step(Ar[bf], Ai[bf], Br[bf], Bi[bf], Dr[bf], Di[bf], wr, wc, lane);
+      acc.template step<TR, TC>(Ar[bf], Ai[bf], Br[bf], Bi[bf], Dr[bf], Di[bf], wr * (TR / 2),
+                                wc * (TC / 2), lane);
       if (more) stage(bf ^ 1);
       __syncthreads();
       bf ^= 1;
@@ -521,13 +552,13 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
   // (row0, col0), which always exists), then the valid ones are stored.
   cpx<T> *Cb = (mode == 1) ? cb + (int64_t)p * cb_stride + ft.cb_off[s] : nullptr;
   cpx<T> *Pw = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  constexpr int NE = WaveAcc<T, TTS, M3>::nelem(), GE = 4;
+  constexpr int NE = Acc::nelem(), GE = 4;
   if (mode == 1) {
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       int rr, cc;
-      WaveAcc<T, TTS, M3>::coord(lane, e, rr, cc);
-      const int64_t row = row0 + wr * (TTS / 2) + rr, col = col0 + wc * (TTS / 2) + cc;
+      Acc::coord(lane, e, rr, cc);
+      const int64_t row = row0 + wr * (TR / 2) + rr, col = col0 + wc * (TC / 2) + cc;
       if (row >= n || col >= cend || row < col) continue;
       Cb[(col - k) * u + (row - k)] = {acc.get_re(e), acc.get_im(e)};
     }
@@ -541,8 +572,8 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
 #pragma unroll
     for (int j = 0; j < GE; ++j) {
       int rr, cc;
-      WaveAcc<T, TTS, M3>::coord(lane, e0 + j, rr, cc);
-      const int64_t row = row0 + wr * (TTS / 2) + rr, col = col0 + wc * (TTS / 2) + cc;
+      Acc::coord(lane, e0 + j, rr, cc);
+      const int64_t row = row0 + wr * (TR / 2) + rr, col = col0 + wc * (TC / 2) + cc;
       ok[j] = !(row >= n || col >= cend || row < col);
       const int64_t r = ok[j] ? row : row0, c = ok[j] ? col : col0;
       qp[j] = Pw + panel_elem(n, r, c);
@@ -566,20 +597,27 @@ hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_n
                                int tile, bool m3) {
   if (n_nodes <= 0 || max_tiles <= 0) return hipSuccess;
   dim3 grid((unsigned)(8 * ((max_tiles + 7) / 8)), n_nodes, npole);
-#define TEM_UPD(TT, M)                                                                            \
-  hipLaunchKernelGGL((k_front_update<T, TT, M>), grid, dim3(256), 0, st, ft, lvl_nodes, mode, j0, \
-                     dw, ccap, factor, f_stride, cb, cb_stride)
+#define TEM_UPD(TR, TC, M)                                                                        \
+  hipLaunchKernelGGL((k_front_update<T, TR, TC, M>), grid, dim3(256), 0, st, ft, lvl_nodes, mode, \
+                     j0, dw, ccap, factor, f_stride, cb, cb_stride)
   if constexpr (sizeof(T) == 4) {
-    if (tile == 128) {   // 4M only: the 3M accumulators do not fit beside it
-      TEM_UPD(128, false);
+    if (tile == UPD_T128) {   // 4M only: the 3M accumulators do not fit beside it
+      TEM_UPD(128, 128, false);
+      return hipGetLastError();
+    }
+    if (tile == UPD_T128x64) {
+      if (m3)
+        TEM_UPD(128, 64, true);
+      else
+        TEM_UPD(128, 64, false);
       return hipGetLastError();
     }
   }
-  if (tile != 64) return hipErrorInvalidValue;   // FP64 runs 64-tiles only
+  if (tile != UPD_T64) return hipErrorInvalidValue;   // FP64 runs 64 x 64 tiles only
   if (m3)
-    TEM_UPD(64, true);
+    TEM_UPD(64, 64, true);
   else
-    TEM_UPD(64, false);
+    TEM_UPD(64, 64, false);
 #undef TEM_UPD
   return hipGetLastError();
 }

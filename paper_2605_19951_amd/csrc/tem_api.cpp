@@ -90,12 +90,14 @@ struct LevelInfo {
 };
 
 struct Tiles {
-  // tiles of edge tt covering the lower trapezoid with columns [cbeg, cend)
-  // of an n-row front
-  static int64_t count(int64_t n, int64_t cbeg, int64_t cend, int64_t tt) {
+  // update tiles of shape `tile` covering the lower trapezoid with columns
+  // [cbeg, cend) of an n-row front (the enumeration of k_front_update)
+  static int64_t count(int64_t n, int64_t cbeg, int64_t cend, int tile) {
     if (cbeg >= cend) return 0;
-    int64_t nct = (cend - cbeg + tt - 1) / tt, tot = 0;
-    for (int64_t ct = 0; ct < nct; ++ct) tot += (n - (cbeg + tt * ct) + tt - 1) / tt;
+    const int64_t tc = upd_tile_cols(tile), tr = upd_tile_rows(tile), r = tr / tc;
+    const int64_t nct = (cend - cbeg + tc - 1) / tc, nrt = (n - cbeg + tr - 1) / tr;
+    int64_t tot = 0;
+    for (int64_t ct = 0; ct < nct; ++ct) tot += nrt - ct / r;
     return tot;
   }
 };
@@ -151,7 +153,7 @@ struct tem_ctx {
   bool aux = true;                 // gradient-space correction in FP32 refinement
   int64_t sweep_bb = 256;          // big column block of the wide-front sweeps
   int64_t sweep_big_limit = 1024;  // fronts x poles below which a level is "wide"
-  bool upd_tile128 = false;        // 128 x 128 MFMA update tiles (FP32)
+  int upd_tile = UPD_T64;          // FP32 update tile shape (FP64: 64 x 64)
   bool upd_m3_f32 = true;          // 3M complex products in the FP32 update
   bool upd_m3_f64 = false;         // 3M complex products in the FP64 update
   // Batch of meshes (B > 0): the per-mesh contexts in `sub` assemble and
@@ -575,6 +577,12 @@ template <typename T>
 bool upd_m3(const tem_ctx *c) {
   return sizeof(T) == 4 ? c->upd_m3_f32 : c->upd_m3_f64;
 }
+// tile shape for an update whose tallest front has `rows` rows below cbeg
+template <typename T>
+int upd_tile(const tem_ctx *c, int64_t rows) {
+  if (sizeof(T) != 4 || rows < 256) return UPD_T64;
+  return c->upd_tile;
+}
 
 FrontTab front_tab(const MF &mf, int p0 = 0) {
   FrontTab ft;
@@ -638,7 +646,7 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
     auto trailing = [&](int j0, int dw, int ccap) -> tem_status {
       int64_t max_tiles = 0;
       double fl = 0;
-      const int tt = (sizeof(T) == 4 && c->upd_tile128 && li.max_n - j0 - dw >= 256) ? 128 : 64;
+      const int tt = upd_tile<T>(c, li.max_n - j0 - dw);
       for (int s : li.nodes) {
         const SymNode &nd = sym.nodes[s];
         const int64_t k = nd.last - nd.first, n = k + nd.nrows;
@@ -682,7 +690,7 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
     }
     int64_t cb_tiles = 0;
     double fl = 0;
-    const int ttc = (sizeof(T) == 4 && c->upd_tile128 && li.max_u >= 256) ? 128 : 64;
+    const int ttc = upd_tile<T>(c, li.max_u);
     for (int s : li.nodes) {
       const SymNode &nd = sym.nodes[s];
       const int64_t k = nd.last - nd.first, n = k + nd.nrows;
@@ -1570,7 +1578,10 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
     long b = std::strtol(v, nullptr, 10);
     if (b >= 0) c->sweep_big_limit = b;
   }
-  if (const char *v = std::getenv("TEM_UPDATE_TILE")) c->upd_tile128 = std::strtol(v, nullptr, 10) == 128;
+  if (const char *v = std::getenv("TEM_UPDATE_TILE")) {   // "64", "128x64" or "128"
+    const std::string m(v);
+    c->upd_tile = m == "64" ? UPD_T64 : m == "128" ? UPD_T128 : UPD_T128x64;
+  }
   if (const char *v = std::getenv("TEM_UPDATE_3M")) {   // "f32", "f64", "both" or "none"
     const std::string m(v);
     c->upd_m3_f32 = m == "f32" || m == "both";

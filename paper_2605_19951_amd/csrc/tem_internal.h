@@ -106,11 +106,18 @@ template <typename T>
 hipError_t launch_panel_trsm(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                              int j0, int max_rows, int npole, cpx<T> *factor, int64_t f_stride);
 
+// Output tile shapes of the front update (rows x columns): 64 x 64; 128 x 64
+// and 128 x 128 (FP32 only; 128 x 128 with four real products only).
+enum { UPD_T64 = 0, UPD_T128x64 = 1, UPD_T128 = 2 };
+inline int upd_tile_rows(int tile) { return tile == UPD_T64 ? 64 : 128; }
+inline int upd_tile_cols(int tile) { return tile == UPD_T128 ? 128 : 64; }
+
 // mode 0: trailing update of panel columns [j0+dw, min(k, ccap)) by the
 // eliminated columns [j0, j0+dw); mode 1: contribution block
-// C -= L21 D L21^T.  tile = 64 or 128 (output tile edge, 128 for FP32
-// only; max_tiles counted with the same edge); m3: complex products with
-// three real matrix-core products instead of four.
+// C = -L21 D L21^T.  tile: one of UPD_T*; max_tiles counted with the same
+// shape (column tile t has ceil((n - cbeg) / rows) - floor(t / (rows /
+// cols)) row tiles); m3: complex products with three real matrix-core
+// products instead of four.
 template <typename T>
 hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                                int mode, int j0, int dw, int ccap, int64_t max_tiles, int npole,
