@@ -320,6 +320,34 @@ tem_status tem_forward_batch(tem_ctx *ctx, const int32_t *S, const double *F, co
                              int32_t K, const double *alpha, const tem_ir_opts *ir, double *d,
                              tem_ir_stats *stats);
 
+/* ------------------------------------------------------------ autotuning */
+
+typedef struct {
+  int32_t n_candidates;       /* update variants timed */
+  int32_t n_levels;           /* tree levels of the edge system */
+  double candidate_ms[8];     /* device time of the factorisation levels per variant */
+  int32_t candidate_tile[8];  /* variant's output tile: 0 = 64x64, 1 = 128x64, 2 = 128x128 */
+  int32_t candidate_m3[8];    /* 1: complex products with three real products, 0: four */
+  double tuned_ms;            /* sum over levels of the fastest variant's time */
+} tem_autotune_report;
+
+/* Times the front-update kernel variants (FP32: 64x64 and 128x64 output
+ * tiles, each with three or four real matrix-core products per complex
+ * product; FP64: 64x64 with three or four) level by level on complete
+ * factorisations of the given poles, and keeps for each level of the tree
+ * the variant that was fastest there.  Later tem_factor_poles calls of that
+ * precision use the choice until the next tem_analyse with other options
+ * or another mesh.  Leaves the context factored (last variant timed).
+ *   m, xi, prec  as tem_factor_poles;  rep  host, may be NULL.
+ * Not available on a batch of meshes. */
+tem_status tem_autotune(tem_ctx *ctx, int32_t m, const double *xi, tem_precision prec,
+                        tem_autotune_report *rep);
+
+/* The tuned variant of one level (0 = root): tile as candidate_tile, m3 as
+ * candidate_m3.  TEM_ESTATE if no tuning is held for that precision. */
+tem_status tem_autotune_level(const tem_ctx *ctx, tem_precision prec, int32_t level,
+                              int32_t *tile, int32_t *m3);
+
 /* ------------------------------------------------------------ statistics */
 
 typedef struct {

@@ -421,9 +421,10 @@ __device__ inline bool trap_tile(int64_t id, int64_t nct, int64_t nrt, int64_t &
 }
 template <int R>
 __device__ inline int64_t trap_count(int64_t nct, int64_t nrt) {
-  int64_t c = 0;
-  for (int64_t t = 0; t < nct; ++t) c += nrt - t / R;
-  return c;
+  // nct * nrt - sum_{t < nct} floor(t / R), R = 1 or 2
+  if (R == 1) return nct * nrt - nct * (nct - 1) / 2;
+  const int64_t m = nct / 2;
+  return nct * nrt - ((nct & 1) ? m * m : m * (m - 1));
 }
 
 // mode 0: depth (eliminated columns) [j0, j0 + dw), updated columns

@@ -156,6 +156,29 @@ struct tem_ctx {
   int upd_tile = UPD_T64;          // FP32 update tile shape (FP64: 64 x 64)
   bool upd_m3_f32 = true;          // 3M complex products in the FP32 update
   bool upd_m3_f64 = false;         // 3M complex products in the FP64 update
+  // Autotuned update variant per tree level of the edge system, by
+  // precision (empty: the defaults above); see tem_autotune.
+  struct UpdCfg {
+    int tile;
+    bool m3;
+  };
+  std::vector<UpdCfg> tuned[2];    // [0] FP64, [1] FP32
+  bool forcing = false;            // tem_autotune: every level uses `forced`
+  UpdCfg forced{UPD_T64, false};
+  // tem_autotune: start/end events per (pole group, level) of the edge
+  // factorisation, [(group * levels + L) * 2 + {0, 1}]
+  bool lvl_timing = false;
+  int lvl_group = 0;
+  std::vector<hipEvent_t> lvl_ev;
+  // HIP graph of the all-pole edge sweep, replayed by every refinement step;
+  // valid while the factors, the vector and its shape are those captured
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  struct SweepGraph {
+    hipGraphExec_t exec = nullptr;
+    const void *x = nullptr, *factor = nullptr, *ws[3] = {nullptr, nullptr, nullptr};
+    int S = 0, npole = 0;
+  } sgraph[2];                     // [0] FP64 factors, [1] FP32 factors
   // Batch of meshes (B > 0): the per-mesh contexts in `sub` assemble and
   // analyse each mesh; this context holds the merged block-diagonal edge and
   // nodal systems (mesh b owns edge rows [row_off[b], row_off[b+1]), matrix
@@ -303,10 +326,17 @@ tem_status upload_pattern_and_assemble(tem_ctx *c) {
 
 // Invalidates the factors and pole solutions; their memory stays allocated
 // for a refactorisation of the same size (free_factors releases it).
+void drop_graphs(tem_ctx *c) {
+  for (auto &g : c->sgraph) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    g = tem_ctx::SweepGraph();
+  }
+}
 void drop_factors(tem_ctx *c) {
   c->nodal_ready = false;
   c->factored = false;
   c->solved = false;
+  drop_graphs(c);
 }
 void free_factors(tem_ctx *c) {
   drop_factors(c);
@@ -577,11 +607,24 @@ template <typename T>
 bool upd_m3(const tem_ctx *c) {
   return sizeof(T) == 4 ? c->upd_m3_f32 : c->upd_m3_f64;
 }
-// tile shape for an update whose tallest front has `rows` rows below cbeg
+// Update variant of level L of system mf: autotuned per level for the edge
+// system when available, else the context defaults (FP32 tiles other than
+// 64 x 64 only where the tallest front has >= 256 rows below cbeg).
 template <typename T>
-int upd_tile(const tem_ctx *c, int64_t rows) {
-  if (sizeof(T) != 4 || rows < 256) return UPD_T64;
-  return c->upd_tile;
+tem_ctx::UpdCfg upd_cfg(const tem_ctx *c, const MF &mf, int L, int64_t rows) {
+  tem_ctx::UpdCfg cf{UPD_T64, upd_m3<T>(c)};
+  const bool edge = &mf == &c->ed;
+  const std::vector<tem_ctx::UpdCfg> &tab = c->tuned[sizeof(T) == 4 ? 1 : 0];
+  if (edge && c->forcing)
+    cf = c->forced;
+  else if (edge && (int)tab.size() > L)
+    cf = tab[L];
+  else if (sizeof(T) == 4 && rows >= 256)
+    cf.tile = c->upd_tile;
+  if (sizeof(T) != 4) cf.tile = UPD_T64;   // FP64 runs 64 x 64 tiles only
+  if (cf.tile == UPD_T128) cf.m3 = false;   // 4M only
+  if (cf.tile != UPD_T64 && rows < 128) cf.tile = UPD_T64;
+  return cf;
 }
 
 FrontTab front_tab(const MF &mf, int p0 = 0) {
@@ -621,11 +664,14 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
   cpx<T> *arena[2] = {arena0, arena1};
   const int nl = (int)mf.levels.size();
   const Symbolic &sym = mf.sym;
+  const bool lvl_timing = &mf == &c->ed && c->lvl_timing;
+  const size_t ev0 = (size_t)c->lvl_group * nl * 2;
   for (int L = nl - 1; L >= 0; --L) {
     const LevelInfo &li = mf.levels[L];
     const int32_t *ln = lvl_ptr(mf, li);
     cpx<T> *cbL = arena[L & 1];
     cpx<T> *cbC = arena[(L + 1) & 1];
+    if (lvl_timing) HIPCHK(hipEventRecord(c->lvl_ev[ev0 + 2 * L], st), "level event");
     HIPCHK(launch_fill_zero<T>(st, F + li.panel_begin, li.panel_end - li.panel_begin, g,
                                mf.pole_stride),
            "zero panels");
@@ -646,7 +692,8 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
     auto trailing = [&](int j0, int dw, int ccap) -> tem_status {
       int64_t max_tiles = 0;
       double fl = 0;
-      const int tt = upd_tile<T>(c, li.max_n - j0 - dw);
+      const tem_ctx::UpdCfg cf = upd_cfg<T>(c, mf, L, li.max_n - j0 - dw);
+      const int tt = cf.tile;
       for (int s : li.nodes) {
         const SymNode &nd = sym.nodes[s];
         const int64_t k = nd.last - nd.first, n = k + nd.nrows;
@@ -664,7 +711,7 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
       if (max_tiles == 0) return TEM_OK;
       hipEvent_t ea = span_begin(c);
       HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 0, j0, dw, ccap, max_tiles, g, F,
-                                    mf.pole_stride, cbL, mf.cb_stride, tt, upd_m3<T>(c)),
+                                    mf.pole_stride, cbL, mf.cb_stride, tt, cf.m3),
              "trailing update");
       span_end(c, ea, fl, 0);
       return TEM_OK;
@@ -690,7 +737,8 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
     }
     int64_t cb_tiles = 0;
     double fl = 0;
-    const int ttc = upd_tile<T>(c, li.max_u);
+    const tem_ctx::UpdCfg cfc = upd_cfg<T>(c, mf, L, li.max_u);
+    const int ttc = cfc.tile;
     for (int s : li.nodes) {
       const SymNode &nd = sym.nodes[s];
       const int64_t k = nd.last - nd.first, n = k + nd.nrows;
@@ -700,13 +748,14 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
     }
     hipEvent_t ea = span_begin(c);
     HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, 0, 0, cb_tiles, g, F, mf.pole_stride,
-                                  cbL, mf.cb_stride, ttc, upd_m3<T>(c)),
+                                  cbL, mf.cb_stride, ttc, cfc.m3),
            "contribution update");
     span_end(c, ea, fl, 0);
     for (int sl = 0; sl < 2; ++sl)
       HIPCHK(launch_extend_add<T>(st, ft, xl + li.xm[sl], li.xe[sl] - li.xm[sl], sl, g, F,
                                   mf.pole_stride, cbL, cbC, mf.cb_stride),
              "extend-add into contribution blocks");
+    if (lvl_timing) HIPCHK(hipEventRecord(c->lvl_ev[ev0 + 2 * L + 1], st), "level event");
   }
   return TEM_OK;
 }
@@ -813,9 +862,61 @@ std::vector<PoleRun> active_runs(const tem_ctx *c, const std::vector<int> &activ
 
 // edge sweep with the cached pole factors for the poles of `runs`; x is
 // the full [pole][N][S] vector (timed when profiling)
+// Capture the all-pole sweep of x into a graph on a private stream (the
+// caller's stream may be the legacy default stream, which cannot capture).
+template <typename T>
+tem_status capture_sweep(tem_ctx *c, cpx<T> *x, int S, tem_ctx::SweepGraph &g) {
+  TRY(ensure_sweep_ws<T>(c, c->ed, c->npole, S));   // no allocation while capturing
+  if (!c->cap_stream)
+    HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
+  hipStream_t saved = c->stream;
+  c->stream = c->cap_stream;
+  HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  tem_status s0 = sweep_levels<T>(c, c->ed, c->d_factor.as<cpx<T>>(), c->ed.pole_stride,
+                                  c->npole, x, S, 0);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  c->stream = saved;
+  if (s0 != TEM_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return s0;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "end capture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(c, e, "instantiate sweep graph");
+  if (g.exec) hipGraphExecDestroy(g.exec);
+  g.exec = exec;
+  g.x = x;
+  g.factor = c->d_factor.p;
+  g.ws[0] = c->ed.w_t.p;
+  g.ws[1] = c->ed.w_w0.p;
+  g.ws[2] = c->ed.w_w1.p;
+  g.S = S;
+  g.npole = c->npole;
+  return TEM_OK;
+}
+
 template <typename T>
 tem_status sweep(tem_ctx *c, cpx<T> *x, int S, const std::vector<PoleRun> &runs) {
   const int64_t N = N_of(c);
+  if (c->use_graphs && runs.size() == 1 && runs[0].p0 == 0 && runs[0].n == c->npole) {
+    tem_ctx::SweepGraph &g = c->sgraph[sizeof(T) == 4 ? 1 : 0];
+    // the graph holds the vector, factor and work-space addresses it was
+    // captured with; any change (or a grown work space) means a new capture
+    TRY(ensure_sweep_ws<T>(c, c->ed, c->npole, S));
+    if (!(g.exec && g.x == x && g.factor == c->d_factor.p && g.S == S &&
+          g.npole == c->npole && g.ws[0] == c->ed.w_t.p && g.ws[1] == c->ed.w_w0.p &&
+          g.ws[2] == c->ed.w_w1.p))
+      TRY(capture_sweep<T>(c, x, S, g));
+    hipEvent_t ea = span_begin(c);
+    HIPCHK(hipGraphLaunch(g.exec, c->stream), "sweep graph");
+    const double bytes = 2.0 * (double)sizeof(cpx<T>) * (double)c->fac_elems +
+                         4.0 * (double)sizeof(cpx<T>) * (double)c->npole * N * S;
+    span_end(c, ea, bytes, 1);
+    return TEM_OK;
+  }
   for (const PoleRun &pr : runs) {
     hipEvent_t ea = span_begin(c);
     TRY(sweep_levels<T>(c, c->ed, c->d_factor.as<cpx<T>>() + (int64_t)pr.p0 * c->ed.pole_stride,
@@ -1340,9 +1441,18 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0), "event");
   HIPCHK(hipEventCreate(&e1), "event");
+  if (c->lvl_timing) {
+    const size_t need = (size_t)2 * ngroups * c->ed.levels.size();
+    while (c->lvl_ev.size() < need) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e), "event");
+      c->lvl_ev.push_back(e);
+    }
+  }
   HIPCHK(hipEventRecord(e0, c->stream), "event");
   for (int p0 = 0; p0 < m; p0 += g) {
     int gg = std::min(g, m - p0);
+    c->lvl_group = p0 / g;
     tem_status s =
         prec == TEM_FP64
             ? factor_group<double>(c, c->ed,
@@ -1578,6 +1688,7 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
     long b = std::strtol(v, nullptr, 10);
     if (b >= 0) c->sweep_big_limit = b;
   }
+  if (const char *v = std::getenv("TEM_GRAPHS")) c->use_graphs = std::strtol(v, nullptr, 10) != 0;
   if (const char *v = std::getenv("TEM_UPDATE_TILE")) {   // "64", "128x64" or "128"
     const std::string m(v);
     c->upd_tile = m == "64" ? UPD_T64 : m == "128" ? UPD_T128 : UPD_T128x64;
@@ -1604,6 +1715,9 @@ void tem_destroy(tem_ctx *c) {
   hipStream_t st = c->stream;
   bool own = c->own_stream;
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : c->lvl_ev) hipEventDestroy(e);
+  drop_graphs(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   delete c;
   if (own) hipStreamDestroy(st);
 }
@@ -1743,6 +1857,10 @@ tem_status tem_analyse(tem_ctx *c, const tem_analyse_opts *opts, tem_symbolic_in
     c->leaf = leaf;
     TRY(batch_analyse(c));
     c->analysed = true;
+  }
+  if (!c->analysed || leaf != c->leaf) {
+    c->tuned[0].clear();
+    c->tuned[1].clear();
   }
   if (c->B == 0 && (!c->analysed || leaf != c->leaf)) {
     free_factors(c);
@@ -2343,6 +2461,76 @@ tem_status tem_forward_batch(tem_ctx *c, const int32_t *S, const double *F, cons
                   res.unconverged, worst, res.solves);
     return fail(c, TEM_ENOCONV, buf);
   }
+  return TEM_OK;
+}
+
+// ------------------------------------------------------------ autotuning
+tem_status tem_autotune(tem_ctx *c, int32_t m, const double *xi, tem_precision prec,
+                        tem_autotune_report *rep) {
+  if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_autotune: not available on a batch of meshes");
+  if (!c->analysed) return fail(c, TEM_ESTATE, "tem_autotune: call tem_analyse first");
+  if (prec != TEM_FP64 && prec != TEM_FP32_IR)
+    return fail(c, TEM_EINVAL, "tem_autotune: unknown precision");
+  const int ip = prec == TEM_FP32_IR ? 1 : 0;
+  std::vector<tem_ctx::UpdCfg> cand;
+  if (ip == 1)
+    cand = {{UPD_T64, true}, {UPD_T64, false}, {UPD_T128x64, true}, {UPD_T128x64, false}};
+  else
+    cand = {{UPD_T64, false}, {UPD_T64, true}};
+  const int nl = (int)c->ed.levels.size();
+  std::vector<std::vector<double>> t(cand.size(), std::vector<double>(nl, 0.0));
+  c->tuned[ip].clear();
+  tem_status st = TEM_OK;
+  for (size_t q = 0; q < cand.size() && st == TEM_OK; ++q) {
+    c->forcing = true;
+    c->forced = cand[q];
+    c->lvl_timing = true;
+    st = tem_factor_poles(c, m, xi, prec, nullptr);
+    c->forcing = false;
+    c->lvl_timing = false;
+    if (st != TEM_OK) break;
+    for (int grp = 0; grp < c->n_groups; ++grp)
+      for (int L = 0; L < nl; ++L) {
+        float ms = 0;
+        const size_t e = ((size_t)grp * nl + L) * 2;
+        if (hipEventElapsedTime(&ms, c->lvl_ev[e], c->lvl_ev[e + 1]) == hipSuccess) t[q][L] += ms;
+      }
+  }
+  if (st != TEM_OK) return st;
+  std::vector<tem_ctx::UpdCfg> best(nl);
+  double tuned = 0;
+  for (int L = 0; L < nl; ++L) {
+    size_t bq = 0;
+    for (size_t q = 1; q < cand.size(); ++q)
+      if (t[q][L] < t[bq][L]) bq = q;
+    best[L] = cand[bq];
+    tuned += t[bq][L];
+  }
+  c->tuned[ip] = best;
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->n_candidates = (int32_t)cand.size();
+    for (size_t q = 0; q < cand.size() && q < 8; ++q) {
+      double sum = 0;
+      for (int L = 0; L < nl; ++L) sum += t[q][L];
+      rep->candidate_ms[q] = sum;
+      rep->candidate_tile[q] = cand[q].tile;
+      rep->candidate_m3[q] = cand[q].m3 ? 1 : 0;
+    }
+    rep->tuned_ms = tuned;
+    rep->n_levels = nl;
+  }
+  return TEM_OK;
+}
+
+tem_status tem_autotune_level(const tem_ctx *c, tem_precision prec, int32_t level, int32_t *tile,
+                              int32_t *m3) {
+  if (!c || !tile || !m3) return TEM_EINVAL;
+  const std::vector<tem_ctx::UpdCfg> &tab = c->tuned[prec == TEM_FP32_IR ? 1 : 0];
+  if (level < 0 || level >= (int)tab.size()) return TEM_ESTATE;
+  *tile = tab[level].tile;
+  *m3 = tab[level].m3 ? 1 : 0;
   return TEM_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = ["tem_create", "tem_destroy", "tem_last_error", "tem_assemble", "tem_s
            "tem_export_operators", "tem_analyse", "tem_symbolic_host", "tem_factor_poles",
            "tem_solve_poles", "tem_forward", "tem_jvp", "tem_vjp", "tem_get_stats",
            "tem_set_profiling", "tem_gn_step", "tem_assemble_batch", "tem_factor_poles_batch",
-           "tem_forward_batch"]
+           "tem_forward_batch", "tem_autotune", "tem_autotune_level"]
 
 
 class TemError(RuntimeError):
@@ -56,6 +56,12 @@ class SymbolicInfo(C.Structure):
 class FactorOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_int64), ("max_group", C.c_int32),
                 ("reserved", C.c_int32)]
+
+
+class AutotuneReport(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("n_levels", C.c_int32),
+                ("candidate_ms", C.c_double * 8), ("candidate_tile", C.c_int32 * 8),
+                ("candidate_m3", C.c_int32 * 8), ("tuned_ms", C.c_double)]
 
 
 class IrOpts(C.Structure):
@@ -112,6 +118,9 @@ def load_library(path: str = LIB_PATH):
         "tem_set_profiling": ([vp, i32], C.c_int),
         "tem_gn_step": ([vp, dp, dp, dp, dp, C.c_double, i32, dp, vp, C.POINTER(IrOpts)], C.c_int),
         "tem_assemble_batch": ([vp, i32, vp, dp], C.c_int),
+        "tem_autotune": ([vp, i32, vp, C.c_int, C.POINTER(AutotuneReport)], C.c_int),
+        "tem_autotune_level": ([vp, C.c_int, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+                               C.c_int),
         "tem_factor_poles_batch": ([vp, vp, vp, C.c_int, C.POINTER(FactorOpts)], C.c_int),
         "tem_forward_batch": ([vp, vp, dp, vp, vp, vp, vp, i32, vp, C.POINTER(IrOpts), dp,
                                C.POINTER(IrStats)], C.c_int),
@@ -311,6 +320,24 @@ class Tem:
                                      _dev(dm, "float64", (self.n_params,)),
                                      hist.ctypes.data_as(C.c_void_p), self._ir(ir)))
         return hist
+
+    def autotune(self, xi, precision=FP32_IR):
+        """Time the front-update variants level by level and keep the fastest
+        per level (tem_autotune).  Returns the report and the per-level choice."""
+        xi = np.asarray(xi, complex)
+        buf, bp = _host(np.stack([xi.real, xi.imag], axis=1).reshape(-1), np.float64)
+        rep = AutotuneReport()
+        self._chk(self.L.tem_autotune(self.h, len(xi), bp, int(precision), C.byref(rep)))
+        self.npole = len(xi)
+        n = rep.n_candidates
+        levels = []
+        for L in range(rep.n_levels):
+            tl, m3 = C.c_int32(), C.c_int32()
+            self._chk(self.L.tem_autotune_level(self.h, int(precision), L, C.byref(tl), C.byref(m3)))
+            levels.append((tl.value, m3.value))
+        return dict(candidate_ms=list(rep.candidate_ms[:n]),
+                    candidates=list(zip(rep.candidate_tile[:n], rep.candidate_m3[:n])),
+                    tuned_ms=rep.tuned_ms, levels=levels)
 
     # ------------------------------------------------------- ragged batches
     def assemble_batch(self, meshes, mu, sigma):
