@@ -13,7 +13,11 @@ vs FP64, same GPU"): value = factor+solve seconds of the FP32+IR path
 update, FP32) from HIP events inside the library; the CPU baseline is the
 FP64 oracle on a bounded sample.
 
+Before the timed steps of each precision the update kernels are autotuned
+per tree level (tem_autotune; untimed set-up, like assembly and analysis).
+
 Usage: python bench.py [--gpus 1] [--steps 1] [--warmup 1] [--no-cpu-baseline]
+                       [--no-autotune] [--no-ragged] [--fp32-only]
 """
 from __future__ import annotations
 
@@ -66,9 +70,17 @@ def copy_probe(torch, dev, n_bytes=1 << 30, reps=5):
     print(json.dumps(dict(copy_probe_bytes=n_bytes, reps=reps)), flush=True)
 
 
-def run_precision(t, wl, prec, steps, warmup, torch, dev, F, v, w):
+def run_precision(t, wl, prec, steps, warmup, torch, dev, F, v, w, autotune=False):
     import numpy as np
     K, R = len(wl.poles.t), wl.rx.n
+    tuned = None
+    if autotune:   # untimed set-up: per-level choice of the update kernel variant
+        ta = time.perf_counter()
+        tuned = t.autotune(wl.poles.xi, prec)
+        tuned["seconds"] = time.perf_counter() - ta
+        print("# prec=%d autotune: candidates %s ms, tuned %.1f ms" % (
+            prec, ["%.1f" % x for x in tuned["candidate_ms"]], tuned["tuned_ms"]),
+            file=sys.stderr, flush=True)
     d = torch.zeros((wl.S, K, R), dtype=torch.float64, device=dev)
     jv = torch.zeros_like(d)
     jtw = torch.zeros(len(wl.params), dtype=torch.float64, device=dev)
@@ -115,6 +127,8 @@ def run_precision(t, wl, prec, steps, warmup, torch, dev, F, v, w):
     out["sweep_ms"] = st["sweep_ms"]
     out["sweep_bytes"] = st["sweep_bytes"]
     out["sweeps"] = st["sweeps"]
+    if tuned is not None:
+        out["autotune"] = tuned
     return out, d.cpu().numpy(), jtw.cpu().numpy()
 
 
@@ -220,6 +234,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the (untimed) per-level autotuning of the update kernels")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the counter-calibration copy (1 GiB, 5 times)")
     args = ap.parse_args()
@@ -251,11 +267,13 @@ def main():
     v = torch.tensor(rng.standard_normal(len(wl.params)), device=dev)
     w = torch.tensor(rng.standard_normal((wl.S, len(wl.poles.t), wl.rx.n)), device=dev)
     phases = {}
-    res32, d32, g32 = run_precision(t, wl, FP32_IR, args.steps, args.warmup, torch, dev, F, v, w)
+    res32, d32, g32 = run_precision(t, wl, FP32_IR, args.steps, args.warmup, torch, dev, F, v, w,
+                                    not args.no_autotune)
     phases["fp32_ir"] = res32
     acc = None
     if not args.fp32_only:
-        res64, d64, g64 = run_precision(t, wl, FP64, args.steps, args.warmup, torch, dev, F, v, w)
+        res64, d64, g64 = run_precision(t, wl, FP64, args.steps, args.warmup, torch, dev, F, v, w,
+                                        not args.no_autotune)
         phases["fp64"] = res64
         acc = dict(data_rel_fp32_vs_fp64=float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64)),
                    jtw_rel_fp32_vs_fp64=float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)))

@@ -746,11 +746,13 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
       fl += 8.0 * (double)k * (double)nd.nrows * (double)(nd.nrows + 1) / 2.0 *
             mf.present(s, p0, g);
     }
-    hipEvent_t ea = span_begin(c);
-    HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, 0, 0, cb_tiles, g, F, mf.pole_stride,
-                                  cbL, mf.cb_stride, ttc, cfc.m3),
-           "contribution update");
-    span_end(c, ea, fl, 0);
+    if (cb_tiles > 0) {   // (the root level has no contribution block)
+      hipEvent_t ea = span_begin(c);
+      HIPCHK(launch_front_update<T>(st, ft, ln, li.n, 1, 0, 0, 0, cb_tiles, g, F, mf.pole_stride,
+                                    cbL, mf.cb_stride, ttc, cfc.m3),
+             "contribution update");
+      span_end(c, ea, fl, 0);
+    }
     for (int sl = 0; sl < 2; ++sl)
       HIPCHK(launch_extend_add<T>(st, ft, xl + li.xm[sl], li.xe[sl] - li.xm[sl], sl, g, F,
                                   mf.pole_stride, cbL, cbC, mf.cb_stride),
