@@ -177,3 +177,35 @@ def test_ragged_batch_of_twelve_meshes_equals_one_at_a_time():
     ds = np.concatenate(singles)
     assert np.linalg.norm(db - ds) <= 1e-10 * np.linalg.norm(ds)
     t.close()
+
+
+def test_hex32_fp64_workload_sampled_poles_against_oracle():
+    """32^3 FP64 workload (12 poles, 4 sources, 40 times): the first and last
+    pole solved by the oracle (SuperLU on its own ordering) against the GPU's
+    solutions of the same poles, in the quantities of the parity tests."""
+    torch = _torch()
+    from paper_2605_19951_amd import FP64, Tem
+    wl = ti.workload(1)
+    me = wl.mesh
+    m, S = len(wl.poles.xi), wl.S
+    dev = torch.device("cuda:0")
+    print("case hex32_fp64: 32^3, 12 poles, 4 sources", flush=True)
+    t = Tem(0)
+    t.assemble(me.nx, me.ny, me.nz, me.h, ti.MU0, torch.tensor(wl.sigma, device=dev), wl.params)
+    t.analyse()
+    t.factor_poles(wl.poles.xi, FP64)
+    F = torch.tensor(wl.F.T.copy(), device=dev)
+    G = torch.zeros((m, S, me.n_edges), dtype=torch.complex128, device=dev)
+    ir = t.solve_poles(F, G)
+    assert ir["n_unconverged"] == 0
+    o = _oracle(wl)
+    Gh = G.cpu().numpy()[:, :, o.unk]
+    for i in (0, m - 1):
+        gref = o.solve(i, o.F)                                  # (N, S)
+        g = Gh[i].T
+        assert np.linalg.norm(o.Q @ (g - gref)) <= 1e-9 * np.linalg.norm(o.Q @ gref)
+        dg = g - gref
+        mn = np.sqrt(abs(np.sum(np.conj(dg) * (o.M @ dg))))
+        mr = np.sqrt(abs(np.sum(np.conj(gref) * (o.M @ gref))))
+        assert mn <= 1e-8 * mr
+    t.close()
