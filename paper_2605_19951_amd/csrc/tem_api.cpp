@@ -154,6 +154,7 @@ struct tem_ctx {
   int64_t sweep_bb = 256;          // big column block of the wide-front sweeps
   int64_t sweep_big_limit = 1024;  // fronts x poles below which a level is "wide"
   int upd_tile = UPD_T64;          // FP32 update tile shape (FP64: 64 x 64)
+  int panel_w = 8 * NB;            // columns per factorisation panel (multiple of NB)
   bool upd_m3_f32 = true;          // 3M complex products in the FP32 update
   bool upd_m3_f64 = false;         // 3M complex products in the FP64 update
   // Autotuned update variant per tree level of the edge system, by
@@ -685,10 +686,10 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
       HIPCHK(launch_extend_add<T>(st, ft, xl + li.xa[sl], li.xm[sl] - li.xa[sl], sl, g, F,
                                   mf.pole_stride, cbL, cbC, mf.cb_stride),
              "extend-add into panels");
-    // 128-column panels: inside a panel every 32-column block is factored and
-    // applied (rank 32) to the rest of the panel only; the panel then
-    // updates all later columns at once (rank 128).
-    const int PW = 4 * NB;
+    // Panels of panel_w columns (256 by default): inside a panel every
+    // 32-column block is factored and applied (rank 32) to the rest of the
+    // panel only; the panel then updates all later columns at once.
+    const int PW = c->panel_w;
     auto trailing = [&](int j0, int dw, int ccap) -> tem_status {
       int64_t max_tiles = 0;
       double fl = 0;
@@ -1691,6 +1692,10 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
     if (b >= 0) c->sweep_big_limit = b;
   }
   if (const char *v = std::getenv("TEM_GRAPHS")) c->use_graphs = std::strtol(v, nullptr, 10) != 0;
+  if (const char *v = std::getenv("TEM_PANEL")) {   // panel width: a multiple of 32, 32..1024
+    const long w = std::strtol(v, nullptr, 10);
+    if (w >= NB && w <= 1024 && w % NB == 0) c->panel_w = (int)w;
+  }
   if (const char *v = std::getenv("TEM_UPDATE_TILE")) {   // "64", "128x64" or "128"
     const std::string m(v);
     c->upd_tile = m == "64" ? UPD_T64 : m == "128" ? UPD_T128 : UPD_T128x64;
