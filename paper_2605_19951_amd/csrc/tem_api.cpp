@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -686,9 +687,13 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
       HIPCHK(launch_extend_add<T>(st, ft, xl + li.xa[sl], li.xm[sl] - li.xa[sl], sl, g, F,
                                   mf.pole_stride, cbL, cbC, mf.cb_stride),
              "extend-add into panels");
-    // Panels of panel_w columns (256 by default): inside a panel every
-    // 32-column block is factored and applied (rank 32) to the rest of the
-    // panel only; the panel then updates all later columns at once.
+    // Panels of panel_w columns (256 by default), each factored recursively:
+    // the left half of a column range is factored, applied to the right half
+    // only (one rank-w/2 update), then the right half is factored; 32-column
+    // blocks at the bottom take the diagonal and triangular-solve kernels.
+    // The finished panel then updates all later columns at once.  This is
+    // the arithmetic of 32-column right-looking steps in another order, with
+    // deeper and fewer read-modify-write passes over the panel.
     const int PW = c->panel_w;
     auto trailing = [&](int j0, int dw, int ccap) -> tem_status {
       int64_t max_tiles = 0;
@@ -717,23 +722,33 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
       span_end(c, ea, fl, 0);
       return TEM_OK;
     };
-    for (int P0 = 0; P0 < li.max_k; P0 += PW) {
-      for (int j0 = P0; j0 < std::min(P0 + PW, li.max_k); j0 += NB) {
-        int max_rows = 0;
-        for (int s : li.nodes) {
-          const SymNode &nd = sym.nodes[s];
-          const int64_t k = nd.last - nd.first, n = k + nd.nrows;
-          if (j0 >= k) continue;
-          const int64_t w = std::min<int64_t>(NB, k - j0);
-          max_rows = std::max<int>(max_rows, (int)(n - j0 - w));
-        }
-        HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, g, F, mf.pole_stride,
-                                    c->d_flags.as<int>()),
-               "panel diag");
-        HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, max_rows, g, F, mf.pole_stride),
-               "panel trsm");
-        TRY(trailing(j0, NB, P0 + PW));
+    auto block = [&](int j0) -> tem_status {   // columns [j0, j0 + NB)
+      int max_rows = 0;
+      for (int s : li.nodes) {
+        const SymNode &nd = sym.nodes[s];
+        const int64_t k = nd.last - nd.first, n = k + nd.nrows;
+        if (j0 >= k) continue;
+        const int64_t w = std::min<int64_t>(NB, k - j0);
+        max_rows = std::max<int>(max_rows, (int)(n - j0 - w));
       }
+      HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, g, F, mf.pole_stride,
+                                  c->d_flags.as<int>()),
+             "panel diag");
+      HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, max_rows, g, F, mf.pole_stride),
+             "panel trsm");
+      return TEM_OK;
+    };
+    // columns [a, a + w) of the panel, w a multiple of NB
+    std::function<tem_status(int, int)> factor_range = [&](int a, int w) -> tem_status {
+      if (a >= li.max_k) return TEM_OK;
+      if (w <= NB) return block(a);
+      const int h = NB * ((w / NB) / 2);
+      TRY(factor_range(a, h));
+      TRY(trailing(a, h, a + w));
+      return factor_range(a + h, w - h);
+    };
+    for (int P0 = 0; P0 < li.max_k; P0 += PW) {
+      TRY(factor_range(P0, PW));
       TRY(trailing(P0, PW, 1 << 30));
     }
     int64_t cb_tiles = 0;
