@@ -430,8 +430,16 @@ __device__ inline int64_t trap_count(int64_t nct, int64_t nrt) {
 // mode 0: depth (eliminated columns) [j0, j0 + dw), updated columns
 // [j0 + dw, min(k, ccap)); mode 1: depth [0, k), contribution block.
 // TR x TC output tile per workgroup, 4 waves of (TR/2) x (TC/2).
+// Waves per SIMD the register allocation must allow: FP32 tiles of 64 x 64
+// fit four (at most 128 registers, accumulators included) and tiles of
+// 128 x 64 three, without spilling.
+template <typename T, int TR, int TC>
+constexpr int update_waves() {
+  return sizeof(T) != 4 ? 1 : (TR == 64 && TC == 64) ? 4 : (TR == 128 && TC == 64) ? 3 : 1;
+}
 template <typename T, int TR, int TC, bool M3>
-__global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t *lvl_nodes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(update_waves<T, TR, TC>())))
+void k_front_update(FrontTab ft, const int32_t *lvl_nodes,
                                                       int mode, int j0, int dw, int ccap,
                                                       cpx<T> *factor, int64_t f_stride,
                                                       cpx<T> *cb, int64_t cb_stride) {
@@ -476,50 +484,56 @@ __global__ __launch_bounds__(256) void k_front_update(FrontTab ft, const int32_t
   __shared__ T Ar[2][KB][TR], Ai[2][KB][TR], Br[2][KB][TC], Bi[2][KB][TC];
   __shared__ T Dr[2][KB], Di[2][KB];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  // the wave index is uniform: computed once on the scalar unit, so that
+  // every depth offset below is scalar arithmetic and only the row offset
+  // is per lane
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave & 1, wc = wave >> 1;
   constexpr int PA = TR * KB / 256, PB = TC * KB / 256;   // elements per thread and chunk
-  const int lra = tid % TR, lka = (tid / TR) * PA;       // A row / first depth it loads
-  const int lrb = tid % TC, lkb = (tid / TC) * PB;       // B row / first depth it loads
+  static_assert(TR % 64 == 0 && TC % 64 == 0, "tiles are whole waves wide");
+  const int lra = (wave % (TR / 64)) * 64 + lane, lka = (wave / (TR / 64)) * PA;
+  const int lrb = (wave % (TC / 64)) * 64 + lane, lkb = (wave / (TC / 64)) * PB;
   // Prefetch of the next depth chunk: unconditional loads from clamped
   // (in-bounds) addresses, so nothing waits on them until the chunk is
-  // written to LDS, where the masking happens.  Clamped rows stay in the
-  // panel block: every row index is >= cbeg >= l1.  Threads tid < KB also
-  // fetch the pivot D of depth column l + tid.
+  // written to LDS.  No value needs masking there: depth columns past l1
+  // get the pivot D = 0, which zeroes their whole contribution (B = L D is
+  // formed from the staged D), and rows past n only reach outputs that the
+  // epilogue discards.  Clamped rows stay in the panel block: every row
+  // index is >= cbeg >= l1.  Threads tid < KB also fetch the pivot of
+  // depth column l + tid.
   cpx<T> pa[PA], pb[PB], pd;
   int64_t pl = l0;
-  const int64_t ra = row0 + lra, rb = col0 + lrb;
-  const int64_t rac = min(ra, n - 1), rbc = min(rb, n - 1);
+  const int32_t rac = (int32_t)min(row0 + lra, n - 1), rbc = (int32_t)min(col0 + lrb, n - 1);
+  const int32_t dl = tid % KB;
   auto fetch = [&](int64_t l) {
     const int64_t b = l / NB, r0 = NB * b, ldb = n - r0;
     const cpx<T> *base = P + panel_block_off(n, b) - r0;
 #pragma unroll
     for (int q = 0; q < PA; ++q) {
       const int64_t lc = min(l + lka + q, l1 - 1);
-      pa[q] = base[(lc - r0) * ldb + rac];
+      pa[q] = (base + (lc - r0) * ldb)[rac];
     }
 #pragma unroll
     for (int q = 0; q < PB; ++q) {
       const int64_t lc = min(l + lkb + q, l1 - 1);
-      pb[q] = base[(lc - r0) * ldb + rbc];
+      pb[q] = (base + (lc - r0) * ldb)[rbc];
     }
-    const int64_t ld = min(l + (tid % KB), l1 - 1);
-    pd = base[(ld - r0) * ldb + ld];
+    const int32_t ld = (int32_t)min(l + dl, l1 - 1) - (int32_t)r0;   // 0 <= ld < NB
+    pd = (base + r0)[__umul24((uint32_t)ld, (uint32_t)ldb + 1u)];
     pl = l;
   };
-  // registers -> LDS buffer bf, masked (columns past l1 get D = 0)
+  // registers -> LDS buffer bf (columns past l1 get D = 0)
   auto stage = [&](int bf) {
 #pragma unroll
     for (int q = 0; q < PA; ++q) {
-      const cpx<T> a = (pl + lka + q < l1 && ra < n) ? pa[q] : czero<T>();
-      Ar[bf][lka + q][lra] = a.re;
-      Ai[bf][lka + q][lra] = a.im;
+      Ar[bf][lka + q][lra] = pa[q].re;
+      Ai[bf][lka + q][lra] = pa[q].im;
     }
 #pragma unroll
     for (int q = 0; q < PB; ++q) {
-      const cpx<T> bb = (pl + lkb + q < l1 && rb < n) ? pb[q] : czero<T>();
-      Br[bf][lkb + q][lrb] = bb.re;
-      Bi[bf][lkb + q][lrb] = bb.im;
+      Br[bf][lkb + q][lrb] = pb[q].re;
+      Bi[bf][lkb + q][lrb] = pb[q].im;
     }
     if (tid < KB) {
       const bool okd = pl + tid < l1;

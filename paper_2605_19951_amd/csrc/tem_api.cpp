@@ -156,6 +156,7 @@ struct tem_ctx {
   int64_t sweep_big_limit = 1024;  // fronts x poles below which a level is "wide"
   int upd_tile = UPD_T64;          // FP32 update tile shape (FP64: 64 x 64)
   int panel_w = 8 * NB;            // columns per factorisation panel (multiple of NB)
+  bool left_looking = true;        // panels take all earlier panels' updates at once
   bool upd_m3_f32 = true;          // 3M complex products in the FP32 update
   bool upd_m3_f64 = false;         // 3M complex products in the FP64 update
   // Autotuned update variant per tree level of the edge system, by
@@ -748,8 +749,13 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
       return factor_range(a + h, w - h);
     };
     for (int P0 = 0; P0 < li.max_k; P0 += PW) {
-      TRY(factor_range(P0, PW));
-      TRY(trailing(P0, PW, 1 << 30));
+      if (c->left_looking) {
+        if (P0 > 0) TRY(trailing(0, P0, P0 + PW));
+        TRY(factor_range(P0, PW));
+      } else {
+        TRY(factor_range(P0, PW));
+        TRY(trailing(P0, PW, 1 << 30));
+      }
     }
     int64_t cb_tiles = 0;
     double fl = 0;
@@ -1711,6 +1717,7 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
     const long w = std::strtol(v, nullptr, 10);
     if (w >= NB && w <= 1024 && w % NB == 0) c->panel_w = (int)w;
   }
+  if (const char *v = std::getenv("TEM_LEFT_LOOKING")) c->left_looking = std::strtol(v, nullptr, 10) != 0;
   if (const char *v = std::getenv("TEM_UPDATE_TILE")) {   // "64", "128x64" or "128"
     const std::string m(v);
     c->upd_tile = m == "64" ? UPD_T64 : m == "128" ? UPD_T128 : UPD_T128x64;
