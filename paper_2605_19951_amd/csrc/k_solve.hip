@@ -295,15 +295,132 @@ __global__ __launch_bounds__(256) void k_fwd_rect(FrontTab ft, const int32_t *lv
   }
 }
 
+// FP32 forward rect on the matrix cores: per front the update rows are
+// W = (children's rows) - L21 Y, a product with few columns (the right-hand
+// sides).  v_mfma_f32_16x16x4f32 multiplies 16 rows of L21 by four columns
+// at a time; its 16 output columns hold Re y and Im y of eight right-hand
+// sides, so Lr B and Li B (B = [Re Y | Im Y]) give all four real products
+// of the complex one: Re(L y) = Lr Re y - Li Im y, Im(L y) = Lr Im y +
+// Li Re y.  Operand lane l carries row (or output column) l % 16 and depth
+// l / 16; result element i of lane l is row 4 (l / 16) + i, column l % 16.
+// Each wave owns 32 rows and walks all k columns on its own (no LDS, no
+// barriers); the loads of a 32-column chunk are issued together.
+// NBK = 1 for S <= 8 right-hand sides, 2 for S <= 16.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+template <int NBK>
+__global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
+                                                       int S, int64_t N, const cpx<float> *factor,
+                                                       int64_t f_stride, const cpx<float> *x,
+                                                       const cpx<float> *w_child,
+                                                       cpx<float> *w_out, int64_t w_stride) {
+  constexpr int RB = 2, KC = 32;   // 16-row blocks per wave, columns per chunk
+  const int s = lvl_nodes[blockIdx.y];
+  const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
+  const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t aw = (int64_t)blockIdx.x * 128 + wave * 32;   // first row of the wave
+  if (aw >= u) return;
+  const cpx<float> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  const cpx<float> *X = x + ((int64_t)p * N + first) * S;
+  const int lr = lane & 15, ld4 = lane >> 4;   // operand row / output column, depth
+  // rows of the two blocks (clamped; rows past u reach no output)
+  int64_t rrow[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) rrow[b] = k + min(aw + b * 16 + lr, u - 1);
+  // B operand: column lr of block nb is Re y_j (lr < 8) or Im y_j, j = 8 nb + lr % 8
+  int yj[NBK];
+  bool yon[NBK];
+#pragma unroll
+  for (int nb = 0; nb < NBK; ++nb) {
+    const int j = 8 * nb + (lr & 7);
+    yon[nb] = j < S;
+    yj[nb] = 2 * min(j, S - 1) + (lr >> 3);   // float index inside a row of X
+  }
+  floatx4 r1[RB][NBK], r2[RB][NBK];
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int nb = 0; nb < NBK; ++nb) {
+      r1[b][nb] = floatx4{0, 0, 0, 0};
+      r2[b][nb] = floatx4{0, 0, 0, 0};
+    }
+  const float *Xf = reinterpret_cast<const float *>(X);
+  for (int64_t jb = 0; jb < k; jb += KC) {
+    int64_t ld;
+    const cpx<float> *Lc = col_ptr(P, n, jb, ld);   // the chunk lies in one column block
+    cpx<float> lv[KC / 4][RB];
+    float yv[KC / 4][NBK];
+#pragma unroll
+    for (int q = 0; q < KC / 4; ++q) {
+      const int64_t col = jb + 4 * q + ld4;
+      const int64_t cc = min(col, k - 1);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) lv[q][b] = Lc[(cc - jb) * ld + rrow[b]];
+#pragma unroll
+      for (int nb = 0; nb < NBK; ++nb) {
+        const float y = Xf[cc * 2 * S + yj[nb]];
+        yv[q][nb] = (col < k && yon[nb]) ? y : 0.f;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KC / 4; ++q)
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int nb = 0; nb < NBK; ++nb) {
+          r1[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(lv[q][b].re, yv[q][nb], r1[b][nb], 0, 0, 0);
+          r2[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(lv[q][b].im, yv[q][nb], r2[b][nb], 0, 0, 0);
+        }
+  }
+  // lanes with lr < 8 hold column j's Lr Re y and Li Re y; lane l ^ 8 holds
+  // Lr Im y and Li Im y of the same j
+  const int c0 = ft.child0[s], c1 = ft.child1[s];
+  const bool h0 = c0 >= 0 && ft.u[c0] > 0, h1 = c1 >= 0 && ft.u[c1] > 0;
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int nb = 0; nb < NBK; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float o1 = __shfl_xor(r1[b][nb][i], 8), o2 = __shfl_xor(r2[b][nb][i], 8);
+        const int64_t a = aw + b * 16 + 4 * ld4 + i;
+        const int j = 8 * nb + lr;
+        if (lr >= 8 || j >= S || a >= u) continue;
+        cpx<float> v = {-(r1[b][nb][i] - o2), -(o1 + r2[b][nb][i])};
+        if (h0) {
+          const int g = ft.gmap0[ft.gmap_off[s] + k + a];
+          if (g >= 0) v = cadd(v, w_child[(int64_t)p * w_stride + (ft.w_off[c0] + g) * S + j]);
+        }
+        if (h1) {
+          const int g = ft.gmap1[ft.gmap_off[s] + k + a];
+          if (g >= 0) v = cadd(v, w_child[(int64_t)p * w_stride + (ft.w_off[c1] + g) * S + j]);
+        }
+        w_out[(int64_t)p * w_stride + (ft.w_off[s] + a) * S + j] = v;
+      }
+}
+
 template <typename T>
 hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_u, int npole, int S, int64_t N, const cpx<T> *factor,
                            int64_t f_stride, const cpx<T> *x, const cpx<T> *w_child,
                            cpx<T> *w_out, int64_t w_stride) {
   if (n_nodes <= 0 || max_u <= 0) return hipSuccess;
-  dim3 grid((max_u + 255) / 256, n_nodes, npole);
-  hipLaunchKernelGGL(k_fwd_rect<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
-                     x, w_child, w_out, w_stride);
+  if constexpr (sizeof(T) == 4) {
+    if (S < 1 || S > 16) return hipErrorInvalidValue;
+    dim3 grid((max_u + 127) / 128, n_nodes, npole);
+    if (S <= 8)
+      hipLaunchKernelGGL(k_fwd_rect_mfma<1>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor,
+                         f_stride, x, w_child, w_out, w_stride);
+    else
+      hipLaunchKernelGGL(k_fwd_rect_mfma<2>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor,
+                         f_stride, x, w_child, w_out, w_stride);
+  } else {
+    dim3 grid((max_u + 255) / 256, n_nodes, npole);
+    hipLaunchKernelGGL(k_fwd_rect<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor,
+                       f_stride, x, w_child, w_out, w_stride);
+  }
   return hipGetLastError();
 }
 

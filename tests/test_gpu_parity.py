@@ -80,6 +80,8 @@ CASES = {
     "c16_32": lambda: Run(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 1),
     "w16_64": lambda: _wide(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 0),
     "w16_32": lambda: _wide(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 1),
+    # twelve right-hand sides: the FP32 forward sweep's two-block path (S > 8)
+    "s12_32": lambda: Run(ti.smooth_workload(16, 2, S=12, m=3, K=5, g=2, seed=23), 1),
 }
 _cache = {}
 
@@ -151,7 +153,8 @@ def test_data_all_times(name):
         assert np.linalg.norm(d[:, j] - dref[:, j]) <= tol * max(nrm, np.linalg.norm(cond[:, j]))
 
 
-@pytest.mark.parametrize("name", ["r13_64", "r13_32", "c16_64", "c16_32", "w16_64", "w16_32"])
+@pytest.mark.parametrize("name", ["r13_64", "r13_32", "c16_64", "c16_32", "w16_64", "w16_32",
+                                  "s12_32"])
 def test_jvp_vjp(name):
     r = get(name)
     torch = r.torch
