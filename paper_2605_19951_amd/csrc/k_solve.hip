@@ -304,7 +304,8 @@ __global__ __launch_bounds__(256) void k_fwd_rect(FrontTab ft, const int32_t *lv
 // Li Re y.  Operand lane l carries row (or output column) l % 16 and depth
 // l / 16; result element i of lane l is row 4 (l / 16) + i, column l % 16.
 // Each wave owns 32 rows and walks all k columns on its own (no LDS, no
-// barriers); the loads of a 32-column chunk are issued together.
+// barriers), 32 columns at a time, loading the next chunk while the
+// current one is multiplied.
 // NBK = 1 for S <= 8 right-hand sides, 2 for S <= 16.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 template <int NBK>
@@ -326,9 +327,9 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
   const cpx<float> *X = x + ((int64_t)p * N + first) * S;
   const int lr = lane & 15, ld4 = lane >> 4;   // operand row / output column, depth
   // rows of the two blocks (clamped; rows past u reach no output)
-  int64_t rrow[RB];
+  int32_t rrow[RB];
 #pragma unroll
-  for (int b = 0; b < RB; ++b) rrow[b] = k + min(aw + b * 16 + lr, u - 1);
+  for (int b = 0; b < RB; ++b) rrow[b] = (int32_t)(k + min(aw + b * 16 + lr, u - 1));
   // B operand: column lr of block nb is Re y_j (lr < 8) or Im y_j, j = 8 nb + lr % 8
   int yj[NBK];
   bool yon[NBK];
@@ -347,23 +348,29 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
       r2[b][nb] = floatx4{0, 0, 0, 0};
     }
   const float *Xf = reinterpret_cast<const float *>(X);
-  for (int64_t jb = 0; jb < k; jb += KC) {
+  // chunk jb into (lv, yv): unconditional loads from clamped addresses (a
+  // chunk past the end re-reads the last one and gets y = 0)
+  const int64_t jlast = ((k - 1) / KC) * KC;
+  auto load = [&](int64_t jb, cpx<float> (&lv)[KC / 4][RB], float (&yv)[KC / 4][NBK]) {
+    const int64_t je = min(jb, jlast);
     int64_t ld;
-    const cpx<float> *Lc = col_ptr(P, n, jb, ld);   // the chunk lies in one column block
-    cpx<float> lv[KC / 4][RB];
-    float yv[KC / 4][NBK];
+    const cpx<float> *Lc = col_ptr(P, n, je, ld);   // the chunk lies in one column block
+    const float *Xc = Xf + je * 2 * S;
+    // 32-bit offsets inside the chunk: column offset <= 31, ld and 2 S below 2^24
+    const int32_t lim = (int32_t)(k - 1 - je), ldi = (int32_t)ld, colk = (int32_t)(k - jb);
 #pragma unroll
     for (int q = 0; q < KC / 4; ++q) {
-      const int64_t col = jb + 4 * q + ld4;
-      const int64_t cc = min(col, k - 1);
+      const int32_t t = 4 * q + ld4, o = min(t, lim);
+      const int32_t lo = (int32_t)__umul24((uint32_t)o, (uint32_t)ldi);
 #pragma unroll
-      for (int b = 0; b < RB; ++b) lv[q][b] = Lc[(cc - jb) * ld + rrow[b]];
+      for (int b = 0; b < RB; ++b) lv[q][b] = Lc[lo + rrow[b]];
+      const int32_t yo = (int32_t)__umul24((uint32_t)o, (uint32_t)(2 * S));
 #pragma unroll
-      for (int nb = 0; nb < NBK; ++nb) {
-        const float y = Xf[cc * 2 * S + yj[nb]];
-        yv[q][nb] = (col < k && yon[nb]) ? y : 0.f;
-      }
+      for (int nb = 0; nb < NBK; ++nb)   // a multiply, not a select: the load stays unconditional
+        yv[q][nb] = Xc[yo + yj[nb]] * ((t < colk && yon[nb]) ? 1.f : 0.f);
     }
+  };
+  auto mma = [&](const cpx<float> (&lv)[KC / 4][RB], const float (&yv)[KC / 4][NBK]) {
 #pragma unroll
     for (int q = 0; q < KC / 4; ++q)
 #pragma unroll
@@ -373,6 +380,18 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
           r1[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(lv[q][b].re, yv[q][nb], r1[b][nb], 0, 0, 0);
           r2[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(lv[q][b].im, yv[q][nb], r2[b][nb], 0, 0, 0);
         }
+  };
+  // two register sets: the loads of the next chunk are in flight while the
+  // current one is multiplied
+  cpx<float> la[KC / 4][RB], lb[KC / 4][RB];
+  float ya[KC / 4][NBK], yb[KC / 4][NBK];
+  load(0, la, ya);
+  for (int64_t jb = 0; jb < k; jb += 2 * KC) {
+    load(jb + KC, lb, yb);
+    mma(la, ya);
+    if (jb + KC >= k) break;
+    load(jb + 2 * KC, la, ya);
+    mma(lb, yb);
   }
   // lanes with lr < 8 hold column j's Lr Re y and Li Re y; lane l ^ 8 holds
   // Lr Im y and Li Im y of the same j
