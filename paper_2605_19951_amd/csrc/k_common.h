@@ -54,6 +54,18 @@ __device__ __forceinline__ bool pole_absent(const FrontTab &ft, int s, int p) {
   return ft.np && ft.p0 + p >= ft.np[s];
 }
 
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations (lgkmcnt 0) but not for its global loads and stores,
+// which __syncthreads (a workgroup release fence) would drain, so that loads
+// issued ahead stay in flight across the barrier.  Not a fence for global
+// memory: threads must not exchange data through it across this barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // vmcnt 63, expcnt 7, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 inline unsigned grid_1d(int64_t n, int block, int64_t cap = 65535 * 16) {
   int64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;

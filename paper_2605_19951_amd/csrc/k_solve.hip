@@ -43,33 +43,19 @@ __device__ __forceinline__ void stage_tile(cpx<T> (*Lt)[RTS + 1], const cpx<T> *
   }
 }
 
-// ------------------------------------------------------------ forward tri
-// Solves the diagonal blocks of columns [cb, ce), ce = min(cb + BB, k), and
-// updates only the rows inside that range; cb == 0 first adds the children's
-// update rows to all top rows.
+// Adds the children's update rows into the top rows X of front s (pole p):
+// four elements per thread in flight, maps, then child rows, then sums.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl_nodes, int S,
-                                                 int64_t N, const cpx<T> *factor,
-                                                 int64_t f_stride, cpx<T> *x,
-                                                 const cpx<T> *w_child, int64_t w_stride,
-                                                 int64_t cb, int64_t BB) {
-  const int s = lvl_nodes[blockIdx.x];
-  const int p = blockIdx.y;
-  if (pole_absent(ft, s, p)) return;
-  const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
-  if (k == 0 || cb >= k) return;
-  const int64_t ce = min(k, cb + BB);
-  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  cpx<T> *X = x + ((int64_t)p * N + first) * S;     // rows of this front's columns
-  const int tid = threadIdx.x;
-  // child contributions into the top rows
+__device__ inline void fwd_child_add(const FrontTab &ft, int s, int p, int64_t k, int S,
+                                     cpx<T> *X, const cpx<T> *w_child, int64_t w_stride,
+                                     int tid) {
   const int32_t *gm0 = ft.gmap0 + ft.gmap_off[s];
   const int32_t *gm1 = ft.gmap1 + ft.gmap_off[s];
   const int c0 = ft.child0[s], c1 = ft.child1[s];
   const cpx<T> *W0 = c0 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c0] * S : nullptr;
   const cpx<T> *W1 = c1 >= 0 ? w_child + (int64_t)p * w_stride + ft.w_off[c1] * S : nullptr;
   const bool h0 = c0 >= 0 && ft.u[c0] > 0, h1 = c1 >= 0 && ft.u[c1] > 0;
-  if ((h0 || h1) && cb == 0) {
+  if (h0 || h1) {
     // four elements per thread in flight: maps, then child rows, then sums
     const int64_t tot = k * S;
     for (int64_t base = tid; base < tot; base += 4 * 256) {
@@ -99,6 +85,28 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
       }
     }
   }
+}
+
+// ------------------------------------------------------------ forward tri
+// Solves the diagonal blocks of columns [cb, ce), ce = min(cb + BB, k), and
+// updates only the rows inside that range; cb == 0 first adds the children's
+// update rows to all top rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl_nodes, int S,
+                                                 int64_t N, const cpx<T> *factor,
+                                                 int64_t f_stride, cpx<T> *x,
+                                                 const cpx<T> *w_child, int64_t w_stride,
+                                                 int64_t cb, int64_t BB) {
+  const int s = lvl_nodes[blockIdx.x];
+  const int p = blockIdx.y;
+  if (pole_absent(ft, s, p)) return;
+  const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
+  if (k == 0 || cb >= k) return;
+  const int64_t ce = min(k, cb + BB);
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;     // rows of this front's columns
+  const int tid = threadIdx.x;
+  if (cb == 0) fwd_child_add<T>(ft, s, p, k, S, X, w_child, w_stride, tid);
   __shared__ cpx<T> Li[NB][NB + 1];   // Li[j][l]: inverse of the unit-lower diagonal block
   __shared__ cpx<T> V[NB][16];
   __shared__ cpx<T> Y[NB][16];
@@ -141,14 +149,128 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
   }
 }
 
+// FP32 forward triangle for ranges of at most 256 rows.  Thread i owns row
+// cb + i of the range and keeps its right-hand sides in registers for the
+// whole range, together with its row of the current 32-column block, loaded
+// one block ahead (as is the inverse diagonal block).  Per block: the owners
+// of the block's rows publish them (V), Y = V + Lo V is formed, Lo the
+// strictly lower part of the stored inverse of the unit-lower diagonal
+// block, and every later row of the range subtracts its L row times Y.  SP
+// (8 or 16) columns are computed for S <= SP right-hand sides, with zero
+// factors in place of branches; barriers order LDS only.
+template <int SP>
+__global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t *lvl_nodes,
+                                                     int S, int64_t N, const cpx<float> *factor,
+                                                     int64_t f_stride, cpx<float> *x,
+                                                     const cpx<float> *w_child, int64_t w_stride,
+                                                     int64_t cb, int64_t BB) {
+  constexpr int NT = NB * SP / 256;   // (row, column) tasks per thread in the block solve
+  const int s = lvl_nodes[blockIdx.x];
+  const int p = blockIdx.y;
+  if (pole_absent(ft, s, p)) return;
+  const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
+  if (k == 0 || cb >= k) return;
+  const int64_t ce = min(k, cb + BB);
+  const cpx<float> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<float> *X = x + ((int64_t)p * N + first) * S;
+  const int tid = threadIdx.x;
+  if (cb == 0) fwd_child_add<float>(ft, s, p, k, S, X, w_child, w_stride, tid);
+  __syncthreads();
+  const int nr = (int)(ce - cb);   // <= 256 (checked by the launcher)
+  const bool own = tid < nr;
+  const int64_t r = cb + min(tid, nr - 1);
+  cpx<float> xr[SP];
+#pragma unroll
+  for (int c = 0; c < SP; ++c) xr[c] = X[r * S + min(c, S - 1)];
+  __shared__ cpx<float> Lo[NB][NB + 1];
+  __shared__ cpx<float> V[NB][SP];
+  __shared__ cpx<float> Y[NB][SP];
+  cpx<float> lv[NB], li[NB * NB / 256];
+  // inverse block of columns [jb, jb + NB): Linv[j][l] at (row jb + l,
+  // column jb + j); clamped to the last block (entries past w are zeroed)
+  auto fetch_li = [&](int64_t jb) {
+    jb = min(jb, NB * ((k - 1) / NB));
+    const int w = (int)min((int64_t)NB, k - jb);
+    int64_t ld;
+    const cpx<float> *Lc = col_ptr(P, n, jb, ld);
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
+      li[q] = Lc[(int64_t)min(j, w - 1) * ld + jb + min(l, w - 1)];
+    }
+  };
+  // the owned row's entries in columns [jb, jb + NB) (rows above the block
+  // are clamped to its first row: they are not stored with it)
+  auto fetch_lv = [&](int64_t jb) {
+    jb = min(jb, NB * ((k - 1) / NB));
+    const int w = (int)min((int64_t)NB, k - jb);
+    int64_t ld;
+    const cpx<float> *Lc = col_ptr(P, n, jb, ld);
+    const int64_t rr = max(r, jb);
+#pragma unroll
+    for (int l = 0; l < NB; ++l) lv[l] = Lc[(int64_t)min(l, w - 1) * ld + rr];
+  };
+  fetch_li(cb);
+  fetch_lv(cb);
+  for (int64_t jb = cb; jb < ce; jb += NB) {
+    const int w = (int)min((int64_t)NB, k - jb);
+    lds_barrier();   // the previous block's readers of Lo, V and Y are done
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
+      Lo[j][l] = (l < j && j < w) ? li[q] : czero<float>();
+    }
+    fetch_li(jb + NB);
+    if (own && r >= jb && r < jb + w) {
+#pragma unroll
+      for (int c = 0; c < SP; ++c) V[r - jb][c] = xr[c];
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {   // rows past w of the block: zero
+      const int idx = tid + 256 * q, j = idx / SP;
+      if (j >= w) V[j][idx % SP] = czero<float>();
+    }
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int idx = tid + 256 * q, j = idx / SP, c = idx % SP;
+      cpx<float> acc = V[j][c];
+#pragma unroll
+      for (int l = 0; l < NB; ++l) acc = cfma(Lo[j][l], V[l][c], acc);
+      Y[j][c] = acc;
+      if (j < w && c < S) X[(jb + j) * S + c] = acc;
+    }
+    lds_barrier();
+    if (own && r >= jb + w) {
+#pragma unroll
+      for (int l = 0; l < NB; ++l) {
+        const cpx<float> a = l < w ? lv[l] : czero<float>();
+#pragma unroll
+        for (int c = 0; c < SP; ++c) xr[c] = csub(xr[c], cmul(a, Y[l][c]));
+      }
+    }
+    fetch_lv(jb + NB);
+  }
+}
+
 template <typename T>
 hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
                           cpx<T> *x, const cpx<T> *w_child, int64_t w_stride, int64_t cb,
                           int64_t BB) {
   if (n_nodes <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
-                     factor, f_stride, x, w_child, w_stride, cb, BB);
+  // the column blocks of wide fronts (at most 256 rows, one per thread)
+  // take the register kernel; whole small fronts, many per level, keep the
+  // lighter LDS kernel
+  if (sizeof(T) == 4 && S >= 1 && S <= 16 && BB <= 256 && BB % NB == 0 && cb % NB == 0)
+    hipLaunchKernelGGL(S <= 8 ? k_fwd_tri_reg<8> : k_fwd_tri_reg<16>, dim3(n_nodes, npole),
+                       dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       reinterpret_cast<const cpx<float> *>(factor), f_stride,
+                       reinterpret_cast<cpx<float> *>(x),
+                       reinterpret_cast<const cpx<float> *>(w_child), w_stride, cb, BB);
+  else
+    hipLaunchKernelGGL(k_fwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, w_child, w_stride, cb, BB);
   return hipGetLastError();
 }
 
@@ -651,14 +773,134 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
   }
 }
 
+// FP32 backward triangle for ranges of at most 256 rows, right-looking:
+// thread i owns row cb + i and keeps its right-hand side v in registers
+// (D^{-1} y - t with init, else the value in x).  Blocks run from the last
+// to the first; per block the owners publish v, x_b = v + Lo^T v is formed
+// and written out (Lo as in the forward kernel), and every earlier row r of
+// the range subtracts sum_l L(jb + l, r) x_b[l], from its own column's
+// entries below the block, loaded one block ahead.  SP as in the forward
+// kernel.
+template <int SP>
+__global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t *lvl_nodes,
+                                                     int S, int64_t N, const cpx<float> *factor,
+                                                     int64_t f_stride, cpx<float> *x,
+                                                     const cpx<float> *t, int64_t t_stride,
+                                                     int64_t cb, int64_t BB, int init) {
+  constexpr int NT = NB * SP / 256;
+  const int s = lvl_nodes[blockIdx.x];
+  const int p = blockIdx.y;
+  if (pole_absent(ft, s, p)) return;
+  const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
+  if (k == 0 || cb >= k) return;
+  const int64_t ce = min(k, cb + BB);
+  const cpx<float> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<float> *X = x + ((int64_t)p * N + first) * S;
+  const cpx<float> *Tv = t + (int64_t)p * t_stride + first * S;
+  const int tid = threadIdx.x;
+  const int nr = (int)(ce - cb);   // <= 256 (checked by the launcher)
+  const bool own = tid < nr;
+  const int64_t r = cb + min(tid, nr - 1);
+  int64_t ldr;
+  const cpx<float> *Lr = col_ptr(P, n, r, ldr);   // column r: element (i, r) at Lr[i]
+  const int64_t r0 = NB * (r / NB);
+  cpx<float> v[SP];
+  {
+    const cpx<float> dinv = init ? cinv(Lr[r]) : cpx<float>{1.f, 0.f};
+    const bool tt = init && u > 0;
+#pragma unroll
+    for (int c = 0; c < SP; ++c) {
+      const int64_t id = r * S + min(c, S - 1);
+      v[c] = cmul(X[id], dinv);
+      if (tt) v[c] = csub(v[c], Tv[id]);
+    }
+  }
+  __shared__ cpx<float> Lo[NB][NB + 1];   // Lo[l][j] = Linv[j][l] for l < j < w
+  __shared__ cpx<float> V[NB][SP];
+  __shared__ cpx<float> Y[NB][SP];
+  cpx<float> lv[NB], li[NB * NB / 256];
+  const int64_t b_first = cb / NB, b_last = (ce + NB - 1) / NB - 1;
+  auto fetch_li = [&](int64_t bi) {
+    const int64_t jb = max(bi, b_first) * NB;
+    const int w = (int)min((int64_t)NB, k - jb);
+    int64_t ld;
+    const cpx<float> *Lc = col_ptr(P, n, jb, ld);
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
+      li[q] = Lc[(int64_t)min(j, w - 1) * ld + jb + min(l, w - 1)];
+    }
+  };
+  // L(jb + l, r) for the block's rows: column r below its own block (rows
+  // before the column's block are clamped to it: they are not stored)
+  auto fetch_lv = [&](int64_t bi) {
+    const int64_t jb = max(bi, b_first) * NB;
+    const int w = (int)min((int64_t)NB, k - jb);
+#pragma unroll
+    for (int l = 0; l < NB; ++l) lv[l] = Lr[max(jb + min(l, w - 1), r0)];
+  };
+  fetch_li(b_last);
+  fetch_lv(b_last);
+  for (int64_t bi = b_last; bi >= b_first; --bi) {
+    const int64_t jb = bi * NB;
+    const int w = (int)min((int64_t)NB, k - jb);
+    lds_barrier();   // the previous block's readers of Lo, V and Y are done
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
+      Lo[l][j] = (l < j && j < w) ? li[q] : czero<float>();
+    }
+    fetch_li(bi - 1);
+    if (own && r >= jb && r < jb + w) {
+#pragma unroll
+      for (int c = 0; c < SP; ++c) V[r - jb][c] = v[c];
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {   // rows past w of the block: zero
+      const int idx = tid + 256 * q, j = idx / SP;
+      if (j >= w) V[j][idx % SP] = czero<float>();
+    }
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int idx = tid + 256 * q, l = idx / SP, c = idx % SP;
+      cpx<float> acc = V[l][c];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc = cfma(Lo[l][j], V[j][c], acc);
+      Y[l][c] = acc;
+      if (l < w && c < S) X[(jb + l) * S + c] = acc;
+    }
+    lds_barrier();
+    if (own && r < jb) {
+#pragma unroll
+      for (int l = 0; l < NB; ++l) {
+        const cpx<float> a = l < w ? lv[l] : czero<float>();
+#pragma unroll
+        for (int c = 0; c < SP; ++c) v[c] = csub(v[c], cmul(a, Y[l][c]));
+      }
+    }
+    fetch_lv(bi - 1);
+  }
+}
+
 template <typename T>
 hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
                           cpx<T> *x, const cpx<T> *t, int64_t t_stride, int64_t cb, int64_t BB,
                           int init) {
   if (n_nodes <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
-                     factor, f_stride, x, t, t_stride, cb, BB, init);
+  // the column blocks of wide fronts (at most 256 rows, one per thread)
+  // take the register kernel; whole small fronts, many per level, keep the
+  // lighter LDS kernel
+  if (sizeof(T) == 4 && S >= 1 && S <= 16 && BB <= 256 && BB % NB == 0 && cb % NB == 0)
+    hipLaunchKernelGGL(S <= 8 ? k_bwd_tri_reg<8> : k_bwd_tri_reg<16>, dim3(n_nodes, npole),
+                       dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       reinterpret_cast<const cpx<float> *>(factor), f_stride,
+                       reinterpret_cast<cpx<float> *>(x), reinterpret_cast<const cpx<float> *>(t),
+                       t_stride, cb, BB, init);
+  else
+    hipLaunchKernelGGL(k_bwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, t, t_stride, cb, BB, init);
   return hipGetLastError();
 }
 

@@ -811,9 +811,12 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
   // Levels whose fronts are few and wide are walked in big column blocks:
   // one workgroup per front solves a BB-wide diagonal block, then many
   // workgroups apply it to the remaining rows (forward) or columns (backward).
+  // In FP32 every level wider than BB is: its triangle kernels then keep a
+  // whole block range in registers (at most 256 rows).
   const int64_t BB = c->sweep_bb;
   auto big = [&](const LevelInfo &li) {
-    return li.max_k > BB && (int64_t)li.n * npole < c->sweep_big_limit;
+    return li.max_k > BB &&
+           (sizeof(T) == 4 || (int64_t)li.n * npole < c->sweep_big_limit);
   };
   for (int L = nl - 1; L >= 0; --L) {
     const LevelInfo &li = mf.levels[L];
