@@ -177,6 +177,11 @@ struct tem_ctx {
   // valid while the factors, the vector and its shape are those captured
   bool use_graphs = true;
   hipStream_t cap_stream = nullptr;
+  // the nodal factorisation runs on its own stream beside the edge factor
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  DBuf d_ncb0, d_ncb1;                  // nodal contribution-block arenas
+  std::vector<double> h_ncoef;          // host copy of the correction coefficients
   struct SweepGraph {
     hipGraphExec_t exec = nullptr;
     const void *x = nullptr, *factor = nullptr, *ws[3] = {nullptr, nullptr, nullptr};
@@ -1385,6 +1390,21 @@ tem_status factor_nodal(tem_ctx *c) {
   c->nodal_ready = false;
   if (nd.N == 0) return TEM_OK;
   hipStream_t st = c->stream;
+  // coefficients -1/xi of the correction, one per pole slot of each mesh;
+  // uploaded first: a copy from pageable memory returns only when the
+  // stream has reached it, which must not wait for the factor launched below
+  // (the host copy is a member, so it outlives the copy in any case)
+  {
+    const size_t nco = (size_t)n_seg(c) * c->npole;
+    std::vector<double> &coef = c->h_ncoef;
+    coef.assign(2 * nco, 0.0);
+    for (size_t p = 0; p < nco; ++p) {
+      std::complex<double> v = -1.0 / std::complex<double>(c->xi[2 * p], c->xi[2 * p + 1]);
+      coef[2 * p] = v.real();
+      coef[2 * p + 1] = v.imag();
+    }
+    HIPCHK(upload(c->d_ncoef, coef, st), "upload coefficients");
+  }
   if (c->B > 0) {
     // each mesh assembles its block of the merged nodal matrix
     for (int b = 0; b < c->B; ++b) {
@@ -1407,28 +1427,18 @@ tem_status factor_nodal(tem_ctx *c) {
   }
   HIPCHK(c->d_nfactor.alloc(sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.pole_stride, 1)),
          "alloc nodal factor");
-  DBuf a0, a1;
   const size_t cbb = sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.cb_stride, 1);
-  HIPCHK(a0.alloc(cbb), "alloc nodal cb");
-  HIPCHK(a1.alloc(cbb), "alloc nodal cb");
+  HIPCHK(c->d_ncb0.alloc(cbb), "alloc nodal cb");
+  HIPCHK(c->d_ncb1.alloc(cbb), "alloc nodal cb");
   // the nodal factor is not part of the timed front-update figures
   const bool prof = c->profile;
   c->profile = false;
   tem_status fs = factor_group<double>(c, nd, c->d_nfactor.as<cpx<double>>(), c->d_nxi.as<double>(),
                                        Seg(), c->d_Ln.as<double>(), c->d_Lzero.as<double>(), 0, 1,
-                                       a0.as<cpx<double>>(), a1.as<cpx<double>>());
+                                       c->d_ncb0.as<cpx<double>>(), c->d_ncb1.as<cpx<double>>());
   c->profile = prof;
   TRY(fs);
-  // coefficients -1/xi of the correction, one per pole slot of each mesh
-  const size_t nco = (size_t)n_seg(c) * c->npole;
-  std::vector<double> coef(2 * nco);
-  for (size_t p = 0; p < nco; ++p) {
-    std::complex<double> v = -1.0 / std::complex<double>(c->xi[2 * p], c->xi[2 * p + 1]);
-    coef[2 * p] = v.real();
-    coef[2 * p + 1] = v.imag();
-  }
-  HIPCHK(upload(c->d_ncoef, coef, st), "upload coefficients");
-  HIPCHK(hipStreamSynchronize(st), "nodal factor sync");
+  // complete once st reaches this point (the caller orders later work after it)
   c->nodal_ready = true;
   return TEM_OK;
 }
@@ -1477,6 +1487,32 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
     }
   }
   HIPCHK(hipEventRecord(e0, c->stream), "event");
+  // The nodal factor (FP32 mode) does not depend on the edge factor: it
+  // runs on a second stream, joined before the factorisation ends, so its
+  // small levels fill gaps of the edge factor's.  Autotuning times the edge
+  // levels alone, with the nodal factor after them.
+  const bool nodal = prec == TEM_FP32_IR && c->aux;
+  const bool overlap = nodal && !c->lvl_timing;
+  if (overlap) {
+    if (!c->aux_stream)
+      HIPCHK(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking), "aux stream");
+    if (!c->ev_fork) HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "event");
+    if (!c->ev_join) HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "event");
+    HIPCHK(hipEventRecord(c->ev_fork, c->stream), "fork");
+    HIPCHK(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0), "fork");
+    hipStream_t main = c->stream;
+    c->stream = c->aux_stream;
+    tem_status s = factor_nodal(c);
+    c->stream = main;
+    if (s == TEM_OK && hipEventRecord(c->ev_join, c->aux_stream) != hipSuccess)
+      s = fail(c, TEM_EDEVICE, "join event");
+    if (s != TEM_OK) {
+      hipStreamSynchronize(c->aux_stream);
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return s;
+    }
+  }
   for (int p0 = 0; p0 < m; p0 += g) {
     int gg = std::min(g, m - p0);
     c->lvl_group = p0 / g;
@@ -1493,11 +1529,13 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
                                   c->d_M.as<double>(), p0, gg, c->d_cb0.as<cpx<float>>(),
                                   c->d_cb1.as<cpx<float>>());
     if (s != TEM_OK) {
+      if (overlap) hipStreamSynchronize(c->aux_stream);
       hipEventDestroy(e0);
       hipEventDestroy(e1);
       return s;
     }
   }
+  if (overlap) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join");
   {
     // keep the arenas for the next factorisation unless the solves need the room
     size_t fr = 0, tt = 0;
@@ -1506,7 +1544,7 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
       c->d_cb1.release();
     }
   }
-  if (prec == TEM_FP32_IR && c->aux) {
+  if (nodal && !overlap) {
     tem_status s = factor_nodal(c);
     if (s != TEM_OK) {
       hipEventDestroy(e0);
@@ -1750,6 +1788,9 @@ void tem_destroy(tem_ctx *c) {
   for (hipEvent_t e : c->lvl_ev) hipEventDestroy(e);
   drop_graphs(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  if (c->aux_stream) hipStreamDestroy(c->aux_stream);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   delete c;
   if (own) hipStreamDestroy(st);
 }
