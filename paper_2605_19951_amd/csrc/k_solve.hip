@@ -244,9 +244,9 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
     if (own && r >= jb + w) {
 #pragma unroll
       for (int l = 0; l < NB; ++l) {
-        const cpx<float> a = l < w ? lv[l] : czero<float>();
+        const cpx<float> a = l < w ? cpx<float>{-lv[l].re, -lv[l].im} : czero<float>();
 #pragma unroll
-        for (int c = 0; c < SP; ++c) xr[c] = csub(xr[c], cmul(a, Y[l][c]));
+        for (int c = 0; c < SP; ++c) xr[c] = cfma(a, Y[l][c], xr[c]);
       }
     }
     fetch_lv(jb + NB);
@@ -874,9 +874,9 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
     if (own && r < jb) {
 #pragma unroll
       for (int l = 0; l < NB; ++l) {
-        const cpx<float> a = l < w ? lv[l] : czero<float>();
+        const cpx<float> a = l < w ? cpx<float>{-lv[l].re, -lv[l].im} : czero<float>();
 #pragma unroll
-        for (int c = 0; c < SP; ++c) v[c] = csub(v[c], cmul(a, Y[l][c]));
+        for (int c = 0; c < SP; ++c) v[c] = cfma(a, Y[l][c], v[c]);
       }
     }
     fetch_lv(bi - 1);
