@@ -34,7 +34,19 @@
  *     pointers must be allocated on the context's device.
  *   Streams: device work is ordered on the context's stream; calls return
  *     once their results are in the caller's buffers (the library
- *     synchronises its stream before returning).
+ *     synchronises its stream before returning).  In FP32 mode the
+ *     factorisation also runs the pole-independent nodal factor on a private
+ *     stream, forked from and joined back into the context's stream within
+ *     the call.
+ *   Environment (read by tem_create; tuning and test knobs, defaults in
+ *     brackets): TEM_PANEL factor panel width, a multiple of 32 [256];
+ *     TEM_LEFT_LOOKING panels take earlier panels' updates at once [1];
+ *     TEM_UPDATE_TILE "64" | "128x64" | "128" [64]; TEM_UPDATE_3M "f32" |
+ *     "f64" | "both" | "none" [f32]; TEM_SWEEP_BLOCK column block of wide
+ *     fronts in the sweeps, a multiple of 32 [256]; TEM_SWEEP_BIG_LIMIT
+ *     fronts x poles below which an FP64 level counts as wide [1024];
+ *     TEM_GRAPHS replay the all-pole sweep from a HIP graph [1].  The
+ *     autotuner (tem_autotune) overrides the update tile per level.
  *   Errors: a negative tem_status; tem_last_error() describes it.  After an
  *     error the context keeps the last stage that completed.
  *   State machine: create -> assemble -> analyse -> factor_poles ->
