@@ -158,11 +158,11 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
 // block, and every later row of the range subtracts its L row times Y.  SP
 // (8 or 16) columns are computed for S <= SP right-hand sides, with zero
 // factors in place of branches; barriers order LDS only.
-template <int SP>
+template <typename T, int SP>
 __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t *lvl_nodes,
-                                                     int S, int64_t N, const cpx<float> *factor,
-                                                     int64_t f_stride, cpx<float> *x,
-                                                     const cpx<float> *w_child, int64_t w_stride,
+                                                     int S, int64_t N, const cpx<T> *factor,
+                                                     int64_t f_stride, cpx<T> *x,
+                                                     const cpx<T> *w_child, int64_t w_stride,
                                                      int64_t cb, int64_t BB) {
   constexpr int NT = NB * SP / 256;   // (row, column) tasks per thread in the block solve
   const int s = lvl_nodes[blockIdx.x];
@@ -171,28 +171,28 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
   const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
   if (k == 0 || cb >= k) return;
   const int64_t ce = min(k, cb + BB);
-  const cpx<float> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  cpx<float> *X = x + ((int64_t)p * N + first) * S;
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;
   const int tid = threadIdx.x;
-  if (cb == 0) fwd_child_add<float>(ft, s, p, k, S, X, w_child, w_stride, tid);
+  if (cb == 0) fwd_child_add<T>(ft, s, p, k, S, X, w_child, w_stride, tid);
   __syncthreads();
   const int nr = (int)(ce - cb);   // <= 256 (checked by the launcher)
   const bool own = tid < nr;
   const int64_t r = cb + min(tid, nr - 1);
-  cpx<float> xr[SP];
+  cpx<T> xr[SP];
 #pragma unroll
   for (int c = 0; c < SP; ++c) xr[c] = X[r * S + min(c, S - 1)];
-  __shared__ cpx<float> Lo[NB][NB + 1];
-  __shared__ cpx<float> V[NB][SP];
-  __shared__ cpx<float> Y[NB][SP];
-  cpx<float> lv[NB], li[NB * NB / 256];
+  __shared__ cpx<T> Lo[NB][NB + 1];
+  __shared__ cpx<T> V[NB][SP];
+  __shared__ cpx<T> Y[NB][SP];
+  cpx<T> lv[NB], li[NB * NB / 256];
   // inverse block of columns [jb, jb + NB): Linv[j][l] at (row jb + l,
   // column jb + j); clamped to the last block (entries past w are zeroed)
   auto fetch_li = [&](int64_t jb) {
     jb = min(jb, NB * ((k - 1) / NB));
     const int w = (int)min((int64_t)NB, k - jb);
     int64_t ld;
-    const cpx<float> *Lc = col_ptr(P, n, jb, ld);
+    const cpx<T> *Lc = col_ptr(P, n, jb, ld);
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
     jb = min(jb, NB * ((k - 1) / NB));
     const int w = (int)min((int64_t)NB, k - jb);
     int64_t ld;
-    const cpx<float> *Lc = col_ptr(P, n, jb, ld);
+    const cpx<T> *Lc = col_ptr(P, n, jb, ld);
     const int64_t rr = max(r, jb);
 #pragma unroll
     for (int l = 0; l < NB; ++l) lv[l] = Lc[(int64_t)min(l, w - 1) * ld + rr];
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
-      Lo[j][l] = (l < j && j < w) ? li[q] : czero<float>();
+      Lo[j][l] = (l < j && j < w) ? li[q] : czero<T>();
     }
     fetch_li(jb + NB);
     if (own && r >= jb && r < jb + w) {
@@ -228,13 +228,13 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
 #pragma unroll
     for (int q = 0; q < NT; ++q) {   // rows past w of the block: zero
       const int idx = tid + 256 * q, j = idx / SP;
-      if (j >= w) V[j][idx % SP] = czero<float>();
+      if (j >= w) V[j][idx % SP] = czero<T>();
     }
     lds_barrier();
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
       const int idx = tid + 256 * q, j = idx / SP, c = idx % SP;
-      cpx<float> acc = V[j][c];
+      cpx<T> acc = V[j][c];
 #pragma unroll
       for (int l = 0; l < NB; ++l) acc = cfma(Lo[j][l], V[l][c], acc);
       Y[j][c] = acc;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
     if (own && r >= jb + w) {
 #pragma unroll
       for (int l = 0; l < NB; ++l) {
-        const cpx<float> a = l < w ? cpx<float>{-lv[l].re, -lv[l].im} : czero<float>();
+        const cpx<T> a = l < w ? cpx<T>{-lv[l].re, -lv[l].im} : czero<T>();
 #pragma unroll
         for (int c = 0; c < SP; ++c) xr[c] = cfma(a, Y[l][c], xr[c]);
       }
@@ -262,12 +262,10 @@ hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
   // the column blocks of wide fronts (at most 256 rows, one per thread)
   // take the register kernel; whole small fronts, many per level, keep the
   // lighter LDS kernel
-  if (sizeof(T) == 4 && S >= 1 && S <= 16 && BB <= 256 && BB % NB == 0 && cb % NB == 0)
-    hipLaunchKernelGGL(S <= 8 ? k_fwd_tri_reg<8> : k_fwd_tri_reg<16>, dim3(n_nodes, npole),
-                       dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       reinterpret_cast<const cpx<float> *>(factor), f_stride,
-                       reinterpret_cast<cpx<float> *>(x),
-                       reinterpret_cast<const cpx<float> *>(w_child), w_stride, cb, BB);
+  if (S >= 1 && S <= 16 && BB <= 256 && BB % NB == 0 && cb % NB == 0)
+    hipLaunchKernelGGL((S <= 8 ? k_fwd_tri_reg<T, 8> : k_fwd_tri_reg<T, 16>), dim3(n_nodes, npole),
+                       dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride, x, w_child,
+                       w_stride, cb, BB);
   else
     hipLaunchKernelGGL(k_fwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
                        factor, f_stride, x, w_child, w_stride, cb, BB);
@@ -781,11 +779,11 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
 // the range subtracts sum_l L(jb + l, r) x_b[l], from its own column's
 // entries below the block, loaded one block ahead.  SP as in the forward
 // kernel.
-template <int SP>
+template <typename T, int SP>
 __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t *lvl_nodes,
-                                                     int S, int64_t N, const cpx<float> *factor,
-                                                     int64_t f_stride, cpx<float> *x,
-                                                     const cpx<float> *t, int64_t t_stride,
+                                                     int S, int64_t N, const cpx<T> *factor,
+                                                     int64_t f_stride, cpx<T> *x,
+                                                     const cpx<T> *t, int64_t t_stride,
                                                      int64_t cb, int64_t BB, int init) {
   constexpr int NT = NB * SP / 256;
   const int s = lvl_nodes[blockIdx.x];
@@ -794,19 +792,19 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
   if (k == 0 || cb >= k) return;
   const int64_t ce = min(k, cb + BB);
-  const cpx<float> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  cpx<float> *X = x + ((int64_t)p * N + first) * S;
-  const cpx<float> *Tv = t + (int64_t)p * t_stride + first * S;
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;
+  const cpx<T> *Tv = t + (int64_t)p * t_stride + first * S;
   const int tid = threadIdx.x;
   const int nr = (int)(ce - cb);   // <= 256 (checked by the launcher)
   const bool own = tid < nr;
   const int64_t r = cb + min(tid, nr - 1);
   int64_t ldr;
-  const cpx<float> *Lr = col_ptr(P, n, r, ldr);   // column r: element (i, r) at Lr[i]
+  const cpx<T> *Lr = col_ptr(P, n, r, ldr);   // column r: element (i, r) at Lr[i]
   const int64_t r0 = NB * (r / NB);
-  cpx<float> v[SP];
+  cpx<T> v[SP];
   {
-    const cpx<float> dinv = init ? cinv(Lr[r]) : cpx<float>{1.f, 0.f};
+    const cpx<T> dinv = init ? cinv(Lr[r]) : cpx<T>{T(1), T(0)};
     const bool tt = init && u > 0;
 #pragma unroll
     for (int c = 0; c < SP; ++c) {
@@ -815,16 +813,16 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
       if (tt) v[c] = csub(v[c], Tv[id]);
     }
   }
-  __shared__ cpx<float> Lo[NB][NB + 1];   // Lo[l][j] = Linv[j][l] for l < j < w
-  __shared__ cpx<float> V[NB][SP];
-  __shared__ cpx<float> Y[NB][SP];
-  cpx<float> lv[NB], li[NB * NB / 256];
+  __shared__ cpx<T> Lo[NB][NB + 1];   // Lo[l][j] = Linv[j][l] for l < j < w
+  __shared__ cpx<T> V[NB][SP];
+  __shared__ cpx<T> Y[NB][SP];
+  cpx<T> lv[NB], li[NB * NB / 256];
   const int64_t b_first = cb / NB, b_last = (ce + NB - 1) / NB - 1;
   auto fetch_li = [&](int64_t bi) {
     const int64_t jb = max(bi, b_first) * NB;
     const int w = (int)min((int64_t)NB, k - jb);
     int64_t ld;
-    const cpx<float> *Lc = col_ptr(P, n, jb, ld);
+    const cpx<T> *Lc = col_ptr(P, n, jb, ld);
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
@@ -848,7 +846,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
-      Lo[l][j] = (l < j && j < w) ? li[q] : czero<float>();
+      Lo[l][j] = (l < j && j < w) ? li[q] : czero<T>();
     }
     fetch_li(bi - 1);
     if (own && r >= jb && r < jb + w) {
@@ -858,13 +856,13 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
 #pragma unroll
     for (int q = 0; q < NT; ++q) {   // rows past w of the block: zero
       const int idx = tid + 256 * q, j = idx / SP;
-      if (j >= w) V[j][idx % SP] = czero<float>();
+      if (j >= w) V[j][idx % SP] = czero<T>();
     }
     lds_barrier();
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
       const int idx = tid + 256 * q, l = idx / SP, c = idx % SP;
-      cpx<float> acc = V[l][c];
+      cpx<T> acc = V[l][c];
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc = cfma(Lo[l][j], V[j][c], acc);
       Y[l][c] = acc;
@@ -874,7 +872,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
     if (own && r < jb) {
 #pragma unroll
       for (int l = 0; l < NB; ++l) {
-        const cpx<float> a = l < w ? cpx<float>{-lv[l].re, -lv[l].im} : czero<float>();
+        const cpx<T> a = l < w ? cpx<T>{-lv[l].re, -lv[l].im} : czero<T>();
 #pragma unroll
         for (int c = 0; c < SP; ++c) v[c] = cfma(a, Y[l][c], v[c]);
       }
@@ -892,12 +890,10 @@ hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
   // the column blocks of wide fronts (at most 256 rows, one per thread)
   // take the register kernel; whole small fronts, many per level, keep the
   // lighter LDS kernel
-  if (sizeof(T) == 4 && S >= 1 && S <= 16 && BB <= 256 && BB % NB == 0 && cb % NB == 0)
-    hipLaunchKernelGGL(S <= 8 ? k_bwd_tri_reg<8> : k_bwd_tri_reg<16>, dim3(n_nodes, npole),
-                       dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       reinterpret_cast<const cpx<float> *>(factor), f_stride,
-                       reinterpret_cast<cpx<float> *>(x), reinterpret_cast<const cpx<float> *>(t),
-                       t_stride, cb, BB, init);
+  if (S >= 1 && S <= 16 && BB <= 256 && BB % NB == 0 && cb % NB == 0)
+    hipLaunchKernelGGL((S <= 8 ? k_bwd_tri_reg<T, 8> : k_bwd_tri_reg<T, 16>), dim3(n_nodes, npole),
+                       dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride, x, t, t_stride,
+                       cb, BB, init);
   else
     hipLaunchKernelGGL(k_bwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
                        factor, f_stride, x, t, t_stride, cb, BB, init);
