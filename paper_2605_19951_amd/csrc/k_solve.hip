@@ -337,104 +337,50 @@ hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 
 // ------------------------------------------------------------ forward rect
 // W_s[a] = child updates at front row k+a  -  sum_j L(k+a, j) y_j
-// Each thread owns one update row a of the front (256 rows per workgroup)
-// and all right-hand sides: W[a] = (children's rows) - sum_l L(k + a, l) y_l.
-// The panel row is read straight from HBM, one column block (FR columns)
-// of loads in flight per thread; y is staged in LDS and read by broadcast.
-template <typename T>
-struct FwdRectCfg {
-  static constexpr int FR = 32;   // columns loaded ahead per thread
-};
-template <>
-struct FwdRectCfg<double> {
-  static constexpr int FR = 16;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_rect(FrontTab ft, const int32_t *lvl_nodes, int S,
-                                                  int64_t N, const cpx<T> *factor,
-                                                  int64_t f_stride, const cpx<T> *x,
-                                                  const cpx<T> *w_child, cpx<T> *w_out,
-                                                  int64_t w_stride) {
-  constexpr int FR = FwdRectCfg<T>::FR;
-  const int s = lvl_nodes[blockIdx.y];
-  const int p = blockIdx.z;
-  if (pole_absent(ft, s, p)) return;
-  const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
-  const int64_t a0 = (int64_t)blockIdx.x * 256;
-  if (a0 >= u) return;
-  const int tid = threadIdx.x;
-  const int64_t a = a0 + tid, ac = min(a, u - 1);
-  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  const cpx<T> *X = x + ((int64_t)p * N + first) * S;
-  // the children's update rows for row a
-  const int c0 = ft.child0[s], c1 = ft.child1[s];
-  const bool h0 = c0 >= 0 && ft.u[c0] > 0, h1 = c1 >= 0 && ft.u[c1] > 0;
-  const int g0 = h0 ? ft.gmap0[ft.gmap_off[s] + k + ac] : -1;
-  const int g1 = h1 ? ft.gmap1[ft.gmap_off[s] + k + ac] : -1;
-  const cpx<T> *W0 = h0 ? w_child + (int64_t)p * w_stride + (ft.w_off[c0] + max(g0, 0)) * S
-                        : nullptr;
-  const cpx<T> *W1 = h1 ? w_child + (int64_t)p * w_stride + (ft.w_off[c1] + max(g1, 0)) * S
-                        : nullptr;
-  cpx<T> acc[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    acc[c] = czero<T>();
-    if (c < S) {
-      if (g0 >= 0) acc[c] = cadd(acc[c], W0[c]);
-      if (g1 >= 0) acc[c] = cadd(acc[c], W1[c]);
-    }
-  }
-  __shared__ cpx<T> Y[FR][16];
-  for (int64_t jb = 0; jb < k; jb += FR) {
-    const int w = (int)min((int64_t)FR, k - jb);
-    // FR consecutive columns lie in one NB-column block of the panel;
-    // column jb + l is at Lc + l * ld
-    int64_t ld;
-    const cpx<T> *Lc = col_ptr(P, n, jb, ld);
-    cpx<T> lv[FR];
-#pragma unroll
-    for (int l = 0; l < FR; ++l) lv[l] = Lc[(int64_t)min(l, w - 1) * ld + k + ac];
-    __syncthreads();
-    for (int idx = tid; idx < w * S; idx += 256) Y[idx / S][idx % S] = X[jb * S + idx];
-    __syncthreads();
-#pragma unroll
-    for (int l = 0; l < FR; ++l) {
-      if (l < w) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-          if (c < S) acc[c] = csub(acc[c], cmul(lv[l], Y[l][c]));
-      }
-    }
-  }
-  if (a < u) {
-    cpx<T> *Wo = w_out + (int64_t)p * w_stride + (ft.w_off[s] + a) * S;
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (c < S) Wo[c] = acc[c];
-  }
-}
-
-// FP32 forward rect on the matrix cores: per front the update rows are
+// Forward rect on the matrix cores: per front the update rows are
 // W = (children's rows) - L21 Y, a product with few columns (the right-hand
-// sides).  v_mfma_f32_16x16x4f32 multiplies 16 rows of L21 by four columns
-// at a time; its 16 output columns hold Re y and Im y of eight right-hand
-// sides, so Lr B and Li B (B = [Re Y | Im Y]) give all four real products
-// of the complex one: Re(L y) = Lr Re y - Li Im y, Im(L y) = Lr Im y +
-// Li Re y.  Operand lane l carries row (or output column) l % 16 and depth
-// l / 16; result element i of lane l is row 4 (l / 16) + i, column l % 16.
-// Each wave owns 32 rows and walks all k columns on its own (no LDS, no
-// barriers), 32 columns at a time, loading the next chunk while the
-// current one is multiplied.
+// sides).  A 16 x 16 x 4 MFMA (f32 or f64) multiplies 16 rows of L21 by four
+// columns at a time; its 16 output columns hold Re y and Im y of eight
+// right-hand sides, so Lr B and Li B (B = [Re Y | Im Y]) give all four real
+// products of the complex one: Re(L y) = Lr Re y - Li Im y, Im(L y) =
+// Lr Im y + Li Re y.  Operand lane l carries row (or output column) l % 16
+// and depth l / 16.  Each wave owns 32 rows and walks all k columns on its
+// own (no LDS, no barriers), a chunk of columns at a time (32 in FP32, 16 in
+// FP64), loading the next chunk while the current one is multiplied.
 // NBK = 1 for S <= 8 right-hand sides, 2 for S <= 16.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-template <int NBK>
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+// 16 x 16 x 4 products: FP32 result element i of lane l is row 4 (l / 16) + i,
+// FP64 row l / 16 + 4 i (column l % 16 for both); operands as above
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<float> {
+  using acc_t = floatx4;
+  static constexpr int KC = 32;   // columns per chunk
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int ld4, int i) { return 4 * ld4 + i; }
+};
+template <>
+struct Mfma16<double> {
+  using acc_t = doublex4;
+  static constexpr int KC = 16;
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int ld4, int i) { return ld4 + 4 * i; }
+};
+template <typename T, int NBK>
 __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
-                                                       int S, int64_t N, const cpx<float> *factor,
-                                                       int64_t f_stride, const cpx<float> *x,
-                                                       const cpx<float> *w_child,
-                                                       cpx<float> *w_out, int64_t w_stride) {
-  constexpr int RB = 2, KC = 32;   // 16-row blocks per wave, columns per chunk
+                                                       int S, int64_t N, const cpx<T> *factor,
+                                                       int64_t f_stride, const cpx<T> *x,
+                                                       const cpx<T> *w_child,
+                                                       cpx<T> *w_out, int64_t w_stride) {
+  using MF = Mfma16<T>;
+  using acc_t = typename MF::acc_t;
+  constexpr int RB = 2, KC = MF::KC;   // 16-row blocks per wave, columns per chunk
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
   if (pole_absent(ft, s, p)) return;
@@ -443,8 +389,8 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t aw = (int64_t)blockIdx.x * 128 + wave * 32;   // first row of the wave
   if (aw >= u) return;
-  const cpx<float> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  const cpx<float> *X = x + ((int64_t)p * N + first) * S;
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  const cpx<T> *X = x + ((int64_t)p * N + first) * S;
   const int lr = lane & 15, ld4 = lane >> 4;   // operand row / output column, depth
   // rows of the two blocks (clamped; rows past u reach no output)
   int32_t rrow[RB];
@@ -459,23 +405,23 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
     yon[nb] = j < S;
     yj[nb] = 2 * min(j, S - 1) + (lr >> 3);   // float index inside a row of X
   }
-  floatx4 r1[RB][NBK], r2[RB][NBK];
+  acc_t r1[RB][NBK], r2[RB][NBK];
 #pragma unroll
   for (int b = 0; b < RB; ++b)
 #pragma unroll
     for (int nb = 0; nb < NBK; ++nb) {
-      r1[b][nb] = floatx4{0, 0, 0, 0};
-      r2[b][nb] = floatx4{0, 0, 0, 0};
+      r1[b][nb] = acc_t{0, 0, 0, 0};
+      r2[b][nb] = acc_t{0, 0, 0, 0};
     }
-  const float *Xf = reinterpret_cast<const float *>(X);
+  const T *Xf = reinterpret_cast<const T *>(X);
   // chunk jb into (lv, yv): unconditional loads from clamped addresses (a
   // chunk past the end re-reads the last one and gets y = 0)
   const int64_t jlast = ((k - 1) / KC) * KC;
-  auto load = [&](int64_t jb, cpx<float> (&lv)[KC / 4][RB], float (&yv)[KC / 4][NBK]) {
+  auto load = [&](int64_t jb, cpx<T> (&lv)[KC / 4][RB], T (&yv)[KC / 4][NBK]) {
     const int64_t je = min(jb, jlast);
     int64_t ld;
-    const cpx<float> *Lc = col_ptr(P, n, je, ld);   // the chunk lies in one column block
-    const float *Xc = Xf + je * 2 * S;
+    const cpx<T> *Lc = col_ptr(P, n, je, ld);   // the chunk lies in one column block
+    const T *Xc = Xf + je * 2 * S;
     // 32-bit offsets inside the chunk: column offset <= 31, ld and 2 S below 2^24
     const int32_t lim = (int32_t)(k - 1 - je), ldi = (int32_t)ld, colk = (int32_t)(k - jb);
 #pragma unroll
@@ -487,24 +433,24 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
       const int32_t yo = (int32_t)__umul24((uint32_t)o, (uint32_t)(2 * S));
 #pragma unroll
       for (int nb = 0; nb < NBK; ++nb)   // a multiply, not a select: the load stays unconditional
-        yv[q][nb] = Xc[yo + yj[nb]] * ((t < colk && yon[nb]) ? 1.f : 0.f);
+        yv[q][nb] = Xc[yo + yj[nb]] * ((t < colk && yon[nb]) ? T(1) : T(0));
     }
   };
-  auto mma = [&](const cpx<float> (&lv)[KC / 4][RB], const float (&yv)[KC / 4][NBK]) {
+  auto mma = [&](const cpx<T> (&lv)[KC / 4][RB], const T (&yv)[KC / 4][NBK]) {
 #pragma unroll
     for (int q = 0; q < KC / 4; ++q)
 #pragma unroll
       for (int b = 0; b < RB; ++b)
 #pragma unroll
         for (int nb = 0; nb < NBK; ++nb) {
-          r1[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(lv[q][b].re, yv[q][nb], r1[b][nb], 0, 0, 0);
-          r2[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(lv[q][b].im, yv[q][nb], r2[b][nb], 0, 0, 0);
+          r1[b][nb] = MF::mma(lv[q][b].re, yv[q][nb], r1[b][nb]);
+          r2[b][nb] = MF::mma(lv[q][b].im, yv[q][nb], r2[b][nb]);
         }
   };
   // two register sets: the loads of the next chunk are in flight while the
   // current one is multiplied
-  cpx<float> la[KC / 4][RB], lb[KC / 4][RB];
-  float ya[KC / 4][NBK], yb[KC / 4][NBK];
+  cpx<T> la[KC / 4][RB], lb[KC / 4][RB];
+  T ya[KC / 4][NBK], yb[KC / 4][NBK];
   load(0, la, ya);
   for (int64_t jb = 0; jb < k; jb += 2 * KC) {
     load(jb + KC, lb, yb);
@@ -523,11 +469,11 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
     for (int nb = 0; nb < NBK; ++nb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float o1 = __shfl_xor(r1[b][nb][i], 8), o2 = __shfl_xor(r2[b][nb][i], 8);
-        const int64_t a = aw + b * 16 + 4 * ld4 + i;
+        const T o1 = __shfl_xor(r1[b][nb][i], 8), o2 = __shfl_xor(r2[b][nb][i], 8);
+        const int64_t a = aw + b * 16 + MF::row(ld4, i);
         const int j = 8 * nb + lr;
         if (lr >= 8 || j >= S || a >= u) continue;
-        cpx<float> v = {-(r1[b][nb][i] - o2), -(o1 + r2[b][nb][i])};
+        cpx<T> v = {-(r1[b][nb][i] - o2), -(o1 + r2[b][nb][i])};
         if (h0) {
           const int g = ft.gmap0[ft.gmap_off[s] + k + a];
           if (g >= 0) v = cadd(v, w_child[(int64_t)p * w_stride + (ft.w_off[c0] + g) * S + j]);
@@ -546,20 +492,14 @@ hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
                            int64_t f_stride, const cpx<T> *x, const cpx<T> *w_child,
                            cpx<T> *w_out, int64_t w_stride) {
   if (n_nodes <= 0 || max_u <= 0) return hipSuccess;
-  if constexpr (sizeof(T) == 4) {
-    if (S < 1 || S > 16) return hipErrorInvalidValue;
-    dim3 grid((max_u + 127) / 128, n_nodes, npole);
-    if (S <= 8)
-      hipLaunchKernelGGL(k_fwd_rect_mfma<1>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor,
-                         f_stride, x, w_child, w_out, w_stride);
-    else
-      hipLaunchKernelGGL(k_fwd_rect_mfma<2>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor,
-                         f_stride, x, w_child, w_out, w_stride);
-  } else {
-    dim3 grid((max_u + 255) / 256, n_nodes, npole);
-    hipLaunchKernelGGL(k_fwd_rect<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor,
-                       f_stride, x, w_child, w_out, w_stride);
-  }
+  if (S < 1 || S > 16) return hipErrorInvalidValue;
+  dim3 grid((max_u + 127) / 128, n_nodes, npole);
+  if (S <= 8)
+    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, w_child, w_out, w_stride);
+  else
+    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, w_child, w_out, w_stride);
   return hipGetLastError();
 }
 
