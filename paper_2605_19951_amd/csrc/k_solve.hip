@@ -505,11 +505,24 @@ hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 
 // ----------------------------------------------------------- backward rect
 // t[first + jb + l] = sum_a L(k + a, jb + l) x[U_s[a]] for one column block
-template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lvl_nodes, int S,
-                                                  int64_t N, const cpx<T> *factor,
-                                                  int64_t f_stride, const cpx<T> *x, cpx<T> *t,
-                                                  int64_t t_stride) {
+// On the matrix cores: the 64-row tiles of the panel and the gathered x
+// rows are staged through LDS (coalesced loads from clamped positions,
+// prefetched into registers one tile ahead, masked when written); the
+// products are 16 x 16 x 4 MFMAs whose rows are the block's columns and
+// whose 16 result columns hold Re x and Im x of eight right-hand sides (as
+// in the forward rect).  Wave w takes columns 16 (w % 2) .. + 15 and rows
+// 32 (w / 2) .. + 31 of every tile; the two row halves are summed through
+// LDS at the end.  x rows past the tile are staged as zeros (a zero panel
+// entry times stale LDS could be NaN).  With the reduction running down the
+// column-major panel, MFMA operands loaded straight from HBM would span 16
+// columns x 4 rows per instruction (a quarter of each cache line used).
+template <typename T, int NBK>
+__global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
+                                                       int S, int64_t N, const cpx<T> *factor,
+                                                       int64_t f_stride, const cpx<T> *x,
+                                                       cpx<T> *t, int64_t t_stride) {
+  using MF = Mfma16<T>;
+  using acc_t = typename MF::acc_t;
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
   if (pole_absent(ft, s, p)) return;
@@ -520,28 +533,23 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
   const cpx<T> *Xp = x + (int64_t)p * N * S;
   const int32_t *rows = ft.rows + ft.rows_off[s];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int mb = wave & 1, rh = wave >> 1;
+  const int lr = lane & 15, ld4 = lane >> 4;
   int64_t ld;
   const cpx<T> *Lc = col_ptr(P, n, jb, ld);
-  __shared__ cpx<T> Lt[NB][RT + 1];
+  __shared__ cpx<T> Lt[NB][RT + 1];   // Lt[l][i] = L(k + ac + i, jb + l)
   __shared__ cpx<T> Xs[RT * 16 + 1];   // x rows [RT][16] and one sink slot
   cpx<T>(*Xt)[16] = reinterpret_cast<cpx<T>(*)[16]>(Xs);
-  // register blocking: a thread owns LB columns x CBK right-hand sides of
-  // the block's outputs over the rows i = grp, grp + ngrp, ... of each tile
-  constexpr int LB = 4;
-  const int CBK = (S % 2 == 0) ? 2 : 1;
-  const int nlb = NB / LB, nblk = nlb * (S / CBK), ngrp = 256 / nblk;
-  const int blk = tid % nblk, grp = tid / nblk;
-  const bool live = grp < ngrp;
-  const int l0 = (blk % nlb) * LB, cb0 = (blk / nlb) * CBK;
-  cpx<T> acc[LB][2];
+  acc_t r1[NBK], r2[NBK];
 #pragma unroll
-  for (int j = 0; j < LB; ++j) acc[j][0] = acc[j][1] = czero<T>();
+  for (int nb = 0; nb < NBK; ++nb) {
+    r1[nb] = acc_t{0, 0, 0, 0};
+    r2[nb] = acc_t{0, 0, 0, 0};
+  }
   // register prefetch of the next 64-row tile: 8 panel elements and up to
-  // 4 x-values per thread (loads from clamped in-bounds positions; masking
-  // happens in LDS)
-  // (the four x values are separate variables: as an array the FP64
-  // instance was kept in scratch memory)
+  // 4 x values per thread (clamped in-bounds positions; masked in LDS)
   cpx<T> pre[8], px0, px1, px2, px3;
   auto xval = [&](int q, int64_t ac, int na) -> cpx<T> {
     const int idx = tid + 256 * q;
@@ -563,55 +571,65 @@ __global__ __launch_bounds__(256) void k_bwd_rect(FrontTab ft, const int32_t *lv
   if (u > 0) fetch(0);
   for (int64_t ac = 0; ac < u; ac += RT) {
     const int na = (int)min((int64_t)RT, u - ac);
-    __syncthreads();
+    lds_barrier();   // the previous tile's readers are done
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int idx = tid + 256 * q;
       const bool ok = idx % RT < na && idx / RT < w;
       Lt[idx / RT][idx % RT] = ok ? pre[q] : czero<T>();
     }
-    // unconditional stores: slots past na rows go to the sink
+    // x rows: values of rows < na, zeros for the rows past na (right-hand
+    // sides past S are never written: they only reach discarded outputs)
     auto xput = [&](int q, cpx<T> v) {
       const int idx = tid + 256 * q;
-      Xs[idx < na * S ? (idx / S) * 16 + idx % S : RT * 16] = v;
+      const int i = idx / S;
+      Xs[idx < RT * S ? i * 16 + idx % S : RT * 16] = i < na ? v : czero<T>();
     };
     xput(0, px0);
     xput(1, px1);
     xput(2, px2);
     xput(3, px3);
-    __syncthreads();
+    lds_barrier();
     if (ac + RT < u) fetch(ac + RT);
-    if (live) {
-      for (int i = grp; i < na; i += ngrp) {
-        const cpx<T> x0 = Xt[i][cb0], x1 = Xt[i][cb0 + CBK - 1];
 #pragma unroll
-        for (int j = 0; j < LB; ++j) {
-          const cpx<T> lv = Lt[l0 + j][i];
-          acc[j][0] = cfma(lv, x0, acc[j][0]);
-          acc[j][1] = cfma(lv, x1, acc[j][1]);
-        }
+    for (int q = 0; q < 8; ++q) {
+      const int i = rh * 32 + 4 * q + ld4;
+      const cpx<T> a = Lt[mb * 16 + lr][i];
+#pragma unroll
+      for (int nb = 0; nb < NBK; ++nb) {
+        const cpx<T> xv = Xt[i][8 * nb + (lr & 7)];
+        const T b = lr < 8 ? xv.re : xv.im;
+        r1[nb] = MF::mma(a.re, b, r1[nb]);
+        r2[nb] = MF::mma(a.im, b, r2[nb]);
       }
     }
   }
-  // sum the row groups' partials in a fixed order (LDS reused)
-  __syncthreads();
-  cpx<T> *red = &Lt[0][0];   // [grp][blk][LB][CBK], 256 * LB * 2 <= NB * (RT + 1) entries
-  if (live) {
+  // sum the row halves: waves 2, 3 hand theirs to waves 0, 1 through LDS
+  lds_barrier();
+  T *red = reinterpret_cast<T *>(&Lt[0][0]);   // [mb][nb][r1/r2][4][64]
+  if (rh == 1) {
 #pragma unroll
-    for (int j = 0; j < LB; ++j)
+    for (int nb = 0; nb < NBK; ++nb)
 #pragma unroll
-      for (int cc = 0; cc < 2; ++cc)
-        if (cc < CBK) red[((grp * nblk + blk) * LB + j) * CBK + cc] = acc[j][cc];
+      for (int i = 0; i < 4; ++i) {
+        red[(((mb * NBK + nb) * 2 + 0) * 4 + i) * 64 + lane] = r1[nb][i];
+        red[(((mb * NBK + nb) * 2 + 1) * 4 + i) * 64 + lane] = r2[nb][i];
+      }
   }
-  __syncthreads();
+  lds_barrier();
+  if (rh == 1) return;
   cpx<T> *To = t + (int64_t)p * t_stride + (first + jb) * S;
-  for (int idx = tid; idx < w * S; idx += 256) {
-    const int l = idx / S, c = idx % S;
-    const int b = (l / LB) + nlb * (c / CBK), j = l % LB, cc = c % CBK;
-    cpx<T> v = czero<T>();
-    for (int g = 0; g < ngrp; ++g) v = cadd(v, red[((g * nblk + b) * LB + j) * CBK + cc]);
-    To[idx] = v;
-  }
+#pragma unroll
+  for (int nb = 0; nb < NBK; ++nb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const T a1 = r1[nb][i] + red[(((mb * NBK + nb) * 2 + 0) * 4 + i) * 64 + lane];
+      const T a2 = r2[nb][i] + red[(((mb * NBK + nb) * 2 + 1) * 4 + i) * 64 + lane];
+      const T o1 = __shfl_xor(a1, 8), o2 = __shfl_xor(a2, 8);
+      const int m = mb * 16 + MF::row(ld4, i), j = 8 * nb + lr;
+      if (lr >= 8 || j >= S || m >= w) continue;
+      To[m * S + j] = {a1 - o2, o1 + a2};
+    }
 }
 
 template <typename T>
@@ -619,9 +637,14 @@ hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
                            int max_k, int npole, int S, int64_t N, const cpx<T> *factor,
                            int64_t f_stride, const cpx<T> *x, cpx<T> *t, int64_t t_stride) {
   if (n_nodes <= 0 || max_k <= 0) return hipSuccess;
+  if (S < 1 || S > 16) return hipErrorInvalidValue;
   dim3 grid((max_k + NB - 1) / NB, n_nodes, npole);
-  hipLaunchKernelGGL(k_bwd_rect<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
-                     x, t, t_stride);
+  if (S <= 8)
+    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, t, t_stride);
+  else
+    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, t, t_stride);
   return hipGetLastError();
 }
 
