@@ -73,14 +73,10 @@ hipError_t launch_assemble_KM(hipStream_t st, int64_t N, const int64_t *rowptr, 
 }
 
 // ------------------------------------------------------ shifted products
-// One thread per (row, rhs, group of RG poles): the row's K, M entries and
-// column indices are loaded once and applied to RG poles; x, y, r are
-// [pole][N][S], threads ordered rhs fastest, then row, then pole group, so
-// that the K, M entries are read once per RG poles.  Workgroups are handed
-// to the eight XCDs round robin; block b works on block (b % 8) * chunk +
-// b / 8, so each XCD walks a contiguous eighth of the rows and the rows of
-// x that neighbouring rows share stay in its L2.
-constexpr int RG = 4;
+// x, y, r are [pole][N][S].  Workgroups are handed to the eight XCDs round
+// robin; block b works on block (b % 8) * chunk + b / 8, so each XCD walks a
+// contiguous eighth of the rows and the rows of x that neighbouring rows
+// share stay in its L2.
 
 __device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
   const int64_t chunk = (nblk + 7) / 8;
@@ -91,50 +87,46 @@ inline unsigned xcd_grid(int64_t tot, int block) {
   return (unsigned)(8 * ((nblk + 7) / 8));
 }
 
-__global__ void k_residual(int64_t N, int npole, int S, const int64_t *rowptr,
-                           const int32_t *col, const double *Kv, const double *Mv,
-                           const double *xi, Seg sg, const double *f_real,
-                           const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r,
-                           int mode) {
-  const int ng = (npole + RG - 1) / RG;
-  const int64_t tot = N * S * ng;
-  const int64_t idx = xcd_block((tot + 255) / 256) * 256 + threadIdx.x;
-  if (idx >= tot) return;
-  const int c = (int)(idx % S);
-  const int64_t q = (idx / S) % N;
-  const int g = (int)(idx / ((int64_t)S * N));
+// r = f - (K - xi_p M) x (mode 1) or y = (K - xi_p M) x (mode 0) for every
+// pole slot p and right-hand side, FP64.  One wave per row: the row's
+// entries and columns are wave-uniform (scalar loads, read once for all
+// poles) and the lanes take (right-hand side, pole) pairs, 64 / S poles at
+// a time; consecutive waves take consecutive rows and each XCD a contiguous
+// eighth of them, so that the x rows a row gathers are shared in cache by
+// its neighbours for all poles at once.
+__global__ __launch_bounds__(256) void k_residual(int64_t N, int npole, int S,
+                                                  const int64_t *rowptr, const int32_t *col,
+                                                  const double *Kv, const double *Mv,
+                                                  const double *xi, Seg sg, const double *f_real,
+                                                  const cpx<double> *f_cplx,
+                                                  const cpx<double> *x, cpx<double> *r, int mode) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t q = xcd_block((N + 3) / 4) * 4 + wv;
+  if (q >= N) return;
+  const int slots = 64 / S, c = lane % S, ps = lane / S;
   const int64_t xb = 2 * (int64_t)seg_find(sg, q) * sg.stride;
-  double xr[RG], xim[RG], ar[RG], ai[RG];
-  const cpx<double> *X[RG];
-#pragma unroll
-  for (int j = 0; j < RG; ++j) {
-    const int p = min(g * RG + j, npole - 1);
-    xr[j] = xi[xb + 2 * p];
-    xim[j] = xi[xb + 2 * p + 1];
-    X[j] = x + (int64_t)p * N * S + c;
-    ar[j] = 0.0;
-    ai[j] = 0.0;
-  }
-  for (int64_t t = rowptr[q]; t < rowptr[q + 1]; ++t) {
-    const double kv = Kv[t], mv = Mv[t];
-    const int64_t o = (int64_t)col[t] * S;
-#pragma unroll
-    for (int j = 0; j < RG; ++j) {
-      const cpx<double> v = X[j][o];
+  const int64_t t0 = rowptr[q], t1 = rowptr[q + 1];
+  for (int p0 = 0; p0 < npole; p0 += slots) {
+    const int p = p0 + ps;
+    const int pc = min(p, npole - 1);
+    const double xr = xi[xb + 2 * pc], xim = xi[xb + 2 * pc + 1];
+    const cpx<double> *X = x + (int64_t)pc * N * S + c;
+    double ar = 0.0, ai = 0.0;
+#pragma unroll 4
+    for (int64_t t = t0; t < t1; ++t) {
+      const double kv = Kv[t], mv = Mv[t];
+      const cpx<double> v = X[(int64_t)col[t] * S];
       // (K - xi M) v, xi M v = (xr + i xim) mv v
-      const double sr = kv - xr[j] * mv, si = -xim[j] * mv;
-      ar[j] += sr * v.re - si * v.im;
-      ai[j] += sr * v.im + si * v.re;
+      const double sr = kv - xr * mv, si = -xim * mv;
+      ar += sr * v.re - si * v.im;
+      ai += sr * v.im + si * v.re;
     }
-  }
-#pragma unroll
-  for (int j = 0; j < RG; ++j) {
-    const int p = g * RG + j;
-    if (p >= npole) break;
+    if (ps >= slots || p >= npole) continue;
     cpx<double> out;
     if (mode == 0) {
-      out.re = ar[j];
-      out.im = ai[j];
+      out.re = ar;
+      out.im = ai;
     } else {
       double fr = 0.0, fi = 0.0;
       if (f_cplx) {
@@ -144,8 +136,8 @@ __global__ void k_residual(int64_t N, int npole, int S, const int64_t *rowptr,
       } else if (f_real) {
         fr = f_real[q * S + c];
       }
-      out.re = fr - ar[j];
-      out.im = fi - ai[j];
+      out.re = fr - ar;
+      out.im = fi - ai;
     }
     r[((int64_t)p * N + q) * S + c] = out;
   }
@@ -155,20 +147,18 @@ hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const in
                            const int32_t *col, const double *Kv, const double *Mv,
                            const double *xi, Seg sg, const double *f_real,
                            const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r) {
-  const int64_t tot = N * S * ((npole + RG - 1) / RG);
-  if (tot <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(tot, 256)), dim3(256), 0, st, N, npole, S, rowptr,
-                     col, Kv, Mv, xi, sg, f_real, f_cplx, x, r, 1);
+  if (N <= 0 || npole <= 0 || S < 1 || S > 64) return N <= 0 || npole <= 0 ? hipSuccess : hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(N * 64, 256)), dim3(256), 0, st, N, npole, S,
+                     rowptr, col, Kv, Mv, xi, sg, f_real, f_cplx, x, r, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                                const int32_t *col, const double *Kv, const double *Mv,
                                const double *xi, Seg sg, const cpx<double> *x, cpx<double> *y) {
-  const int64_t tot = N * S * ((npole + RG - 1) / RG);
-  if (tot <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(tot, 256)), dim3(256), 0, st, N, npole, S, rowptr,
-                     col, Kv, Mv, xi, sg, nullptr, nullptr, x, y, 0);
+  if (N <= 0 || npole <= 0 || S < 1 || S > 64) return N <= 0 || npole <= 0 ? hipSuccess : hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(N * 64, 256)), dim3(256), 0, st, N, npole, S,
+                     rowptr, col, Kv, Mv, xi, sg, nullptr, nullptr, x, y, 0);
   return hipGetLastError();
 }
 
