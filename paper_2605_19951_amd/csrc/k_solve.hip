@@ -272,69 +272,6 @@ hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
   return hipGetLastError();
 }
 
-// ------------------------------------------------------- forward rows
-// X[r] -= sum_{j in [cb, ce)} L(r, j) y_j for L11 rows r in [ce, k)
-template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_rows(FrontTab ft, const int32_t *lvl_nodes, int S,
-                                                  int64_t N, const cpx<T> *factor,
-                                                  int64_t f_stride, cpx<T> *x, int64_t cb,
-                                                  int64_t BB) {
-  const int s = lvl_nodes[blockIdx.y];
-  const int p = blockIdx.z;
-  if (pole_absent(ft, s, p)) return;
-  const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
-  const int64_t ce = min(k, cb + BB);
-  const int64_t a0 = ce + (int64_t)blockIdx.x * RT;
-  if (cb >= k || a0 >= k) return;
-  const int na = (int)min((int64_t)RT, k - a0);
-  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  cpx<T> *X = x + ((int64_t)p * N + first) * S;
-  const int tid = threadIdx.x;
-  cpx<T> acc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = czero<T>();
-  __shared__ cpx<T> Lt[NB][RT + 1];
-  __shared__ cpx<T> Y[NB][16];
-  for (int64_t jb = cb; jb < ce; jb += NB) {
-    const int w = (int)min((int64_t)NB, k - jb);
-    int64_t ld;
-    const cpx<T> *Lc = col_ptr(P, n, jb, ld);
-    __syncthreads();
-    stage_tile<T, RT>(Lt, Lc, ld, a0, na, w, tid);
-    for (int idx = tid; idx < w * S; idx += blockDim.x) Y[idx / S][idx % S] = X[jb * S + idx];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q;
-      if (idx < na * S) {
-        const int i = idx / S, c = idx % S;
-        cpx<T> sacc = acc[q];
-        for (int l = 0; l < w; ++l) sacc = cfma(Lt[l][i], Y[l][c], sacc);
-        acc[q] = sacc;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = tid + 256 * q;
-    if (idx < na * S) {
-      cpx<T> *o = X + a0 * S + idx;
-      *o = csub(*o, acc[q]);
-    }
-  }
-}
-
-template <typename T>
-hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                           int max_rows, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB) {
-  if (n_nodes <= 0 || max_rows <= 0) return hipSuccess;
-  dim3 grid((max_rows + RT - 1) / RT, n_nodes, npole);
-  hipLaunchKernelGGL(k_fwd_rows<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
-                     x, cb, BB);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------ forward rect
 // W_s[a] = child updates at front row k+a  -  sum_j L(k+a, j) y_j
 // Forward rect on the matrix cores: per front the update rows are
@@ -372,12 +309,16 @@ struct Mfma16<double> {
   }
   __device__ static int row(int ld4, int i) { return ld4 + 4 * i; }
 };
-template <typename T, int NBK>
+// ROWS = true is the same product for the pivot rows below a block of
+// columns of a wide front: X[r] -= sum_{j in [cb, ce)} L(r, j) y_j for rows r
+// in [ce, k), ce = min(k, cb + BB), in place.
+template <typename T, int NBK, bool ROWS>
 __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
                                                        int S, int64_t N, const cpx<T> *factor,
-                                                       int64_t f_stride, const cpx<T> *x,
+                                                       int64_t f_stride, cpx<T> *x,
                                                        const cpx<T> *w_child,
-                                                       cpx<T> *w_out, int64_t w_stride) {
+                                                       cpx<T> *w_out, int64_t w_stride,
+                                                       int64_t cb, int64_t BB) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
   constexpr int RB = 2, KC = MF::KC;   // 16-row blocks per wave, columns per chunk
@@ -385,17 +326,26 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
   const int p = blockIdx.z;
   if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
+  // output rows row0 + [0, nrows), depth columns [d0, d1)
+  int64_t row0 = k, nrows = u, d0 = 0, d1 = k;
+  if (ROWS) {
+    if (cb >= k) return;
+    d0 = cb;
+    d1 = min(k, cb + BB);
+    row0 = d1;
+    nrows = k - d1;
+  }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t aw = (int64_t)blockIdx.x * 128 + wave * 32;   // first row of the wave
-  if (aw >= u) return;
+  if (aw >= nrows) return;
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  const cpx<T> *X = x + ((int64_t)p * N + first) * S;
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;
   const int lr = lane & 15, ld4 = lane >> 4;   // operand row / output column, depth
   // rows of the two blocks (clamped; rows past u reach no output)
   int32_t rrow[RB];
 #pragma unroll
-  for (int b = 0; b < RB; ++b) rrow[b] = (int32_t)(k + min(aw + b * 16 + lr, u - 1));
+  for (int b = 0; b < RB; ++b) rrow[b] = (int32_t)(row0 + min(aw + b * 16 + lr, nrows - 1));
   // B operand: column lr of block nb is Re y_j (lr < 8) or Im y_j, j = 8 nb + lr % 8
   int yj[NBK];
   bool yon[NBK];
@@ -416,14 +366,14 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
   const T *Xf = reinterpret_cast<const T *>(X);
   // chunk jb into (lv, yv): unconditional loads from clamped addresses (a
   // chunk past the end re-reads the last one and gets y = 0)
-  const int64_t jlast = ((k - 1) / KC) * KC;
+  const int64_t jlast = d0 + ((d1 - 1 - d0) / KC) * KC;
   auto load = [&](int64_t jb, cpx<T> (&lv)[KC / 4][RB], T (&yv)[KC / 4][NBK]) {
     const int64_t je = min(jb, jlast);
     int64_t ld;
     const cpx<T> *Lc = col_ptr(P, n, je, ld);   // the chunk lies in one column block
     const T *Xc = Xf + je * 2 * S;
     // 32-bit offsets inside the chunk: column offset <= 31, ld and 2 S below 2^24
-    const int32_t lim = (int32_t)(k - 1 - je), ldi = (int32_t)ld, colk = (int32_t)(k - jb);
+    const int32_t lim = (int32_t)(d1 - 1 - je), ldi = (int32_t)ld, colk = (int32_t)(d1 - jb);
 #pragma unroll
     for (int q = 0; q < KC / 4; ++q) {
       const int32_t t = 4 * q + ld4, o = min(t, lim);
@@ -451,11 +401,11 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
   // current one is multiplied
   cpx<T> la[KC / 4][RB], lb[KC / 4][RB];
   T ya[KC / 4][NBK], yb[KC / 4][NBK];
-  load(0, la, ya);
-  for (int64_t jb = 0; jb < k; jb += 2 * KC) {
+  load(d0, la, ya);
+  for (int64_t jb = d0; jb < d1; jb += 2 * KC) {
     load(jb + KC, lb, yb);
     mma(la, ya);
-    if (jb + KC >= k) break;
+    if (jb + KC >= d1) break;
     load(jb + 2 * KC, la, ya);
     mma(lb, yb);
   }
@@ -472,8 +422,13 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
         const T o1 = __shfl_xor(r1[b][nb][i], 8), o2 = __shfl_xor(r2[b][nb][i], 8);
         const int64_t a = aw + b * 16 + MF::row(ld4, i);
         const int j = 8 * nb + lr;
-        if (lr >= 8 || j >= S || a >= u) continue;
+        if (lr >= 8 || j >= S || a >= nrows) continue;
         cpx<T> v = {-(r1[b][nb][i] - o2), -(o1 + r2[b][nb][i])};
+        if (ROWS) {
+          cpx<T> *o = X + (row0 + a) * S + j;
+          *o = cadd(*o, v);
+          continue;
+        }
         if (h0) {
           const int g = ft.gmap0[ft.gmap_off[s] + k + a];
           if (g >= 0) v = cadd(v, w_child[(int64_t)p * w_stride + (ft.w_off[c0] + g) * S + j]);
@@ -494,12 +449,30 @@ hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
   if (n_nodes <= 0 || max_u <= 0) return hipSuccess;
   if (S < 1 || S > 16) return hipErrorInvalidValue;
   dim3 grid((max_u + 127) / 128, n_nodes, npole);
+  cpx<T> *xm = const_cast<cpx<T> *>(x);   // read only in this mode
   if (S <= 8)
-    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, w_child, w_out, w_stride);
+    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, false>), grid, dim3(256), 0, st, ft, lvl_nodes, S,
+                       N, factor, f_stride, xm, w_child, w_out, w_stride, 0, 0);
   else
-    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, w_child, w_out, w_stride);
+    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, false>), grid, dim3(256), 0, st, ft, lvl_nodes, S,
+                       N, factor, f_stride, xm, w_child, w_out, w_stride, 0, 0);
+  return hipGetLastError();
+}
+
+// rows [ce, k) of each wide front -= L(rows, [cb, ce)) y, ce = min(k, cb + BB)
+template <typename T>
+hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                           int max_rows, int npole, int S, int64_t N, const cpx<T> *factor,
+                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB) {
+  if (n_nodes <= 0 || max_rows <= 0) return hipSuccess;
+  if (S < 1 || S > 16) return hipErrorInvalidValue;
+  dim3 grid((max_rows + 127) / 128, n_nodes, npole);
+  if (S <= 8)
+    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, true>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, nullptr, nullptr, 0, cb, BB);
+  else
+    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, true>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, nullptr, nullptr, 0, cb, BB);
   return hipGetLastError();
 }
 
@@ -516,11 +489,15 @@ hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 // entry times stale LDS could be NaN).  With the reduction running down the
 // column-major panel, MFMA operands loaded straight from HBM would span 16
 // columns x 4 rows per instruction (a quarter of each cache line used).
-template <typename T, int NBK>
+// COLS = true is the same product for a wide front's columns left of a
+// block of rows: X[j] -= sum_{r in [cb, ce)} L(r, j) x_r for j < cb, x read
+// in place (no gather), ce = min(k, cb + BB).
+template <typename T, int NBK, bool COLS>
 __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
                                                        int S, int64_t N, const cpx<T> *factor,
-                                                       int64_t f_stride, const cpx<T> *x,
-                                                       cpx<T> *t, int64_t t_stride) {
+                                                       int64_t f_stride, cpx<T> *x,
+                                                       cpx<T> *t, int64_t t_stride, int64_t cb,
+                                                       int64_t BB) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
   const int s = lvl_nodes[blockIdx.y];
@@ -528,10 +505,19 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
   if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
   const int64_t jb = (int64_t)blockIdx.x * NB;
-  if (jb >= k) return;
-  const int w = (int)min((int64_t)NB, k - jb);
+  // columns [jb, jb + w) take rows row0 + [0, u) of the panel
+  int64_t row0 = k, ncol = k;
+  if (COLS) {
+    if (cb >= k) return;
+    row0 = cb;
+    ncol = cb;
+  }
+  if (jb >= ncol) return;
+  const int w = (int)min((int64_t)NB, ncol - jb);
+  const int64_t nr = COLS ? min(k, cb + BB) - cb : u;   // rows of the reduction
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
   const cpx<T> *Xp = x + (int64_t)p * N * S;
+  cpx<T> *Xf = x + ((int64_t)p * N + first) * S;
   const int32_t *rows = ft.rows + ft.rows_off[s];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -554,23 +540,24 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
   auto xval = [&](int q, int64_t ac, int na) -> cpx<T> {
     const int idx = tid + 256 * q;
     const int i = min(idx / S, na - 1), c = idx % S;
+    if (COLS) return Xf[(row0 + ac + i) * S + c];
     return Xp[(int64_t)rows[ac + i] * S + c];
   };
   auto fetch = [&](int64_t ac) {
-    const int na = (int)min((int64_t)RT, u - ac);
+    const int na = (int)min((int64_t)RT, nr - ac);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int idx = tid + 256 * q, i = min(idx % RT, na - 1), l = min(idx / RT, w - 1);
-      pre[q] = Lc[(int64_t)l * ld + k + ac + i];
+      pre[q] = Lc[(int64_t)l * ld + row0 + ac + i];
     }
     px0 = xval(0, ac, na);
     px1 = xval(1, ac, na);
     px2 = xval(2, ac, na);
     px3 = xval(3, ac, na);
   };
-  if (u > 0) fetch(0);
-  for (int64_t ac = 0; ac < u; ac += RT) {
-    const int na = (int)min((int64_t)RT, u - ac);
+  if (nr > 0) fetch(0);
+  for (int64_t ac = 0; ac < nr; ac += RT) {
+    const int na = (int)min((int64_t)RT, nr - ac);
     lds_barrier();   // the previous tile's readers are done
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -590,7 +577,7 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
     xput(2, px2);
     xput(3, px3);
     lds_barrier();
-    if (ac + RT < u) fetch(ac + RT);
+    if (ac + RT < nr) fetch(ac + RT);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int i = rh * 32 + 4 * q + ld4;
@@ -628,7 +615,12 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
       const T o1 = __shfl_xor(a1, 8), o2 = __shfl_xor(a2, 8);
       const int m = mb * 16 + MF::row(ld4, i), j = 8 * nb + lr;
       if (lr >= 8 || j >= S || m >= w) continue;
-      To[m * S + j] = {a1 - o2, o1 + a2};
+      if (COLS) {
+        cpx<T> *o = Xf + (jb + m) * S + j;
+        *o = csub(*o, cpx<T>{a1 - o2, o1 + a2});
+      } else {
+        To[m * S + j] = {a1 - o2, o1 + a2};
+      }
     }
 }
 
@@ -639,12 +631,13 @@ hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
   if (n_nodes <= 0 || max_k <= 0) return hipSuccess;
   if (S < 1 || S > 16) return hipErrorInvalidValue;
   dim3 grid((max_k + NB - 1) / NB, n_nodes, npole);
+  cpx<T> *xm = const_cast<cpx<T> *>(x);   // read only in this mode
   if (S <= 8)
-    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, t, t_stride);
+    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, false>), grid, dim3(256), 0, st, ft, lvl_nodes, S,
+                       N, factor, f_stride, xm, t, t_stride, 0, 0);
   else
-    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, t, t_stride);
+    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, false>), grid, dim3(256), 0, st, ft, lvl_nodes, S,
+                       N, factor, f_stride, xm, t, t_stride, 0, 0);
   return hipGetLastError();
 }
 
@@ -896,68 +889,22 @@ hipError_t launch_bwd_init(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 }
 
 // ------------------------------------------------------ backward cols
-// X[j] -= sum_{r in [cb, ce)} L(r, j) x_r for the column block of j < cb
-template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_cols(FrontTab ft, const int32_t *lvl_nodes, int S,
-                                                  int64_t N, const cpx<T> *factor,
-                                                  int64_t f_stride, cpx<T> *x, int64_t cb,
-                                                  int64_t BB) {
-  const int s = lvl_nodes[blockIdx.y];
-  const int p = blockIdx.z;
-  if (pole_absent(ft, s, p)) return;
-  const int64_t k = ft.k[s], n = k + ft.u[s], first = ft.first[s];
-  const int64_t jb = (int64_t)blockIdx.x * NB;
-  if (cb >= k || jb >= cb) return;
-  const int64_t ce = min(k, cb + BB);
-  const int w = (int)min((int64_t)NB, cb - jb);
-  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  cpx<T> *X = x + ((int64_t)p * N + first) * S;
-  const int tid = threadIdx.x;
-  int64_t ld;
-  const cpx<T> *Lc = col_ptr(P, n, jb, ld);
-  __shared__ cpx<T> Lt[NB][RT + 1];
-  __shared__ cpx<T> Xt[RT][16];
-  cpx<T> acc[2];
-  acc[0] = czero<T>();
-  acc[1] = czero<T>();
-  for (int64_t rc = cb; rc < ce; rc += RT) {
-    const int nr = (int)min((int64_t)RT, ce - rc);
-    __syncthreads();
-    stage_tile<T, RT>(Lt, Lc, ld, rc, nr, w, tid);
-    for (int idx = tid; idx < nr * S; idx += blockDim.x) Xt[idx / S][idx % S] = X[rc * S + idx];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int idx = tid + 256 * q;
-      if (idx < w * S) {
-        const int l = idx / S, c = idx % S;
-        cpx<T> sacc = acc[q];
-        for (int i = 0; i < nr; ++i) sacc = cfma(Lt[l][i], Xt[i][c], sacc);
-        acc[q] = sacc;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int idx = tid + 256 * q;
-    if (idx < w * S) {
-      cpx<T> *o = X + jb * S + idx;
-      *o = csub(*o, acc[q]);
-    }
-  }
-}
-
+// X[j] -= sum_{r in [cb, ce)} L(r, j) x_r for the column blocks of j < cb
 template <typename T>
 hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int64_t cb, int npole, int S, int64_t N, const cpx<T> *factor,
                            int64_t f_stride, cpx<T> *x, int64_t BB) {
   if (n_nodes <= 0 || cb <= 0) return hipSuccess;
+  if (S < 1 || S > 16) return hipErrorInvalidValue;
   dim3 grid((unsigned)((cb + NB - 1) / NB), n_nodes, npole);
-  hipLaunchKernelGGL(k_bwd_cols<T>, grid, dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride,
-                     x, cb, BB);
+  if (S <= 8)
+    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, true>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, nullptr, 0, cb, BB);
+  else
+    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, true>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, nullptr, 0, cb, BB);
   return hipGetLastError();
 }
-
 
 #define TEM_INST(T)                                                                              \
   template hipError_t launch_fwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
