@@ -114,7 +114,9 @@ hipError_t launch_extend_add(hipStream_t st, FrontTab ft, const int2 *cols, int6
 // LDL^T (no pivoting) of the NB x NB diagonal block of column block j0/NB,
 // then the inverse of its unit-lower factor, stored transposed in the
 // strictly upper part of the block.  flags[0] |= 1 on a zero or non-finite
-// pivot; flags[1] counts tiny pivots.
+// pivot; flags[1] counts tiny pivots.  Both triangular recurrences (the
+// elimination and the inverse) run a column step at a time over all the
+// entries that step updates.
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel_diag(FrontTab ft, const int32_t *lvl_nodes, int j0,
                                                     cpx<T> *factor, int64_t f_stride,
@@ -154,18 +156,23 @@ __global__ __launch_bounds__(256) void k_panel_diag(FrontTab ft, const int32_t *
     for (int r = j + 1 + tid; r < w; r += blockDim.x) F[j][r] = cmul(F[j][r], inv);
     __syncthreads();
   }
-  // inverse of the unit lower triangular factor, one column per thread
-  if (tid < w) {
-    const int c = tid;
-    for (int r = 0; r < w; ++r) Iv[c][r] = czero<T>();
-    Iv[c][c] = {T(1), T(0)};
-    for (int r = c + 1; r < w; ++r) {
-      cpx<T> acc = czero<T>();
-      for (int l = c; l < r; ++l) acc = cfma(F[l][r], Iv[c][l], acc);
-      Iv[c][r] = {-acc.re, -acc.im};
-    }
+  // inverse of the unit lower triangular factor by column sweeps: after step
+  // l entry l of every column c <= l is final and is eliminated from the
+  // rows below it (Iv[c][r] is row r of column c of the inverse)
+  for (int idx = tid; idx < w * w; idx += blockDim.x) {
+    const int r = idx % w, c = idx / w;
+    Iv[c][r] = (r == c) ? cpx<T>{T(1), T(0)} : czero<T>();
   }
   __syncthreads();
+  for (int l = 0; l + 1 < w; ++l) {
+    const int nr = w - l - 1;   // rows l+1 .. w-1 of columns 0 .. l
+    for (int idx = tid; idx < (l + 1) * nr; idx += blockDim.x) {
+      const int c = idx / nr, r = l + 1 + idx % nr;
+      const cpx<T> a = F[l][r];
+      Iv[c][r] = cfma(cpx<T>{-a.re, -a.im}, Iv[c][l], Iv[c][r]);
+    }
+    __syncthreads();
+  }
   for (int idx = tid; idx < w * w; idx += blockDim.x) {
     const int r = idx % w, c = idx / w;
     // lower part (r >= c): L and D; upper (r < c): transpose of the inverse
@@ -220,7 +227,7 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FrontTab ft, const int32_t *
       cpx<T> acc = x[j];
 #pragma unroll
       for (int l = 0; l < NB; ++l)
-        if (l < j) acc = csub(acc, cmul(x[l], W[j][l]));
+        if (l < j) acc = cfma(cpx<T>{-x[l].re, -x[l].im}, W[j][l], acc);
       x[j] = cmul(acc, invd[j]);
     }
   }
