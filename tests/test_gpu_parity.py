@@ -55,12 +55,11 @@ class Run:
         self.o = _oracle(wl)
 
 
-def _wide(wl, prec):
-    """Run with the big-block sweep schedule forced on every level."""
+def _env_run(wl, prec, env):
+    """Run with the library's schedule knobs (read by tem_create) set to env."""
     import os
-    old = {k: os.environ.get(k) for k in ("TEM_SWEEP_BLOCK", "TEM_SWEEP_BIG_LIMIT")}
-    os.environ["TEM_SWEEP_BLOCK"] = "64"
-    os.environ["TEM_SWEEP_BIG_LIMIT"] = "1000000"
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
     try:
         return Run(wl, prec)
     finally:
@@ -69,6 +68,11 @@ def _wide(wl, prec):
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
+
+
+def _wide(wl, prec):
+    """Run with the big-block sweep schedule forced on every level."""
+    return _env_run(wl, prec, {"TEM_SWEEP_BLOCK": "64", "TEM_SWEEP_BIG_LIMIT": "1000000"})
 
 
 CASES = {
@@ -82,6 +86,13 @@ CASES = {
     "w16_32": lambda: _wide(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 1),
     # twelve right-hand sides: the FP32 forward sweep's two-block path (S > 8)
     "s12_32": lambda: Run(ti.smooth_workload(16, 2, S=12, m=3, K=5, g=2, seed=23), 1),
+    # factor panel schedules (the 13^3 root separator has 312 columns): 64-column
+    # left-looking panels, and 96-column right-looking panels (recursion halves
+    # of 32 and 64 columns)
+    "p64_32": lambda: _env_run(ti.smooth_workload(13, 2, S=3, m=5, K=7, g=2, seed=21), 1,
+                               {"TEM_PANEL": "64"}),
+    "p96rl_64": lambda: _env_run(ti.smooth_workload(13, 2, S=3, m=5, K=7, g=2, seed=21), 0,
+                                 {"TEM_PANEL": "96", "TEM_LEFT_LOOKING": "0"}),
 }
 _cache = {}
 
