@@ -116,10 +116,12 @@ hipError_t launch_extend_add(hipStream_t st, FrontTab ft, const int2 *cols, int6
 // strictly upper part of the block.  flags[0] |= 1 on a zero or non-finite
 // pivot; flags[1] counts tiny pivots.  Both triangular recurrences (the
 // elimination and the inverse) run a column step at a time over all the
-// entries that step updates.
+// entries that step updates.  With jp >= 0 (= j0 - NB) the block first takes
+// the update of the factored block jp: A_jj -= L_j,p D_p L_j,p^T (the last
+// update of the block, left-looking, in place of a separate launch).
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel_diag(FrontTab ft, const int32_t *lvl_nodes, int j0,
-                                                    cpx<T> *factor, int64_t f_stride,
+                                                    int jp, cpx<T> *factor, int64_t f_stride,
                                                     int *flags) {
   const int s = lvl_nodes[blockIdx.x];
   const int p = blockIdx.y;
@@ -136,6 +138,28 @@ __global__ __launch_bounds__(256) void k_panel_diag(FrontTab ft, const int32_t *
   for (int idx = tid; idx < w * w; idx += blockDim.x) {
     const int r = idx % w, c = idx / w;
     F[c][r] = (r >= c) ? blk[(int64_t)c * ld + r] : czero<T>();
+  }
+  if (jp >= 0) {
+    // rows j0 .. j0+w-1 of block jp (below its diagonal block: plain L) and
+    // its pivots; Iv is free until the inverse is formed
+    const int64_t ldp = n - jp;
+    const cpx<T> *bp = factor + (int64_t)p * f_stride + ft.panel_off[s] + panel_block_off(n, jp / NB);
+    for (int idx = tid; idx < NB * w; idx += blockDim.x) {
+      const int r = idx % w, l = idx / w;
+      Iv[l][r] = bp[(int64_t)l * ldp + (j0 - jp) + r];
+    }
+    if (tid < NB) Iv[tid][NB] = bp[(int64_t)tid * ldp + tid];   // d_l in the pad column
+    __syncthreads();
+    for (int idx = tid; idx < w * w; idx += blockDim.x) {
+      const int r = idx % w, c = idx / w;
+      if (r < c) continue;
+      cpx<T> acc = F[c][r];
+      for (int l = 0; l < NB; ++l) {
+        const cpx<T> a = cmul(Iv[l][r], Iv[l][NB]);
+        acc = cfma(cpx<T>{-a.re, -a.im}, Iv[l][c], acc);
+      }
+      F[c][r] = acc;
+    }
   }
   __syncthreads();
   const T tiny = sizeof(T) == 4 ? T(1e-30) : T(1e-300);
@@ -182,19 +206,23 @@ __global__ __launch_bounds__(256) void k_panel_diag(FrontTab ft, const int32_t *
 
 template <typename T>
 hipError_t launch_panel_diag(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                             int j0, int npole, cpx<T> *factor, int64_t f_stride, int *flags) {
+                             int j0, int jp, int npole, cpx<T> *factor, int64_t f_stride,
+                             int *flags) {
   if (n_nodes <= 0) return hipSuccess;
+  if (jp >= 0 && jp != j0 - NB) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_panel_diag<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, j0,
-                     factor, f_stride, flags);
+                     jp, factor, f_stride, flags);
   return hipGetLastError();
 }
 
 // --------------------------------------------------------- panel rows
 // Rows below the diagonal block: L[r, j] = (A[r, j] - sum_{l<j} L[r, l] d_l
-// L[j, l]) / d_j, one row per thread.
+// L[j, l]) / d_j, one row per thread.  With jp >= 0 (= j0 - NB) each row
+// first takes the update of block jp: A[r, j] -= sum_l L[r, jp+l] d_l
+// L[j, jp+l] (as in k_panel_diag).
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel_trsm(FrontTab ft, const int32_t *lvl_nodes, int j0,
-                                                    cpx<T> *factor, int64_t f_stride) {
+                                                    int jp, cpx<T> *factor, int64_t f_stride) {
   const int s = lvl_nodes[blockIdx.y];
   const int p = blockIdx.z;
   if (pole_absent(ft, s, p)) return;
@@ -204,8 +232,13 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FrontTab ft, const int32_t *
   const int64_t n = (int64_t)k + ft.u[s];
   const int64_t ld = n - j0;
   cpx<T> *blk = factor + (int64_t)p * f_stride + ft.panel_off[s] + panel_block_off(n, j0 / NB);
-  __shared__ cpx<T> W[NB][NB];   // W[j][l] = d_l L[j][l]
+  __shared__ cpx<T> W[NB][NB];    // W[j][l] = d_l L[j][l]
+  __shared__ cpx<T> W2[NB][NB];   // W2[j][l] = d_l L[j0 + j][jp + l] (jp >= 0)
   __shared__ cpx<T> invd[NB];
+  const int64_t ldp = n - jp;
+  const cpx<T> *bp =
+      jp >= 0 ? factor + (int64_t)p * f_stride + ft.panel_off[s] + panel_block_off(n, jp / NB)
+              : nullptr;
   const int tid = threadIdx.x;
   const int64_t rloc0 = (int64_t)w + (int64_t)blockIdx.x * blockDim.x;  // block-local row
   if (rloc0 >= ld) return;
@@ -214,6 +247,12 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FrontTab ft, const int32_t *
     if (l < j) W[j][l] = cmul(blk[(int64_t)l * ld + l], blk[(int64_t)l * ld + j]);
   }
   if (tid < w) invd[tid] = cinv(blk[(int64_t)tid * ld + tid]);
+  if (jp >= 0) {
+    for (int idx = tid; idx < w * NB; idx += blockDim.x) {
+      const int j = idx % w, l = idx / w;
+      W2[j][l] = cmul(bp[(int64_t)l * ldp + l], bp[(int64_t)l * ldp + (j0 - jp) + j]);
+    }
+  }
   __syncthreads();
   const int64_t r = rloc0 + tid;
   if (r >= ld) return;
@@ -221,6 +260,17 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FrontTab ft, const int32_t *
 #pragma unroll
   for (int j = 0; j < NB; ++j)
     if (j < w) x[j] = blk[(int64_t)j * ld + r];
+  if (jp >= 0) {
+    // row r of block jp, one entry at a time
+#pragma unroll 4
+    for (int l = 0; l < NB; ++l) {
+      const cpx<T> a = bp[(int64_t)l * ldp + (j0 - jp) + r];
+      const cpx<T> na = {-a.re, -a.im};
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j < w) x[j] = cfma(na, W2[j][l], x[j]);
+    }
+  }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     if (j < w) {
@@ -238,10 +288,12 @@ __global__ __launch_bounds__(256) void k_panel_trsm(FrontTab ft, const int32_t *
 
 template <typename T>
 hipError_t launch_panel_trsm(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                             int j0, int max_rows, int npole, cpx<T> *factor, int64_t f_stride) {
+                             int j0, int jp, int max_rows, int npole, cpx<T> *factor,
+                             int64_t f_stride) {
   if (n_nodes <= 0 || max_rows <= 0) return hipSuccess;
+  if (jp >= 0 && jp != j0 - NB) return hipErrorInvalidValue;
   dim3 grid((max_rows + 255) / 256, n_nodes, npole);
-  hipLaunchKernelGGL(k_panel_trsm<T>, grid, dim3(256), 0, st, ft, lvl_nodes, j0, factor,
+  hipLaunchKernelGGL(k_panel_trsm<T>, grid, dim3(256), 0, st, ft, lvl_nodes, j0, jp, factor,
                      f_stride);
   return hipGetLastError();
 }
@@ -653,9 +705,9 @@ hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_n
   template hipError_t launch_extend_add<T>(hipStream_t, FrontTab, const int2 *, int64_t, int, int, \
                                            cpx<T> *, int64_t, cpx<T> *, cpx<T> *, int64_t);      \
   template hipError_t launch_panel_diag<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \
-                                           cpx<T> *, int64_t, int *);                            \
+                                           int, cpx<T> *, int64_t, int *);                       \
   template hipError_t launch_panel_trsm<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \
-                                           int, cpx<T> *, int64_t);                              \
+                                           int, int, cpx<T> *, int64_t);                         \
   template hipError_t launch_front_update<T>(hipStream_t, FrontTab, const int32_t *, int, int,    \
                                              int, int, int, int64_t, int, cpx<T> *, int64_t,      \
                                              cpx<T> *, int64_t, int, bool);

@@ -728,7 +728,9 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
       span_end(c, ea, fl, 0);
       return TEM_OK;
     };
-    auto block = [&](int j0) -> tem_status {   // columns [j0, j0 + NB)
+    // columns [j0, j0 + NB); jp = j0 - NB folds in the update of the block
+    // just factored (the last one these columns need), jp = -1 none
+    auto block = [&](int j0, int jp) -> tem_status {
       int max_rows = 0;
       for (int s : li.nodes) {
         const SymNode &nd = sym.nodes[s];
@@ -737,17 +739,23 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
         const int64_t w = std::min<int64_t>(NB, k - j0);
         max_rows = std::max<int>(max_rows, (int)(n - j0 - w));
       }
-      HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, g, F, mf.pole_stride,
+      HIPCHK(launch_panel_diag<T>(st, ft, ln, li.n, j0, jp, g, F, mf.pole_stride,
                                   c->d_flags.as<int>()),
              "panel diag");
-      HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, max_rows, g, F, mf.pole_stride),
+      HIPCHK(launch_panel_trsm<T>(st, ft, ln, li.n, j0, jp, max_rows, g, F, mf.pole_stride),
              "panel trsm");
       return TEM_OK;
     };
-    // columns [a, a + w) of the panel, w a multiple of NB
+    // columns [a, a + w) of the panel, w a multiple of NB; a range of two
+    // blocks factors the second with the first's update folded in (the rank-NB
+    // update of NB columns, a separate launch otherwise)
     std::function<tem_status(int, int)> factor_range = [&](int a, int w) -> tem_status {
       if (a >= li.max_k) return TEM_OK;
-      if (w <= NB) return block(a);
+      if (w <= NB) return block(a, -1);
+      if (w == 2 * NB) {
+        TRY(block(a, -1));
+        return a + NB < li.max_k ? block(a + NB, a) : TEM_OK;
+      }
       const int h = NB * ((w / NB) / 2);
       TRY(factor_range(a, h));
       TRY(trailing(a, h, a + w));

@@ -98,13 +98,17 @@ hipError_t launch_extend_add(hipStream_t st, FrontTab ft, const int2 *cols, int6
                              int slot, int npole, cpx<T> *factor, int64_t f_stride,
                              cpx<T> *cb_parent, cpx<T> *cb_child, int64_t cb_stride);
 
+// Diagonal block and the rows below it of column block j0 / NB; jp = j0 - NB
+// makes both first apply the update of the factored block jp, jp = -1 none.
 template <typename T>
 hipError_t launch_panel_diag(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                             int j0, int npole, cpx<T> *factor, int64_t f_stride, int *flags);
+                             int j0, int jp, int npole, cpx<T> *factor, int64_t f_stride,
+                             int *flags);
 
 template <typename T>
 hipError_t launch_panel_trsm(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
-                             int j0, int max_rows, int npole, cpx<T> *factor, int64_t f_stride);
+                             int j0, int jp, int max_rows, int npole, cpx<T> *factor,
+                             int64_t f_stride);
 
 // Output tile shapes of the front update (rows x columns): 64 x 64; 128 x 64
 // and 128 x 128 (FP32 only; 128 x 128 with four real products only).
