@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
   }
 }
 
-// FP32 forward triangle for ranges of at most 256 rows.  Thread i owns row
+// Forward triangle for ranges of at most 256 rows.  Thread i owns row
 // cb + i of the range and keeps its right-hand sides in registers for the
 // whole range, together with its row of the current 32-column block, loaded
 // one block ahead (as is the inverse diagonal block).  Per block: the owners
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
   }
 }
 
-// FP32 backward triangle for ranges of at most 256 rows, right-looking:
+// Backward triangle for ranges of at most 256 rows, right-looking:
 // thread i owns row cb + i and keeps its right-hand side v in registers
 // (D^{-1} y - t with init, else the value in x).  Blocks run from the last
 // to the first; per block the owners publish v, x_b = v + Lo^T v is formed
