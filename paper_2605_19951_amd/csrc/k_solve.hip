@@ -311,8 +311,9 @@ struct Mfma16<double> {
 };
 // ROWS = true is the same product for the pivot rows below a block of
 // columns of a wide front: X[r] -= sum_{j in [cb, ce)} L(r, j) y_j for rows r
-// in [ce, k), ce = min(k, cb + BB), in place.
-template <typename T, int NBK, bool ROWS>
+// in [ce, k), ce = min(k, cb + BB), in place.  RL = true: the factor is
+// real (its imaginary parts are zero), so the Li products are skipped.
+template <typename T, int NBK, bool ROWS, bool RL = false>
 __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
                                                        int S, int64_t N, const cpx<T> *factor,
                                                        int64_t f_stride, cpx<T> *x,
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
 #pragma unroll
         for (int nb = 0; nb < NBK; ++nb) {
           r1[b][nb] = MF::mma(lv[q][b].re, yv[q][nb], r1[b][nb]);
-          r2[b][nb] = MF::mma(lv[q][b].im, yv[q][nb], r2[b][nb]);
+          if constexpr (!RL) r2[b][nb] = MF::mma(lv[q][b].im, yv[q][nb], r2[b][nb]);
         }
   };
   // two register sets: the loads of the next chunk are in flight while the
@@ -441,39 +442,56 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
       }
 }
 
+// launches the forward MFMA kernel for S right-hand sides (NBK from S; the
+// real-factor variant only exists in FP64)
+template <typename T, bool ROWS>
+hipError_t fwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lvl_nodes, int S,
+                       int64_t N, const cpx<T> *factor, int64_t f_stride, cpx<T> *x,
+                       const cpx<T> *w_child, cpx<T> *w_out, int64_t w_stride, int64_t cb,
+                       int64_t BB, bool real_l) {
+  if (S < 1 || S > 16) return hipErrorInvalidValue;
+  const bool two = S > 8;
+  if constexpr (sizeof(T) == 8) {
+    if (real_l) {
+      if (two)
+        hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, ROWS, true>), grid, dim3(256), 0, st, ft,
+                           lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB);
+      else
+        hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, ROWS, true>), grid, dim3(256), 0, st, ft,
+                           lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB);
+      return hipGetLastError();
+    }
+  }
+  if (two)
+    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, ROWS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB);
+  else
+    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, ROWS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_u, int npole, int S, int64_t N, const cpx<T> *factor,
                            int64_t f_stride, const cpx<T> *x, const cpx<T> *w_child,
-                           cpx<T> *w_out, int64_t w_stride) {
+                           cpx<T> *w_out, int64_t w_stride, bool real_l) {
   if (n_nodes <= 0 || max_u <= 0) return hipSuccess;
-  if (S < 1 || S > 16) return hipErrorInvalidValue;
   dim3 grid((max_u + 127) / 128, n_nodes, npole);
   cpx<T> *xm = const_cast<cpx<T> *>(x);   // read only in this mode
-  if (S <= 8)
-    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, false>), grid, dim3(256), 0, st, ft, lvl_nodes, S,
-                       N, factor, f_stride, xm, w_child, w_out, w_stride, 0, 0);
-  else
-    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, false>), grid, dim3(256), 0, st, ft, lvl_nodes, S,
-                       N, factor, f_stride, xm, w_child, w_out, w_stride, 0, 0);
-  return hipGetLastError();
+  return fwd_mfma_go<T, false>(st, grid, ft, lvl_nodes, S, N, factor, f_stride, xm, w_child,
+                               w_out, w_stride, 0, 0, real_l);
 }
 
 // rows [ce, k) of each wide front -= L(rows, [cb, ce)) y, ce = min(k, cb + BB)
 template <typename T>
 hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_rows, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB) {
+                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB, bool real_l) {
   if (n_nodes <= 0 || max_rows <= 0) return hipSuccess;
-  if (S < 1 || S > 16) return hipErrorInvalidValue;
   dim3 grid((max_rows + 127) / 128, n_nodes, npole);
-  if (S <= 8)
-    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, true>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, nullptr, nullptr, 0, cb, BB);
-  else
-    hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, true>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, nullptr, nullptr, 0, cb, BB);
-  return hipGetLastError();
+  return fwd_mfma_go<T, true>(st, grid, ft, lvl_nodes, S, N, factor, f_stride, x, nullptr,
+                              nullptr, 0, cb, BB, real_l);
 }
 
 // ----------------------------------------------------------- backward rect
@@ -491,8 +509,8 @@ hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 // columns x 4 rows per instruction (a quarter of each cache line used).
 // COLS = true is the same product for a wide front's columns left of a
 // block of rows: X[j] -= sum_{r in [cb, ce)} L(r, j) x_r for j < cb, x read
-// in place (no gather), ce = min(k, cb + BB).
-template <typename T, int NBK, bool COLS>
+// in place (no gather), ce = min(k, cb + BB).  RL as in the forward kernel.
+template <typename T, int NBK, bool COLS, bool RL = false>
 __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
                                                        int S, int64_t N, const cpx<T> *factor,
                                                        int64_t f_stride, cpx<T> *x,
@@ -587,7 +605,7 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
         const cpx<T> xv = Xt[i][8 * nb + (lr & 7)];
         const T b = lr < 8 ? xv.re : xv.im;
         r1[nb] = MF::mma(a.re, b, r1[nb]);
-        r2[nb] = MF::mma(a.im, b, r2[nb]);
+        if constexpr (!RL) r2[nb] = MF::mma(a.im, b, r2[nb]);
       }
     }
   }
@@ -624,21 +642,43 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
     }
 }
 
+// launches the backward MFMA kernel (as fwd_mfma_go)
+template <typename T, bool COLS>
+hipError_t bwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lvl_nodes, int S,
+                       int64_t N, const cpx<T> *factor, int64_t f_stride, cpx<T> *x, cpx<T> *t,
+                       int64_t t_stride, int64_t cb, int64_t BB, bool real_l) {
+  if (S < 1 || S > 16) return hipErrorInvalidValue;
+  const bool two = S > 8;
+  if constexpr (sizeof(T) == 8) {
+    if (real_l) {
+      if (two)
+        hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, COLS, true>), grid, dim3(256), 0, st, ft,
+                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB);
+      else
+        hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, COLS, true>), grid, dim3(256), 0, st, ft,
+                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB);
+      return hipGetLastError();
+    }
+  }
+  if (two)
+    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, COLS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, t, t_stride, cb, BB);
+  else
+    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, COLS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
+                       factor, f_stride, x, t, t_stride, cb, BB);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_k, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, const cpx<T> *x, cpx<T> *t, int64_t t_stride) {
+                           int64_t f_stride, const cpx<T> *x, cpx<T> *t, int64_t t_stride,
+                           bool real_l) {
   if (n_nodes <= 0 || max_k <= 0) return hipSuccess;
-  if (S < 1 || S > 16) return hipErrorInvalidValue;
   dim3 grid((max_k + NB - 1) / NB, n_nodes, npole);
   cpx<T> *xm = const_cast<cpx<T> *>(x);   // read only in this mode
-  if (S <= 8)
-    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, false>), grid, dim3(256), 0, st, ft, lvl_nodes, S,
-                       N, factor, f_stride, xm, t, t_stride, 0, 0);
-  else
-    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, false>), grid, dim3(256), 0, st, ft, lvl_nodes, S,
-                       N, factor, f_stride, xm, t, t_stride, 0, 0);
-  return hipGetLastError();
+  return bwd_mfma_go<T, false>(st, grid, ft, lvl_nodes, S, N, factor, f_stride, xm, t, t_stride,
+                               0, 0, real_l);
 }
 
 // ------------------------------------------------------------ backward tri
@@ -893,17 +933,11 @@ hipError_t launch_bwd_init(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 template <typename T>
 hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int64_t cb, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t BB) {
+                           int64_t f_stride, cpx<T> *x, int64_t BB, bool real_l) {
   if (n_nodes <= 0 || cb <= 0) return hipSuccess;
-  if (S < 1 || S > 16) return hipErrorInvalidValue;
   dim3 grid((unsigned)((cb + NB - 1) / NB), n_nodes, npole);
-  if (S <= 8)
-    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, true>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, nullptr, 0, cb, BB);
-  else
-    hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, true>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, nullptr, 0, cb, BB);
-  return hipGetLastError();
+  return bwd_mfma_go<T, true>(st, grid, ft, lvl_nodes, S, N, factor, f_stride, x, nullptr, 0, cb,
+                              BB, real_l);
 }
 
 #define TEM_INST(T)                                                                              \
@@ -912,19 +946,19 @@ hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
                                         const cpx<T> *, int64_t, int64_t, int64_t);              \
   template hipError_t launch_fwd_rows<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, cpx<T> *,        \
-                                         int64_t, int64_t);                                      \
+                                         int64_t, int64_t, bool);                                \
   template hipError_t launch_bwd_init<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, cpx<T> *,        \
                                          const cpx<T> *, int64_t);                               \
   template hipError_t launch_bwd_cols<T>(hipStream_t, FrontTab, const int32_t *, int, int64_t,    \
                                          int, int, int64_t, const cpx<T> *, int64_t, cpx<T> *,   \
-                                         int64_t);                                               \
+                                         int64_t, bool);                                         \
   template hipError_t launch_fwd_rect<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, const cpx<T> *,  \
-                                         const cpx<T> *, cpx<T> *, int64_t);                     \
+                                         const cpx<T> *, cpx<T> *, int64_t, bool);               \
   template hipError_t launch_bwd_rect<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, const cpx<T> *,  \
-                                         cpx<T> *, int64_t);                                     \
+                                         cpx<T> *, int64_t, bool);                               \
   template hipError_t launch_bwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
                                         int64_t, const cpx<T> *, int64_t, cpx<T> *,              \
                                         const cpx<T> *, int64_t, int64_t, int64_t, int);

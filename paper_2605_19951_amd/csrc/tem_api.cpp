@@ -812,7 +812,7 @@ tem_status ensure_sweep_ws(tem_ctx *c, MF &mf, int npole, int S) {
 // systems whose factors start at F with stride f_stride (0: one shared factor)
 template <typename T>
 tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, int npole,
-                        cpx<T> *x, int S, int p0 = 0) {
+                        cpx<T> *x, int S, int p0 = 0, bool real_l = false) {
   TRY(ensure_sweep_ws<T>(c, mf, npole, S));
   hipStream_t st = c->stream;
   FrontTab ft = front_tab(mf, p0);
@@ -844,18 +844,19 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
                                  ws, cb, BB),
                "fwd tri");
         HIPCHK(launch_fwd_rows<T>(st, ft, ln, li.n, (int)std::max<int64_t>(0, li.max_k - cb - BB),
-                                  npole, S, N, F, f_stride, x, cb, BB),
+                                  npole, S, N, F, f_stride, x, cb, BB, real_l),
                "fwd rows");
       }
     }
     HIPCHK(launch_fwd_rect<T>(st, ft, ln, li.n, li.max_u, npole, S, N, F, f_stride, x,
-                              W[(L + 1) & 1], W[L & 1], ws),
+                              W[(L + 1) & 1], W[L & 1], ws, real_l),
            "fwd rect");
   }
   for (int L = 0; L < nl; ++L) {
     const LevelInfo &li = mf.levels[L];
     const int32_t *ln = lvl_ptr(mf, li);
-    HIPCHK(launch_bwd_rect<T>(st, ft, ln, li.n, li.max_k, npole, S, N, F, f_stride, x, t, N * S),
+    HIPCHK(launch_bwd_rect<T>(st, ft, ln, li.n, li.max_k, npole, S, N, F, f_stride, x, t, N * S,
+                              real_l),
            "bwd rect");
     if (!big(li)) {
       HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, 0,
@@ -870,7 +871,7 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
         HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, cb, BB,
                                  0),
                "bwd tri");
-        HIPCHK(launch_bwd_cols<T>(st, ft, ln, li.n, cb, npole, S, N, F, f_stride, x, BB),
+        HIPCHK(launch_bwd_cols<T>(st, ft, ln, li.n, cb, npole, S, N, F, f_stride, x, BB, real_l),
                "bwd cols");
       }
     }
@@ -1036,7 +1037,8 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
     // run's systems packed S2 = 16 to a pass
     const int nsys = pr.n * S, S2 = std::min(16, nsys), nv = (nsys + S2 - 1) / S2;
     HIPCHK(launch_grad_T(st, Nn, pr.n, S, S2, N, c->d_node_edges.as<int32_t>(), w + o, y), "G^T");
-    TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, nv, y, S2));
+    TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, nv, y, S2, 0,
+                                   /*real_l=*/true));
     HIPCHK(launch_grad_add(st, N, pr.n, S, S2, Nn, c->d_edge_nodes.as<int32_t>(),
                            c->d_ncoef.as<cpx<double>>() + pr.p0, rs, y, z + o),
            "z += G y");

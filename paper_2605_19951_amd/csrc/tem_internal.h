@@ -141,7 +141,8 @@ hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
 template <typename T>
 hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_rows, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB);
+                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB,
+                           bool real_l = false);
 // x_j = y_j / d_j - t_j
 template <typename T>
 hipError_t launch_bwd_init(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
@@ -151,18 +152,21 @@ hipError_t launch_bwd_init(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 template <typename T>
 hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int64_t cb, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t BB);
+                           int64_t f_stride, cpx<T> *x, int64_t BB, bool real_l = false);
 
+// real_l: the factor's imaginary parts are zero (FP64 only; skips the
+// products with them)
 template <typename T>
 hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_u, int npole, int S, int64_t N, const cpx<T> *factor,
                            int64_t f_stride, const cpx<T> *x, const cpx<T> *w_child,
-                           cpx<T> *w_out, int64_t w_stride);
+                           cpx<T> *w_out, int64_t w_stride, bool real_l = false);
 
 template <typename T>
 hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_k, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, const cpx<T> *x, cpx<T> *t, int64_t t_stride);
+                           int64_t f_stride, const cpx<T> *x, cpx<T> *t, int64_t t_stride,
+                           bool real_l = false);
 
 template <typename T>
 hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
