@@ -337,7 +337,7 @@ tem_status tem_forward_batch(tem_ctx *ctx, const int32_t *S, const double *F, co
 typedef struct {
   int32_t n_candidates;       /* update variants timed */
   int32_t n_levels;           /* tree levels of the edge system */
-  double candidate_ms[8];     /* device time of the factorisation levels per variant */
+  double candidate_ms[8];     /* per variant: sum over levels of the level's time */
   int32_t candidate_tile[8];  /* variant's output tile: 0 = 64x64, 1 = 128x64, 2 = 128x128 */
   int32_t candidate_m3[8];    /* 1: complex products with three real products, 0: four */
   double tuned_ms;            /* sum over levels of the fastest variant's time */
@@ -347,9 +347,11 @@ typedef struct {
  * tiles, each with three or four real matrix-core products per complex
  * product; FP64: 64x64 with three or four) level by level on complete
  * factorisations of the given poles, and keeps for each level of the tree
- * the variant that was fastest there.  Later tem_factor_poles calls of that
- * precision use the choice until the next tem_analyse with other options
- * or another mesh.  Leaves the context factored (last variant timed).
+ * the variant that was fastest there.  Every variant is timed twice, in two
+ * passes over the list (the second in reverse order); a level's time is the
+ * smaller of its two.  Later tem_factor_poles calls of that precision use
+ * the choice until the next tem_analyse with other options or another mesh.
+ * Leaves the context factored (by the first variant, timed last).
  *   m, xi, prec  as tem_factor_poles;  rep  host, may be NULL.
  * Not available on a batch of meshes. */
 tem_status tem_autotune(tem_ctx *ctx, int32_t m, const double *xi, tem_precision prec,

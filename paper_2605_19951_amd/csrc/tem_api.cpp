@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -2562,10 +2563,17 @@ tem_status tem_autotune(tem_ctx *c, int32_t m, const double *xi, tem_precision p
   else
     cand = {{UPD_T64, false}, {UPD_T64, true}};
   const int nl = (int)c->ed.levels.size();
-  std::vector<std::vector<double>> t(cand.size(), std::vector<double>(nl, 0.0));
+  // t[q][L]: the smaller of two timings of level L under candidate q, taken
+  // in two passes over the candidates, the second in reverse order, so that
+  // neither the first factorisation of the process nor a drift of the clocks
+  // during the runs decides a level.
+  const double unset = std::numeric_limits<double>::infinity();
+  std::vector<std::vector<double>> t(cand.size(), std::vector<double>(nl, unset));
   c->tuned[ip].clear();
   tem_status st = TEM_OK;
-  for (size_t q = 0; q < cand.size() && st == TEM_OK; ++q) {
+  const size_t nq = cand.size();
+  for (size_t run = 0; run < 2 * nq && st == TEM_OK; ++run) {
+    const size_t q = run < nq ? run : 2 * nq - 1 - run;
     c->forcing = true;
     c->forced = cand[q];
     c->lvl_timing = true;
@@ -2573,12 +2581,14 @@ tem_status tem_autotune(tem_ctx *c, int32_t m, const double *xi, tem_precision p
     c->forcing = false;
     c->lvl_timing = false;
     if (st != TEM_OK) break;
+    std::vector<double> lv(nl, 0.0);
     for (int grp = 0; grp < c->n_groups; ++grp)
       for (int L = 0; L < nl; ++L) {
         float ms = 0;
         const size_t e = ((size_t)grp * nl + L) * 2;
-        if (hipEventElapsedTime(&ms, c->lvl_ev[e], c->lvl_ev[e + 1]) == hipSuccess) t[q][L] += ms;
+        if (hipEventElapsedTime(&ms, c->lvl_ev[e], c->lvl_ev[e + 1]) == hipSuccess) lv[L] += ms;
       }
+    for (int L = 0; L < nl; ++L) t[q][L] = std::min(t[q][L], lv[L]);
   }
   if (st != TEM_OK) return st;
   std::vector<tem_ctx::UpdCfg> best(nl);
