@@ -37,6 +37,47 @@ def test_element_matrices_match_quadrature(h):
     assert np.max(np.abs(Ke - Kq)) <= 1e-13 * np.max(np.abs(Kq))
 
 
+@pytest.mark.parametrize("h", [1.0, 25.0])
+def test_element_matrices_closed_form(h):
+    # Closed forms worked out by hand from the 1-D integrals of the linear
+    # hat functions (int phi_a phi_b = h m1[a, b], phi_a' = s_a / h with
+    # s_0 = -1, s_1 = +1), independent of the oracle's basis functions.  An
+    # edge along axis d starting at node offsets o (0/1 per axis) has
+    # N = e_d prod_{t != d} phi_{o_t}(x_t) / h, so
+    #   int N_p . N_q = h prod_{t != d} m1[o_t, o'_t]           (same d)
+    #   mu int curl N_p . curl N_q
+    #     = (1/h) sum_{t != d} s_{o_t} s_{o'_t} m1[o_u, o'_u]   (same d, u the third axis)
+    #     = -(1/h) s_{o_{d'}} s_{o'_d} m1[o_u, o'_u]            (directions d != d', u the third)
+    m1 = np.array([[1.0 / 3.0, 1.0 / 6.0], [1.0 / 6.0, 1.0 / 3.0]])
+    sg = np.array([-1.0, 1.0])
+    mesh = HexMesh(1, 1, 1, h)
+    geo = [mesh.edge_geometry(e) for e in mesh.cell_edges()[0]]
+    Mc = np.zeros((12, 12))
+    Kc = np.zeros((12, 12))
+    for p, (d, *op) in enumerate(geo):
+        for q, (d2, *oq) in enumerate(geo):
+            if d == d2:
+                t1, t2 = [t for t in range(3) if t != d]
+                Mc[p, q] = h * m1[op[t1], oq[t1]] * m1[op[t2], oq[t2]]
+                Kc[p, q] = (sg[op[t1]] * sg[oq[t1]] * m1[op[t2], oq[t2]]
+                            + sg[op[t2]] * sg[oq[t2]] * m1[op[t1], oq[t1]]) / h
+            else:
+                u = 3 - d - d2
+                Kc[p, q] = -sg[op[d2]] * sg[oq[d]] * m1[op[u], oq[u]] / h
+    # the hand derivation itself: symmetric, curl-free on element gradients
+    assert np.array_equal(Kc, Kc.T)
+    Ge = np.zeros((12, 8))
+    for p, (d, i, j, k) in enumerate(geo):
+        a = (i, j, k)
+        b = list(a)
+        b[d] += 1
+        Ge[p, a[0] + 2 * a[1] + 4 * a[2]] -= 1.0
+        Ge[p, b[0] + 2 * b[1] + 4 * b[2]] += 1.0
+    assert np.max(np.abs(Kc @ Ge)) <= 1e-15 / h
+    assert np.max(np.abs(element_mass_unit(h) - Mc)) <= 1e-15 * h
+    assert np.max(np.abs(element_stiffness(h, MU0) * MU0 - Kc)) <= 1e-14 / h
+
+
 def test_basis_degrees_of_freedom_are_line_integrals():
     # int over edge e' of N_e . t_e' = delta_{e e'} (2-point Gauss is exact).
     h = 2.0
