@@ -30,7 +30,7 @@ within the scalar error bound; conjugate-pole symmetry; divergence
 invariants; SuperLU against dense LAPACK solves; adjoint test; Taylor
 slopes 1 and 2; central finite differences; LSQR against SciPy's LSQR and,
 after P iterations on a tiny problem, against the dense least-squares
-solution).
+solution, and on degenerate right-hand sides, b = 0 and A^T b = 0).
 """
 from __future__ import annotations
 
@@ -214,7 +214,10 @@ def first_difference(nx, ny, nz_earth):
 
 def lsqr(matvec, rmatvec, b, n, iters):
     """Plain LSQR (Paige & Saunders 1982), x0 = 0, no damping, fixed number
-    of iterations.  Returns x and the per-iteration estimates of ||r||."""
+    of iterations.  Returns x and the per-iteration estimates of ||r||.
+    When the bidiagonalisation ends (rho = 0: A^T b = 0, or the Krylov space
+    is exhausted) x already solves the problem; it is returned as is and the
+    remaining estimates repeat the last one."""
     x = np.zeros(n)
     u = np.array(b, float)
     beta = np.linalg.norm(u)
@@ -238,6 +241,9 @@ def lsqr(matvec, rmatvec, b, n, iters):
         if alpha > 0:
             v = v / alpha
         rho = math.hypot(rhobar, beta)
+        if rho == 0.0:
+            hist.extend([phibar] * (iters - len(hist)))
+            break
         c = rhobar / rho
         s = beta / rho
         theta = s * alpha

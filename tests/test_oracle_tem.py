@@ -193,6 +193,24 @@ def test_lsqr_matches_scipy_and_lstsq():
     assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
 
 
+def test_lsqr_degenerate_right_hand_sides():
+    # b = 0: x = 0 and a zero residual; A^T b = 0 (b orthogonal to the range
+    # of A): x = 0 is the least-squares solution and ||r|| = ||b|| throughout.
+    # Both end the bidiagonalisation at once (rho = 0), as in SciPy's LSQR.
+    rng = np.random.default_rng(5)
+    A = np.zeros((30, 6))
+    A[:10] = rng.standard_normal((10, 6))
+    x, hist = lsqr(lambda v: A @ v, lambda u: A.T @ u, np.zeros(30), 6, 5)
+    assert np.array_equal(x, np.zeros(6)) and hist == [0.0] * 5
+    b = np.zeros(30)
+    b[10:] = rng.standard_normal(20)
+    x, hist = lsqr(lambda v: A @ v, lambda u: A.T @ u, b, 6, 5)
+    assert np.array_equal(x, np.zeros(6))
+    assert np.allclose(hist, np.linalg.norm(b), rtol=1e-15)
+    xs = spla.lsqr(A, b, atol=0, btol=0, conlim=0, iter_lim=5)[0]
+    assert np.array_equal(xs, np.zeros(6))
+
+
 def test_first_difference_operator():
     R = first_difference(3, 2, 2)
     # faces between earth cells: x: 2*2*2, y: 3*1*2, z: 3*2*1
