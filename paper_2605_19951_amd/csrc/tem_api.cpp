@@ -181,6 +181,9 @@ struct tem_ctx {
   // the nodal factorisation runs on its own stream beside the edge factor
   hipStream_t aux_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // start/end of the device time of a factorisation or solve call (made once
+  // by tem_create, so no error path of those calls leaks events)
+  hipEvent_t t_ev[2] = {nullptr, nullptr};
   DBuf d_ncb0, d_ncb1;                  // nodal contribution-block arenas
   std::vector<double> h_ncoef;          // host copy of the correction coefficients
   struct SweepGraph {
@@ -1486,9 +1489,7 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
   HIPCHK(c->d_cb0.alloc(cb_pole * g), "alloc cb arena");
   HIPCHK(c->d_cb1.alloc(cb_pole * g), "alloc cb arena");
   HIPCHK(hipMemsetAsync(c->d_flags.p, 0, sizeof(int) * 4, c->stream), "clear flags");
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0), "event");
-  HIPCHK(hipEventCreate(&e1), "event");
+  hipEvent_t e0 = c->t_ev[0], e1 = c->t_ev[1];
   if (c->lvl_timing) {
     const size_t need = (size_t)2 * ngroups * c->ed.levels.size();
     while (c->lvl_ev.size() < need) {
@@ -1519,8 +1520,6 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
       s = fail(c, TEM_EDEVICE, "join event");
     if (s != TEM_OK) {
       hipStreamSynchronize(c->aux_stream);
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
       return s;
     }
   }
@@ -1541,8 +1540,6 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
                                   c->d_cb1.as<cpx<float>>());
     if (s != TEM_OK) {
       if (overlap) hipStreamSynchronize(c->aux_stream);
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
       return s;
     }
   }
@@ -1558,8 +1555,6 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
   if (nodal && !overlap) {
     tem_status s = factor_nodal(c);
     if (s != TEM_OK) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
       return s;
     }
   }
@@ -1567,8 +1562,6 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
   HIPCHK(hipEventSynchronize(e1), "factor sync");
   float ms = 0;
   hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   c->factor_ms = ms;
   spans_collect(c);
   int flags[4];
@@ -1782,7 +1775,16 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
   e = c->d_flags.alloc(sizeof(int) * 4);
   if (e != hipSuccess) {
     g_create_error = "tem_create: flags allocation failed";
+    tem_destroy(c.release());
     return TEM_ENOMEM;
+  }
+  for (hipEvent_t &ev : c->t_ev) {
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) {
+      g_create_error = std::string("tem_create: hipEventCreate: ") + hipGetErrorString(e);
+      tem_destroy(c.release());
+      return TEM_EDEVICE;
+    }
   }
   *out = c.release();
   return TEM_OK;
@@ -1802,6 +1804,8 @@ void tem_destroy(tem_ctx *c) {
   if (c->aux_stream) hipStreamDestroy(c->aux_stream);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
   if (c->ev_join) hipEventDestroy(c->ev_join);
+  for (hipEvent_t e : c->t_ev)
+    if (e) hipEventDestroy(e);
   delete c;
   if (own) hipStreamDestroy(st);
 }
@@ -2058,9 +2062,7 @@ tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
                            c->d_fnew.as<double>()),
          "gather f");
   TRY(ensure_vec(c, c->d_g, sizeof(cpx<double>) * (size_t)c->npole * N * S, "alloc g"));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0), "event");
-  HIPCHK(hipEventCreate(&e1), "event");
+  hipEvent_t e0 = c->t_ev[0], e1 = c->t_ev[1];
   HIPCHK(hipEventRecord(e0, st), "event");
   IrResult res;
   tem_status s = refine_solve(c, c->d_fnew.as<double>(), nullptr, S, c->d_g.as<cpx<double>>(), ir, res);
@@ -2068,8 +2070,6 @@ tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
   hipEventSynchronize(e1);
   float ms = 0;
   hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   if (s != TEM_OK) return s;
   c->solve_ms = ms;
   spans_collect(c);
@@ -2137,6 +2137,9 @@ tem_status tem_forward(tem_ctx *c, int32_t S, const double *F, int32_t R, const 
   if (!c->factored) return fail(c, TEM_ESTATE, "tem_forward: call tem_factor_poles first");
   if (!d) return fail(c, TEM_EINVAL, "tem_forward: d is NULL");
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  // the cached solutions and survey belong together: until this call has
+  // both, Jv / J^T w are refused
+  c->surveyed = false;
   TRY(set_survey(c, R, q_ptr, q_col, q_val, K, alpha));
   tem_status s = tem_solve_poles(c, S, F, nullptr, ir, stats);
   if (s != TEM_OK && s != TEM_ENOCONV) return s;
@@ -2296,6 +2299,11 @@ tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const 
     TRY(lsqr_norm(c, P, v, alpha));
     if (alpha > 0) HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 1.0 / alpha, v), "v scale");
     const double rho = std::hypot(rhobar, beta);
+    if (rho == 0) {   // the bidiagonalisation has ended: x solves the problem
+      if (hist)
+        for (int k = it; k < iters; ++k) hist[k] = phibar;
+      break;
+    }
     const double cs = rhobar / rho, sn = beta / rho;
     const double theta = sn * alpha;
     rhobar = -cs * alpha;
@@ -2506,9 +2514,7 @@ tem_status tem_forward_batch(tem_ctx *c, const int32_t *S, const double *F, cons
     fo += sb->mt.n_edges * S[b];
   }
   TRY(ensure_vec(c, c->d_g, sizeof(cpx<double>) * (size_t)MP * N * Smax, "alloc g"));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0), "event");
-  HIPCHK(hipEventCreate(&e1), "event");
+  hipEvent_t e0 = c->t_ev[0], e1 = c->t_ev[1];
   HIPCHK(hipEventRecord(e0, st), "event");
   IrResult res;
   tem_status s = refine_solve(c, c->d_fnew.as<double>(), nullptr, Smax, c->d_g.as<cpx<double>>(),
@@ -2517,8 +2523,6 @@ tem_status tem_forward_batch(tem_ctx *c, const int32_t *S, const double *F, cons
   hipEventSynchronize(e1);
   float ms = 0;
   hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   if (s != TEM_OK) return s;
   c->solve_ms = ms;
   spans_collect(c);

@@ -90,4 +90,12 @@ def test_gauss_newton_step_matches_oracle(prec):
     tol = 1e-9 if prec == 0 else 1e-6
     assert np.linalg.norm(dm.cpu().numpy() - dm_ref) <= tol * np.linalg.norm(dm_ref)
     assert np.allclose(hist, hist_ref, rtol=10 * tol)
+    # degenerate step: the model fits its own data and equals the reference,
+    # so the least-squares right-hand side is zero and LSQR ends at once
+    # (the oracle's LSQR does the same: tests/test_oracle_tem.py)
+    dm.fill_(1.0)
+    hist0 = t.gn_step(d.clone(), torch.tensor(wd.reshape(shp), device=dev), mt, mt.clone(), 1.0,
+                      iters, dm)
+    assert torch.count_nonzero(dm).item() == 0
+    assert np.array_equal(hist0, np.zeros(iters))
     t.close()

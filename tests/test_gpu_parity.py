@@ -224,7 +224,26 @@ def test_state_machine_and_argument_errors():
     assert e.value.status == TEM_EINVAL
     t.factor_poles(wl.poles.xi, 0)
     d = torch.zeros((1, 20, 5), dtype=torch.float64, device=dev)
+    v = torch.zeros(len(wl.params), dtype=torch.float64, device=dev)
     with pytest.raises(TemError) as e:
-        t.jvp(torch.zeros(len(wl.params), dtype=torch.float64, device=dev), d)
+        t.jvp(v, d)
     assert e.value.status == TEM_ESTATE
+    # a forward call that is refused (17 sources) leaves no survey behind:
+    # Jv is refused until a forward call succeeds again
+    F = torch.tensor(wl.F.T.copy(), device=dev)
+    K, R = len(wl.poles.t), wl.rx.n
+    d = torch.zeros((wl.S, K, R), dtype=torch.float64, device=dev)
+    t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+    jv = torch.zeros_like(d)
+    t.jvp(v, jv)
+    F17 = F[:1].repeat(17, 1).contiguous()
+    d17 = torch.zeros((17, K, R), dtype=torch.float64, device=dev)
+    with pytest.raises(TemError) as e:
+        t.forward(F17, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d17)
+    assert e.value.status == TEM_EINVAL
+    with pytest.raises(TemError) as e:
+        t.jvp(v, jv)
+    assert e.value.status == TEM_ESTATE
+    t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+    t.jvp(v, jv)
     t.close()
