@@ -688,7 +688,8 @@ hipError_t launch_bwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 // Blocks of columns [cb, ce) from the last to the first.  With init the
 // right-hand side of each block is D^{-1} y - t (the whole triangle in one
 // launch when cb = 0 and BB >= k); without, X already holds that value
-// minus the contributions of the rows below ce (k_bwd_init + k_bwd_cols).
+// minus the contributions of the rows below ce (k_bwd_init, then the
+// column mode of k_bwd_rect_mfma).
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl_nodes, int S,
                                                  int64_t N, const cpx<T> *factor,
