@@ -238,7 +238,10 @@ tem_status tem_solve_poles(tem_ctx *ctx, int32_t nrhs, const double *F, double *
  *          (int64), q_col[nnz] (int32), q_val[nnz] (double).  Copied.
  *   alpha  host, K x m complex (re, im interleaved; time slowest).  Copied.
  *   d      device, S*K*R doubles, layout [s][j][r].
- * Also fixes S, Q and alpha for later tem_jvp / tem_vjp calls. */
+ * Also fixes S, Q and alpha for later tem_jvp / tem_vjp calls.  A call
+ * that fails while taking the new Q and alpha or while solving drops the
+ * cached survey: tem_jvp, tem_vjp and tem_gn_step return TEM_ESTATE until a
+ * tem_forward succeeds (or ends in TEM_ENOCONV, which still fills d). */
 tem_status tem_forward(tem_ctx *ctx, int32_t S, const double *F, int32_t R,
                        const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
                        int32_t K, const double *alpha, const tem_ir_opts *ir, double *d,
@@ -271,7 +274,11 @@ tem_status tem_vjp(tem_ctx *ctx, const double *w, double *jtw, const tem_ir_opts
  *   m, m_ref    device, P doubles
  *   dm          device, P doubles (output; the step, m is not updated)
  *   hist        host, iters doubles or NULL: LSQR residual estimate per iteration
- *   ir          refinement options of the inner solves (may be NULL) */
+ *   ir          refinement options of the inner solves (may be NULL)
+ * When the bidiagonalisation ends early (rho = 0, e.g. a zero right-hand
+ * side) the iterate is the least-squares solution: LSQR stops there and the
+ * remaining hist entries repeat the last estimate.  A refinement that misses
+ * its tolerance inside a J v or J^T w returns TEM_ENOCONV. */
 tem_status tem_gn_step(tem_ctx *ctx, const double *d_obs, const double *wd, const double *m,
                        const double *m_ref, double lambda, int32_t iters, double *dm,
                        double *hist, const tem_ir_opts *ir);
