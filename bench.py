@@ -6,8 +6,8 @@ assemble M(sigma) on the device, factor all 16 shifted matrices, solve all
 poles x sources with FP64 refinement to 1e-10, assemble the data at all
 times, then one J v and one J^T w through the cached factors.
 
-Reported (BASELINE metric "all-pole factor+solve s & J^T v/s at 64^3, FP32+IR
-vs FP64, same GPU"): value = factor+solve seconds of the FP32+IR path
+Reported metric "all-pole factor+solve s & J^T v/s at 64^3, FP32+IR vs FP64,
+same GPU": value = factor+solve seconds of the FP32+IR path
 (median over the timed steps); J^T v per second and the FP64 figures are in
 ``phases``.  The roofline object covers the dominant kernel (the MFMA front
 update, FP32) from HIP events inside the library; the CPU baseline is the
