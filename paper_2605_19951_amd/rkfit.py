@@ -88,21 +88,15 @@ def _real_fractions(z, xi):
     return out
 
 
-def _orth(X):
-    q, r = np.linalg.qr(X)
-    return q, r
-
-
 def relocate(z, b, targets, xi):
     """One RKFIT step: new pole pairs from the pairs xi.
 
     z (N,) sample points, b (N,) weights, targets (K, N) values F_j(z_k).
     Returns (new xi with Im > 0, sigma_min, the real roots found if any)."""
-    p = len(xi)
     Phi_m = b[:, None] * _real_fractions(z, xi)             # spans W_m
     Phi = np.hstack([b[:, None], Phi_m])                     # spans W_{m+1}
-    Q, R = _orth(Phi)
-    Vm, _ = _orth(Phi_m)
+    Q, R = np.linalg.qr(Phi)
+    Vm, _ = np.linalg.qr(Phi_m)
     blocks = []
     for f in targets:
         FQ = f[:, None] * Q
@@ -126,10 +120,10 @@ def _roots(c0, a, bb, xi):
     conj(xi_k)) with C_k = (a_k - i bb_k)/2, whose roots are the eigenvalues of
     diag(P) - (C / c0) 1^T (P the poles).  The similarity by the blocks
     [[1, 1], [-i, i]] / sqrt 2 of each conjugate pair makes that matrix real:
-    per pair the block [[Re xi, -Im xi], [Im xi, Re xi]], minus the rank-one
-    term whose column 2k holds (a_k, -bb_k) / c0 in the rows of every pair and
-    whose column 2k+1 is zero.  A real matrix has exactly conjugate complex
-    eigenvalues and exactly real ones."""
+    the blocks [[Re xi_k, -Im xi_k], [Im xi_k, Re xi_k]] on the diagonal, minus
+    u e^T, where u holds (a_k, -bb_k) / c0 in the two rows of pair k and e is
+    1 in the first column of every pair and 0 in the second.  A real matrix
+    has exactly conjugate complex eigenvalues and exactly real ones."""
     p = len(xi)
     Mr = np.zeros((2 * p, 2 * p))
     for k, x in enumerate(xi):
