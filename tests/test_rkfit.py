@@ -71,6 +71,20 @@ def test_exp_table_error_and_gain_over_the_contour(p):
     assert tab.err.max() * gain <= contour.err.max()
 
 
+@pytest.mark.parametrize("p", [4, 6])
+def test_real_roots_end_the_iteration_with_a_valid_table(p):
+    # With few pairs a step's denominator can have real roots, which the
+    # 2 Re form cannot hold: the iteration stops and returns the best
+    # conjugate-pair iterate so far (the start included).
+    t = ti.log_times(1e-5, 1e-2, 60)
+    tab = rkfit.rkfit_exp(t, p)
+    assert tab.info["stop"] == "real poles"
+    assert np.all(tab.xi.imag > 0) and tab.alpha.shape == (60, p)
+    fits = tab.info["misfits"]
+    assert fits[tab.info["best_step"]] == min(fits)
+    assert tab.err.max() <= ti.pole_table(p, 1e-5, 1e-2, 60).err.max() * 1.05
+
+
 def test_rkfit_table_drives_the_oracle_within_the_scalar_bound():
     """The oracle's u(t) = 2 Re sum_i alpha_i (K - xi_i M)^{-1} f with an RKFIT
     table equals r_t(M^{-1} K) b, so its M-norm error against the exact
