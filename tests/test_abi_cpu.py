@@ -29,7 +29,11 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("dims,leaf", [((8, 8, 8), 4), ((10, 9, 7), 4), ((16, 16, 16), 4),
-                                       ((18, 18, 18), 4), ((12, 6, 9), 3), ((5, 5, 5), 2)])
+                                       ((18, 18, 18), 4), ((12, 6, 9), 3), ((5, 5, 5), 2),
+                                       # edge cases: the smallest mesh, leaf size 1 (empty
+                                       # separators), one supernode, a thin column of cells
+                                       ((2, 2, 2), 4), ((2, 3, 4), 1), ((6, 6, 6), 1000),
+                                       ((2, 2, 9), 2)])
 def test_symbolic_bit_exact_against_oracle(dims, leaf):
     from paper_2605_19951_amd import symbolic_host
     lib = symbolic_host(*dims, leaf_max=leaf)
