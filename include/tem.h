@@ -100,8 +100,9 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream);
 /* Free every library allocation of ctx.  NULL-safe. */
 void tem_destroy(tem_ctx *ctx);
 
-/* Text of the last error on ctx (or of the last failed tem_create when ctx
- * is NULL).  Valid until the next call on ctx. */
+/* Text of the last error on ctx (or, when ctx is NULL, of the calling
+ * thread's last failed tem_create).  Valid until the next call on ctx (or
+ * the thread's next tem_create). */
 const char *tem_last_error(const tem_ctx *ctx);
 
 /* ------------------------------------------------------------- assembly */

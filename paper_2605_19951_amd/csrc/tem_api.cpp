@@ -23,7 +23,8 @@ using namespace tem;
 
 namespace {
 
-std::string g_create_error;
+// text of the calling thread's last failed tem_create
+thread_local std::string g_create_error;
 
 // ------------------------------------------------------------ device buffer
 struct DBuf {
