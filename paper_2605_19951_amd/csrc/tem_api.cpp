@@ -2118,7 +2118,7 @@ static tem_status set_survey(tem_ctx *c, int R, const int64_t *q_ptr, const int3
     }
     qp[r + 1] = (int64_t)qc.size();
   }
-  for (int i = 0; i < 2 * K * c->npole; ++i)
+  for (int64_t i = 0; i < 2 * (int64_t)K * c->npole; ++i)
     if (!std::isfinite(alpha[i])) return fail(c, TEM_EINVAL, "tem_forward: non-finite residue");
   std::vector<double> al(alpha, alpha + 2 * (size_t)K * c->npole);
   HIPCHK(upload(c->d_qptr, qp, c->stream), "upload q_ptr");
