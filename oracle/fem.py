@@ -12,9 +12,11 @@ line integrals of E along the edges.
 
 Pins (tests/test_oracle_fem.py): element matrices against tensor Gauss
 quadrature of the explicitly written basis functions; the discrete de Rham
-identities curl(grad) = 0 and K grad = 0; symmetry and definiteness of M;
-the exact physics of the whole-space step-off dipole (through the forward
-map, tests/test_oracle_physics.py).
+identities curl(grad) = 0 and K grad = 0; symmetry and definiteness of M.
+Through the forward map of ``oracle.tem``, the exact whole-space step-off
+transient of a square loop (closed form from the diffusion Green's function)
+pins K, M, mu and the seeded source and receiver rows at two resolutions,
+with an error that falls under refinement (tests/test_oracle_physics.py).
 """
 from __future__ import annotations
 

@@ -146,19 +146,21 @@ def earth_cells(mesh: Mesh) -> np.ndarray:
 # --------------------------------------------------------------------------
 # sources: square loops on the interface plane
 # --------------------------------------------------------------------------
-def loop_edges(mesh: Mesh, cx: int, cy: int):
-    """Edges and signs of a 2x2-cell square loop on node plane k_if spanning
-    nodes [cx-1, cx+1] x [cy-1, cy+1], counter-clockwise seen from +z."""
+def loop_edges(mesh: Mesh, cx: int, cy: int, half: int = 1):
+    """Edges and signs of a square loop of 2*half x 2*half cells on node
+    plane k_if spanning nodes [cx-half, cx+half] x [cy-half, cy+half],
+    counter-clockwise seen from +z (the workloads use half = 1: a 2x2-cell
+    loop)."""
     k = mesh.k_if
     out = []
-    for i in (cx - 1, cx):                      # y = cy-1, +x
-        out.append((mesh.xedge(i, cy - 1, k), +1.0))
-    for j in (cy - 1, cy):                      # x = cx+1, +y
-        out.append((mesh.yedge(cx + 1, j, k), +1.0))
-    for i in (cx, cx - 1):                      # y = cy+1, -x
-        out.append((mesh.xedge(i, cy + 1, k), -1.0))
-    for j in (cy, cy - 1):                      # x = cx-1, -y
-        out.append((mesh.yedge(cx - 1, j, k), -1.0))
+    for i in range(cx - half, cx + half):           # y = cy-half, +x
+        out.append((mesh.xedge(i, cy - half, k), +1.0))
+    for j in range(cy - half, cy + half):           # x = cx+half, +y
+        out.append((mesh.yedge(cx + half, j, k), +1.0))
+    for i in range(cx + half - 1, cx - half - 1, -1):   # y = cy+half, -x
+        out.append((mesh.xedge(i, cy + half, k), -1.0))
+    for j in range(cy + half - 1, cy - half - 1, -1):   # x = cx-half, -y
+        out.append((mesh.yedge(cx - half, j, k), -1.0))
     return out
 
 
@@ -178,13 +180,14 @@ def seeded_loop_centres(mesh: Mesh, rng, n_loops: int, margin=3):
     return cs
 
 
-def source_matrix(mesh: Mesh, centres, current=1.0):
+def source_matrix(mesh: Mesh, centres, current=1.0, half=1):
     """f for each loop as a dense (n_edges, S) float64 array in canonical
     edge numbering: +/- current on loop edges (the line integral of the
-    source trace against each edge basis function), zero elsewhere."""
+    source trace against each edge basis function), zero elsewhere.  Loops
+    have 2*half x 2*half cells."""
     F = np.zeros((mesh.n_edges, len(centres)))
     for s, (cx, cy) in enumerate(centres):
-        for e, sg in loop_edges(mesh, cx, cy):
+        for e, sg in loop_edges(mesh, cx, cy, half):
             F[e, s] += sg * current
     return F
 
@@ -224,6 +227,14 @@ def _csr(rows):
                      np.asarray(val, np.float64), "")
 
 
+def edge_receivers_at(mesh: Mesh, edges):
+    """Tangential-E receivers: mean field along each given edge (row =
+    e^T / h, since the degree of freedom is the line integral)."""
+    r = _csr([[(int(e), 1.0 / mesh.h)] for e in edges])
+    r.kind = "edge"
+    return r
+
+
 def edge_receivers(mesh: Mesh):
     """Five tangential-E receivers: mean field along y-edges on the
     interface plane (row = e^T / h) at j = ny/2-1 and i in {1, 2, nx-2,
@@ -232,30 +243,32 @@ def edge_receivers(mesh: Mesh):
     k = mesh.k_if
     es = [mesh.yedge(i, j, k) for i in (1, 2, mesh.nx - 2, mesh.nx - 1)]
     es.append(mesh.yedge(mesh.nx - 2, j, k - 1))
-    r = _csr([[(e, 1.0 / mesh.h)] for e in es])
-    r.kind = "edge"
+    return edge_receivers_at(mesh, es)
+
+
+def bz_receivers_at(mesh: Mesh, faces):
+    """dB_z/dt receivers on the given horizontal interface faces (ci, cj)
+    (the face spans nodes [ci, ci+1] x [cj, cj+1] on plane k_if).  The row
+    is -(circulation of E around the face, counter-clockwise from +z) / h^2,
+    since dB/dt = -curl E and the edge degrees of freedom are line
+    integrals: the face mean of dB_z/dt."""
+    k = mesh.k_if
+    w = 1.0 / (mesh.h * mesh.h)
+    rows = [[(mesh.xedge(ci, cj, k), -w),
+             (mesh.yedge(ci + 1, cj, k), -w),
+             (mesh.xedge(ci, cj + 1, k), +w),
+             (mesh.yedge(ci, cj, k), +w)] for (ci, cj) in faces]
+    r = _csr(rows)
+    r.kind = "bz"
     return r
 
 
 def bz_receivers(mesh: Mesh, g: int):
     """g x g grid of dB_z/dt receivers on horizontal interface faces with
-    two-cell spacing around the mesh centre.  On face (ci, cj) the row is
-    -(circulation of E around the face) / h^2, since dB/dt = -curl E and the
-    edge degrees of freedom are line integrals."""
-    k = mesh.k_if
-    rows = []
-    w = 1.0 / (mesh.h * mesh.h)
-    for b in range(g):
-        for a in range(g):
-            ci = mesh.nx // 2 + 2 * a - g
-            cj = mesh.ny // 2 + 2 * b - g
-            rows.append([(mesh.xedge(ci, cj, k), -w),
-                         (mesh.yedge(ci + 1, cj, k), -w),
-                         (mesh.xedge(ci, cj + 1, k), +w),
-                         (mesh.yedge(ci, cj, k), +w)])
-    r = _csr(rows)
-    r.kind = "bz"
-    return r
+    two-cell spacing around the mesh centre (rows as ``bz_receivers_at``)."""
+    faces = [(mesh.nx // 2 + 2 * a - g, mesh.ny // 2 + 2 * b - g)
+             for b in range(g) for a in range(g)]
+    return bz_receivers_at(mesh, faces)
 
 
 # --------------------------------------------------------------------------
