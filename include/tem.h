@@ -85,9 +85,11 @@ typedef enum {
 
 typedef enum {
   TEM_FP64 = 0,     /* complex FP64 factors, FP64 solves, FP64 refinement */
-  TEM_FP32_IR = 1   /* complex FP32 factors; FP64 residuals and GMRES-based
-                       iterative refinement (preconditioned by the FP32
-                       factors) */
+  TEM_FP32_IR = 1   /* complex FP32 factors; classical iterative refinement
+                       on FP64 residuals, each FP32 solve followed by the
+                       FP64 Galerkin correction on the gradient space
+                       z += G (G^T A G)^{-1} G^T (r - A z) (one real nodal
+                       factor of G^T M G serves every pole, since K G = 0) */
 } tem_precision;
 
 /* ---------------------------------------------------------------- context */
@@ -208,8 +210,7 @@ tem_status tem_factor_poles(tem_ctx *ctx, int32_t m, const double *xi, tem_preci
 typedef struct {
   double rtol;          /* target ||f - A x||_2 / ||f||_2 per system (<= 0: 1e-10) */
   int32_t max_iter;     /* max refinement solves per system (<= 0: 200) */
-  int32_t restart;      /* GMRES restart length in FP32 mode (<= 0: 30, max 60);
-                           1 gives classical iterative refinement */
+  int32_t reserved;     /* ignored */
 } tem_ir_opts;
 
 typedef struct {
@@ -221,7 +222,9 @@ typedef struct {
 
 /* g_is = A_i^{-1} f_s for every pole i and right-hand side s, refined in
  * FP64 to ir->rtol (Algorithm 1, "compute A_i^{-1} f"); caches g for
- * tem_jvp / tem_vjp.
+ * tem_jvp / tem_vjp.  Up to 16 right-hand sides share one pass over the
+ * factors; more (up to 1024) are solved in equal blocks of at most 16.
+ *   nrhs 1..1024.
  *   F    device, n_edges x nrhs doubles, column-major (column s = f_s).
  *   G    device or NULL: m x nrhs x n_edges complex doubles (interleaved
  *        re, im; pole slowest, edge fastest); boundary edges get 0.

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_residual(int64_t N, int npole, int S,
     const cpx<double> *X = x + (int64_t)pc * N * S + c;
     double ar = 0.0, ai = 0.0;
 #pragma unroll 4
-    for (int64_t t = t0; t < t1; ++t) {
+    for (int64_t t = x ? t0 : t1; t < t1; ++t) {
       const double kv = Kv[t], mv = Mv[t];
       const cpx<double> v = X[(int64_t)col[t] * S];
       // (K - xi M) v, xi M v = (xr + i xim) mv v
@@ -150,15 +150,6 @@ hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const in
   if (N <= 0 || npole <= 0 || S < 1 || S > 64) return N <= 0 || npole <= 0 ? hipSuccess : hipErrorInvalidValue;
   hipLaunchKernelGGL(k_residual, dim3(xcd_grid(N * 64, 256)), dim3(256), 0, st, N, npole, S,
                      rowptr, col, Kv, Mv, xi, sg, f_real, f_cplx, x, r, 1);
-  return hipGetLastError();
-}
-
-hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
-                               const int32_t *col, const double *Kv, const double *Mv,
-                               const double *xi, Seg sg, const cpx<double> *x, cpx<double> *y) {
-  if (N <= 0 || npole <= 0 || S < 1 || S > 64) return N <= 0 || npole <= 0 ? hipSuccess : hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(N * 64, 256)), dim3(256), 0, st, N, npole, S,
-                     rowptr, col, Kv, Mv, xi, sg, nullptr, nullptr, x, y, 0);
   return hipGetLastError();
 }
 
@@ -259,24 +250,23 @@ hipError_t launch_batched_axpy(hipStream_t st, int64_t N, int npole, int S,
   return hipGetLastError();
 }
 
-__global__ void k_scale(int64_t N, int npole, int S, const double *scale, cpx<double> *x) {
+// dst[row * ldd + d0 + j] = j < cnt ? src[row * lds + s0 + j] : 0 for
+// j < width (columns of row-major blocks, counted in doubles)
+__global__ void k_copy_cols(int64_t rows, const double *src, int lds, int s0, int cnt, double *dst,
+                            int ldd, int d0, int width) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = N * npole * S;
-  if (idx >= tot) return;
-  const int c = (int)(idx % S);
-  const int p = (int)(idx / ((int64_t)N * S));
-  const double s = scale[p * S + c];
-  cpx<double> v = x[idx];
-  v.re *= s;
-  v.im *= s;
-  x[idx] = v;
+  if (idx >= rows * width) return;
+  const int64_t row = idx / width;
+  const int j = (int)(idx % width);
+  dst[row * ldd + d0 + j] = j < cnt ? src[row * lds + s0 + j] : 0.0;
 }
 
-hipError_t launch_batched_scale(hipStream_t st, int64_t N, int npole, int S, const double *scale,
-                                cpx<double> *x) {
-  const int64_t tot = N * npole * S;
-  hipLaunchKernelGGL(k_scale, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     scale, x);
+hipError_t launch_copy_cols(hipStream_t st, int64_t rows, const double *src, int lds, int s0,
+                            int cnt, double *dst, int ldd, int d0, int width) {
+  if (rows <= 0 || width <= 0) return hipSuccess;
+  if (cnt > width || s0 + cnt > lds || d0 + width > ldd) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy_cols, dim3(grid_1d(rows * width, 256, 1 << 30)), dim3(256), 0, st,
+                     rows, src, lds, s0, cnt, dst, ldd, d0, width);
   return hipGetLastError();
 }
 

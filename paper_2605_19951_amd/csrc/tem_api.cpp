@@ -231,9 +231,8 @@ struct tem_ctx {
   DBuf l_u, l_v, l_w, l_x, l_tmpd, l_tmpm, l_part, l_scal;
   // work space
   DBuf w_x;                        // factor-precision sweep vector
-  DBuf v_r, v_z, v_x, v_w, v_rhs, v_lam, v_vs, v_dots, v_partial, v_inv, v_nrm, v_coef, v_mask;
-  DBuf v_basis, v_aux;
-  int basis_len = 0;
+  DBuf v_r, v_z, v_rhs, v_lam, v_vs, v_dots, v_partial, v_inv, v_nrm, v_coef, v_mask;
+  DBuf v_aux, v_fblk, v_xblk;
   // profiling (HIP events around the update launches and the sweeps)
   bool profile = false;
   std::vector<hipEvent_t> ev_pool;
@@ -1096,12 +1095,15 @@ struct IrResult {
   int solves = 0;
 };
 
-// Solve A_p x_ps = f_ps for all systems.  f either real [N][S] (same for
-// all poles) or complex [pole][N][S].  x: [pole][N][S] complex double.
-// FP64 factors: classical refinement.  FP32 factors: restarted GMRES in
-// FP64 right-preconditioned by the FP32 factors (GMRES-based iterative
-// refinement), restart = 1 being classical refinement.
-tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_cplx, int S,
+// Solve A_p x_ps = f_ps for all systems by classical iterative refinement
+// (S <= 16).  f either real [N][S] (same for all poles) or complex
+// [pole][N][S]; x: [pole][N][S] complex double.  Each step computes the FP64
+// residual r = f - A_p x, judges ||r|| / ||f|| per system against rtol,
+// solves A_p z = r through the cached factors (FP32 factors: followed by
+// the gradient-space correction) and adds z to x.  Only the contiguous runs
+// of pole slots that still hold an unconverged system are swept, corrected
+// and have their residual recomputed; converged systems keep x and r.
+tem_status refine_block(tem_ctx *c, const double *f_real, const cpx<double> *f_cplx, int S,
                         cpx<double> *x, const tem_ir_opts *ir, IrResult &res) {
   hipStream_t st = c->stream;
   const int64_t N = N_of(c);
@@ -1109,17 +1111,9 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
   const int mS = m * S;
   const double rtol = (ir && ir->rtol > 0) ? ir->rtol : 1e-10;
   const int max_iter = (ir && ir->max_iter > 0) ? ir->max_iter : 200;
-  int restart = (ir && ir->restart > 0) ? ir->restart : 30;
-  restart = std::min(restart, 60);
-  // FP64 factors: classical refinement.  FP32 factors with the gradient-space
-  // correction: classical refinement unless GMRES is asked for explicitly.
-  if (c->prec == TEM_FP64) restart = 1;
-  if (c->prec == TEM_FP32_IR && c->aux && c->nodal_ready && !(ir && ir->restart > 1)) restart = 1;
-  if (c->B > 0) restart = 1;   // batches: classical refinement only
   const size_t vbytes = sizeof(cpx<double>) * (size_t)mS * N;
   TRY(ensure_vec(c, c->v_r, vbytes, "alloc r"));
   TRY(ensure_vec(c, c->v_z, vbytes, "alloc z"));
-  TRY(ensure_vec(c, c->v_w, vbytes, "alloc w"));
   // systems: [mesh][pole][s] (one mesh unless a batch); absent poles of a
   // mesh in a batch are padding and never active
   const int nsys = n_seg(c) * mS;
@@ -1128,206 +1122,113 @@ tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_c
     for (int b = 0; b < c->B; ++b)
       for (int p = c->np_mesh[b]; p < m; ++p)
         for (int q = 0; q < S; ++q) pad[(size_t)b * mS + p * S + q] = 1;
-  TRY(ensure_vec(c, c->v_coef, sizeof(cpx<double>) * (size_t)mS * 2, "alloc coef"));
+  TRY(ensure_vec(c, c->v_coef, sizeof(cpx<double>) * (size_t)mS, "alloc coef"));
   TRY(ensure_vec(c, c->v_mask, sizeof(int) * (size_t)nsys, "alloc mask"));
   cpx<double> *r = c->v_r.as<cpx<double>>();
   cpx<double> *z = c->v_z.as<cpx<double>>();
-  cpx<double> *w = c->v_w.as<cpx<double>>();
   const double *xi = c->d_xi.as<double>();
-  // x = 0, so that r = f and ||r|| = ||f||
-  std::vector<double> fn;
-  HIPCHK(launch_fill_f64(st, (double *)x, 2 * (int64_t)mS * N, 0.0), "zero x");
   const Seg rs = row_seg(c);
-  HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                         c->d_K.as<double>(), c->d_M.as<double>(), xi, rs, f_real, f_cplx, x, r),
-         "residual");
+  auto residual = [&](const std::vector<PoleRun> &runs, const cpx<double> *xv) -> tem_status {
+    for (const PoleRun &pr : runs) {
+      // the shift table is [mesh][pole]: offsetting it by p0 keeps the
+      // (mesh, p0 + p) entry under index mesh * stride + p
+      const int64_t o = (int64_t)pr.p0 * N * S;
+      HIPCHK(launch_residual(st, N, pr.n, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
+                             c->d_K.as<double>(), c->d_M.as<double>(), xi + 2 * pr.p0, rs, f_real,
+                             f_cplx ? f_cplx + o : nullptr, xv ? xv + o : nullptr, r + o),
+             "residual");
+    }
+    return TEM_OK;
+  };
+  // x = 0, so that r = f and ||r|| = ||f||
+  HIPCHK(launch_fill_f64(st, (double *)x, 2 * (int64_t)mS * N, 0.0), "zero x");
+  TRY(residual(all_poles(c), nullptr));
+  std::vector<double> fn;
   TRY(sysnorms(c, r, S, fn));
   res.iters.assign(nsys, 0);
   res.rel.assign(nsys, 0.0);
   std::vector<int> active(nsys, 1);
   for (int i = 0; i < nsys; ++i)
     if (fn[i] == 0.0 || pad[i]) active[i] = 0;
+  {
+    std::vector<cpx<double>> one(mS, {1.0, 0.0});
+    HIPCHK(h2d(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS, st), "coef");
+  }
   int solves = 0;
-  if (restart <= 1) {
-    // classical refinement
-    for (int it = 0; it <= max_iter; ++it) {
-      std::vector<double> rn;
-      TRY(sysnorms(c, r, S, rn));
-      bool any = false;
-      for (int i = 0; i < nsys; ++i) {
-        res.rel[i] = (fn[i] > 0 && !pad[i]) ? rn[i] / fn[i] : 0.0;
-        if (active[i] && res.rel[i] <= rtol) active[i] = 0;
-        any = any || active[i];
-      }
-      if (!any || it == max_iter) break;
-      HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * nsys, st),
-             "mask");
-      TRY(precond(c, r, z, S, active_runs(c, active, S)));
-      ++solves;
-      for (int i = 0; i < nsys; ++i)
-        if (active[i]) res.iters[i]++;
-      std::vector<cpx<double>> one(mS, {1.0, 0.0});
-      HIPCHK(h2d(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS, st),
-             "coef");
-      HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
-                                 c->v_mask.as<int>(), rs),
-             "x += z");
-      HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                             c->d_K.as<double>(), c->d_M.as<double>(), xi, rs, f_real, f_cplx, x,
-                             r),
-             "residual");
+  std::vector<double> rn = fn;
+  for (int it = 0; it <= max_iter; ++it) {
+    bool any = false;
+    for (int i = 0; i < nsys; ++i) {
+      res.rel[i] = (fn[i] > 0 && !pad[i]) ? rn[i] / fn[i] : 0.0;
+      if (active[i] && res.rel[i] <= rtol) active[i] = 0;
+      any = any || active[i];
     }
-  } else {
-    // GMRES(restart) with right preconditioning, all systems in lock step
-    const int kmax = restart;
-    TRY(ensure_vec(c, c->v_basis, vbytes * (size_t)(kmax + 1), "alloc krylov basis"));
-    cpx<double> *V = c->v_basis.as<cpx<double>>();
-    const int64_t vs = (int64_t)mS * N;
-    const int nb = dot_blocks(N);
-    TRY(ensure_vec(c, c->v_partial, sizeof(cpx<double>) * (size_t)nb * mS * 2, "alloc partial"));
-    TRY(ensure_vec(c, c->v_dots, sizeof(cpx<double>) * (size_t)mS * 64, "alloc dots"));
-    TRY(ensure_vec(c, c->v_inv, sizeof(double) * mS, "alloc inv"));
-    TRY(ensure_vec(c, c->v_nrm, sizeof(double) * mS, "alloc nrm"));
-    cpx<double> *dots = c->v_dots.as<cpx<double>>();
-    typedef std::complex<double> cd;
-    int total = 0;
-    while (true) {
-      std::vector<double> rn;
-      TRY(sysnorms(c, r, S, rn));
-      bool any = false;
-      for (int i = 0; i < mS; ++i) {
-        res.rel[i] = fn[i] > 0 ? rn[i] / fn[i] : 0.0;
-        if (active[i] && res.rel[i] <= rtol) active[i] = 0;
-        any = any || active[i];
-      }
-      if (!any || total >= max_iter) break;
-      // V0 = r / ||r||
-      std::vector<double> inv(mS);
-      for (int i = 0; i < mS; ++i) inv[i] = rn[i] > 0 ? 1.0 / rn[i] : 0.0;
-      HIPCHK(hipMemcpyAsync(V, r, vbytes, hipMemcpyDeviceToDevice, st), "V0");
-      HIPCHK(h2d(c->v_inv.p, inv.data(), sizeof(double) * mS, st),
-             "inv");
-      HIPCHK(launch_batched_scale(st, N, m, S, c->v_inv.as<double>(), V), "V0 scale");
-      // Hessenberg per system (column-major (kmax+1) x kmax), Givens
-      std::vector<cd> H((size_t)mS * (kmax + 1) * kmax, cd(0, 0));
-      std::vector<cd> cs((size_t)mS * kmax), sn((size_t)mS * kmax);
-      std::vector<cd> gvec((size_t)mS * (kmax + 1), cd(0, 0));
-      for (int i = 0; i < mS; ++i) gvec[(size_t)i * (kmax + 1)] = cd(rn[i], 0);
-      int kdone = 0;
-      std::vector<cpx<double>> hcol((size_t)mS * (kmax + 1));
-      for (int k = 0; k < kmax && total < max_iter; ++k) {
-        TRY(precond(c, V + k * vs, z, S, all_poles(c)));
-        ++solves;
-        ++total;
-        HIPCHK(launch_spmv_shifted(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                                   c->d_K.as<double>(), c->d_M.as<double>(), xi, rs, z, w),
-               "A z");
-        // modified Gram-Schmidt, twice (reorthogonalisation)
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int j = 0; j <= k; ++j) {
-            HIPCHK(launch_batched_dot(st, N, m, S, N * S, V + j * vs, w, true,
-                                      c->v_partial.as<cpx<double>>(), nb, dots + j * mS),
-                   "mgs dot");
-            HIPCHK(launch_batched_axpy(st, N, m, S, dots + j * mS, -1.0, V + j * vs, w, nullptr),
-                   "mgs axpy");
-          }
-          HIPCHK(hipMemcpyAsync(hcol.data(), dots,
-                                sizeof(cpx<double>) * (size_t)mS * (k + 1), hipMemcpyDeviceToHost,
-                                st),
-                 "h d2h");
-          HIPCHK(hipStreamSynchronize(st), "h sync");
-          for (int j = 0; j <= k; ++j)
-            for (int i = 0; i < mS; ++i) {
-              const cpx<double> hv = hcol[(size_t)j * mS + i];
-              H[((size_t)i * kmax + k) * (kmax + 1) + j] += cd(hv.re, hv.im);
-            }
-        }
-        std::vector<double> wn;
-        TRY(sysnorms(c, w, S, wn));
-        std::vector<double> winv(mS);
-        for (int i = 0; i < mS; ++i) {
-          H[((size_t)i * kmax + k) * (kmax + 1) + k + 1] = cd(wn[i], 0);
-          winv[i] = wn[i] > 0 ? 1.0 / wn[i] : 0.0;
-        }
-        HIPCHK(hipMemcpyAsync(V + (k + 1) * vs, w, vbytes, hipMemcpyDeviceToDevice, st), "V k+1");
-        HIPCHK(h2d(c->v_inv.p, winv.data(), sizeof(double) * mS, st),
-               "winv");
-        HIPCHK(launch_batched_scale(st, N, m, S, c->v_inv.as<double>(), V + (k + 1) * vs),
-               "V scale");
-        // Givens per system
-        bool all_small = true;
-        for (int i = 0; i < mS; ++i) {
-          cd *h = &H[((size_t)i * kmax + k) * (kmax + 1)];
-          for (int j = 0; j < k; ++j) {
-            cd a = h[j], b = h[j + 1];
-            h[j] = std::conj(cs[(size_t)i * kmax + j]) * a + std::conj(sn[(size_t)i * kmax + j]) * b;
-            h[j + 1] = -sn[(size_t)i * kmax + j] * a + cs[(size_t)i * kmax + j] * b;
-          }
-          cd a = h[k], b = h[k + 1];
-          double den = std::sqrt(std::norm(a) + std::norm(b));
-          cd cc = den > 0 ? a / den : cd(1, 0), ss = den > 0 ? b / den : cd(0, 0);
-          cs[(size_t)i * kmax + k] = cc;
-          sn[(size_t)i * kmax + k] = ss;
-          h[k] = std::conj(cc) * a + std::conj(ss) * b;
-          h[k + 1] = 0;
-          cd g0 = gvec[(size_t)i * (kmax + 1) + k];
-          gvec[(size_t)i * (kmax + 1) + k] = std::conj(cc) * g0;
-          gvec[(size_t)i * (kmax + 1) + k + 1] = -ss * g0;
-          if (active[i] && std::abs(gvec[(size_t)i * (kmax + 1) + k + 1]) > 0.5 * rtol * fn[i])
-            all_small = false;
-        }
-        for (int i = 0; i < mS; ++i)
-          if (active[i]) res.iters[i]++;
-        kdone = k + 1;
-        if (all_small) break;
-      }
-      // y = R^{-1} g per system; update u = V y; x += M^{-1} u
-      std::vector<cd> Y((size_t)mS * kdone, cd(0, 0));
-      for (int i = 0; i < mS; ++i) {
-        if (!active[i]) continue;
-        for (int j = kdone - 1; j >= 0; --j) {
-          cd acc = gvec[(size_t)i * (kmax + 1) + j];
-          for (int l = j + 1; l < kdone; ++l)
-            acc -= H[((size_t)i * kmax + l) * (kmax + 1) + j] * Y[(size_t)i * kdone + l];
-          cd hjj = H[((size_t)i * kmax + j) * (kmax + 1) + j];
-          Y[(size_t)i * kdone + j] = std::abs(hjj) > 0 ? acc / hjj : cd(0, 0);
-        }
-      }
-      HIPCHK(launch_fill_f64(st, (double *)w, 2 * vs, 0.0), "zero u");
-      std::vector<cpx<double>> yc(mS);
-      for (int j = 0; j < kdone; ++j) {
-        for (int i = 0; i < mS; ++i) {
-          cd v = Y[(size_t)i * kdone + j];
-          yc[i] = {v.real(), v.imag()};
-        }
-        HIPCHK(h2d(c->v_coef.p, yc.data(), sizeof(cpx<double>) * mS, st),
-               "y");
-        HIPCHK(hipStreamSynchronize(st), "y sync");
-        HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, V + j * vs, w,
-                                   nullptr),
-               "u += V y");
-      }
-      TRY(precond(c, w, z, S, all_poles(c)));
-      ++solves;
-      std::vector<cpx<double>> one(mS, {1.0, 0.0});
-      HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * mS, st),
-             "mask");
-      HIPCHK(h2d(c->v_coef.p, one.data(), sizeof(cpx<double>) * mS, st),
-             "coef");
-      HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
-                                 c->v_mask.as<int>()),
-             "x += z");
-      HIPCHK(hipStreamSynchronize(st), "x sync");
-      HIPCHK(launch_residual(st, N, m, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                             c->d_K.as<double>(), c->d_M.as<double>(), xi, rs, f_real, f_cplx, x,
-                             r),
-             "residual");
-    }
+    if (!any || it == max_iter) break;
+    const std::vector<PoleRun> runs = active_runs(c, active, S);
+    HIPCHK(h2d(c->v_mask.p, active.data(), sizeof(int) * nsys, st), "mask");
+    TRY(precond(c, r, z, S, runs));
+    ++solves;
+    for (int i = 0; i < nsys; ++i)
+      if (active[i]) res.iters[i]++;
+    HIPCHK(launch_batched_axpy(st, N, m, S, c->v_coef.as<cpx<double>>(), 1.0, z, x,
+                               c->v_mask.as<int>(), rs),
+           "x += z");
+    TRY(residual(runs, x));
+    TRY(sysnorms(c, r, S, rn));
   }
   res.unconverged = 0;
   for (int i = 0; i < nsys; ++i)
     if (!(res.rel[i] <= rtol)) res.unconverged++;   // NaN counts as unconverged
   res.solves = solves;
+  return TEM_OK;
+}
+
+// refine_block for any number of right-hand sides: more than 16 are solved
+// in equal blocks of at most 16 (the last one padded with zero right-hand
+// sides, which count as converged), gathered from and scattered back to the
+// [pole][N][S] vectors.  Single meshes only (a batch has <= 16 per mesh).
+tem_status refine_solve(tem_ctx *c, const double *f_real, const cpx<double> *f_cplx, int S,
+                        cpx<double> *x, const tem_ir_opts *ir, IrResult &res) {
+  if (S <= MAX_BLOCK_RHS) return refine_block(c, f_real, f_cplx, S, x, ir, res);
+  if (c->B > 0) return fail(c, TEM_EINVAL, "more than 16 sources per mesh in a batch");
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c);
+  const int m = c->npole;
+  const int nblk = (S + MAX_BLOCK_RHS - 1) / MAX_BLOCK_RHS;
+  const int Sb = (S + nblk - 1) / nblk;
+  // sized for a complex block, so that real and complex calls share it
+  TRY(ensure_vec(c, c->v_fblk, sizeof(cpx<double>) * (size_t)m * N * Sb, "alloc rhs block"));
+  TRY(ensure_vec(c, c->v_xblk, sizeof(cpx<double>) * (size_t)m * N * Sb, "alloc solution block"));
+  res.iters.assign((size_t)m * S, 0);
+  res.rel.assign((size_t)m * S, 0.0);
+  res.unconverged = 0;
+  res.solves = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int s0 = b * Sb, cnt = std::min(Sb, S - s0);
+    // doubles per element: 1 (real f) or 2 (complex)
+    if (f_real)
+      HIPCHK(launch_copy_cols(st, N, f_real, S, s0, cnt, c->v_fblk.as<double>(), Sb, 0, Sb),
+             "gather rhs block");
+    else
+      HIPCHK(launch_copy_cols(st, (int64_t)m * N, (const double *)f_cplx, 2 * S, 2 * s0, 2 * cnt,
+                              c->v_fblk.as<double>(), 2 * Sb, 0, 2 * Sb),
+             "gather rhs block");
+    IrResult rb;
+    TRY(refine_block(c, f_real ? c->v_fblk.as<double>() : nullptr,
+                     f_real ? nullptr : c->v_fblk.as<cpx<double>>(), Sb,
+                     c->v_xblk.as<cpx<double>>(), ir, rb));
+    HIPCHK(launch_copy_cols(st, (int64_t)m * N, c->v_xblk.as<double>(), 2 * Sb, 0, 2 * cnt,
+                            (double *)x, 2 * S, 2 * s0, 2 * cnt),
+           "scatter solution block");
+    for (int p = 0; p < m; ++p)
+      for (int q = 0; q < cnt; ++q) {
+        res.iters[(size_t)p * S + s0 + q] = rb.iters[(size_t)p * Sb + q];
+        res.rel[(size_t)p * S + s0 + q] = rb.rel[(size_t)p * Sb + q];
+        if (!(rb.rel[(size_t)p * Sb + q] <= ((ir && ir->rtol > 0) ? ir->rtol : 1e-10)))
+          res.unconverged++;
+      }
+    res.solves = std::max(res.solves, rb.solves);
+  }
   return TEM_OK;
 }
 
@@ -1766,10 +1667,20 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
   if (const char *v = std::getenv("TEM_LEFT_LOOKING")) c->left_looking = std::strtol(v, nullptr, 10) != 0;
   if (const char *v = std::getenv("TEM_UPDATE_TILE")) {   // "64", "128x64" or "128"
     const std::string m(v);
+    if (m != "64" && m != "128x64" && m != "128") {
+      g_create_error = "tem_create: TEM_UPDATE_TILE must be 64, 128x64 or 128, not '" + m + "'";
+      tem_destroy(c.release());
+      return TEM_EINVAL;
+    }
     c->upd_tile = m == "64" ? UPD_T64 : m == "128" ? UPD_T128 : UPD_T128x64;
   }
   if (const char *v = std::getenv("TEM_UPDATE_3M")) {   // "f32", "f64", "both" or "none"
     const std::string m(v);
+    if (m != "f32" && m != "f64" && m != "both" && m != "none") {
+      g_create_error = "tem_create: TEM_UPDATE_3M must be f32, f64, both or none, not '" + m + "'";
+      tem_destroy(c.release());
+      return TEM_EINVAL;
+    }
     c->upd_m3_f32 = m == "f32" || m == "both";
     c->upd_m3_f64 = m == "f64" || m == "both";
   }
@@ -2038,7 +1949,8 @@ tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precisi
   drop_factors(c);
   if (m != c->npole) c->surveyed = false;   // residues are per pole
   c->w_x.release();
-  c->v_basis.release();
+  c->v_fblk.release();
+  c->v_xblk.release();
   c->npole = m;
   c->prec = prec;
   c->xi.assign(xi, xi + 2 * m);
@@ -2051,8 +1963,8 @@ tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
   if (!c) return TEM_EINVAL;
   if (c->B > 0) return fail(c, TEM_ESTATE, "tem_solve_poles: not available on a batch of meshes");
   if (!c->factored) return fail(c, TEM_ESTATE, "tem_solve_poles: call tem_factor_poles first");
-  if (nrhs <= 0 || nrhs > 16 || !F)
-    return fail(c, TEM_EINVAL, "tem_solve_poles: need 1 <= nrhs <= 16 and a source array");
+  if (nrhs <= 0 || nrhs > 1024 || !F)
+    return fail(c, TEM_EINVAL, "tem_solve_poles: need 1 <= nrhs <= 1024 and a source array");
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
   const int64_t N = N_of(c);
   const int S = nrhs;
@@ -2407,7 +2319,8 @@ tem_status tem_factor_poles_batch(tem_ctx *c, const int32_t *m, const double *xi
   drop_factors(c);
   c->surveyed = false;
   c->w_x.release();
-  c->v_basis.release();
+  c->v_fblk.release();
+  c->v_xblk.release();
   // pole table [mesh][MP]; absent slots repeat the mesh's last pole (never
   // computed: the kernels skip them, the table only stays well defined)
   c->np_mesh.assign(m, m + c->B);
@@ -2641,7 +2554,7 @@ tem_status tem_get_stats(const tem_ctx *c, tem_stats *out) {
   out->precision = (int32_t)c->prec;
   out->factor_bytes = (int64_t)c->d_factor.bytes;
   out->workspace_bytes = (int64_t)(c->w_x.bytes + c->ed.w_t.bytes + c->ed.w_w0.bytes + c->ed.w_w1.bytes +
-                                   c->v_r.bytes + c->v_z.bytes + c->v_w.bytes + c->v_basis.bytes +
+                                   c->v_r.bytes + c->v_z.bytes + c->v_fblk.bytes + c->v_xblk.bytes +
                                    c->v_rhs.bytes + c->v_lam.bytes);
   out->n_tiny_pivots = c->n_tiny;
   out->last_solves = c->last_solves;

@@ -8,6 +8,7 @@
 namespace tem {
 
 constexpr int NB = 32;          // panel (column block) width of the factors
+constexpr int MAX_BLOCK_RHS = 16;  // right-hand sides per sweep (more are solved in blocks)
 
 // Complex value stored as interleaved (re, im).
 template <typename T>
@@ -176,18 +177,12 @@ hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
 
 // ------------------------------------------------------- vector kernels
 // Residual r = f - (K - xi_p M) x for all poles p and rhs s (FP64);
-// x, r: [pole][N][S] complex double; f: [N][S] real (new ordering) or, with
-// f_cplx, [pole][N][S] complex.
+// x, r: [pole][N][S] complex double (x = NULL: x = 0, r = f); f: [N][S]
+// real (new ordering) or, with f_cplx, [pole][N][S] complex.
 hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                            const int32_t *col, const double *Kv, const double *Mv,
                            const double *xi, Seg row_seg, const double *f_real,
                            const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r);
-
-// y = (K - xi_p M) x  (FP64), same layout as residual.
-hipError_t launch_spmv_shifted(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
-                               const int32_t *col, const double *Kv, const double *Mv,
-                               const double *xi, Seg row_seg, const cpx<double> *x,
-                               cpx<double> *y);
 
 // Batched complex dot products over N rows for all (pole, s):
 // out[p*S+s] = sum_row conj(a) * b (conj_a) or sum a*b.  Deterministic.
@@ -209,9 +204,11 @@ hipError_t launch_batched_axpy(hipStream_t st, int64_t N, int npole, int S,
 hipError_t launch_norm_scales(hipStream_t st, int n, const cpx<double> *dots, double *inv,
                               double *nrm);
 hipError_t launch_fill_f64(hipStream_t st, double *p, int64_t n, double v);
-// x[p][i][s] *= scale[p*S+s] (real)
-hipError_t launch_batched_scale(hipStream_t st, int64_t N, int npole, int S, const double *scale,
-                                cpx<double> *x);
+// dst[row * ldd + d0 + j] = (j < cnt ? src[row * lds + s0 + j] : 0) for
+// j < width: a block of columns of row-major arrays (in doubles; a complex
+// column is two).  Gathers and scatters blocks of right-hand sides.
+hipError_t launch_copy_cols(hipStream_t st, int64_t rows, const double *src, int lds, int s0,
+                            int cnt, double *dst, int ldd, int d0, int width);
 
 // conversions between the FP64 refinement vectors and the factor precision,
 // with a per-system scale: out = in * scale[p*S+s].

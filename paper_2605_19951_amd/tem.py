@@ -65,7 +65,7 @@ class AutotuneReport(C.Structure):
 
 
 class IrOpts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32)]
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("reserved", C.c_int32)]
 
 
 class IrStats(C.Structure):
@@ -255,8 +255,7 @@ class Tem:
     def _ir(ir):
         if ir is None:
             return None
-        return C.byref(IrOpts(float(ir.get("rtol", 0.0)), int(ir.get("max_iter", 0)),
-                              int(ir.get("restart", 0))))
+        return C.byref(IrOpts(float(ir.get("rtol", 0.0)), int(ir.get("max_iter", 0)), 0))
 
     def _stats_struct(self, n):
         it = np.zeros(n, np.int32)

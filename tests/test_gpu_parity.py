@@ -75,6 +75,19 @@ def _wide(wl, prec):
     return _env_run(wl, prec, {"TEM_SWEEP_BLOCK": "64", "TEM_SWEEP_BIG_LIMIT": "1000000"})
 
 
+def C16():
+    return ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22)
+
+
+def S17():
+    """12^3 mesh with seventeen loop sources on a grid of centres (loops may
+    share edges; each column of F is still one loop)."""
+    wl = ti.smooth_workload(12, 2, S=1, m=3, K=5, g=2, seed=24)
+    centres = [(cx, cy) for cx in range(3, 10, 2) for cy in range(3, 10, 2)][:16] + [(6, 6)]
+    wl.F = ti.source_matrix(wl.mesh, centres)
+    return wl
+
+
 CASES = {
     "tiny64": lambda: Run(ti.tiny_workload(), 0),
     "tiny32": lambda: Run(ti.tiny_workload(), 1),
@@ -86,6 +99,10 @@ CASES = {
     "w16_32": lambda: _wide(ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22), 1),
     # twelve right-hand sides: the FP32 forward sweep's two-block path (S > 8)
     "s12_32": lambda: Run(ti.smooth_workload(16, 2, S=12, m=3, K=5, g=2, seed=23), 1),
+    # seventeen right-hand sides: solved in two blocks of nine (the second
+    # padded with a zero right-hand side), both precisions
+    "s17_64": lambda: Run(S17(), 0),
+    "s17_32": lambda: Run(S17(), 1),
     # factor panel schedules (the 13^3 root separator has 312 columns): 64-column
     # left-looking panels, and 96-column right-looking panels (recursion halves
     # of 32 and 64 columns)
@@ -93,7 +110,18 @@ CASES = {
                                {"TEM_PANEL": "64"}),
     "p96rl_64": lambda: _env_run(ti.smooth_workload(13, 2, S=3, m=5, K=7, g=2, seed=21), 0,
                                  {"TEM_PANEL": "96", "TEM_LEFT_LOOKING": "0"}),
+    # every front-update variant the autotuner or the knobs can select, on every
+    # level of a 16^3 tree (fronts up to 712 rows): FP32 64x64 with four real
+    # products, 128x64 with three and four, 128x128 (four); FP64 64x64 with three
+    "u64m4_32": lambda: _env_run(C16(), 1, {"TEM_UPDATE_TILE": "64", "TEM_UPDATE_3M": "none"}),
+    "u128x64m3_32": lambda: _env_run(C16(), 1, {"TEM_UPDATE_TILE": "128x64",
+                                                "TEM_UPDATE_3M": "f32"}),
+    "u128x64m4_32": lambda: _env_run(C16(), 1, {"TEM_UPDATE_TILE": "128x64",
+                                                "TEM_UPDATE_3M": "none"}),
+    "u128_32": lambda: _env_run(C16(), 1, {"TEM_UPDATE_TILE": "128", "TEM_UPDATE_3M": "none"}),
+    "u64m3_64": lambda: _env_run(C16(), 0, {"TEM_UPDATE_TILE": "64", "TEM_UPDATE_3M": "f64"}),
 }
+UPDATE_VARIANTS = ["u64m4_32", "u128x64m3_32", "u128x64m4_32", "u128_32", "u64m3_64"]
 _cache = {}
 
 
@@ -165,7 +193,7 @@ def test_data_all_times(name):
 
 
 @pytest.mark.parametrize("name", ["r13_64", "r13_32", "c16_64", "c16_32", "w16_64", "w16_32",
-                                  "s12_32"])
+                                  "s12_32", "s17_64", "s17_32"] + UPDATE_VARIANTS)
 def test_jvp_vjp(name):
     r = get(name)
     torch = r.torch
@@ -186,6 +214,35 @@ def test_jvp_vjp(name):
     a = np.vdot(jv.cpu().numpy().ravel(), w.ravel())
     b = np.vdot(v, jtw.cpu().numpy())
     assert abs(a - b) <= 10 * tol * max(abs(a), abs(b))
+
+
+@pytest.mark.parametrize("name", UPDATE_VARIANTS)
+def test_update_variant_needs_no_extra_refinement(name):
+    """A forced update kernel factors as accurately as the default one: its
+    forward needs at most one refinement solve more than the default kernel's
+    on any pole and source (the rounding of the two kernels differs)."""
+    r = get(name)
+    base = get("c16_32" if name.endswith("32") else "c16_64")
+    assert np.max(r.ir["iters"]) <= np.max(base.ir["iters"]) + 1
+
+
+def test_unknown_update_knob_is_refused():
+    """tem_create rejects a TEM_UPDATE_TILE or TEM_UPDATE_3M value it does not know."""
+    _torch()
+    import os
+    from paper_2605_19951_amd import Tem, TemError
+    for k, v in (("TEM_UPDATE_TILE", "96"), ("TEM_UPDATE_3M", "yes")):
+        old = os.environ.get(k)
+        os.environ[k] = v
+        try:
+            with pytest.raises(TemError) as e:
+                Tem(0)
+            assert k in str(e.value)
+        finally:
+            if old is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = old
 
 
 def test_bitwise_determinism():
@@ -228,18 +285,29 @@ def test_state_machine_and_argument_errors():
     with pytest.raises(TemError) as e:
         t.jvp(v, d)
     assert e.value.status == TEM_ESTATE
-    # a forward call that is refused (17 sources) leaves no survey behind:
-    # Jv is refused until a forward call succeeds again
+    # a forward call that is refused (a receiver column past the last edge)
+    # leaves no survey behind: Jv is refused until a forward call succeeds
     F = torch.tensor(wl.F.T.copy(), device=dev)
     K, R = len(wl.poles.t), wl.rx.n
     d = torch.zeros((wl.S, K, R), dtype=torch.float64, device=dev)
     t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
     jv = torch.zeros_like(d)
     t.jvp(v, jv)
-    F17 = F[:1].repeat(17, 1).contiguous()
-    d17 = torch.zeros((17, K, R), dtype=torch.float64, device=dev)
+    bad_col = np.array(wl.rx.col, np.int32).copy()
+    bad_col[0] = me.n_edges
     with pytest.raises(TemError) as e:
-        t.forward(F17, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d17)
+        t.forward(F, wl.rx.ptr, bad_col, wl.rx.val, wl.poles.alpha, d)
+    assert e.value.status == TEM_EINVAL
+    with pytest.raises(TemError) as e:
+        t.jvp(v, jv)
+    assert e.value.status == TEM_ESTATE
+    t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+    t.jvp(v, jv)
+    # more than 1024 right-hand sides are refused, with the survey dropped
+    F1025 = F[:1].repeat(1025, 1).contiguous()
+    d1025 = torch.zeros((1025, K, R), dtype=torch.float64, device=dev)
+    with pytest.raises(TemError) as e:
+        t.forward(F1025, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d1025)
     assert e.value.status == TEM_EINVAL
     with pytest.raises(TemError) as e:
         t.jvp(v, jv)
