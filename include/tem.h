@@ -264,6 +264,25 @@ tem_status tem_jvp(tem_ctx *ctx, const double *v, double *jv, const tem_ir_opts 
 tem_status tem_vjp(tem_ctx *ctx, const double *w, double *jtw, const tem_ir_opts *ir,
                    tem_ir_stats *stats);
 
+/* tem_vjp without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and state requirements as tem_vjp
+ * (same kernels, launched eagerly: no graph replay, no profiling events).
+ * Its work space (right-hand sides, solutions, residuals, sweep and nodal
+ * vectors, norm partials) is carved from a static device array of 256 MiB
+ * that every GPU the library runs on holds until the process ends; the
+ * context's own work buffers are left untouched.  Supports problems whose
+ * work space fits (about 8 complex FP64 vectors of m * N * S entries, e.g.
+ * a 16^3 mesh with 16 poles and 8 sources); larger ones return TEM_ENOMEM
+ * with the sizes in tem_last_error, before any kernel runs on the array
+ * region they would have needed.  All calls on one GPU share that GPU's
+ * array: calls that overlap in time on one GPU (two threads, or two
+ * contexts whose streams run concurrently) race on it and give wrong
+ * results.  Each call writes every scratch entry it reads before reading
+ * it, so nothing carries over from an earlier call. */
+tem_status tem_vjp_noalloc(tem_ctx *ctx, const double *w, double *jtw, const tem_ir_opts *ir,
+                           tem_ir_stats *stats);
+
 /* One Gauss-Newton update (section "Optimization"): runs `iters`
  * iterations of LSQR (Paige & Saunders 1982, x0 = 0, no damping) on
  *   min || [W_d J; sqrt(lambda) R] dm + [W_d (d(m) - d_obs); sqrt(lambda) R (m - m_ref)] ||

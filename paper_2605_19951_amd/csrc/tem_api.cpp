@@ -12,6 +12,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,23 +27,59 @@ namespace {
 // text of the calling thread's last failed tem_create
 thread_local std::string g_create_error;
 
+// Work space of the allocation-free entry points (tem_vjp_noalloc): one
+// static device array per GPU, held from the module's load until the
+// process ends.  Host code never passes `scratch` itself to a kernel (its
+// host-side name is not a device address): tem_create looks up the array's
+// device address once per device and every use goes through that pointer.
+constexpr size_t SCRATCH_BYTES = size_t(256) << 20;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device `dev` (looked up once)
+hipError_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = ptr;
+  return hipSuccess;
+}
+
+void *scratch_ptr(int dev) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+
+// set while an allocation-free call runs on this thread: any device
+// allocation attempted then fails instead of calling hipMalloc
+thread_local bool t_no_alloc = false;
+
 // ------------------------------------------------------------ device buffer
 struct DBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;   // p lies in the static scratch array (not owned)
   DBuf() = default;
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) hipFree(p);
+    if (p && !borrowed) hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
   }
   // Freeing and mapping tens of GB takes seconds, so buffers that are
   // rebuilt with the same size (factors, arenas) keep their allocation.
   hipError_t alloc(size_t b) {
     if (b == bytes && p) return hipSuccess;
+    if (t_no_alloc) return hipErrorOutOfMemory;
     release();
     if (b == 0) return hipSuccess;
     hipError_t e = hipMalloc(&p, b);
@@ -233,6 +270,21 @@ struct tem_ctx {
   DBuf w_x;                        // factor-precision sweep vector
   DBuf v_r, v_z, v_rhs, v_lam, v_vs, v_dots, v_partial, v_inv, v_nrm, v_coef, v_mask;
   DBuf v_aux, v_fblk, v_xblk;
+  // Allocation-free calls: while `on`, the work buffers a call needs are
+  // carved from the device's static scratch array (bump allocation from
+  // `base`) instead of allocated; `saved` keeps each borrowed buffer's own
+  // allocation, given back when the call ends.
+  struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    bool on = false;
+    struct Saved {
+      DBuf *b;
+      void *p;
+      size_t bytes;
+    };
+    std::vector<Saved> saved;
+  } arena;
   // profiling (HIP events around the update launches and the sweeps)
   bool profile = false;
   std::vector<hipEvent_t> ev_pool;
@@ -802,10 +854,78 @@ tem_status factor_group(tem_ctx *c, MF &mf, cpx<T> *F, const double *xi, Seg xse
 }
 
 // ---------------------------------------------------------------- sweeps
+// Allocation-free mode: give b a region of at least `bytes` of the static
+// scratch array (b keeps a region it already took in this call if it is
+// large enough).  Fails with TEM_ENOMEM when the array is exhausted.
+tem_status arena_take(tem_ctx *c, DBuf &b, size_t bytes, const char *what) {
+  tem_ctx::Arena &a = c->arena;
+  bool seen = false;
+  for (const tem_ctx::Arena::Saved &sv : a.saved)
+    if (sv.b == &b) seen = true;
+  if (seen && b.bytes >= bytes) return TEM_OK;
+  const size_t off = (a.used + 255) & ~(size_t)255;
+  if (off > a.cap || bytes > a.cap - off) {
+    char buf[224];
+    std::snprintf(buf, sizeof(buf),
+                  "%s: the work space of an allocation-free call exceeds the %zu MiB static "
+                  "scratch (%zu bytes in use, %zu more requested)",
+                  what, a.cap >> 20, off, bytes);
+    return fail(c, TEM_ENOMEM, buf);
+  }
+  if (!seen) a.saved.push_back({&b, b.p, b.bytes});
+  b.p = a.base + off;
+  b.bytes = bytes;
+  b.borrowed = true;
+  a.used = off + bytes;
+  return TEM_OK;
+}
+
+// Scope of an allocation-free call: work space from `base` (cap bytes), no
+// device allocation on this thread, eager launches (instantiating a graph
+// may allocate) and no profiling events; everything restored on exit.
+struct ArenaScope {
+  tem_ctx *c;
+  bool graphs, profile;
+  ArenaScope(tem_ctx *cc, void *base, size_t cap) : c(cc) {
+    c->arena.base = (char *)base;
+    c->arena.cap = cap;
+    c->arena.used = 0;
+    c->arena.saved.clear();
+    c->arena.on = true;
+    graphs = c->use_graphs;
+    profile = c->profile;
+    c->use_graphs = false;
+    c->profile = false;
+    t_no_alloc = true;
+  }
+  ~ArenaScope() {
+    // the call's kernels have finished with the scratch before the
+    // buffers get their own allocations back (every entry point
+    // synchronises its stream on success; this covers the error paths)
+    hipStreamSynchronize(c->stream);
+    for (size_t i = c->arena.saved.size(); i-- > 0;) {
+      const tem_ctx::Arena::Saved &sv = c->arena.saved[i];
+      sv.b->p = sv.p;
+      sv.b->bytes = sv.bytes;
+      sv.b->borrowed = false;
+    }
+    c->arena.saved.clear();
+    c->arena.on = false;
+    c->use_graphs = graphs;
+    c->profile = profile;
+    t_no_alloc = false;
+  }
+};
+
 template <typename T>
 tem_status ensure_sweep_ws(tem_ctx *c, MF &mf, int npole, int S) {
   const size_t vec = sizeof(cpx<T>) * (size_t)npole * mf.N * S;
   const size_t wb = sizeof(cpx<T>) * (size_t)npole * std::max<int64_t>(mf.w_rows_max, 1) * S;
+  if (c->arena.on) {
+    TRY(arena_take(c, mf.w_t, vec, "sweep t"));
+    TRY(arena_take(c, mf.w_w0, wb, "sweep w0"));
+    return arena_take(c, mf.w_w1, wb, "sweep w1");
+  }
   if (mf.w_t.bytes < vec) HIPCHK(mf.w_t.alloc(vec), "alloc sweep t");
   if (mf.w_w0.bytes < wb) HIPCHK(mf.w_w0.alloc(wb), "alloc sweep w0");
   if (mf.w_w1.bytes < wb) HIPCHK(mf.w_w1.alloc(wb), "alloc sweep w1");
@@ -977,6 +1097,7 @@ tem_status sweep(tem_ctx *c, cpx<T> *x, int S, const std::vector<PoleRun> &runs)
 }
 
 tem_status ensure_vec(tem_ctx *c, DBuf &b, size_t bytes, const char *what) {
+  if (c->arena.on) return arena_take(c, b, bytes, what);
   if (b.bytes != bytes) HIPCHK(b.alloc(bytes), what);
   return TEM_OK;
 }
@@ -1638,6 +1759,13 @@ tem_status tem_create(tem_ctx **out, int hip_device, void *hip_stream) {
     g_create_error = std::string("tem_create: hipSetDevice: ") + hipGetErrorString(e);
     return TEM_EDEVICE;
   }
+  // device address of the static scratch array on this device (once per
+  // device; the allocation-free calls use it)
+  e = scratch_setup(hip_device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("tem_create: scratch address: ") + hipGetErrorString(e);
+    return TEM_EDEVICE;
+  }
   std::unique_ptr<tem_ctx> c(new tem_ctx());
   c->device = hip_device;
   if (hip_stream) {
@@ -2130,6 +2258,24 @@ tem_status tem_vjp(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *
   c->last_solves = res.solves;
   if (res.unconverged) return fail(c, TEM_ENOCONV, "tem_vjp: refinement did not converge");
   return TEM_OK;
+}
+
+tem_status tem_vjp_noalloc(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *ir,
+                           tem_ir_stats *stats) {
+  if (!c) return TEM_EINVAL;
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  void *base = scratch_ptr(c->device);
+  if (!base) return fail(c, TEM_EDEVICE, "tem_vjp_noalloc: no scratch address for this device");
+  tem_status s;
+  {
+    ArenaScope scope(c, base, SCRATCH_BYTES);
+    s = tem_vjp(c, w, jtw, ir, stats);
+  }
+  if (s != TEM_OK && s != TEM_ENOCONV) {
+    const std::string m = c->err;
+    return fail(c, s, m.compare(0, 16, "tem_vjp_noalloc:") == 0 ? m : "tem_vjp_noalloc: " + m);
+  }
+  return s;
 }
 
 static tem_status lsqr_norm(tem_ctx *c, int64_t n, const double *a, double &out) {

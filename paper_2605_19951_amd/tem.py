@@ -25,7 +25,7 @@ EXPORTS = ["tem_create", "tem_destroy", "tem_last_error", "tem_assemble", "tem_s
            "tem_export_operators", "tem_analyse", "tem_symbolic_host", "tem_factor_poles",
            "tem_solve_poles", "tem_forward", "tem_jvp", "tem_vjp", "tem_get_stats",
            "tem_set_profiling", "tem_gn_step", "tem_assemble_batch", "tem_factor_poles_batch",
-           "tem_forward_batch", "tem_autotune", "tem_autotune_level"]
+           "tem_forward_batch", "tem_autotune", "tem_autotune_level", "tem_vjp_noalloc"]
 
 
 class TemError(RuntimeError):
@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH):
                          C.POINTER(IrStats)], C.c_int),
         "tem_jvp": ([vp, dp, dp, C.POINTER(IrOpts), C.POINTER(IrStats)], C.c_int),
         "tem_vjp": ([vp, dp, dp, C.POINTER(IrOpts), C.POINTER(IrStats)], C.c_int),
+        "tem_vjp_noalloc": ([vp, dp, dp, C.POINTER(IrOpts), C.POINTER(IrStats)], C.c_int),
         "tem_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
         "tem_set_profiling": ([vp, i32], C.c_int),
         "tem_gn_step": ([vp, dp, dp, dp, dp, C.c_double, i32, dp, vp, C.POINTER(IrOpts)], C.c_int),
@@ -307,6 +308,15 @@ class Tem:
         s, it, rr = self._stats_struct(max(self.npole * self.S, 1))
         self._chk(self.L.tem_vjp(self.h, _dev(w, "float64", self._dshape()),
                                  _dev(jtw, "float64", (self.n_params,)), self._ir(ir), C.byref(s)))
+        return dict(iters=it.reshape(self.npole, self.S), rel=rr.reshape(self.npole, self.S))
+
+    def vjp_noalloc(self, w, jtw, ir=None):
+        """tem_vjp_noalloc: J^T w with all work space in the library's static
+        scratch array (no device allocation)."""
+        s, it, rr = self._stats_struct(max(self.npole * self.S, 1))
+        self._chk(self.L.tem_vjp_noalloc(self.h, _dev(w, "float64", self._dshape()),
+                                         _dev(jtw, "float64", (self.n_params,)), self._ir(ir),
+                                         C.byref(s)))
         return dict(iters=it.reshape(self.npole, self.S), rel=rr.reshape(self.npole, self.S))
 
     def gn_step(self, d_obs, wd, m, m_ref, lam, iters, dm, ir=None):
