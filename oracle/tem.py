@@ -30,7 +30,10 @@ within the scalar error bound; conjugate-pole symmetry; divergence
 invariants; SuperLU against dense LAPACK solves; adjoint test; Taylor
 slopes 1 and 2; central finite differences; LSQR against SciPy's LSQR and,
 after P iterations on a tiny problem, against the dense least-squares
-solution, and on degenerate right-hand sides, b = 0 and A^T b = 0).
+solution, and on degenerate right-hand sides, b = 0 and A^T b = 0; the
+reorthogonalised LSQR against the least-squares solution over the Krylov
+space K_k(A^T A, A^T b) built densely, and against plain LSQR in its first
+iterations).
 """
 from __future__ import annotations
 
@@ -212,12 +215,21 @@ def first_difference(nx, ny, nz_earth):
     return sp.csr_matrix((vals, (rows, cols)), shape=(r, nx * ny * nz_earth))
 
 
-def lsqr(matvec, rmatvec, b, n, iters):
-    """Plain LSQR (Paige & Saunders 1982), x0 = 0, no damping, fixed number
-    of iterations.  Returns x and the per-iteration estimates of ||r||.
+def lsqr(matvec, rmatvec, b, n, iters, reorth=False):
+    """LSQR (Paige & Saunders 1982), x0 = 0, no damping, fixed number of
+    iterations.  Returns x and the per-iteration estimates of ||r||.
     When the bidiagonalisation ends (rho = 0: A^T b = 0, or the Krylov space
     is exhausted) x already solves the problem; it is returned as is and the
-    remaining estimates repeat the last one."""
+    remaining estimates repeat the last one.
+
+    reorth: orthogonalise each new v against all earlier v twice (modified
+    Gram-Schmidt) before normalising it (one-sided reorthogonalisation,
+    Simon & Zha 2000).  In exact arithmetic the v are already orthonormal
+    and the iterates are those of plain LSQR; in floating point plain LSQR
+    loses that orthogonality after a few iterations on these ill-conditioned
+    weighted operators, and its iterates then move by O(1) under rounding
+    perturbations, while the reorthogonalised ones stay within rounding of
+    the Krylov least-squares solution."""
     x = np.zeros(n)
     u = np.array(b, float)
     beta = np.linalg.norm(u)
@@ -228,6 +240,7 @@ def lsqr(matvec, rmatvec, b, n, iters):
     if alpha > 0:
         v = v / alpha
     w = v.copy()
+    basis = [v.copy()]
     phibar = beta
     rhobar = alpha
     hist = []
@@ -237,9 +250,14 @@ def lsqr(matvec, rmatvec, b, n, iters):
         if beta > 0:
             u = u / beta
         v = rmatvec(u) - beta * v
+        if reorth:
+            for _pass in range(2):
+                for q in basis:
+                    v = v - (q @ v) * q
         alpha = np.linalg.norm(v)
         if alpha > 0:
             v = v / alpha
+        basis.append(v.copy())
         rho = math.hypot(rhobar, beta)
         if rho == 0.0:
             hist.extend([phibar] * (iters - len(hist)))
@@ -256,9 +274,10 @@ def lsqr(matvec, rmatvec, b, n, iters):
     return x, hist
 
 
-def gauss_newton_step(orc: OracleTEM, m, d_obs, wd, m_ref, lam, Rmat, iters):
+def gauss_newton_step(orc: OracleTEM, m, d_obs, wd, m_ref, lam, Rmat, iters, reorth=False):
     """One Gauss-Newton update dm from LSQR on
-    min || [W_d J; sqrt(lam) R] dm + [W_d (d(m) - d_obs); sqrt(lam) R (m - m_ref)] ||."""
+    min || [W_d J; sqrt(lam) R] dm + [W_d (d(m) - d_obs); sqrt(lam) R (m - m_ref)] ||
+    (reorth: LSQR with one-sided reorthogonalisation, see ``lsqr``)."""
     orc.set_model(m)
     d = orc.data().reshape(-1)
     sl = math.sqrt(lam)
@@ -272,5 +291,5 @@ def gauss_newton_step(orc: OracleTEM, m, d_obs, wd, m_ref, lam, Rmat, iters):
     def rmv(u):
         return orc.vjp((wd * u[:nd]).reshape(shape)) + sl * (Rmat.T @ u[nd:])
 
-    dm, hist = lsqr(mv, rmv, b, len(m), iters)
+    dm, hist = lsqr(mv, rmv, b, len(m), iters, reorth)
     return dm, hist, b

@@ -745,6 +745,52 @@ hipError_t launch_rdot(hipStream_t st, int64_t n, const double *a, const double 
   return hipGetLastError();
 }
 
+// Reorthogonalisation of an LSQR vector v (n entries) against the nv
+// stored basis vectors V (row j at V + j * n): h = V v in a fixed-order
+// two-stage reduction (block (chunk, j), then one thread per j), then
+// v -= V^T h.
+__global__ __launch_bounds__(256) void k_vdots1(int64_t n, const double *V, const double *v,
+                                                double *partial) {
+  __shared__ double sh[256];
+  const double *a = V + (int64_t)blockIdx.y * n;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += a[i] * v[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void k_vdots2(int nv, int nb, const double *partial, double *h) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nv) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(int64_t)j * nb + b];
+  h[j] = s;
+}
+
+__global__ void k_vsub(int64_t n, int nv, const double *V, const double *h, double *v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = v[i];
+  for (int j = 0; j < nv; ++j) acc -= V[(int64_t)j * n + i] * h[j];
+  v[i] = acc;
+}
+
+hipError_t launch_reorth(hipStream_t st, int64_t n, int nv, const double *V, double *v,
+                         double *partial, double *h) {
+  if (n <= 0 || nv <= 0) return hipSuccess;
+  const int nb = 64;   // partial holds nv * 64 doubles
+  hipLaunchKernelGGL(k_vdots1, dim3(nb, nv), dim3(256), 0, st, n, V, v, partial);
+  hipLaunchKernelGGL(k_vdots2, dim3((nv + 63) / 64), dim3(64), 0, st, nv, nb, partial, h);
+  hipLaunchKernelGGL(k_vsub, dim3(grid_1d(n, 256, 1 << 30)), dim3(256), 0, st, n, nv, V, h, v);
+  return hipGetLastError();
+}
+
 // y = a * x + b * y   (x may be null: y = b * y); with w: x is weighted by w
 __global__ void k_raxpby(int64_t n, double a, const double *x, const double *w, double b,
                          double *y) {

@@ -265,7 +265,7 @@ struct tem_ctx {
   int64_t n_reg = 0;
   DBuf d_reg_lo, d_reg_hi, d_reg_incp, d_reg_inc;
   // LSQR work space
-  DBuf l_u, l_v, l_w, l_x, l_tmpd, l_tmpm, l_part, l_scal;
+  DBuf l_u, l_v, l_w, l_x, l_tmpd, l_tmpm, l_part, l_scal, l_V;
   // work space
   DBuf w_x;                        // factor-precision sweep vector
   DBuf v_r, v_z, v_rhs, v_lam, v_vs, v_dots, v_partial, v_inv, v_nrm, v_coef, v_mask;
@@ -2307,8 +2307,11 @@ tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const 
   TRY(ensure_vec(c, c->l_x, sizeof(double) * P, "alloc lsqr"));
   TRY(ensure_vec(c, c->l_tmpd, sizeof(double) * nd, "alloc lsqr"));
   TRY(ensure_vec(c, c->l_tmpm, sizeof(double) * P, "alloc lsqr"));
-  TRY(ensure_vec(c, c->l_part, sizeof(double) * 256, "alloc lsqr"));
-  TRY(ensure_vec(c, c->l_scal, sizeof(double) * 4, "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_part, sizeof(double) * 64 * std::max(iters + 1, 4), "alloc lsqr"));
+  TRY(ensure_vec(c, c->l_scal, sizeof(double) * (iters + 1), "alloc lsqr"));
+  // the v vectors of the bidiagonalisation, kept for reorthogonalisation
+  TRY(ensure_vec(c, c->l_V, sizeof(double) * (size_t)P * (iters + 1), "alloc lsqr basis"));
+  double *Vb = c->l_V.as<double>();
   double *u = c->l_u.as<double>(), *v = c->l_v.as<double>(), *w = c->l_w.as<double>();
   double *x = c->l_x.as<double>(), *td = c->l_tmpd.as<double>(), *tm = c->l_tmpm.as<double>();
   const int32_t *rlo = c->d_reg_lo.as<int32_t>(), *rhi = c->d_reg_hi.as<int32_t>();
@@ -2347,6 +2350,7 @@ tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const 
   TRY(rmatvec(1.0, 0.0));
   TRY(lsqr_norm(c, P, v, alpha));
   if (alpha > 0) HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 1.0 / alpha, v), "v /= alpha");
+  HIPCHK(launch_raxpby(st, P, 1.0, v, nullptr, 0.0, Vb), "V0 = v");
   HIPCHK(launch_raxpby(st, P, 1.0, v, nullptr, 0.0, w), "w = v");
   HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 0.0, x), "x = 0");
   double phibar = beta, rhobar = alpha;
@@ -2355,8 +2359,13 @@ tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const 
     TRY(lsqr_norm(c, nu, u, beta));
     if (beta > 0) HIPCHK(launch_raxpby(st, nu, 0.0, nullptr, nullptr, 1.0 / beta, u), "u scale");
     TRY(rmatvec(1.0, -beta));                     // v = A^T u - beta v
+    // one-sided reorthogonalisation: v against every earlier v, twice
+    for (int pass = 0; pass < 2; ++pass)
+      HIPCHK(launch_reorth(st, P, it + 1, Vb, v, c->l_part.as<double>(), c->l_scal.as<double>()),
+             "reorthogonalise v");
     TRY(lsqr_norm(c, P, v, alpha));
     if (alpha > 0) HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 1.0 / alpha, v), "v scale");
+    HIPCHK(launch_raxpby(st, P, 1.0, v, nullptr, 0.0, Vb + (size_t)P * (it + 1)), "store v");
     const double rho = std::hypot(rhobar, beta);
     if (rho == 0) {   // the bidiagonalisation has ended: x solves the problem
       if (hist)

@@ -262,6 +262,11 @@ hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int64_t N,
                              const cpx<double> *lam, double *out);
 
 // ----------------------------------------------------- LSQR helpers (FP64)
+// v -= V^T (V v): one classical Gram-Schmidt pass of v (n entries) against
+// the nv rows of V (row-major, row j at V + j * n); partial: nv * 64
+// doubles, h: nv doubles (work space).  Deterministic.
+hipError_t launch_reorth(hipStream_t st, int64_t n, int nv, const double *V, double *v,
+                         double *partial, double *h);
 hipError_t launch_rdot(hipStream_t st, int64_t n, const double *a, const double *b,
                        double *partial /* 256 */, double *out);
 hipError_t launch_raxpby(hipStream_t st, int64_t n, double a, const double *x, const double *w,

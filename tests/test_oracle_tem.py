@@ -196,6 +196,46 @@ def test_lsqr_matches_scipy_and_lstsq():
     assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
 
 
+def _krylov_lstsq(A, b, k):
+    """min ||A x - b|| over x in K_k(A^T A, A^T b), with an orthonormal
+    basis of the Krylov space from Arnoldi (modified Gram-Schmidt, twice)
+    on the normal operator and a dense least-squares solve."""
+    q = A.T @ b
+    Q = [q / np.linalg.norm(q)]
+    for _ in range(k - 1):
+        z = A.T @ (A @ Q[-1])
+        for _pass in range(2):
+            for qq in Q:
+                z = z - (qq @ z) * qq
+        Q.append(z / np.linalg.norm(z))
+    V = np.stack(Q, axis=1)
+    y = np.linalg.lstsq(A @ V, b, rcond=None)[0]
+    return V @ y
+
+
+def test_reorthogonalised_lsqr_is_the_krylov_least_squares_solution():
+    """On an ill-conditioned operator (singular values from 1 to 1e-8) the
+    reorthogonalised LSQR iterate after k steps is the least-squares solution
+    over the k-dimensional Krylov space; plain LSQR agrees with it while its
+    vectors are still orthogonal and drifts away later."""
+    rng = np.random.default_rng(8)
+    m, n = 200, 120
+    U = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    A = U @ np.diag(np.logspace(0, -8, n)) @ V.T
+    b = rng.standard_normal(m)
+    mv, rmv = (lambda v: A @ v), (lambda u: A.T @ u)
+    for k in (3, 10, 30):
+        x, hist = lsqr(mv, rmv, b, n, k, reorth=True)
+        ref = _krylov_lstsq(A, b, k)
+        assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+        # the residual estimate is the residual norm of the iterate
+        assert abs(hist[-1] - np.linalg.norm(b - A @ x)) <= 1e-8 * np.linalg.norm(b)
+    xp, _ = lsqr(mv, rmv, b, n, 3)
+    xr, _ = lsqr(mv, rmv, b, n, 3, reorth=True)
+    assert np.linalg.norm(xp - xr) <= 1e-12 * np.linalg.norm(xr)
+
+
 def test_lsqr_degenerate_right_hand_sides():
     # b = 0: x = 0 and a zero residual; A^T b = 0 (b orthogonal to the range
     # of A): x = 0 is the least-squares solution and ||r|| = ||b|| throughout.
@@ -204,6 +244,8 @@ def test_lsqr_degenerate_right_hand_sides():
     A = np.zeros((30, 6))
     A[:10] = rng.standard_normal((10, 6))
     x, hist = lsqr(lambda v: A @ v, lambda u: A.T @ u, np.zeros(30), 6, 5)
+    assert np.array_equal(x, np.zeros(6)) and hist == [0.0] * 5
+    x, hist = lsqr(lambda v: A @ v, lambda u: A.T @ u, np.zeros(30), 6, 5, reorth=True)
     assert np.array_equal(x, np.zeros(6)) and hist == [0.0] * 5
     b = np.zeros(30)
     b[10:] = rng.standard_normal(20)
@@ -240,8 +282,16 @@ def test_gauss_newton_step_with_explicit_jacobian():
     R = first_difference(2, 2, 2)
     P = len(params)
     dm, hist, b = gauss_newton_step(o, m0, d_obs, wd, m0, 1.0, R, P)
+    dmr, _, _ = gauss_newton_step(o, m0, d_obs, wd, m0, 1.0, R, P, reorth=True)
     o.set_model(m0)
     J = np.stack([o.jvp(e).reshape(-1) for e in np.eye(P)], axis=1)
     Aug = np.vstack([wd[:, None] * J, R.toarray()])
     ref = np.linalg.lstsq(Aug, b, rcond=None)[0]
     assert np.linalg.norm(dm - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert np.linalg.norm(dmr - ref) <= 1e-8 * np.linalg.norm(ref)
+    # after fewer iterations: the least-squares solution over the Krylov space
+    for k in (2, 5):
+        dmk, _, _ = gauss_newton_step(o, m0, d_obs, wd, m0, 1.0, R, k, reorth=True)
+        o.set_model(m0)
+        refk = _krylov_lstsq(Aug, b, k)
+        assert np.linalg.norm(dmk - refk) <= 1e-8 * np.linalg.norm(refk)
