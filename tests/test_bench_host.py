@@ -19,10 +19,13 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_cpu_baseline_fields():
     sys.path.insert(0, ROOT)
     import bench
-    from paper_2605_19951_amd import symbolic_host
-    flops64 = symbolic_host(64, 64, 64)["flops_per_pole"]
-    cb = bench.cpu_baseline(flops64)
+    cb = bench.cpu_baseline()
     assert cb["kind"] == "oracle" and cb["unit"] == "s"
     assert isinstance(cb["cores"], int) and 1 <= cb["cores"] <= (os.cpu_count() or 1)
-    assert cb["value"] > 0 and "32^3" in cb["sample"]
+    assert cb["value"] > 0 and "32^3" in cb["sample"] and "64^3" in cb["sample"]
+    with open(bench.ORACLE_RECORD) as f:
+        rec = json.load(f)
+    # the record is a measurement of the oracle at 64^3 (one pole, 8 sources)
+    assert rec["factor_s"] > 0 and rec["solve_s"] > 0 and rec["ratio_hex64_over_hex32"] > 1
+    assert "Model name" in rec["host"]
     json.dumps(cb)

@@ -79,6 +79,16 @@ def C16():
     return ti.smooth_workload(16, 2, S=2, m=6, K=9, g=4, seed=22)
 
 
+def RK13():
+    """13^3 workload whose poles and residues come from RKFIT (six conjugate
+    pairs fitted to exp(-t z) at its seven times) instead of the contour."""
+    from paper_2605_19951_amd import rkfit
+    wl = ti.smooth_workload(13, 2, S=3, m=6, K=7, g=2, seed=21)
+    tab = rkfit.rkfit_exp(wl.poles.t, 6)
+    wl.poles = ti.PoleTable(t=tab.t, xi=tab.xi, alpha=tab.alpha, err=tab.err)
+    return wl
+
+
 def S17():
     """12^3 mesh with seventeen loop sources on a grid of centres (loops may
     share edges; each column of F is still one loop)."""
@@ -101,6 +111,9 @@ CASES = {
     "s12_32": lambda: Run(ti.smooth_workload(16, 2, S=12, m=3, K=5, g=2, seed=23), 1),
     # seventeen right-hand sides: solved in two blocks of nine (the second
     # padded with a zero right-hand side), both precisions
+    # an RKFIT pole/residue table through the whole path, both precisions
+    "rk13_64": lambda: Run(RK13(), 0),
+    "rk13_32": lambda: Run(RK13(), 1),
     "s17_64": lambda: Run(S17(), 0),
     "s17_32": lambda: Run(S17(), 1),
     # factor panel schedules (the 13^3 root separator has 312 columns): 64-column
@@ -193,7 +206,8 @@ def test_data_all_times(name):
 
 
 @pytest.mark.parametrize("name", ["r13_64", "r13_32", "c16_64", "c16_32", "w16_64", "w16_32",
-                                  "s12_32", "s17_64", "s17_32"] + UPDATE_VARIANTS)
+                                  "s12_32", "s17_64", "s17_32", "rk13_64", "rk13_32"]
+                         + UPDATE_VARIANTS)
 def test_jvp_vjp(name):
     r = get(name)
     torch = r.torch
