@@ -201,33 +201,118 @@ def _flops_per_mesh(wls):
     return [symbolic_host(w.mesh.nx, w.mesh.ny, w.mesh.nz)["flops_per_pole"] for w in wls]
 
 
-def cpu_baseline(flops64):
-    """The FP64 oracle on the host: factor + solve of one pole of the same
-    generator on a 32^3 mesh (8 sources), scaled to all 16 poles at 64^3 by
-    the ratio of multifrontal factor flops.  The oracle runs as it stands:
-    its sparse LU calls the host BLAS, which may use several threads, so
-    `cores` is the process CPU time of the timed solve over its wall time."""
+def inversion_phase(torch, dev, prec, max_gn=25, lsqr_iters=20, lambda0=10.0,
+                    runtime_counts=(1, 5, 10, 20, 35)):
+    """The paper's inversion experiment on a uniform-hex analogue of its
+    four-block model (tem_inputs.four_block_workload: 32^3 cells of 5 m, a
+    40 m loop, 7 x 7 dB_z/dt receivers, 31 times in [1e-6, 1e-3] s, 21 RKFIT
+    pole pairs, 24,576 parameters): observed data = the forward response of
+    the true model plus 3 % Gaussian noise (+1e-9 absolute); Gauss-Newton
+    from the 0.1 S/m half-space with line search and lambda cooling
+    (tem_invert).  Then one Gauss-Newton iteration from the same start per
+    LSQR count in runtime_counts, and a least-squares fit of the paper's
+    linear runtime model t = a + b n_LSQR to them."""
     import numpy as np
     import tem_inputs as ti
-    from oracle.ordering import analyse, factor_flops
+    from paper_2605_19951_amd import Tem, rkfit
+    times = ti.log_times(1e-6, 1e-3, 31)
+    tab = rkfit.rkfit_exp(times, 21)
+    wl = ti.four_block_workload(poles=ti.PoleTable(t=tab.t, xi=tab.xi, alpha=tab.alpha,
+                                                   err=tab.err))
+    me = wl.mesh
+    K, R, P = len(times), wl.rx.n, len(wl.params)
+    t = Tem(0)
+    t.assemble(me.nx, me.ny, me.nz, me.h, 4e-7 * math.pi, torch.tensor(wl.sigma, device=dev),
+               wl.params)
+    t.analyse()
+    t.factor_poles(wl.poles.xi, prec)
+    F = torch.tensor(wl.F.T.copy(), device=dev)
+    d = torch.zeros((wl.S, K, R), dtype=torch.float64, device=dev)
+    t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+    d_true = d.cpu().numpy()
+    sd = 0.03 * np.abs(d_true) + 1e-9
+    d_obs = torch.tensor(d_true + sd * wl.extra["rng_noise"].standard_normal(d_true.shape),
+                         device=dev)
+    wd = torch.tensor(1.0 / sd, device=dev)
+    m0 = torch.full((P,), math.log(0.1), dtype=torch.float64, device=dev)
+
+    def restart():
+        m = m0.clone()
+        t.set_model(m)
+        t.factor_poles(wl.poles.xi, prec)
+        t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+        return m
+
+    m = restart()
+    t0 = time.perf_counter()
+    log = t.invert(d_obs, wd, m, m0, lambda0, max_gn, lsqr_iters)
+    total = time.perf_counter() - t0
+    # recovered conductivity of the four blocks (mean log10 over each block)
+    mf = m.cpu().numpy() / math.log(10.0)
+    c, k = me.nx // 2, me.k_if - 3
+    blocks = []
+    for (i0, j0), val in (((c - 7, c - 7), 1.0), ((c + 2, c + 2), 1.0),
+                          ((c + 2, c - 7), 0.01), ((c - 7, c + 2), 0.01)):
+        ids = [i + me.nx * (j + me.ny * k) for j in range(j0, j0 + 5) for i in range(i0, i0 + 5)]
+        blocks.append(dict(true_log10=math.log10(val), recovered_log10=float(mf[ids].mean())))
+    # runtime model: one iteration per LSQR count from the same start
+    pts = []
+    for n in runtime_counts:
+        m = restart()
+        r = t.invert(d_obs, wd, m, m0, lambda0, 1, n)[0]
+        pts.append(dict(lsqr=n, seconds=r["seconds"], factor_seconds=r["factor_seconds"],
+                        trials=r["trials"]))
+    A = np.array([[1.0, p_["lsqr"]] for p_ in pts])
+    y = np.array([p_["seconds"] for p_ in pts])
+    (a, b), *_ = np.linalg.lstsq(A, y, rcond=None)
+    t.close()
+    return dict(workload=wl.name, mesh="%dx%dx%d" % (me.nx, me.ny, me.nz), h_m=me.h,
+                n_unknowns=3 * me.nx * (me.nx - 1) ** 2, poles=len(wl.poles.xi),
+                rkfit_max_err=float(tab.err.max()), receivers=R, times=K, params=P,
+                precision="fp32_ir" if prec == 1 else "fp64", lambda0=lambda0,
+                lsqr_iters=lsqr_iters, seconds=total, iterations=log, blocks=blocks,
+                runtime_points=pts, runtime_model=dict(fixed_s=float(a), per_lsqr_s=float(b)))
+
+
+ORACLE_RECORD = os.path.join(ROOT, "profiles", "oracle_hex64_pole_cpu.json")
+
+
+def cpu_baseline():
+    """The FP64 oracle on the host, as it stands: factor + solve of pole 0 x
+    8 sources on the 32^3 sample mesh of the same generator, timed here
+    (about 10-20 s), scaled to all 16 poles at 64^3 by the ratio of the
+    oracle's 64^3 pole to the same 32^3 sample, both measured on one host
+    (profiles/oracle_hex64_pole_cpu.json, written by
+    tests/golden/make_hex64_pole.py).  The oracle's sparse LU calls the host
+    BLAS, which may use several threads, so `cores` is the process CPU time
+    of the timed solve over its wall time."""
+    import tem_inputs as ti
     from oracle.tem import OracleTEM
+    with open(ORACLE_RECORD) as f:
+        rec = json.load(f)
     wl = ti.smooth_workload(32, 4, S=8, m=16, K=60, g=4, seed=3, name="hex32_sample")
     me = wl.mesh
     o = OracleTEM(me.nx, me.ny, me.nz, me.h, wl.sigma, wl.F, wl.rx.ptr, wl.rx.col, wl.rx.val,
-                  wl.poles.xi, wl.poles.alpha, wl.params)
+                  wl.poles.xi[:1], wl.poles.alpha[:, :1], wl.params)
     o.ordering()
     c0 = time.process_time()
     t0 = time.perf_counter()
     o.solve(0, o.F)
     dt = time.perf_counter() - t0
     cpu = time.process_time() - c0
-    nodes, _, _ = analyse(o.mesh)
-    f32 = factor_flops(nodes)
-    scale = 16.0 * flops64 / f32
-    return dict(value=dt * scale, unit="s", cores=max(1, int(round(cpu / dt))), kind="oracle",
-                sample="factor+solve of 1 pole x 8 sources on a 32^3 mesh of the same generator "
-                       "(%.1f s wall, %.1f s CPU over its threads), scaled x%.0f (16 poles x "
-                       "factor-flop ratio 64^3/32^3)" % (dt, cpu, scale))
+    ratio = rec["ratio_hex64_over_hex32"]
+    pole64 = rec["factor_s"] + rec["solve_s"]
+    host = rec["host"]
+    return dict(value=16.0 * ratio * dt, unit="s", cores=max(1, int(round(cpu / dt))),
+                kind="oracle",
+                sample="factor+solve of 1 pole x 8 sources on the 32^3 sample mesh of the same "
+                       "generator, timed here (%.1f s wall, %.1f s CPU over its threads), x16 "
+                       "poles x %.1f, the measured ratio of the oracle's 64^3 pole (%.0f s "
+                       "factor+solve, peak %.0f GB) to the same 32^3 sample on one host (%s, "
+                       "%s CPUs)" % (dt, cpu, ratio, pole64, rec["peak_rss_gb"],
+                                     host.get("Model name", "?"), host.get("CPU(s)", "?")),
+                oracle_hex64_pole_s=pole64,
+                oracle_hex64_vjp_per_pole_s=rec["vjp_s"])
 
 
 def main():
@@ -242,6 +327,10 @@ def main():
                     help="skip the (untimed) per-level autotuning of the update kernels")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the counter-calibration copy (1 GiB, 5 times)")
+    ap.add_argument("--inversion", action="store_true",
+                    help="only run the four-block Gauss-Newton inversion and the runtime-model "
+                         "fit (prints its own JSON line)")
+    ap.add_argument("--inversion-precision", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the pole-sharded multi-GPU path is not part of this "
@@ -257,6 +346,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_probe:
         copy_probe(torch, dev)
+        return
+    if args.inversion:
+        print(json.dumps(inversion_phase(torch, dev, args.inversion_precision)), flush=True)
         return
     wl = ti.workload(2)
     me = wl.mesh
@@ -304,7 +396,7 @@ def main():
                 sweep=dict(bound="hbm", achieved=sweep_bw / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
                            frac=sweep_bw / PEAK_HBM))
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(info["flops_per_pole"])
+        line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
 
 

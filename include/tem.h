@@ -221,7 +221,7 @@ typedef struct {
 } tem_ir_stats;
 
 /* g_is = A_i^{-1} f_s for every pole i and right-hand side s, refined in
- * FP64 to ir->rtol (Algorithm 1, "compute A_i^{-1} f"); caches g for
+ * FP64 to ir->rtol (Algorithm 1, the shifted solve of each pole); caches g for
  * tem_jvp / tem_vjp.  Up to 16 right-hand sides share one pass over the
  * factors; more (up to 1024) are solved in equal blocks of at most 16.
  *   nrhs 1..1024.
@@ -306,6 +306,57 @@ tem_status tem_gn_step(tem_ctx *ctx, const double *d_obs, const double *wd, cons
                        const double *m_ref, double lambda, int32_t iters, double *dm,
                        double *hist, const tem_ir_opts *ir);
 
+/* ------------------------------------------------------------ inversion */
+
+typedef struct {
+  double lambda0;      /* initial regularisation weight, > 0 */
+  double chi2_target;  /* stop once chi^2 = ||W_d (d - d_obs)||^2 / n_data <= this (<= 0: 1) */
+  double c1;           /* Armijo constant (<= 0: 1e-4) */
+  double eta_min;      /* smallest step length tried (<= 0: 1/32) */
+  double conv_rtol;    /* an accepted step that lowers phi by less than conv_rtol * phi
+                          halves lambda (<= 0: 1e-2) */
+  int32_t max_gn;      /* Gauss-Newton iterations, >= 1 */
+  int32_t lsqr_iters;  /* LSQR iterations per step, >= 1 */
+} tem_invert_opts;
+
+typedef struct {
+  double lambda;         /* regularisation weight of the iteration */
+  double chi2;           /* chi^2 at the start of the iteration */
+  double phi;            /* phi = ||W_d (d - d_obs)||^2 + lambda ||R (m - m_ref)||^2 there */
+  double slope;          /* grad phi^T dm of the Gauss-Newton step dm */
+  double eta;            /* step length of the last trial */
+  double phi_new;        /* phi after the iteration (= phi when the step was rejected) */
+  double seconds;        /* wall time of the iteration: step, line search, restore */
+  double factor_seconds; /* of which: factorisations of the trial (and restored) models */
+  int32_t accepted;      /* 1: m += eta dm; 0: no trial down to eta_min met the condition */
+  int32_t trials;        /* forward runs of the line search */
+  int32_t lsqr_iters;    /* LSQR iterations of the step */
+  int32_t stop;          /* 1: chi^2 <= chi2_target ended the run (no step taken) */
+} tem_invert_record;
+
+/* Gauss-Newton inversion (section "Optimization") from the model of the
+ * last tem_forward, whose sources, receivers, residues, poles and
+ * precision it keeps using.  Iteration: phi and chi^2 at m (stop when
+ * chi^2 <= chi2_target); the step dm from LSQR as in tem_gn_step
+ * (lsqr_iters iterations, at the current lambda); a backtracking line
+ * search from eta = 1 that refactors every pole at m + eta dm and accepts
+ * the first trial with phi(m + eta dm) <= phi(m) + c1 eta grad phi^T dm,
+ * the next trial being the minimiser of the quadratic through phi(0), its
+ * slope and phi(eta), kept in [eta/10, eta/2]; lambda is halved when no
+ * trial down to eta_min is accepted (m stays) or when an accepted step lowers
+ * phi by less than conv_rtol * phi (the adaptive cooling of the section).
+ *   d_obs, wd   device, S*K*R doubles ([s][j][r]); wd = W_d diagonal
+ *   m           device, P doubles: in, the model of the last tem_forward
+ *               (m = ln sigma on the parameter cells); out, the final model
+ *   m_ref       device, P doubles
+ *   ir          refinement options of every solve (may be NULL)
+ *   log         host, opts->max_gn records (one per iteration);
+ *               *n_records receives how many were written
+ * On return the context is factored and solved at the final model. */
+tem_status tem_invert(tem_ctx *ctx, const double *d_obs, const double *wd, double *m,
+                      const double *m_ref, const tem_invert_opts *opts, const tem_ir_opts *ir,
+                      tem_invert_record *log, int32_t *n_records);
+
 /* ------------------------------------------------------ ragged batches
  * Several independent meshes solved together: the per-pole shifted systems
  * of every mesh (the paper's Algorithm 1, repeated per mesh) are merged
@@ -314,8 +365,9 @@ tem_status tem_gn_step(tem_ctx *ctx, const double *d_obs, const double *wd, cons
  * meshes and all poles.  Meshes may differ in size, pole count and source
  * count; missing poles of a mesh are not computed.  After
  * tem_assemble_batch the context is in batch mode: tem_analyse (with its
- * usual options) analyses every mesh, then tem_factor_poles_batch and
- * tem_forward_batch apply.  tem_set_model, tem_factor_poles,
+ * usual options) analyses every mesh, then tem_factor_poles_batch,
+ * tem_forward_batch and (after tem_set_params_batch) tem_jvp_batch and
+ * tem_vjp_batch apply.  tem_set_model, tem_factor_poles,
  * tem_solve_poles, tem_forward, tem_jvp, tem_vjp, tem_gn_step and
  * tem_export_operators return TEM_ESTATE in batch mode; tem_assemble
  * returns the context to single-mesh mode. */
@@ -361,6 +413,26 @@ tem_status tem_forward_batch(tem_ctx *ctx, const int32_t *S, const double *F, co
                              const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
                              int32_t K, const double *alpha, const tem_ir_opts *ir, double *d,
                              tem_ir_stats *stats);
+
+/* Model parameters of every mesh of a batch (m = ln sigma on the given cells
+ * of each mesh, section "The Inverse Problem"); needed by tem_jvp_batch and
+ * tem_vjp_batch.  Kept until the batch changes meshes.
+ *   n_params     host, n_mesh counts (0..cells of the mesh).
+ *   param_cells  host, mesh b's n_params[b] distinct cell ids (its own cell
+ *                numbering) after those of meshes 0..b-1.  Copied. */
+tem_status tem_set_params_batch(tem_ctx *ctx, const int32_t *n_params, const int32_t *param_cells);
+
+/* J v and J^T w of every mesh of a batch through the cached factors of the
+ * last tem_forward_batch (as tem_jvp / tem_vjp per mesh; the adjoint and
+ * tangent solves of all meshes and poles run as one merged system).
+ *   v    device, mesh b's n_params[b] doubles after those of the previous meshes.
+ *   jv   device, mesh b's S[b]*K*R[b] doubles ([s][j][r]) after the previous ones.
+ *   w    device, laid out as jv.   jtw  device, laid out as v.
+ *   stats  as tem_forward_batch. */
+tem_status tem_jvp_batch(tem_ctx *ctx, const double *v, double *jv, const tem_ir_opts *ir,
+                         tem_ir_stats *stats);
+tem_status tem_vjp_batch(tem_ctx *ctx, const double *w, double *jtw, const tem_ir_opts *ir,
+                         tem_ir_stats *stats);
 
 /* ------------------------------------------------------------ autotuning */
 

@@ -143,6 +143,117 @@ __global__ __launch_bounds__(256) void k_residual(int64_t N, int npole, int S,
   }
 }
 
+// r = f - (K - xi_p M) x by row blocks: a workgroup owns one block of at
+// most RB_ROWS consecutive rows whose columns (its "halo", at most RB_HALO
+// distinct rows of x) are listed per block; for every pole of the launch and
+// every chunk of up to RB_SC right-hand sides it stages those x rows in LDS
+// with coalesced loads, then forms the sums from LDS.  Four consecutive
+// lanes share a row: each keeps a quarter of the row's K and M entries and
+// local column indices in registers for all poles (the matrix is read once
+// per call, each x row once per block that touches it instead of once per
+// nonzero), accumulates its quarter for every source of the chunk, and the
+// four partial sums are added across the lanes.
+__global__ __launch_bounds__(256) void k_residual_blk(
+    int64_t N, int npole, int S, int64_t nblk, const int64_t *rb_row, const int64_t *rb_hoff,
+    const int32_t *rb_h, const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
+    const double *Mv, const double *xi, Seg sg, const double *f_real, const cpx<double> *f_cplx,
+    const cpx<double> *x, cpx<double> *r) {
+  constexpr int PER = (RB_NNZ + 3) / 4;   // entries per lane
+  __shared__ cpx<double> xs[RB_HALO * RB_SC];
+  const int64_t b = xcd_block(nblk);
+  if (b >= nblk) return;   // uniform over the workgroup
+  const int64_t row0 = rb_row[b];
+  const int nrow = (int)(rb_row[b + 1] - row0);
+  const int64_t h0 = rb_hoff[b];
+  const int nh = (int)(rb_hoff[b + 1] - h0);
+  const int t = threadIdx.x, lr = t >> 2, qt = t & 3;
+  const bool has_row = lr < nrow;
+  const int64_t row = row0 + (has_row ? lr : 0);
+  double kv[PER], mv[PER];
+  int lc[PER];
+  int cnt = 0;   // entries of this lane
+  {
+    const int64_t t0 = rowptr[row];
+    const int nnz = has_row ? (int)(rowptr[row + 1] - t0) : 0;
+    cnt = min(PER, max(0, nnz - qt * PER));
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const bool in = j < cnt;
+      const int64_t e = t0 + qt * PER + j;
+      kv[j] = in ? Kv[e] : 0.0;
+      mv[j] = in ? Mv[e] : 0.0;
+      lc[j] = in ? (int)lcol[e] : 0;
+    }
+  }
+  const int64_t xb = 2 * (int64_t)seg_find(sg, row0) * sg.stride;
+  for (int p = 0; p < npole; ++p) {
+    const double xr = xi[xb + 2 * p], xim = xi[xb + 2 * p + 1];
+    const cpx<double> *X = x + (int64_t)p * N * S;
+    for (int s0 = 0; s0 < S; s0 += RB_SC) {
+      const int sc = min(RB_SC, S - s0);
+      __syncthreads();   // the previous chunk's sums have read xs
+      for (int e = t; e < nh * sc; e += 256) {
+        const int hh = e / sc, ss = e - hh * sc;
+        xs[hh * RB_SC + ss] = X[(int64_t)rb_h[h0 + hh] * S + s0 + ss];
+      }
+      __syncthreads();
+      double ar[RB_SC], ai[RB_SC];
+#pragma unroll
+      for (int ss = 0; ss < RB_SC; ++ss) ar[ss] = ai[ss] = 0.0;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        if (j < cnt) {
+          const double sr = kv[j] - xr * mv[j], si = -xim * mv[j];
+          const cpx<double> *xv = xs + lc[j] * RB_SC;
+#pragma unroll
+          for (int ss = 0; ss < RB_SC; ++ss) {
+            if (ss < sc) {
+              const cpx<double> v = xv[ss];
+              ar[ss] += sr * v.re - si * v.im;
+              ai[ss] += sr * v.im + si * v.re;
+            }
+          }
+        }
+      }
+      // the row's four partial sums (lanes 4 lr .. 4 lr + 3)
+#pragma unroll
+      for (int ss = 0; ss < RB_SC; ++ss) {
+        ar[ss] += __shfl_xor(ar[ss], 1);
+        ai[ss] += __shfl_xor(ai[ss], 1);
+        ar[ss] += __shfl_xor(ar[ss], 2);
+        ai[ss] += __shfl_xor(ai[ss], 2);
+      }
+      if (!has_row) continue;
+#pragma unroll
+      for (int ss = 0; ss < RB_SC; ++ss) {
+        if ((ss & 3) != qt || ss >= sc) continue;
+        const int c = s0 + ss;
+        double fr = 0.0, fi = 0.0;
+        if (f_cplx) {
+          const cpx<double> f = f_cplx[((int64_t)p * N + row) * S + c];
+          fr = f.re;
+          fi = f.im;
+        } else if (f_real) {
+          fr = f_real[row * S + c];
+        }
+        r[((int64_t)p * N + row) * S + c] = {fr - ar[ss], fi - ai[ss]};
+      }
+    }
+  }
+}
+
+hipError_t launch_residual_blk(hipStream_t st, int64_t N, int npole, int S, int64_t nblk,
+                               const int64_t *rb_row, const int64_t *rb_hoff, const int32_t *rb_h,
+                               const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
+                               const double *Mv, const double *xi, Seg sg, const double *f_real,
+                               const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r) {
+  if (N <= 0 || npole <= 0 || nblk <= 0) return hipSuccess;
+  if (S < 1 || S > 16 || !x) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_residual_blk, dim3(xcd_grid(nblk, 1)), dim3(256), 0, st, N, npole, S, nblk,
+                     rb_row, rb_hoff, rb_h, rowptr, lcol, Kv, Mv, xi, sg, f_real, f_cplx, x, r);
+  return hipGetLastError();
+}
+
 hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
                            const int32_t *col, const double *Kv, const double *Mv,
                            const double *xi, Seg sg, const double *f_real,
@@ -435,10 +546,10 @@ hipError_t launch_param_scatter(hipStream_t st, int P, const int32_t *params, co
 }
 
 // rhs[p][q][s] = xi_p sum_{cells c of edge q} vs[c] sum_b Me[la][b] g[p][cell_new[c][b]][s]
-__global__ void k_jv_rhs(int64_t N, int npole, int S, int nx, int ny, int nz,
-                         const int32_t *row_edge, const int32_t *cell_new, const double *vs,
-                         const double *Me, const double *xi, const cpx<double> *g,
-                         cpx<double> *rhs) {
+__global__ void k_jv_rhs(int64_t N, int npole, int S, int ldS, int64_t pstride, int nx, int ny,
+                         int nz, const int32_t *row_edge, const int32_t *cell_new,
+                         const double *vs, const double *Me, const double *xi,
+                         const cpx<double> *g, cpx<double> *rhs) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t mS = (int64_t)npole * S;
   if (idx >= N * mS) return;
@@ -457,7 +568,7 @@ __global__ void k_jv_rhs(int64_t N, int npole, int S, int nx, int ny, int nz,
     e -= ex + ey; d = 2; i = (int)(e % (nx + 1)); int64_t r = e / (nx + 1); j = (int)(r % (ny + 1)); k = (int)(r / (ny + 1));
   }
   const int AB[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
-  const cpx<double> *G = g + (int64_t)p * N * S + c;
+  const cpx<double> *G = g + (int64_t)p * pstride + c;
   double ar = 0.0, ai = 0.0;
   for (int pp = 0; pp < 4; ++pp) {
     const int a = AB[pp][0], b = AB[pp][1];
@@ -475,7 +586,7 @@ __global__ void k_jv_rhs(int64_t N, int npole, int S, int nx, int ny, int nz,
       const int lb = 4 * d + t;
       const int32_t qb = cell_new[cell * 12 + lb];
       if (qb < 0) continue;
-      const cpx<double> v = G[(int64_t)qb * S];
+      const cpx<double> v = G[(int64_t)qb * ldS];
       sr += Me[la * 12 + lb] * v.re;
       si += Me[la * 12 + lb] * v.im;
     }
@@ -483,28 +594,30 @@ __global__ void k_jv_rhs(int64_t N, int npole, int S, int nx, int ny, int nz,
     ai += w * si;
   }
   const double xr = xi[2 * p], xim = xi[2 * p + 1];
-  rhs[((int64_t)p * N + q) * S + c] = {xr * ar - xim * ai, xr * ai + xim * ar};
+  rhs[(int64_t)p * pstride + q * ldS + c] = {xr * ar - xim * ai, xr * ai + xim * ar};
 }
 
-hipError_t launch_jv_rhs(hipStream_t st, int64_t N, int npole, int S, int nx, int ny, int nz,
-                         const int32_t *row_edge, const int32_t *cell_new, const double *vs,
-                         const double *Me, const double *xi, const cpx<double> *g,
-                         cpx<double> *rhs) {
+hipError_t launch_jv_rhs(hipStream_t st, int64_t N, int npole, int S, int ldS, int64_t pstride,
+                         int nx, int ny, int nz, const int32_t *row_edge, const int32_t *cell_new,
+                         const double *vs, const double *Me, const double *xi,
+                         const cpx<double> *g, cpx<double> *rhs) {
   const int64_t tot = N * npole * S;
+  if (tot <= 0) return hipSuccess;
+  if (S > ldS || pstride < N * ldS) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_jv_rhs, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole, S,
-                     nx, ny, nz, row_edge, cell_new, vs, Me, xi, g, rhs);
+                     ldS, pstride, nx, ny, nz, row_edge, cell_new, vs, Me, xi, g, rhs);
   return hipGetLastError();
 }
 
 // rhs = Q^T (sum_j alpha[j][p] w[s][j][:]); one thread per (pole, rhs) walks
 // the receivers in order (rhs must be zeroed first).
-__global__ void k_jtw_rhs(int S, int K, int R, int npole, int64_t N, const int64_t *q_ptr,
-                          const int32_t *q_col, const double *q_val, const cpx<double> *alpha,
-                          const double *w, cpx<double> *rhs) {
+__global__ void k_jtw_rhs(int S, int ldS, int64_t pstride, int K, int R, int npole,
+                          const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
+                          const cpx<double> *alpha, const double *w, cpx<double> *rhs) {
   const int ps = blockIdx.x * blockDim.x + threadIdx.x;
   if (ps >= npole * S) return;
   const int p = ps / S, s = ps % S;
-  cpx<double> *Rv = rhs + (int64_t)p * N * S + s;
+  cpx<double> *Rv = rhs + (int64_t)p * pstride + s;
   for (int r = 0; r < R; ++r) {
     double wr = 0.0, wi = 0.0;
     for (int j = 0; j < K; ++j) {
@@ -514,29 +627,30 @@ __global__ void k_jtw_rhs(int S, int K, int R, int npole, int64_t N, const int64
       wi += a.im * x;
     }
     for (int64_t t = q_ptr[r]; t < q_ptr[r + 1]; ++t) {
-      cpx<double> v = Rv[(int64_t)q_col[t] * S];
+      cpx<double> v = Rv[(int64_t)q_col[t] * ldS];
       v.re += q_val[t] * wr;
       v.im += q_val[t] * wi;
-      Rv[(int64_t)q_col[t] * S] = v;
+      Rv[(int64_t)q_col[t] * ldS] = v;
     }
   }
 }
 
-hipError_t launch_jtw_rhs(hipStream_t st, int S, int K, int R, int npole, int64_t N,
-                          const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
-                          const cpx<double> *alpha, const double *w, cpx<double> *rhs) {
-  hipError_t e = launch_fill_f64(st, (double *)rhs, 2 * N * npole * S, 0.0);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_jtw_rhs, dim3((npole * S + 63) / 64), dim3(64), 0, st, S, K, R, npole, N,
-                     q_ptr, q_col, q_val, alpha, w, rhs);
+hipError_t launch_jtw_rhs(hipStream_t st, int S, int ldS, int64_t pstride, int K, int R,
+                          int npole, const int64_t *q_ptr, const int32_t *q_col,
+                          const double *q_val, const cpx<double> *alpha, const double *w,
+                          cpx<double> *rhs) {
+  if (npole * S <= 0) return hipSuccess;
+  if (S > ldS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jtw_rhs, dim3((npole * S + 63) / 64), dim3(64), 0, st, S, ldS, pstride, K,
+                     R, npole, q_ptr, q_col, q_val, alpha, w, rhs);
   return hipGetLastError();
 }
 
 // (J^T w)_p = 2 Re sum_{i,s} xi_i sigma_c g|_c^T Me lam|_c, one thread per parameter
-__global__ void k_jtw_reduce(int P, int npole, int S, int64_t N, const int32_t *params,
-                             const int32_t *cell_new, const double *sigma, const double *Me,
-                             const double *xi, const cpx<double> *g, const cpx<double> *lam,
-                             double *out) {
+__global__ void k_jtw_reduce(int P, int npole, int S, int ldS, int64_t pstride,
+                             const int32_t *params, const int32_t *cell_new, const double *sigma,
+                             const double *Me, const double *xi, const cpx<double> *g,
+                             const cpx<double> *lam, double *out) {
   const int pp = blockIdx.x * blockDim.x + threadIdx.x;
   if (pp >= P) return;
   const int64_t cell = params[pp];
@@ -546,14 +660,14 @@ __global__ void k_jtw_reduce(int P, int npole, int S, int64_t N, const int32_t *
   for (int i = 0; i < npole; ++i) {
     double br = 0.0, bi = 0.0;
     for (int s = 0; s < S; ++s) {
-      const cpx<double> *G = g + (int64_t)i * N * S + s;
-      const cpx<double> *L = lam + (int64_t)i * N * S + s;
+      const cpx<double> *G = g + (int64_t)i * pstride + s;
+      const cpx<double> *L = lam + (int64_t)i * pstride + s;
       for (int dd = 0; dd < 3; ++dd) {
         cpx<double> gv[4], lv[4];
         for (int t = 0; t < 4; ++t) {
           const int32_t q = qe[4 * dd + t];
-          gv[t] = q >= 0 ? G[(int64_t)q * S] : cpx<double>{0.0, 0.0};
-          lv[t] = q >= 0 ? L[(int64_t)q * S] : cpx<double>{0.0, 0.0};
+          gv[t] = q >= 0 ? G[(int64_t)q * ldS] : cpx<double>{0.0, 0.0};
+          lv[t] = q >= 0 ? L[(int64_t)q * ldS] : cpx<double>{0.0, 0.0};
         }
         for (int a = 0; a < 4; ++a) {
           double mr = 0.0, mi = 0.0;
@@ -572,13 +686,14 @@ __global__ void k_jtw_reduce(int P, int npole, int S, int64_t N, const int32_t *
   out[pp] = tot * sigma[cell];
 }
 
-hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int64_t N,
+hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int ldS, int64_t pstride,
                              const int32_t *params, const int32_t *cell_new, const double *sigma,
                              const double *Me, const double *xi, const cpx<double> *g,
                              const cpx<double> *lam, double *out) {
   if (P <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_jtw_reduce, dim3((P + 127) / 128), dim3(128), 0, st, P, npole, S, N, params,
-                     cell_new, sigma, Me, xi, g, lam, out);
+  if (S > ldS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jtw_reduce, dim3((P + 127) / 128), dim3(128), 0, st, P, npole, S, ldS,
+                     pstride, params, cell_new, sigma, Me, xi, g, lam, out);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <limits>
 #include <cmath>
 #include <complex>
@@ -160,6 +161,9 @@ struct MF {
   int64_t w_rows_max = 0;
   DBuf w_t, w_w0, w_w1;            // sweep work space
   DBuf d_np;                       // batch: poles of each front's mesh (else empty)
+  // row blocks of the FP64 residual (edge system; see launch_residual_blk)
+  int64_t rb_n = 0;
+  DBuf d_rb_row, d_rb_hoff, d_rb_h, d_lcol;
   std::vector<int32_t> h_np;
   // poles of front s among the g slots starting at p0
   int present(int s, int p0, int g) const {
@@ -242,8 +246,11 @@ struct tem_ctx {
   int MP = 0;
   DBuf d_row_seg, d_nnz_seg;
   std::vector<int32_t> h_node_edges, h_edge_nodes;   // nodal incidence (host copies)
+  // survey of the last tem_forward_batch: sources and receivers per mesh,
+  // first merged receiver row of each mesh; parameter cells per mesh
+  // (tem_set_params_batch): mesh b's parameters are [param_off[b], param_off[b+1])
   std::vector<int> S_mesh, R_mesh;
-  int S_max = 0;
+  std::vector<int64_t> q_row_off, param_off;
   // factors
   int npole = 0;                   // pole slots (a batch: the largest pole count)
   int64_t fac_elems = 0;           // factor elements of the poles present
@@ -266,6 +273,8 @@ struct tem_ctx {
   DBuf d_reg_lo, d_reg_hi, d_reg_incp, d_reg_inc;
   // LSQR work space
   DBuf l_u, l_v, l_w, l_x, l_tmpd, l_tmpm, l_part, l_scal, l_V;
+  // inversion work space (tem_invert)
+  DBuf inv_d, inv_dt, inv_mt, inv_dm, inv_t1, inv_t2, inv_t3;
   // work space
   DBuf w_x;                        // factor-precision sweep vector
   DBuf v_r, v_z, v_rhs, v_lam, v_vs, v_dots, v_partial, v_inv, v_nrm, v_coef, v_mask;
@@ -357,6 +366,63 @@ tem_status run_assemble_edges(tem_ctx *c) {
   return TEM_OK;
 }
 
+// Row blocks of the residual: consecutive rows, at most RB_ROWS of them and
+// at most RB_HALO distinct columns, never across a segment start (a mesh of
+// a batch); each block's halo is its sorted column set and lcol gives every
+// entry's position in it.  Rows longer than RB_NNZ are refused.
+tem_status build_res_blocks(tem_ctx *c, MF &mf, const std::vector<int64_t> &rowptr,
+                            const std::vector<int32_t> &col, const std::vector<int64_t> &seg) {
+  const int64_t N = (int64_t)rowptr.size() - 1;
+  std::vector<int64_t> brow(1, 0), hoff(1, 0);
+  std::vector<int32_t> halo;
+  std::vector<uint16_t> lcol(col.size());
+  std::vector<int64_t> stamp(std::max<int64_t>(N, 1), -1);
+  std::vector<int32_t> pos(std::max<int64_t>(N, 1), 0);
+  std::vector<int32_t> h;
+  size_t si = 0;
+  int64_t r = 0;
+  while (r < N) {
+    while (si + 1 < seg.size() && seg[si + 1] <= r) ++si;
+    const int64_t seg_end = si + 1 < seg.size() ? seg[si + 1] : N;
+    const int64_t blk = (int64_t)brow.size() - 1, r0 = r;
+    h.clear();
+    while (r < N && r < seg_end && r - r0 < RB_ROWS) {
+      if (rowptr[r + 1] - rowptr[r] > RB_NNZ)
+        return fail(c, TEM_EINVAL, "residual blocks: a row has more than 33 entries");
+      int add = 0;
+      for (int64_t t = rowptr[r]; t < rowptr[r + 1]; ++t)
+        if (stamp[col[t]] != blk) {
+          stamp[col[t]] = blk;
+          ++add;
+          h.push_back(col[t]);
+        }
+      if ((int64_t)h.size() > RB_HALO) {
+        // the row does not fit: undo its new columns (r > r0 here, since a
+        // single row has at most RB_NNZ < RB_HALO columns)
+        for (int k = 0; k < add; ++k) {
+          stamp[h.back()] = -1;
+          h.pop_back();
+        }
+        break;
+      }
+      ++r;
+    }
+    std::sort(h.begin(), h.end());
+    for (size_t k = 0; k < h.size(); ++k) pos[h[k]] = (int32_t)k;
+    for (int64_t t = rowptr[r0]; t < rowptr[r]; ++t) lcol[t] = (uint16_t)pos[col[t]];
+    halo.insert(halo.end(), h.begin(), h.end());
+    brow.push_back(r);
+    hoff.push_back((int64_t)halo.size());
+  }
+  hipStream_t st = c->stream;
+  mf.rb_n = (int64_t)brow.size() - 1;
+  HIPCHK(upload(mf.d_rb_row, brow, st), "upload residual blocks");
+  HIPCHK(upload(mf.d_rb_hoff, hoff, st), "upload residual blocks");
+  HIPCHK(upload(mf.d_rb_h, halo, st), "upload residual blocks");
+  HIPCHK(upload(mf.d_lcol, lcol, st), "upload residual blocks");
+  return TEM_OK;
+}
+
 tem_status upload_pattern(tem_ctx *c, MF &mf) {
   hipStream_t st = c->stream;
   build_pattern(c->mt, mf.perm, mf.pat, mf.nodes);
@@ -365,6 +431,7 @@ tem_status upload_pattern(tem_ctx *c, MF &mf) {
   HIPCHK(upload(mf.d_col, mf.pat.col, st), "upload col");
   HIPCHK(upload(mf.d_row_ent, mf.pat.row_edge, st), "upload row map");
   HIPCHK(upload(mf.d_ent_new, mf.pat.edge_new, st), "upload entity map");
+  if (!mf.nodes) TRY(build_res_blocks(c, mf, mf.pat.rowptr, mf.pat.col, {0}));
   return TEM_OK;
 }
 
@@ -1154,9 +1221,11 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
     // the shift and coefficient tables are [mesh][pole]: offsetting them
     // by p0 keeps the (mesh, p0 + p) entry under index mesh * stride + p
     const int64_t o = (int64_t)pr.p0 * N * S;
-    HIPCHK(launch_residual(st, N, pr.n, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                           c->d_K.as<double>(), c->d_M.as<double>(),
-                           c->d_xi.as<double>() + 2 * pr.p0, rs, nullptr, r + o, z + o, w + o),
+    HIPCHK(launch_residual_blk(st, N, pr.n, S, c->ed.rb_n, c->ed.d_rb_row.as<int64_t>(),
+                               c->ed.d_rb_hoff.as<int64_t>(), c->ed.d_rb_h.as<int32_t>(),
+                               c->ed.d_rowptr.as<int64_t>(), c->ed.d_lcol.as<uint16_t>(),
+                               c->d_K.as<double>(), c->d_M.as<double>(),
+                               c->d_xi.as<double>() + 2 * pr.p0, rs, nullptr, r + o, z + o, w + o),
            "aux residual");
     // the nodal factor is the same for every pole: its sweep takes the
     // run's systems packed S2 = 16 to a pass
@@ -1254,10 +1323,19 @@ tem_status refine_block(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       // the shift table is [mesh][pole]: offsetting it by p0 keeps the
       // (mesh, p0 + p) entry under index mesh * stride + p
       const int64_t o = (int64_t)pr.p0 * N * S;
-      HIPCHK(launch_residual(st, N, pr.n, S, c->ed.d_rowptr.as<int64_t>(), c->ed.d_col.as<int32_t>(),
-                             c->d_K.as<double>(), c->d_M.as<double>(), xi + 2 * pr.p0, rs, f_real,
-                             f_cplx ? f_cplx + o : nullptr, xv ? xv + o : nullptr, r + o),
-             "residual");
+      if (xv)
+        HIPCHK(launch_residual_blk(st, N, pr.n, S, c->ed.rb_n, c->ed.d_rb_row.as<int64_t>(),
+                                   c->ed.d_rb_hoff.as<int64_t>(), c->ed.d_rb_h.as<int32_t>(),
+                                   c->ed.d_rowptr.as<int64_t>(), c->ed.d_lcol.as<uint16_t>(),
+                                   c->d_K.as<double>(), c->d_M.as<double>(), xi + 2 * pr.p0, rs,
+                                   f_real, f_cplx ? f_cplx + o : nullptr, xv + o, r + o),
+               "residual");
+      else   // x = 0: r = f
+        HIPCHK(launch_residual(st, N, pr.n, S, c->ed.d_rowptr.as<int64_t>(),
+                               c->ed.d_col.as<int32_t>(), c->d_K.as<double>(), c->d_M.as<double>(),
+                               xi + 2 * pr.p0, rs, f_real, f_cplx ? f_cplx + o : nullptr, nullptr,
+                               r + o),
+               "residual");
     }
     return TEM_OK;
   };
@@ -1674,6 +1752,7 @@ tem_status merge_systems(tem_ctx *c, bool nodes) {
   HIPCHK(upload(M.d_col, P.col, st), "upload col");
   HIPCHK(upload(M.d_row_ent, P.row_edge, st), "upload row map");
   HIPCHK(upload(M.d_ent_new, P.edge_new, st), "upload entity map");
+  if (!nodes) TRY(build_res_blocks(c, M, P.rowptr, P.col, roff));
   return build_front_maps(c, M);
 }
 
@@ -1733,6 +1812,10 @@ void batch_release(tem_ctx *c) {
   c->np_mesh.clear();
   c->ed.h_np.clear();
   c->ed.d_np.release();
+  c->S_mesh.clear();
+  c->R_mesh.clear();
+  c->q_row_off.clear();
+  c->param_off.clear();
 }
 
 // =================================================================== ABI
@@ -2210,9 +2293,10 @@ tem_status tem_jvp(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *i
   HIPCHK(launch_param_scatter(st, (int)c->params.size(), c->d_params.as<int32_t>(), v,
                               c->d_sigma.as<double>(), c->mt.n_cells, c->v_vs.as<double>()),
          "param scatter");
-  HIPCHK(launch_jv_rhs(st, N, m, S, c->mt.nx, c->mt.ny, c->mt.nz, c->ed.d_row_ent.as<int32_t>(),
-                       c->d_cell_new.as<int32_t>(), c->v_vs.as<double>(), c->d_Me.as<double>(),
-                       c->d_xi.as<double>(), c->d_g.as<cpx<double>>(), c->v_rhs.as<cpx<double>>()),
+  HIPCHK(launch_jv_rhs(st, N, m, S, S, N * S, c->mt.nx, c->mt.ny, c->mt.nz,
+                       c->ed.d_row_ent.as<int32_t>(), c->d_cell_new.as<int32_t>(),
+                       c->v_vs.as<double>(), c->d_Me.as<double>(), c->d_xi.as<double>(),
+                       c->d_g.as<cpx<double>>(), c->v_rhs.as<cpx<double>>()),
          "jv rhs");
   IrResult res;
   TRY(refine_solve(c, nullptr, c->v_rhs.as<cpx<double>>(), S, c->v_lam.as<cpx<double>>(), ir, res));
@@ -2241,13 +2325,14 @@ tem_status tem_vjp(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *
   const int S = c->S, m = c->npole;
   TRY(ensure_vec(c, c->v_rhs, sizeof(cpx<double>) * (size_t)m * N * S, "alloc rhs"));
   TRY(ensure_vec(c, c->v_lam, sizeof(cpx<double>) * (size_t)m * N * S, "alloc sol"));
-  HIPCHK(launch_jtw_rhs(st, S, c->K, c->R, m, N, c->d_qptr.as<int64_t>(), c->d_qcol.as<int32_t>(),
-                        c->d_qval.as<double>(), c->d_alpha.as<cpx<double>>(), w,
-                        c->v_rhs.as<cpx<double>>()),
+  HIPCHK(launch_fill_f64(st, (double *)c->v_rhs.p, 2 * N * m * S, 0.0), "zero rhs");
+  HIPCHK(launch_jtw_rhs(st, S, S, N * S, c->K, c->R, m, c->d_qptr.as<int64_t>(),
+                        c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
+                        c->d_alpha.as<cpx<double>>(), w, c->v_rhs.as<cpx<double>>()),
          "jtw rhs");
   IrResult res;
   TRY(refine_solve(c, nullptr, c->v_rhs.as<cpx<double>>(), S, c->v_lam.as<cpx<double>>(), ir, res));
-  HIPCHK(launch_jtw_reduce(st, (int)c->params.size(), m, S, N, c->d_params.as<int32_t>(),
+  HIPCHK(launch_jtw_reduce(st, (int)c->params.size(), m, S, S, N * S, c->d_params.as<int32_t>(),
                            c->d_cell_new.as<int32_t>(), c->d_sigma.as<double>(),
                            c->d_Me.as<double>(), c->d_xi.as<double>(), c->d_g.as<cpx<double>>(),
                            c->v_lam.as<cpx<double>>(), jtw),
@@ -2287,16 +2372,15 @@ static tem_status lsqr_norm(tem_ctx *c, int64_t n, const double *a, double &out)
   return TEM_OK;
 }
 
-tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const double *m,
-                       const double *m_ref, double lambda, int32_t iters, double *dm,
-                       double *hist, const tem_ir_opts *ir) {
-  if (!c) return TEM_EINVAL;
-  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_gn_step: not available on a batch of meshes");
-  if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_gn_step: call tem_forward first");
-  if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_gn_step: no model parameters");
-  if (!d_obs || !wd || !m || !m_ref || !dm || iters <= 0 || !(lambda >= 0) || !std::isfinite(lambda))
-    return fail(c, TEM_EINVAL, "tem_gn_step: bad argument");
-  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+// LSQR on the Gauss-Newton least-squares problem at the current model (the
+// one the cached factors and solutions belong to).  With slope != NULL also
+// returns grad phi(m)^T dm for phi = ||W_d (d - d_obs)||^2 + lambda
+// ||R (m - m_ref)||^2: the first bidiagonalisation step gives
+// A^T b = alpha_1 beta_1 v_1 = -grad phi / 2, so the slope is
+// -2 alpha_1 beta_1 v_1^T dm (no further solve).
+tem_status gn_lsqr(tem_ctx *c, const double *d_obs, const double *wd, const double *m,
+                   const double *m_ref, double lambda, int32_t iters, double *dm, double *hist,
+                   const tem_ir_opts *ir, double *slope) {
   hipStream_t st = c->stream;
   const int64_t nd = (int64_t)c->S * c->K * c->R, nr = c->n_reg, nu = nd + nr;
   const int P = (int)c->params.size();
@@ -2349,6 +2433,7 @@ tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const 
   HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 0.0, v), "v = 0");
   TRY(rmatvec(1.0, 0.0));
   TRY(lsqr_norm(c, P, v, alpha));
+  const double ab1 = alpha * beta;
   if (alpha > 0) HIPCHK(launch_raxpby(st, P, 0.0, nullptr, nullptr, 1.0 / alpha, v), "v /= alpha");
   HIPCHK(launch_raxpby(st, P, 1.0, v, nullptr, 0.0, Vb), "V0 = v");
   HIPCHK(launch_raxpby(st, P, 1.0, v, nullptr, 0.0, w), "w = v");
@@ -2382,7 +2467,199 @@ tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const 
     if (hist) hist[it] = phibar;
   }
   HIPCHK(hipMemcpyAsync(dm, x, sizeof(double) * P, hipMemcpyDeviceToDevice, st), "dm");
+  if (slope) {
+    double v1x = 0.0;
+    HIPCHK(launch_rdot(st, P, Vb, x, c->l_part.as<double>(), c->l_scal.as<double>()), "v1 . dm");
+    HIPCHK(hipMemcpyAsync(&v1x, c->l_scal.p, sizeof(double), hipMemcpyDeviceToHost, st), "d2h");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    *slope = -2.0 * ab1 * v1x;
+  }
   HIPCHK(hipStreamSynchronize(st), "gn sync");
+  return TEM_OK;
+}
+
+tem_status tem_gn_step(tem_ctx *c, const double *d_obs, const double *wd, const double *m,
+                       const double *m_ref, double lambda, int32_t iters, double *dm,
+                       double *hist, const tem_ir_opts *ir) {
+  if (!c) return TEM_EINVAL;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_gn_step: not available on a batch of meshes");
+  if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_gn_step: call tem_forward first");
+  if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_gn_step: no model parameters");
+  if (!d_obs || !wd || !m || !m_ref || !dm || iters <= 0 || !(lambda >= 0) || !std::isfinite(lambda))
+    return fail(c, TEM_EINVAL, "tem_gn_step: bad argument");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  return gn_lsqr(c, d_obs, wd, m, m_ref, lambda, iters, dm, hist, ir, nullptr);
+}
+
+// ------------------------------------------------------------ inversion
+// ||a||^2 of n device doubles (host result)
+static tem_status sq_norm(tem_ctx *c, int64_t n, const double *a, double &out) {
+  double r = 0.0;
+  TRY(lsqr_norm(c, n, a, r));
+  out = r * r;
+  return TEM_OK;
+}
+
+// misfit ||W_d (d - d_obs)||^2 and roughness ||R (m - m_ref)||^2 (device
+// inputs; work buffers inv_t1 (nd), inv_t2 (P), inv_t3 (n_reg))
+static tem_status objective_parts(tem_ctx *c, const double *d, const double *d_obs,
+                                  const double *wd, const double *m, const double *m_ref,
+                                  double &mis, double &reg) {
+  hipStream_t st = c->stream;
+  const int64_t nd = (int64_t)c->S * c->K * c->R;
+  const int P = (int)c->params.size();
+  double *t1 = c->inv_t1.as<double>(), *t2 = c->inv_t2.as<double>(), *t3 = c->inv_t3.as<double>();
+  HIPCHK(launch_raxpby(st, nd, 1.0, d, nullptr, 0.0, t1), "d");
+  HIPCHK(launch_raxpby(st, nd, -1.0, d_obs, nullptr, 1.0, t1), "d - d_obs");
+  HIPCHK(launch_raxpby(st, nd, 1.0, t1, wd, 0.0, t1), "W_d (d - d_obs)");
+  TRY(sq_norm(c, nd, t1, mis));
+  HIPCHK(launch_raxpby(st, P, 1.0, m, nullptr, 0.0, t2), "m");
+  HIPCHK(launch_raxpby(st, P, -1.0, m_ref, nullptr, 1.0, t2), "m - m_ref");
+  HIPCHK(launch_reg(st, c->n_reg, c->d_reg_lo.as<int32_t>(), c->d_reg_hi.as<int32_t>(), 1.0, t2,
+                    0.0, t3),
+         "R (m - m_ref)");
+  TRY(sq_norm(c, c->n_reg, t3, reg));
+  return TEM_OK;
+}
+
+// the forward map at the context's current model: factor every pole (the
+// poles and precision of the last factorisation), solve for the sources of
+// the last tem_forward (kept in the new ordering) and assemble the data
+// into d; fac_s receives the factorisation's wall time
+static tem_status forward_current(tem_ctx *c, const tem_ir_opts *ir, double *d, double &fac_s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> xi = c->xi;
+  TRY(tem_factor_poles(c, c->npole, xi.data(), c->prec, nullptr));
+  fac_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const int64_t N = N_of(c);
+  const int S = c->S;
+  TRY(ensure_vec(c, c->d_g, sizeof(cpx<double>) * (size_t)c->npole * N * S, "alloc g"));
+  IrResult res;
+  TRY(refine_solve(c, c->d_fnew.as<double>(), nullptr, S, c->d_g.as<cpx<double>>(), ir, res));
+  spans_collect(c);
+  c->last_solves = res.solves;
+  if (res.unconverged) return fail(c, TEM_ENOCONV, "refinement did not converge in a forward solve");
+  c->solved = true;
+  HIPCHK(launch_time_assembly(c->stream, S, c->K, c->R, c->npole, N, S, c->d_qptr.as<int64_t>(),
+                              c->d_qcol.as<int32_t>(), c->d_qval.as<double>(),
+                              c->d_alpha.as<cpx<double>>(), c->d_g.as<cpx<double>>(), d),
+         "time assembly");
+  HIPCHK(hipStreamSynchronize(c->stream), "forward sync");
+  return TEM_OK;
+}
+
+// next trial step length after a failed trial at eta: the minimiser of the
+// quadratic through phi(0), phi'(0) = slope and phi(eta), kept in
+// [eta/10, eta/2] (eta/2 when that quadratic is not convex)
+static double next_trial(double phi0, double slope, double eta, double phi_eta) {
+  const double cq = (phi_eta - phi0 - slope * eta) / (eta * eta);
+  if (!(cq > 0.0)) return 0.5 * eta;
+  const double s = -slope / (2.0 * cq);
+  return std::min(std::max(s, 0.1 * eta), 0.5 * eta);
+}
+
+tem_status tem_invert(tem_ctx *c, const double *d_obs, const double *wd, double *m,
+                      const double *m_ref, const tem_invert_opts *opts, const tem_ir_opts *ir,
+                      tem_invert_record *log, int32_t *n_records) {
+  if (!c) return TEM_EINVAL;
+  if (n_records) *n_records = 0;
+  if (c->B > 0) return fail(c, TEM_ESTATE, "tem_invert: not available on a batch of meshes");
+  if (!c->surveyed || !c->solved) return fail(c, TEM_ESTATE, "tem_invert: call tem_forward first");
+  if (c->params.empty()) return fail(c, TEM_EINVAL, "tem_invert: no model parameters");
+  if (!d_obs || !wd || !m || !m_ref || !opts || !log)
+    return fail(c, TEM_EINVAL, "tem_invert: NULL argument");
+  const double lam0 = opts->lambda0;
+  const double chi2_target = opts->chi2_target > 0 ? opts->chi2_target : 1.0;
+  const double c1 = opts->c1 > 0 ? opts->c1 : 1e-4;
+  const double eta_min = opts->eta_min > 0 ? opts->eta_min : 1.0 / 32.0;
+  const double conv_rtol = opts->conv_rtol > 0 ? opts->conv_rtol : 1e-2;
+  if (!(lam0 > 0) || !std::isfinite(lam0) || opts->max_gn <= 0 || opts->lsqr_iters <= 0 ||
+      !(eta_min < 1.0) || !(c1 < 1.0))
+    return fail(c, TEM_EINVAL, "tem_invert: need lambda0 > 0, max_gn >= 1, lsqr_iters >= 1, "
+                               "c1 < 1 and eta_min < 1");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = c->stream;
+  const int64_t nd = (int64_t)c->S * c->K * c->R;
+  const int P = (int)c->params.size();
+  TRY(ensure_vec(c, c->inv_d, sizeof(double) * nd, "alloc inversion"));
+  TRY(ensure_vec(c, c->inv_dt, sizeof(double) * nd, "alloc inversion"));
+  TRY(ensure_vec(c, c->inv_mt, sizeof(double) * P, "alloc inversion"));
+  TRY(ensure_vec(c, c->inv_dm, sizeof(double) * P, "alloc inversion"));
+  TRY(ensure_vec(c, c->inv_t1, sizeof(double) * nd, "alloc inversion"));
+  TRY(ensure_vec(c, c->inv_t2, sizeof(double) * P, "alloc inversion"));
+  TRY(ensure_vec(c, c->inv_t3, sizeof(double) * std::max<int64_t>(c->n_reg, 1), "alloc inversion"));
+  // LSQR's reduction buffers, sized as gn_lsqr sizes them
+  TRY(ensure_vec(c, c->l_part, sizeof(double) * 64 * std::max(opts->lsqr_iters + 1, 4),
+                 "alloc inversion"));
+  TRY(ensure_vec(c, c->l_scal, sizeof(double) * (opts->lsqr_iters + 1), "alloc inversion"));
+  double *d = c->inv_d.as<double>(), *dt = c->inv_dt.as<double>();
+  double *mt = c->inv_mt.as<double>(), *dm = c->inv_dm.as<double>();
+  // the data at m: the time assembly of the cached solutions
+  HIPCHK(launch_time_assembly(st, c->S, c->K, c->R, c->npole, N_of(c), c->S,
+                              c->d_qptr.as<int64_t>(), c->d_qcol.as<int32_t>(),
+                              c->d_qval.as<double>(), c->d_alpha.as<cpx<double>>(),
+                              c->d_g.as<cpx<double>>(), d),
+         "d(m0)");
+  double lam = lam0;
+  int nrec = 0;
+  for (int it = 0; it < opts->max_gn; ++it) {
+    const auto t0 = std::chrono::steady_clock::now();
+    double fac_s = 0.0;
+    tem_invert_record rec{};
+    double mis, reg;
+    TRY(objective_parts(c, d, d_obs, wd, m, m_ref, mis, reg));
+    const double phi = mis + lam * reg;
+    rec.lambda = lam;
+    rec.chi2 = mis / (double)nd;
+    rec.phi = phi;
+    if (rec.chi2 <= chi2_target) {
+      rec.stop = 1;
+      log[nrec++] = rec;
+      break;
+    }
+    double slope = 0.0;
+    TRY(gn_lsqr(c, d_obs, wd, m, m_ref, lam, opts->lsqr_iters, dm, nullptr, ir, &slope));
+    rec.slope = slope;
+    rec.lsqr_iters = opts->lsqr_iters;
+    double eta = 1.0, phit = phi;
+    bool ok = false;
+    for (;;) {
+      HIPCHK(launch_raxpby(st, P, 1.0, m, nullptr, 0.0, mt), "m_t = m");
+      HIPCHK(launch_raxpby(st, P, eta, dm, nullptr, 1.0, mt), "m_t += eta dm");
+      TRY(tem_set_model(c, mt));
+      TRY(forward_current(c, ir, dt, fac_s));
+      double mis_t, reg_t;
+      TRY(objective_parts(c, dt, d_obs, wd, mt, m_ref, mis_t, reg_t));
+      phit = mis_t + lam * reg_t;
+      rec.trials++;
+      if (phit <= phi + c1 * eta * slope) {
+        ok = true;
+        break;
+      }
+      const double nxt = next_trial(phi, slope, eta, phit);
+      if (nxt < eta_min) break;
+      eta = nxt;
+    }
+    rec.accepted = ok ? 1 : 0;
+    rec.eta = eta;
+    rec.phi_new = ok ? phit : phi;
+    if (ok) {
+      // the context is factored and solved at m_t already
+      HIPCHK(hipMemcpyAsync(m, mt, sizeof(double) * P, hipMemcpyDeviceToDevice, st), "m = m_t");
+      HIPCHK(hipMemcpyAsync(d, dt, sizeof(double) * nd, hipMemcpyDeviceToDevice, st), "d = d_t");
+      if (phi - phit < conv_rtol * phi) lam *= 0.5;
+    } else {
+      // back to m: its factors and solutions are needed by the next step
+      TRY(tem_set_model(c, m));
+      TRY(forward_current(c, ir, d, fac_s));
+      lam *= 0.5;
+    }
+    HIPCHK(hipStreamSynchronize(st), "inversion sync");
+    rec.factor_seconds = fac_s;
+    rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    log[nrec++] = rec;
+  }
+  if (n_records) *n_records = nrec;
   return TEM_OK;
 }
 
@@ -2526,6 +2803,7 @@ tem_status tem_forward_batch(tem_ctx *c, const int32_t *S, const double *F, cons
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
   hipStream_t st = c->stream;
   const int64_t N = N_of(c);
+  c->surveyed = false;
   // receivers in merged numbering, residues [mesh][K][MP] (0 for absent poles)
   std::vector<int64_t> qp(1, 0), qrow(B + 1, 0);
   std::vector<int32_t> qc;
@@ -2597,6 +2875,10 @@ tem_status tem_forward_batch(tem_ctx *c, const int32_t *S, const double *F, cons
   spans_collect(c);
   c->last_solves = res.solves;
   c->S = Smax;
+  c->K = K;
+  c->S_mesh.assign(S, S + B);
+  c->R_mesh.assign(R, R + B);
+  c->q_row_off = qrow;
   int64_t dof = 0;
   for (int b = 0; b < B; ++b) {
     HIPCHK(launch_time_assembly(st, S[b], K, R[b], MP, N, Smax, c->d_qptr.as<int64_t>() + qrow[b],
@@ -2609,6 +2891,7 @@ tem_status tem_forward_batch(tem_ctx *c, const int32_t *S, const double *F, cons
   HIPCHK(hipStreamSynchronize(st), "forward sync");
   fill_stats(res, stats);
   c->solved = true;
+  c->surveyed = true;
   if (res.unconverged) {
     double worst = 0;
     for (double v : res.rel) worst = std::max(worst, v);
@@ -2618,6 +2901,138 @@ tem_status tem_forward_batch(tem_ctx *c, const int32_t *S, const double *F, cons
                   res.unconverged, worst, res.solves);
     return fail(c, TEM_ENOCONV, buf);
   }
+  return TEM_OK;
+}
+
+tem_status tem_set_params_batch(tem_ctx *c, const int32_t *n_params, const int32_t *param_cells) {
+  if (!c) return TEM_EINVAL;
+  if (c->B == 0) return fail(c, TEM_ESTATE, "tem_set_params_batch: no batch assembled");
+  if (!n_params || !param_cells) return fail(c, TEM_EINVAL, "tem_set_params_batch: NULL argument");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  std::vector<int64_t> off(c->B + 1, 0);
+  for (int b = 0; b < c->B; ++b) {
+    const int64_t nc = c->sub[b]->mt.n_cells;
+    if (n_params[b] < 0 || n_params[b] > nc)
+      return fail(c, TEM_EINVAL, "tem_set_params_batch: parameter count out of range");
+    std::vector<char> seen(nc, 0);
+    for (int p = 0; p < n_params[b]; ++p) {
+      const int32_t cell = param_cells[off[b] + p];
+      if (cell < 0 || cell >= nc || seen[cell])
+        return fail(c, TEM_EINVAL, "tem_set_params_batch: cell ids must be distinct and in range");
+      seen[cell] = 1;
+    }
+    off[b + 1] = off[b] + n_params[b];
+  }
+  for (int b = 0; b < c->B; ++b) {
+    tem_ctx *sb = c->sub[b];
+    sb->params.assign(param_cells + off[b], param_cells + off[b + 1]);
+    HIPCHK(upload(sb->d_params, sb->params, c->stream), "upload params");
+  }
+  c->param_off = off;
+  return TEM_OK;
+}
+
+static tem_status batch_jac_check(tem_ctx *c, const char *who, const void *a, const void *b) {
+  if (c->B == 0) return fail(c, TEM_ESTATE, std::string(who) + ": no batch assembled");
+  if (!c->surveyed || !c->solved)
+    return fail(c, TEM_ESTATE, std::string(who) + ": call tem_forward_batch first");
+  if ((int)c->param_off.size() != c->B + 1 || c->param_off[c->B] == 0)
+    return fail(c, TEM_ESTATE, std::string(who) + ": call tem_set_params_batch first");
+  if (!a || !b) return fail(c, TEM_EINVAL, std::string(who) + ": NULL argument");
+  return TEM_OK;
+}
+
+tem_status tem_jvp_batch(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *ir,
+                         tem_ir_stats *stats) {
+  if (!c) return TEM_EINVAL;
+  TRY(batch_jac_check(c, "tem_jvp_batch", v, jv));
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c);
+  const int MP = c->MP, Sm = c->S, B = c->B;
+  const int64_t pst = N * Sm;
+  int64_t ncell = 1;
+  for (int b = 0; b < B; ++b) ncell = std::max<int64_t>(ncell, c->sub[b]->mt.n_cells);
+  TRY(ensure_vec(c, c->v_vs, sizeof(double) * (size_t)ncell, "alloc vs"));
+  TRY(ensure_vec(c, c->v_rhs, sizeof(cpx<double>) * (size_t)MP * N * Sm, "alloc rhs"));
+  TRY(ensure_vec(c, c->v_lam, sizeof(cpx<double>) * (size_t)MP * N * Sm, "alloc sol"));
+  cpx<double> *rhs = c->v_rhs.as<cpx<double>>(), *lam = c->v_lam.as<cpx<double>>();
+  const cpx<double> *g = c->d_g.as<cpx<double>>();
+  HIPCHK(launch_fill_f64(st, (double *)rhs, 2 * (int64_t)MP * N * Sm, 0.0), "zero rhs");
+  for (int b = 0; b < B; ++b) {
+    const tem_ctx *sb = c->sub[b];
+    const int64_t r0 = c->row_off[b] * Sm;
+    HIPCHK(launch_param_scatter(st, (int)sb->params.size(), sb->d_params.as<int32_t>(),
+                                v + c->param_off[b], sb->d_sigma.as<double>(), sb->mt.n_cells,
+                                c->v_vs.as<double>()),
+           "param scatter");
+    HIPCHK(launch_jv_rhs(st, sb->ed.N, c->np_mesh[b], c->S_mesh[b], Sm, pst, sb->mt.nx, sb->mt.ny,
+                         sb->mt.nz, sb->ed.d_row_ent.as<int32_t>(), sb->d_cell_new.as<int32_t>(),
+                         c->v_vs.as<double>(), sb->d_Me.as<double>(),
+                         c->d_xi.as<double>() + 2 * (size_t)b * MP, g + r0, rhs + r0),
+           "jv rhs");
+  }
+  IrResult res;
+  TRY(refine_solve(c, nullptr, rhs, Sm, lam, ir, res));
+  int64_t dof = 0;
+  for (int b = 0; b < B; ++b) {
+    HIPCHK(launch_time_assembly(st, c->S_mesh[b], c->K, c->R_mesh[b], MP, N, Sm,
+                                c->d_qptr.as<int64_t>() + c->q_row_off[b], c->d_qcol.as<int32_t>(),
+                                c->d_qval.as<double>(),
+                                c->d_alpha.as<cpx<double>>() + (size_t)b * c->K * MP, lam,
+                                jv + dof),
+           "jv time assembly");
+    dof += (int64_t)c->S_mesh[b] * c->K * c->R_mesh[b];
+  }
+  HIPCHK(hipStreamSynchronize(st), "jvp sync");
+  spans_collect(c);
+  fill_stats(res, stats);
+  c->last_solves = res.solves;
+  if (res.unconverged) return fail(c, TEM_ENOCONV, "tem_jvp_batch: refinement did not converge");
+  return TEM_OK;
+}
+
+tem_status tem_vjp_batch(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *ir,
+                         tem_ir_stats *stats) {
+  if (!c) return TEM_EINVAL;
+  TRY(batch_jac_check(c, "tem_vjp_batch", w, jtw));
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = c->stream;
+  const int64_t N = N_of(c);
+  const int MP = c->MP, Sm = c->S, B = c->B;
+  const int64_t pst = N * Sm;
+  TRY(ensure_vec(c, c->v_rhs, sizeof(cpx<double>) * (size_t)MP * N * Sm, "alloc rhs"));
+  TRY(ensure_vec(c, c->v_lam, sizeof(cpx<double>) * (size_t)MP * N * Sm, "alloc sol"));
+  cpx<double> *rhs = c->v_rhs.as<cpx<double>>(), *lam = c->v_lam.as<cpx<double>>();
+  const cpx<double> *g = c->d_g.as<cpx<double>>();
+  HIPCHK(launch_fill_f64(st, (double *)rhs, 2 * (int64_t)MP * N * Sm, 0.0), "zero rhs");
+  int64_t dof = 0;
+  for (int b = 0; b < B; ++b) {
+    // receivers are in merged rows: the whole vector is the base
+    HIPCHK(launch_jtw_rhs(st, c->S_mesh[b], Sm, pst, c->K, c->R_mesh[b], MP,
+                          c->d_qptr.as<int64_t>() + c->q_row_off[b], c->d_qcol.as<int32_t>(),
+                          c->d_qval.as<double>(),
+                          c->d_alpha.as<cpx<double>>() + (size_t)b * c->K * MP, w + dof, rhs),
+           "jtw rhs");
+    dof += (int64_t)c->S_mesh[b] * c->K * c->R_mesh[b];
+  }
+  IrResult res;
+  TRY(refine_solve(c, nullptr, rhs, Sm, lam, ir, res));
+  for (int b = 0; b < B; ++b) {
+    const tem_ctx *sb = c->sub[b];
+    const int64_t r0 = c->row_off[b] * Sm;
+    HIPCHK(launch_jtw_reduce(st, (int)sb->params.size(), c->np_mesh[b], c->S_mesh[b], Sm, pst,
+                             sb->d_params.as<int32_t>(), sb->d_cell_new.as<int32_t>(),
+                             sb->d_sigma.as<double>(), sb->d_Me.as<double>(),
+                             c->d_xi.as<double>() + 2 * (size_t)b * MP, g + r0, lam + r0,
+                             jtw + c->param_off[b]),
+           "jtw reduce");
+  }
+  HIPCHK(hipStreamSynchronize(st), "vjp sync");
+  spans_collect(c);
+  fill_stats(res, stats);
+  c->last_solves = res.solves;
+  if (res.unconverged) return fail(c, TEM_ENOCONV, "tem_vjp_batch: refinement did not converge");
   return TEM_OK;
 }
 

@@ -184,6 +184,21 @@ hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const in
                            const double *xi, Seg row_seg, const double *f_real,
                            const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r);
 
+// Row blocks of the FP64 residual (launch_residual_blk): at most RB_ROWS
+// consecutive rows per block whose columns span at most RB_HALO distinct
+// rows (the block's halo), rows of at most RB_NNZ entries; right-hand sides
+// are staged RB_SC at a time.
+constexpr int RB_ROWS = 64, RB_HALO = 512, RB_NNZ = 33, RB_SC = 8;
+// r = f - (K - xi_p M) x (x != NULL) by row blocks: block b holds rows
+// [rb_row[b], rb_row[b+1]) and halo rows rb_h[rb_hoff[b] .. rb_hoff[b+1]);
+// lcol[t] is the position of col[t] in its block's halo.  Same layouts and
+// results (up to rounding) as launch_residual; S <= 16.
+hipError_t launch_residual_blk(hipStream_t st, int64_t N, int npole, int S, int64_t nblk,
+                               const int64_t *rb_row, const int64_t *rb_hoff, const int32_t *rb_h,
+                               const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
+                               const double *Mv, const double *xi, Seg sg, const double *f_real,
+                               const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r);
+
 // Batched complex dot products over N rows for all (pole, s):
 // out[p*S+s] = sum_row conj(a) * b (conj_a) or sum a*b.  Deterministic.
 // Pole p's rows start at a + p * pstride (pstride = N * S for whole
@@ -236,12 +251,16 @@ hipError_t launch_time_assembly(hipStream_t st, int S, int K, int R, int npole, 
                                 const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
                                 const cpx<double> *alpha, const cpx<double> *g, double *d);
 
+// Vectors of the Jacobian kernels are [pole][row][ldS] complex with pole
+// stride pstride (elements); S <= ldS right-hand sides are used (a mesh of a
+// batch: its rows and sources inside the merged vectors).
+//
 // Jv right-hand sides: rhs[p][e][s] = xi_p sum_{cells c of e} vs[c] (Me1 g_p|_c)[local]
-// with vs[c] = v_param * sigma_c (0 for non-parameter cells).
-hipError_t launch_jv_rhs(hipStream_t st, int64_t N, int npole, int S, int nx, int ny, int nz,
-                         const int32_t *row_edge, const int32_t *cell_new, const double *vs,
-                         const double *Me, const double *xi, const cpx<double> *g,
-                         cpx<double> *rhs);
+// with vs[c] = v_param * sigma_c (0 for non-parameter cells); N rows.
+hipError_t launch_jv_rhs(hipStream_t st, int64_t N, int npole, int S, int ldS, int64_t pstride,
+                         int nx, int ny, int nz, const int32_t *row_edge, const int32_t *cell_new,
+                         const double *vs, const double *Me, const double *xi,
+                         const cpx<double> *g, cpx<double> *rhs);
 
 // sigma[params[p]] = exp(m[p])
 hipError_t launch_set_sigma_exp(hipStream_t st, int P, const int32_t *params, const double *m,
@@ -250,13 +269,15 @@ hipError_t launch_set_sigma_exp(hipStream_t st, int P, const int32_t *params, co
 hipError_t launch_param_scatter(hipStream_t st, int P, const int32_t *params, const double *v,
                                 const double *sigma, int64_t n_cells, double *vs);
 
-// J^T w right-hand sides: rhs[p][e][s] = sum_r Q[r][e] sum_j alpha[j][p] w[s][j][r]
-hipError_t launch_jtw_rhs(hipStream_t st, int S, int K, int R, int npole, int64_t N,
-                          const int64_t *q_ptr, const int32_t *q_col, const double *q_val,
-                          const cpx<double> *alpha, const double *w, cpx<double> *rhs);
+// J^T w right-hand sides: rhs[p][e][s] += sum_r Q[r][e] sum_j alpha[j][p] w[s][j][r]
+// (rhs zeroed by the caller; alpha is [K][npole])
+hipError_t launch_jtw_rhs(hipStream_t st, int S, int ldS, int64_t pstride, int K, int R,
+                          int npole, const int64_t *q_ptr, const int32_t *q_col,
+                          const double *q_val, const cpx<double> *alpha, const double *w,
+                          cpx<double> *rhs);
 
 // (J^T w)_p = 2 Re sum_{i,s} xi_i sigma_c g_is|_c^T Me1 lam_is|_c, c = params[p]
-hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int64_t N,
+hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int ldS, int64_t pstride,
                              const int32_t *params, const int32_t *cell_new, const double *sigma,
                              const double *Me, const double *xi, const cpx<double> *g,
                              const cpx<double> *lam, double *out);

@@ -25,7 +25,8 @@ EXPORTS = ["tem_create", "tem_destroy", "tem_last_error", "tem_assemble", "tem_s
            "tem_export_operators", "tem_analyse", "tem_symbolic_host", "tem_factor_poles",
            "tem_solve_poles", "tem_forward", "tem_jvp", "tem_vjp", "tem_get_stats",
            "tem_set_profiling", "tem_gn_step", "tem_assemble_batch", "tem_factor_poles_batch",
-           "tem_forward_batch", "tem_autotune", "tem_autotune_level", "tem_vjp_noalloc"]
+           "tem_forward_batch", "tem_autotune", "tem_autotune_level", "tem_vjp_noalloc",
+           "tem_invert", "tem_set_params_batch", "tem_jvp_batch", "tem_vjp_batch"]
 
 
 class TemError(RuntimeError):
@@ -62,6 +63,20 @@ class AutotuneReport(C.Structure):
     _fields_ = [("n_candidates", C.c_int32), ("n_levels", C.c_int32),
                 ("candidate_ms", C.c_double * 8), ("candidate_tile", C.c_int32 * 8),
                 ("candidate_m3", C.c_int32 * 8), ("tuned_ms", C.c_double)]
+
+
+class InvertOpts(C.Structure):
+    _fields_ = [("lambda0", C.c_double), ("chi2_target", C.c_double), ("c1", C.c_double),
+                ("eta_min", C.c_double), ("conv_rtol", C.c_double), ("max_gn", C.c_int32),
+                ("lsqr_iters", C.c_int32)]
+
+
+class InvertRecord(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("chi2", C.c_double), ("phi", C.c_double),
+                ("slope", C.c_double), ("eta", C.c_double), ("phi_new", C.c_double),
+                ("seconds", C.c_double), ("factor_seconds", C.c_double),
+                ("accepted", C.c_int32), ("trials", C.c_int32), ("lsqr_iters", C.c_int32),
+                ("stop", C.c_int32)]
 
 
 class IrOpts(C.Structure):
@@ -118,11 +133,16 @@ def load_library(path: str = LIB_PATH):
         "tem_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
         "tem_set_profiling": ([vp, i32], C.c_int),
         "tem_gn_step": ([vp, dp, dp, dp, dp, C.c_double, i32, dp, vp, C.POINTER(IrOpts)], C.c_int),
+        "tem_invert": ([vp, dp, dp, dp, dp, C.POINTER(InvertOpts), C.POINTER(IrOpts), vp,
+                        C.POINTER(C.c_int32)], C.c_int),
         "tem_assemble_batch": ([vp, i32, vp, dp], C.c_int),
         "tem_autotune": ([vp, i32, vp, C.c_int, C.POINTER(AutotuneReport)], C.c_int),
         "tem_autotune_level": ([vp, C.c_int, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
                                C.c_int),
         "tem_factor_poles_batch": ([vp, vp, vp, C.c_int, C.POINTER(FactorOpts)], C.c_int),
+        "tem_set_params_batch": ([vp, vp, vp], C.c_int),
+        "tem_jvp_batch": ([vp, dp, dp, C.POINTER(IrOpts), C.POINTER(IrStats)], C.c_int),
+        "tem_vjp_batch": ([vp, dp, dp, C.POINTER(IrOpts), C.POINTER(IrStats)], C.c_int),
         "tem_forward_batch": ([vp, vp, dp, vp, vp, vp, vp, i32, vp, C.POINTER(IrOpts), dp,
                                C.POINTER(IrStats)], C.c_int),
     }
@@ -330,6 +350,28 @@ class Tem:
                                      hist.ctypes.data_as(C.c_void_p), self._ir(ir)))
         return hist
 
+    def invert(self, d_obs, wd, m, m_ref, lambda0, max_gn, lsqr_iters, chi2_target=0.0,
+               c1=0.0, eta_min=0.0, conv_rtol=0.0, ir=None):
+        """Gauss-Newton inversion from the model of the last forward (tem_invert);
+        m (P,) float64 on the GPU is updated in place.  Returns one dict per
+        iteration."""
+        shp = self._dshape()
+        opts = InvertOpts(float(lambda0), float(chi2_target), float(c1), float(eta_min),
+                          float(conv_rtol), int(max_gn), int(lsqr_iters))
+        recs = (InvertRecord * int(max_gn))()
+        n = C.c_int32(0)
+        self._chk(self.L.tem_invert(self.h, _dev(d_obs, "float64", shp), _dev(wd, "float64", shp),
+                                    _dev(m, "float64", (self.n_params,)),
+                                    _dev(m_ref, "float64", (self.n_params,)), C.byref(opts),
+                                    self._ir(ir), C.cast(recs, C.c_void_p), C.byref(n)))
+        out = []
+        for r in recs[:n.value]:
+            d = {f: getattr(r, f) for f, _ in r._fields_}
+            d["lam"] = d.pop("lambda_")
+            d["accepted"] = bool(d["accepted"])
+            out.append(d)
+        return out
+
     def autotune(self, xi, precision=FP32_IR):
         """Time the front-update variants level by level and keep the fastest
         per level (tem_autotune).  Returns the report and the per-level choice."""
@@ -394,8 +436,34 @@ class Tem:
         st = self.L.tem_forward_batch(self.h, sp, _dev(F, "float64", (nf,)), rp, qpp, qcp, qvp, K,
                                       alp, self._ir(ir), _dev(d, "float64", (nd,)), C.byref(s))
         self._chk(st, (TEM_ENOCONV,) if allow_noconv else ())
+        self._bsurvey = dict(nd=nd, nsys=B * MP * Smax, shape=(B, MP, Smax))
         return dict(iters=it.reshape(B, MP, Smax), rel=rr.reshape(B, MP, Smax),
                     n_unconverged=s.n_unconverged, status=st)
+
+    def set_params_batch(self, params_list):
+        """params_list: one array of parameter cell ids per mesh of the batch."""
+        n, npp = _host([len(p) for p in params_list], np.int32)
+        cells, cp = _host(np.concatenate([np.asarray(p, np.int32) for p in params_list]),
+                          np.int32)
+        self._chk(self.L.tem_set_params_batch(self.h, npp, cp))
+        self.batch_params = [len(p) for p in params_list]
+
+    def jvp_batch(self, v, jv, ir=None):
+        """v: float64 GPU tensor of all meshes' parameters; jv: like forward_batch's d."""
+        P = sum(self.batch_params)
+        s, it, rr = self._stats_struct(self._bsurvey["nsys"])
+        self._chk(self.L.tem_jvp_batch(self.h, _dev(v, "float64", (P,)),
+                                       _dev(jv, "float64", (self._bsurvey["nd"],)), self._ir(ir),
+                                       C.byref(s)))
+        return dict(iters=it.reshape(self._bsurvey["shape"]))
+
+    def vjp_batch(self, w, jtw, ir=None):
+        """w: like forward_batch's d; jtw: float64 GPU tensor of all meshes' parameters."""
+        P = sum(self.batch_params)
+        s, it, rr = self._stats_struct(self._bsurvey["nsys"])
+        self._chk(self.L.tem_vjp_batch(self.h, _dev(w, "float64", (self._bsurvey["nd"],)),
+                                       _dev(jtw, "float64", (P,)), self._ir(ir), C.byref(s)))
+        return dict(iters=it.reshape(self._bsurvey["shape"]))
 
     def set_profiling(self, enable=True):
         self._chk(self.L.tem_set_profiling(self.h, 1 if enable else 0))

@@ -412,6 +412,36 @@ def workload(index: int) -> Workload:
     raise ValueError(index)
 
 
+def four_block_workload(n=32, h=5.0, n_air=8, m=21, K=31, seed=6, poles=None):
+    """Uniform-hex analogue of the paper's inversion example (section
+    "Synthetic examples"): a 0.1 S/m half-space under n_air air layers with
+    two conductive (1 S/m) and two resistive (0.01 S/m) blocks of 5 x 5 x 1
+    cells (25 x 25 x 5 m at h = 5 m) whose tops lie 2 cells (10 m) below the
+    surface, at the four corners of a square around the centre; one square
+    loop of 8 x 8 cells (40 m) centred on the surface; a 7 x 7 grid of
+    dB_z/dt receivers with 3-cell (15 m) spacing around the centre; K times
+    log-spaced in [1e-6, 1e-3] s; m poles (the contour table unless ``poles``
+    (a PoleTable) is given).  Parameters are all earth cells.  The paper's
+    receiver grid is stated both as 7 x 7 with 15 m spacing and as spanning
+    -60..60 m (which 7 stations at 15 m do not reach); the spacing is kept.
+    The noise draws (for the observed data) come from the seeded stream."""
+    mesh = Mesh(n, n, n, h, n_air)
+    s = np.full((mesh.nz, mesh.ny, mesh.nx), SIGMA_AIR)
+    s[:mesh.k_if] = 0.1
+    c = n // 2
+    k = mesh.k_if - 3                     # one layer, its top 2 cells below the interface
+    for (i0, j0), val in (((c - 7, c - 7), 1.0), ((c + 2, c + 2), 1.0),
+                          ((c + 2, c - 7), 0.01), ((c - 7, c + 2), 0.01)):
+        s[k, j0:j0 + 5, i0:i0 + 5] = val
+    F = source_matrix(mesh, [(c, c)], half=4)
+    faces = [(c + 3 * (a - 3) - 1, c + 3 * (b - 3) - 1) for b in range(7) for a in range(7)]
+    rx = bz_receivers_at(mesh, faces)
+    pt = poles if poles is not None else pole_table(m, 1e-6, 1e-3, K)
+    wl = Workload("hex%d_four_blocks" % n, mesh, s.reshape(-1), F, rx, pt, earth_cells(mesh))
+    wl.extra["rng_noise"] = _streams(seed)[3]
+    return wl
+
+
 def inversion_inputs(wl: Workload, eps_r=0.03, eps_a=1e-9, n_dirs=32):
     """Inputs of one Gauss-Newton step: true model ln(sigma) on earth cells,
     starting/reference model ln(0.01), regularisation weight 1, unit-normal

@@ -140,3 +140,74 @@ def test_gauss_newton_step_matches_oracle(prec):
     assert torch.count_nonzero(dm).item() == 0
     assert np.array_equal(hist0, np.zeros(iters))
     t.close()
+
+
+@pytest.mark.parametrize("prec,lam0,conv,max_gn", [(0, 1.0, 0.0, 3), (1, 1.0, 0.0, 3),
+                                                    (0, 3e4, 0.1, 4), (1, 3e4, 0.1, 4)])
+def test_inversion_loop_matches_oracle(prec, lam0, conv, max_gn):
+    """Gauss-Newton iterations with the backtracking line search and lambda
+    cooling (tem_invert) against the oracle's loop on a 10^3 problem (one
+    loop, 4 x 4 receivers, 6 times, 5 poles).  With lambda0 = 1 the second
+    iteration backtracks (the quadratic model picks eta ~ 0.39); with
+    lambda0 = 3e4 and conv_rtol = 0.1 the third iteration's small decrease
+    halves lambda.  The decisions (accepted, trials, stop, lambda) must be
+    equal, chi^2, phi, the slope and eta agree to 1e-6, and so does the
+    final model."""
+    from oracle.inversion import Problem, invert
+    torch, wl, t, prob, dev = _setup(prec, n=10, S=1, m=5, K=6, g=4, seed=41)
+    me = wl.mesh
+    o = OracleTEM(me.nx, me.ny, me.nz, me.h, wl.sigma, wl.F, wl.rx.ptr, wl.rx.col, wl.rx.val,
+                  wl.poles.xi, wl.poles.alpha, wl.params)
+    d_true = o.data().reshape(-1)
+    shape = o.data().shape
+    sd = 0.03 * np.abs(d_true) + 1e-9
+    d_obs = d_true + sd * np.random.default_rng(2).standard_normal(d_true.shape)
+
+    def fwd(m):
+        o.set_model(m)
+        return o.data().reshape(-1)
+
+    def jv(m, v):
+        o.set_model(m)
+        return o.jvp(v).reshape(-1)
+
+    def jtw(m, w):
+        o.set_model(m)
+        return o.vjp(w.reshape(shape))
+
+    R = first_difference(me.nx, me.ny, me.k_if)
+    m0 = np.full(len(wl.params), math.log(1e-2))
+    kw = dict(conv_rtol=conv) if conv > 0 else {}
+    m_fin, log_ref = invert(Problem(fwd, jv, jtw, R, d_obs, 1.0 / sd, m0), m0, lam0,
+                            max_gn=max_gn, lsqr_iters=8, **kw)
+    mt = torch.tensor(m0, device=dev)
+    t.set_model(mt)
+    t.factor_poles(wl.poles.xi, prec)
+    d = torch.zeros(shape, dtype=torch.float64, device=dev)
+    t.forward(prob.F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+    log = t.invert(torch.tensor(d_obs.reshape(shape), device=dev),
+                   torch.tensor((1.0 / sd).reshape(shape), device=dev), mt,
+                   torch.tensor(m0, device=dev), lam0, max_gn, 8, conv_rtol=conv)
+    print("invert prec=%d lam0=%g: %s" % (prec, lam0, [(r["accepted"], r["trials"], r["lam"],
+                                                        round(r["eta"], 4)) for r in log]),
+          flush=True)
+    assert len(log) == len(log_ref)
+    for r, q in zip(log, log_ref):
+        assert r["lam"] == q["lam"]
+        assert bool(r["stop"]) == ("stop" in q)
+        assert r["chi2"] == pytest.approx(q["chi2"], rel=1e-6)
+        assert r["phi"] == pytest.approx(q["phi"], rel=1e-6)
+        if "stop" in q:
+            continue
+        assert r["accepted"] == q["accepted"] and r["trials"] == q["trials"]
+        assert r["slope"] == pytest.approx(q["slope"], rel=1e-6)
+        assert r["eta"] == pytest.approx(q["eta"], rel=1e-6)
+        assert r["phi_new"] == pytest.approx(q["phi_new"], rel=1e-6)
+        assert r["seconds"] > 0 and 0 < r["factor_seconds"] <= r["seconds"]
+    if lam0 == 1.0:
+        assert any(r["trials"] > 1 for r in log)
+    else:
+        assert log[-1]["lam"] < lam0
+    mg = mt.cpu().numpy()
+    assert np.linalg.norm(mg - m_fin) <= 1e-6 * np.linalg.norm(m_fin)
+    t.close()
