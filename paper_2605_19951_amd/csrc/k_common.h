@@ -26,6 +26,31 @@ __device__ __forceinline__ cpx<T> cfma(cpx<T> a, cpx<T> b, cpx<T> acc) {
   acc.im = fma(a.im, b.re, acc.im);
   return acc;
 }
+// acc + a*b for a real a
+template <typename T>
+__device__ __forceinline__ cpx<T> rfma(T a, cpx<T> b, cpx<T> acc) {
+  acc.re = fma(a, b.re, acc.re);
+  acc.im = fma(a, b.im, acc.im);
+  return acc;
+}
+// factor entries as the register triangle kernels keep them: complex, or
+// the real part alone when the factor is real (its imaginary parts zero)
+template <typename T, bool RL>
+struct FacVal {
+  typedef cpx<T> type;
+  __device__ static type of(cpx<T> v) { return v; }
+  __device__ static cpx<T> as_cpx(type v) { return v; }
+  __device__ static type neg(type v) { return {-v.re, -v.im}; }
+  __device__ static cpx<T> fma_(type a, cpx<T> b, cpx<T> acc) { return cfma(a, b, acc); }
+};
+template <typename T>
+struct FacVal<T, true> {
+  typedef T type;
+  __device__ static type of(cpx<T> v) { return v.re; }
+  __device__ static cpx<T> as_cpx(type v) { return {v, T(0)}; }
+  __device__ static type neg(type v) { return -v; }
+  __device__ static cpx<T> fma_(type a, cpx<T> b, cpx<T> acc) { return rfma(a, b, acc); }
+};
 template <typename T>
 __device__ __forceinline__ cpx<T> cinv(cpx<T> a) {
   T den = a.re * a.re + a.im * a.im;

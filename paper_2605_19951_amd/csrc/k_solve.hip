@@ -158,13 +158,14 @@ __global__ __launch_bounds__(256) void k_fwd_tri(FrontTab ft, const int32_t *lvl
 // block, and every later row of the range subtracts its L row times Y.  SP
 // (8 or 16) columns are computed for S <= SP right-hand sides, with zero
 // factors in place of branches; barriers order LDS only.
-template <typename T, int SP>
+template <typename T, int SP, bool RL>
 __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t *lvl_nodes,
                                                      int S, int64_t N, const cpx<T> *factor,
                                                      int64_t f_stride, cpx<T> *x,
                                                      const cpx<T> *w_child, int64_t w_stride,
                                                      int64_t cb, int64_t BB) {
   constexpr int NT = NB * SP / 256;   // (row, column) tasks per thread in the block solve
+  typedef FacVal<T, RL> FV;           // RL: real factor, kept and applied as real
   const int s = lvl_nodes[blockIdx.x];
   const int p = blockIdx.y;
   if (pole_absent(ft, s, p)) return;
@@ -182,10 +183,10 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
   cpx<T> xr[SP];
 #pragma unroll
   for (int c = 0; c < SP; ++c) xr[c] = X[r * S + min(c, S - 1)];
-  __shared__ cpx<T> Lo[NB][NB + 1];
+  __shared__ typename FV::type Lo[NB][NB + 1];
   __shared__ cpx<T> V[NB][SP];
   __shared__ cpx<T> Y[NB][SP];
-  cpx<T> lv[NB], li[NB * NB / 256];
+  typename FV::type lv[NB], li[NB * NB / 256];
   // inverse block of columns [jb, jb + NB): Linv[j][l] at (row jb + l,
   // column jb + j); clamped to the last block (entries past w are zeroed)
   auto fetch_li = [&](int64_t jb) {
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
-      li[q] = Lc[(int64_t)min(j, w - 1) * ld + jb + min(l, w - 1)];
+      li[q] = FV::of(Lc[(int64_t)min(j, w - 1) * ld + jb + min(l, w - 1)]);
     }
   };
   // the owned row's entries in columns [jb, jb + NB) (rows above the block
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
     const cpx<T> *Lc = col_ptr(P, n, jb, ld);
     const int64_t rr = max(r, jb);
 #pragma unroll
-    for (int l = 0; l < NB; ++l) lv[l] = Lc[(int64_t)min(l, w - 1) * ld + rr];
+    for (int l = 0; l < NB; ++l) lv[l] = FV::of(Lc[(int64_t)min(l, w - 1) * ld + rr]);
   };
   fetch_li(cb);
   fetch_lv(cb);
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
-      Lo[j][l] = (l < j && j < w) ? li[q] : czero<T>();
+      Lo[j][l] = (l < j && j < w) ? li[q] : FV::of(czero<T>());
     }
     fetch_li(jb + NB);
     if (own && r >= jb && r < jb + w) {
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
       const int idx = tid + 256 * q, j = idx / SP, c = idx % SP;
       cpx<T> acc = V[j][c];
 #pragma unroll
-      for (int l = 0; l < NB; ++l) acc = cfma(Lo[j][l], V[l][c], acc);
+      for (int l = 0; l < NB; ++l) acc = FV::fma_(Lo[j][l], V[l][c], acc);
       Y[j][c] = acc;
       if (j < w && c < S) X[(jb + j) * S + c] = acc;
     }
@@ -244,9 +245,9 @@ __global__ __launch_bounds__(256) void k_fwd_tri_reg(FrontTab ft, const int32_t 
     if (own && r >= jb + w) {
 #pragma unroll
       for (int l = 0; l < NB; ++l) {
-        const cpx<T> a = l < w ? cpx<T>{-lv[l].re, -lv[l].im} : czero<T>();
+        const typename FV::type a = l < w ? FV::neg(lv[l]) : FV::of(czero<T>());
 #pragma unroll
-        for (int c = 0; c < SP; ++c) xr[c] = cfma(a, Y[l][c], xr[c]);
+        for (int c = 0; c < SP; ++c) xr[c] = FV::fma_(a, Y[l][c], xr[c]);
       }
     }
     fetch_lv(jb + NB);
@@ -257,15 +258,17 @@ template <typename T>
 hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
                           cpx<T> *x, const cpx<T> *w_child, int64_t w_stride, int64_t cb,
-                          int64_t BB) {
+                          int64_t BB, bool real_l) {
   if (n_nodes <= 0) return hipSuccess;
   // the column blocks of wide fronts (at most 256 rows, one per thread)
   // take the register kernel; whole small fronts, many per level, keep the
   // lighter LDS kernel
   if (S >= 1 && S <= 16 && BB <= 256 && BB % NB == 0 && cb % NB == 0)
-    hipLaunchKernelGGL((S <= 8 ? k_fwd_tri_reg<T, 8> : k_fwd_tri_reg<T, 16>), dim3(n_nodes, npole),
-                       dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride, x, w_child,
-                       w_stride, cb, BB);
+    hipLaunchKernelGGL((real_l ? (S <= 8 ? k_fwd_tri_reg<T, 8, true> : k_fwd_tri_reg<T, 16, true>)
+                               : (S <= 8 ? k_fwd_tri_reg<T, 8, false>
+                                         : k_fwd_tri_reg<T, 16, false>)),
+                       dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N, factor,
+                       f_stride, x, w_child, w_stride, cb, BB);
   else
     hipLaunchKernelGGL(k_fwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
                        factor, f_stride, x, w_child, w_stride, cb, BB);
@@ -319,12 +322,15 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
                                                        int64_t f_stride, cpx<T> *x,
                                                        const cpx<T> *w_child,
                                                        cpx<T> *w_out, int64_t w_stride,
-                                                       int64_t cb, int64_t BB) {
+                                                       int64_t cb, int64_t BB, int pf) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
   constexpr int RB = 2, KC = MF::KC;   // 16-row blocks per wave, columns per chunk
   const int s = lvl_nodes[blockIdx.y];
-  const int p = blockIdx.z;
+  // pf > 1: the pole is the fastest part of blockIdx.x (a factor shared by
+  // all poles is then read by their workgroups together, once from HBM)
+  const int p = pf > 1 ? (int)(blockIdx.x % pf) : (int)blockIdx.z;
+  const int64_t bx = pf > 1 ? (int64_t)(blockIdx.x / pf) : (int64_t)blockIdx.x;
   if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
   // output rows row0 + [0, nrows), depth columns [d0, d1)
@@ -338,7 +344,7 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t aw = (int64_t)blockIdx.x * 128 + wave * 32;   // first row of the wave
+  const int64_t aw = bx * 128 + wave * 32;   // first row of the wave
   if (aw >= nrows) return;
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
   cpx<T> *X = x + ((int64_t)p * N + first) * S;
@@ -453,21 +459,30 @@ hipError_t fwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lv
   const bool two = S > 8;
   if constexpr (sizeof(T) == 8) {
     if (real_l) {
+      // one real factor for every pole slot (f_stride == 0): interleave the
+      // poles into the fastest grid dimension
+      const int pf = f_stride == 0 ? (int)grid.z : 1;
+      if (pf > 1) {
+        grid.x *= pf;
+        grid.z = 1;
+      }
       if (two)
         hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, ROWS, true>), grid, dim3(256), 0, st, ft,
-                           lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB);
+                           lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB,
+                           pf);
       else
         hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, ROWS, true>), grid, dim3(256), 0, st, ft,
-                           lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB);
+                           lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB,
+                           pf);
       return hipGetLastError();
     }
   }
   if (two)
     hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, ROWS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB);
+                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, 1);
   else
     hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, ROWS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB);
+                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, 1);
   return hipGetLastError();
 }
 
@@ -515,14 +530,15 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
                                                        int S, int64_t N, const cpx<T> *factor,
                                                        int64_t f_stride, cpx<T> *x,
                                                        cpx<T> *t, int64_t t_stride, int64_t cb,
-                                                       int64_t BB) {
+                                                       int64_t BB, int pf) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
   const int s = lvl_nodes[blockIdx.y];
-  const int p = blockIdx.z;
+  const int p = pf > 1 ? (int)(blockIdx.x % pf) : (int)blockIdx.z;   // as in the forward kernel
+  const int64_t bx = pf > 1 ? (int64_t)(blockIdx.x / pf) : (int64_t)blockIdx.x;
   if (pole_absent(ft, s, p)) return;
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
-  const int64_t jb = (int64_t)blockIdx.x * NB;
+  const int64_t jb = bx * NB;
   // columns [jb, jb + w) take rows row0 + [0, u) of the panel
   int64_t row0 = k, ncol = k;
   if (COLS) {
@@ -651,21 +667,26 @@ hipError_t bwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lv
   const bool two = S > 8;
   if constexpr (sizeof(T) == 8) {
     if (real_l) {
+      const int pf = f_stride == 0 ? (int)grid.z : 1;   // as in fwd_mfma_go
+      if (pf > 1) {
+        grid.x *= pf;
+        grid.z = 1;
+      }
       if (two)
         hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, COLS, true>), grid, dim3(256), 0, st, ft,
-                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB);
+                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB, pf);
       else
         hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, COLS, true>), grid, dim3(256), 0, st, ft,
-                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB);
+                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB, pf);
       return hipGetLastError();
     }
   }
   if (two)
     hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, COLS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, t, t_stride, cb, BB);
+                       factor, f_stride, x, t, t_stride, cb, BB, 1);
   else
     hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, COLS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, t, t_stride, cb, BB);
+                       factor, f_stride, x, t, t_stride, cb, BB, 1);
   return hipGetLastError();
 }
 
@@ -776,13 +797,14 @@ __global__ __launch_bounds__(256) void k_bwd_tri(FrontTab ft, const int32_t *lvl
 // the range subtracts sum_l L(jb + l, r) x_b[l], from its own column's
 // entries below the block, loaded one block ahead.  SP as in the forward
 // kernel.
-template <typename T, int SP>
+template <typename T, int SP, bool RL>
 __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t *lvl_nodes,
                                                      int S, int64_t N, const cpx<T> *factor,
                                                      int64_t f_stride, cpx<T> *x,
                                                      const cpx<T> *t, int64_t t_stride,
                                                      int64_t cb, int64_t BB, int init) {
   constexpr int NT = NB * SP / 256;
+  typedef FacVal<T, RL> FV;           // RL: real factor, kept and applied as real
   const int s = lvl_nodes[blockIdx.x];
   const int p = blockIdx.y;
   if (pole_absent(ft, s, p)) return;
@@ -810,10 +832,10 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
       if (tt) v[c] = csub(v[c], Tv[id]);
     }
   }
-  __shared__ cpx<T> Lo[NB][NB + 1];   // Lo[l][j] = Linv[j][l] for l < j < w
+  __shared__ typename FV::type Lo[NB][NB + 1];   // Lo[l][j] = Linv[j][l] for l < j < w
   __shared__ cpx<T> V[NB][SP];
   __shared__ cpx<T> Y[NB][SP];
-  cpx<T> lv[NB], li[NB * NB / 256];
+  typename FV::type lv[NB], li[NB * NB / 256];
   const int64_t b_first = cb / NB, b_last = (ce + NB - 1) / NB - 1;
   auto fetch_li = [&](int64_t bi) {
     const int64_t jb = max(bi, b_first) * NB;
@@ -823,7 +845,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
-      li[q] = Lc[(int64_t)min(j, w - 1) * ld + jb + min(l, w - 1)];
+      li[q] = FV::of(Lc[(int64_t)min(j, w - 1) * ld + jb + min(l, w - 1)]);
     }
   };
   // L(jb + l, r) for the block's rows: column r below its own block (rows
@@ -832,7 +854,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
     const int64_t jb = max(bi, b_first) * NB;
     const int w = (int)min((int64_t)NB, k - jb);
 #pragma unroll
-    for (int l = 0; l < NB; ++l) lv[l] = Lr[max(jb + min(l, w - 1), r0)];
+    for (int l = 0; l < NB; ++l) lv[l] = FV::of(Lr[max(jb + min(l, w - 1), r0)]);
   };
   fetch_li(b_last);
   fetch_lv(b_last);
@@ -843,7 +865,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int idx = tid + 256 * q, j = idx % NB, l = idx / NB;
-      Lo[l][j] = (l < j && j < w) ? li[q] : czero<T>();
+      Lo[l][j] = (l < j && j < w) ? li[q] : FV::of(czero<T>());
     }
     fetch_li(bi - 1);
     if (own && r >= jb && r < jb + w) {
@@ -861,7 +883,7 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
       const int idx = tid + 256 * q, l = idx / SP, c = idx % SP;
       cpx<T> acc = V[l][c];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) acc = cfma(Lo[l][j], V[j][c], acc);
+      for (int j = 0; j < NB; ++j) acc = FV::fma_(Lo[l][j], V[j][c], acc);
       Y[l][c] = acc;
       if (l < w && c < S) X[(jb + l) * S + c] = acc;
     }
@@ -869,9 +891,9 @@ __global__ __launch_bounds__(256) void k_bwd_tri_reg(FrontTab ft, const int32_t 
     if (own && r < jb) {
 #pragma unroll
       for (int l = 0; l < NB; ++l) {
-        const cpx<T> a = l < w ? cpx<T>{-lv[l].re, -lv[l].im} : czero<T>();
+        const typename FV::type a = l < w ? FV::neg(lv[l]) : FV::of(czero<T>());
 #pragma unroll
-        for (int c = 0; c < SP; ++c) v[c] = cfma(a, Y[l][c], v[c]);
+        for (int c = 0; c < SP; ++c) v[c] = FV::fma_(a, Y[l][c], v[c]);
       }
     }
     fetch_lv(bi - 1);
@@ -882,15 +904,17 @@ template <typename T>
 hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
                           cpx<T> *x, const cpx<T> *t, int64_t t_stride, int64_t cb, int64_t BB,
-                          int init) {
+                          int init, bool real_l) {
   if (n_nodes <= 0) return hipSuccess;
   // the column blocks of wide fronts (at most 256 rows, one per thread)
   // take the register kernel; whole small fronts, many per level, keep the
   // lighter LDS kernel
   if (S >= 1 && S <= 16 && BB <= 256 && BB % NB == 0 && cb % NB == 0)
-    hipLaunchKernelGGL((S <= 8 ? k_bwd_tri_reg<T, 8> : k_bwd_tri_reg<T, 16>), dim3(n_nodes, npole),
-                       dim3(256), 0, st, ft, lvl_nodes, S, N, factor, f_stride, x, t, t_stride,
-                       cb, BB, init);
+    hipLaunchKernelGGL((real_l ? (S <= 8 ? k_bwd_tri_reg<T, 8, true> : k_bwd_tri_reg<T, 16, true>)
+                               : (S <= 8 ? k_bwd_tri_reg<T, 8, false>
+                                         : k_bwd_tri_reg<T, 16, false>)),
+                       dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N, factor,
+                       f_stride, x, t, t_stride, cb, BB, init);
   else
     hipLaunchKernelGGL(k_bwd_tri<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S, N,
                        factor, f_stride, x, t, t_stride, cb, BB, init);
@@ -944,7 +968,7 @@ hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 #define TEM_INST(T)                                                                              \
   template hipError_t launch_fwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
                                         int64_t, const cpx<T> *, int64_t, cpx<T> *,              \
-                                        const cpx<T> *, int64_t, int64_t, int64_t);              \
+                                        const cpx<T> *, int64_t, int64_t, int64_t, bool);        \
   template hipError_t launch_fwd_rows<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, cpx<T> *,        \
                                          int64_t, int64_t, bool);                                \
@@ -962,7 +986,7 @@ hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
                                          cpx<T> *, int64_t, bool);                               \
   template hipError_t launch_bwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
                                         int64_t, const cpx<T> *, int64_t, cpx<T> *,              \
-                                        const cpx<T> *, int64_t, int64_t, int64_t, int);
+                                        const cpx<T> *, int64_t, int64_t, int64_t, int, bool);
 TEM_INST(float)
 TEM_INST(double)
 #undef TEM_INST

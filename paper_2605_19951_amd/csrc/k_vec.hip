@@ -144,101 +144,96 @@ __global__ __launch_bounds__(256) void k_residual(int64_t N, int npole, int S,
 }
 
 // r = f - (K - xi_p M) x by row blocks: a workgroup owns one block of at
-// most RB_ROWS consecutive rows whose columns (its "halo", at most RB_HALO
-// distinct rows of x) are listed per block; for every pole of the launch and
-// every chunk of up to RB_SC right-hand sides it stages those x rows in LDS
-// with coalesced loads, then forms the sums from LDS.  Four consecutive
-// lanes share a row: each keeps a quarter of the row's K and M entries and
-// local column indices in registers for all poles (the matrix is read once
-// per call, each x row once per block that touches it instead of once per
-// nonzero), accumulates its quarter for every source of the chunk, and the
-// four partial sums are added across the lanes.
+// most RB_ROWS consecutive rows; the block's columns (its "halo", at most
+// RB_HALO distinct rows of x) are listed per block.  The workgroup stages
+// the block's K and M entries and their halo positions in LDS once; then it
+// walks the (pole, chunk of up to RB_SC right-hand sides) pairs of the
+// launch: the halo rows of x for the next pair are loaded into registers
+// (coalesced, the halo indices kept in registers for all pairs) while the
+// current pair's rows sit in LDS, where eight lanes per row, one right-hand
+// side each, form the row's sums (one 128-byte halo row per entry spans all
+// LDS banks; the entry itself is a broadcast).  The matrix is read once per
+// call and each x row once per block that touches it, instead of once per
+// nonzero.  The sum over a row runs in CSR order, as in k_residual.
 __global__ __launch_bounds__(256) void k_residual_blk(
     int64_t N, int npole, int S, int64_t nblk, const int64_t *rb_row, const int64_t *rb_hoff,
     const int32_t *rb_h, const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
     const double *Mv, const double *xi, Seg sg, const double *f_real, const cpx<double> *f_cplx,
     const cpx<double> *x, cpx<double> *r) {
-  constexpr int PER = (RB_NNZ + 3) / 4;   // entries per lane
+  constexpr int NS = RB_HALO * RB_SC / 256;      // halo loads per lane and pair
+  constexpr int NE = (RB_ROWS * RB_NNZ + 255) / 256;
   __shared__ cpx<double> xs[RB_HALO * RB_SC];
+  __shared__ cpx<double> km[RB_ROWS * RB_NNZ];   // (K, M) of each entry
+  __shared__ int kl[RB_ROWS * RB_NNZ];           // its halo position * RB_SC
+  __shared__ int64_t rp[RB_ROWS + 1];            // the block's row pointers
   const int64_t b = xcd_block(nblk);
   if (b >= nblk) return;   // uniform over the workgroup
   const int64_t row0 = rb_row[b];
   const int nrow = (int)(rb_row[b + 1] - row0);
   const int64_t h0 = rb_hoff[b];
   const int nh = (int)(rb_hoff[b + 1] - h0);
-  const int t = threadIdx.x, lr = t >> 2, qt = t & 3;
-  const bool has_row = lr < nrow;
-  const int64_t row = row0 + (has_row ? lr : 0);
-  double kv[PER], mv[PER];
-  int lc[PER];
-  int cnt = 0;   // entries of this lane
-  {
-    const int64_t t0 = rowptr[row];
-    const int nnz = has_row ? (int)(rowptr[row + 1] - t0) : 0;
-    cnt = min(PER, max(0, nnz - qt * PER));
+  const int t = threadIdx.x, lr = t >> 3, ls = t & (RB_SC - 1);
+  if (t <= nrow) rp[t] = rowptr[row0 + t];
+  int hidx[NS];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const bool in = j < cnt;
-      const int64_t e = t0 + qt * PER + j;
-      kv[j] = in ? Kv[e] : 0.0;
-      mv[j] = in ? Mv[e] : 0.0;
-      lc[j] = in ? (int)lcol[e] : 0;
+  for (int i = 0; i < NS; ++i) hidx[i] = rb_h[h0 + min(lr + 32 * i, nh - 1)];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int q = t + 256 * i;
+    const int rr = q / RB_NNZ, j = q - rr * RB_NNZ;
+    if (rr < nrow && rp[rr] + j < rp[rr + 1]) {
+      const int64_t e = rp[rr] + j;
+      km[q] = {Kv[e], Mv[e]};
+      kl[q] = (int)lcol[e] * RB_SC;
     }
   }
+  const bool has_row = lr < nrow;
+  const int64_t row = row0 + (has_row ? lr : 0);
+  const int nnz = has_row ? (int)(rp[lr + 1] - rp[lr]) : 0;
   const int64_t xb = 2 * (int64_t)seg_find(sg, row0) * sg.stride;
-  for (int p = 0; p < npole; ++p) {
+  const int nch = (S + RB_SC - 1) / RB_SC, npair = npole * nch;
+  cpx<double> stg[NS];
+  auto load_pair = [&](int q) {
+    const int p = q / nch, s0 = (q - p * nch) * RB_SC;
+    const int sc = min(RB_SC, S - s0);
+    const cpx<double> *X = x + (int64_t)p * N * S + s0 + min(ls, sc - 1);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) stg[i] = X[(int64_t)hidx[i] * S];
+  };
+  load_pair(0);
+  for (int q = 0; q < npair; ++q) {
+    const int p = q / nch, s0 = (q - p * nch) * RB_SC;
+    const int sc = min(RB_SC, S - s0);
+    __syncthreads();   // the previous pair's sums have read xs
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+      if (lr + 32 * i < nh) xs[(lr + 32 * i) * RB_SC + ls] = stg[i];
+    __syncthreads();
+    if (q + 1 < npair) load_pair(q + 1);   // in flight during this pair's sums
+    if (!has_row || ls >= sc) continue;
     const double xr = xi[xb + 2 * p], xim = xi[xb + 2 * p + 1];
-    const cpx<double> *X = x + (int64_t)p * N * S;
-    for (int s0 = 0; s0 < S; s0 += RB_SC) {
-      const int sc = min(RB_SC, S - s0);
-      __syncthreads();   // the previous chunk's sums have read xs
-      for (int e = t; e < nh * sc; e += 256) {
-        const int hh = e / sc, ss = e - hh * sc;
-        xs[hh * RB_SC + ss] = X[(int64_t)rb_h[h0 + hh] * S + s0 + ss];
-      }
-      __syncthreads();
-      double ar[RB_SC], ai[RB_SC];
-#pragma unroll
-      for (int ss = 0; ss < RB_SC; ++ss) ar[ss] = ai[ss] = 0.0;
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        if (j < cnt) {
-          const double sr = kv[j] - xr * mv[j], si = -xim * mv[j];
-          const cpx<double> *xv = xs + lc[j] * RB_SC;
-#pragma unroll
-          for (int ss = 0; ss < RB_SC; ++ss) {
-            if (ss < sc) {
-              const cpx<double> v = xv[ss];
-              ar[ss] += sr * v.re - si * v.im;
-              ai[ss] += sr * v.im + si * v.re;
-            }
-          }
-        }
-      }
-      // the row's four partial sums (lanes 4 lr .. 4 lr + 3)
-#pragma unroll
-      for (int ss = 0; ss < RB_SC; ++ss) {
-        ar[ss] += __shfl_xor(ar[ss], 1);
-        ai[ss] += __shfl_xor(ai[ss], 1);
-        ar[ss] += __shfl_xor(ar[ss], 2);
-        ai[ss] += __shfl_xor(ai[ss], 2);
-      }
-      if (!has_row) continue;
-#pragma unroll
-      for (int ss = 0; ss < RB_SC; ++ss) {
-        if ((ss & 3) != qt || ss >= sc) continue;
-        const int c = s0 + ss;
-        double fr = 0.0, fi = 0.0;
-        if (f_cplx) {
-          const cpx<double> f = f_cplx[((int64_t)p * N + row) * S + c];
-          fr = f.re;
-          fi = f.im;
-        } else if (f_real) {
-          fr = f_real[row * S + c];
-        }
-        r[((int64_t)p * N + row) * S + c] = {fr - ar[ss], fi - ai[ss]};
-      }
+    const cpx<double> *kmr = km + lr * RB_NNZ;
+    const int *klr = kl + lr * RB_NNZ;
+    double ar = 0.0, ai = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < nnz; ++j) {
+      const cpx<double> v = xs[klr[j] + ls];
+      const cpx<double> a = kmr[j];
+      const double sr = a.re - xr * a.im, si = -xim * a.im;
+      ar += sr * v.re - si * v.im;
+      ai += sr * v.im + si * v.re;
     }
+    const int c = s0 + ls;
+    double fr = 0.0, fi = 0.0;
+    if (f_cplx) {
+      const cpx<double> f = f_cplx[((int64_t)p * N + row) * S + c];
+      fr = f.re;
+      fi = f.im;
+    } else if (f_real) {
+      fr = f_real[row * S + c];
+    }
+    r[((int64_t)p * N + row) * S + c] = {fr - ar, fi - ai};
   }
 }
 

@@ -984,6 +984,22 @@ struct ArenaScope {
   }
 };
 
+// Allocate b; if the device is out of memory, give back the contribution-
+// block arenas that the factorisation keeps for the next one (they are idle
+// once a factorisation has finished) and try once more.
+tem_status alloc_or_reclaim(tem_ctx *c, DBuf &b, size_t bytes, const char *what) {
+  hipError_t e = b.alloc(bytes);
+  if (e == hipErrorOutOfMemory && (c->d_cb0.p || c->d_cb1.p) && !t_no_alloc) {
+    (void)hipGetLastError();   // clear the failed allocation's error
+    HIPCHK(hipStreamSynchronize(c->stream), "sync before freeing the arenas");
+    c->d_cb0.release();
+    c->d_cb1.release();
+    e = b.alloc(bytes);
+  }
+  HIPCHK(e, what);
+  return TEM_OK;
+}
+
 template <typename T>
 tem_status ensure_sweep_ws(tem_ctx *c, MF &mf, int npole, int S) {
   const size_t vec = sizeof(cpx<T>) * (size_t)npole * mf.N * S;
@@ -993,9 +1009,9 @@ tem_status ensure_sweep_ws(tem_ctx *c, MF &mf, int npole, int S) {
     TRY(arena_take(c, mf.w_w0, wb, "sweep w0"));
     return arena_take(c, mf.w_w1, wb, "sweep w1");
   }
-  if (mf.w_t.bytes < vec) HIPCHK(mf.w_t.alloc(vec), "alloc sweep t");
-  if (mf.w_w0.bytes < wb) HIPCHK(mf.w_w0.alloc(wb), "alloc sweep w0");
-  if (mf.w_w1.bytes < wb) HIPCHK(mf.w_w1.alloc(wb), "alloc sweep w1");
+  if (mf.w_t.bytes < vec) TRY(alloc_or_reclaim(c, mf.w_t, vec, "alloc sweep t"));
+  if (mf.w_w0.bytes < wb) TRY(alloc_or_reclaim(c, mf.w_w0, wb, "alloc sweep w0"));
+  if (mf.w_w1.bytes < wb) TRY(alloc_or_reclaim(c, mf.w_w1, wb, "alloc sweep w1"));
   return TEM_OK;
 }
 
@@ -1027,12 +1043,12 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
     const int32_t *ln = lvl_ptr(mf, li);
     if (!big(li)) {
       HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, W[(L + 1) & 1], ws,
-                               0, (int64_t)1 << 40),
+                               0, (int64_t)1 << 40, real_l),
              "fwd tri");
     } else {
       for (int64_t cb = 0; cb < li.max_k; cb += BB) {
         HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, W[(L + 1) & 1],
-                                 ws, cb, BB),
+                                 ws, cb, BB, real_l),
                "fwd tri");
         HIPCHK(launch_fwd_rows<T>(st, ft, ln, li.n, (int)std::max<int64_t>(0, li.max_k - cb - BB),
                                   npole, S, N, F, f_stride, x, cb, BB, real_l),
@@ -1051,7 +1067,7 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
            "bwd rect");
     if (!big(li)) {
       HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, 0,
-                               (int64_t)1 << 40, 1),
+                               (int64_t)1 << 40, 1, real_l),
              "bwd tri");
     } else {
       HIPCHK(launch_bwd_init<T>(st, ft, ln, li.n, li.max_k, npole, S, N, F, f_stride, x, t, N * S),
@@ -1060,7 +1076,7 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
       for (int64_t bb = nbb - 1; bb >= 0; --bb) {
         const int64_t cb = bb * BB;
         HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, cb, BB,
-                                 0),
+                                 0, real_l),
                "bwd tri");
         HIPCHK(launch_bwd_cols<T>(st, ft, ln, li.n, cb, npole, S, N, F, f_stride, x, BB, real_l),
                "bwd cols");
@@ -1165,7 +1181,7 @@ tem_status sweep(tem_ctx *c, cpx<T> *x, int S, const std::vector<PoleRun> &runs)
 
 tem_status ensure_vec(tem_ctx *c, DBuf &b, size_t bytes, const char *what) {
   if (c->arena.on) return arena_take(c, b, bytes, what);
-  if (b.bytes != bytes) HIPCHK(b.alloc(bytes), what);
+  if (b.bytes != bytes) TRY(alloc_or_reclaim(c, b, bytes, what));
   return TEM_OK;
 }
 
@@ -1645,14 +1661,8 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
     }
   }
   if (overlap) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join");
-  {
-    // keep the arenas for the next factorisation unless the solves need the room
-    size_t fr = 0, tt = 0;
-    if (hipMemGetInfo(&fr, &tt) != hipSuccess || fr < (size_t)32 << 30) {
-      c->d_cb0.release();
-      c->d_cb1.release();
-    }
-  }
+  // the arenas stay allocated for the next factorisation of this size; a
+  // solve that runs out of device memory gives them back (alloc_or_reclaim)
   if (nodal && !overlap) {
     tem_status s = factor_nodal(c);
     if (s != TEM_OK) {

@@ -133,11 +133,13 @@ hipError_t launch_front_update(hipStream_t st, FrontTab ft, const int32_t *lvl_n
 // Vectors are [pole][N][S] complex T (S fastest), S <= 16.
 // Triangle kernels work on the column range [cb, min(cb + BB, k)); BB >= k
 // covers the whole front in one launch (one workgroup per front and pole).
+// real_l: the factor's imaginary parts are zero (the register kernels then
+// keep and apply its real parts only).
 template <typename T>
 hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
                           cpx<T> *x, const cpx<T> *w_child, int64_t w_stride, int64_t cb,
-                          int64_t BB);
+                          int64_t BB, bool real_l = false);
 // rows [cb+BB, k) -= L(rows, [cb, cb+BB)) y   (many workgroups per front)
 template <typename T>
 hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
@@ -173,7 +175,7 @@ template <typename T>
 hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
                           cpx<T> *x, const cpx<T> *t, int64_t t_stride, int64_t cb, int64_t BB,
-                          int init);
+                          int init, bool real_l = false);
 
 // ------------------------------------------------------- vector kernels
 // Residual r = f - (K - xi_p M) x for all poles p and rhs s (FP64);
@@ -188,7 +190,7 @@ hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const in
 // consecutive rows per block whose columns span at most RB_HALO distinct
 // rows (the block's halo), rows of at most RB_NNZ entries; right-hand sides
 // are staged RB_SC at a time.
-constexpr int RB_ROWS = 64, RB_HALO = 512, RB_NNZ = 33, RB_SC = 8;
+constexpr int RB_ROWS = 32, RB_HALO = 384, RB_NNZ = 33, RB_SC = 8;
 // r = f - (K - xi_p M) x (x != NULL) by row blocks: block b holds rows
 // [rb_row[b], rb_row[b+1]) and halo rows rb_h[rb_hoff[b] .. rb_hoff[b+1]);
 // lcol[t] is the position of col[t] in its block's halo.  Same layouts and
