@@ -193,24 +193,37 @@ __global__ __launch_bounds__(256) void k_residual_blk(
   const int nnz = has_row ? (int)(rp[lr + 1] - rp[lr]) : 0;
   const int64_t xb = 2 * (int64_t)seg_find(sg, row0) * sg.stride;
   const int nch = (S + RB_SC - 1) / RB_SC, npair = npole * nch;
-  cpx<double> stg[NS];
-  auto load_pair = [&](int q) {
-    const int p = q / nch, s0 = (q - p * nch) * RB_SC;
-    const int sc = min(RB_SC, S - s0);
-    const cpx<double> *X = x + (int64_t)p * N * S + s0 + min(ls, sc - 1);
+  // halo rows of the current pair, in registers (real and imaginary parts
+  // in separate arrays of doubles, which the compiler keeps in registers)
+  double sre[NS], sim[NS];
+  {
+    const cpx<double> *X = x + min(ls, min(RB_SC, S) - 1);
 #pragma unroll
-    for (int i = 0; i < NS; ++i) stg[i] = X[(int64_t)hidx[i] * S];
-  };
-  load_pair(0);
+    for (int i = 0; i < NS; ++i) {
+      const cpx<double> v = X[(int64_t)hidx[i] * S];
+      sre[i] = v.re;
+      sim[i] = v.im;
+    }
+  }
   for (int q = 0; q < npair; ++q) {
     const int p = q / nch, s0 = (q - p * nch) * RB_SC;
     const int sc = min(RB_SC, S - s0);
     __syncthreads();   // the previous pair's sums have read xs
 #pragma unroll
     for (int i = 0; i < NS; ++i)
-      if (lr + 32 * i < nh) xs[(lr + 32 * i) * RB_SC + ls] = stg[i];
+      if (lr + 32 * i < nh) xs[(lr + 32 * i) * RB_SC + ls] = {sre[i], sim[i]};
     __syncthreads();
-    if (q + 1 < npair) load_pair(q + 1);   // in flight during this pair's sums
+    if (q + 1 < npair) {   // the next pair's rows, in flight during this pair's sums
+      const int pn = (q + 1) / nch, sn = (q + 1 - pn * nch) * RB_SC;
+      const cpx<double> *X =
+          x + (int64_t)pn * N * S + sn + min(ls, min(RB_SC, S - sn) - 1);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const cpx<double> v = X[(int64_t)hidx[i] * S];
+        sre[i] = v.re;
+        sim[i] = v.im;
+      }
+    }
     if (!has_row || ls >= sc) continue;
     const double xr = xi[xb + 2 * p], xim = xi[xb + 2 * p + 1];
     const cpx<double> *kmr = km + lr * RB_NNZ;
@@ -641,44 +654,59 @@ hipError_t launch_jtw_rhs(hipStream_t st, int S, int ldS, int64_t pstride, int K
   return hipGetLastError();
 }
 
-// (J^T w)_p = 2 Re sum_{i,s} xi_i sigma_c g|_c^T Me lam|_c, one thread per parameter
-__global__ void k_jtw_reduce(int P, int npole, int S, int ldS, int64_t pstride,
-                             const int32_t *params, const int32_t *cell_new, const double *sigma,
-                             const double *Me, const double *xi, const cpx<double> *g,
-                             const cpx<double> *lam, double *out) {
-  const int pp = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pp >= P) return;
+// (J^T w)_p = 2 Re sum_{i,s} xi_i sigma_c g|_c^T Me lam|_c, c = params[p]:
+// one wave per parameter, the lanes taking (pole, right-hand side) pairs,
+// 64 / S poles at a time (a pole's rows of g and lam for the cell's edges
+// are contiguous over the right-hand sides); the lanes' terms are summed by
+// a fixed shuffle tree, so the result is deterministic.
+__global__ __launch_bounds__(256) void k_jtw_reduce(int P, int npole, int S, int ldS,
+                                                    int64_t pstride, const int32_t *params,
+                                                    const int32_t *cell_new, const double *sigma,
+                                                    const double *Me, const double *xi,
+                                                    const cpx<double> *g, const cpx<double> *lam,
+                                                    double *out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t pp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pp >= P) return;   // the whole wave
   const int64_t cell = params[pp];
   int32_t qe[12];
+#pragma unroll
   for (int t = 0; t < 12; ++t) qe[t] = cell_new[cell * 12 + t];
+  const int slots = 64 / S, c = lane % S, ps = lane / S;
   double tot = 0.0;
-  for (int i = 0; i < npole; ++i) {
+  for (int p0 = 0; p0 < npole; p0 += slots) {
+    const int i = p0 + ps;
+    if (ps >= slots || i >= npole) continue;
+    const cpx<double> *G = g + (int64_t)i * pstride + c;
+    const cpx<double> *L = lam + (int64_t)i * pstride + c;
     double br = 0.0, bi = 0.0;
-    for (int s = 0; s < S; ++s) {
-      const cpx<double> *G = g + (int64_t)i * pstride + s;
-      const cpx<double> *L = lam + (int64_t)i * pstride + s;
-      for (int dd = 0; dd < 3; ++dd) {
-        cpx<double> gv[4], lv[4];
-        for (int t = 0; t < 4; ++t) {
-          const int32_t q = qe[4 * dd + t];
-          gv[t] = q >= 0 ? G[(int64_t)q * ldS] : cpx<double>{0.0, 0.0};
-          lv[t] = q >= 0 ? L[(int64_t)q * ldS] : cpx<double>{0.0, 0.0};
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+      cpx<double> gv[4], lv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int32_t q = qe[4 * dd + t];
+        gv[t] = q >= 0 ? G[(int64_t)q * ldS] : cpx<double>{0.0, 0.0};
+        lv[t] = q >= 0 ? L[(int64_t)q * ldS] : cpx<double>{0.0, 0.0};
+      }
+#pragma unroll
+      for (int a2 = 0; a2 < 4; ++a2) {
+        double mr = 0.0, mi = 0.0;
+#pragma unroll
+        for (int b2 = 0; b2 < 4; ++b2) {
+          const double m = Me[(4 * dd + a2) * 12 + 4 * dd + b2];
+          mr += m * lv[b2].re;
+          mi += m * lv[b2].im;
         }
-        for (int a = 0; a < 4; ++a) {
-          double mr = 0.0, mi = 0.0;
-          for (int b = 0; b < 4; ++b) {
-            const double m = Me[(4 * dd + a) * 12 + 4 * dd + b];
-            mr += m * lv[b].re;
-            mi += m * lv[b].im;
-          }
-          br += gv[a].re * mr - gv[a].im * mi;
-          bi += gv[a].re * mi + gv[a].im * mr;
-        }
+        br += gv[a2].re * mr - gv[a2].im * mi;
+        bi += gv[a2].re * mi + gv[a2].im * mr;
       }
     }
     tot += 2.0 * (xi[2 * i] * br - xi[2 * i + 1] * bi);
   }
-  out[pp] = tot * sigma[cell];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+  if (lane == 0) out[pp] = tot * sigma[cell];
 }
 
 hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int ldS, int64_t pstride,
@@ -686,8 +714,8 @@ hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int ldS, i
                              const double *Me, const double *xi, const cpx<double> *g,
                              const cpx<double> *lam, double *out) {
   if (P <= 0) return hipSuccess;
-  if (S > ldS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jtw_reduce, dim3((P + 127) / 128), dim3(128), 0, st, P, npole, S, ldS,
+  if (S < 1 || S > 64 || S > ldS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jtw_reduce, dim3((P + 3) / 4), dim3(256), 0, st, P, npole, S, ldS,
                      pstride, params, cell_new, sigma, Me, xi, g, lam, out);
   return hipGetLastError();
 }
