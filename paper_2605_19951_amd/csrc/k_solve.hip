@@ -327,8 +327,9 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
   using acc_t = typename MF::acc_t;
   constexpr int RB = 2, KC = MF::KC;   // 16-row blocks per wave, columns per chunk
   const int s = lvl_nodes[blockIdx.y];
-  // pf > 1: the pole is the fastest part of blockIdx.x (a factor shared by
-  // all poles is then read by their workgroups together, once from HBM)
+  // pf > 1: the pole is the fastest part of blockIdx.x (the workgroups of all
+  // poles for the same rows run together; a factor shared by all poles is
+  // then read once from HBM)
   const int p = pf > 1 ? (int)(blockIdx.x % pf) : (int)blockIdx.z;
   const int64_t bx = pf > 1 ? (int64_t)(blockIdx.x / pf) : (int64_t)blockIdx.x;
   if (pole_absent(ft, s, p)) return;
@@ -457,15 +458,15 @@ hipError_t fwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lv
                        int64_t BB, bool real_l) {
   if (S < 1 || S > 16) return hipErrorInvalidValue;
   const bool two = S > 8;
+  // the poles go into the fastest grid dimension, so that the workgroups of
+  // all poles for the same rows run together
+  const int pf = (int)grid.z;
+  if (pf > 1) {
+    grid.x *= pf;
+    grid.z = 1;
+  }
   if constexpr (sizeof(T) == 8) {
     if (real_l) {
-      // one real factor for every pole slot (f_stride == 0): interleave the
-      // poles into the fastest grid dimension
-      const int pf = f_stride == 0 ? (int)grid.z : 1;
-      if (pf > 1) {
-        grid.x *= pf;
-        grid.z = 1;
-      }
       if (two)
         hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, ROWS, true>), grid, dim3(256), 0, st, ft,
                            lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB,
@@ -479,10 +480,10 @@ hipError_t fwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lv
   }
   if (two)
     hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, ROWS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, 1);
+                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, pf);
   else
     hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, ROWS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, 1);
+                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, pf);
   return hipGetLastError();
 }
 
@@ -665,13 +666,13 @@ hipError_t bwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lv
                        int64_t t_stride, int64_t cb, int64_t BB, bool real_l) {
   if (S < 1 || S > 16) return hipErrorInvalidValue;
   const bool two = S > 8;
+  const int pf = (int)grid.z;   // poles fastest, as in fwd_mfma_go
+  if (pf > 1) {
+    grid.x *= pf;
+    grid.z = 1;
+  }
   if constexpr (sizeof(T) == 8) {
     if (real_l) {
-      const int pf = f_stride == 0 ? (int)grid.z : 1;   // as in fwd_mfma_go
-      if (pf > 1) {
-        grid.x *= pf;
-        grid.z = 1;
-      }
       if (two)
         hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, COLS, true>), grid, dim3(256), 0, st, ft,
                            lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB, pf);
@@ -683,10 +684,10 @@ hipError_t bwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lv
   }
   if (two)
     hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, COLS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, t, t_stride, cb, BB, 1);
+                       factor, f_stride, x, t, t_stride, cb, BB, pf);
   else
     hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, COLS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, t, t_stride, cb, BB, 1);
+                       factor, f_stride, x, t, t_stride, cb, BB, pf);
   return hipGetLastError();
 }
 

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_residual(int64_t N, int npole, int S,
 // side each, form the row's sums (one 128-byte halo row per entry spans all
 // LDS banks; the entry itself is a broadcast).  The matrix is read once per
 // call and each x row once per block that touches it, instead of once per
-// nonzero.  The sum over a row runs in CSR order, as in k_residual.
+// nonzero.  The sums over a row run in CSR order.
 __global__ __launch_bounds__(256) void k_residual_blk(
     int64_t N, int npole, int S, int64_t nblk, const int64_t *rb_row, const int64_t *rb_hoff,
     const int32_t *rb_h, const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
@@ -228,15 +228,19 @@ __global__ __launch_bounds__(256) void k_residual_blk(
     const double xr = xi[xb + 2 * p], xim = xi[xb + 2 * p + 1];
     const cpx<double> *kmr = km + lr * RB_NNZ;
     const int *klr = kl + lr * RB_NNZ;
-    double ar = 0.0, ai = 0.0;
+    // K x and M x of the row, then (K - xi M) x = K x - xi (M x): four
+    // multiply-adds per entry instead of six for the entry's shifted value
+    double kr = 0.0, ki = 0.0, mr = 0.0, mi = 0.0;
 #pragma unroll 4
     for (int j = 0; j < nnz; ++j) {
       const cpx<double> v = xs[klr[j] + ls];
       const cpx<double> a = kmr[j];
-      const double sr = a.re - xr * a.im, si = -xim * a.im;
-      ar += sr * v.re - si * v.im;
-      ai += sr * v.im + si * v.re;
+      kr += a.re * v.re;
+      ki += a.re * v.im;
+      mr += a.im * v.re;
+      mi += a.im * v.im;
     }
+    const double ar = kr - (xr * mr - xim * mi), ai = ki - (xr * mi + xim * mr);
     const int c = s0 + ls;
     double fr = 0.0, fi = 0.0;
     if (f_cplx) {
