@@ -316,13 +316,18 @@ struct Mfma16<double> {
 // columns of a wide front: X[r] -= sum_{j in [cb, ce)} L(r, j) y_j for rows r
 // in [ce, k), ce = min(k, cb + BB), in place.  RL = true: the factor is
 // real (its imaginary parts are zero), so the Li products are skipped.
+// yin (ROWS only, may be null): y of the block's columns is read from yin
+// ([pole][N][S] like x) instead of x, and the workgroups copy those rows of
+// yin into x (the explicit-inverse schedule leaves the block's solution
+// there; no workgroup of the launch reads x in those rows).
 template <typename T, int NBK, bool ROWS, bool RL = false>
 __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
                                                        int S, int64_t N, const cpx<T> *factor,
                                                        int64_t f_stride, cpx<T> *x,
                                                        const cpx<T> *w_child,
                                                        cpx<T> *w_out, int64_t w_stride,
-                                                       int64_t cb, int64_t BB, int pf) {
+                                                       int64_t cb, int64_t BB, int pf,
+                                                       const cpx<T> *yin) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
   constexpr int RB = 2, KC = MF::KC;   // 16-row blocks per wave, columns per chunk
@@ -336,19 +341,26 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
   const int64_t k = ft.k[s], u = ft.u[s], n = k + u, first = ft.first[s];
   // output rows row0 + [0, nrows), depth columns [d0, d1)
   int64_t row0 = k, nrows = u, d0 = 0, d1 = k;
+  cpx<T> *X = x + ((int64_t)p * N + first) * S;
+  const cpx<T> *Y = X;   // where y of the depth columns is read
   if (ROWS) {
     if (cb >= k) return;
     d0 = cb;
     d1 = min(k, cb + BB);
     row0 = d1;
     nrows = k - d1;
+    if (yin) {
+      Y = yin + ((int64_t)p * N + first) * S;
+      // block rows [d0 + 128 bx, +128) of yin -> x
+      const int64_t c0 = d0 + bx * 128, c1 = min(d1, c0 + 128);
+      for (int64_t idx = c0 * S + threadIdx.x; idx < c1 * S; idx += 256) X[idx] = Y[idx];
+    }
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t aw = bx * 128 + wave * 32;   // first row of the wave
   if (aw >= nrows) return;
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
-  cpx<T> *X = x + ((int64_t)p * N + first) * S;
   const int lr = lane & 15, ld4 = lane >> 4;   // operand row / output column, depth
   // rows of the two blocks (clamped; rows past u reach no output)
   int32_t rrow[RB];
@@ -371,7 +383,7 @@ __global__ __launch_bounds__(256) void k_fwd_rect_mfma(FrontTab ft, const int32_
       r1[b][nb] = acc_t{0, 0, 0, 0};
       r2[b][nb] = acc_t{0, 0, 0, 0};
     }
-  const T *Xf = reinterpret_cast<const T *>(X);
+  const T *Xf = reinterpret_cast<const T *>(Y);
   // chunk jb into (lv, yv): unconditional loads from clamped addresses (a
   // chunk past the end re-reads the last one and gets y = 0)
   const int64_t jlast = d0 + ((d1 - 1 - d0) / KC) * KC;
@@ -455,7 +467,7 @@ template <typename T, bool ROWS>
 hipError_t fwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lvl_nodes, int S,
                        int64_t N, const cpx<T> *factor, int64_t f_stride, cpx<T> *x,
                        const cpx<T> *w_child, cpx<T> *w_out, int64_t w_stride, int64_t cb,
-                       int64_t BB, bool real_l) {
+                       int64_t BB, bool real_l, const cpx<T> *yin = nullptr) {
   if (S < 1 || S > 16) return hipErrorInvalidValue;
   const bool two = S > 8;
   // the poles go into the fastest grid dimension, so that the workgroups of
@@ -470,20 +482,20 @@ hipError_t fwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lv
       if (two)
         hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, ROWS, true>), grid, dim3(256), 0, st, ft,
                            lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB,
-                           pf);
+                           pf, yin);
       else
         hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, ROWS, true>), grid, dim3(256), 0, st, ft,
                            lvl_nodes, S, N, factor, f_stride, x, w_child, w_out, w_stride, cb, BB,
-                           pf);
+                           pf, yin);
       return hipGetLastError();
     }
   }
   if (two)
     hipLaunchKernelGGL((k_fwd_rect_mfma<T, 2, ROWS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, pf);
+                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, pf, yin);
   else
     hipLaunchKernelGGL((k_fwd_rect_mfma<T, 1, ROWS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, pf);
+                       factor, f_stride, x, w_child, w_out, w_stride, cb, BB, pf, yin);
   return hipGetLastError();
 }
 
@@ -499,15 +511,20 @@ hipError_t launch_fwd_rect(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
                                w_out, w_stride, 0, 0, real_l);
 }
 
-// rows [ce, k) of each wide front -= L(rows, [cb, ce)) y, ce = min(k, cb + BB)
+// rows [ce, k) of each wide front -= L(rows, [cb, ce)) y, ce = min(k, cb + BB);
+// yin: y in rows [cb, ce) of yin, copied into x by the same launch
 template <typename T>
 hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_rows, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB, bool real_l) {
-  if (n_nodes <= 0 || max_rows <= 0) return hipSuccess;
-  dim3 grid((max_rows + 127) / 128, n_nodes, npole);
+                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB, bool real_l,
+                           const cpx<T> *yin) {
+  if (n_nodes <= 0) return hipSuccess;
+  int64_t nbx = (max_rows + 127) / 128;
+  if (yin) nbx = std::max<int64_t>(nbx, (BB + 127) / 128);   // the copy of the block rows
+  if (nbx <= 0) return hipSuccess;
+  dim3 grid((unsigned)nbx, n_nodes, npole);
   return fwd_mfma_go<T, true>(st, grid, ft, lvl_nodes, S, N, factor, f_stride, x, nullptr,
-                              nullptr, 0, cb, BB, real_l);
+                              nullptr, 0, cb, BB, real_l, yin);
 }
 
 // ----------------------------------------------------------- backward rect
@@ -526,12 +543,15 @@ hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 // COLS = true is the same product for a wide front's columns left of a
 // block of rows: X[j] -= sum_{r in [cb, ce)} L(r, j) x_r for j < cb, x read
 // in place (no gather), ce = min(k, cb + BB).  RL as in the forward kernel.
+// xin (COLS only, may be null): the block's x rows are read from xin
+// ([pole][N][S]) and copied into x by the launch, as yin in the forward
+// kernel.
 template <typename T, int NBK, bool COLS, bool RL = false>
 __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_t *lvl_nodes,
                                                        int S, int64_t N, const cpx<T> *factor,
                                                        int64_t f_stride, cpx<T> *x,
                                                        cpx<T> *t, int64_t t_stride, int64_t cb,
-                                                       int64_t BB, int pf) {
+                                                       int64_t BB, int pf, const cpx<T> *xin) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
   const int s = lvl_nodes[blockIdx.y];
@@ -542,17 +562,24 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
   const int64_t jb = bx * NB;
   // columns [jb, jb + w) take rows row0 + [0, u) of the panel
   int64_t row0 = k, ncol = k;
+  cpx<T> *Xf = x + ((int64_t)p * N + first) * S;
+  const cpx<T> *Xr = Xf;   // where the block's x rows are read (COLS)
   if (COLS) {
     if (cb >= k) return;
     row0 = cb;
     ncol = cb;
+    if (xin) {
+      Xr = xin + ((int64_t)p * N + first) * S;
+      // block rows [cb + NB bx, + NB) of xin -> x
+      const int64_t c0 = cb + bx * NB, c1 = min(min(k, cb + BB), c0 + NB);
+      for (int64_t idx = c0 * S + threadIdx.x; idx < c1 * S; idx += 256) Xf[idx] = Xr[idx];
+    }
   }
   if (jb >= ncol) return;
   const int w = (int)min((int64_t)NB, ncol - jb);
   const int64_t nr = COLS ? min(k, cb + BB) - cb : u;   // rows of the reduction
   const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
   const cpx<T> *Xp = x + (int64_t)p * N * S;
-  cpx<T> *Xf = x + ((int64_t)p * N + first) * S;
   const int32_t *rows = ft.rows + ft.rows_off[s];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -575,7 +602,7 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
   auto xval = [&](int q, int64_t ac, int na) -> cpx<T> {
     const int idx = tid + 256 * q;
     const int i = min(idx / S, na - 1), c = idx % S;
-    if (COLS) return Xf[(row0 + ac + i) * S + c];
+    if (COLS) return Xr[(row0 + ac + i) * S + c];
     return Xp[(int64_t)rows[ac + i] * S + c];
   };
   auto fetch = [&](int64_t ac) {
@@ -663,7 +690,8 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
 template <typename T, bool COLS>
 hipError_t bwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lvl_nodes, int S,
                        int64_t N, const cpx<T> *factor, int64_t f_stride, cpx<T> *x, cpx<T> *t,
-                       int64_t t_stride, int64_t cb, int64_t BB, bool real_l) {
+                       int64_t t_stride, int64_t cb, int64_t BB, bool real_l,
+                       const cpx<T> *xin = nullptr) {
   if (S < 1 || S > 16) return hipErrorInvalidValue;
   const bool two = S > 8;
   const int pf = (int)grid.z;   // poles fastest, as in fwd_mfma_go
@@ -675,19 +703,19 @@ hipError_t bwd_mfma_go(hipStream_t st, dim3 grid, FrontTab ft, const int32_t *lv
     if (real_l) {
       if (two)
         hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, COLS, true>), grid, dim3(256), 0, st, ft,
-                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB, pf);
+                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB, pf, xin);
       else
         hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, COLS, true>), grid, dim3(256), 0, st, ft,
-                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB, pf);
+                           lvl_nodes, S, N, factor, f_stride, x, t, t_stride, cb, BB, pf, xin);
       return hipGetLastError();
     }
   }
   if (two)
     hipLaunchKernelGGL((k_bwd_rect_mfma<T, 2, COLS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, t, t_stride, cb, BB, pf);
+                       factor, f_stride, x, t, t_stride, cb, BB, pf, xin);
   else
     hipLaunchKernelGGL((k_bwd_rect_mfma<T, 1, COLS>), grid, dim3(256), 0, st, ft, lvl_nodes, S, N,
-                       factor, f_stride, x, t, t_stride, cb, BB, pf);
+                       factor, f_stride, x, t, t_stride, cb, BB, pf, xin);
   return hipGetLastError();
 }
 
@@ -956,15 +984,298 @@ hipError_t launch_bwd_init(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 
 // ------------------------------------------------------ backward cols
 // X[j] -= sum_{r in [cb, ce)} L(r, j) x_r for the column blocks of j < cb
+// xin: the block's x rows in rows [cb, ce) of xin, copied into x by the
+// same launch
 template <typename T>
 hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int64_t cb, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t BB, bool real_l) {
-  if (n_nodes <= 0 || cb <= 0) return hipSuccess;
-  dim3 grid((unsigned)((cb + NB - 1) / NB), n_nodes, npole);
+                           int64_t f_stride, cpx<T> *x, int64_t BB, bool real_l,
+                           const cpx<T> *xin) {
+  if (n_nodes <= 0) return hipSuccess;
+  int64_t nbx = (cb + NB - 1) / NB;
+  if (xin) nbx = std::max<int64_t>(nbx, (BB + NB - 1) / NB);   // the copy of the block rows
+  if (nbx <= 0) return hipSuccess;
+  dim3 grid((unsigned)nbx, n_nodes, npole);
   return bwd_mfma_go<T, true>(st, grid, ft, lvl_nodes, S, N, factor, f_stride, x, nullptr, 0, cb,
-                              BB, real_l);
+                              BB, real_l, xin);
 }
+
+// ------------------------------------------- explicit diagonal-block inverses
+// For the wide fronts (levels walked in BB-column blocks) the unit-lower
+// diagonal block of columns [b BB, b BB + w), w = min(BB, k - b BB), is
+// inverted once per factorisation, so that a sweep applies it as one
+// matrix product over many workgroups instead of a chain of NB-column
+// steps inside one workgroup per front and pole.  From the stored NB x NB
+// diagonal inverses Linv_i (the panel's strictly upper diagonal-block parts)
+// and the panel's off-diagonal NB x NB blocks L_iq:
+//   X_jj = Linv_j,   X_ij = -Linv_i sum_{j <= q < i} L_iq X_qj   (i > j).
+// X (column-major, leading dimension w) and then its transpose (the same
+// layout) start at xoff[s] + 2 b BB^2 of the pole's region (x_stride
+// elements per pole).  One workgroup per group of CW columns of a block:
+// the group's columns of X stay in LDS while its NB-row blocks are formed
+// in order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_inverse(FrontTab ft, const int32_t *lvl_nodes,
+                                                      const cpx<T> *factor, int64_t f_stride,
+                                                      cpx<T> *xinv, int64_t x_stride,
+                                                      const int64_t *xoff, int BB) {
+  constexpr int CW = sizeof(T) == 4 ? 16 : 8;   // columns per workgroup
+  constexpr int NE = NB * CW / 256;             // entries of a row block per thread
+  const int gpb = BB / CW;
+  const int s = lvl_nodes[blockIdx.y];
+  const int p = blockIdx.z;
+  if (pole_absent(ft, s, p)) return;
+  const int64_t k = ft.k[s], n = k + ft.u[s];
+  const int bb = (int)(blockIdx.x / gpb), g = (int)(blockIdx.x % gpb);
+  const int64_t cb = (int64_t)bb * BB;
+  if (cb >= k) return;
+  const int w = (int)min((int64_t)BB, k - cb);
+  const int c0 = g * CW;
+  if (c0 >= w) return;
+  const int j = c0 / NB, nbw = (w + NB - 1) / NB;
+  const cpx<T> *P = factor + (int64_t)p * f_stride + ft.panel_off[s];
+  __shared__ cpx<T> Xs[256][CW];        // rows [NB j, w) of the group's columns
+  __shared__ cpx<T> Ts[NB][CW];
+  __shared__ cpx<T> Lt[NB][NB + 1];     // Linv_i[a][b], b < a
+  const int tid = threadIdx.x, a = tid % NB, cg = tid / NB;
+  // X_jj = Linv_j: unit diagonal; Linv_j[r][c] (r > c) is stored at (row c, column r)
+  for (int idx = tid; idx < NB * CW; idx += 256) {
+    const int r = idx / CW, c = idx % CW, cc = c0 + c - NB * j;
+    cpx<T> v = czero<T>();
+    if (NB * j + r < w && c0 + c < w) {
+      if (r == cc)
+        v = cpx<T>{T(1), T(0)};
+      else if (r > cc)
+        v = P[panel_elem(n, cb + NB * j + cc, cb + NB * j + r)];
+    }
+    Xs[NB * j + r][c] = v;
+  }
+  __syncthreads();
+  for (int i = j + 1; i < nbw; ++i) {
+    const int wi = min(NB, w - NB * i);
+    for (int idx = tid; idx < NB * NB; idx += 256) {   // Linv_i (consecutive b: one column)
+      const int ra = idx / NB, b = idx % NB;
+      Lt[ra][b] = (b < ra && ra < wi) ? P[panel_elem(n, cb + NB * i + b, cb + NB * i + ra)]
+                                      : czero<T>();
+    }
+    // T[a][c] = sum_{q in [NB j, NB i)} L(cb + NB i + a, cb + q) X[q][c], the
+    // row's entries loaded NB at a time (rows past wi clamped, results unused)
+    const int64_t row = cb + NB * i + min(a, wi - 1);
+    cpx<T> acc[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) acc[e] = czero<T>();
+    for (int q0 = NB * j; q0 < NB * i; q0 += NB) {
+      const cpx<T> *Lc = P + panel_block_off(n, (cb + q0) / NB) - (cb + q0) + row;
+      const int64_t ld = n - (cb + q0);   // column block of q0: element (r, c) at Lc[(c - q0') ld]
+      cpx<T> lq[NB];
+#pragma unroll
+      for (int l = 0; l < NB; ++l) lq[l] = Lc[(int64_t)l * ld];
+#pragma unroll
+      for (int l = 0; l < NB; ++l)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) acc[e] = cfma(lq[l], Xs[q0 + l][cg + 8 * e], acc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) Ts[a][cg + 8 * e] = a < wi ? acc[e] : czero<T>();
+    __syncthreads();
+    // X_ij = -Linv_i T = -(T + Lo_i T)
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int c = cg + 8 * e;
+      cpx<T> r = Ts[a][c];
+      for (int b = 0; b < a; ++b) r = cfma(Lt[a][b], Ts[b][c], r);
+      if (a < wi) Xs[NB * i + a][c] = cpx<T>{-r.re, -r.im};
+    }
+    __syncthreads();
+  }
+  // X and its transpose; rows above block j are zero
+  cpx<T> *Xo = xinv + (int64_t)p * x_stride + xoff[s] + 2 * (int64_t)bb * BB * BB;
+  cpx<T> *XTo = Xo + (int64_t)w * w;
+  const int cw = min(CW, w - c0);
+  for (int idx = tid; idx < w * cw; idx += 256) {
+    const int c = idx / w, r = idx % w;
+    Xo[(int64_t)(c0 + c) * w + r] = r < NB * j ? czero<T>() : Xs[r][c];
+  }
+  for (int idx = tid; idx < w * cw; idx += 256) {
+    const int r = idx / cw, c = idx % cw;
+    XTo[(int64_t)r * w + c0 + c] = r < NB * j ? czero<T>() : Xs[r][c];
+  }
+}
+
+template <typename T>
+hipError_t launch_diag_inverse(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                               int max_k, int npole, const cpx<T> *factor, int64_t f_stride,
+                               cpx<T> *xinv, int64_t x_stride, const int64_t *xoff, int BB) {
+  constexpr int CW = sizeof(T) == 4 ? 16 : 8;
+  if (n_nodes <= 0 || max_k <= 0) return hipSuccess;
+  if (BB < NB || BB > 256 || BB % NB != 0) return hipErrorInvalidValue;
+  const int64_t nbb = (max_k + BB - 1) / BB;
+  dim3 grid((unsigned)(nbb * (BB / CW)), n_nodes, npole);
+  hipLaunchKernelGGL(k_diag_inverse<T>, grid, dim3(256), 0, st, ft, lvl_nodes, factor, f_stride,
+                     xinv, x_stride, xoff, BB);
+  return hipGetLastError();
+}
+
+// The children's update rows added to the top rows of every front of a
+// level (the first step of the forward sweep of a wide front).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_child_add(FrontTab ft, const int32_t *lvl_nodes,
+                                                       int S, int64_t N, cpx<T> *x,
+                                                       const cpx<T> *w_child, int64_t w_stride) {
+  const int s = lvl_nodes[blockIdx.x];
+  const int p = blockIdx.y;
+  if (pole_absent(ft, s, p)) return;
+  const int64_t k = ft.k[s];
+  if (k == 0) return;
+  cpx<T> *X = x + ((int64_t)p * N + ft.first[s]) * S;
+  fwd_child_add<T>(ft, s, p, k, S, X, w_child, w_stride, threadIdx.x);
+}
+
+template <typename T>
+hipError_t launch_fwd_child_add(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                                int npole, int S, int64_t N, cpx<T> *x, const cpx<T> *w_child,
+                                int64_t w_stride) {
+  if (n_nodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fwd_child_add<T>, dim3(n_nodes, npole), dim3(256), 0, st, ft, lvl_nodes, S,
+                     N, x, w_child, w_stride);
+  return hipGetLastError();
+}
+
+// out rows [cb, cb + w) = M x rows [cb, cb + w) for every front and pole of
+// a level: M = X_b (UPPER false, the forward step) or its transpose (UPPER
+// true, the backward step), b = cb / BB.  A workgroup takes one NB-row
+// slab of M; its wave q multiplies the slab's q-th NB x NB tile (the tiles
+// on the other side of the diagonal are zero and skipped) with x on the
+// matrix cores (operands as in the forward rect kernel), and the tiles'
+// products are summed through LDS in tile order.
+template <typename T, int NBK, bool UPPER>
+__global__ __launch_bounds__(512) void k_blk_apply(FrontTab ft, const int32_t *lvl_nodes, int S,
+                                                   int64_t N, const cpx<T> *xinv,
+                                                   int64_t x_stride, const int64_t *xoff, int BB,
+                                                   int64_t cb, const cpx<T> *x, cpx<T> *out,
+                                                   int pf) {
+  using MF = Mfma16<T>;
+  using acc_t = typename MF::acc_t;
+  const int s = lvl_nodes[blockIdx.y];
+  const int p = pf > 1 ? (int)(blockIdx.x % pf) : (int)blockIdx.z;
+  const int i = pf > 1 ? (int)(blockIdx.x / pf) : (int)blockIdx.x;   // row slab
+  if (pole_absent(ft, s, p)) return;
+  const int64_t k = ft.k[s], first = ft.first[s];
+  if (cb >= k) return;
+  const int w = (int)min((int64_t)BB, k - cb);
+  if (NB * i >= w) return;   // uniform over the workgroup
+  const int nq = (w + NB - 1) / NB;
+  const cpx<T> *M = xinv + (int64_t)p * x_stride + xoff[s] + 2 * (cb / BB) * BB * BB +
+                    (UPPER ? (int64_t)w * w : 0);
+  __shared__ cpx<T> red[8][NB][8 * NBK];
+  const int lane = threadIdx.x & 63;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // column tile
+  const bool act = q < nq && (UPPER ? q >= i : q <= i);
+  if (act) {
+    const int lr = lane & 15, ld4 = lane >> 4;
+    int rrow[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) rrow[b] = min(NB * i + 16 * b + lr, w - 1);
+    int yj[NBK];
+    bool yon[NBK];
+#pragma unroll
+    for (int nb = 0; nb < NBK; ++nb) {
+      const int jj = 8 * nb + (lr & 7);
+      yon[nb] = jj < S;
+      yj[nb] = 2 * min(jj, S - 1) + (lr >> 3);
+    }
+    const T *Xv = reinterpret_cast<const T *>(x + ((int64_t)p * N + first + cb) * S);
+    cpx<T> lv[NB / 4][2];
+    T yv[NB / 4][NBK];
+#pragma unroll
+    for (int qq = 0; qq < NB / 4; ++qq) {
+      const int col = NB * q + 4 * qq + ld4, cc = min(col, w - 1);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) lv[qq][b] = M[(int64_t)cc * w + rrow[b]];
+#pragma unroll
+      for (int nb = 0; nb < NBK; ++nb)   // a multiply, not a select: the load stays unconditional
+        yv[qq][nb] = Xv[(int64_t)cc * 2 * S + yj[nb]] * ((col < w && yon[nb]) ? T(1) : T(0));
+    }
+    acc_t r1[2][NBK], r2[2][NBK];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int nb = 0; nb < NBK; ++nb) {
+        r1[b][nb] = acc_t{0, 0, 0, 0};
+        r2[b][nb] = acc_t{0, 0, 0, 0};
+      }
+#pragma unroll
+    for (int qq = 0; qq < NB / 4; ++qq)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int nb = 0; nb < NBK; ++nb) {
+          r1[b][nb] = MF::mma(lv[qq][b].re, yv[qq][nb], r1[b][nb]);
+          r2[b][nb] = MF::mma(lv[qq][b].im, yv[qq][nb], r2[b][nb]);
+        }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int nb = 0; nb < NBK; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const T o1 = __shfl_xor(r1[b][nb][e], 8), o2 = __shfl_xor(r2[b][nb][e], 8);
+          if (lr < 8)
+            red[q][16 * b + MF::row(ld4, e)][8 * nb + lr] =
+                cpx<T>{r1[b][nb][e] - o2, o1 + r2[b][nb][e]};
+        }
+  }
+  __syncthreads();
+  const int q0 = UPPER ? i : 0, q1 = UPPER ? nq - 1 : i;
+  cpx<T> *O = out + ((int64_t)p * N + first + cb) * S;
+  for (int idx = threadIdx.x; idx < NB * S; idx += 512) {
+    const int ra = idx / S, jj = idx % S;
+    const int r = NB * i + ra;
+    if (r >= w) continue;
+    cpx<T> v = czero<T>();
+    for (int qt = q0; qt <= q1; ++qt) v = cadd(v, red[qt][ra][jj]);
+    O[(int64_t)r * S + jj] = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_blk_apply(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                            int npole, int S, int64_t N, const cpx<T> *xinv, int64_t x_stride,
+                            const int64_t *xoff, int BB, int64_t cb, bool upper,
+                            const cpx<T> *x, cpx<T> *out) {
+  if (n_nodes <= 0) return hipSuccess;
+  if (S < 1 || S > 16 || BB < NB || BB > 256 || BB % NB != 0) return hipErrorInvalidValue;
+  const int pf = npole;   // poles fastest, as in the rect kernels
+  dim3 grid((unsigned)((BB / NB) * pf), n_nodes, 1);
+  const bool two = S > 8;
+  if (upper) {
+    if (two)
+      hipLaunchKernelGGL((k_blk_apply<T, 2, true>), grid, dim3(512), 0, st, ft, lvl_nodes, S, N,
+                         xinv, x_stride, xoff, BB, cb, x, out, pf);
+    else
+      hipLaunchKernelGGL((k_blk_apply<T, 1, true>), grid, dim3(512), 0, st, ft, lvl_nodes, S, N,
+                         xinv, x_stride, xoff, BB, cb, x, out, pf);
+  } else {
+    if (two)
+      hipLaunchKernelGGL((k_blk_apply<T, 2, false>), grid, dim3(512), 0, st, ft, lvl_nodes, S, N,
+                         xinv, x_stride, xoff, BB, cb, x, out, pf);
+    else
+      hipLaunchKernelGGL((k_blk_apply<T, 1, false>), grid, dim3(512), 0, st, ft, lvl_nodes, S, N,
+                         xinv, x_stride, xoff, BB, cb, x, out, pf);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_diag_inverse<float>(hipStream_t, FrontTab, const int32_t *, int, int,
+                                               int, const cpx<float> *, int64_t, cpx<float> *,
+                                               int64_t, const int64_t *, int);
+template hipError_t launch_fwd_child_add<float>(hipStream_t, FrontTab, const int32_t *, int, int,
+                                                int, int64_t, cpx<float> *, const cpx<float> *,
+                                                int64_t);
+template hipError_t launch_blk_apply<float>(hipStream_t, FrontTab, const int32_t *, int, int, int,
+                                            int64_t, const cpx<float> *, int64_t,
+                                            const int64_t *, int, int64_t, bool,
+                                            const cpx<float> *, cpx<float> *);
 
 #define TEM_INST(T)                                                                              \
   template hipError_t launch_fwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \
@@ -972,13 +1283,13 @@ hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
                                         const cpx<T> *, int64_t, int64_t, int64_t, bool);        \
   template hipError_t launch_fwd_rows<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, cpx<T> *,        \
-                                         int64_t, int64_t, bool);                                \
+                                         int64_t, int64_t, bool, const cpx<T> *);                \
   template hipError_t launch_bwd_init<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, cpx<T> *,        \
                                          const cpx<T> *, int64_t);                               \
   template hipError_t launch_bwd_cols<T>(hipStream_t, FrontTab, const int32_t *, int, int64_t,    \
                                          int, int, int64_t, const cpx<T> *, int64_t, cpx<T> *,   \
-                                         int64_t, bool);                                         \
+                                         int64_t, bool, const cpx<T> *);                         \
   template hipError_t launch_fwd_rect<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,   \
                                          int, int64_t, const cpx<T> *, int64_t, const cpx<T> *,  \
                                          const cpx<T> *, cpx<T> *, int64_t, bool);               \

@@ -161,6 +161,12 @@ struct MF {
   int64_t w_rows_max = 0;
   DBuf w_t, w_w0, w_w1;            // sweep work space
   DBuf d_np;                       // batch: poles of each front's mesh (else empty)
+  // explicit inverses of the BB-column diagonal blocks of the wide fronts
+  // (levels with max_k > BB): per front the offset of its first block in
+  // one pole's region of x_stride elements (k_diag_inverse)
+  DBuf d_xoff;
+  int64_t x_stride = 0;
+  int x_bb = 0;
   // row blocks of the FP64 residual (edge system; see launch_residual_blk)
   int64_t rb_n = 0;
   DBuf d_rb_row, d_rb_hoff, d_rb_h, d_lcol;
@@ -230,7 +236,8 @@ struct tem_ctx {
   std::vector<double> h_ncoef;          // host copy of the correction coefficients
   struct SweepGraph {
     hipGraphExec_t exec = nullptr;
-    const void *x = nullptr, *factor = nullptr, *ws[3] = {nullptr, nullptr, nullptr};
+    const void *x = nullptr, *factor = nullptr, *xinv = nullptr;
+    const void *ws[3] = {nullptr, nullptr, nullptr};
     int S = 0, npole = 0;
   } sgraph[2];                     // [0] FP64 factors, [1] FP32 factors
   // Batch of meshes (B > 0): the per-mesh contexts in `sub` assemble and
@@ -257,6 +264,8 @@ struct tem_ctx {
   tem_precision prec = TEM_FP64;
   std::vector<double> xi;
   DBuf d_xi, d_factor, d_cb0, d_cb1, d_flags;
+  DBuf d_xinv;                     // FP32 factors: the wide fronts' block inverses
+  bool xinv_ok = false;
   int n_groups = 0, group_size = 0;
   int n_tiny = 0;
   double factor_ms = 0.0, solve_ms = 0.0;
@@ -466,12 +475,14 @@ void drop_graphs(tem_ctx *c) {
 void drop_factors(tem_ctx *c) {
   c->nodal_ready = false;
   c->factored = false;
+  c->xinv_ok = false;
   c->solved = false;
   drop_graphs(c);
 }
 void free_factors(tem_ctx *c) {
   drop_factors(c);
   c->d_factor.release();
+  c->d_xinv.release();
   c->d_cb0.release();
   c->d_cb1.release();
   c->d_g.release();
@@ -560,6 +571,7 @@ tem_status build_front_maps(tem_ctx *c, MF &mf) {
   // levels (depth); factor/solve order is deepest first
   int nl = sym.n_levels;
   mf.levels.assign(nl, LevelInfo());
+  mf.x_bb = 0;   // block-inverse offsets follow the new structure
   for (int s = 0; s < ns; ++s) mf.levels[sym.nodes[s].level].nodes.push_back(s);
   std::vector<int32_t> lvl_nodes;
   int64_t poff = 0;
@@ -1038,6 +1050,16 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
     return li.max_k > BB &&
            (sizeof(T) == 4 || (int64_t)li.n * npole < c->sweep_big_limit);
   };
+  // FP32 edge factors: the wide fronts' BB-column diagonal blocks are
+  // applied through their explicit inverses (k_diag_inverse), the block's
+  // solution going through t (free during the forward pass, and after
+  // bwd init in the backward pass) so that the launch that uses it can
+  // write it into x
+  const cpx<T> *XI = nullptr;
+  if constexpr (sizeof(T) == 4)
+    if (&mf == &c->ed && c->xinv_ok && mf.x_bb == BB && !real_l)
+      XI = c->d_xinv.as<cpx<T>>() + (int64_t)p0 * mf.x_stride;
+  const int64_t *xoff = mf.d_xoff.as<int64_t>();
   for (int L = nl - 1; L >= 0; --L) {
     const LevelInfo &li = mf.levels[L];
     const int32_t *ln = lvl_ptr(mf, li);
@@ -1045,13 +1067,27 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
       HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, W[(L + 1) & 1], ws,
                                0, (int64_t)1 << 40, real_l),
              "fwd tri");
+    } else if (XI) {
+      if constexpr (sizeof(T) == 4) {
+        HIPCHK(launch_fwd_child_add<T>(st, ft, ln, li.n, npole, S, N, x, W[(L + 1) & 1], ws),
+               "fwd child add");
+        for (int64_t cb = 0; cb < li.max_k; cb += BB) {
+          HIPCHK(launch_blk_apply<T>(st, ft, ln, li.n, npole, S, N, XI, mf.x_stride, xoff,
+                                     (int)BB, cb, false, x, t),
+                 "fwd block inverse");
+          HIPCHK(launch_fwd_rows<T>(st, ft, ln, li.n,
+                                    (int)std::max<int64_t>(0, li.max_k - cb - BB), npole, S, N, F,
+                                    f_stride, x, cb, BB, real_l, t),
+                 "fwd rows");
+        }
+      }
     } else {
       for (int64_t cb = 0; cb < li.max_k; cb += BB) {
         HIPCHK(launch_fwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, W[(L + 1) & 1],
                                  ws, cb, BB, real_l),
                "fwd tri");
         HIPCHK(launch_fwd_rows<T>(st, ft, ln, li.n, (int)std::max<int64_t>(0, li.max_k - cb - BB),
-                                  npole, S, N, F, f_stride, x, cb, BB, real_l),
+                                  npole, S, N, F, f_stride, x, cb, BB, real_l, nullptr),
                "fwd rows");
       }
     }
@@ -1075,10 +1111,18 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
       const int64_t nbb = (li.max_k + BB - 1) / BB;
       for (int64_t bb = nbb - 1; bb >= 0; --bb) {
         const int64_t cb = bb * BB;
-        HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, cb, BB,
-                                 0, real_l),
-               "bwd tri");
-        HIPCHK(launch_bwd_cols<T>(st, ft, ln, li.n, cb, npole, S, N, F, f_stride, x, BB, real_l),
+        if (XI) {
+          if constexpr (sizeof(T) == 4)
+            HIPCHK(launch_blk_apply<T>(st, ft, ln, li.n, npole, S, N, XI, mf.x_stride, xoff,
+                                       (int)BB, cb, true, x, t),
+                   "bwd block inverse");
+        } else {
+          HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, cb,
+                                   BB, 0, real_l),
+                 "bwd tri");
+        }
+        HIPCHK(launch_bwd_cols<T>(st, ft, ln, li.n, cb, npole, S, N, F, f_stride, x, BB, real_l,
+                                  XI ? t : nullptr),
                "bwd cols");
       }
     }
@@ -1138,6 +1182,7 @@ tem_status capture_sweep(tem_ctx *c, cpx<T> *x, int S, tem_ctx::SweepGraph &g) {
   g.exec = exec;
   g.x = x;
   g.factor = c->d_factor.p;
+  g.xinv = c->d_xinv.p;
   g.ws[0] = c->ed.w_t.p;
   g.ws[1] = c->ed.w_w0.p;
   g.ws[2] = c->ed.w_w1.p;
@@ -1154,7 +1199,7 @@ tem_status sweep(tem_ctx *c, cpx<T> *x, int S, const std::vector<PoleRun> &runs)
     // the graph holds the vector, factor and work-space addresses it was
     // captured with; any change (or a grown work space) means a new capture
     TRY(ensure_sweep_ws<T>(c, c->ed, c->npole, S));
-    if (!(g.exec && g.x == x && g.factor == c->d_factor.p && g.S == S &&
+    if (!(g.exec && g.x == x && g.factor == c->d_factor.p && g.xinv == c->d_xinv.p && g.S == S &&
           g.npole == c->npole && g.ws[0] == c->ed.w_t.p && g.ws[1] == c->ed.w_w0.p &&
           g.ws[2] == c->ed.w_w1.p))
       TRY(capture_sweep<T>(c, x, S, g));
@@ -1244,8 +1289,9 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
                                c->d_xi.as<double>() + 2 * pr.p0, rs, nullptr, r + o, z + o, w + o),
            "aux residual");
     // the nodal factor is the same for every pole: its sweep takes the
-    // run's systems packed S2 = 16 to a pass
-    const int nsys = pr.n * S, S2 = std::min(16, nsys), nv = (nsys + S2 - 1) / S2;
+    // run's systems packed S2 = 8 to a virtual pole (eight right-hand sides
+    // keep its register triangle kernels at two blocks in flight)
+    const int nsys = pr.n * S, S2 = std::min(8, nsys), nv = (nsys + S2 - 1) / S2;
     HIPCHK(launch_grad_T(st, Nn, pr.n, S, S2, N, c->d_node_edges.as<int32_t>(), w + o, y), "G^T");
     TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, nv, y, S2, 0,
                                    /*real_l=*/true));
@@ -1574,6 +1620,31 @@ tem_status factor_nodal(tem_ctx *c) {
   return TEM_OK;
 }
 
+// Offsets of the explicit inverses of the wide fronts' BB-column diagonal
+// blocks (levels with max_k > BB, the ones the FP32 sweeps walk in blocks):
+// per front 2 ((nbb - 1) BB^2 + w_last^2) elements (each block and its
+// transpose, w_last the width of the last block), per pole.
+tem_status prepare_xinv(tem_ctx *c, MF &mf, int BB) {
+  if (mf.x_bb == BB && mf.d_xoff.p) return TEM_OK;
+  std::vector<int64_t> off(std::max<size_t>(mf.sym.nodes.size(), 1), 0);
+  int64_t tot = 0;
+  for (const LevelInfo &li : mf.levels) {
+    if (li.max_k <= BB) continue;
+    for (int s : li.nodes) {
+      const SymNode &nd = mf.sym.nodes[s];
+      const int64_t k = nd.last - nd.first;
+      if (k <= 0) continue;
+      const int64_t nbb = (k + BB - 1) / BB, wl = k - (nbb - 1) * BB;
+      off[s] = tot;
+      tot += 2 * ((nbb - 1) * (int64_t)BB * BB + wl * wl);
+    }
+  }
+  HIPCHK(upload(mf.d_xoff, off, c->stream), "upload block-inverse offsets");
+  mf.x_stride = tot;
+  mf.x_bb = BB;
+  return TEM_OK;
+}
+
 // Factor every pole slot of c->xi (a table [mesh][npole] for a batch) in
 // precision prec; pole groups when the arenas do not fit beside the factors.
 tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *opts) {
@@ -1582,18 +1653,26 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
   const size_t esz = prec == TEM_FP64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
   const size_t fbytes = esz * (size_t)c->ed.pole_stride * m;
   const size_t cb_pole = esz * (size_t)std::max<int64_t>(c->ed.cb_stride, 1);
+  // FP32: the wide fronts' diagonal-block inverses beside the factors
+  const bool xinv = prec == TEM_FP32_IR && c->sweep_bb <= 256;
+  c->xinv_ok = false;
+  if (xinv) TRY(prepare_xinv(c, c->ed, (int)c->sweep_bb));
+  const size_t xbytes = xinv ? sizeof(cpx<float>) * (size_t)c->ed.x_stride * m : 0;
   // a factor buffer of another size and the arenas are given back first;
   // the budget counts what is still held as available.
   if (c->d_factor.bytes != fbytes) c->d_factor.release();
+  if (c->d_xinv.bytes != xbytes) c->d_xinv.release();
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-  const int64_t held = (int64_t)(c->d_factor.bytes + c->d_cb0.bytes + c->d_cb1.bytes);
+  const int64_t held =
+      (int64_t)(c->d_factor.bytes + c->d_xinv.bytes + c->d_cb0.bytes + c->d_cb1.bytes);
   int64_t budget = (opts && opts->mem_budget_bytes > 0)
                        ? opts->mem_budget_bytes
                        : (int64_t)(0.92 * (double)free_b) + held;
-  if ((int64_t)fbytes + 2 * (int64_t)cb_pole > budget)
+  const int64_t fixed = (int64_t)(fbytes + xbytes);
+  if (fixed + 2 * (int64_t)cb_pole > budget)
     return fail(c, TEM_ENOMEM, "tem_factor_poles: factors do not fit in the memory budget");
-  int g = (int)std::min<int64_t>(m, (budget - (int64_t)fbytes) / (2 * (int64_t)cb_pole));
+  int g = (int)std::min<int64_t>(m, (budget - fixed) / (2 * (int64_t)cb_pole));
   if (opts && opts->max_group > 0) g = std::min(g, (int)opts->max_group);
   g = std::max(g, 1);
   const int ngroups = (m + g - 1) / g;
@@ -1603,6 +1682,7 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
     c->d_cb1.release();
   }
   HIPCHK(c->d_factor.alloc(fbytes), "alloc factors");
+  if (xbytes) HIPCHK(c->d_xinv.alloc(xbytes), "alloc block inverses");
   HIPCHK(c->d_cb0.alloc(cb_pole * g), "alloc cb arena");
   HIPCHK(c->d_cb1.alloc(cb_pole * g), "alloc cb arena");
   HIPCHK(hipMemsetAsync(c->d_flags.p, 0, sizeof(int) * 4, c->stream), "clear flags");
@@ -1660,6 +1740,17 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
       return s;
     }
   }
+  if (xbytes) {
+    // the wide fronts' diagonal blocks are final: their inverses, all poles
+    const FrontTab ft = front_tab(c->ed, 0);
+    for (const LevelInfo &li : c->ed.levels)
+      if (li.max_k > c->sweep_bb)
+        HIPCHK(launch_diag_inverse<float>(c->stream, ft, lvl_ptr(c->ed, li), li.n, li.max_k, m,
+                                          c->d_factor.as<cpx<float>>(), c->ed.pole_stride,
+                                          c->d_xinv.as<cpx<float>>(), c->ed.x_stride,
+                                          c->ed.d_xoff.as<int64_t>(), (int)c->sweep_bb),
+               "diagonal-block inverses");
+  }
   if (overlap) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join");
   // the arenas stay allocated for the next factorisation of this size; a
   // solve that runs out of device memory gives them back (alloc_or_reclaim)
@@ -1684,6 +1775,7 @@ tem_status factor_core(tem_ctx *c, tem_precision prec, const tem_factor_opts *op
     return fail(c, TEM_EPIVOT, "tem_factor_poles: zero or non-finite pivot");
   }
   c->factored = true;
+  c->xinv_ok = xbytes > 0;
   return TEM_OK;
 }
 

@@ -140,22 +140,46 @@ hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
                           int npole, int S, int64_t N, const cpx<T> *factor, int64_t f_stride,
                           cpx<T> *x, const cpx<T> *w_child, int64_t w_stride, int64_t cb,
                           int64_t BB, bool real_l = false);
-// rows [cb+BB, k) -= L(rows, [cb, cb+BB)) y   (many workgroups per front)
+// rows [cb+BB, k) -= L(rows, [cb, cb+BB)) y   (many workgroups per front);
+// yin non-null: y is read from rows [cb, cb+BB) of yin and copied into x
 template <typename T>
 hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_rows, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB,
-                           bool real_l = false);
+                           int64_t f_stride, cpx<T> *x, int64_t cb, int64_t BB, bool real_l,
+                           const cpx<T> *yin);
 // x_j = y_j / d_j - t_j
 template <typename T>
 hipError_t launch_bwd_init(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int max_k, int npole, int S, int64_t N, const cpx<T> *factor,
                            int64_t f_stride, cpx<T> *x, const cpx<T> *t, int64_t t_stride);
-// columns [0, cb) -= L([cb, cb+BB), cols)^T x  (many workgroups per front)
+// columns [0, cb) -= L([cb, cb+BB), cols)^T x  (many workgroups per front);
+// xin non-null: the block's x rows are read from xin and copied into x
 template <typename T>
 hipError_t launch_bwd_cols(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                            int64_t cb, int npole, int S, int64_t N, const cpx<T> *factor,
-                           int64_t f_stride, cpx<T> *x, int64_t BB, bool real_l = false);
+                           int64_t f_stride, cpx<T> *x, int64_t BB, bool real_l,
+                           const cpx<T> *xin);
+
+// Explicit inverses of the unit-lower BB-column diagonal blocks of the
+// fronts of a level (BB a multiple of NB, at most 256): block b of front s
+// and its transpose at xoff[s] + 2 b BB^2 of each pole's x_stride-element
+// region (column-major, leading dimension = the block's width).
+template <typename T>
+hipError_t launch_diag_inverse(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                               int max_k, int npole, const cpx<T> *factor, int64_t f_stride,
+                               cpx<T> *xinv, int64_t x_stride, const int64_t *xoff, int BB);
+// the children's update rows added to the top rows of every front of a level
+template <typename T>
+hipError_t launch_fwd_child_add(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                                int npole, int S, int64_t N, cpx<T> *x, const cpx<T> *w_child,
+                                int64_t w_stride);
+// out rows [cb, cb + w) = X_b x rows [cb, cb + w) (upper: X_b^T), b = cb / BB,
+// for every front and pole of a level (out and x: [pole][N][S])
+template <typename T>
+hipError_t launch_blk_apply(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
+                            int npole, int S, int64_t N, const cpx<T> *xinv, int64_t x_stride,
+                            const int64_t *xoff, int BB, int64_t cb, bool upper,
+                            const cpx<T> *x, cpx<T> *out);
 
 // real_l: the factor's imaginary parts are zero (FP64 only; skips the
 // products with them)

@@ -240,6 +240,31 @@ def test_update_variant_needs_no_extra_refinement(name):
     assert np.max(r.ir["iters"]) <= np.max(base.ir["iters"]) + 1
 
 
+def test_block_inverse_sweep_matches_triangle_sweep():
+    """FP32 factors: the wide fronts' diagonal blocks applied through their
+    explicit inverses (column blocks of 64, every level wide) give the same
+    single unrefined FP32 solve as the triangle kernels (blocks of 512, no
+    inverses), to FP32 rounding, on every pole and source; the data of both
+    refined solves agree to the refinement tolerance."""
+    inv = _env_run(C16(), 1, {"TEM_SWEEP_BLOCK": "64", "TEM_SWEEP_BIG_LIMIT": "1000000"})
+    tri = _env_run(C16(), 1, {"TEM_SWEEP_BLOCK": "512", "TEM_SWEEP_BIG_LIMIT": "1000000"})
+    torch = inv.torch
+    wl = inv.wl
+    d1 = []
+    for r in (inv, tri):
+        d = torch.zeros_like(r.d)
+        ir = r.t.forward(r.F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d,
+                         ir=dict(rtol=1e-10, max_iter=1), allow_noconv=True)
+        rel = np.asarray(ir["rel"])
+        print("one FP32 solve: worst relative residual %.2e" % rel.max(), flush=True)
+        assert rel.max() < 1e-4
+        d1.append(d.cpu().numpy())
+    scale = np.abs(d1[1]).max()
+    assert np.abs(d1[0] - d1[1]).max() <= 1e-4 * scale
+    assert np.max(inv.ir["iters"]) <= np.max(tri.ir["iters"]) + 1
+    assert np.abs(inv.d.cpu().numpy() - tri.d.cpu().numpy()).max() <= 1e-8 * scale
+
+
 def test_unknown_update_knob_is_refused():
     """tem_create rejects a TEM_UPDATE_TILE or TEM_UPDATE_3M value it does not know."""
     _torch()
