@@ -1148,7 +1148,7 @@ hipError_t launch_fwd_child_add(hipStream_t st, FrontTab ft, const int32_t *lvl_
 // on the other side of the diagonal are zero and skipped) with x on the
 // matrix cores (operands as in the forward rect kernel), and the tiles'
 // products are summed through LDS in tile order.
-template <typename T, int NBK, bool UPPER>
+template <typename T, int NBK, bool UPPER, bool RL>
 __global__ __launch_bounds__(512) void k_blk_apply(FrontTab ft, const int32_t *lvl_nodes, int S,
                                                    int64_t N, const cpx<T> *xinv,
                                                    int64_t x_stride, const int64_t *xoff, int BB,
@@ -1211,7 +1211,7 @@ __global__ __launch_bounds__(512) void k_blk_apply(FrontTab ft, const int32_t *l
 #pragma unroll
         for (int nb = 0; nb < NBK; ++nb) {
           r1[b][nb] = MF::mma(lv[qq][b].re, yv[qq][nb], r1[b][nb]);
-          r2[b][nb] = MF::mma(lv[qq][b].im, yv[qq][nb], r2[b][nb]);
+          if constexpr (!RL) r2[b][nb] = MF::mma(lv[qq][b].im, yv[qq][nb], r2[b][nb]);
         }
 #pragma unroll
     for (int b = 0; b < 2; ++b)
@@ -1238,44 +1238,63 @@ __global__ __launch_bounds__(512) void k_blk_apply(FrontTab ft, const int32_t *l
   }
 }
 
+template <typename T, int NBK, bool UPPER>
+void blk_apply_go(hipStream_t st, dim3 grid, bool real_l, FrontTab ft, const int32_t *lvl_nodes,
+                  int S, int64_t N, const cpx<T> *xinv, int64_t x_stride, const int64_t *xoff,
+                  int BB, int64_t cb, const cpx<T> *x, cpx<T> *out, int pf) {
+  if (real_l)
+    hipLaunchKernelGGL((k_blk_apply<T, NBK, UPPER, true>), grid, dim3(512), 0, st, ft, lvl_nodes,
+                       S, N, xinv, x_stride, xoff, BB, cb, x, out, pf);
+  else
+    hipLaunchKernelGGL((k_blk_apply<T, NBK, UPPER, false>), grid, dim3(512), 0, st, ft, lvl_nodes,
+                       S, N, xinv, x_stride, xoff, BB, cb, x, out, pf);
+}
+
+// real_l: the inverses are real (a real factor; their imaginary parts are
+// zero and skipped).  FP64 takes at most 8 right-hand sides (the LDS of the
+// tile sums).
 template <typename T>
 hipError_t launch_blk_apply(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                             int npole, int S, int64_t N, const cpx<T> *xinv, int64_t x_stride,
-                            const int64_t *xoff, int BB, int64_t cb, bool upper,
+                            const int64_t *xoff, int BB, int64_t cb, bool upper, bool real_l,
                             const cpx<T> *x, cpx<T> *out) {
   if (n_nodes <= 0) return hipSuccess;
-  if (S < 1 || S > 16 || BB < NB || BB > 256 || BB % NB != 0) return hipErrorInvalidValue;
+  if (S < 1 || S > (sizeof(T) == 4 ? 16 : 8) || BB < NB || BB > 256 || BB % NB != 0)
+    return hipErrorInvalidValue;
   const int pf = npole;   // poles fastest, as in the rect kernels
   dim3 grid((unsigned)((BB / NB) * pf), n_nodes, 1);
-  const bool two = S > 8;
-  if (upper) {
-    if (two)
-      hipLaunchKernelGGL((k_blk_apply<T, 2, true>), grid, dim3(512), 0, st, ft, lvl_nodes, S, N,
-                         xinv, x_stride, xoff, BB, cb, x, out, pf);
-    else
-      hipLaunchKernelGGL((k_blk_apply<T, 1, true>), grid, dim3(512), 0, st, ft, lvl_nodes, S, N,
-                         xinv, x_stride, xoff, BB, cb, x, out, pf);
-  } else {
-    if (two)
-      hipLaunchKernelGGL((k_blk_apply<T, 2, false>), grid, dim3(512), 0, st, ft, lvl_nodes, S, N,
-                         xinv, x_stride, xoff, BB, cb, x, out, pf);
-    else
-      hipLaunchKernelGGL((k_blk_apply<T, 1, false>), grid, dim3(512), 0, st, ft, lvl_nodes, S, N,
-                         xinv, x_stride, xoff, BB, cb, x, out, pf);
+  if constexpr (sizeof(T) == 4) {
+    if (S > 8) {
+      if (upper)
+        blk_apply_go<T, 2, true>(st, grid, real_l, ft, lvl_nodes, S, N, xinv, x_stride, xoff, BB,
+                                 cb, x, out, pf);
+      else
+        blk_apply_go<T, 2, false>(st, grid, real_l, ft, lvl_nodes, S, N, xinv, x_stride, xoff,
+                                  BB, cb, x, out, pf);
+      return hipGetLastError();
+    }
   }
+  if (upper)
+    blk_apply_go<T, 1, true>(st, grid, real_l, ft, lvl_nodes, S, N, xinv, x_stride, xoff, BB, cb,
+                             x, out, pf);
+  else
+    blk_apply_go<T, 1, false>(st, grid, real_l, ft, lvl_nodes, S, N, xinv, x_stride, xoff, BB, cb,
+                              x, out, pf);
   return hipGetLastError();
 }
 
-template hipError_t launch_diag_inverse<float>(hipStream_t, FrontTab, const int32_t *, int, int,
-                                               int, const cpx<float> *, int64_t, cpx<float> *,
-                                               int64_t, const int64_t *, int);
-template hipError_t launch_fwd_child_add<float>(hipStream_t, FrontTab, const int32_t *, int, int,
-                                                int, int64_t, cpx<float> *, const cpx<float> *,
-                                                int64_t);
-template hipError_t launch_blk_apply<float>(hipStream_t, FrontTab, const int32_t *, int, int, int,
-                                            int64_t, const cpx<float> *, int64_t,
-                                            const int64_t *, int, int64_t, bool,
-                                            const cpx<float> *, cpx<float> *);
+#define TEM_INST_INV(T)                                                                          \
+  template hipError_t launch_diag_inverse<T>(hipStream_t, FrontTab, const int32_t *, int, int,   \
+                                             int, const cpx<T> *, int64_t, cpx<T> *, int64_t,    \
+                                             const int64_t *, int);                              \
+  template hipError_t launch_fwd_child_add<T>(hipStream_t, FrontTab, const int32_t *, int, int,  \
+                                              int, int64_t, cpx<T> *, const cpx<T> *, int64_t);  \
+  template hipError_t launch_blk_apply<T>(hipStream_t, FrontTab, const int32_t *, int, int, int, \
+                                          int64_t, const cpx<T> *, int64_t, const int64_t *,     \
+                                          int, int64_t, bool, bool, const cpx<T> *, cpx<T> *);
+TEM_INST_INV(float)
+TEM_INST_INV(double)
+#undef TEM_INST_INV
 
 #define TEM_INST(T)                                                                              \
   template hipError_t launch_fwd_tri<T>(hipStream_t, FrontTab, const int32_t *, int, int, int,    \

@@ -266,6 +266,8 @@ struct tem_ctx {
   DBuf d_xi, d_factor, d_cb0, d_cb1, d_flags;
   DBuf d_xinv;                     // FP32 factors: the wide fronts' block inverses
   bool xinv_ok = false;
+  DBuf d_nxinv;                    // the same for the nodal factor (FP64, real)
+  bool nxinv_ok = false;
   int n_groups = 0, group_size = 0;
   int n_tiny = 0;
   double factor_ms = 0.0, solve_ms = 0.0;
@@ -476,6 +478,7 @@ void drop_factors(tem_ctx *c) {
   c->nodal_ready = false;
   c->factored = false;
   c->xinv_ok = false;
+  c->nxinv_ok = false;
   c->solved = false;
   drop_graphs(c);
 }
@@ -1055,10 +1058,19 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
   // solution going through t (free during the forward pass, and after
   // bwd init in the backward pass) so that the launch that uses it can
   // write it into x
+  // (the nodal factor's, shared by all its virtual poles, for up to eight
+  // right-hand sides)
   const cpx<T> *XI = nullptr;
-  if constexpr (sizeof(T) == 4)
-    if (&mf == &c->ed && c->xinv_ok && mf.x_bb == BB && !real_l)
+  int64_t xs = 0;   // elements per pole of the inverses
+  if constexpr (sizeof(T) == 4) {
+    if (&mf == &c->ed && c->xinv_ok && mf.x_bb == BB && !real_l) {
       XI = c->d_xinv.as<cpx<T>>() + (int64_t)p0 * mf.x_stride;
+      xs = mf.x_stride;
+    }
+  } else {
+    if (&mf == &c->nd && c->nxinv_ok && mf.x_bb == BB && real_l && f_stride == 0 && S <= 8)
+      XI = c->d_nxinv.as<cpx<T>>();
+  }
   const int64_t *xoff = mf.d_xoff.as<int64_t>();
   for (int L = nl - 1; L >= 0; --L) {
     const LevelInfo &li = mf.levels[L];
@@ -1068,18 +1080,15 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
                                0, (int64_t)1 << 40, real_l),
              "fwd tri");
     } else if (XI) {
-      if constexpr (sizeof(T) == 4) {
-        HIPCHK(launch_fwd_child_add<T>(st, ft, ln, li.n, npole, S, N, x, W[(L + 1) & 1], ws),
-               "fwd child add");
-        for (int64_t cb = 0; cb < li.max_k; cb += BB) {
-          HIPCHK(launch_blk_apply<T>(st, ft, ln, li.n, npole, S, N, XI, mf.x_stride, xoff,
-                                     (int)BB, cb, false, x, t),
-                 "fwd block inverse");
-          HIPCHK(launch_fwd_rows<T>(st, ft, ln, li.n,
-                                    (int)std::max<int64_t>(0, li.max_k - cb - BB), npole, S, N, F,
-                                    f_stride, x, cb, BB, real_l, t),
-                 "fwd rows");
-        }
+      HIPCHK(launch_fwd_child_add<T>(st, ft, ln, li.n, npole, S, N, x, W[(L + 1) & 1], ws),
+             "fwd child add");
+      for (int64_t cb = 0; cb < li.max_k; cb += BB) {
+        HIPCHK(launch_blk_apply<T>(st, ft, ln, li.n, npole, S, N, XI, xs, xoff, (int)BB, cb,
+                                   false, real_l, x, t),
+               "fwd block inverse");
+        HIPCHK(launch_fwd_rows<T>(st, ft, ln, li.n, (int)std::max<int64_t>(0, li.max_k - cb - BB),
+                                  npole, S, N, F, f_stride, x, cb, BB, real_l, t),
+               "fwd rows");
       }
     } else {
       for (int64_t cb = 0; cb < li.max_k; cb += BB) {
@@ -1112,10 +1121,9 @@ tem_status sweep_levels(tem_ctx *c, MF &mf, const cpx<T> *F, int64_t f_stride, i
       for (int64_t bb = nbb - 1; bb >= 0; --bb) {
         const int64_t cb = bb * BB;
         if (XI) {
-          if constexpr (sizeof(T) == 4)
-            HIPCHK(launch_blk_apply<T>(st, ft, ln, li.n, npole, S, N, XI, mf.x_stride, xoff,
-                                       (int)BB, cb, true, x, t),
-                   "bwd block inverse");
+          HIPCHK(launch_blk_apply<T>(st, ft, ln, li.n, npole, S, N, XI, xs, xoff, (int)BB, cb,
+                                     true, real_l, x, t),
+                 "bwd block inverse");
         } else {
           HIPCHK(launch_bwd_tri<T>(st, ft, ln, li.n, npole, S, N, F, f_stride, x, t, N * S, cb,
                                    BB, 0, real_l),
@@ -1562,6 +1570,31 @@ tem_status setup_nodal(tem_ctx *c, int leaf) {
 }
 
 // assemble G^T M G for the current sigma and factor it (FP64)
+// Offsets of the explicit inverses of the wide fronts' BB-column diagonal
+// blocks (levels with max_k > BB, the ones the sweeps may walk in blocks):
+// per front 2 ((nbb - 1) BB^2 + w_last^2) elements (each block and its
+// transpose, w_last the width of the last block), per pole.
+tem_status prepare_xinv(tem_ctx *c, MF &mf, int BB) {
+  if (mf.x_bb == BB && mf.d_xoff.p) return TEM_OK;
+  std::vector<int64_t> off(std::max<size_t>(mf.sym.nodes.size(), 1), 0);
+  int64_t tot = 0;
+  for (const LevelInfo &li : mf.levels) {
+    if (li.max_k <= BB) continue;
+    for (int s : li.nodes) {
+      const SymNode &nd = mf.sym.nodes[s];
+      const int64_t k = nd.last - nd.first;
+      if (k <= 0) continue;
+      const int64_t nbb = (k + BB - 1) / BB, wl = k - (nbb - 1) * BB;
+      off[s] = tot;
+      tot += 2 * ((nbb - 1) * (int64_t)BB * BB + wl * wl);
+    }
+  }
+  HIPCHK(upload(mf.d_xoff, off, c->stream), "upload block-inverse offsets");
+  mf.x_stride = tot;
+  mf.x_bb = BB;
+  return TEM_OK;
+}
+
 tem_status factor_nodal(tem_ctx *c) {
   MF &nd = c->nd;
   c->nodal_ready = false;
@@ -1602,6 +1635,15 @@ tem_status factor_nodal(tem_ctx *c) {
                                  c->d_sigma.as<double>(), c->d_Ln.as<double>()),
            "nodal assembly");
   }
+  // the nodal factor's wide diagonal blocks get explicit inverses too (one
+  // real factor for every pole: one region)
+  c->nxinv_ok = false;
+  const bool xinv = c->sweep_bb <= 256;
+  if (xinv) {
+    TRY(prepare_xinv(c, nd, (int)c->sweep_bb));
+    HIPCHK(c->d_nxinv.alloc(sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.x_stride, 1)),
+           "alloc nodal block inverses");
+  }
   HIPCHK(c->d_nfactor.alloc(sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.pole_stride, 1)),
          "alloc nodal factor");
   const size_t cbb = sizeof(cpx<double>) * (size_t)std::max<int64_t>(nd.cb_stride, 1);
@@ -1615,33 +1657,19 @@ tem_status factor_nodal(tem_ctx *c) {
                                        c->d_ncb0.as<cpx<double>>(), c->d_ncb1.as<cpx<double>>());
   c->profile = prof;
   TRY(fs);
+  if (xinv && nd.x_stride > 0) {
+    const FrontTab ft = front_tab(nd, 0);
+    for (const LevelInfo &li : nd.levels)
+      if (li.max_k > c->sweep_bb)
+        HIPCHK(launch_diag_inverse<double>(st, ft, lvl_ptr(nd, li), li.n, li.max_k, 1,
+                                           c->d_nfactor.as<cpx<double>>(), 0,
+                                           c->d_nxinv.as<cpx<double>>(), 0,
+                                           nd.d_xoff.as<int64_t>(), (int)c->sweep_bb),
+               "nodal diagonal-block inverses");
+    c->nxinv_ok = true;
+  }
   // complete once st reaches this point (the caller orders later work after it)
   c->nodal_ready = true;
-  return TEM_OK;
-}
-
-// Offsets of the explicit inverses of the wide fronts' BB-column diagonal
-// blocks (levels with max_k > BB, the ones the FP32 sweeps walk in blocks):
-// per front 2 ((nbb - 1) BB^2 + w_last^2) elements (each block and its
-// transpose, w_last the width of the last block), per pole.
-tem_status prepare_xinv(tem_ctx *c, MF &mf, int BB) {
-  if (mf.x_bb == BB && mf.d_xoff.p) return TEM_OK;
-  std::vector<int64_t> off(std::max<size_t>(mf.sym.nodes.size(), 1), 0);
-  int64_t tot = 0;
-  for (const LevelInfo &li : mf.levels) {
-    if (li.max_k <= BB) continue;
-    for (int s : li.nodes) {
-      const SymNode &nd = mf.sym.nodes[s];
-      const int64_t k = nd.last - nd.first;
-      if (k <= 0) continue;
-      const int64_t nbb = (k + BB - 1) / BB, wl = k - (nbb - 1) * BB;
-      off[s] = tot;
-      tot += 2 * ((nbb - 1) * (int64_t)BB * BB + wl * wl);
-    }
-  }
-  HIPCHK(upload(mf.d_xoff, off, c->stream), "upload block-inverse offsets");
-  mf.x_stride = tot;
-  mf.x_bb = BB;
   return TEM_OK;
 }
 

@@ -174,11 +174,13 @@ hipError_t launch_fwd_child_add(hipStream_t st, FrontTab ft, const int32_t *lvl_
                                 int npole, int S, int64_t N, cpx<T> *x, const cpx<T> *w_child,
                                 int64_t w_stride);
 // out rows [cb, cb + w) = X_b x rows [cb, cb + w) (upper: X_b^T), b = cb / BB,
-// for every front and pole of a level (out and x: [pole][N][S])
+// for every front and pole of a level (out and x: [pole][N][S]; x_stride 0:
+// one set of inverses for every pole slot; real_l: real inverses; S <= 16,
+// FP64 S <= 8)
 template <typename T>
 hipError_t launch_blk_apply(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes, int n_nodes,
                             int npole, int S, int64_t N, const cpx<T> *xinv, int64_t x_stride,
-                            const int64_t *xoff, int BB, int64_t cb, bool upper,
+                            const int64_t *xoff, int BB, int64_t cb, bool upper, bool real_l,
                             const cpx<T> *x, cpx<T> *out);
 
 // real_l: the factor's imaginary parts are zero (FP64 only; skips the
