@@ -45,8 +45,10 @@
  *     "f64" | "both" | "none" [f32]; TEM_SWEEP_BLOCK column block of wide
  *     fronts in the sweeps, a multiple of 32 [256]; TEM_SWEEP_BIG_LIMIT
  *     fronts x poles below which an FP64 level counts as wide [1024];
- *     TEM_GRAPHS replay the all-pole sweep from a HIP graph [1].  The
- *     autotuner (tem_autotune) overrides the update tile per level.
+ *     TEM_GRAPHS replay the all-pole sweep from a HIP graph [1].  With FP32
+ *     factors and TEM_SWEEP_BLOCK at most 256 the wide fronts' diagonal
+ *     blocks are inverted once per factorisation and applied as products.
+ *     The autotuner (tem_autotune) overrides the update tile per level.
  *   Errors: a negative tem_status; tem_last_error() describes it.  After an
  *     error the context keeps the last stage that completed.
  *   State machine: create -> assemble -> analyse -> factor_poles ->
