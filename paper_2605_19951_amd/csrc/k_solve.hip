@@ -285,8 +285,8 @@ hipError_t launch_fwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
 // products of the complex one: Re(L y) = Lr Re y - Li Im y, Im(L y) =
 // Lr Im y + Li Re y.  Operand lane l carries row (or output column) l % 16
 // and depth l / 16.  Each wave owns 32 rows and walks all k columns on its
-// own (no LDS, no barriers), a chunk of columns at a time (32 in FP32, 16 in
-// FP64), loading the next chunk while the current one is multiplied.
+// own (no LDS, no barriers), a chunk of 16 columns at a time
+// (FP32 and FP64), loading the next chunk while the current one is multiplied.
 // NBK = 1 for S <= 8 right-hand sides, 2 for S <= 16.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -297,7 +297,9 @@ struct Mfma16;
 template <>
 struct Mfma16<float> {
   using acc_t = floatx4;
-  static constexpr int KC = 32;   // columns per chunk
+  // columns per chunk: 16 keeps two chunks of operands in 75 registers (six
+  // waves per SIMD; 32 columns needed 112, four waves)
+  static constexpr int KC = 16;
   __device__ static acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
