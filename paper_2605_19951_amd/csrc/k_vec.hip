@@ -87,59 +87,22 @@ inline unsigned xcd_grid(int64_t tot, int block) {
   return (unsigned)(8 * ((nblk + 7) / 8));
 }
 
-// r = f - (K - xi_p M) x (mode 1) or y = (K - xi_p M) x (mode 0) for every
-// pole slot p and right-hand side, FP64.  One wave per row: the row's
-// entries and columns are wave-uniform (scalar loads, read once for all
-// poles) and the lanes take (right-hand side, pole) pairs, 64 / S poles at
-// a time; consecutive waves take consecutive rows and each XCD a contiguous
-// eighth of them, so that the x rows a row gathers are shared in cache by
-// its neighbours for all poles at once.
-__global__ __launch_bounds__(256) void k_residual(int64_t N, int npole, int S,
-                                                  const int64_t *rowptr, const int32_t *col,
-                                                  const double *Kv, const double *Mv,
-                                                  const double *xi, Seg sg, const double *f_real,
-                                                  const cpx<double> *f_cplx,
-                                                  const cpx<double> *x, cpx<double> *r, int mode) {
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t q = xcd_block((N + 3) / 4) * 4 + wv;
-  if (q >= N) return;
-  const int slots = 64 / S, c = lane % S, ps = lane / S;
-  const int64_t xb = 2 * (int64_t)seg_find(sg, q) * sg.stride;
-  const int64_t t0 = rowptr[q], t1 = rowptr[q + 1];
-  for (int p0 = 0; p0 < npole; p0 += slots) {
-    const int p = p0 + ps;
-    const int pc = min(p, npole - 1);
-    const double xr = xi[xb + 2 * pc], xim = xi[xb + 2 * pc + 1];
-    const cpx<double> *X = x + (int64_t)pc * N * S + c;
-    double ar = 0.0, ai = 0.0;
-#pragma unroll 4
-    for (int64_t t = x ? t0 : t1; t < t1; ++t) {
-      const double kv = Kv[t], mv = Mv[t];
-      const cpx<double> v = X[(int64_t)col[t] * S];
-      // (K - xi M) v, xi M v = (xr + i xim) mv v
-      const double sr = kv - xr * mv, si = -xim * mv;
-      ar += sr * v.re - si * v.im;
-      ai += sr * v.im + si * v.re;
-    }
-    if (ps >= slots || p >= npole) continue;
-    cpx<double> out;
-    if (mode == 0) {
-      out.re = ar;
-      out.im = ai;
-    } else {
-      double fr = 0.0, fi = 0.0;
-      if (f_cplx) {
-        const cpx<double> f = f_cplx[((int64_t)p * N + q) * S + c];
-        fr = f.re;
-        fi = f.im;
-      } else if (f_real) {
-        fr = f_real[q * S + c];
-      }
-      out.re = fr - ar;
-      out.im = fi - ai;
-    }
-    r[((int64_t)p * N + q) * S + c] = out;
+// r = f for every pole slot and right-hand side: the residual of x = 0, the
+// start of a refined solve.  f real [N][S] (the same for every pole) or
+// complex [pole][N][S]; r [pole][N][S].
+__global__ __launch_bounds__(256) void k_residual_init(int64_t N, int npole, int S,
+                                                       const double *f_real,
+                                                       const cpx<double> *f_cplx,
+                                                       cpx<double> *r) {
+  const int64_t NS = N * S, tot = (int64_t)npole * NS;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot;
+       i += (int64_t)gridDim.x * 256) {
+    cpx<double> v = {0.0, 0.0};
+    if (f_cplx)
+      v = f_cplx[i];
+    else if (f_real)
+      v.re = f_real[i % NS];
+    r[i] = v;
   }
 }
 
@@ -266,13 +229,14 @@ hipError_t launch_residual_blk(hipStream_t st, int64_t N, int npole, int S, int6
   return hipGetLastError();
 }
 
-hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
-                           const int32_t *col, const double *Kv, const double *Mv,
-                           const double *xi, Seg sg, const double *f_real,
-                           const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r) {
-  if (N <= 0 || npole <= 0 || S < 1 || S > 64) return N <= 0 || npole <= 0 ? hipSuccess : hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_residual, dim3(xcd_grid(N * 64, 256)), dim3(256), 0, st, N, npole, S,
-                     rowptr, col, Kv, Mv, xi, sg, f_real, f_cplx, x, r, 1);
+hipError_t launch_residual_init(hipStream_t st, int64_t N, int npole, int S,
+                                const double *f_real, const cpx<double> *f_cplx, cpx<double> *r) {
+  if (N <= 0 || npole <= 0) return hipSuccess;
+  if (S < 1 || !r) return hipErrorInvalidValue;
+  const int64_t tot = (int64_t)npole * N * S;
+  const int64_t blocks = std::min<int64_t>((tot + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_residual_init, dim3((unsigned)blocks), dim3(256), 0, st, N, npole, S,
+                     f_real, f_cplx, r);
   return hipGetLastError();
 }
 

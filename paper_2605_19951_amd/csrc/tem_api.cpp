@@ -1401,10 +1401,7 @@ tem_status refine_block(tem_ctx *c, const double *f_real, const cpx<double> *f_c
                                    f_real, f_cplx ? f_cplx + o : nullptr, xv + o, r + o),
                "residual");
       else   // x = 0: r = f
-        HIPCHK(launch_residual(st, N, pr.n, S, c->ed.d_rowptr.as<int64_t>(),
-                               c->ed.d_col.as<int32_t>(), c->d_K.as<double>(), c->d_M.as<double>(),
-                               xi + 2 * pr.p0, rs, f_real, f_cplx ? f_cplx + o : nullptr, nullptr,
-                               r + o),
+        HIPCHK(launch_residual_init(st, N, pr.n, S, f_real, f_cplx ? f_cplx + o : nullptr, r + o),
                "residual");
     }
     return TEM_OK;

@@ -204,13 +204,10 @@ hipError_t launch_bwd_tri(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes,
                           int init, bool real_l = false);
 
 // ------------------------------------------------------- vector kernels
-// Residual r = f - (K - xi_p M) x for all poles p and rhs s (FP64);
-// x, r: [pole][N][S] complex double (x = NULL: x = 0, r = f); f: [N][S]
-// real (new ordering) or, with f_cplx, [pole][N][S] complex.
-hipError_t launch_residual(hipStream_t st, int64_t N, int npole, int S, const int64_t *rowptr,
-                           const int32_t *col, const double *Kv, const double *Mv,
-                           const double *xi, Seg row_seg, const double *f_real,
-                           const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r);
+// r = f for all poles p and rhs s (the residual of x = 0, FP64): f [N][S]
+// real (new ordering) or, with f_cplx, [pole][N][S] complex; r [pole][N][S].
+hipError_t launch_residual_init(hipStream_t st, int64_t N, int npole, int S,
+                                const double *f_real, const cpx<double> *f_cplx, cpx<double> *r);
 
 // Row blocks of the FP64 residual (launch_residual_blk): at most RB_ROWS
 // consecutive rows per block whose columns span at most RB_HALO distinct
