@@ -10,7 +10,9 @@
 
 namespace tem {
 
-constexpr int RT = 64;   // rows per LDS tile (rectangle kernels)
+// rows per LDS tile of the backward rectangle kernel (32: 64 registers,
+// eight waves per SIMD; 64 rows took 92, five)
+constexpr int RT = 32;
 constexpr int RTT = 32;  // rows per LDS tile (triangle kernels, keeps LDS under 64 KiB)
 
 // Pointer to column c's data such that element (r, c) is colptr[r].
@@ -531,13 +533,13 @@ hipError_t launch_fwd_rows(hipStream_t st, FrontTab ft, const int32_t *lvl_nodes
 
 // ----------------------------------------------------------- backward rect
 // t[first + jb + l] = sum_a L(k + a, jb + l) x[U_s[a]] for one column block
-// On the matrix cores: the 64-row tiles of the panel and the gathered x
+// On the matrix cores: the RT-row tiles of the panel and the gathered x
 // rows are staged through LDS (coalesced loads from clamped positions,
 // prefetched into registers one tile ahead, masked when written); the
 // products are 16 x 16 x 4 MFMAs whose rows are the block's columns and
 // whose 16 result columns hold Re x and Im x of eight right-hand sides (as
 // in the forward rect).  Wave w takes columns 16 (w % 2) .. + 15 and rows
-// 32 (w / 2) .. + 31 of every tile; the two row halves are summed through
+// (RT / 2) (w / 2) .. of every tile; the two row halves are summed through
 // LDS at the end.  x rows past the tile are staged as zeros (a zero panel
 // entry times stale LDS could be NaN).  With the reduction running down the
 // column-major panel, MFMA operands loaded straight from HBM would span 16
@@ -598,9 +600,10 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
     r1[nb] = acc_t{0, 0, 0, 0};
     r2[nb] = acc_t{0, 0, 0, 0};
   }
-  // register prefetch of the next 64-row tile: 8 panel elements and up to
-  // 4 x values per thread (clamped in-bounds positions; masked in LDS)
-  cpx<T> pre[8], px0, px1, px2, px3;
+  // register prefetch of the next RT-row tile: NP panel elements and two x
+  // values per thread (clamped in-bounds positions; masked in LDS)
+  constexpr int NP = RT * NB / 256;   // panel elements per thread and tile
+  cpx<T> pre[NP], px0, px1;
   auto xval = [&](int q, int64_t ac, int na) -> cpx<T> {
     const int idx = tid + 256 * q;
     const int i = min(idx / S, na - 1), c = idx % S;
@@ -610,21 +613,19 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
   auto fetch = [&](int64_t ac) {
     const int na = (int)min((int64_t)RT, nr - ac);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NP; ++q) {
       const int idx = tid + 256 * q, i = min(idx % RT, na - 1), l = min(idx / RT, w - 1);
       pre[q] = Lc[(int64_t)l * ld + row0 + ac + i];
     }
     px0 = xval(0, ac, na);
     px1 = xval(1, ac, na);
-    px2 = xval(2, ac, na);
-    px3 = xval(3, ac, na);
   };
   if (nr > 0) fetch(0);
   for (int64_t ac = 0; ac < nr; ac += RT) {
     const int na = (int)min((int64_t)RT, nr - ac);
     lds_barrier();   // the previous tile's readers are done
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NP; ++q) {
       const int idx = tid + 256 * q;
       const bool ok = idx % RT < na && idx / RT < w;
       Lt[idx / RT][idx % RT] = ok ? pre[q] : czero<T>();
@@ -638,13 +639,11 @@ __global__ __launch_bounds__(256) void k_bwd_rect_mfma(FrontTab ft, const int32_
     };
     xput(0, px0);
     xput(1, px1);
-    xput(2, px2);
-    xput(3, px3);
     lds_barrier();
     if (ac + RT < nr) fetch(ac + RT);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = rh * 32 + 4 * q + ld4;
+    for (int q = 0; q < RT / 8; ++q) {
+      const int i = rh * (RT / 2) + 4 * q + ld4;
       const cpx<T> a = Lt[mb * 16 + lr][i];
 #pragma unroll
       for (int nb = 0; nb < NBK; ++nb) {
