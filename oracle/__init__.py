@@ -15,6 +15,9 @@ the paper computes:
                 structure of the shifted matrices (the structure one
                 factorisation of each shifted matrix needs, shared by all
                 poles);
+* ``tet``       the same operators with lowest-order edge elements on
+                tetrahedra, and the RT0 smoothness operator with a lumped
+                (diagonal) mass (section "Regularization");
 * ``tem``       shifted solves g_i = (K - xi_i M)^{-1} f (Algorithm 1),
                 time assembly u(t_j) = 2 Re sum_i alpha_i^[j] g_i, data
                 d_j = Q u(t_j), Jv and J^T w (section "Jacobian
