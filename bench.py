@@ -16,8 +16,11 @@ FP64 oracle on a bounded sample.
 Before the timed steps of each precision the update kernels are autotuned
 per tree level (tem_autotune; untimed set-up, like assembly and analysis).
 
+``--tet`` runs the same step on a jittered tetrahedral mesh instead (both
+precisions) and prints that workload's own line.
+
 Usage: python bench.py [--gpus 1] [--steps 1] [--warmup 1] [--no-cpu-baseline]
-                       [--no-autotune] [--no-ragged] [--fp32-only]
+                       [--no-autotune] [--no-ragged] [--fp32-only] [--tet [--tet-cubes 32]]
 """
 from __future__ import annotations
 
@@ -277,6 +280,98 @@ def inversion_phase(torch, dev, prec, max_gn=25, lsqr_iters=20, lambda0=10.0,
 ORACLE_RECORD = os.path.join(ROOT, "profiles", "oracle_hex64_pole_cpu.json")
 
 
+def tet_phase(torch, dev, steps, warmup, n=32):
+    """The same step on a jittered tetrahedral mesh (n^3 cubes, six
+    tetrahedra each; 8 loops, 16 poles, 60 times, 4 x 4 receivers) in both
+    precisions: M(sigma) re-assembled on the device, all poles factored,
+    forward, J v, J^T w.  Returns that workload's JSON line (value: the
+    FP32+IR factor+solve seconds, as for the hexahedral line)."""
+    import numpy as np
+    from paper_2605_19951_amd import FP32_IR, FP64, Tem
+    from tem_inputs.tet import tet_workload
+    wl = tet_workload(n, n // 8, h=25.0, S=8, m=16, K=60, g=4, seed=51, name="tet%d" % n)
+    me = wl.mesh
+    t = Tem(0)
+    sigma = torch.tensor(wl.sigma, device=dev)
+    t.assemble_tet(me.xyz, me.tets, wl.mu, sigma, wl.params)
+    ta = time.perf_counter()
+    info = t.analyse()
+    analyse_s = time.perf_counter() - ta
+    F = torch.tensor(wl.F.T.copy(), device=dev)
+    rng = np.random.default_rng(7)
+    v = torch.tensor(rng.standard_normal(len(wl.params)), device=dev)
+    w = torch.tensor(rng.standard_normal((wl.S, len(wl.poles.t), wl.rx.n)), device=dev)
+    d = torch.zeros((wl.S, len(wl.poles.t), wl.rx.n), dtype=torch.float64, device=dev)
+    jv = torch.zeros_like(d)
+    jtw = torch.zeros(len(wl.params), dtype=torch.float64, device=dev)
+    m = torch.log(sigma[torch.tensor(wl.params, device=dev, dtype=torch.long)])
+    phases, outs = {}, {}
+    for name, prec in (("fp32_ir", FP32_IR), ("fp64", FP64)):
+        rec = []
+        for it in range(warmup + steps):
+            timed = it >= warmup
+            t.set_profiling(timed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t.set_model(m)            # M(sigma) re-assembled on the device
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            t.factor_poles(wl.poles.xi, prec)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            ir = t.forward(F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            t.jvp(v, jv)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            t.vjp(w, jtw)
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            st = t.stats()
+            if timed:
+                rec.append(dict(assemble=t1 - t0, factor=t2 - t1, forward=t3 - t2, jvp=t4 - t3,
+                                vjp=t5 - t4, solves=int(ir["iters"].max()), stats=st))
+            print("# tet %s step %d: assemble %.3f factor %.3f forward %.3f jvp %.3f vjp %.3f s"
+                  % (name, it, t1 - t0, t2 - t1, t3 - t2, t4 - t3, t5 - t4), file=sys.stderr,
+                  flush=True)
+        med = lambda k: sorted(r[k] for r in rec)[len(rec) // 2]  # noqa: E731
+        st = rec[-1]["stats"]
+        phases[name] = dict(
+            assemble_s=med("assemble"), factor_s=med("factor"), forward_s=med("forward"),
+            jvp_s=med("jvp"), vjp_s=med("vjp"), factor_solve_s=med("factor") + med("forward"),
+            jtv_per_s=1.0 / med("vjp"), ir_solves=rec[-1]["solves"],
+            factor_gb=st["factor_bytes"] / 1e9, update_ms=st["update_ms"],
+            update_flops=st["update_flops"], update_launches=st["update_launches"],
+            sweep_ms=st["sweep_ms"], sweep_bytes=st["sweep_bytes"])
+        outs[name] = (d.cpu().numpy(), jtw.cpu().numpy())
+    t.close()
+    acc = dict(data_rel_fp32_vs_fp64=float(np.linalg.norm(outs["fp32_ir"][0] - outs["fp64"][0])
+                                           / np.linalg.norm(outs["fp64"][0])),
+               jtw_rel_fp32_vs_fp64=float(np.linalg.norm(outs["fp32_ir"][1] - outs["fp64"][1])
+                                          / np.linalg.norm(outs["fp64"][1])))
+    r32 = phases["fp32_ir"]
+    ach = r32["update_flops"] / (r32["update_ms"] * 1e-3) if r32["update_ms"] > 0 else 0.0
+    bw = r32["sweep_bytes"] / (r32["sweep_ms"] * 1e-3) if r32["sweep_ms"] > 0 else 0.0
+    return dict(
+        metric="all-pole factor+solve s & J\u1d40v/s on a tetrahedral edge mesh, FP32+IR vs FP64",
+        value=r32["factor_solve_s"], unit="s", n_gpus=1, steps=steps, warmup=warmup,
+        ms_per_step=1e3 * sum(r32[k] for k in ("assemble_s", "factor_s", "forward_s", "jvp_s",
+                                                 "vjp_s")),
+        higher_is_better=False, scaling="weak", vs_baseline=None,
+        dtype="c64 factors + f64 refinement", data="synthetic",
+        config=dict(workload=wl.name, cubes="%dx%dx%d" % (n, n, n), tets=me.n_tets,
+                    n_unknowns=info["n_unknowns"], poles=len(wl.poles.xi), sources=wl.S,
+                    times=len(wl.poles.t), receivers=wl.rx.n, params=len(wl.params),
+                    flops_per_pole=info["flops_per_pole"], max_front=info["max_front"],
+                    analyse_s=analyse_s),
+        phases=phases, accuracy=acc,
+        roofline=dict(bound="mfma", kernel="k_front_update<float>", achieved=ach / 1e12,
+                      peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=ach / PEAK_FP32, traffic=None),
+        sweep=dict(bound="hbm", achieved=bw / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                   frac=bw / PEAK_HBM))
+
+
 def cpu_baseline():
     """The FP64 oracle on the host, as it stands: factor + solve of pole 0 x
     8 sources on the 32^3 sample mesh of the same generator, timed here
@@ -331,6 +426,9 @@ def main():
                     help="only run the four-block Gauss-Newton inversion and the runtime-model "
                          "fit (prints its own JSON line)")
     ap.add_argument("--inversion-precision", type=int, default=1)
+    ap.add_argument("--tet", action="store_true",
+                    help="only run the tetrahedral-mesh workload (prints its own JSON line)")
+    ap.add_argument("--tet-cubes", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the pole-sharded multi-GPU path is not part of this "
@@ -349,6 +447,9 @@ def main():
         return
     if args.inversion:
         print(json.dumps(inversion_phase(torch, dev, args.inversion_precision)), flush=True)
+        return
+    if args.tet:
+        print(json.dumps(tet_phase(torch, dev, args.steps, args.warmup, args.tet_cubes)), flush=True)
         return
     wl = ti.workload(2)
     me = wl.mesh

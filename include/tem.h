@@ -184,6 +184,59 @@ tem_status tem_symbolic_host(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_ma
                              tem_symbolic_info *info, int32_t *perm, int32_t *sn_ptr,
                              int32_t *sn_parent, int64_t *rows_ptr, int32_t *rows);
 
+/* ---------------------------------------------------- tetrahedral meshes
+ * The paper's discretisation (section "Spatial discretization": lowest-order
+ * curl-conforming elements on tetrahedra) and regulariser (section
+ * "Regularization": RT0 smoothness with a lumped mass).  A context holds
+ * either a hexahedral mesh (tem_assemble) or a tetrahedral one; every
+ * single-mesh call after assembly works on either, in both precisions (the
+ * gradient-space correction of TEM_FP32_IR uses the interior nodes of the
+ * tetrahedra: G^T M G = sum_T sigma_T |T| grad l_i . grad l_j); batches are
+ * hexahedral only.
+ *
+ * Canonical edges of a tetrahedral mesh are the distinct node pairs (a, b),
+ * a < b, of its tetrahedra sorted lexicographically and oriented a -> b;
+ * sources (tem_forward's F, tem_solve_poles) and receiver columns use this
+ * numbering.  The unknowns are the edges on no boundary face (a face of one
+ * tetrahedron only), in canonical order. */
+
+typedef struct {
+  int64_t n_nodes;      /* >= 4 */
+  int64_t n_tets;       /* >= 1, at most 2^31 / 36 - 1 */
+  const double *xyz;    /* host, 3 * n_nodes coordinates (m), finite */
+  const int32_t *tets;  /* host, 4 * n_tets node ids, distinct per tetrahedron;
+                           every tetrahedron of nonzero volume (either
+                           orientation); a face belongs to at most two */
+  double mu;            /* magnetic permeability (H/m), > 0 */
+} tem_tet_mesh;
+
+/* Assemble K (1/mu int curl N_a . curl N_b) and M (int sigma N_a . N_b)
+ * over the unknown edges on the device, FP64: element matrices per
+ * tetrahedron in one kernel, then a gather of the pattern entries.
+ *   sigma_tets   device, n_tets doubles (S/m), > 0 and finite
+ *   n_params     P (m = ln sigma on these tetrahedra); 0 disables jvp/vjp
+ *   param_tets   host, P distinct tetrahedron ids.  Copied.
+ * The mesh arrays are copied.  The regulariser of tem_gn_step and
+ * tem_invert is then R = diag(d)^(-1/2) D^T: one row (m_b - m_a) / sqrt(d_f)
+ * per face shared by two parameter tetrahedra a < b (faces in increasing
+ * order of their sorted node triple), d_f the diagonal of the RT0 mass of
+ * the face's unit-flux function over both tetrahedra, so R^T R =
+ * D diag(M_div)^-1 D^T with the lumped M_div (no flux through the other
+ * faces).  Errors: TEM_EINVAL for invalid meshes (message names the
+ * defect), parameters or conductivities. */
+tem_status tem_assemble_tet(tem_ctx *ctx, const tem_tet_mesh *mesh, const double *sigma_tets,
+                            int32_t n_params, const int32_t *param_tets);
+
+/* Host-only symbolic analysis of a tetrahedral mesh (the ordering
+ * tem_analyse computes for it): nested dissection of the unknown graph
+ * (unknowns sharing a tetrahedron), each subgraph of more than
+ * 3 * leaf_max_cells^3 unknowns split at the median edge midpoint along its
+ * longest extent, the separator being the smaller one-sided boundary.
+ * Outputs as tem_symbolic_host (nnz_a is that of the unknown graph). */
+tem_status tem_symbolic_tet_host(const tem_tet_mesh *mesh, int32_t leaf_max_cells,
+                                 tem_symbolic_info *info, int32_t *perm, int32_t *sn_ptr,
+                                 int32_t *sn_parent, int64_t *rows_ptr, int32_t *rows);
+
 /* ---------------------------------------------------------- factorisation */
 
 typedef struct {

@@ -13,7 +13,7 @@ LIB = os.path.join(OUT_DIR, "libtem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("TEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["host_mesh.cpp", "tem_api.cpp", "k_factor.hip", "k_solve.hip", "k_vec.hip"]
+SOURCES = ["host_mesh.cpp", "host_tet.cpp", "tem_api.cpp", "k_factor.hip", "k_solve.hip", "k_vec.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]

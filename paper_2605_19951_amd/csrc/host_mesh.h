@@ -88,3 +88,61 @@ void build_pattern(const MeshTopo &mt, const std::vector<int32_t> &perm, Pattern
                    bool nodes = false);
 
 }  // namespace tem
+
+namespace tem {
+
+// Tetrahedral mesh topology.  Canonical edges are the distinct node pairs
+// (a, b), a < b, sorted lexicographically and oriented a -> b; the unknowns
+// are the edges on no boundary face (a face of one tetrahedron only), in
+// canonical order.
+struct TetTopo {
+  int64_t n_nodes = 0, n_tets = 0, n_edges = 0, n_unknowns = 0;
+  std::vector<double> xyz;           // 3 per node
+  std::vector<int32_t> tets;         // 4 per tetrahedron
+  std::vector<int32_t> edges;        // 2 per canonical edge
+  std::vector<int32_t> tet_edges;    // 6 per tetrahedron, local edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)
+  std::vector<int8_t> tet_signs;     // +1 where the local direction i -> j is the canonical one
+  std::vector<int32_t> unk_of_edge;  // canonical edge -> unknown or -1
+  std::vector<int32_t> edge_of_unk;
+  // faces shared by two tetrahedra: the two tetrahedra and, for each, the
+  // local index of the node opposite the face
+  std::vector<int32_t> iface_tets;   // 2 per interior face
+  std::vector<int8_t> iface_opp;     // 2 per interior face
+  // unknown adjacency (unknowns sharing a tetrahedron, itself included), CSR
+  // in unknown order with sorted columns
+  std::vector<int64_t> adj_ptr;
+  std::vector<int32_t> adj;
+  // interior nodes (on no boundary face; their hat functions' gradients
+  // span the curl-free part of the unknown space) and their adjacency
+  // (interior nodes sharing a tetrahedron, itself included)
+  int64_t n_inodes = 0;
+  std::vector<int32_t> unk_of_node, node_of_unk;
+  std::vector<int64_t> nadj_ptr;
+  std::vector<int32_t> nadj;
+  // Build from host arrays; returns an error text ("" on success).
+  std::string init(const double *xyz, const int32_t *tets, int64_t n_nodes, int64_t n_tets);
+};
+
+// Diagonal of the 4x4 lowest-order Raviart-Thomas mass matrix of one
+// tetrahedron (x: 12 coordinates), face functions of unit flux, the face
+// opposite local node p first-to-last.
+void tet_rt0_diag(const double x[12], double out[4]);
+
+// Nested dissection of a graph with vertex coordinates and the supernodal
+// symbolic factorisation (the separator of each split is one supernode).
+// Each subgraph of more than leaf_max vertices is split at the median of its
+// longest coordinate extent; the separator is the smaller of the two sets of
+// vertices on one side with a neighbour on the other.  Columns within a
+// supernode are in increasing vertex order; supernodes in post-order.
+//   adj_ptr/adj: symmetric adjacency (self loops allowed), coords: 3 per vertex.
+void analyse_graph(int64_t n, const std::vector<int64_t> &adj_ptr, const std::vector<int32_t> &adj,
+                   const std::vector<double> &coords, int64_t leaf_max, Symbolic &sym);
+
+// CSR pattern of the adjacency in the ordering perm (perm[new] = vertex);
+// row_edge[new] = canonical id of the vertex (ent_of_vertex), edge_new maps
+// canonical ids (n_ent of them) to new indices or -1.
+void build_pattern_graph(const std::vector<int64_t> &adj_ptr, const std::vector<int32_t> &adj,
+                         const std::vector<int32_t> &perm, const std::vector<int32_t> &ent_of_vertex,
+                         int64_t n_ent, Pattern &pat);
+
+}  // namespace tem

@@ -72,6 +72,111 @@ hipError_t launch_assemble_KM(hipStream_t st, int64_t N, const int64_t *rowptr, 
   return hipGetLastError();
 }
 
+// ------------------------------------------------- tetrahedral assembly
+// Element matrices of lowest-order edge elements on tetrahedra (section
+// "Spatial discretization"): basis of local edge (i, j) is
+// l_i grad l_j - l_j grad l_i, so with int l_p l_q = |T| (1 + [p = q]) / 20
+//   M[(ij),(kl)] = <ik> g_j.g_l - <il> g_j.g_k - <jk> g_i.g_l + <jl> g_i.g_k
+//   K[(ij),(kl)] = (4 |T| / mu) (g_i x g_j).(g_k x g_l)
+// (g = barycentric gradients), times the edge signs on both sides; and the
+// unit-conductivity nodal block G_T^T M_T G_T = |T| g_i . g_j (Lt, 4 x 4:
+// the gradients of the hat functions are edge functions).  One thread per
+// tetrahedron; outputs entry-major, Kt[ab * nt + t], so that neighbouring
+// threads write neighbouring addresses.
+__global__ void k_tet_elements(int64_t nt, const double *xyz, const int32_t *tets,
+                               const int8_t *sgn, double inv_mu, double *Kt, double *Mt,
+                               double *Lt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  double x[4][3];
+  for (int i = 0; i < 4; ++i) {
+    const int64_t v = tets[4 * t + i];
+    for (int d = 0; d < 3; ++d) x[i][d] = xyz[3 * v + d];
+  }
+  double e[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int d = 0; d < 3; ++d) e[i][d] = x[i + 1][d] - x[0][d];
+  // rows of J are e_i; grad l_{i+1} = column i of J^{-1} = (e_{i+1} x e_{i+2}) / det
+  const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                     e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                     e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+  double g[4][3];
+  for (int i = 0; i < 3; ++i) {
+    const double *a = e[(i + 1) % 3], *b = e[(i + 2) % 3];
+    g[i + 1][0] = (a[1] * b[2] - a[2] * b[1]) / det;
+    g[i + 1][1] = (a[2] * b[0] - a[0] * b[2]) / det;
+    g[i + 1][2] = (a[0] * b[1] - a[1] * b[0]) / det;
+  }
+  for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+  const double vol = fabs(det) / 6.0;
+  double gg[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) gg[i][j] = g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) Lt[(int64_t)(i * 4 + j) * nt + t] = vol * gg[i][j];
+  const int LE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  double cr[6][3];
+  for (int a = 0; a < 6; ++a) {
+    const double *p = g[LE[a][0]], *q = g[LE[a][1]];
+    cr[a][0] = p[1] * q[2] - p[2] * q[1];
+    cr[a][1] = p[2] * q[0] - p[0] * q[2];
+    cr[a][2] = p[0] * q[1] - p[1] * q[0];
+  }
+  const double w0 = vol / 20.0, w1 = vol / 10.0;
+  for (int a = 0; a < 6; ++a) {
+    const int i = LE[a][0], j = LE[a][1];
+    for (int b = 0; b < 6; ++b) {
+      const int k = LE[b][0], l = LE[b][1];
+      const double ik = i == k ? w1 : w0, il = i == l ? w1 : w0;
+      const double jk = j == k ? w1 : w0, jl = j == l ? w1 : w0;
+      const double s = (double)(sgn[6 * t + a] * sgn[6 * t + b]);
+      const double m = ik * gg[j][l] - il * gg[j][k] - jk * gg[i][l] + jl * gg[i][k];
+      const double kv = 4.0 * vol * inv_mu *
+                        (cr[a][0] * cr[b][0] + cr[a][1] * cr[b][1] + cr[a][2] * cr[b][2]);
+      Mt[(int64_t)(a * 6 + b) * nt + t] = s * m;
+      Kt[(int64_t)(a * 6 + b) * nt + t] = s * kv;
+    }
+  }
+}
+
+hipError_t launch_tet_elements(hipStream_t st, int64_t nt, const double *xyz, const int32_t *tets,
+                               const int8_t *sgn, double mu, double *Kt, double *Mt, double *Lt) {
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tet_elements, dim3(grid_1d(nt, 128, 1 << 30)), dim3(128), 0, st, nt, xyz,
+                     tets, sgn, 1.0 / mu, Kt, Mt, Lt);
+  return hipGetLastError();
+}
+
+// Entry-owner gather: entry e of the CSR pattern sums its element
+// contributions src = t * ne + ab (ne entries per element matrix; a fixed
+// order, so the sums are deterministic); K is written only when with_k.
+__global__ void k_tet_gather(int64_t nnz, const int64_t *ent_ptr, const int32_t *ent_src,
+                             int ne, int64_t nt, const double *Kt, const double *Mt,
+                             const double *sigma, int with_k, double *Kv, double *Mv) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  double k = 0.0, m = 0.0;
+  for (int64_t q = ent_ptr[e]; q < ent_ptr[e + 1]; ++q) {
+    const int32_t src = ent_src[q];
+    const int64_t t = src / ne, ab = src % ne;
+    if (with_k) k += Kt[ab * nt + t];
+    m += sigma[t] * Mt[ab * nt + t];
+  }
+  if (with_k) Kv[e] = k;
+  Mv[e] = m;
+}
+
+hipError_t launch_tet_gather(hipStream_t st, int64_t nnz, const int64_t *ent_ptr,
+                             const int32_t *ent_src, int ne, int64_t nt, const double *Kt,
+                             const double *Mt, const double *sigma, bool with_k, double *Kv,
+                             double *Mv) {
+  if (nnz <= 0) return hipSuccess;
+  if (with_k && (!Kt || !Kv)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tet_gather, dim3(grid_1d(nnz, 256, 1 << 30)), dim3(256), 0, st, nnz,
+                     ent_ptr, ent_src, ne, nt, Kt, Mt, sigma, with_k ? 1 : 0, Kv, Mv);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------ shifted products
 // x, y, r are [pole][N][S].  Workgroups are handed to the eight XCDs round
 // robin; block b works on block (b % 8) * chunk + b / 8, so each XCD walks a
@@ -688,6 +793,115 @@ hipError_t launch_jtw_reduce(hipStream_t st, int P, int npole, int S, int ldS, i
   return hipGetLastError();
 }
 
+// Jv right-hand sides on tetrahedra: rhs[p][q][s] = xi_p sum over the
+// tetrahedra t of edge q (list et_ptr/et_src = t * 6 + local index) of
+// vs[t] sum_b Mt[la][b] g[p][tet_new[t][b]][s] (boundary edges skipped).
+__global__ void k_jv_rhs_tet(int64_t N, int npole, int S, int ldS, int64_t pstride,
+                             const int64_t *et_ptr, const int32_t *et_src, const int32_t *tet_new,
+                             int64_t nt, const double *vs, const double *Mt, const double *xi,
+                             const cpx<double> *g, cpx<double> *rhs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mS = (int64_t)npole * S;
+  if (idx >= N * mS) return;
+  const int64_t q = idx / mS;
+  const int ps = (int)(idx % mS);
+  const int p = ps / S, c = ps % S;
+  const cpx<double> *G = g + (int64_t)p * pstride + c;
+  double ar = 0.0, ai = 0.0;
+  for (int64_t u = et_ptr[q]; u < et_ptr[q + 1]; ++u) {
+    const int64_t t = et_src[u] / 6;
+    const int la = et_src[u] % 6;
+    const double w = vs[t];
+    if (w == 0.0) continue;
+    double sr = 0.0, si = 0.0;
+    for (int lb = 0; lb < 6; ++lb) {
+      const int32_t qb = tet_new[6 * t + lb];
+      if (qb < 0) continue;
+      const cpx<double> v = G[(int64_t)qb * ldS];
+      const double m = Mt[(int64_t)(la * 6 + lb) * nt + t];
+      sr += m * v.re;
+      si += m * v.im;
+    }
+    ar += w * sr;
+    ai += w * si;
+  }
+  const double xr = xi[2 * p], xim = xi[2 * p + 1];
+  rhs[(int64_t)p * pstride + q * ldS + c] = {xr * ar - xim * ai, xr * ai + xim * ar};
+}
+
+hipError_t launch_jv_rhs_tet(hipStream_t st, int64_t N, int npole, int S, int ldS, int64_t pstride,
+                             const int64_t *et_ptr, const int32_t *et_src, const int32_t *tet_new,
+                             int64_t nt, const double *vs, const double *Mt, const double *xi,
+                             const cpx<double> *g, cpx<double> *rhs) {
+  const int64_t tot = N * npole * S;
+  if (tot <= 0) return hipSuccess;
+  if (S > ldS || pstride < N * ldS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jv_rhs_tet, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, N, npole,
+                     S, ldS, pstride, et_ptr, et_src, tet_new, nt, vs, Mt, xi, g, rhs);
+  return hipGetLastError();
+}
+
+// (J^T w)_p = 2 Re sum_{i,s} xi_i sigma_t g|_t^T M_t lam|_t, t = params[p],
+// on tetrahedra: one wave per parameter as in k_jtw_reduce.
+__global__ __launch_bounds__(256) void k_jtw_reduce_tet(int P, int npole, int S, int ldS,
+                                                        int64_t pstride, const int32_t *params,
+                                                        const int32_t *tet_new, int64_t nt,
+                                                        const double *sigma, const double *Mt,
+                                                        const double *xi, const cpx<double> *g,
+                                                        const cpx<double> *lam, double *out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t pp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pp >= P) return;   // the whole wave
+  const int64_t t = params[pp];
+  int32_t qe[6];
+  double me[36];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) qe[a] = tet_new[6 * t + a];
+#pragma unroll
+  for (int a = 0; a < 36; ++a) me[a] = Mt[(int64_t)a * nt + t];
+  const int slots = 64 / S, c = lane % S, ps = lane / S;
+  double tot = 0.0;
+  for (int p0 = 0; p0 < npole; p0 += slots) {
+    const int i = p0 + ps;
+    if (ps >= slots || i >= npole) continue;
+    const cpx<double> *G = g + (int64_t)i * pstride + c;
+    const cpx<double> *L = lam + (int64_t)i * pstride + c;
+    cpx<double> gv[6], lv[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      gv[a] = qe[a] >= 0 ? G[(int64_t)qe[a] * ldS] : cpx<double>{0.0, 0.0};
+      lv[a] = qe[a] >= 0 ? L[(int64_t)qe[a] * ldS] : cpx<double>{0.0, 0.0};
+    }
+    double br = 0.0, bi = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double mr = 0.0, mi = 0.0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        mr += me[a * 6 + b] * lv[b].re;
+        mi += me[a * 6 + b] * lv[b].im;
+      }
+      br += gv[a].re * mr - gv[a].im * mi;
+      bi += gv[a].re * mi + gv[a].im * mr;
+    }
+    tot += 2.0 * (xi[2 * i] * br - xi[2 * i + 1] * bi);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+  if (lane == 0) out[pp] = tot * sigma[t];
+}
+
+hipError_t launch_jtw_reduce_tet(hipStream_t st, int P, int npole, int S, int ldS, int64_t pstride,
+                                 const int32_t *params, const int32_t *tet_new, int64_t nt,
+                                 const double *sigma, const double *Mt, const double *xi,
+                                 const cpx<double> *g, const cpx<double> *lam, double *out) {
+  if (P <= 0) return hipSuccess;
+  if (S < 1 || S > 64 || S > ldS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jtw_reduce_tet, dim3((P + 3) / 4), dim3(256), 0, st, P, npole, S, ldS,
+                     pstride, params, tet_new, nt, sigma, Mt, xi, g, lam, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ nodal gradient space
 // Row-owner assembly of G^T M G over interior nodes: each thread sums the
 // sigma-weighted 8x8 element blocks of the <= 8 cells around its node.
@@ -740,7 +954,7 @@ hipError_t launch_assemble_nodal(hipStream_t st, int64_t Nn, const int64_t *rowp
 // slots past npole * S are zero.
 // out = G^T r: sum over the 6 incident edges, + for the edge ending at n
 // and - for the edge starting at n
-__global__ void k_grad_T(int64_t Nn, int npole, int S, int S2, int64_t N,
+__global__ void k_grad_T(int64_t Nn, int npole, int S, int S2, int64_t N, const int64_t *node_ptr,
                          const int32_t *node_edges, const cpx<double> *r, cpx<double> *out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int nsys = npole * S, nv = (nsys + S2 - 1) / S2;
@@ -753,23 +967,34 @@ __global__ void k_grad_T(int64_t Nn, int npole, int S, int S2, int64_t N,
   if (j < nsys) {
     const int p = j / S, c = j % S;
     const cpx<double> *R = r + (int64_t)p * N * S + c;
-    for (int t = 0; t < 6; ++t) {
-      const cpx<double> v = R[(int64_t)node_edges[n * 6 + t] * S];
-      const double sg = (t & 1) ? -1.0 : 1.0;
-      ar += sg * v.re;
-      ai += sg * v.im;
+    if (node_ptr) {   // signed edge+1 lists: + where the node ends the edge
+      for (int64_t t = node_ptr[n]; t < node_ptr[n + 1]; ++t) {
+        const int32_t q = node_edges[t];
+        const cpx<double> v = R[(int64_t)(q > 0 ? q - 1 : -q - 1) * S];
+        const double sg = q > 0 ? 1.0 : -1.0;
+        ar += sg * v.re;
+        ai += sg * v.im;
+      }
+    } else {
+      for (int t = 0; t < 6; ++t) {
+        const cpx<double> v = R[(int64_t)node_edges[n * 6 + t] * S];
+        const double sg = (t & 1) ? -1.0 : 1.0;
+        ar += sg * v.re;
+        ai += sg * v.im;
+      }
     }
   }
   out[idx] = {ar, ai};
 }
 
 hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int S2, int64_t N,
-                         const int32_t *node_edges, const cpx<double> *r, cpx<double> *out) {
+                         const int64_t *node_ptr, const int32_t *node_edges, const cpx<double> *r,
+                         cpx<double> *out) {
   const int nv = (npole * S + S2 - 1) / S2;
   const int64_t tot = Nn * nv * S2;
   if (tot <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_grad_T, dim3(grid_1d(tot, 256, 1 << 30)), dim3(256), 0, st, Nn, npole, S,
-                     S2, N, node_edges, r, out);
+                     S2, N, node_ptr, node_edges, r, out);
   return hipGetLastError();
 }
 
@@ -915,43 +1140,46 @@ hipError_t launch_raxpby(hipStream_t st, int64_t n, double a, const double *x, c
   return hipGetLastError();
 }
 
-// first-difference rows: out[r] = a * out[r] + sc * (m[hi[r]] - m[lo[r]])
-__global__ void k_reg(int64_t nr, const int32_t *lo, const int32_t *hi, double sc,
+// difference rows: out[r] = a * out[r] + sc * w_r * (m[hi[r]] - m[lo[r]])
+// (w NULL: w_r = 1)
+__global__ void k_reg(int64_t nr, const int32_t *lo, const int32_t *hi, const double *w, double sc,
                       const double *m, double a, double *out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nr) return;
-  const double v = sc * (m[hi[r]] - m[lo[r]]);
+  const double v = sc * (w ? w[r] : 1.0) * (m[hi[r]] - m[lo[r]]);
   out[r] = a == 0.0 ? v : a * out[r] + v;
 }
 
-hipError_t launch_reg(hipStream_t st, int64_t nr, const int32_t *lo, const int32_t *hi, double sc,
-                      const double *m, double a, double *out) {
+hipError_t launch_reg(hipStream_t st, int64_t nr, const int32_t *lo, const int32_t *hi,
+                      const double *w, double sc, const double *m, double a, double *out) {
   if (nr <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reg, dim3(grid_1d(nr, 256, 1 << 30)), dim3(256), 0, st, nr, lo, hi, sc, m,
-                     a, out);
+  hipLaunchKernelGGL(k_reg, dim3(grid_1d(nr, 256, 1 << 30)), dim3(256), 0, st, nr, lo, hi, w, sc,
+                     m, a, out);
   return hipGetLastError();
 }
 
-// transpose, gathered per parameter: out[p] = a * out[p] + sc * sum_t sgn_t u[row_t]
+// transpose, gathered per parameter: out[p] = a * out[p] + sc * sum_t sgn_t w_row u[row_t]
 // (incidence CSR inc_ptr/inc_row; sign encoded as the sign of row+1)
-__global__ void k_regT(int P, const int64_t *inc_ptr, const int32_t *inc_row, double sc,
-                       const double *u, double a, double *out) {
+__global__ void k_regT(int P, const int64_t *inc_ptr, const int32_t *inc_row, const double *w,
+                       double sc, const double *u, double a, double *out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   double s = 0.0;
   for (int64_t t = inc_ptr[p]; t < inc_ptr[p + 1]; ++t) {
     const int32_t e = inc_row[t];
-    if (e > 0) s += u[e - 1];
-    else s -= u[-e - 1];
+    const int64_t r = e > 0 ? e - 1 : -e - 1;
+    const double v = (w ? w[r] : 1.0) * u[r];
+    if (e > 0) s += v;
+    else s -= v;
   }
   out[p] = a == 0.0 ? sc * s : a * out[p] + sc * s;
 }
 
 hipError_t launch_regT(hipStream_t st, int P, const int64_t *inc_ptr, const int32_t *inc_row,
-                       double sc, const double *u, double a, double *out) {
+                       const double *w, double sc, const double *u, double a, double *out) {
   if (P <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_regT, dim3((P + 255) / 256), dim3(256), 0, st, P, inc_ptr, inc_row, sc, u,
-                     a, out);
+  hipLaunchKernelGGL(k_regT, dim3((P + 255) / 256), dim3(256), 0, st, P, inc_ptr, inc_row, w, sc,
+                     u, a, out);
   return hipGetLastError();
 }
 

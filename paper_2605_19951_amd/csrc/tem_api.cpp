@@ -190,6 +190,17 @@ struct tem_ctx {
   // mesh
   tem_mesh mesh{};
   MeshTopo mt;
+  // tetrahedral mesh (tem_assemble_tet): topology, coordinates and
+  // connectivity on the device, element matrices [36][n_tets], the
+  // element-to-entry gather lists of the pattern, each row's tetrahedra and
+  // each tetrahedron's six new edge indices
+  bool tet = false;
+  TetTopo tt;
+  double tet_mu = 0.0;
+  DBuf d_xyz, d_tetv, d_tsign, d_Kt, d_Mt, d_ent_ptr, d_ent_src, d_et_ptr, d_et_src, d_tet_new;
+  // and its gradient-space system: unit nodal blocks [16][n_tets], the
+  // gather lists of the nodal pattern, each node's signed edges (CSR)
+  DBuf d_Lt, d_nent_ptr, d_nent_src, d_node_ptr;
   double Ke[144], Me[144];
   std::vector<int32_t> params;
   int leaf = 4;
@@ -279,9 +290,10 @@ struct tem_ctx {
   // survey
   int R = 0, K = 0;
   DBuf d_qptr, d_qcol, d_qval, d_alpha;
-  // first-difference regularisation over faces shared by two parameter cells
+  // regularisation rows w_r (m_hi - m_lo) over faces shared by two
+  // parameter cells (hex: w = 1, d_reg_w empty; tetrahedra: RT0 weights)
   int64_t n_reg = 0;
-  DBuf d_reg_lo, d_reg_hi, d_reg_incp, d_reg_inc;
+  DBuf d_reg_lo, d_reg_hi, d_reg_incp, d_reg_inc, d_reg_w;
   // LSQR work space
   DBuf l_u, l_v, l_w, l_x, l_tmpd, l_tmpm, l_part, l_scal, l_V;
   // inversion work space (tem_invert)
@@ -346,6 +358,12 @@ tem_status hip_fail(tem_ctx *c, hipError_t e, const char *where) {
   } while (0)
 
 int64_t N_of(const tem_ctx *c) { return c->ed.N; }
+// canonical edges (the numbering of sources and receiver columns) and cells
+int64_t n_ent(const tem_ctx *c) { return c->tet ? c->tt.n_edges : c->mt.n_edges; }
+int64_t n_cells_of(const tem_ctx *c) { return c->tet ? c->tt.n_tets : c->mt.n_cells; }
+// unknowns per nested-dissection leaf of a tetrahedral mesh for the leaf
+// size given in cells per side (about the edges of that many cubes)
+int64_t tet_leaf(int leaf) { return 3 * (int64_t)leaf * leaf * leaf; }
 
 // systems per (pole, source) slot: one per mesh of a batch
 int n_seg(const tem_ctx *c) { return c->B > 0 ? c->B : 1; }
@@ -466,6 +484,171 @@ tem_status upload_pattern_and_assemble(tem_ctx *c) {
   return run_assemble_edges(c);
 }
 
+// ------------------------------------------ tetrahedral mesh (device side)
+tem_status run_assemble_tet(tem_ctx *c, bool with_k) {
+  const MF &e = c->ed;
+  HIPCHK(launch_tet_gather(c->stream, (int64_t)e.pat.col.size(), c->d_ent_ptr.as<int64_t>(),
+                           c->d_ent_src.as<int32_t>(), 36, c->tt.n_tets, c->d_Kt.as<double>(),
+                           c->d_Mt.as<double>(), c->d_sigma.as<double>(), with_k,
+                           c->d_K.as<double>(), c->d_M.as<double>()),
+         "tet gather");
+  return TEM_OK;
+}
+
+// Pattern in the current ordering, the gather lists from element entries
+// (t * 36 + 6 a + b, increasing) to pattern entries, each row's tetrahedra,
+// each tetrahedron's new edge indices; element matrices; K and M.
+tem_status upload_pattern_and_assemble_tet(tem_ctx *c) {
+  hipStream_t st = c->stream;
+  MF &e = c->ed;
+  const TetTopo &tt = c->tt;
+  build_pattern_graph(tt.adj_ptr, tt.adj, e.perm, tt.edge_of_unk, tt.n_edges, e.pat);
+  e.N = (int64_t)e.perm.size();
+  HIPCHK(upload(e.d_rowptr, e.pat.rowptr, st), "upload rowptr");
+  HIPCHK(upload(e.d_col, e.pat.col, st), "upload col");
+  HIPCHK(upload(e.d_row_ent, e.pat.row_edge, st), "upload row map");
+  HIPCHK(upload(e.d_ent_new, e.pat.edge_new, st), "upload entity map");
+  TRY(build_res_blocks(c, e, e.pat.rowptr, e.pat.col, {0}));
+  const int64_t nt = tt.n_tets, N = e.N;
+  const size_t nnz = e.pat.col.size();
+  std::vector<int32_t> tn((size_t)nt * 6);
+  for (int64_t t = 0; t < nt * 6; ++t) tn[t] = e.pat.edge_new[tt.tet_edges[t]];
+  auto entry = [&](int32_t qa, int32_t qb) {
+    const int32_t *b = e.pat.col.data() + e.pat.rowptr[qa], *en = e.pat.col.data() + e.pat.rowptr[qa + 1];
+    return (int64_t)(std::lower_bound(b, en, qb) - e.pat.col.data());
+  };
+  std::vector<int64_t> eptr(nnz + 1, 0), etp(N + 1, 0);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int a = 0; a < 6; ++a) {
+      const int32_t qa = tn[t * 6 + a];
+      if (qa < 0) continue;
+      ++etp[qa + 1];
+      for (int b = 0; b < 6; ++b)
+        if (tn[t * 6 + b] >= 0) ++eptr[entry(qa, tn[t * 6 + b]) + 1];
+    }
+  for (size_t k = 0; k < nnz; ++k) eptr[k + 1] += eptr[k];
+  for (int64_t q = 0; q < N; ++q) etp[q + 1] += etp[q];
+  std::vector<int32_t> esrc(eptr[nnz]), ets(etp[N]);
+  std::vector<int64_t> ef(eptr.begin(), eptr.end() - 1), tf(etp.begin(), etp.end() - 1);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int a = 0; a < 6; ++a) {
+      const int32_t qa = tn[t * 6 + a];
+      if (qa < 0) continue;
+      ets[tf[qa]++] = (int32_t)(t * 6 + a);
+      for (int b = 0; b < 6; ++b)
+        if (tn[t * 6 + b] >= 0) esrc[ef[entry(qa, tn[t * 6 + b])]++] = (int32_t)(t * 36 + a * 6 + b);
+    }
+  HIPCHK(upload(c->d_ent_ptr, eptr, st), "upload gather lists");
+  HIPCHK(upload(c->d_ent_src, esrc, st), "upload gather lists");
+  HIPCHK(upload(c->d_et_ptr, etp, st), "upload row tetrahedra");
+  HIPCHK(upload(c->d_et_src, ets, st), "upload row tetrahedra");
+  HIPCHK(upload(c->d_tet_new, tn, st), "upload tetrahedron edges");
+  HIPCHK(c->d_K.alloc(sizeof(double) * nnz), "alloc K");
+  HIPCHK(c->d_M.alloc(sizeof(double) * nnz), "alloc M");
+  HIPCHK(c->d_Kt.alloc(sizeof(double) * 36 * (size_t)nt), "alloc element K");
+  HIPCHK(c->d_Mt.alloc(sizeof(double) * 36 * (size_t)nt), "alloc element M");
+  HIPCHK(c->d_Lt.alloc(sizeof(double) * 16 * (size_t)nt), "alloc nodal blocks");
+  HIPCHK(launch_tet_elements(st, nt, c->d_xyz.as<double>(), c->d_tetv.as<int32_t>(),
+                             c->d_tsign.as<int8_t>(), c->tet_mu, c->d_Kt.as<double>(),
+                             c->d_Mt.as<double>(), c->d_Lt.as<double>()),
+         "tet elements");
+  return run_assemble_tet(c, true);
+}
+
+void release_tet(tem_ctx *c) {
+  c->tet = false;
+  c->tt = TetTopo();
+  for (DBuf *b : {&c->d_xyz, &c->d_tetv, &c->d_tsign, &c->d_Kt, &c->d_Mt, &c->d_ent_ptr,
+                  &c->d_ent_src, &c->d_et_ptr, &c->d_et_src, &c->d_tet_new, &c->d_Lt,
+                  &c->d_nent_ptr, &c->d_nent_src, &c->d_node_ptr})
+    b->release();
+}
+
+tem_status build_front_maps(tem_ctx *c, MF &mf);
+
+// The gradient-space system of a tetrahedral mesh (as setup_nodal for
+// hexahedra): nested dissection of the interior-node graph, its pattern,
+// the gather lists of G^T M G from the unit nodal blocks, each node's
+// signed edges and each edge's two nodes (new indices).
+tem_status setup_nodal_tet(tem_ctx *c, int leaf) {
+  MF &nd = c->nd;
+  nd.nodes = true;
+  c->nodal_ready = false;
+  const TetTopo &tt = c->tt;
+  nd.N = 0;
+  if (tt.n_inodes == 0) return TEM_OK;
+  std::vector<double> xy((size_t)tt.n_inodes * 3);
+  for (int64_t u = 0; u < tt.n_inodes; ++u)
+    for (int k = 0; k < 3; ++k) xy[3 * u + k] = tt.xyz[3 * (size_t)tt.node_of_unk[u] + k];
+  try {
+    analyse_graph(tt.n_inodes, tt.nadj_ptr, tt.nadj, xy, (int64_t)leaf * leaf * leaf, nd.sym);
+  } catch (const std::exception &ex) {
+    return fail(c, TEM_EINVAL, std::string("nodal analysis: ") + ex.what());
+  }
+  nd.perm = nd.sym.perm;
+  hipStream_t st = c->stream;
+  build_pattern_graph(tt.nadj_ptr, tt.nadj, nd.perm, tt.node_of_unk, tt.n_nodes, nd.pat);
+  nd.N = (int64_t)nd.perm.size();
+  HIPCHK(upload(nd.d_rowptr, nd.pat.rowptr, st), "upload nodal rowptr");
+  HIPCHK(upload(nd.d_col, nd.pat.col, st), "upload nodal col");
+  HIPCHK(upload(nd.d_row_ent, nd.pat.row_edge, st), "upload nodal row map");
+  HIPCHK(upload(nd.d_ent_new, nd.pat.edge_new, st), "upload nodal map");
+  TRY(build_front_maps(c, nd));
+  const int64_t nt = tt.n_tets, Nn = nd.N;
+  const size_t nnz = nd.pat.col.size();
+  // G^T M G entries from the blocks t * 16 + 4 i + j of interior nodes
+  std::vector<int32_t> tn((size_t)nt * 4);
+  for (int64_t t = 0; t < nt * 4; ++t) tn[t] = nd.pat.edge_new[tt.tets[t]];
+  auto entry = [&](int32_t qa, int32_t qb) {
+    const int32_t *b = nd.pat.col.data() + nd.pat.rowptr[qa], *en = nd.pat.col.data() + nd.pat.rowptr[qa + 1];
+    return (int64_t)(std::lower_bound(b, en, qb) - nd.pat.col.data());
+  };
+  std::vector<int64_t> eptr(nnz + 1, 0);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        if (tn[t * 4 + i] >= 0 && tn[t * 4 + j] >= 0) ++eptr[entry(tn[t * 4 + i], tn[t * 4 + j]) + 1];
+  for (size_t k = 0; k < nnz; ++k) eptr[k + 1] += eptr[k];
+  std::vector<int32_t> esrc(eptr[nnz]);
+  std::vector<int64_t> ef(eptr.begin(), eptr.end() - 1);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        if (tn[t * 4 + i] >= 0 && tn[t * 4 + j] >= 0)
+          esrc[ef[entry(tn[t * 4 + i], tn[t * 4 + j])]++] = (int32_t)(t * 16 + i * 4 + j);
+  HIPCHK(upload(c->d_nent_ptr, eptr, st), "upload nodal gather lists");
+  HIPCHK(upload(c->d_nent_src, esrc, st), "upload nodal gather lists");
+  // node -> signed unknown edges (new indices), edge -> (start, end) nodes
+  const Pattern &ep = c->ed.pat;
+  std::vector<int64_t> np_(Nn + 1, 0);
+  std::vector<int32_t> en((size_t)c->ed.N * 2);
+  for (int64_t q = 0; q < c->ed.N; ++q) {
+    const int64_t e = ep.row_edge[q];
+    const int32_t a = nd.pat.edge_new[tt.edges[2 * e]], b = nd.pat.edge_new[tt.edges[2 * e + 1]];
+    en[q * 2] = a;
+    en[q * 2 + 1] = b;
+    if (a >= 0) ++np_[a + 1];
+    if (b >= 0) ++np_[b + 1];
+  }
+  for (int64_t v = 0; v < Nn; ++v) np_[v + 1] += np_[v];
+  std::vector<int32_t> ne(np_[Nn]);
+  std::vector<int64_t> nf(np_.begin(), np_.end() - 1);
+  for (int64_t q = 0; q < c->ed.N; ++q) {
+    if (en[q * 2] >= 0) ne[nf[en[q * 2]]++] = -(int32_t)(q + 1);
+    if (en[q * 2 + 1] >= 0) ne[nf[en[q * 2 + 1]]++] = (int32_t)(q + 1);
+  }
+  HIPCHK(upload(c->d_node_ptr, np_, st), "upload node edges");
+  HIPCHK(upload(c->d_node_edges, ne, st), "upload node edges");
+  HIPCHK(upload(c->d_edge_nodes, en, st), "upload edge nodes");
+  HIPCHK(c->d_Ln.alloc(sizeof(double) * nnz), "alloc nodal values");
+  HIPCHK(c->d_Lzero.alloc(sizeof(double) * nnz), "alloc zeros");
+  HIPCHK(launch_fill_f64(st, c->d_Lzero.as<double>(), (int64_t)nnz, 0.0), "zeros");
+  std::vector<double> zxi = {0.0, 0.0};
+  HIPCHK(upload(c->d_nxi, zxi, st), "upload zero shift");
+  HIPCHK(hipStreamSynchronize(st), "nodal setup sync");
+  return TEM_OK;
+}
+
 // Invalidates the factors and pole solutions; their memory stays allocated
 // for a refactorisation of the same size (free_factors releases it).
 void drop_graphs(tem_ctx *c) {
@@ -495,6 +678,9 @@ void free_factors(tem_ctx *c) {
 // Rows (m_b - m_a) for every face shared by two parameter cells a < b:
 // x-faces, then y-faces, then z-faces, each in increasing cell index of the
 // lower cell; parameter incidence lists (signed row+1) for the transpose.
+tem_status upload_regulariser(tem_ctx *c, const std::vector<int32_t> &lo,
+                              const std::vector<int32_t> &hi, const std::vector<double> &w);
+
 tem_status build_regulariser(tem_ctx *c) {
   const MeshTopo &mt = c->mt;
   std::vector<int32_t> pid(mt.n_cells, -1);
@@ -512,6 +698,44 @@ tem_status build_regulariser(tem_ctx *c) {
       lo.push_back(pid[cell]);
       hi.push_back(nb);
     }
+  return upload_regulariser(c, lo, hi, {});
+}
+
+// Tetrahedra (section "Regularization"): one row per face shared by two
+// parameter tetrahedra a < b, in increasing order of the face's sorted node
+// triple, (m_b - m_a) / sqrt(d_f) with d_f the diagonal of the lowest-order
+// Raviart-Thomas mass of the face's unit-flux function over both
+// tetrahedra (the lumped M_div), so that R^T R = D diag(M_div)^-1 D^T.
+tem_status build_regulariser_tet(tem_ctx *c) {
+  const TetTopo &tt = c->tt;
+  std::vector<int32_t> pid(tt.n_tets, -1);
+  for (size_t p = 0; p < c->params.size(); ++p) pid[c->params[p]] = (int32_t)p;
+  std::vector<int32_t> lo, hi;
+  std::vector<double> w;
+  const size_t nf = tt.iface_opp.size() / 2;
+  for (size_t f = 0; f < nf; ++f) {
+    const int32_t t1 = tt.iface_tets[2 * f], t2 = tt.iface_tets[2 * f + 1];
+    if (pid[t1] < 0 || pid[t2] < 0) continue;
+    double d = 0.0;
+    for (int side = 0; side < 2; ++side) {
+      const int32_t t = tt.iface_tets[2 * f + side];
+      double x[12], dg[4];
+      for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 3; ++k) x[3 * i + k] = tt.xyz[3 * (size_t)tt.tets[4 * (size_t)t + i] + k];
+      tet_rt0_diag(x, dg);
+      d += dg[tt.iface_opp[2 * f + side]];
+    }
+    lo.push_back(std::min(pid[t1], pid[t2]));
+    hi.push_back(std::max(pid[t1], pid[t2]));
+    w.push_back(1.0 / std::sqrt(d));
+  }
+  return upload_regulariser(c, lo, hi, w);
+}
+
+// Rows (lo, hi, optional weights) and the parameter incidence lists
+// (signed row+1) of the transpose.
+tem_status upload_regulariser(tem_ctx *c, const std::vector<int32_t> &lo,
+                              const std::vector<int32_t> &hi, const std::vector<double> &w) {
   const int P = (int)c->params.size();
   std::vector<int64_t> incp(P + 1, 0);
   for (size_t r = 0; r < lo.size(); ++r) {
@@ -526,6 +750,10 @@ tem_status build_regulariser(tem_ctx *c) {
     inc[fill[hi[r]]++] = (int32_t)(r + 1);
   }
   c->n_reg = (int64_t)lo.size();
+  if (w.empty())
+    c->d_reg_w.release();
+  else
+    HIPCHK(upload(c->d_reg_w, w, c->stream), "upload reg weights");
   HIPCHK(upload(c->d_reg_lo, lo, c->stream), "upload reg");
   HIPCHK(upload(c->d_reg_hi, hi, c->stream), "upload reg");
   HIPCHK(upload(c->d_reg_incp, incp, c->stream), "upload reg");
@@ -1300,7 +1528,9 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
     // run's systems packed S2 = 8 to a virtual pole (eight right-hand sides
     // keep its register triangle kernels at two blocks in flight)
     const int nsys = pr.n * S, S2 = std::min(8, nsys), nv = (nsys + S2 - 1) / S2;
-    HIPCHK(launch_grad_T(st, Nn, pr.n, S, S2, N, c->d_node_edges.as<int32_t>(), w + o, y), "G^T");
+    HIPCHK(launch_grad_T(st, Nn, pr.n, S, S2, N, c->tet ? c->d_node_ptr.as<int64_t>() : nullptr,
+                         c->d_node_edges.as<int32_t>(), w + o, y),
+           "G^T");
     TRY(sweep_levels<double>(c, c->nd, c->d_nfactor.as<cpx<double>>(), 0, nv, y, S2, 0,
                                    /*real_l=*/true));
     HIPCHK(launch_grad_add(st, N, pr.n, S, S2, Nn, c->d_edge_nodes.as<int32_t>(),
@@ -1625,6 +1855,12 @@ tem_status factor_nodal(tem_ctx *c) {
                                    c->d_Ln.as<double>() + c->nnz_node_off[b]),
              "nodal assembly");
     }
+  } else if (c->tet) {
+    HIPCHK(launch_tet_gather(st, (int64_t)nd.pat.col.size(), c->d_nent_ptr.as<int64_t>(),
+                             c->d_nent_src.as<int32_t>(), 16, c->tt.n_tets, nullptr,
+                             c->d_Lt.as<double>(), c->d_sigma.as<double>(), false, nullptr,
+                             c->d_Ln.as<double>()),
+           "nodal assembly");
   } else {
     HIPCHK(launch_assemble_nodal(st, nd.N, nd.d_rowptr.as<int64_t>(), nd.d_col.as<int32_t>(),
                                  nd.d_row_ent.as<int32_t>(), nd.d_ent_new.as<int32_t>(), c->mt.nx,
@@ -2101,6 +2337,12 @@ tem_status tem_assemble(tem_ctx *c, const tem_mesh *mesh, const double *sigma_ce
     c->assembled = false;
     c->analysed = false;
   }
+  if (c->tet) {   // leaving tetrahedral mode
+    release_tet(c);
+    free_factors(c);
+    c->assembled = false;
+    c->analysed = false;
+  }
   const bool same_mesh = c->assembled && c->mesh.nx == mesh->nx && c->mesh.ny == mesh->ny &&
                          c->mesh.nz == mesh->nz && c->mesh.h == mesh->h && c->mesh.mu == mesh->mu;
   if (same_mesh)
@@ -2153,7 +2395,10 @@ tem_status tem_set_model(tem_ctx *c, const double *m) {
   drop_factors(c);
   HIPCHK(launch_set_sigma_exp(c->stream, P, c->d_params.as<int32_t>(), m, c->d_sigma.as<double>()),
          "set sigma");
-  TRY(run_assemble_edges(c));
+  if (c->tet)
+    TRY(run_assemble_tet(c, false));
+  else
+    TRY(run_assemble_edges(c));
   HIPCHK(hipStreamSynchronize(c->stream), "set_model sync");
   return TEM_OK;
 }
@@ -2200,7 +2445,29 @@ tem_status tem_analyse(tem_ctx *c, const tem_analyse_opts *opts, tem_symbolic_in
     c->tuned[0].clear();
     c->tuned[1].clear();
   }
-  if (c->B == 0 && (!c->analysed || leaf != c->leaf)) {
+  if (c->B == 0 && c->tet && (!c->analysed || leaf != c->leaf)) {
+    free_factors(c);
+    const TetTopo &tt = c->tt;
+    std::vector<double> mid((size_t)tt.n_unknowns * 3);
+    for (int64_t u = 0; u < tt.n_unknowns; ++u) {
+      const int64_t e = tt.edge_of_unk[u];
+      for (int k = 0; k < 3; ++k)
+        mid[3 * u + k] = 0.5 * (tt.xyz[3 * (size_t)tt.edges[2 * e] + k] +
+                                tt.xyz[3 * (size_t)tt.edges[2 * e + 1] + k]);
+    }
+    try {
+      analyse_graph(tt.n_unknowns, tt.adj_ptr, tt.adj, mid, tet_leaf(leaf), c->ed.sym);
+    } catch (const std::exception &ex) {
+      return fail(c, TEM_EINVAL, std::string("tem_analyse: ") + ex.what());
+    }
+    c->leaf = leaf;
+    c->ed.perm = c->ed.sym.perm;
+    TRY(upload_pattern_and_assemble_tet(c));
+    TRY(build_front_maps(c, c->ed));
+    TRY(setup_nodal_tet(c, leaf));
+    c->analysed = true;
+  }
+  if (c->B == 0 && !c->tet && (!c->analysed || leaf != c->leaf)) {
     free_factors(c);
     try {
       analyse_symbolic(c->mt, leaf, c->ed.sym, false);
@@ -2270,6 +2537,118 @@ tem_status tem_symbolic_host(int32_t nx, int32_t ny, int32_t nz, int32_t leaf_ma
   return TEM_OK;
 }
 
+// ------------------------------------------------------ tetrahedral meshes
+tem_status tem_assemble_tet(tem_ctx *c, const tem_tet_mesh *mesh, const double *sigma_tets,
+                            int32_t n_params, const int32_t *param_tets) {
+  if (!c) return TEM_EINVAL;
+  if (!mesh || !mesh->xyz || !mesh->tets || !sigma_tets)
+    return fail(c, TEM_EINVAL, "tem_assemble_tet: NULL mesh arrays or sigma");
+  if (!(mesh->mu > 0) || !std::isfinite(mesh->mu))
+    return fail(c, TEM_EINVAL, "tem_assemble_tet: mu must be positive and finite");
+  if (mesh->n_tets > ((int64_t)1 << 31) / 36 - 1)
+    return fail(c, TEM_EINVAL, "tem_assemble_tet: too many tetrahedra for 32-bit element ids");
+  TetTopo tt;
+  const std::string err = tt.init(mesh->xyz, mesh->tets, mesh->n_nodes, mesh->n_tets);
+  if (!err.empty()) return fail(c, TEM_EINVAL, "tem_assemble_tet: " + err);
+  if (tt.n_unknowns == 0) return fail(c, TEM_EINVAL, "tem_assemble_tet: no interior edges");
+  const int64_t nt = tt.n_tets;
+  if (n_params < 0 || (n_params > 0 && !param_tets))
+    return fail(c, TEM_EINVAL, "tem_assemble_tet: bad parameter list");
+  std::vector<int32_t> prm(param_tets, param_tets + n_params);
+  {
+    std::vector<char> seen(nt, 0);
+    for (int32_t p : prm) {
+      if (p < 0 || p >= nt) return fail(c, TEM_EINVAL, "tem_assemble_tet: parameter tetrahedron out of range");
+      if (seen[p]) return fail(c, TEM_EINVAL, "tem_assemble_tet: duplicate parameter tetrahedron");
+      seen[p] = 1;
+    }
+  }
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  std::vector<double> sg(nt);
+  HIPCHK(hipMemcpy(sg.data(), sigma_tets, sizeof(double) * nt, hipMemcpyDeviceToHost),
+         "tem_assemble_tet: sigma d2h");
+  for (double v : sg)
+    if (!(v > 0) || !std::isfinite(v))
+      return fail(c, TEM_EINVAL, "tem_assemble_tet: sigma must be positive and finite");
+  if (c->B > 0) batch_release(c);
+  free_factors(c);
+  release_tet(c);
+  c->assembled = false;
+  c->analysed = false;
+  c->mesh = tem_mesh{};
+  c->mt = MeshTopo();
+  c->nd.N = 0;
+  c->nodal_ready = false;
+  c->tuned[0].clear();
+  c->tuned[1].clear();
+  c->tet = true;
+  c->tt = std::move(tt);
+  c->tet_mu = mesh->mu;
+  hipStream_t st = c->stream;
+  HIPCHK(upload(c->d_xyz, c->tt.xyz, st), "upload coordinates");
+  HIPCHK(upload(c->d_tetv, c->tt.tets, st), "upload tetrahedra");
+  HIPCHK(upload(c->d_tsign, c->tt.tet_signs, st), "upload edge signs");
+  HIPCHK(c->d_sigma.alloc(sizeof(double) * nt), "alloc sigma");
+  HIPCHK(hipMemcpyAsync(c->d_sigma.p, sigma_tets, sizeof(double) * nt, hipMemcpyDeviceToDevice, st),
+         "copy sigma");
+  c->params = prm;
+  HIPCHK(upload(c->d_params, c->params, st), "upload params");
+  TRY(build_regulariser_tet(c));
+  c->ed.perm.resize(c->tt.n_unknowns);
+  for (int64_t q = 0; q < c->tt.n_unknowns; ++q) c->ed.perm[q] = (int32_t)q;
+  TRY(upload_pattern_and_assemble_tet(c));
+  HIPCHK(hipStreamSynchronize(st), "tem_assemble_tet sync");
+  c->assembled = true;
+  return TEM_OK;
+}
+
+tem_status tem_symbolic_tet_host(const tem_tet_mesh *mesh, int32_t leaf_max_cells,
+                                 tem_symbolic_info *info, int32_t *perm, int32_t *sn_ptr,
+                                 int32_t *sn_parent, int64_t *rows_ptr, int32_t *rows) {
+  if (!mesh || !mesh->xyz || !mesh->tets) return TEM_EINVAL;
+  TetTopo tt;
+  Symbolic sym;
+  try {
+    if (!tt.init(mesh->xyz, mesh->tets, mesh->n_nodes, mesh->n_tets).empty()) return TEM_EINVAL;
+    std::vector<double> mid((size_t)tt.n_unknowns * 3);
+    for (int64_t u = 0; u < tt.n_unknowns; ++u) {
+      const int64_t e = tt.edge_of_unk[u];
+      for (int k = 0; k < 3; ++k)
+        mid[3 * u + k] = 0.5 * (tt.xyz[3 * (size_t)tt.edges[2 * e] + k] +
+                                tt.xyz[3 * (size_t)tt.edges[2 * e + 1] + k]);
+    }
+    analyse_graph(tt.n_unknowns, tt.adj_ptr, tt.adj, mid,
+                  tet_leaf(leaf_max_cells > 0 ? leaf_max_cells : 4), sym);
+  } catch (...) {
+    return TEM_EINVAL;
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->n_unknowns = tt.n_unknowns;
+    info->nnz_a = (int64_t)tt.adj.size();
+    info->nnz_l = sym.nnz_l;
+    info->n_rows_total = (int64_t)sym.rows.size();
+    info->n_supernodes = (int32_t)sym.nodes.size();
+    info->n_levels = sym.n_levels;
+    info->max_front = sym.max_front;
+    info->flops_per_pole = sym.flops_per_pole;
+  }
+  const int ns = (int)sym.nodes.size();
+  if (perm) std::memcpy(perm, sym.perm.data(), sizeof(int32_t) * sym.perm.size());
+  if (sn_ptr) {
+    for (int s = 0; s < ns; ++s) sn_ptr[s] = (int32_t)sym.nodes[s].first;
+    sn_ptr[ns] = (int32_t)tt.n_unknowns;
+  }
+  if (sn_parent)
+    for (int s = 0; s < ns; ++s) sn_parent[s] = sym.nodes[s].parent;
+  if (rows_ptr) {
+    for (int s = 0; s < ns; ++s) rows_ptr[s] = sym.nodes[s].rows_off;
+    rows_ptr[ns] = (int64_t)sym.rows.size();
+  }
+  if (rows) std::memcpy(rows, sym.rows.data(), sizeof(int32_t) * sym.rows.size());
+  return TEM_OK;
+}
+
 tem_status tem_factor_poles(tem_ctx *c, int32_t m, const double *xi, tem_precision prec,
                             const tem_factor_opts *opts) {
   if (!c) return TEM_EINVAL;
@@ -2309,7 +2688,7 @@ tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
   hipStream_t st = c->stream;
   c->solved = false;
   TRY(ensure_vec(c, c->d_fnew, sizeof(double) * (size_t)N * S, "alloc f"));
-  HIPCHK(launch_gather_rhs(st, N, S, S, c->mt.n_edges, c->ed.d_row_ent.as<int32_t>(), F,
+  HIPCHK(launch_gather_rhs(st, N, S, S, n_ent(c), c->ed.d_row_ent.as<int32_t>(), F,
                            c->d_fnew.as<double>()),
          "gather f");
   TRY(ensure_vec(c, c->d_g, sizeof(cpx<double>) * (size_t)c->npole * N * S, "alloc g"));
@@ -2327,7 +2706,7 @@ tem_status tem_solve_poles(tem_ctx *c, int32_t nrhs, const double *F, double *G,
   c->last_solves = res.solves;
   c->S = S;
   if (G) {
-    HIPCHK(launch_scatter_solution(st, N, c->npole, S, c->mt.n_edges, c->ed.d_ent_new.as<int32_t>(),
+    HIPCHK(launch_scatter_solution(st, N, c->npole, S, n_ent(c), c->ed.d_ent_new.as<int32_t>(),
                                    c->d_g.as<cpx<double>>(), (cpx<double> *)G),
            "scatter g");
   }
@@ -2358,7 +2737,7 @@ static tem_status set_survey(tem_ctx *c, int R, const int64_t *q_ptr, const int3
     if (q_ptr[r + 1] < q_ptr[r] || q_ptr[r + 1] > nnz)
       return fail(c, TEM_EINVAL, "tem_forward: q_ptr not monotone");
     for (int64_t t = q_ptr[r]; t < q_ptr[r + 1]; ++t) {
-      if (q_col[t] < 0 || q_col[t] >= c->mt.n_edges)
+      if (q_col[t] < 0 || q_col[t] >= n_ent(c))
         return fail(c, TEM_EINVAL, "tem_forward: receiver column out of range");
       if (!std::isfinite(q_val[t])) return fail(c, TEM_EINVAL, "tem_forward: non-finite Q value");
       int32_t q = c->ed.pat.edge_new[q_col[t]];
@@ -2414,17 +2793,24 @@ tem_status tem_jvp(tem_ctx *c, const double *v, double *jv, const tem_ir_opts *i
   hipStream_t st = c->stream;
   const int64_t N = N_of(c);
   const int S = c->S, m = c->npole;
-  TRY(ensure_vec(c, c->v_vs, sizeof(double) * (size_t)c->mt.n_cells, "alloc vs"));
+  TRY(ensure_vec(c, c->v_vs, sizeof(double) * (size_t)n_cells_of(c), "alloc vs"));
   TRY(ensure_vec(c, c->v_rhs, sizeof(cpx<double>) * (size_t)m * N * S, "alloc rhs"));
   TRY(ensure_vec(c, c->v_lam, sizeof(cpx<double>) * (size_t)m * N * S, "alloc sol"));
   HIPCHK(launch_param_scatter(st, (int)c->params.size(), c->d_params.as<int32_t>(), v,
-                              c->d_sigma.as<double>(), c->mt.n_cells, c->v_vs.as<double>()),
+                              c->d_sigma.as<double>(), n_cells_of(c), c->v_vs.as<double>()),
          "param scatter");
-  HIPCHK(launch_jv_rhs(st, N, m, S, S, N * S, c->mt.nx, c->mt.ny, c->mt.nz,
-                       c->ed.d_row_ent.as<int32_t>(), c->d_cell_new.as<int32_t>(),
-                       c->v_vs.as<double>(), c->d_Me.as<double>(), c->d_xi.as<double>(),
-                       c->d_g.as<cpx<double>>(), c->v_rhs.as<cpx<double>>()),
-         "jv rhs");
+  if (c->tet)
+    HIPCHK(launch_jv_rhs_tet(st, N, m, S, S, N * S, c->d_et_ptr.as<int64_t>(),
+                             c->d_et_src.as<int32_t>(), c->d_tet_new.as<int32_t>(), c->tt.n_tets,
+                             c->v_vs.as<double>(), c->d_Mt.as<double>(), c->d_xi.as<double>(),
+                             c->d_g.as<cpx<double>>(), c->v_rhs.as<cpx<double>>()),
+           "jv rhs");
+  else
+    HIPCHK(launch_jv_rhs(st, N, m, S, S, N * S, c->mt.nx, c->mt.ny, c->mt.nz,
+                         c->ed.d_row_ent.as<int32_t>(), c->d_cell_new.as<int32_t>(),
+                         c->v_vs.as<double>(), c->d_Me.as<double>(), c->d_xi.as<double>(),
+                         c->d_g.as<cpx<double>>(), c->v_rhs.as<cpx<double>>()),
+           "jv rhs");
   IrResult res;
   TRY(refine_solve(c, nullptr, c->v_rhs.as<cpx<double>>(), S, c->v_lam.as<cpx<double>>(), ir, res));
   HIPCHK(launch_time_assembly(st, S, c->K, c->R, m, N, S, c->d_qptr.as<int64_t>(),
@@ -2459,11 +2845,19 @@ tem_status tem_vjp(tem_ctx *c, const double *w, double *jtw, const tem_ir_opts *
          "jtw rhs");
   IrResult res;
   TRY(refine_solve(c, nullptr, c->v_rhs.as<cpx<double>>(), S, c->v_lam.as<cpx<double>>(), ir, res));
-  HIPCHK(launch_jtw_reduce(st, (int)c->params.size(), m, S, S, N * S, c->d_params.as<int32_t>(),
-                           c->d_cell_new.as<int32_t>(), c->d_sigma.as<double>(),
-                           c->d_Me.as<double>(), c->d_xi.as<double>(), c->d_g.as<cpx<double>>(),
-                           c->v_lam.as<cpx<double>>(), jtw),
-         "jtw reduce");
+  if (c->tet)
+    HIPCHK(launch_jtw_reduce_tet(st, (int)c->params.size(), m, S, S, N * S,
+                                 c->d_params.as<int32_t>(), c->d_tet_new.as<int32_t>(),
+                                 c->tt.n_tets, c->d_sigma.as<double>(), c->d_Mt.as<double>(),
+                                 c->d_xi.as<double>(), c->d_g.as<cpx<double>>(),
+                                 c->v_lam.as<cpx<double>>(), jtw),
+           "jtw reduce");
+  else
+    HIPCHK(launch_jtw_reduce(st, (int)c->params.size(), m, S, S, N * S,
+                             c->d_params.as<int32_t>(), c->d_cell_new.as<int32_t>(),
+                             c->d_sigma.as<double>(), c->d_Me.as<double>(), c->d_xi.as<double>(),
+                             c->d_g.as<cpx<double>>(), c->v_lam.as<cpx<double>>(), jtw),
+           "jtw reduce");
   HIPCHK(hipStreamSynchronize(st), "vjp sync");
   spans_collect(c);
   fill_stats(res, stats);
@@ -2526,11 +2920,12 @@ tem_status gn_lsqr(tem_ctx *c, const double *d_obs, const double *wd, const doub
   double *u = c->l_u.as<double>(), *v = c->l_v.as<double>(), *w = c->l_w.as<double>();
   double *x = c->l_x.as<double>(), *td = c->l_tmpd.as<double>(), *tm = c->l_tmpm.as<double>();
   const int32_t *rlo = c->d_reg_lo.as<int32_t>(), *rhi = c->d_reg_hi.as<int32_t>();
+  const double *rw = c->d_reg_w.as<double>();
   // A v = [W_d J v ; sqrt(lam) R v] -> u (times a, plus b u)
   auto matvec = [&](const double *vin, double a, double b) -> tem_status {
     TRY(tem_jvp(c, vin, td, ir, nullptr));
     HIPCHK(launch_raxpby(st, nd, a, td, wd, b, u), "u data");
-    HIPCHK(launch_reg(st, nr, rlo, rhi, a * sl, vin, b, u + nd), "u reg");
+    HIPCHK(launch_reg(st, nr, rlo, rhi, rw, a * sl, vin, b, u + nd), "u reg");
     return TEM_OK;
   };
   // A^T u = J^T (W_d u_d) + sqrt(lam) R^T u_r -> v (times a, plus b v)
@@ -2538,8 +2933,8 @@ tem_status gn_lsqr(tem_ctx *c, const double *d_obs, const double *wd, const doub
     HIPCHK(launch_raxpby(st, nd, 1.0, u, wd, 0.0, td), "W u");
     TRY(tem_vjp(c, td, tm, ir, nullptr));
     HIPCHK(launch_raxpby(st, P, a, tm, nullptr, b, v), "v data");
-    HIPCHK(launch_regT(st, P, c->d_reg_incp.as<int64_t>(), c->d_reg_inc.as<int32_t>(), a * sl,
-                       u + nd, 1.0, v),
+    HIPCHK(launch_regT(st, P, c->d_reg_incp.as<int64_t>(), c->d_reg_inc.as<int32_t>(), rw,
+                       a * sl, u + nd, 1.0, v),
            "v reg");
     return TEM_OK;
   };
@@ -2553,7 +2948,7 @@ tem_status gn_lsqr(tem_ctx *c, const double *d_obs, const double *wd, const doub
   HIPCHK(launch_raxpby(st, nd, -1.0, td, wd, 0.0, u), "b data");
   HIPCHK(launch_raxpby(st, P, 1.0, m, nullptr, 0.0, tm), "m");
   HIPCHK(launch_raxpby(st, P, -1.0, m_ref, nullptr, 1.0, tm), "m - m_ref");
-  HIPCHK(launch_reg(st, nr, rlo, rhi, -sl, tm, 0.0, u + nd), "b reg");
+  HIPCHK(launch_reg(st, nr, rlo, rhi, rw, -sl, tm, 0.0, u + nd), "b reg");
   double beta, alpha;
   TRY(lsqr_norm(c, nu, u, beta));
   if (beta > 0) HIPCHK(launch_raxpby(st, nu, 0.0, nullptr, nullptr, 1.0 / beta, u), "u /= beta");
@@ -2642,8 +3037,8 @@ static tem_status objective_parts(tem_ctx *c, const double *d, const double *d_o
   TRY(sq_norm(c, nd, t1, mis));
   HIPCHK(launch_raxpby(st, P, 1.0, m, nullptr, 0.0, t2), "m");
   HIPCHK(launch_raxpby(st, P, -1.0, m_ref, nullptr, 1.0, t2), "m - m_ref");
-  HIPCHK(launch_reg(st, c->n_reg, c->d_reg_lo.as<int32_t>(), c->d_reg_hi.as<int32_t>(), 1.0, t2,
-                    0.0, t3),
+  HIPCHK(launch_reg(st, c->n_reg, c->d_reg_lo.as<int32_t>(), c->d_reg_hi.as<int32_t>(),
+                    c->d_reg_w.as<double>(), 1.0, t2, 0.0, t3),
          "R (m - m_ref)");
   TRY(sq_norm(c, c->n_reg, t3, reg));
   return TEM_OK;
@@ -2813,6 +3208,7 @@ tem_status tem_assemble_batch(tem_ctx *c, int32_t n_mesh, const tem_mesh *meshes
   if (!same) {
     free_factors(c);
     batch_release(c);
+    if (c->tet) release_tet(c);
     c->assembled = false;
     c->analysed = false;
     c->mesh = tem_mesh{};

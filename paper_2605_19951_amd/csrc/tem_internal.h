@@ -287,6 +287,27 @@ hipError_t launch_jv_rhs(hipStream_t st, int64_t N, int npole, int S, int ldS, i
                          const double *vs, const double *Me, const double *xi,
                          const cpx<double> *g, cpx<double> *rhs);
 
+// Tetrahedra: element matrices (entry-major Kt/Mt [36][nt], unit
+// conductivity mass, edge signs applied; Lt [16][nt] the unit nodal blocks
+// |T| g_i . g_j), the entry-owner gather of a pattern from element entries
+// src = t * ne + ab (M only unless with_k), and the Jacobian pieces as above with the
+// per-tetrahedron masses (et_ptr/et_src: tetrahedra t * 6 + local index of
+// each row; tet_new: 6 new indices per tetrahedron, -1 on the boundary).
+hipError_t launch_tet_elements(hipStream_t st, int64_t nt, const double *xyz, const int32_t *tets,
+                               const int8_t *sgn, double mu, double *Kt, double *Mt, double *Lt);
+hipError_t launch_tet_gather(hipStream_t st, int64_t nnz, const int64_t *ent_ptr,
+                             const int32_t *ent_src, int ne, int64_t nt, const double *Kt,
+                             const double *Mt, const double *sigma, bool with_k, double *Kv,
+                             double *Mv);
+hipError_t launch_jv_rhs_tet(hipStream_t st, int64_t N, int npole, int S, int ldS, int64_t pstride,
+                             const int64_t *et_ptr, const int32_t *et_src, const int32_t *tet_new,
+                             int64_t nt, const double *vs, const double *Mt, const double *xi,
+                             const cpx<double> *g, cpx<double> *rhs);
+hipError_t launch_jtw_reduce_tet(hipStream_t st, int P, int npole, int S, int ldS, int64_t pstride,
+                                 const int32_t *params, const int32_t *tet_new, int64_t nt,
+                                 const double *sigma, const double *Mt, const double *xi,
+                                 const cpx<double> *g, const cpx<double> *lam, double *out);
+
 // sigma[params[p]] = exp(m[p])
 hipError_t launch_set_sigma_exp(hipStream_t st, int P, const int32_t *params, const double *m,
                                 double *sigma);
@@ -317,10 +338,11 @@ hipError_t launch_rdot(hipStream_t st, int64_t n, const double *a, const double 
                        double *partial /* 256 */, double *out);
 hipError_t launch_raxpby(hipStream_t st, int64_t n, double a, const double *x, const double *w,
                          double b, double *y);
-hipError_t launch_reg(hipStream_t st, int64_t nr, const int32_t *lo, const int32_t *hi, double sc,
-                      const double *m, double a, double *out);
+// regulariser rows sc w_r (m[hi] - m[lo]) and their transpose (w NULL: 1)
+hipError_t launch_reg(hipStream_t st, int64_t nr, const int32_t *lo, const int32_t *hi,
+                      const double *w, double sc, const double *m, double a, double *out);
 hipError_t launch_regT(hipStream_t st, int P, const int64_t *inc_ptr, const int32_t *inc_row,
-                       double sc, const double *u, double a, double *out);
+                       const double *w, double sc, const double *u, double a, double *out);
 
 // ------------------------------------------------ nodal gradient space
 // G^T M G on interior nodes (row-owner gather over the <= 8 cells of a node)
@@ -330,9 +352,13 @@ hipError_t launch_assemble_nodal(hipStream_t st, int64_t Nn, const int64_t *rowp
                                  const double *sigma, double *Lv);
 // out = G^T r  (edge vectors [pole][N][S] -> packed nodal vectors: system
 // j = p * S + s in column j % S2 of virtual pole j / S2, [vp][Nn][S2],
-// zero past npole * S)
+// zero past npole * S).  node_ptr NULL: six edges per node in the
+// hexahedral order (signs +, -, +, -, +, -); else the node's edges are the
+// signed edge+1 entries node_edges[node_ptr[n] .. node_ptr[n+1]) (+ where
+// the node ends the edge).
 hipError_t launch_grad_T(hipStream_t st, int64_t Nn, int npole, int S, int S2, int64_t N,
-                         const int32_t *node_edges, const cpx<double> *r, cpx<double> *out);
+                         const int64_t *node_ptr, const int32_t *node_edges, const cpx<double> *r,
+                         cpx<double> *out);
 // z += coef[pole] * G y
 // z += coef * G y with y packed as for launch_grad_T; coef indexed
 // [segment of the edge row * row_seg.stride + pole]

@@ -26,7 +26,8 @@ EXPORTS = ["tem_create", "tem_destroy", "tem_last_error", "tem_assemble", "tem_s
            "tem_solve_poles", "tem_forward", "tem_jvp", "tem_vjp", "tem_get_stats",
            "tem_set_profiling", "tem_gn_step", "tem_assemble_batch", "tem_factor_poles_batch",
            "tem_forward_batch", "tem_autotune", "tem_autotune_level", "tem_vjp_noalloc",
-           "tem_invert", "tem_set_params_batch", "tem_jvp_batch", "tem_vjp_batch"]
+           "tem_invert", "tem_set_params_batch", "tem_jvp_batch", "tem_vjp_batch",
+           "tem_assemble_tet", "tem_symbolic_tet_host"]
 
 
 class TemError(RuntimeError):
@@ -38,6 +39,11 @@ class TemError(RuntimeError):
 class Mesh(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double),
                 ("mu", C.c_double)]
+
+
+class TetMesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("xyz", C.c_void_p),
+                ("tets", C.c_void_p), ("mu", C.c_double)]
 
 
 class AnalyseOpts(C.Structure):
@@ -136,6 +142,9 @@ def load_library(path: str = LIB_PATH):
         "tem_invert": ([vp, dp, dp, dp, dp, C.POINTER(InvertOpts), C.POINTER(IrOpts), vp,
                         C.POINTER(C.c_int32)], C.c_int),
         "tem_assemble_batch": ([vp, i32, vp, dp], C.c_int),
+        "tem_assemble_tet": ([vp, C.POINTER(TetMesh), dp, i32, vp], C.c_int),
+        "tem_symbolic_tet_host": ([C.POINTER(TetMesh), i32, C.POINTER(SymbolicInfo), vp, vp, vp,
+                                   vp, vp], C.c_int),
         "tem_autotune": ([vp, i32, vp, C.c_int, C.POINTER(AutotuneReport)], C.c_int),
         "tem_autotune_level": ([vp, C.c_int, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
                                C.c_int),
@@ -196,6 +205,43 @@ def symbolic_host(nx, ny, nz, leaf_max=4):
     return out
 
 
+def _tet_mesh(xyz, tets, mu):
+    xyz, _ = _host(xyz, np.float64)
+    tets, _ = _host(tets, np.int32)
+    if xyz.ndim != 2 or xyz.shape[1] != 3 or tets.ndim != 2 or tets.shape[1] != 4:
+        raise ValueError("expected xyz (n_nodes, 3) and tets (n_tets, 4)")
+    m = TetMesh(len(xyz), len(tets), xyz.ctypes.data_as(C.c_void_p),
+                tets.ctypes.data_as(C.c_void_p), mu)
+    return m, (xyz, tets)
+
+
+def symbolic_tet_host(xyz, tets, leaf_max=4, mu=4.0e-7 * np.pi):
+    """Host-only analysis of a tetrahedral mesh (no GPU); as symbolic_host."""
+    L = load_library()
+    mesh, keep = _tet_mesh(xyz, tets, mu)
+    info = SymbolicInfo()
+    st = L.tem_symbolic_tet_host(C.byref(mesh), leaf_max, C.byref(info), None, None, None, None,
+                                 None)
+    if st != TEM_OK:
+        raise TemError(st, "tem_symbolic_tet_host failed")
+    N, ns, nr = info.n_unknowns, info.n_supernodes, info.n_rows_total
+    perm = np.zeros(N, np.int32)
+    sn_ptr = np.zeros(ns + 1, np.int32)
+    par = np.zeros(ns, np.int32)
+    rptr = np.zeros(ns + 1, np.int64)
+    rows = np.zeros(max(nr, 1), np.int32)
+    st = L.tem_symbolic_tet_host(C.byref(mesh), leaf_max, C.byref(info),
+                                 perm.ctypes.data_as(C.c_void_p), sn_ptr.ctypes.data_as(C.c_void_p),
+                                 par.ctypes.data_as(C.c_void_p), rptr.ctypes.data_as(C.c_void_p),
+                                 rows.ctypes.data_as(C.c_void_p))
+    if st != TEM_OK:
+        raise TemError(st, "tem_symbolic_tet_host failed")
+    del keep
+    out = info.as_dict()
+    out.update(perm=perm, sn_ptr=sn_ptr, sn_parent=par, rows_ptr=rptr, rows=rows[:nr])
+    return out
+
+
 class Tem:
     """One library context (one mesh, its factors and cached solutions)."""
 
@@ -241,6 +287,20 @@ class Tem:
         self.n_edges = nx * (ny + 1) * (nz + 1) + (nx + 1) * ny * (nz + 1) + (nx + 1) * (ny + 1) * nz
         self._chk(self.L.tem_assemble(self.h, C.byref(self.mesh), _dev(sigma, "float64", (self.n_cells,)),
                                       len(params), pp))
+        self.n_params = len(params)
+
+    def assemble_tet(self, xyz, tets, mu, sigma, params):
+        """Tetrahedral mesh: xyz (n_nodes, 3), tets (n_tets, 4) host arrays,
+        sigma a device float64 tensor per tetrahedron, params tetrahedron ids."""
+        params, pp = _host(params, np.int32)
+        mesh, keep = _tet_mesh(xyz, tets, mu)
+        self.n_cells = int(mesh.n_tets)
+        self._chk(self.L.tem_assemble_tet(self.h, C.byref(mesh),
+                                          _dev(sigma, "float64", (self.n_cells,)), len(params), pp))
+        del keep
+        t = np.sort(np.asarray(tets, np.int64), axis=1)
+        pairs = np.concatenate([t[:, [a, b]] for a, b in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))])
+        self.n_edges = len(np.unique(pairs, axis=0))
         self.n_params = len(params)
 
     def set_model(self, m):

@@ -64,6 +64,7 @@ class TetMesh:
         self.edges = np.unique(pairs.reshape(-1, 2), axis=0).astype(np.int32)
         tri = np.stack([t[:, [0, 0, 0, 1]], t[:, [1, 1, 2, 2]], t[:, [2, 3, 3, 3]]], axis=2)
         self.faces = np.unique(tri.reshape(-1, 3), axis=0).astype(np.int32)
+        self._keys = self.edges[:, 0].astype(np.int64) * len(self.xyz) + self.edges[:, 1]
 
     @property
     def n_nodes(self):
@@ -85,7 +86,7 @@ class TetMesh:
         the direction a -> b relative to its orientation."""
         lo, hi = (a, b) if a < b else (b, a)
         key = lo * np.int64(self.n_nodes) + hi
-        keys = self.edges[:, 0].astype(np.int64) * self.n_nodes + self.edges[:, 1]
+        keys = self._keys
         pos = int(np.searchsorted(keys, key))
         if pos >= len(keys) or keys[pos] != key:
             raise KeyError((a, b))

@@ -1,0 +1,251 @@
+"""GPU parity of the tetrahedral path (through the C ABI) against the FP64
+tetrahedral oracle: assembly, pole solutions, data at all times, J v,
+J^T w, re-assembly after a model change, and a Gauss-Newton step with the
+RT0 regulariser.  Tolerances as for the hexahedral path: FP64 factors 1e-9,
+FP32 factors with FP64 refinement and the gradient-space correction 1e-6
+(relative on the outputs; pole solutions in the M-norm)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tet as ot
+from oracle.tem import gauss_newton_step
+from tem_inputs.tet import tet_workload
+
+pytestmark = pytest.mark.gpu
+
+TOLS = (1e-9, 1e-6)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+class TetRun:
+    def __init__(self, wl, leaf=2, prec=0, o=None):
+        torch = _torch()
+        from paper_2605_19951_amd import Tem
+        self.torch = torch
+        self.wl = wl
+        me = wl.mesh
+        self.dev = torch.device("cuda:0")
+        print("case %s tets=%d S=%d m=%d leaf=%d prec=%d" % (wl.name, me.n_tets, wl.S,
+                                                            len(wl.poles.xi), leaf, prec), flush=True)
+        self.prec = prec
+        self.tol = TOLS[prec]
+        self.t = Tem(0)
+        self.t.assemble_tet(me.xyz, me.tets, wl.mu, torch.tensor(wl.sigma, device=self.dev),
+                            wl.params)
+        self.info = self.t.analyse(leaf)
+        self.t.factor_poles(wl.poles.xi, prec)
+        self.F = torch.tensor(wl.F.T.copy(), device=self.dev)
+        self.d = torch.zeros((wl.S, len(wl.poles.t), wl.rx.n), dtype=torch.float64,
+                             device=self.dev)
+        self.ir = self.t.forward(self.F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, self.d)
+        self.o = o if o is not None else ot.OracleTetTEM(
+            me.xyz, me.tets, wl.sigma, wl.F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.xi,
+            wl.poles.alpha, wl.params, wl.mu)
+
+
+WORKLOADS = {
+    # several levels, fronts across several 64-row tiles with ragged tails
+    "t8": lambda: tet_workload(8, 2, S=2, m=6, K=9, g=3, seed=41),
+    # larger leaves and wider separators
+    "t11": lambda: tet_workload(11, 3, S=3, m=5, K=7, g=3, seed=42),
+}
+CASES = ["t8_64", "t8_32", "t11_64", "t11_32"]
+_runs = {}
+
+
+def get(name):
+    """The run of a case; both precisions of a workload share one oracle."""
+    if name not in _runs:
+        base, p = name.split("_")
+        other = [r for k, r in _runs.items() if k.split("_")[0] == base]
+        o = other[0].o if other else None
+        _runs[name] = TetRun(WORKLOADS[base](), leaf=2 if base == "t8" else 3,
+                             prec=0 if p == "64" else 1, o=o)
+    return _runs[name]
+
+
+@pytest.mark.parametrize("name", ["t8_64", "t11_64"])
+def test_tet_assembly_matches_oracle(name):
+    r = get(name)
+    perm, rowptr, col, kv, mv = r.t.export_operators()
+    K, M = r.o.K, r.o.M
+    Kp = K[perm][:, perm].tocsr()
+    Mp = M[perm][:, perm].tocsr()
+    Kp.sort_indices()
+    Mp.sort_indices()
+    N = len(perm)
+    assert np.array_equal(np.sort(perm), np.arange(N))
+    # the library's pattern is the unknown graph; the oracle's matrices may
+    # hold fewer entries (none cancel exactly here, but compare densely)
+    import scipy.sparse as sp
+    Kg = sp.csr_matrix((kv, col, rowptr), shape=(N, N))
+    Mg = sp.csr_matrix((mv, col, rowptr), shape=(N, N))
+    assert abs(Kg - Kp).max() <= 8 * np.finfo(float).eps * abs(Kp).max()
+    assert abs(Mg - Mp).max() <= 8 * np.finfo(float).eps * abs(Mp).max()
+    assert r.info["n_unknowns"] == len(r.o.unk)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_tet_pole_solutions(name):
+    r = get(name)
+    TOL = r.tol
+    torch = r.torch
+    G = torch.zeros((len(r.wl.poles.xi), r.wl.S, r.wl.mesh.n_edges), dtype=torch.complex128,
+                    device=r.dev)
+    r.t.solve_poles(r.F, G)
+    g = G.cpu().numpy()[:, :, r.o.unk].transpose(0, 2, 1)
+    gref = r.o.solve_poles()
+    Q = r.o.Q
+    for i in range(g.shape[0]):
+        dq = Q @ (g[i] - gref[i])
+        assert np.linalg.norm(dq) <= TOL * np.linalg.norm(Q @ gref[i])
+        dg = g[i] - gref[i]
+        mn = np.sqrt(np.abs(np.sum(np.conj(dg) * (r.o.M @ dg))))
+        mr = np.sqrt(np.abs(np.sum(np.conj(gref[i]) * (r.o.M @ gref[i]))))
+        assert mn <= 10 * TOL * mr
+        res = r.o.F - r.o.A(i) @ g[i]
+        assert np.linalg.norm(res) <= 1.5e-10 * np.linalg.norm(r.o.F)
+    other = np.setdiff1d(np.arange(r.wl.mesh.n_edges), r.o.unk)
+    assert np.all(G.cpu().numpy()[:, :, other] == 0)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_tet_data_all_times(name):
+    r = get(name)
+    TOL = r.tol
+    d = r.d.cpu().numpy()
+    dref = r.o.data()
+    cond = r.o.data_condition()
+    assert np.all(np.abs(d - dref) <= TOL * cond + 1e-300)
+    for j in range(d.shape[1]):
+        nrm = np.linalg.norm(dref[:, j])
+        assert np.linalg.norm(d[:, j] - dref[:, j]) <= TOL * max(nrm, np.linalg.norm(cond[:, j]))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_tet_jvp_vjp(name):
+    r = get(name)
+    TOL = r.tol
+    torch = r.torch
+    rng = np.random.default_rng(9)
+    P = len(r.wl.params)
+    v = rng.standard_normal(P)
+    w = rng.standard_normal(tuple(r.d.shape))
+    jv = torch.zeros_like(r.d)
+    jtw = torch.zeros(P, dtype=torch.float64, device=r.dev)
+    r.t.jvp(torch.tensor(v, device=r.dev), jv)
+    r.t.vjp(torch.tensor(w, device=r.dev), jtw)
+    jv_ref = r.o.jvp(v)
+    jtw_ref = r.o.vjp(w)
+    assert np.linalg.norm(jv.cpu().numpy() - jv_ref) <= TOL * np.linalg.norm(jv_ref)
+    assert np.linalg.norm(jtw.cpu().numpy() - jtw_ref) <= TOL * np.linalg.norm(jtw_ref)
+
+
+def test_tet_set_model_reassembles_mass():
+    r = get("t8_64")
+    torch = r.torch
+    rng = np.random.default_rng(11)
+    m = np.log(r.wl.sigma[r.wl.params]) + 0.3 * rng.standard_normal(len(r.wl.params))
+    r.t.set_model(torch.tensor(m, device=r.dev))
+    perm, rowptr, col, kv, mv = r.t.export_operators()
+    sig = r.wl.sigma.copy()
+    sig[r.wl.params] = np.exp(m)
+    Kr, Mr = ot.assemble(r.o.topo, sig, r.wl.mu, r.o.Ks, r.o.Ms)
+    import scipy.sparse as sp
+    N = len(perm)
+    Mg = sp.csr_matrix((mv, col, rowptr), shape=(N, N))
+    Kg = sp.csr_matrix((kv, col, rowptr), shape=(N, N))
+    Mp = Mr[perm][:, perm]
+    assert abs(Mg - Mp).max() <= 8 * np.finfo(float).eps * abs(Mp).max()
+    assert abs(Kg - Kr[perm][:, perm]).max() <= 8 * np.finfo(float).eps * abs(Kr).max()
+    # back to the workload's model for the other tests
+    r.t.set_model(torch.tensor(np.log(r.wl.sigma[r.wl.params]), device=r.dev))
+    r.t.factor_poles(r.wl.poles.xi, 0)
+    r.t.forward(r.F, r.wl.rx.ptr, r.wl.rx.col, r.wl.rx.val, r.wl.poles.alpha, r.d)
+
+
+@pytest.mark.parametrize("name", ["t8_64", "t8_32"])
+def test_tet_gauss_newton_step_matches_oracle(name):
+    """Twelve LSQR iterations with the RT0 regulariser (lumped mass) on the
+    t8 case: step and residual estimates against the oracle's
+    reorthogonalised LSQR (1e-9 with FP64 factors, 1e-6 with FP32)."""
+    r = get(name)
+    torch = r.torch
+    wl, o = r.wl, r.o
+    o.set_sigma(wl.sigma)
+    d_true = o.data().reshape(-1)
+    sd = 0.03 * np.abs(d_true) + 1e-9
+    d_obs = d_true + np.random.default_rng(4).standard_normal(d_true.shape) * sd
+    wd = 1.0 / sd
+    m0 = np.full(len(wl.params), math.log(1e-2))
+    R = ot.rt0_regulariser(o.topo, wl.params)[0]
+    iters = 12
+    dm_ref, hist_ref, _ = gauss_newton_step(o, m0, d_obs, wd, m0, 1.0, R, iters, reorth=True)
+    mt = torch.tensor(m0, device=r.dev)
+    r.t.set_model(mt)
+    r.t.factor_poles(wl.poles.xi, r.prec)
+    d = torch.zeros_like(r.d)
+    r.t.forward(r.F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, d)
+    dm = torch.zeros(len(m0), dtype=torch.float64, device=r.dev)
+    shp = tuple(d.shape)
+    hist = r.t.gn_step(torch.tensor(d_obs.reshape(shp), device=r.dev),
+                       torch.tensor(wd.reshape(shp), device=r.dev), mt, mt.clone(), 1.0, iters, dm)
+    err = np.linalg.norm(dm.cpu().numpy() - dm_ref) / np.linalg.norm(dm_ref)
+    herr = np.max(np.abs(np.asarray(hist) - hist_ref) / np.abs(hist_ref))
+    print("tet GN %d its prec=%d: dm rel err %.2e, residual estimates %.2e"
+          % (iters, r.prec, err, herr), flush=True)
+    assert err <= r.tol and herr <= r.tol
+    # restore
+    o.set_sigma(wl.sigma)
+    r.t.set_model(torch.tensor(np.log(wl.sigma[wl.params]), device=r.dev))
+    r.t.factor_poles(wl.poles.xi, r.prec)
+    r.t.forward(r.F, wl.rx.ptr, wl.rx.col, wl.rx.val, wl.poles.alpha, r.d)
+
+
+def test_tet_fp32_refinement_counts():
+    """With the gradient-space correction every pole and source of the FP32
+    factors reaches the 1e-10 refinement tolerance in a few solves."""
+    r = get("t8_32")
+    assert r.ir["n_unconverged"] == 0
+    assert int(r.ir["iters"].max()) <= 5
+
+
+def test_tet_then_hex_context_reuse():
+    """A context goes from a tetrahedral mesh to a hexahedral one and back."""
+    torch = _torch()
+    import tem_inputs as ti
+    from paper_2605_19951_amd import Tem
+    dev = torch.device("cuda:0")
+    wt = tet_workload(6, 2, S=1, m=3, K=4, g=2, seed=43)
+    wh = ti.smooth_workload(8, 2, S=1, m=3, K=4, g=2, seed=44)
+    t = Tem(0)
+    outs = []
+    for wl in (wt, wh, wt):
+        if hasattr(wl.mesh, "tets"):
+            t.assemble_tet(wl.mesh.xyz, wl.mesh.tets, wl.mu, torch.tensor(wl.sigma, device=dev),
+                           wl.params)
+        else:
+            me = wl.mesh
+            t.assemble(me.nx, me.ny, me.nz, me.h, ti.MU0, torch.tensor(wl.sigma, device=dev),
+                       wl.params)
+        t.analyse(2)
+        t.factor_poles(wl.poles.xi, 0)
+        d = torch.zeros((wl.S, len(wl.poles.t), wl.rx.n), dtype=torch.float64, device=dev)
+        t.forward(torch.tensor(wl.F.T.copy(), device=dev), wl.rx.ptr, wl.rx.col, wl.rx.val,
+                  wl.poles.alpha, d)
+        outs.append(d.cpu().numpy())
+    assert np.array_equal(outs[0], outs[2])
+    TOL = TOLS[0]
+    o = ot.OracleTetTEM(wt.mesh.xyz, wt.mesh.tets, wt.sigma, wt.F, wt.rx.ptr, wt.rx.col,
+                        wt.rx.val, wt.poles.xi, wt.poles.alpha, wt.params, wt.mu)
+    dref = o.data()
+    assert np.linalg.norm(outs[0] - dref) <= TOL * np.linalg.norm(dref)
+    t.close()
