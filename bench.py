@@ -20,7 +20,7 @@ per tree level (tem_autotune; untimed set-up, like assembly and analysis).
 precisions) and prints that workload's own line.
 
 Usage: python bench.py [--gpus 1] [--steps 1] [--warmup 1] [--no-cpu-baseline]
-                       [--no-autotune] [--no-ragged] [--fp32-only] [--tet [--tet-cubes 32]]
+                       [--no-autotune] [--no-ragged] [--fp32-only] [--tet [--tet-cubes 48]]
 """
 from __future__ import annotations
 
@@ -280,7 +280,7 @@ def inversion_phase(torch, dev, prec, max_gn=25, lsqr_iters=20, lambda0=10.0,
 ORACLE_RECORD = os.path.join(ROOT, "profiles", "oracle_hex64_pole_cpu.json")
 
 
-def tet_phase(torch, dev, steps, warmup, n=32):
+def tet_phase(torch, dev, steps, warmup, n=48):
     """The same step on a jittered tetrahedral mesh (n^3 cubes, six
     tetrahedra each; 8 loops, 16 poles, 60 times, 4 x 4 receivers) in both
     precisions: M(sigma) re-assembled on the device, all poles factored,
@@ -428,7 +428,7 @@ def main():
     ap.add_argument("--inversion-precision", type=int, default=1)
     ap.add_argument("--tet", action="store_true",
                     help="only run the tetrahedral-mesh workload (prints its own JSON line)")
-    ap.add_argument("--tet-cubes", type=int, default=32)
+    ap.add_argument("--tet-cubes", type=int, default=48)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the pole-sharded multi-GPU path is not part of this "

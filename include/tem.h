@@ -231,7 +231,8 @@ tem_status tem_assemble_tet(tem_ctx *ctx, const tem_tet_mesh *mesh, const double
  * tem_analyse computes for it): nested dissection of the unknown graph
  * (unknowns sharing a tetrahedron), each subgraph of more than
  * 3 * leaf_max_cells^3 unknowns split at the median edge midpoint along its
- * longest extent, the separator being the smaller one-sided boundary.
+ * longest extent, the separator being a minimum vertex cover of the edges
+ * cut by the split.
  * Outputs as tem_symbolic_host (nnz_a is that of the unknown graph). */
 tem_status tem_symbolic_tet_host(const tem_tet_mesh *mesh, int32_t leaf_max_cells,
                                  tem_symbolic_info *info, int32_t *perm, int32_t *sn_ptr,

@@ -131,8 +131,9 @@ void tet_rt0_diag(const double x[12], double out[4]);
 // Nested dissection of a graph with vertex coordinates and the supernodal
 // symbolic factorisation (the separator of each split is one supernode).
 // Each subgraph of more than leaf_max vertices is split at the median of its
-// longest coordinate extent; the separator is the smaller of the two sets of
-// vertices on one side with a neighbour on the other.  Columns within a
+// longest coordinate extent; the separator is a minimum vertex cover of the
+// edges the split cuts (it lies in the two sets of vertices with a
+// neighbour on the other side).  Columns within a
 // supernode are in increasing vertex order; supernodes in post-order.
 //   adj_ptr/adj: symmetric adjacency (self loops allowed), coords: 3 per vertex.
 void analyse_graph(int64_t n, const std::vector<int64_t> &adj_ptr, const std::vector<int32_t> &adj,

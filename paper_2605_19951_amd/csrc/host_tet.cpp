@@ -249,6 +249,116 @@ struct GraphND {
     return (int)sym.nodes.size() - 1;
   }
 
+  // Smallest vertex separator inside the two one-sided boundaries: a
+  // minimum vertex cover of the bipartite graph of the cut edges between SA
+  // and SB (Hopcroft-Karp matching, then Konig's construction: Z = vertices
+  // reached from unmatched SA vertices by alternating paths, cover =
+  // (SA \ Z) + (SB & Z)).  Uncovered boundary vertices go back to their side.
+  // side[] still marks A (1) and B (2) on entry.
+  std::vector<int32_t> loc;
+
+  void min_cover(const std::vector<int32_t> &SA, const std::vector<int32_t> &SB,
+                 std::vector<int32_t> &A, std::vector<int32_t> &B, std::vector<int32_t> &S) {
+    const int L = (int)SA.size(), R = (int)SB.size();
+    if (loc.empty()) loc.assign(side.size(), -1);
+    for (int i = 0; i < L; ++i) loc[SA[i]] = i;
+    for (int j = 0; j < R; ++j) loc[SB[j]] = j;
+    std::vector<int64_t> gp(L + 1, 0);
+    std::vector<int32_t> gj;
+    for (int i = 0; i < L; ++i) {
+      const int32_t v = SA[i];
+      for (int64_t t = ap[v]; t < ap[v + 1]; ++t)
+        if (side[aj[t]] == 2) gj.push_back(loc[aj[t]]);
+      gp[i + 1] = (int64_t)gj.size();
+    }
+    std::vector<int> mL(L, -1), mR(R, -1), dist(L), it(L);
+    const int INF = 1 << 30;
+    std::vector<int> q;
+    q.reserve(L);
+    auto bfs = [&]() {
+      q.clear();
+      bool found = false;
+      for (int i = 0; i < L; ++i) {
+        dist[i] = mL[i] < 0 ? 0 : INF;
+        if (mL[i] < 0) q.push_back(i);
+      }
+      for (size_t h = 0; h < q.size(); ++h) {
+        const int u = q[h];
+        for (int64_t t = gp[u]; t < gp[u + 1]; ++t) {
+          const int w = mR[gj[t]];
+          if (w < 0)
+            found = true;
+          else if (dist[w] == INF) {
+            dist[w] = dist[u] + 1;
+            q.push_back(w);
+          }
+        }
+      }
+      return found;
+    };
+    // iterative layered DFS for an augmenting path from free vertex u0
+    std::vector<int> stk;
+    auto dfs = [&](int u0) {
+      stk.assign(1, u0);
+      while (!stk.empty()) {
+        const int u = stk.back();
+        bool advanced = false;
+        for (; it[u] < gp[u + 1] - gp[u]; ++it[u]) {
+          const int r = gj[gp[u] + it[u]], w = mR[r];
+          if (w < 0) {   // augment along the stack
+            for (int k = (int)stk.size() - 1; k >= 0; --k) {
+              const int uu = stk[k], rr = gj[gp[uu] + it[uu]];
+              mL[uu] = rr;
+              mR[rr] = uu;
+            }
+            return true;
+          }
+          if (dist[w] == dist[u] + 1) {
+            stk.push_back(w);
+            advanced = true;
+            break;
+          }
+        }
+        if (!advanced) {
+          dist[u] = INF;
+          stk.pop_back();
+          if (!stk.empty()) ++it[stk.back()];
+        }
+      }
+      return false;
+    };
+    while (bfs()) {
+      std::fill(it.begin(), it.end(), 0);
+      for (int i = 0; i < L; ++i)
+        if (mL[i] < 0) dfs(i);
+    }
+    // Konig: alternating reachability from the unmatched left vertices
+    std::vector<char> zl(L, 0), zr(R, 0);
+    q.clear();
+    for (int i = 0; i < L; ++i)
+      if (mL[i] < 0) {
+        zl[i] = 1;
+        q.push_back(i);
+      }
+    for (size_t h = 0; h < q.size(); ++h) {
+      const int u = q[h];
+      for (int64_t t = gp[u]; t < gp[u + 1]; ++t) {
+        const int r = gj[t];
+        if (zr[r] || mL[u] == r) continue;
+        zr[r] = 1;
+        const int w = mR[r];
+        if (w >= 0 && !zl[w]) {
+          zl[w] = 1;
+          q.push_back(w);
+        }
+      }
+    }
+    for (int i = 0; i < L; ++i) (zl[i] ? A : S).push_back(SA[i]);
+    for (int j = 0; j < R; ++j) (zr[j] ? S : B).push_back(SB[j]);
+    for (int32_t v : SA) loc[v] = -1;
+    for (int32_t v : SB) loc[v] = -1;
+  }
+
   int rec(std::vector<int32_t> &V, int level) {
     if ((int64_t)V.size() <= leaf_max) return leaf(V, level);
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -277,15 +387,9 @@ struct GraphND {
       else
         (cut ? SB : B).push_back(v);
     }
-    for (int32_t v : V) side[v] = 0;
     std::vector<int32_t> S;
-    if (SA.size() <= SB.size()) {
-      S.swap(SA);
-      B.insert(B.end(), SB.begin(), SB.end());
-    } else {
-      S.swap(SB);
-      A.insert(A.end(), SA.begin(), SA.end());
-    }
+    min_cover(SA, SB, A, B, S);
+    for (int32_t v : V) side[v] = 0;
     if (S.empty()) {   // the halves are not connected: a one-vertex separator
       std::vector<int32_t> &big = A.size() >= B.size() ? A : B;
       S.push_back(big.back());
