@@ -16,11 +16,14 @@ FP64 oracle on a bounded sample.
 Before the timed steps of each precision the update kernels are autotuned
 per tree level (tem_autotune; untimed set-up, like assembly and analysis).
 
-``--tet`` runs the same step on a jittered tetrahedral mesh instead (both
-precisions) and prints that workload's own line.
+The default run also times one step of each precision on a jittered
+48^3-cube tetrahedral mesh (``phases.tet``; ``--no-tet`` skips it).
+``--tet`` runs only that workload (both
+precisions, autotuned the same way) and prints that workload's own line.
 
 Usage: python bench.py [--gpus 1] [--steps 1] [--warmup 1] [--no-cpu-baseline]
-                       [--no-autotune] [--no-ragged] [--fp32-only] [--tet [--tet-cubes 48]]
+                       [--no-autotune] [--no-ragged] [--no-tet] [--fp32-only]
+                       [--tet [--tet-cubes 48]]
 """
 from __future__ import annotations
 
@@ -280,7 +283,7 @@ def inversion_phase(torch, dev, prec, max_gn=25, lsqr_iters=20, lambda0=10.0,
 ORACLE_RECORD = os.path.join(ROOT, "profiles", "oracle_hex64_pole_cpu.json")
 
 
-def tet_phase(torch, dev, steps, warmup, n=48):
+def tet_phase(torch, dev, steps, warmup, n=48, autotune=True):
     """The same step on a jittered tetrahedral mesh (n^3 cubes, six
     tetrahedra each; 8 loops, 16 poles, 60 times, 4 x 4 receivers) in both
     precisions: M(sigma) re-assembled on the device, all poles factored,
@@ -307,6 +310,14 @@ def tet_phase(torch, dev, steps, warmup, n=48):
     m = torch.log(sigma[torch.tensor(wl.params, device=dev, dtype=torch.long)])
     phases, outs = {}, {}
     for name, prec in (("fp32_ir", FP32_IR), ("fp64", FP64)):
+        tuned = None
+        if autotune:   # untimed set-up, as for the hexahedral workload
+            ta = time.perf_counter()
+            tuned = t.autotune(wl.poles.xi, prec)
+            tuned["seconds"] = time.perf_counter() - ta
+            print("# tet %s autotune: candidates %s ms, tuned %.1f ms" % (
+                name, ["%.1f" % x for x in tuned["candidate_ms"]], tuned["tuned_ms"]),
+                file=sys.stderr, flush=True)
         rec = []
         for it in range(warmup + steps):
             timed = it >= warmup
@@ -344,6 +355,8 @@ def tet_phase(torch, dev, steps, warmup, n=48):
             factor_gb=st["factor_bytes"] / 1e9, update_ms=st["update_ms"],
             update_flops=st["update_flops"], update_launches=st["update_launches"],
             sweep_ms=st["sweep_ms"], sweep_bytes=st["sweep_bytes"])
+        if tuned is not None:
+            phases[name]["autotune"] = tuned
         outs[name] = (d.cpu().numpy(), jtw.cpu().numpy())
     t.close()
     acc = dict(data_rel_fp32_vs_fp64=float(np.linalg.norm(outs["fp32_ir"][0] - outs["fp64"][0])
@@ -429,6 +442,8 @@ def main():
     ap.add_argument("--tet", action="store_true",
                     help="only run the tetrahedral-mesh workload (prints its own JSON line)")
     ap.add_argument("--tet-cubes", type=int, default=48)
+    ap.add_argument("--no-tet", action="store_true",
+                    help="skip the tetrahedral-mesh phase of the default run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the pole-sharded multi-GPU path is not part of this "
@@ -449,7 +464,8 @@ def main():
         print(json.dumps(inversion_phase(torch, dev, args.inversion_precision)), flush=True)
         return
     if args.tet:
-        print(json.dumps(tet_phase(torch, dev, args.steps, args.warmup, args.tet_cubes)), flush=True)
+        print(json.dumps(tet_phase(torch, dev, args.steps, args.warmup, args.tet_cubes,
+                                   not args.no_autotune)), flush=True)
         return
     wl = ti.workload(2)
     me = wl.mesh
@@ -478,6 +494,11 @@ def main():
     del t
     if not args.no_ragged:
         phases["ragged_batch_fp32_ir"] = ragged_phase(torch, dev, FP32_IR)
+    if not args.no_tet:
+        # the paper's discretisation: the same step on a 48^3-cube tetrahedral mesh
+        tl = tet_phase(torch, dev, 1, 1, args.tet_cubes, not args.no_autotune)
+        phases["tet"] = dict(config=tl["config"], phases=tl["phases"], accuracy=tl["accuracy"],
+                             roofline=tl["roofline"], sweep=tl["sweep"])
     ach = res32["update_flops"] / (res32["update_ms"] * 1e-3) if res32["update_ms"] > 0 else 0.0
     roof = dict(bound="mfma", kernel="k_front_update<float>", achieved=ach / 1e12,
                 peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=ach / PEAK_FP32,

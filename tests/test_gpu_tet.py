@@ -321,3 +321,44 @@ def test_tet48_workload_properties():
     b = float((v * jtw).sum())
     assert abs(a - b) <= 1e-9 * max(abs(a), abs(b))
     t.close()
+
+
+def test_tet_invalid_meshes_are_refused():
+    """Invalid meshes and parameter lists give TEM_EINVAL with a message
+    naming the defect; the context then takes a valid mesh."""
+    torch = _torch()
+    from paper_2605_19951_amd import Tem
+    from paper_2605_19951_amd.tem import TemError
+    wl = tet_workload(6, 2, S=1, m=3, K=4, g=2, seed=45)
+    me = wl.mesh
+    dev = torch.device("cuda:0")
+    sig = torch.tensor(wl.sigma, device=dev)
+    t = Tem(0)
+    bad = me.tets.copy()
+    bad[3, 2] = bad[3, 0]
+    with pytest.raises(TemError, match="repeated node"):
+        t.assemble_tet(me.xyz, bad, wl.mu, sig, wl.params)
+    flat = me.xyz.copy()
+    flat[:, 2] = 0.0
+    with pytest.raises(TemError, match="zero volume"):
+        t.assemble_tet(flat, me.tets, wl.mu, sig, wl.params)
+    with pytest.raises(TemError, match="more than two"):
+        t.assemble_tet(me.xyz, np.concatenate([me.tets, me.tets[:1]]), wl.mu,
+                       torch.cat([sig, sig[:1]]), wl.params)
+    with pytest.raises(TemError, match="duplicate parameter"):
+        t.assemble_tet(me.xyz, me.tets, wl.mu, sig, np.array([0, 0], np.int32))
+    neg = sig.clone()
+    neg[5] = -1.0
+    with pytest.raises(TemError, match="positive"):
+        t.assemble_tet(me.xyz, me.tets, wl.mu, neg, wl.params)
+    with pytest.raises(TemError, match="interior edges"):   # one tetrahedron: all boundary
+        t.assemble_tet(me.xyz[[0, 1, 7, 49]], np.array([[0, 1, 2, 3]], np.int32), wl.mu,
+                       sig[:1].contiguous(), np.zeros(0, np.int32))
+    t.assemble_tet(me.xyz, me.tets, wl.mu, sig, wl.params)
+    t.analyse(2)
+    t.factor_poles(wl.poles.xi, 0)
+    d = torch.zeros((wl.S, len(wl.poles.t), wl.rx.n), dtype=torch.float64, device=dev)
+    t.forward(torch.tensor(wl.F.T.copy(), device=dev), wl.rx.ptr, wl.rx.col, wl.rx.val,
+              wl.poles.alpha, d)
+    assert np.isfinite(d.cpu().numpy()).all() and np.abs(d.cpu().numpy()).max() > 0
+    t.close()
