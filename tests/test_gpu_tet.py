@@ -362,3 +362,75 @@ def test_tet_invalid_meshes_are_refused():
               wl.poles.alpha, d)
     assert np.isfinite(d.cpu().numpy()).all() and np.abs(d.cpu().numpy()).max() > 0
     t.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tet_inversion_loop_matches_oracle(prec):
+    """Three Gauss-Newton iterations of tem_invert (line search, lambda
+    cooling) with the RT0 regulariser on a 6^3-cube tetrahedral mesh against
+    the oracle's loop: the decisions are equal, chi^2, phi, the slope, eta
+    and the final model agree to 1e-6."""
+    from oracle.inversion import Problem, invert
+    torch = _torch()
+    from paper_2605_19951_amd import Tem
+    wl = tet_workload(6, 2, S=1, m=5, K=6, g=3, seed=46)
+    me = wl.mesh
+    dev = torch.device("cuda:0")
+    o = ot.OracleTetTEM(me.xyz, me.tets, wl.sigma, wl.F, wl.rx.ptr, wl.rx.col, wl.rx.val,
+                        wl.poles.xi, wl.poles.alpha, wl.params, wl.mu)
+    d_true = o.data().reshape(-1)
+    shape = o.data().shape
+    sd = 0.03 * np.abs(d_true) + 1e-9
+    d_obs = d_true + sd * np.random.default_rng(2).standard_normal(d_true.shape)
+    last = {}
+
+    def at(m):   # re-assemble (and refactor) only for a new model
+        if "m" not in last or not np.array_equal(last["m"], m):
+            o.set_model(m)
+            last["m"] = np.array(m, copy=True)
+
+    def fwd(m):
+        at(m)
+        return o.data().reshape(-1)
+
+    def jv(m, v):
+        at(m)
+        return o.jvp(v).reshape(-1)
+
+    def jtw(m, w):
+        at(m)
+        return o.vjp(w.reshape(shape))
+
+    R = ot.rt0_regulariser(o.topo, wl.params)[0]
+    m0 = np.full(len(wl.params), math.log(1e-2))
+    m_fin, log_ref = invert(Problem(fwd, jv, jtw, R, d_obs, 1.0 / sd, m0), m0, 1.0,
+                            max_gn=3, lsqr_iters=8)
+    t = Tem(0)
+    t.assemble_tet(me.xyz, me.tets, wl.mu, torch.tensor(wl.sigma, device=dev), wl.params)
+    t.analyse(2)
+    mt = torch.tensor(m0, device=dev)
+    t.set_model(mt)
+    t.factor_poles(wl.poles.xi, prec)
+    d = torch.zeros(shape, dtype=torch.float64, device=dev)
+    t.forward(torch.tensor(wl.F.T.copy(), device=dev), wl.rx.ptr, wl.rx.col, wl.rx.val,
+              wl.poles.alpha, d)
+    log = t.invert(torch.tensor(d_obs.reshape(shape), device=dev),
+                   torch.tensor((1.0 / sd).reshape(shape), device=dev), mt,
+                   torch.tensor(m0, device=dev), 1.0, 3, 8)
+    print("tet invert prec=%d: %s" % (prec, [(r["accepted"], r["trials"], r["lam"],
+                                              round(r["eta"], 4)) for r in log]), flush=True)
+    assert len(log) == len(log_ref)
+    for r, q in zip(log, log_ref):
+        assert r["lam"] == q["lam"]
+        assert bool(r["stop"]) == ("stop" in q)
+        assert r["chi2"] == pytest.approx(q["chi2"], rel=1e-6)
+        assert r["phi"] == pytest.approx(q["phi"], rel=1e-6)
+        if "stop" in q:
+            continue
+        assert r["accepted"] == q["accepted"] and r["trials"] == q["trials"]
+        assert r["slope"] == pytest.approx(q["slope"], rel=1e-6)
+        assert r["eta"] == pytest.approx(q["eta"], rel=1e-6)
+        assert r["phi_new"] == pytest.approx(q["phi_new"], rel=1e-6)
+    mg = mt.cpu().numpy()
+    assert np.linalg.norm(mg - m_fin) <= 1e-6 * np.linalg.norm(m_fin)
+    t.close()
