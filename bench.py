@@ -43,6 +43,7 @@ PEAK_FP32 = 157.3e12      # dense FP32 MFMA, MI355X
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "front_update_hex64_fp32_traffic.json")
+TET_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "front_update_tet48_fp32_traffic.json")
 UPDATE_SOURCE = os.path.join(ROOT, "paper_2605_19951_amd", "csrc", "k_factor.hip")
 
 
@@ -52,13 +53,13 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the FP32 front update from the committed
+def recorded_traffic(record=TRAFFIC_RECORD):
+    """HBM bytes per launch of the FP32 front update from a committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE record, if it was taken on the current
     kernel source (else None)."""
-    if not os.path.exists(TRAFFIC_RECORD):
+    if not os.path.exists(record):
         return None
-    with open(TRAFFIC_RECORD) as f:
+    with open(record) as f:
         rec = json.load(f)
     if rec.get("source_sha256_16") != source_hash(UPDATE_SOURCE):
         return None
@@ -380,7 +381,8 @@ def tet_phase(torch, dev, steps, warmup, n=48, autotune=True):
                     analyse_s=analyse_s),
         phases=phases, accuracy=acc,
         roofline=dict(bound="mfma", kernel="k_front_update<float>", achieved=ach / 1e12,
-                      peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=ach / PEAK_FP32, traffic=None),
+                      peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=ach / PEAK_FP32,
+                      traffic=recorded_traffic(TET_TRAFFIC_RECORD) if n == 48 else None),
         sweep=dict(bound="hbm", achieved=bw / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
                    frac=bw / PEAK_HBM))
 
