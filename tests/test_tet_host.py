@@ -122,3 +122,32 @@ def test_tet_host_rejects_bad_meshes():
     dup = np.concatenate([me.tets, me.tets[:1]])   # a face of three tetrahedra
     with pytest.raises(tem.TemError):
         tem.symbolic_tet_host(me.xyz, dup)
+
+
+def test_disconnected_mesh_gets_a_valid_tree():
+    """Two blocks of cubes that share no node: the split between them cuts no
+    edge, so the separator is a single unknown; the structure still holds
+    the exact fill."""
+    _lib_or_skip()
+    a = kuhn_mesh(3, 3, 3, 10.0, 1, 0.1, np.random.default_rng(8))
+    b = kuhn_mesh(3, 3, 3, 10.0, 1, 0.1, np.random.default_rng(9))
+    xyz = np.concatenate([a.xyz, b.xyz + np.array([100.0, 0.0, 0.0])])
+    tets = np.concatenate([a.tets, b.tets + len(a.xyz)]).astype(np.int32)
+    sym = tem.symbolic_tet_host(xyz, tets, 1)
+    topo = ot.TetTopology(xyz, tets)
+    adj = unknown_graph(topo)
+    N = len(topo.unknown)
+    assert sym["n_unknowns"] == N
+    perm, sp_, par = sym["perm"], sym["sn_ptr"], sym["sn_parent"]
+    assert np.array_equal(np.sort(perm), np.arange(N))
+    ns = len(par)
+    assert par[-1] == -1 and all(par[s] > s for s in range(ns - 1))
+    assert sp_[-1] - sp_[-2] == 1          # the root: a one-unknown separator
+    lcols = eliminate(adj, perm)
+    rp, rows = sym["rows_ptr"], sym["rows"]
+    for s in range(ns):
+        fill = set()
+        for j in range(sp_[s], sp_[s + 1]):
+            fill.update(lcols[j])
+        fill -= set(range(sp_[s], sp_[s + 1]))
+        assert fill <= set(rows[rp[s]:rp[s + 1]]), s
