@@ -224,8 +224,9 @@ __global__ __launch_bounds__(256) void k_residual_init(int64_t N, int npole, int
 // call and each x row once per block that touches it, instead of once per
 // nonzero.  The sums over a row run in CSR order.
 __global__ __launch_bounds__(256) void k_residual_blk(
-    int64_t N, int npole, int S, int64_t nblk, const int64_t *rb_row, const int64_t *rb_hoff,
-    const int32_t *rb_h, const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
+    int64_t N, int npole, int S, int64_t nblk, const int64_t *rb_row, const int32_t *rb_rows,
+    const int64_t *rb_hoff, const int32_t *rb_h, const int64_t *rowptr, const uint16_t *lcol,
+    const double *Kv,
     const double *Mv, const double *xi, Seg sg, const double *f_real, const cpx<double> *f_cplx,
     const cpx<double> *x, cpx<double> *r) {
   constexpr int NS = RB_HALO * RB_SC / 256;      // halo loads per lane and pair
@@ -233,15 +234,21 @@ __global__ __launch_bounds__(256) void k_residual_blk(
   __shared__ cpx<double> xs[RB_HALO * RB_SC];
   __shared__ cpx<double> km[RB_ROWS * RB_NNZ];   // (K, M) of each entry
   __shared__ int kl[RB_ROWS * RB_NNZ];           // its halo position * RB_SC
-  __shared__ int64_t rp[RB_ROWS + 1];            // the block's row pointers
+  __shared__ int64_t rp0[RB_ROWS], rp1[RB_ROWS];  // each row's entries
+  __shared__ int32_t rws[RB_ROWS];                 // the block's rows
   const int64_t b = xcd_block(nblk);
   if (b >= nblk) return;   // uniform over the workgroup
-  const int64_t row0 = rb_row[b];
-  const int nrow = (int)(rb_row[b + 1] - row0);
+  const int64_t i0 = rb_row[b];
+  const int nrow = (int)(rb_row[b + 1] - i0);
   const int64_t h0 = rb_hoff[b];
   const int nh = (int)(rb_hoff[b + 1] - h0);
   const int t = threadIdx.x, lr = t >> 3, ls = t & (RB_SC - 1);
-  if (t <= nrow) rp[t] = rowptr[row0 + t];
+  if (t < nrow) {
+    const int32_t rw = rb_rows[i0 + t];
+    rws[t] = rw;
+    rp0[t] = rowptr[rw];
+    rp1[t] = rowptr[rw + 1];
+  }
   int hidx[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) hidx[i] = rb_h[h0 + min(lr + 32 * i, nh - 1)];
@@ -250,16 +257,16 @@ __global__ __launch_bounds__(256) void k_residual_blk(
   for (int i = 0; i < NE; ++i) {
     const int q = t + 256 * i;
     const int rr = q / RB_NNZ, j = q - rr * RB_NNZ;
-    if (rr < nrow && rp[rr] + j < rp[rr + 1]) {
-      const int64_t e = rp[rr] + j;
+    if (rr < nrow && rp0[rr] + j < rp1[rr]) {
+      const int64_t e = rp0[rr] + j;
       km[q] = {Kv[e], Mv[e]};
       kl[q] = (int)lcol[e] * RB_SC;
     }
   }
   const bool has_row = lr < nrow;
-  const int64_t row = row0 + (has_row ? lr : 0);
-  const int nnz = has_row ? (int)(rp[lr + 1] - rp[lr]) : 0;
-  const int64_t xb = 2 * (int64_t)seg_find(sg, row0) * sg.stride;
+  const int64_t row = rws[has_row ? lr : 0];
+  const int nnz = has_row ? (int)(rp1[lr] - rp0[lr]) : 0;
+  const int64_t xb = 2 * (int64_t)seg_find(sg, rws[0]) * sg.stride;
   const int nch = (S + RB_SC - 1) / RB_SC, npair = npole * nch;
   // halo rows of the current pair, in registers (real and imaginary parts
   // in separate arrays of doubles, which the compiler keeps in registers)
@@ -323,14 +330,16 @@ __global__ __launch_bounds__(256) void k_residual_blk(
 }
 
 hipError_t launch_residual_blk(hipStream_t st, int64_t N, int npole, int S, int64_t nblk,
-                               const int64_t *rb_row, const int64_t *rb_hoff, const int32_t *rb_h,
+                               const int64_t *rb_row, const int32_t *rb_rows,
+                               const int64_t *rb_hoff, const int32_t *rb_h,
                                const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
                                const double *Mv, const double *xi, Seg sg, const double *f_real,
                                const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r) {
   if (N <= 0 || npole <= 0 || nblk <= 0) return hipSuccess;
-  if (S < 1 || S > 16 || !x) return hipErrorInvalidValue;
+  if (S < 1 || S > 16 || !x || !rb_rows) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_residual_blk, dim3(xcd_grid(nblk, 1)), dim3(256), 0, st, N, npole, S, nblk,
-                     rb_row, rb_hoff, rb_h, rowptr, lcol, Kv, Mv, xi, sg, f_real, f_cplx, x, r);
+                     rb_row, rb_rows, rb_hoff, rb_h, rowptr, lcol, Kv, Mv, xi, sg, f_real, f_cplx,
+                     x, r);
   return hipGetLastError();
 }
 

@@ -169,7 +169,7 @@ struct MF {
   int x_bb = 0;
   // row blocks of the FP64 residual (edge system; see launch_residual_blk)
   int64_t rb_n = 0;
-  DBuf d_rb_row, d_rb_hoff, d_rb_h, d_lcol;
+  DBuf d_rb_row, d_rb_rows, d_rb_hoff, d_rb_h, d_lcol;
   std::vector<int32_t> h_np;
   // poles of front s among the g slots starting at p0
   int present(int s, int p0, int g) const {
@@ -395,27 +395,70 @@ tem_status run_assemble_edges(tem_ctx *c) {
   return TEM_OK;
 }
 
-// Row blocks of the residual: consecutive rows, at most RB_ROWS of them and
-// at most RB_HALO distinct columns, never across a segment start (a mesh of
-// a batch); each block's halo is its sorted column set and lcol gives every
-// entry's position in it.  Rows longer than RB_NNZ are refused.
+// Row blocks of the residual: at most RB_ROWS rows and at most RB_HALO
+// distinct columns per block, never across a segment start (a mesh of a
+// batch).  With positions (3 per row) the rows are taken, segment by
+// segment, in Morton order of their position on a grid of about three rows
+// per cell, so that a block's rows are neighbours in space and share most of
+// their columns (about a third fewer halo rows per row than in elimination
+// order); without, in row order.  Each block's halo is its sorted column set
+// and lcol gives every entry's position in it.  Rows longer than RB_NNZ are
+// refused.
+uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  uint64_t k = 0;
+  for (int b = 0; b < 21; ++b)
+    k |= ((uint64_t)((x >> b) & 1) << (3 * b)) | ((uint64_t)((y >> b) & 1) << (3 * b + 1)) |
+         ((uint64_t)((z >> b) & 1) << (3 * b + 2));
+  return k;
+}
+
 tem_status build_res_blocks(tem_ctx *c, MF &mf, const std::vector<int64_t> &rowptr,
-                            const std::vector<int32_t> &col, const std::vector<int64_t> &seg) {
+                            const std::vector<int32_t> &col, const std::vector<int64_t> &seg,
+                            const std::vector<double> *pos = nullptr) {
   const int64_t N = (int64_t)rowptr.size() - 1;
+  std::vector<int32_t> order(std::max<int64_t>(N, 0));
+  for (int64_t q = 0; q < N; ++q) order[q] = (int32_t)q;
+  if (pos && (int64_t)pos->size() == 3 * N) {
+    for (size_t si = 0; si < seg.size(); ++si) {
+      const int64_t a = seg[si], e = si + 1 < seg.size() ? seg[si + 1] : N;
+      if (e - a < 2) continue;
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int64_t q = a; q < e; ++q)
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = std::min(lo[d], (*pos)[3 * q + d]);
+          hi[d] = std::max(hi[d], (*pos)[3 * q + d]);
+        }
+      double vol = 1.0;
+      for (int d = 0; d < 3; ++d) vol *= std::max(hi[d] - lo[d], 1e-300);
+      const double cs = std::cbrt(vol * 3.0 / (double)(e - a));
+      std::vector<std::pair<uint64_t, int32_t>> key(e - a);
+      for (int64_t q = a; q < e; ++q) {
+        uint32_t g[3];
+        for (int d = 0; d < 3; ++d)
+          g[d] = (uint32_t)std::min(2097151.0, std::max(0.0, ((*pos)[3 * q + d] - lo[d]) / cs));
+        key[q - a] = {morton3(g[0], g[1], g[2]), (int32_t)q};
+      }
+      std::sort(key.begin(), key.end());
+      for (int64_t q = a; q < e; ++q) order[q] = key[q - a].second;
+    }
+  }
   std::vector<int64_t> brow(1, 0), hoff(1, 0);
   std::vector<int32_t> halo;
   std::vector<uint16_t> lcol(col.size());
   std::vector<int64_t> stamp(std::max<int64_t>(N, 1), -1);
-  std::vector<int32_t> pos(std::max<int64_t>(N, 1), 0);
+  std::vector<int32_t> pos_(std::max<int64_t>(N, 1), 0);
   std::vector<int32_t> h;
   size_t si = 0;
-  int64_t r = 0;
-  while (r < N) {
-    while (si + 1 < seg.size() && seg[si + 1] <= r) ++si;
-    const int64_t seg_end = si + 1 < seg.size() ? seg[si + 1] : N;
-    const int64_t blk = (int64_t)brow.size() - 1, r0 = r;
+  int64_t i = 0;
+  while (i < N) {
+    const int64_t first = order[i];
+    while (si + 1 < seg.size() && seg[si + 1] <= first) ++si;
+    const int64_t seg_lo = seg[si], seg_end = si + 1 < seg.size() ? seg[si + 1] : N;
+    const int64_t blk = (int64_t)brow.size() - 1, i0 = i;
     h.clear();
-    while (r < N && r < seg_end && r - r0 < RB_ROWS) {
+    while (i < N && i - i0 < RB_ROWS) {
+      const int64_t r = order[i];
+      if (r < seg_lo || r >= seg_end) break;   // the next segment starts a block
       if (rowptr[r + 1] - rowptr[r] > RB_NNZ)
         return fail(c, TEM_EINVAL, "residual blocks: a row has more than 33 entries");
       int add = 0;
@@ -426,7 +469,7 @@ tem_status build_res_blocks(tem_ctx *c, MF &mf, const std::vector<int64_t> &rowp
           h.push_back(col[t]);
         }
       if ((int64_t)h.size() > RB_HALO) {
-        // the row does not fit: undo its new columns (r > r0 here, since a
+        // the row does not fit: undo its new columns (i > i0 here, since a
         // single row has at most RB_NNZ < RB_HALO columns)
         for (int k = 0; k < add; ++k) {
           stamp[h.back()] = -1;
@@ -434,22 +477,50 @@ tem_status build_res_blocks(tem_ctx *c, MF &mf, const std::vector<int64_t> &rowp
         }
         break;
       }
-      ++r;
+      ++i;
     }
     std::sort(h.begin(), h.end());
-    for (size_t k = 0; k < h.size(); ++k) pos[h[k]] = (int32_t)k;
-    for (int64_t t = rowptr[r0]; t < rowptr[r]; ++t) lcol[t] = (uint16_t)pos[col[t]];
+    for (size_t k = 0; k < h.size(); ++k) pos_[h[k]] = (int32_t)k;
+    for (int64_t j = i0; j < i; ++j) {
+      const int64_t r = order[j];
+      for (int64_t t = rowptr[r]; t < rowptr[r + 1]; ++t) lcol[t] = (uint16_t)pos_[col[t]];
+    }
     halo.insert(halo.end(), h.begin(), h.end());
-    brow.push_back(r);
+    brow.push_back(i);
     hoff.push_back((int64_t)halo.size());
   }
   hipStream_t st = c->stream;
   mf.rb_n = (int64_t)brow.size() - 1;
   HIPCHK(upload(mf.d_rb_row, brow, st), "upload residual blocks");
+  HIPCHK(upload(mf.d_rb_rows, order, st), "upload residual blocks");
   HIPCHK(upload(mf.d_rb_hoff, hoff, st), "upload residual blocks");
   HIPCHK(upload(mf.d_rb_h, halo, st), "upload residual blocks");
   HIPCHK(upload(mf.d_lcol, lcol, st), "upload residual blocks");
   return TEM_OK;
+}
+
+// Entity positions of the rows of a pattern (3 per row): edge midpoints of
+// a hexahedral mesh (cell units) or of a tetrahedral one (coordinates).
+std::vector<double> hex_row_positions(const MeshTopo &mt, const std::vector<int32_t> &row_edge) {
+  std::vector<double> p(3 * row_edge.size());
+  for (size_t q = 0; q < row_edge.size(); ++q) {
+    int d, i, j, k;
+    mt.geometry(row_edge[q], d, i, j, k);
+    p[3 * q] = i + 0.5 * (d == 0);
+    p[3 * q + 1] = j + 0.5 * (d == 1);
+    p[3 * q + 2] = k + 0.5 * (d == 2);
+  }
+  return p;
+}
+std::vector<double> tet_row_positions(const TetTopo &tt, const std::vector<int32_t> &row_edge) {
+  std::vector<double> p(3 * row_edge.size());
+  for (size_t q = 0; q < row_edge.size(); ++q) {
+    const int64_t e = row_edge[q];
+    for (int k = 0; k < 3; ++k)
+      p[3 * q + k] = 0.5 * (tt.xyz[3 * (size_t)tt.edges[2 * e] + k] +
+                            tt.xyz[3 * (size_t)tt.edges[2 * e + 1] + k]);
+  }
+  return p;
 }
 
 tem_status upload_pattern(tem_ctx *c, MF &mf) {
@@ -460,7 +531,10 @@ tem_status upload_pattern(tem_ctx *c, MF &mf) {
   HIPCHK(upload(mf.d_col, mf.pat.col, st), "upload col");
   HIPCHK(upload(mf.d_row_ent, mf.pat.row_edge, st), "upload row map");
   HIPCHK(upload(mf.d_ent_new, mf.pat.edge_new, st), "upload entity map");
-  if (!mf.nodes) TRY(build_res_blocks(c, mf, mf.pat.rowptr, mf.pat.col, {0}));
+  if (!mf.nodes) {
+    const std::vector<double> pos = hex_row_positions(c->mt, mf.pat.row_edge);
+    TRY(build_res_blocks(c, mf, mf.pat.rowptr, mf.pat.col, {0}, &pos));
+  }
   return TEM_OK;
 }
 
@@ -508,7 +582,10 @@ tem_status upload_pattern_and_assemble_tet(tem_ctx *c) {
   HIPCHK(upload(e.d_col, e.pat.col, st), "upload col");
   HIPCHK(upload(e.d_row_ent, e.pat.row_edge, st), "upload row map");
   HIPCHK(upload(e.d_ent_new, e.pat.edge_new, st), "upload entity map");
-  TRY(build_res_blocks(c, e, e.pat.rowptr, e.pat.col, {0}));
+  {
+    const std::vector<double> pos = tet_row_positions(tt, e.pat.row_edge);
+    TRY(build_res_blocks(c, e, e.pat.rowptr, e.pat.col, {0}, &pos));
+  }
   const int64_t nt = tt.n_tets, N = e.N;
   const size_t nnz = e.pat.col.size();
   std::vector<int32_t> tn((size_t)nt * 6);
@@ -1519,6 +1596,7 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
     // by p0 keeps the (mesh, p0 + p) entry under index mesh * stride + p
     const int64_t o = (int64_t)pr.p0 * N * S;
     HIPCHK(launch_residual_blk(st, N, pr.n, S, c->ed.rb_n, c->ed.d_rb_row.as<int64_t>(),
+                               c->ed.d_rb_rows.as<int32_t>(),
                                c->ed.d_rb_hoff.as<int64_t>(), c->ed.d_rb_h.as<int32_t>(),
                                c->ed.d_rowptr.as<int64_t>(), c->ed.d_lcol.as<uint16_t>(),
                                c->d_K.as<double>(), c->d_M.as<double>(),
@@ -1625,6 +1703,7 @@ tem_status refine_block(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       const int64_t o = (int64_t)pr.p0 * N * S;
       if (xv)
         HIPCHK(launch_residual_blk(st, N, pr.n, S, c->ed.rb_n, c->ed.d_rb_row.as<int64_t>(),
+                               c->ed.d_rb_rows.as<int32_t>(),
                                    c->ed.d_rb_hoff.as<int64_t>(), c->ed.d_rb_h.as<int32_t>(),
                                    c->ed.d_rowptr.as<int64_t>(), c->ed.d_lcol.as<uint16_t>(),
                                    c->d_K.as<double>(), c->d_M.as<double>(), xi + 2 * pr.p0, rs,
@@ -2060,6 +2139,7 @@ tem_status merge_systems(tem_ctx *c, bool nodes) {
   P.rowptr.assign(1, 0);
   P.col.clear();
   P.row_edge.clear();
+  std::vector<double> posv;   // entity positions of the rows (edge systems)
   P.edge_new.clear();
   M.h_np.clear();
   M.d_np.release();
@@ -2096,6 +2176,10 @@ tem_status merge_systems(tem_ctx *c, bool nodes) {
     for (size_t i = 0; i + 1 < m.pat.rowptr.size(); ++i) P.rowptr.push_back(m.pat.rowptr[i + 1] + z0);
     for (int32_t q : m.pat.col) P.col.push_back((int32_t)(q + r0));
     for (int32_t e : m.pat.row_edge) P.row_edge.push_back((int32_t)(e + e0));
+    if (!nodes) {
+      const std::vector<double> p = hex_row_positions(sb->mt, m.pat.row_edge);
+      posv.insert(posv.end(), p.begin(), p.end());
+    }
     for (int32_t q : m.pat.edge_new) P.edge_new.push_back(q >= 0 ? (int32_t)(q + r0) : -1);
     r0 += m.N;
     e0 += ents;
@@ -2115,7 +2199,7 @@ tem_status merge_systems(tem_ctx *c, bool nodes) {
   HIPCHK(upload(M.d_col, P.col, st), "upload col");
   HIPCHK(upload(M.d_row_ent, P.row_edge, st), "upload row map");
   HIPCHK(upload(M.d_ent_new, P.edge_new, st), "upload entity map");
-  if (!nodes) TRY(build_res_blocks(c, M, P.rowptr, P.col, roff));
+  if (!nodes) TRY(build_res_blocks(c, M, P.rowptr, P.col, roff, &posv));
   return build_front_maps(c, M);
 }
 
