@@ -230,10 +230,11 @@ __global__ __launch_bounds__(256) void k_residual_blk(
     const double *Mv, const double *xi, Seg sg, const double *f_real, const cpx<double> *f_cplx,
     const cpx<double> *x, cpx<double> *r) {
   constexpr int NS = RB_HALO * RB_SC / 256;      // halo loads per lane and pair
+  static_assert(RB_HALO * RB_SC <= 65536, "halo offsets are 16-bit");
   constexpr int NE = (RB_ROWS * RB_NNZ + 255) / 256;
   __shared__ cpx<double> xs[RB_HALO * RB_SC];
   __shared__ cpx<double> km[RB_ROWS * RB_NNZ];   // (K, M) of each entry
-  __shared__ int kl[RB_ROWS * RB_NNZ];           // its halo position * RB_SC
+  __shared__ uint16_t kl[RB_ROWS * RB_NNZ];      // its halo position * RB_SC
   __shared__ int64_t rp0[RB_ROWS], rp1[RB_ROWS];  // each row's entries
   __shared__ int32_t rws[RB_ROWS];                 // the block's rows
   const int64_t b = xcd_block(nblk);
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(256) void k_residual_blk(
     if (rr < nrow && rp0[rr] + j < rp1[rr]) {
       const int64_t e = rp0[rr] + j;
       km[q] = {Kv[e], Mv[e]};
-      kl[q] = (int)lcol[e] * RB_SC;
+      kl[q] = (uint16_t)(lcol[e] * RB_SC);
     }
   }
   const bool has_row = lr < nrow;
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(256) void k_residual_blk(
     if (!has_row || ls >= sc) continue;
     const double xr = xi[xb + 2 * p], xim = xi[xb + 2 * p + 1];
     const cpx<double> *kmr = km + lr * RB_NNZ;
-    const int *klr = kl + lr * RB_NNZ;
+    const uint16_t *klr = kl + lr * RB_NNZ;
     // K x and M x of the row, then (K - xi M) x = K x - xi (M x): four
     // multiply-adds per entry instead of six for the entry's shifted value
     double kr = 0.0, ki = 0.0, mr = 0.0, mi = 0.0;

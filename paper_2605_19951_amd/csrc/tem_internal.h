@@ -214,7 +214,7 @@ hipError_t launch_residual_init(hipStream_t st, int64_t N, int npole, int S,
 // their entities' positions) whose columns span at most RB_HALO distinct
 // rows (the block's halo), rows of at most RB_NNZ entries; right-hand sides
 // are staged RB_SC at a time.
-constexpr int RB_ROWS = 32, RB_HALO = 384, RB_NNZ = 33, RB_SC = 8;
+constexpr int RB_ROWS = 32, RB_HALO = 256, RB_NNZ = 33, RB_SC = 8;
 // r = f - (K - xi_p M) x (x != NULL) by row blocks: block b holds the rows
 // rb_rows[rb_row[b] .. rb_row[b+1]) and halo rows rb_h[rb_hoff[b] ..
 // rb_hoff[b+1]); lcol[t] is the position of col[t] in its block's halo.
