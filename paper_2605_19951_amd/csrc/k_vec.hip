@@ -223,6 +223,7 @@ __global__ __launch_bounds__(256) void k_residual_init(int64_t N, int npole, int
 // LDS banks; the entry itself is a broadcast).  The matrix is read once per
 // call and each x row once per block that touches it, instead of once per
 // nonzero.  The sums over a row run in CSR order.
+template <bool PK>
 __global__ __launch_bounds__(256) void k_residual_blk(
     int64_t N, int npole, int S, int64_t nblk, const int64_t *rb_row, const int32_t *rb_rows,
     const int64_t *rb_hoff, const int32_t *rb_h, const int64_t *rowptr, const uint16_t *lcol,
@@ -233,9 +234,12 @@ __global__ __launch_bounds__(256) void k_residual_blk(
   static_assert(RB_HALO * RB_SC <= 65536, "halo offsets are 16-bit");
   constexpr int NE = (RB_ROWS * RB_NNZ + 255) / 256;
   __shared__ cpx<double> xs[RB_HALO * RB_SC];
+  // the block's entries: row lr's at lr * RB_NNZ (rows of at most RB_NNZ
+  // entries) or, with PK, packed row after row from ro[lr]
   __shared__ cpx<double> km[RB_ROWS * RB_NNZ];   // (K, M) of each entry
   __shared__ uint16_t kl[RB_ROWS * RB_NNZ];      // its halo position * RB_SC
-  __shared__ int64_t rp0[RB_ROWS], rp1[RB_ROWS];  // each row's entries
+  __shared__ int64_t rp0[RB_ROWS], rp1[RB_ROWS];  // each row's entries in the matrix
+  __shared__ int16_t ro[RB_ROWS + 1];              // and in km / kl
   __shared__ int32_t rws[RB_ROWS];                 // the block's rows
   const int64_t b = xcd_block(nblk);
   if (b >= nblk) return;   // uniform over the workgroup
@@ -254,14 +258,41 @@ __global__ __launch_bounds__(256) void k_residual_blk(
 #pragma unroll
   for (int i = 0; i < NS; ++i) hidx[i] = rb_h[h0 + min(lr + 32 * i, nh - 1)];
   __syncthreads();
+  if constexpr (PK) {
+    if (t == 0) {   // packed offsets (the host keeps a block's entries <= RB_ROWS * RB_NNZ)
+      int acc = 0;
+      for (int rr = 0; rr < nrow; ++rr) {
+        ro[rr] = (int16_t)acc;
+        acc += (int)(rp1[rr] - rp0[rr]);
+      }
+      ro[nrow] = (int16_t)acc;
+    }
+    __syncthreads();
+    const int ntot = ro[nrow];
 #pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    const int q = t + 256 * i;
-    const int rr = q / RB_NNZ, j = q - rr * RB_NNZ;
-    if (rr < nrow && rp0[rr] + j < rp1[rr]) {
-      const int64_t e = rp0[rr] + j;
-      km[q] = {Kv[e], Mv[e]};
-      kl[q] = (uint16_t)(lcol[e] * RB_SC);
+    for (int i = 0; i < NE; ++i) {
+      const int q = t + 256 * i;
+      if (q < ntot) {
+        int lo = 0, hi = nrow;   // the row rr with ro[rr] <= q < ro[rr + 1]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (ro[mid] <= q) lo = mid; else hi = mid;
+        }
+        const int64_t e = rp0[lo] + (q - ro[lo]);
+        km[q] = {Kv[e], Mv[e]};
+        kl[q] = (uint16_t)(lcol[e] * RB_SC);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int q = t + 256 * i;
+      const int rr = q / RB_NNZ, j = q - rr * RB_NNZ;
+      if (rr < nrow && rp0[rr] + j < rp1[rr]) {
+        const int64_t e = rp0[rr] + j;
+        km[q] = {Kv[e], Mv[e]};
+        kl[q] = (uint16_t)(lcol[e] * RB_SC);
+      }
     }
   }
   const bool has_row = lr < nrow;
@@ -302,8 +333,9 @@ __global__ __launch_bounds__(256) void k_residual_blk(
     }
     if (!has_row || ls >= sc) continue;
     const double xr = xi[xb + 2 * p], xim = xi[xb + 2 * p + 1];
-    const cpx<double> *kmr = km + lr * RB_NNZ;
-    const uint16_t *klr = kl + lr * RB_NNZ;
+    const int off = PK ? (int)ro[lr] : lr * RB_NNZ;
+    const cpx<double> *kmr = km + off;
+    const uint16_t *klr = kl + off;
     // K x and M x of the row, then (K - xi M) x = K x - xi (M x): four
     // multiply-adds per entry instead of six for the entry's shifted value
     double kr = 0.0, ki = 0.0, mr = 0.0, mi = 0.0;
@@ -332,15 +364,20 @@ __global__ __launch_bounds__(256) void k_residual_blk(
 
 hipError_t launch_residual_blk(hipStream_t st, int64_t N, int npole, int S, int64_t nblk,
                                const int64_t *rb_row, const int32_t *rb_rows,
-                               const int64_t *rb_hoff, const int32_t *rb_h,
+                               const int64_t *rb_hoff, const int32_t *rb_h, bool packed,
                                const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
                                const double *Mv, const double *xi, Seg sg, const double *f_real,
                                const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r) {
   if (N <= 0 || npole <= 0 || nblk <= 0) return hipSuccess;
   if (S < 1 || S > 16 || !x || !rb_rows) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_residual_blk, dim3(xcd_grid(nblk, 1)), dim3(256), 0, st, N, npole, S, nblk,
-                     rb_row, rb_rows, rb_hoff, rb_h, rowptr, lcol, Kv, Mv, xi, sg, f_real, f_cplx,
-                     x, r);
+  if (packed)
+    hipLaunchKernelGGL(k_residual_blk<true>, dim3(xcd_grid(nblk, 1)), dim3(256), 0, st, N, npole,
+                       S, nblk, rb_row, rb_rows, rb_hoff, rb_h, rowptr, lcol, Kv, Mv, xi, sg,
+                       f_real, f_cplx, x, r);
+  else
+    hipLaunchKernelGGL(k_residual_blk<false>, dim3(xcd_grid(nblk, 1)), dim3(256), 0, st, N, npole,
+                       S, nblk, rb_row, rb_rows, rb_hoff, rb_h, rowptr, lcol, Kv, Mv, xi, sg,
+                       f_real, f_cplx, x, r);
   return hipGetLastError();
 }
 

@@ -169,6 +169,7 @@ struct MF {
   int x_bb = 0;
   // row blocks of the FP64 residual (edge system; see launch_residual_blk)
   int64_t rb_n = 0;
+  bool rb_packed = false;   // some row has more than RB_NNZ entries
   DBuf d_rb_row, d_rb_rows, d_rb_hoff, d_rb_h, d_lcol;
   std::vector<int32_t> h_np;
   // poles of front s among the g slots starting at p0
@@ -402,8 +403,8 @@ tem_status run_assemble_edges(tem_ctx *c) {
 // per cell, so that a block's rows are neighbours in space and share most of
 // their columns (about a third fewer halo rows per row than in elimination
 // order); without, in row order.  Each block's halo is its sorted column set
-// and lcol gives every entry's position in it.  Rows longer than RB_NNZ are
-// refused.
+// and lcol gives every entry's position in it; a block holds at most
+// RB_ROWS * RB_NNZ entries, and a longer row is refused.
 uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   uint64_t k = 0;
   for (int b = 0; b < 21; ++b)
@@ -456,11 +457,17 @@ tem_status build_res_blocks(tem_ctx *c, MF &mf, const std::vector<int64_t> &rowp
     const int64_t seg_lo = seg[si], seg_end = si + 1 < seg.size() ? seg[si + 1] : N;
     const int64_t blk = (int64_t)brow.size() - 1, i0 = i;
     h.clear();
+    int64_t ents = 0;
     while (i < N && i - i0 < RB_ROWS) {
       const int64_t r = order[i];
       if (r < seg_lo || r >= seg_end) break;   // the next segment starts a block
-      if (rowptr[r + 1] - rowptr[r] > RB_NNZ)
-        return fail(c, TEM_EINVAL, "residual blocks: a row has more than 33 entries");
+      const int64_t len = rowptr[r + 1] - rowptr[r];
+      if (len > (int64_t)RB_ROWS * RB_NNZ)
+        return fail(c, TEM_EINVAL, "residual blocks: a row has more than 1056 entries");
+      if (len > RB_HALO)
+        return fail(c, TEM_EINVAL, "residual blocks: a row has more than 256 distinct columns");
+      if (ents + len > (int64_t)RB_ROWS * RB_NNZ) break;   // the block's entries are full
+      ents += len;
       int add = 0;
       for (int64_t t = rowptr[r]; t < rowptr[r + 1]; ++t)
         if (stamp[col[t]] != blk) {
@@ -470,7 +477,7 @@ tem_status build_res_blocks(tem_ctx *c, MF &mf, const std::vector<int64_t> &rowp
         }
       if ((int64_t)h.size() > RB_HALO) {
         // the row does not fit: undo its new columns (i > i0 here, since a
-        // single row has at most RB_NNZ < RB_HALO columns)
+        // single row has at most RB_HALO columns)
         for (int k = 0; k < add; ++k) {
           stamp[h.back()] = -1;
           h.pop_back();
@@ -491,6 +498,8 @@ tem_status build_res_blocks(tem_ctx *c, MF &mf, const std::vector<int64_t> &rowp
   }
   hipStream_t st = c->stream;
   mf.rb_n = (int64_t)brow.size() - 1;
+  mf.rb_packed = false;
+  for (int64_t q = 0; q < N && !mf.rb_packed; ++q) mf.rb_packed = rowptr[q + 1] - rowptr[q] > RB_NNZ;
   HIPCHK(upload(mf.d_rb_row, brow, st), "upload residual blocks");
   HIPCHK(upload(mf.d_rb_rows, order, st), "upload residual blocks");
   HIPCHK(upload(mf.d_rb_hoff, hoff, st), "upload residual blocks");
@@ -1598,6 +1607,7 @@ tem_status aux_correct(tem_ctx *c, const cpx<double> *r, cpx<double> *z, int S,
     HIPCHK(launch_residual_blk(st, N, pr.n, S, c->ed.rb_n, c->ed.d_rb_row.as<int64_t>(),
                                c->ed.d_rb_rows.as<int32_t>(),
                                c->ed.d_rb_hoff.as<int64_t>(), c->ed.d_rb_h.as<int32_t>(),
+                               c->ed.rb_packed,
                                c->ed.d_rowptr.as<int64_t>(), c->ed.d_lcol.as<uint16_t>(),
                                c->d_K.as<double>(), c->d_M.as<double>(),
                                c->d_xi.as<double>() + 2 * pr.p0, rs, nullptr, r + o, z + o, w + o),
@@ -1703,8 +1713,9 @@ tem_status refine_block(tem_ctx *c, const double *f_real, const cpx<double> *f_c
       const int64_t o = (int64_t)pr.p0 * N * S;
       if (xv)
         HIPCHK(launch_residual_blk(st, N, pr.n, S, c->ed.rb_n, c->ed.d_rb_row.as<int64_t>(),
-                               c->ed.d_rb_rows.as<int32_t>(),
+                                   c->ed.d_rb_rows.as<int32_t>(),
                                    c->ed.d_rb_hoff.as<int64_t>(), c->ed.d_rb_h.as<int32_t>(),
+                                   c->ed.rb_packed,
                                    c->ed.d_rowptr.as<int64_t>(), c->ed.d_lcol.as<uint16_t>(),
                                    c->d_K.as<double>(), c->d_M.as<double>(), xi + 2 * pr.p0, rs,
                                    f_real, f_cplx ? f_cplx + o : nullptr, xv + o, r + o),

@@ -212,8 +212,10 @@ hipError_t launch_residual_init(hipStream_t st, int64_t N, int npole, int S,
 // Row blocks of the FP64 residual (launch_residual_blk): at most RB_ROWS
 // rows per block (neighbours in space: the rows are taken in Morton order of
 // their entities' positions) whose columns span at most RB_HALO distinct
-// rows (the block's halo), rows of at most RB_NNZ entries; right-hand sides
-// are staged RB_SC at a time.
+// rows (the block's halo), with at most RB_ROWS * RB_NNZ entries in all (any
+// row length up to that: rows of at most RB_NNZ entries keep a fixed stride
+// in LDS, longer ones need the packed layout); right-hand sides are staged
+// RB_SC at a time.
 constexpr int RB_ROWS = 32, RB_HALO = 256, RB_NNZ = 33, RB_SC = 8;
 // r = f - (K - xi_p M) x (x != NULL) by row blocks: block b holds the rows
 // rb_rows[rb_row[b] .. rb_row[b+1]) and halo rows rb_h[rb_hoff[b] ..
@@ -221,7 +223,7 @@ constexpr int RB_ROWS = 32, RB_HALO = 256, RB_NNZ = 33, RB_SC = 8;
 // Each row's sum runs over its entries in order.  S <= 16.
 hipError_t launch_residual_blk(hipStream_t st, int64_t N, int npole, int S, int64_t nblk,
                                const int64_t *rb_row, const int32_t *rb_rows,
-                               const int64_t *rb_hoff, const int32_t *rb_h,
+                               const int64_t *rb_hoff, const int32_t *rb_h, bool packed,
                                const int64_t *rowptr, const uint16_t *lcol, const double *Kv,
                                const double *Mv, const double *xi, Seg sg, const double *f_real,
                                const cpx<double> *f_cplx, const cpx<double> *x, cpx<double> *r);

@@ -230,3 +230,43 @@ def tet_workload(n=8, n_air=2, h=25.0, S=2, m=8, K=12, g=3, jitter=0.15, seed=11
     wl.extra["rng_noise"] = r_noise
     wl.extra["rng_dir"] = r_dir
     return wl
+
+
+def delaunay_workload(n_points=700, L=500.0, S=2, R=6, m=5, K=6, seed=61):
+    """A mesh with no structure at all: the Delaunay tetrahedralisation
+    (scipy.spatial.Delaunay, joggled input so every cell is a tetrahedron)
+    of the eight corners of an L-cube and n_points seeded uniform points
+    inside it.  Air (1e-6 S/m) above z = 0.8 L by tetrahedron centroid,
+    earth 0.01 S/m with a 1 S/m box [0.3, 0.6] L x [0.3, 0.6] L x
+    [0.4, 0.6] L; S current-element sources of unit current on seeded edges
+    between interior points, R tangential-E receivers (mean field along the
+    edge: e^T / length) on further such edges; m contour poles and K times in
+    [1e-5, 1e-2] s.  Parameters are the earth tetrahedra."""
+    import scipy.spatial as ss
+    r_pts, r_src, r_rx, r_noise, r_dir = _streams(seed)
+    corners = np.array([[x, y, z] for z in (0.0, L) for y in (0.0, L) for x in (0.0, L)])
+    pts = np.vstack([corners, r_pts.uniform(0.02 * L, 0.98 * L, (n_points, 3))])
+    tets = ss.Delaunay(pts, qhull_options="QJ").simplices.astype(np.int32)
+    mesh = TetMesh(pts, tets, 0, 0, 0, float(L), 0, np.zeros(len(tets), np.int64), 0.8 * L)
+    cen = pts[tets].mean(axis=1)
+    sigma = np.where(cen[:, 2] > 0.8 * L, SIGMA_AIR, 0.01)
+    blk = ((cen[:, 0] > 0.3 * L) & (cen[:, 0] < 0.6 * L) & (cen[:, 1] > 0.3 * L)
+           & (cen[:, 1] < 0.6 * L) & (cen[:, 2] > 0.4 * L) & (cen[:, 2] < 0.6 * L))
+    sigma[blk] = 1.0
+    inner = np.nonzero((mesh.edges[:, 0] >= 8) & (mesh.edges[:, 1] >= 8))[0]
+    pick = r_src.choice(inner, S + R, replace=False)
+    F = np.zeros((mesh.n_edges, S))
+    for s in range(S):
+        F[pick[s], s] = 1.0
+    rows = []
+    for e in pick[S:]:
+        a, b = mesh.edges[e]
+        rows.append([(int(e), 1.0 / float(np.linalg.norm(pts[b] - pts[a])))])
+    rx = _csr(rows)
+    rx.kind = "edge"
+    params = np.nonzero(cen[:, 2] <= 0.8 * L)[0].astype(np.int32)
+    wl = TetWorkload("delaunay%d" % n_points, mesh, sigma, F, rx, pole_table(m, 1e-5, 1e-2, K),
+                     params)
+    wl.extra["rng_noise"] = r_noise
+    wl.extra["rng_dir"] = r_dir
+    return wl

@@ -11,7 +11,7 @@ import pytest
 
 from oracle import tet as ot
 from oracle.tem import gauss_newton_step
-from tem_inputs.tet import tet_workload
+from tem_inputs.tet import delaunay_workload, tet_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -56,8 +56,10 @@ WORKLOADS = {
     "t8": lambda: tet_workload(8, 2, S=2, m=6, K=9, g=3, seed=41),
     # larger leaves and wider separators
     "t11": lambda: tet_workload(11, 3, S=3, m=5, K=7, g=3, seed=42),
+    # no structure at all: a Delaunay mesh of random points (slivers included)
+    "dl": lambda: delaunay_workload(700, S=2, R=6, m=5, K=6, seed=61),
 }
-CASES = ["t8_64", "t8_32", "t11_64", "t11_32"]
+CASES = ["t8_64", "t8_32", "t11_64", "t11_32", "dl_64", "dl_32"]
 _runs = {}
 
 
@@ -72,7 +74,7 @@ def get(name):
     return _runs[name]
 
 
-@pytest.mark.parametrize("name", ["t8_64", "t11_64"])
+@pytest.mark.parametrize("name", ["t8_64", "t11_64", "dl_64"])
 def test_tet_assembly_matches_oracle(name):
     r = get(name)
     perm, rowptr, col, kv, mv = r.t.export_operators()
@@ -88,8 +90,18 @@ def test_tet_assembly_matches_oracle(name):
     import scipy.sparse as sp
     Kg = sp.csr_matrix((kv, col, rowptr), shape=(N, N))
     Mg = sp.csr_matrix((mv, col, rowptr), shape=(N, N))
-    assert abs(Kg - Kp).max() <= 8 * np.finfo(float).eps * abs(Kp).max()
-    assert abs(Mg - Mp).max() <= 8 * np.finfo(float).eps * abs(Mp).max()
+    # entrywise against the sum of the magnitudes of the element terms (the
+    # entries of a mesh with slivers are sums of large terms that cancel)
+    Ka, Ma = ot.assemble(r.o.topo, r.o.sigma, r.wl.mu, np.abs(r.o.Ks), np.abs(r.o.Ms))
+    Ka = Ka[perm][:, perm].tocsr()
+    Ma = Ma[perm][:, perm].tocsr()
+    eps = np.finfo(float).eps
+    for D, A, X in ((abs(Kg - Kp).tocoo(), Ka, Kp), (abs(Mg - Mp).tocoo(), Ma, Mp)):
+        lim = np.asarray(A[D.row, D.col]).ravel()
+        assert np.all(D.data <= 1e-12 * lim + 8 * eps * abs(X).max())
+    if not name.startswith("dl"):   # well-shaped elements: within a few ulp of the largest entry
+        assert abs(Kg - Kp).max() <= 8 * np.finfo(float).eps * abs(Kp).max()
+        assert abs(Mg - Mp).max() <= 8 * np.finfo(float).eps * abs(Mp).max()
     assert r.info["n_unknowns"] == len(r.o.unk)
 
 
@@ -141,8 +153,13 @@ def test_tet_jvp_vjp(name):
     w = rng.standard_normal(tuple(r.d.shape))
     jv = torch.zeros_like(r.d)
     jtw = torch.zeros(P, dtype=torch.float64, device=r.dev)
-    r.t.jvp(torch.tensor(v, device=r.dev), jv)
-    r.t.vjp(torch.tensor(w, device=r.dev), jtw)
+    # On the Delaunay mesh (slivers included) the adjoint right-hand sides, a
+    # few receiver edges, are badly scaled: |A| |x| / |b| reaches 1.2e7 for
+    # the pole of smallest |xi|, where the oracle's own LU solution leaves a
+    # residual ratio of 1.7e-9.  Its refinement target is 1e-9.
+    ir = dict(rtol=1e-9) if name.startswith("dl") else None
+    r.t.jvp(torch.tensor(v, device=r.dev), jv, ir=ir)
+    r.t.vjp(torch.tensor(w, device=r.dev), jtw, ir=ir)
     jv_ref = r.o.jvp(v)
     jtw_ref = r.o.vjp(w)
     assert np.linalg.norm(jv.cpu().numpy() - jv_ref) <= TOL * np.linalg.norm(jv_ref)

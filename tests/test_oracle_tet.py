@@ -8,7 +8,7 @@ import pytest
 
 from oracle import tet as ot
 from tem_inputs import MU0
-from tem_inputs.tet import kuhn_mesh, tet_workload
+from tem_inputs.tet import delaunay_workload, kuhn_mesh, tet_workload
 
 # quadrature exact for quadratics on a tetrahedron: -1/20 of the vertex
 # values plus 1/5 of the edge-midpoint values, times the volume
@@ -210,3 +210,25 @@ def test_forward_finite_differences(tiny_tet):
     orc.set_model(m0)
     fd = (dp - dm) / (2 * h)
     assert np.linalg.norm(fd - jv) <= 1e-6 * np.linalg.norm(jv)
+
+
+def test_assembled_forms_on_a_delaunay_mesh():
+    """The global forms of a field a + b x x and K G = 0 on a mesh with no
+    structure (Delaunay of random points, slivers included)."""
+    wl = delaunay_workload(300, S=1, R=2, m=3, K=3, seed=62)
+    me = wl.mesh
+    topo = ot.TetTopology(me.xyz, me.tets)
+    assert np.array_equal(topo.edges, me.edges)
+    rng = np.random.default_rng(7)
+    K, M = ot.assemble_all(topo, wl.sigma, MU0)
+    a, b = rng.standard_normal(3), rng.standard_normal(3) / 500.0
+    f = lambda p: a + np.cross(b, p)
+    u = np.array([edge_dof(f, me.xyz[e0], me.xyz[e1]) for e0, e1 in topo.edges])
+    qm, qk = 0.0, 0.0
+    for c, t in enumerate(me.tets):
+        q, vol = quad2(me.xyz[t], lambda p: f(p) @ f(p))
+        qm += wl.sigma[c] * q
+        qk += vol * 4.0 * (b @ b) / MU0
+    assert abs(u @ (M @ u) - qm) <= 1e-10 * qm
+    assert abs(u @ (K @ u) - qk) <= 1e-10 * qk
+    assert abs(K @ topo.gradient()).max() <= 1e-11 * abs(K).max()
